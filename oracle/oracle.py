@@ -1,0 +1,547 @@
+"""FP64 CPU oracle for the implicit TDGL step of Sadovskyy et al.,
+"Stable large-scale solver for Ginzburg-Landau equations for superconductors"
+(arXiv:1409.8340).
+
+TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT.  Only ``tests/``, the smoke
+check and the CPU-baseline leg of the benchmark may import this module.  It
+shares no code with the HIP path; both sides only receive the same seeded
+input arrays.
+
+Plain stencil loops live in ``tdgl_oracle.c`` (double precision, loaded with
+ctypes); this module adds what is clearer in numpy: the Landau-gauge link
+variables, the exact Poisson solve (spectral, with scipy's FFT/DCT as a
+library step), the time-step driver and the inclusion rasteriser.
+
+Readings of places where the paper is silent or ambiguous are marked
+"reading:" below; the same list is kept with the design notes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.fft as sfft
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liborc.so")
+_SRC_PATH = os.path.join(_HERE, "tdgl_oracle.c")
+
+
+def build(force: bool = False) -> str:
+    """Compile the C part of the oracle (gcc, -O2, OpenMP, no FMA contraction
+    beyond what plain x86-64 code generation does)."""
+    if force or not os.path.exists(_LIB_PATH) or (
+            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC_PATH)):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-ffp-contract=off", "-o", tmp, _SRC_PATH, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _CGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("open_x", ctypes.c_int), ("open_y", ctypes.c_int), ("open_z", ctypes.c_int),
+                ("hx", ctypes.c_double), ("hy", ctypes.c_double), ("hz", ctypes.c_double),
+                ("g", ctypes.c_double)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(build())
+        P = ctypes.c_void_p
+        G = ctypes.POINTER(_CGrid)
+        D = ctypes.c_double
+        lib.orc_neighbour_sum.argtypes = [G, P, P, P, P, P]
+        lib.orc_laplacian.argtypes = [G, P, P, P, P, P]
+        lib.orc_assemble.argtypes = [G, P, P, P, P, P, P, D, D, P, P]
+        lib.orc_apply_M.argtypes = [G, P, P, P, P, D, P, P]
+        lib.orc_jacobi_sweep.argtypes = [G, P, P, P, P, P, D, P, P]
+        lib.orc_jacobi_sweep.restype = D
+        lib.orc_residual_max2.argtypes = [G, P, P, P, P, P, D, P]
+        lib.orc_residual_max2.restype = D
+        lib.orc_jav.argtypes = [G, P, P]
+        lib.orc_jav.restype = D
+        lib.orc_poisson_rhs.argtypes = [G, P, P, P, P, P]
+        lib.orc_poisson_apply.argtypes = [G, P, P]
+        lib.orc_node_weights.argtypes = [G, P]
+        lib.orc_free_energy.argtypes = [G, P, P, P, P, P]
+        lib.orc_free_energy.restype = D
+        lib.orc_weighted_sum.argtypes = [G, P]
+        lib.orc_weighted_sum.restype = D
+        _lib = lib
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ---------------------------------------------------------------------------
+# Grid, field, links
+# ---------------------------------------------------------------------------
+@dataclass
+class Grid:
+    """Cuboid mesh of Sec. 3: nodes x = i hx, y = j hy, z = k hz.
+
+    ``open_`` holds, per axis, True for open (Neumann, Sec. 3.3.2) and False
+    for periodic / quasi-periodic (Sec. 3.3.1).
+    """
+    nx: int
+    ny: int
+    nz: int
+    hx: float = 0.5
+    hy: float = 0.5
+    hz: float = 0.5
+    open_: tuple = (False, False, True)
+    g: float = 1.0
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    @property
+    def N(self):
+        return self.nx * self.ny * self.nz
+
+    def length(self, axis: int) -> float:
+        """System size: L = N h for periodic axes, (N-1) h for open axes
+        (Sec. 3, mesh spacing definitions)."""
+        n = (self.nx, self.ny, self.nz)[axis]
+        h = (self.hx, self.hy, self.hz)[axis]
+        return (n - 1) * h if self.open_[axis] else n * h
+
+    def c(self) -> _CGrid:
+        return _CGrid(self.nx, self.ny, self.nz, int(self.open_[0]), int(self.open_[1]),
+                      int(self.open_[2]), self.hx, self.hy, self.hz, self.g)
+
+
+def quantize_field(grid: Grid, Bx: float, Bz: float):
+    """Round the field of the xz-plane gauge to whole flux quanta through the
+    periodic cross sections (Sec. 3.3.1, "Implications for the magnetic
+    field"): Bz = 2 pi n_z / (Lx Ly) when x and y are both periodic,
+    Bx = 2 pi n_x / (Ly Lz) when y and z are both periodic.  Components that
+    are not constrained are returned unchanged."""
+    Lx, Ly, Lz = grid.length(0), grid.length(1), grid.length(2)
+    if not grid.open_[0] and not grid.open_[1]:
+        Bz = 2 * np.pi * np.round(Bz * Lx * Ly / (2 * np.pi)) / (Lx * Ly)
+    if not grid.open_[1] and not grid.open_[2]:
+        Bx = 2 * np.pi * np.round(Bx * Ly * Lz / (2 * np.pi)) / (Ly * Lz)
+    return float(Bx), float(Bz)
+
+
+def landau_links(grid: Grid, Bx: float, Bz: float, K: float):
+    """Per-edge link variables U = exp(-i h_a A~_a) (Eq. link_variables) for
+    the xz-plane field in the Landau gauge A = ybar [-Bz, 0, Bx]
+    (Eq. A_xz), with the current phase K folded into A~ = A - [K, 0, 0]
+    (Sec. 2.2):
+
+      x links: exp(+i hx (K + Bz ybar_j))
+      z links: exp(-i hz Bx ybar_j)
+      y links: 1, except the wrap edge j = ny-1 -> 0 of a periodic y axis,
+               which carries conj(P_{i,k}),
+               P_{i,k} = exp(i (i hx Ly Bz - k hz Ly Bx))  (Sec. 3.3.1),
+               so that psi_{i,-1,k} = P_{i,k} psi_{i,ny-1,k}.
+
+    reading: ybar_j = j hy - Ly/2 with Ly the system size of Sec. 3.
+    """
+    nz, ny, nx = grid.shape
+    Ly = grid.length(1)
+    j = np.arange(ny, dtype=np.float64)
+    ybar = j * grid.hy - Ly / 2.0
+    phx = grid.hx * (K + Bz * ybar)
+    phz = -grid.hz * Bx * ybar
+    lx = np.broadcast_to(np.exp(1j * phx)[None, :, None], grid.shape).astype(np.complex128)
+    lz = np.broadcast_to(np.exp(1j * phz)[None, :, None], grid.shape).astype(np.complex128)
+    ly = np.ones(grid.shape, dtype=np.complex128)
+    if not grid.open_[1]:
+        i = np.arange(nx, dtype=np.float64)[None, :]
+        k = np.arange(nz, dtype=np.float64)[:, None]
+        P = np.exp(1j * (i * grid.hx * Ly * Bz - k * grid.hz * Ly * Bx))
+        ly[:, ny - 1, :] = np.conj(P)
+    return (np.ascontiguousarray(lx), np.ascontiguousarray(ly), np.ascontiguousarray(lz))
+
+
+def rewind_K(K: float, hx: float) -> float:
+    """Phase rewind K -> K - (2 pi / hx) floor(K hx / 2 pi) (Sec. 2.2).
+
+    reading: applied after every K update; it maps K into [0, 2 pi / hx) and
+    leaves every link variable unchanged."""
+    return K - (2 * np.pi / hx) * np.floor(K * hx / (2 * np.pi))
+
+
+# ---------------------------------------------------------------------------
+# Operators (thin wrappers over the C loops)
+# ---------------------------------------------------------------------------
+def _c128(a):
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def neighbour_sum(grid, links, psi):
+    psi = _c128(psi)
+    out = np.empty(grid.shape, np.complex128)
+    G = grid.c()
+    _load().orc_neighbour_sum(ctypes.byref(G), *map(_p, links), _p(psi), _p(out))
+    return out
+
+
+def laplacian(grid, links, psi):
+    """Covariant 7-point Laplacian (Eq. LaplUV_xz, Sec. 3.3 boundary forms)."""
+    psi = _c128(psi)
+    out = np.empty(grid.shape, np.complex128)
+    G = grid.c()
+    _load().orc_laplacian(ctypes.byref(G), *map(_p, links), _p(psi), _p(out))
+    return out
+
+
+def assemble(grid, links, psi_prev, eps, mu, u, ht):
+    """b and diag(M) of Eq. GL_linearized / Eq. b."""
+    psi_prev = _c128(psi_prev)
+    eps = _f64(eps)
+    mu_arr = _f64(mu) if mu is not None else None  # keep a reference for the call
+    mu_p = _p(mu_arr) if mu_arr is not None else None
+    b = np.empty(grid.shape, np.complex128)
+    d = np.empty(grid.shape, np.complex128)
+    G = grid.c()
+    _load().orc_assemble(ctypes.byref(G), *map(_p, links), _p(psi_prev), _p(eps), mu_p,
+                         float(u), float(ht), _p(b), _p(d))
+    return b, d
+
+
+def apply_M(grid, links, diag, ht, psi):
+    psi = _c128(psi)
+    out = np.empty(grid.shape, np.complex128)
+    G = grid.c()
+    _load().orc_apply_M(ctypes.byref(G), *map(_p, links), _p(_c128(diag)), float(ht), _p(psi),
+                        _p(out))
+    return out
+
+
+def jacobi_sweep(grid, links, b, diag, ht, psi_in):
+    """One iteration of Eq. final; returns (psi_out, max |r(psi_in)|^2)."""
+    psi_in = _c128(psi_in)
+    out = np.empty(grid.shape, np.complex128)
+    G = grid.c()
+    r2 = _load().orc_jacobi_sweep(ctypes.byref(G), *map(_p, links), _p(_c128(b)),
+                                  _p(_c128(diag)), float(ht), _p(psi_in), _p(out))
+    return out, r2
+
+
+def residual_max2(grid, links, b, diag, ht, psi):
+    G = grid.c()
+    return _load().orc_residual_max2(ctypes.byref(G), *map(_p, links), _p(_c128(b)),
+                                     _p(_c128(diag)), float(ht), _p(_c128(psi)))
+
+
+def jav(grid, links, psi):
+    """Average supercurrent J_av (Sec. 3.1.1)."""
+    G = grid.c()
+    return _load().orc_jav(ctypes.byref(G), _p(links[0]), _p(_c128(psi)))
+
+
+def poisson_rhs(grid, links, psi):
+    """Right side of the discrete Poisson equation (Sec. 3.2)."""
+    out = np.empty(grid.shape, np.float64)
+    G = grid.c()
+    _load().orc_poisson_rhs(ctypes.byref(G), *map(_p, links), _p(_c128(psi)), _p(out))
+    return out
+
+
+def poisson_apply(grid, mu):
+    """Discrete Laplacian of the scalar potential (Sec. 3.2, left side)."""
+    out = np.empty(grid.shape, np.float64)
+    G = grid.c()
+    _load().orc_poisson_apply(ctypes.byref(G), _p(_f64(mu)), _p(out))
+    return out
+
+
+def node_weights(grid):
+    out = np.empty(grid.shape, np.float64)
+    G = grid.c()
+    _load().orc_node_weights(ctypes.byref(G), _p(out))
+    return out
+
+
+def weighted_sum(grid, x):
+    G = grid.c()
+    return _load().orc_weighted_sum(ctypes.byref(G), _p(_f64(x)))
+
+
+def free_energy(grid, links, eps, psi):
+    """Discrete GL free energy (dimensionless functional whose psi* derivative
+    is the right side of Eq. GL_dimensionless; B uniform so the field energy
+    is a constant and omitted)."""
+    G = grid.c()
+    return _load().orc_free_energy(ctypes.byref(G), *map(_p, links), _p(_f64(eps)),
+                                   _p(_c128(psi)))
+
+
+# ---------------------------------------------------------------------------
+# Exact solves
+# ---------------------------------------------------------------------------
+def _axis_eigs(n, h, open_, cfac=1.0):
+    """Eigenvalues of minus the 1D second difference (Sec. 3.2 stencil) with
+    periodic wrap (Fourier modes) or Neumann reflection (cosine modes)."""
+    c = cfac / (h * h)
+    if n == 1:
+        return np.zeros(1)
+    k = np.arange(n, dtype=np.float64)
+    if open_:
+        return c * (2.0 - 2.0 * np.cos(np.pi * k / (n - 1)))
+    return c * (2.0 - 2.0 * np.cos(2.0 * np.pi * k / n))
+
+
+def poisson_exact(grid: Grid, f: np.ndarray) -> np.ndarray:
+    """Exact solution of  Delta_h mu = f  (Sec. 3.2 discretisation) with the
+    weighted mean  sum_m w_m mu_m = 0  (w = 1/2 per open face).
+
+    Delta_h is diagonalised exactly by a DFT along periodic axes and a DCT-I
+    along open axes (Neumann reflection); the solve divides by the
+    eigenvalues and drops the zero mode.  The zero mode of the DCT-I is
+    proportional to the weighted sum, so dropping it both projects f onto the
+    range of Delta_h and fixes the weighted mean of mu to zero.
+
+    reading: the paper's pseudo-time relaxation (Sec. 3.2) is an iterative
+    route to this same solution; the oracle solves it exactly.
+    """
+    f = np.asarray(f, dtype=np.float64).reshape(grid.shape)
+    axes_np = {0: 2, 1: 1, 2: 0}  # physical axis -> numpy axis
+    ns = (grid.nx, grid.ny, grid.nz)
+    hs = (grid.hx, grid.hy, grid.hz)
+    cf = (1.0, 1.0, 1.0 / (grid.g * grid.g))
+    x = f.astype(np.float64)
+    for a in range(3):
+        if grid.open_[a] and ns[a] > 1:
+            x = sfft.dct(x, type=1, axis=axes_np[a])
+    x = x.astype(np.complex128)
+    for a in range(3):
+        if not grid.open_[a]:
+            x = sfft.fft(x, axis=axes_np[a])
+    lam = np.zeros(grid.shape)
+    lam += _axis_eigs(grid.nx, grid.hx, grid.open_[0], cf[0])[None, None, :]
+    lam += _axis_eigs(grid.ny, grid.hy, grid.open_[1], cf[1])[None, :, None]
+    lam += _axis_eigs(grid.nz, grid.hz, grid.open_[2], cf[2])[:, None, None]
+    lam[0, 0, 0] = 1.0
+    x = -x / lam
+    x[0, 0, 0] = 0.0
+    for a in range(3):
+        if not grid.open_[a]:
+            x = sfft.ifft(x, axis=axes_np[a])
+    x = x.real
+    for a in range(3):
+        if grid.open_[a] and ns[a] > 1:
+            x = sfft.idct(x, type=1, axis=axes_np[a])
+    return np.ascontiguousarray(x)
+
+
+# ---------------------------------------------------------------------------
+# Time step
+# ---------------------------------------------------------------------------
+@dataclass
+class Params:
+    """Physical and solver parameters (reduced units of Sec. 2.1).
+
+    tol: threshold on max_m |r_m|^2 (Eq. convergence; squared max norm).
+    mode: "mirror" -- the paper's Jacobi iteration with its stop rule
+          (psi^(0) = psi^-, stop after the first sweep whose input residual
+          meets tol, return that sweep's output);
+          "exact" -- Jacobi iterated to max|r| <= 1e-13 max(1, max|b|).
+    driven: solve mu~ and K (Sec. 2.2); without a current both stay zero.
+    """
+    Bx: float = 0.0
+    Bz: float = 0.0
+    J_ext: float = 0.0
+    u: float = 1.0
+    dt: float = 0.1
+    tol: float = 1e-8
+    max_iter: int = 100
+    mode: str = "mirror"
+    driven: bool = False
+
+
+@dataclass
+class State:
+    psi: np.ndarray
+    mu: np.ndarray
+    K: float = 0.0
+    n: int = 0
+    V_sum: float = 0.0
+    n_avg: int = 0
+    last_sweeps: int = 0
+    last_res2: float = 0.0
+    last_E: float = 0.0
+    last_Jav: float = 0.0
+    sweeps_hist: list = field(default_factory=list)
+
+
+def new_state(grid: Grid, psi0) -> State:
+    return State(psi=_c128(np.asarray(psi0).reshape(grid.shape)).copy(),
+                 mu=np.zeros(grid.shape))
+
+
+def gl_solve(grid, links, b, diag, ht, psi_prev, tol, max_iter, mode):
+    """Jacobi solution of M psi = b (Sec. 3.1, Eq. final / Eq. convergence).
+
+    reading: the initial iterate is psi^-; the residual tested after sweep l
+    is that of the sweep's input, r^(l) = b - M psi^(l) = M_mm (psi^(l+1) -
+    psi^(l)); the output of the first sweep whose r^(l) passes is returned.
+    Returns (psi, sweeps, last max|r|^2)."""
+    psi = psi_prev
+    if mode == "exact":
+        bmax = float(np.max(np.abs(b)))
+        thr = (1e-13 * max(1.0, bmax)) ** 2
+        for l in range(100000):
+            psi_new, r2 = jacobi_sweep(grid, links, b, diag, ht, psi)
+            psi = psi_new
+            if r2 <= thr:
+                return psi, l + 1, r2
+        raise RuntimeError("exact GL solve did not converge")
+    r2 = np.inf
+    for l in range(max_iter):
+        psi_new, r2 = jacobi_sweep(grid, links, b, diag, ht, psi)
+        psi = psi_new
+        if r2 < tol:
+            return psi, l + 1, r2
+    return psi, max_iter, r2
+
+
+def with_K(base_links, hx: float, K: float):
+    """Links of A~ = A - [K, 0, 0]: every x link gains the factor exp(i hx K)
+    (Eq. link_variables with Eq. psi_transformation)."""
+    lx, ly, lz = base_links
+    return (np.ascontiguousarray(lx * np.exp(1j * hx * K)), ly, lz)
+
+
+def step(grid: Grid, p: Params, eps: np.ndarray, st: State, in_window: bool = True,
+         base_links=None):
+    """One implicit time step in the order of Sec. 4.1: solve psi, then the
+    electric field and K, then mu~.
+
+    reading (step order): the paper's Sec. 3 introduction lists psi -> mu~ ->
+    K, its implementation section psi -> E/K -> mu~; the implementation order
+    is used.  Step n assembles with mu~_{n-1} and K_{n-1}; J_av uses
+    (psi_n, K_{n-1}); the Poisson right side uses (psi_n, K_n).
+    reading (K integrator): explicit Euler, K_n = K_{n-1} + dt (J_ext - J_av),
+    from Eq. K_ODE with dA/dt = 0 (large-lambda limit, Sec. 2.3) and
+    Eq. fig:KttoE; the voltage is accumulated from E_n, never from K.
+    reading (u): ht = dt/u (the footnote of Eq. GL_numCN), the i u mu~ term
+    keeps u, and K advances in real time dt.
+    """
+    ht = p.dt / p.u
+    base = base_links if base_links is not None else landau_links(grid, p.Bx, p.Bz, 0.0)
+    links = with_K(base, grid.hx, st.K)
+    mu = st.mu if p.driven else None
+    b, d = assemble(grid, links, st.psi, eps, mu, p.u, ht)
+    psi, sweeps, r2 = gl_solve(grid, links, b, d, ht, st.psi, p.tol, p.max_iter, p.mode)
+    st.psi = psi
+    st.last_sweeps, st.last_res2 = sweeps, r2
+    st.sweeps_hist.append(sweeps)
+    if p.driven:
+        Jav = jav(grid, links, psi)
+        E = p.J_ext - Jav
+        st.K = st.K + p.dt * E
+        if in_window:
+            st.V_sum += E
+            st.n_avg += 1
+        st.K = rewind_K(st.K, grid.hx)
+        st.last_E, st.last_Jav = E, Jav
+        links = with_K(base, grid.hx, st.K)
+        f = poisson_rhs(grid, links, psi)
+        st.mu = poisson_exact(grid, f)
+    st.n += 1
+    return st
+
+
+def run(grid, p, eps, st, nsteps, window_begin=0, base_links=None):
+    """Advance nsteps; the voltage window holds the steps with index >=
+    window_begin (counted from the state's step counter at entry).
+    base_links: links at K = 0 (default: Landau gauge of the field in p)."""
+    n0 = st.n
+    if base_links is None:
+        base_links = landau_links(grid, p.Bx, p.Bz, 0.0)
+    for s in range(nsteps):
+        step(grid, p, eps, st, in_window=(st.n - n0) >= window_begin, base_links=base_links)
+    return st
+
+
+def mean_E(st: State) -> float:
+    """Time-averaged electric field <E_x> over the voltage window; the
+    voltage across the sample is Lx <E_x>."""
+    return st.V_sum / max(st.n_avg, 1)
+
+
+# ---------------------------------------------------------------------------
+# Inclusion generator (Sec. 3.4)
+# ---------------------------------------------------------------------------
+def gen_inclusions(grid: Grid, centers: np.ndarray, diameters: np.ndarray,
+                   target: float, eps_in: float = -1.0, eps_out: float = 1.0):
+    """Random spherical inclusions modulating eps (Sec. 3.4, item (i); random
+    arrangement of spheres, Sec. 3.4 second paragraph).
+
+    reading: candidate spheres (centre, diameter) are taken in the given
+    order; sphere s is added and the covered-node count updated until
+    count >= target * N.  A node is inside a sphere iff, for some periodic
+    image of the node, ((dx*dx + dy*dy) + dz*dz) <= (d/2)*(d/2) in double
+    precision without fused multiply-add, where dx = u*hx - cx with u the
+    node's (unwrapped) integer coordinate.  Open axes are clipped, not
+    wrapped.  Returns (eps, spheres_used, covered_fraction).
+    """
+    nz, ny, nx = grid.shape
+    N = grid.N
+    covered = np.zeros(grid.shape, dtype=bool)
+    count = 0
+    used = 0
+    ns = (nx, ny, nz)
+    hs = (grid.hx, grid.hy, grid.hz)
+    need = target * float(N)
+    if need > 0:
+        for s in range(len(diameters)):
+            c = centers[s]
+            r = 0.5 * float(diameters[s])
+            r2 = r * r
+            rng_idx = []
+            rng_off = []
+            ok = True
+            for a in range(3):
+                lo = int(np.floor((c[a] - r) / hs[a])) - 1
+                hi = int(np.ceil((c[a] + r) / hs[a])) + 1
+                uu = np.arange(lo, hi + 1, dtype=np.int64)
+                if grid.open_[a]:
+                    uu = uu[(uu >= 0) & (uu < ns[a])]
+                d = uu.astype(np.float64) * hs[a] - c[a]
+                rng_idx.append(np.mod(uu, ns[a]))
+                rng_off.append(d)
+                if len(uu) == 0:
+                    ok = False
+            used = s + 1
+            if ok:
+                dx2 = rng_off[0] * rng_off[0]
+                dy2 = rng_off[1] * rng_off[1]
+                dz2 = rng_off[2] * rng_off[2]
+                d2 = (dx2[None, None, :] + dy2[None, :, None]) + dz2[:, None, None]
+                inside = d2 <= r2
+                kk, jj, ii = np.nonzero(inside)
+                K_ = rng_idx[2][kk]
+                J_ = rng_idx[1][jj]
+                I_ = rng_idx[0][ii]
+                newly = ~covered[K_, J_, I_]
+                # duplicates within one sphere (images mapping to one node)
+                sel = np.unique(np.stack([K_[newly], J_[newly], I_[newly]]), axis=1)
+                covered[sel[0], sel[1], sel[2]] = True
+                count += sel.shape[1]
+            if count >= need:
+                break
+    eps = np.where(covered, eps_in, eps_out).astype(np.float64)
+    return eps, used, count / N

@@ -1,0 +1,491 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix:
+dense brute force on tiny grids, closed forms, invariants and textbook
+special cases.  CPU only."""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import brute
+from oracle import oracle as O
+from paper_1409_8340_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rand_c(shape, seed, scale=1.0):
+    return inputs.random_complex(shape, seed, scale).astype(np.complex128)
+
+
+def _bc_grids():
+    """Every periodic/open combination on small ragged grids, g != 1."""
+    for ox, oy, oz in itertools.product([False, True], repeat=3):
+        yield O.Grid(4, 3, 5, 0.5, 0.6, 0.45, (ox, oy, oz), g=1.3)
+
+
+def _field(grid):
+    # a field that respects flux quantisation wherever it is required
+    Bx, Bz = O.quantize_field(grid, 0.37, 0.41)
+    if grid.open_[1] or grid.open_[2]:
+        Bx = 0.23
+    if grid.open_[0] or grid.open_[1]:
+        Bz = 0.31
+    return Bx, Bz
+
+
+# ---------------------------------------------------------------- brute force
+@pytest.mark.parametrize("grid", list(_bc_grids()), ids=lambda g: "open" + "".join(
+    "xyz"[a] for a in range(3) if g.open_[a]) or "periodic")
+def test_gl_system_matches_dense(grid):
+    Bx, Bz = _field(grid)
+    K = 0.7
+    psi = _rand_c(grid.shape, 1)
+    eps = inputs.random_real(grid.shape, 2, -1, 1).astype(np.float64)
+    mu = inputs.random_real(grid.shape, 3, -0.5, 0.5).astype(np.float64)
+    u, ht = 1.7, 0.1
+    links = O.with_K(O.landau_links(grid, Bx, Bz, 0.0), grid.hx, K)
+    M, b = brute.gl_system(grid, Bx, Bz, K, psi, eps, mu, u, ht)
+    b_o, d_o = O.assemble(grid, links, psi, eps, mu, u, ht)
+    np.testing.assert_allclose(b_o.reshape(-1), b, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(d_o.reshape(-1), np.diag(M), rtol=0, atol=1e-13)
+    v = _rand_c(grid.shape, 4)
+    np.testing.assert_allclose(O.apply_M(grid, links, d_o, ht, v).reshape(-1), M @ v.reshape(-1),
+                               rtol=0, atol=1e-12)
+    # EXACT mode against a dense LAPACK solve
+    x_dense = np.linalg.solve(M, b)
+    x, sweeps, r2 = O.gl_solve(grid, links, b_o, d_o, ht, psi, 0.0, 0, "exact")
+    np.testing.assert_allclose(x.reshape(-1), x_dense, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("grid", list(_bc_grids()), ids=lambda g: "open" + "".join(
+    "xyz"[a] for a in range(3) if g.open_[a]) or "periodic")
+def test_poisson_matches_dense(grid):
+    Bx, Bz = _field(grid)
+    K = -0.4
+    links = O.with_K(O.landau_links(grid, Bx, Bz, 0.0), grid.hx, K)
+    psi = _rand_c(grid.shape, 5)
+    f_b = brute.poisson_rhs(grid, Bx, Bz, K, psi)
+    f_o = O.poisson_rhs(grid, links, psi)
+    np.testing.assert_allclose(f_o.reshape(-1), f_b, rtol=0, atol=1e-12)
+    mu = inputs.random_real(grid.shape, 6).astype(np.float64)
+    A = brute.poisson_matrix(grid)
+    np.testing.assert_allclose(O.poisson_apply(grid, mu).reshape(-1), A @ mu.reshape(-1),
+                               rtol=0, atol=1e-12)
+    np.testing.assert_allclose(O.poisson_exact(grid, f_o).reshape(-1),
+                               brute.poisson_solve(grid, f_o), rtol=0, atol=1e-11)
+
+
+def test_laplacian_is_weighted_hermitian_and_negative():
+    """W L is Hermitian and negative semi-definite for every boundary kind."""
+    for grid in _bc_grids():
+        Bx, Bz = _field(grid)
+        L = brute.laplacian_matrix(grid, Bx, Bz, 0.3)
+        W = np.diag(brute.weights(grid))
+        WL = W @ L
+        np.testing.assert_allclose(WL, WL.conj().T, atol=1e-12)
+        assert np.linalg.eigvalsh(WL).max() < 1e-10
+        # oracle Laplacian agrees with the dense one
+        links = O.with_K(O.landau_links(grid, Bx, Bz, 0.0), grid.hx, 0.3)
+        v = _rand_c(grid.shape, 9)
+        np.testing.assert_allclose(O.laplacian(grid, links, v).reshape(-1), L @ v.reshape(-1),
+                                   atol=1e-12)
+
+
+# ---------------------------------------------------------------- closed forms
+def test_meissner_fixed_point():
+    """B = 0, uniform eps, psi = sqrt(eps) e^{i phi}: b = psi^-, M psi^- = b,
+    r^(0) = 0, and the state is a fixed point of any number of steps."""
+    grid = O.Grid(6, 5, 4)
+    eps = np.full(grid.shape, 0.7)
+    psi0 = np.full(grid.shape, np.sqrt(0.7) * np.exp(0.3j))
+    p = O.Params(Bx=0, Bz=0, mode="mirror", tol=1e-28, max_iter=3)
+    links = O.landau_links(grid, 0, 0, 0)
+    b, d = O.assemble(grid, links, psi0, eps, None, 1.0, 0.1)
+    np.testing.assert_allclose(b, psi0, atol=1e-15)
+    assert O.residual_max2(grid, links, b, d, 0.1, psi0) < 1e-30
+    st = O.new_state(grid, psi0)
+    O.run(grid, p, eps, st, 5)
+    np.testing.assert_allclose(st.psi, psi0, atol=1e-14)
+    assert st.sweeps_hist == [1] * 5  # residual of psi^- is already zero
+
+
+def test_scalar_recurrence():
+    """A uniform state at B = 0 stays uniform and follows
+    psi_n = psi_{n-1} [1 + ht/2 (eps - |psi|^2)] / [1 + ht/2 (|psi|^2 - eps)]."""
+    grid = O.Grid(4, 4, 3, open_=(False, True, True))
+    epsv, ht = 0.8, 0.1
+    eps = np.full(grid.shape, epsv)
+    a = 0.3 + 0.1j
+    st = O.new_state(grid, np.full(grid.shape, a))
+    p = O.Params(Bx=0, Bz=0, mode="exact")
+    for n in range(30):
+        O.step(grid, p, eps, st)
+        x2 = abs(a) ** 2
+        a = a * (1 + 0.5 * ht * (epsv - x2)) / (1 + 0.5 * ht * (x2 - epsv))
+        np.testing.assert_allclose(st.psi, a, rtol=1e-12, atol=0)
+    assert abs(abs(a) ** 2 - epsv) < 0.05  # relaxes towards |psi|^2 = eps
+
+
+def test_current_carrying_uniform_state():
+    """B = 0, psi~ = a uniform, U_x = e^{i hx K}: L psi = -(2-2cos hx K)/hx^2 psi,
+    J_av = a^2 sin(hx K)/hx, and with a^2 = eps - (2-2cos hx K)/hx^2 the
+    state is stationary (Sec. 2.2 with Eq. J_av)."""
+    grid = O.Grid(8, 4, 3, open_=(False, False, True))
+    hx, K, epsv = grid.hx, 0.5, 1.0
+    a2 = epsv - (2 - 2 * np.cos(hx * K)) / hx ** 2
+    psi = np.full(grid.shape, np.sqrt(a2) + 0j)
+    links = O.with_K(O.landau_links(grid, 0, 0, 0), hx, K)
+    lap = O.laplacian(grid, links, psi)
+    np.testing.assert_allclose(lap, -(2 - 2 * np.cos(hx * K)) / hx ** 2 * psi, atol=1e-14)
+    Jav = O.jav(grid, links, psi)
+    assert abs(Jav - a2 * np.sin(hx * K) / hx) < 1e-14
+    # driven at exactly that current: stationary, E = 0
+    p = O.Params(Bx=0, Bz=0, J_ext=Jav, driven=True, mode="exact")
+    st = O.new_state(grid, psi)
+    st.K = K
+    O.run(grid, p, np.full(grid.shape, epsv), st, 3)
+    np.testing.assert_allclose(st.psi, psi, atol=1e-13)
+    assert abs(st.last_E) < 1e-13 and abs(st.K - K) < 1e-13
+    assert np.max(np.abs(st.mu)) < 1e-12
+
+
+def test_driven_uniform_relaxes_to_current_root():
+    """Driven below the depairing maximum, K relaxes to the root of
+    J_ext = a(K)^2 sin(hx K)/hx on the stable branch and E -> 0."""
+    grid = O.Grid(4, 4, 4, open_=(False, False, False))
+    hx = grid.hx
+    Jext = 0.15
+    p = O.Params(Bx=0, Bz=0, J_ext=Jext, driven=True, mode="exact", dt=0.1)
+    st = O.new_state(grid, np.ones(grid.shape, complex))
+    O.run(grid, p, np.ones(grid.shape), st, 1500)
+    Ks = np.linspace(0, 0.6, 200001)
+    Jk = (1 - (2 - 2 * np.cos(hx * Ks)) / hx ** 2) * np.sin(hx * Ks) / hx
+    K_root = Ks[np.argmin(np.abs(Jk - Jext))]
+    assert abs(st.K - K_root) < 1e-4
+    assert abs(st.last_E) < 1e-6
+    assert abs(st.last_Jav - Jext) < 1e-6
+
+
+def test_depairing_current_closed_form():
+    """max_K of the uniform-state current tends to 2/(3 sqrt 3) eps^{3/2}
+    (~0.385, the footnote on the depairing current in Sec. 2.1) as hx -> 0,
+    using the oracle's J_av on uniform states."""
+    gold = json.load(open(os.path.join(GOLDEN, "paper_numbers.json")))
+    for hx, tol in [(0.05, 2e-3), (0.02, 4e-4)]:
+        grid = O.Grid(4, 2, 1, hx=hx, open_=(False, False, True))
+        best = 0.0
+        for K in np.linspace(0.45, 0.70, 251):
+            a2 = 1.0 - (2 - 2 * np.cos(hx * K)) / hx ** 2
+            links = O.with_K(O.landau_links(grid, 0, 0, 0), hx, K)
+            best = max(best, O.jav(grid, links, np.full(grid.shape, np.sqrt(a2) + 0j)))
+        assert abs(best - 2 / (3 * np.sqrt(3))) < tol
+        assert abs(best - gold["depairing_current"]["value"]) < 1e-3 + tol
+
+
+def test_normal_state_ohm():
+    """eps = -1: psi decays to 0, J_av -> 0, E -> J_ext (normal current,
+    sigma = 1 in reduced units)."""
+    grid = O.Grid(4, 4, 3)
+    p = O.Params(Bx=0, Bz=0, J_ext=0.04, driven=True, mode="exact")
+    st = O.new_state(grid, 0.05 * _rand_c(grid.shape, 3))
+    O.run(grid, p, -np.ones(grid.shape), st, 400)
+    assert np.max(np.abs(st.psi)) < 1e-6
+    assert abs(st.last_E - 0.04) < 1e-10
+
+
+def test_rewind_invariance():
+    """K -> K + 2 pi / hx changes no link and hence no result."""
+    grid = O.Grid(6, 4, 3)
+    Bx, Bz = O.quantize_field(grid, 0, 0.5)
+    eps = np.ones(grid.shape)
+    psi = inputs.psi_init(6, 4, 3, 7).astype(np.complex128)
+    out = []
+    for K in (0.3, 0.3 + 2 * np.pi / grid.hx):
+        st = O.new_state(grid, psi)
+        st.K = K
+        p = O.Params(Bx=Bx, Bz=Bz, J_ext=0.02, driven=True, mode="exact")
+        O.step(grid, p, eps, st)
+        out.append((st.psi.copy(), st.mu.copy(), st.last_E))
+    np.testing.assert_allclose(out[0][0], out[1][0], atol=1e-13)
+    np.testing.assert_allclose(out[0][1], out[1][1], atol=1e-12)
+    assert abs(out[0][2] - out[1][2]) < 1e-13
+    assert 0 <= O.rewind_K(0.3 + 5 * 2 * np.pi / grid.hx, grid.hx) < 2 * np.pi / grid.hx
+
+
+def test_gauge_covariance_of_step():
+    """psi' = e^{i chi} psi, U'_{m,m+a} = U_{m,m+a} e^{-i(chi_{m+a} - chi_m)}
+    (wrap edges included): one driven step maps covariantly, |psi|, F, f, mu~,
+    J_av and E are invariant."""
+    for open_ in [(False, False, True), (False, False, False), (False, True, True)]:
+        grid = O.Grid(6, 5, 4, open_=open_)
+        Bx, Bz = O.quantize_field(grid, 0.2 if open_[2] else 0.0, 0.4)
+        if open_[1]:
+            Bz = 0.3
+        base = O.landau_links(grid, Bx, Bz, 0.0)
+        chi = inputs.random_real(grid.shape, 11, -3, 3).astype(np.float64)
+        sh = lambda a, ax: np.roll(chi, -1, axis=ax)  # chi at m + axis (wrapped)
+        lxp = base[0] * np.exp(-1j * (sh(chi, 2) - chi))
+        lyp = base[1] * np.exp(-1j * (sh(chi, 1) - chi))
+        lzp = base[2] * np.exp(-1j * (sh(chi, 0) - chi))
+        basep = tuple(np.ascontiguousarray(x) for x in (lxp, lyp, lzp))
+        eps = inputs.random_real(grid.shape, 12, 0.2, 1.0).astype(np.float64)
+        psi = inputs.psi_init(6, 5, 4, 13).astype(np.complex128)
+        mu0 = inputs.random_real(grid.shape, 14, -0.1, 0.1).astype(np.float64)
+        p = O.Params(Bx=Bx, Bz=Bz, J_ext=0.03, driven=True, mode="exact")
+        a = O.new_state(grid, psi)
+        a.mu, a.K = mu0.copy(), 0.2
+        b = O.new_state(grid, np.exp(1j * chi) * psi)
+        b.mu, b.K = mu0.copy(), 0.2
+        Fa = O.free_energy(grid, O.with_K(base, grid.hx, 0.2), eps, a.psi)
+        Fb = O.free_energy(grid, O.with_K(basep, grid.hx, 0.2), eps, b.psi)
+        assert abs(Fa - Fb) < 1e-12 * abs(Fa)
+        O.step(grid, p, eps, a, base_links=base)
+        O.step(grid, p, eps, b, base_links=basep)
+        np.testing.assert_allclose(b.psi, np.exp(1j * chi) * a.psi, atol=1e-13)
+        np.testing.assert_allclose(b.mu, a.mu, atol=1e-12)
+        assert abs(a.last_Jav - b.last_Jav) < 1e-14
+        assert abs(a.last_E - b.last_E) < 1e-14
+
+
+def test_landau_levels_of_magnetic_laplacian():
+    """-L for B along z on a periodic grid (quasi-periodic y wrap) has the
+    Landau spectrum: the lowest n_z eigenvalues (n_z flux quanta) cluster at
+    ~B and the next band starts near 3B (textbook Landau levels
+    E_n = (2n+1) B, discretisation error O(B h^2))."""
+    grid = O.Grid(24, 24, 1, hx=0.5, hy=0.5, hz=0.5, open_=(False, False, True))
+    nq = 6
+    Bz = 2 * np.pi * nq / (grid.length(0) * grid.length(1))
+    L = brute.laplacian_matrix(grid, 0.0, Bz, 0.0)
+    ev = np.sort(np.linalg.eigvalsh(-0.5 * (L + L.conj().T)))
+    assert np.all(np.abs(ev[:nq] / Bz - 1) < 0.02)
+    assert np.all(np.abs(ev[nq:2 * nq] / Bz - 3) < 0.06)
+    # the oracle's Laplacian is that same operator
+    links = O.landau_links(grid, 0.0, Bz, 0.0)
+    v = _rand_c(grid.shape, 21)
+    np.testing.assert_allclose(O.laplacian(grid, links, v).reshape(-1), L @ v.reshape(-1),
+                               atol=1e-12)
+
+
+def test_harper_reduction():
+    """With B along z and periodic x, a Fourier mode e^{i q x} in x reduces
+    -L to Harper's tridiagonal operator in j with diagonal
+    (2 - 2 cos(hx (q + Bz ybar_j)))/hx^2 + 2/hy^2 and the wrap phase P."""
+    grid = O.Grid(12, 10, 1, open_=(False, False, True))
+    nq = 3
+    Bz = 2 * np.pi * nq / (grid.length(0) * grid.length(1))
+    links = O.landau_links(grid, 0.0, Bz, 0.0)
+    L = brute.laplacian_matrix(grid, 0.0, Bz, 0.0)
+    spec_full = np.sort(np.linalg.eigvalsh(-0.5 * (L + L.conj().T)))
+    Ly = grid.length(1)
+    spec = []
+    for qi in range(grid.nx):
+        q = 2 * np.pi * qi / grid.length(0)
+        H = np.zeros((grid.ny, grid.ny), complex)
+        for j in range(grid.ny):
+            yb = j * grid.hy - Ly / 2
+            H[j, j] = (2 - 2 * np.cos(grid.hx * (q + Bz * yb))) / grid.hx ** 2 + 2 / grid.hy ** 2
+        for j in range(grid.ny - 1):
+            H[j, j + 1] = H[j + 1, j] = -1 / grid.hy ** 2
+        spec.append(H)
+    # assemble the block operator over (q, j)
+    nxq = grid.nx
+    big = np.zeros((nxq * grid.ny, nxq * grid.ny), complex)
+    shift = int(round(Ly * Bz * grid.length(0) / (2 * np.pi)))
+    for qi in range(nxq):
+        big[qi * grid.ny:(qi + 1) * grid.ny, qi * grid.ny:(qi + 1) * grid.ny] = spec[qi]
+        qo = (qi + shift) % nxq
+        # the wrap link conj(P_i) = e^{-i x_i Ly Bz} feeds the input mode
+        # q + Ly Bz at j = 0 into the output mode q at j = ny-1 (and back)
+        big[qi * grid.ny + grid.ny - 1, qo * grid.ny + 0] += -1 / grid.hy ** 2
+        big[qo * grid.ny + 0, qi * grid.ny + grid.ny - 1] += -1 / grid.hy ** 2
+    spec_harper = np.sort(np.linalg.eigvalsh(big))
+    np.testing.assert_allclose(spec_harper, spec_full, atol=1e-10)
+    v = _rand_c(grid.shape, 22)
+    np.testing.assert_allclose(O.laplacian(grid, links, v).reshape(-1), L @ v.reshape(-1),
+                               atol=1e-12)
+
+
+# ---------------------------------------------------------------- identities
+def test_jacobi_residual_identity():
+    grid = O.Grid(6, 5, 4)
+    Bx, Bz = O.quantize_field(grid, 0.0, 0.4)
+    links = O.with_K(O.landau_links(grid, Bx, Bz, 0.0), grid.hx, 0.1)
+    psi = inputs.psi_init(6, 5, 4, 3).astype(np.complex128)
+    eps = np.ones(grid.shape)
+    mu = inputs.random_real(grid.shape, 4, -0.2, 0.2).astype(np.float64)
+    b, d = O.assemble(grid, links, psi, eps, mu, 1.0, 0.1)
+    x = _rand_c(grid.shape, 5)
+    _, r2 = O.jacobi_sweep(grid, links, b, d, 0.1, x)
+    assert abs(r2 - O.residual_max2(grid, links, b, d, 0.1, x)) < 1e-12 * r2
+
+
+def test_jav_symmetric_equals_one_sided():
+    grid = O.Grid(6, 5, 4)
+    Bx, Bz = O.quantize_field(grid, 0.0, 0.4)
+    links = O.with_K(O.landau_links(grid, Bx, Bz, 0.0), grid.hx, 0.37)
+    psi = _rand_c(grid.shape, 8)
+    one = np.sum(np.imag(np.conj(psi) * links[0] * np.roll(psi, -1, axis=2))) / (grid.N * grid.hx)
+    assert abs(O.jav(grid, links, psi) - one) < 1e-14
+
+
+def test_poisson_rhs_identities():
+    """sum_m w_m f_m = 0 (discrete divergence theorem) and f = Im[psi^* L psi]."""
+    for grid in _bc_grids():
+        Bx, Bz = _field(grid)
+        links = O.with_K(O.landau_links(grid, Bx, Bz, 0.0), grid.hx, 0.2)
+        psi = _rand_c(grid.shape, 31)
+        f = O.poisson_rhs(grid, links, psi)
+        scale = np.sum(np.abs(f))
+        assert abs(O.weighted_sum(grid, f)) < 1e-13 * scale
+        np.testing.assert_allclose(f, np.imag(np.conj(psi) * O.laplacian(grid, links, psi)),
+                                   atol=1e-12)
+
+
+def test_poisson_manufactured_modes():
+    """Delta_h applied to a product of Fourier / cosine modes multiplies it by
+    -(sum of the 1D eigenvalues); the exact solver recovers any mu* up to its
+    weighted mean."""
+    grid = O.Grid(8, 6, 5, 0.5, 0.7, 0.4, (False, False, True), g=1.2)
+    i = np.arange(8)[None, None, :]
+    j = np.arange(6)[None, :, None]
+    k = np.arange(5)[:, None, None]
+    mode = np.cos(2 * np.pi * 3 * i / 8) * np.cos(2 * np.pi * 1 * j / 6) * np.cos(np.pi * 2 * k / 4)
+    lam = ((2 - 2 * np.cos(2 * np.pi * 3 / 8)) / 0.25 + (2 - 2 * np.cos(2 * np.pi / 6)) / 0.49
+           + (2 - 2 * np.cos(np.pi * 2 / 4)) / (1.44 * 0.16))
+    np.testing.assert_allclose(O.poisson_apply(grid, mode), -lam * mode, atol=1e-12)
+    mus = inputs.random_real(grid.shape, 41).astype(np.float64)
+    w = O.node_weights(grid)
+    rec = O.poisson_exact(grid, O.poisson_apply(grid, mus))
+    np.testing.assert_allclose(rec, mus - np.sum(w * mus) / np.sum(w), atol=1e-12)
+    assert abs(O.weighted_sum(grid, rec)) < 1e-12
+
+
+def test_free_energy_gradient_identity():
+    """dF/dpsi*_m = -w_m h^3 (eps psi - |psi|^2 psi + L psi)_m, checked by
+    central differences on a 4^3 grid with open faces."""
+    grid = O.Grid(4, 4, 4, 0.5, 0.5, 0.5, (False, True, True), g=1.1)
+    Bx, Bz = 0.2, 0.3
+    links = O.with_K(O.landau_links(grid, Bx, Bz, 0.0), grid.hx, 0.25)
+    psi = _rand_c(grid.shape, 51, 0.7)
+    eps = inputs.random_real(grid.shape, 52, -1, 1).astype(np.float64)
+    w = O.node_weights(grid)
+    h3 = grid.hx * grid.hy * grid.hz
+    rhs = eps * psi - np.abs(psi) ** 2 * psi + O.laplacian(grid, links, psi)
+    rng = np.random.default_rng(0)
+    for m in rng.choice(grid.N, 12, replace=False):
+        idx = np.unravel_index(m, grid.shape)
+        d = 1e-6
+        g = np.zeros(2)
+        for c, dd in enumerate((d, 1j * d)):
+            pp = psi.copy()
+            pm = psi.copy()
+            pp[idx] += dd
+            pm[idx] -= dd
+            g[c] = (O.free_energy(grid, links, eps, pp) - O.free_energy(grid, links, eps, pm)) / (2 * d)
+        grad_conj = 0.5 * (g[0] + 1j * g[1])  # dF/dpsi* = (dF/dRe + i dF/dIm)/2
+        expect = -w[idx] * h3 * rhs[idx]
+        assert abs(grad_conj - expect) < 1e-6 * max(1.0, abs(expect))
+
+
+def test_free_energy_meissner_and_zero_decay():
+    grid = O.Grid(5, 4, 4)
+    epsv = 0.6
+    eps = np.full(grid.shape, epsv)
+    psi = np.full(grid.shape, np.sqrt(epsv) * np.exp(1.1j))
+    links = O.landau_links(grid, 0, 0, 0)
+    w = O.node_weights(grid)
+    F = O.free_energy(grid, links, eps, psi)
+    assert abs(F - (-(epsv ** 2) / 2) * np.sum(w) * grid.hx * grid.hy * grid.hz) < 1e-13
+    st = O.new_state(grid, psi)
+    O.run(grid, O.Params(mode="exact"), eps, st, 3)
+    assert abs(O.free_energy(grid, links, eps, st.psi) - F) < 1e-13
+
+
+def test_diagonal_dominance_bound():
+    """M is strictly diagonally dominant when ht max(eps) < 2; the Jacobi
+    contraction factor is then below ht S / (1 + ht/2 (2S - max eps))."""
+    grid = O.Grid(8, 8, 4)
+    Bx, Bz = O.quantize_field(grid, 0, 0.3)
+    links = O.landau_links(grid, Bx, Bz, 0)
+    psi = inputs.psi_init(8, 8, 4, 61).astype(np.complex128)
+    eps = np.ones(grid.shape)
+    b, d = O.assemble(grid, links, psi, eps, None, 1.0, 0.1)
+    S = 3 / 0.25
+    rho = 0.1 * S / (1 + 0.05 * (2 * S - 1))
+    x = np.zeros(grid.shape, complex)
+    exact, _, _ = O.gl_solve(grid, links, b, d, 0.1, psi, 0, 0, "exact")
+    e_prev = np.max(np.abs(x - exact))
+    for _ in range(10):
+        x, _ = O.jacobi_sweep(grid, links, b, d, 0.1, x)
+        e = np.max(np.abs(x - exact))
+        assert e <= rho * e_prev * (1 + 1e-9)
+        e_prev = e
+
+
+def test_nan_propagates_to_residual():
+    grid = O.Grid(4, 4, 4)
+    links = O.landau_links(grid, 0, 0, 0)
+    psi = np.ones(grid.shape, complex)
+    psi[1, 2, 3] = np.nan
+    b, d = O.assemble(grid, links, psi, np.ones(grid.shape), None, 1.0, 0.1)
+    _, r2 = O.jacobi_sweep(grid, links, b, d, 0.1, psi)
+    assert np.isnan(r2)
+
+
+# ---------------------------------------------------------------- inclusions
+def _brute_inside(grid, c, dia):
+    """Node-by-node, image-by-image membership test (no bounding boxes)."""
+    out = np.zeros(grid.shape, bool)
+    ns = (grid.nx, grid.ny, grid.nz)
+    hs = (grid.hx, grid.hy, grid.hz)
+    r = 0.5 * dia
+    for k in range(grid.nz):
+        for j in range(grid.ny):
+            for i in range(grid.nx):
+                pos = (i, j, k)
+                best = False
+                shifts = [[0] if grid.open_[a] else [-1, 0, 1] for a in range(3)]
+                for sx in shifts[0]:
+                    for sy in shifts[1]:
+                        for sz in shifts[2]:
+                            u = (pos[0] + sx * ns[0], pos[1] + sy * ns[1], pos[2] + sz * ns[2])
+                            d = [u[a] * hs[a] - c[a] for a in range(3)]
+                            if (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2] <= r * r:
+                                best = True
+                out[k, j, i] = best
+    return out
+
+
+def test_inclusion_generator_against_brute_force():
+    grid = O.Grid(10, 9, 7, open_=(False, False, True))
+    L = [grid.length(a) for a in range(3)]
+    c, dia = inputs.sphere_candidates(L, 40, 77, law="uniform", d_lo=1.5, d_hi=3.0)
+    target = 0.2
+    eps, used, frac = O.gen_inclusions(grid, c, dia, target)
+    cover = np.zeros(grid.shape, bool)
+    for s in range(used):
+        cover |= _brute_inside(grid, c[s], dia[s])
+    np.testing.assert_array_equal(eps < 0, cover)
+    assert frac >= target
+    # one sphere fewer does not reach the target
+    prev = np.zeros(grid.shape, bool)
+    for s in range(used - 1):
+        prev |= _brute_inside(grid, c[s], dia[s])
+    assert prev.sum() < target * grid.N
+    # achieved fraction exceeds the target by less than one sphere volume
+    vol = np.pi / 6 * dia[0] ** 3 / (grid.hx * grid.hy * grid.hz)
+    assert frac < target + vol / grid.N + 1e-12
+
+
+def test_inclusion_generator_statistics():
+    w = inputs.Workload("t", 64, 64, 16, fraction=0.10, law="fixed", d=4.0, incl_seed=5)
+    grid = O.Grid(64, 64, 16)
+    c, dia = inputs.candidates_for(w)
+    eps1, used1, frac1 = O.gen_inclusions(grid, c, dia, 0.10)
+    eps2, used2, frac2 = O.gen_inclusions(grid, c, dia, 0.10)
+    assert used1 == used2 and np.array_equal(eps1, eps2)
+    assert 0.10 <= frac1 < 0.10 + (np.pi / 6 * 64) / grid.N
+    assert used1 > 10 and used1 < len(dia)
+    assert set(np.unique(eps1)) == {-1.0, 1.0}
