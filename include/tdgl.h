@@ -1,0 +1,224 @@
+/*
+ * tdgl.h -- C ABI of libtdgl, an MI355X (gfx950) solver for the implicit
+ * time step of the time-dependent Ginzburg-Landau equations in the form of
+ * Sadovskyy, Koshelev, Phillips, Karpeyev and Glatz, "Stable large-scale
+ * solver for Ginzburg-Landau equations for superconductors"
+ * (arXiv:1409.8340).
+ *
+ * Model (reduced units of Sec. 2.1: lengths in xi_0, time in t_0, field in
+ * H_c2(0), current in J_0):
+ *     u (d/dt + i mu~) psi~ = eps(r) psi~ - |psi~|^2 psi~ + (grad - i A~)^2 psi~
+ * (Eq. GL_external_current, noise term zero) with a uniform field in the xz
+ * plane in the Landau gauge A = ybar [-Bz, 0, Bx] (Sec. 2.3, Eq. A_xz),
+ * A~ = A - [K, 0, 0], the current phase K(t) driven by Eq. K_ODE and the
+ * scalar potential mu~ from the Poisson equation of Sec. 2.2.
+ *
+ * Conventions shared by every entry point
+ *   - A context holds one or more independent instances ("batch").  Calls
+ *     that act on one instance take its index `inst` (0 for a single one).
+ *   - Every array argument is a DEVICE pointer into memory the caller owns,
+ *     on the device that was current at tdgl_create.  Scalars and the small
+ *     structs below are host memory.
+ *   - Grid arrays are laid out x fastest: element m = i + nx*(j + ny*k)
+ *     (Sec. 3).  Complex values are interleaved single precision
+ *     (re, im) pairs, i.e. the layout of float2 / torch.complex64.
+ *   - The library allocates no device memory.  All device state lives in a
+ *     caller-supplied workspace of tdgl_plan() bytes (256-byte aligned) that
+ *     must outlive the context.  It allocates a few hundred bytes of pinned
+ *     host memory per context for convergence polling.
+ *   - Work is enqueued on the stream given at tdgl_create.  Calls return
+ *     after enqueueing unless documented as synchronising.
+ *   - Every function returns a tdgl_status.  On failure nothing is enqueued
+ *     and tdgl_last_error() (per calling thread) describes the problem.  No
+ *     exception or abort crosses this interface.
+ */
+#ifndef TDGL_H
+#define TDGL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int tdgl_status;
+#define TDGL_OK 0
+#define TDGL_EINVAL 1    /* invalid argument or parameter combination      */
+#define TDGL_EWS 2       /* workspace missing, misaligned or too small      */
+#define TDGL_ENOCONV 3   /* strict mode: a solve hit its iteration cap      */
+#define TDGL_EDEVICE 4   /* HIP runtime error (message names the call)      */
+#define TDGL_ESTATE 5    /* call not valid in the context's current state   */
+
+#define TDGL_PERIODIC 0  /* periodic; quasi-periodic y when the field needs it (Sec. 3.3.1) */
+#define TDGL_OPEN 1      /* open / Neumann face, zero normal current (Sec. 3.3.2)          */
+
+#define TDGL_MAX_ITER 256   /* upper bound for tdgl_params.max_iter    */
+#define TDGL_MAX_CYCLES 64  /* upper bound for tdgl_params.mu_max_cycles */
+
+/* Parameters of one instance.  The mesh of Sec. 3: nodes x = i hx,
+ * y = j hy, z = k hz; system size L = n h on periodic axes and (n-1) h on
+ * open axes. */
+typedef struct tdgl_params {
+    int nx, ny, nz;       /* nodes per axis, >= 1; nx*ny*nz < 2^31          */
+    double hx, hy, hz;    /* mesh spacing (xi_0), > 0                        */
+    int bc[3];            /* TDGL_PERIODIC or TDGL_OPEN for x, y, z          */
+    double g;             /* anisotropy (Sec. 2.1): z terms carry 1/g^2      */
+    double u;             /* relaxation constant u of Eq. GL_dimensionless   */
+    double dt;            /* time step; the CN step uses ht = dt / u         */
+    double tol;           /* stop when max_m |r_m|^2 < tol (Eq. convergence) */
+    int max_iter;         /* Jacobi sweep cap per step (1..TDGL_MAX_ITER)    */
+    int driven;           /* 1: solve K and mu~ (Sec. 2.2); 0: K = mu~ = 0    */
+    double mu_tol;        /* Poisson stop: max_m |Delta mu~ - f|_m < mu_tol  */
+    int mu_max_cycles;    /* multigrid cycle cap per step (1..TDGL_MAX_CYCLES) */
+    int strict;           /* 1: tdgl_step returns TDGL_ENOCONV on a capped solve */
+    int tile_cz;          /* z planes per stencil work-group; 0 = library default */
+    int reserved[7];      /* must be zero */
+} tdgl_params;
+
+/* Per-call statistics of tdgl_step (filled only when a pointer is given;
+ * that makes the call synchronising). */
+typedef struct tdgl_step_stats {
+    int steps;              /* steps advanced                                  */
+    int sweeps_min, sweeps_max;
+    long long sweeps_sum;   /* Jacobi sweeps over all steps                    */
+    int capped_steps;       /* steps whose Jacobi solve hit max_iter           */
+    float last_res2;        /* max |r|^2 of the last sweep's input iterate     */
+    int mu_cycles_sum;      /* multigrid cycles over all steps                 */
+    int mu_capped_steps;    /* steps whose Poisson solve hit mu_max_cycles      */
+    float mu_last_res;      /* last Poisson residual max-norm                  */
+} tdgl_step_stats;
+
+/* Scalars that, with psi~ and mu~, make up the full state (exact resume). */
+typedef struct tdgl_scalars {
+    double K;        /* current phase of Eq. psi_transformation              */
+    double t;        /* simulated time                                       */
+    double V_sum;    /* sum of E_x over the steps in the voltage window      */
+    long long n;     /* steps taken                                          */
+    long long n_avg; /* steps in the voltage window                          */
+    double E_last;   /* E_x of the last step                                 */
+    double J_av_last;/* J_av of the last step (Sec. 3.1.1)                   */
+} tdgl_scalars;
+
+/* Observables, reduced in double precision on the device. */
+typedef struct tdgl_obs {
+    double F;        /* GL free energy of the current psi~ (see tdgl_observables) */
+    double E_last;   /* E_x = J_ext - J_av of the last step                  */
+    double E_mean;   /* V_sum / n_avg: time-averaged electric field          */
+    double V_mean;   /* Lx * E_mean: time-averaged voltage across the sample */
+    double J_av;     /* J_av of the last step                                */
+    double K;        /* current phase                                        */
+    double res2_last;/* last Jacobi max |r|^2                                */
+    double mu_mean_w;/* weighted mean of mu~ as stored (the solver subtracts it) */
+    double psi2_mean;/* mean |psi~|^2                                        */
+    long long n, n_avg;
+} tdgl_obs;
+
+typedef struct tdgl_ctx tdgl_ctx;
+
+/* Thread-local description of the last failure on this thread. */
+const char *tdgl_last_error(void);
+
+/* Validates `n` parameter sets and returns the workspace size in bytes a
+ * context holding them needs.  Host only; touches no device.  Rejects an
+ * open x axis together with driven = 1 (a current along x needs periodic x,
+ * Sec. 3.3.2). */
+tdgl_status tdgl_plan(int n, const tdgl_params *params, size_t *ws_bytes);
+
+/* Creates a context with `n` instances on the current device, carving all
+ * device state out of `ws` (ws_bytes >= tdgl_plan's result, 256-byte
+ * aligned).  `stream` is a hipStream_t (NULL: the default stream).  Every
+ * instance starts with psi~ = 1, mu~ = 0, K = 0, eps = 1, B = 0, J = 0.
+ * Synchronising (uploads small coefficient tables). */
+tdgl_status tdgl_create(int n, const tdgl_params *params, void *ws, size_t ws_bytes,
+                        void *stream, tdgl_ctx **out);
+
+/* Destroys the context (the workspace stays the caller's).  Synchronising. */
+tdgl_status tdgl_destroy(tdgl_ctx *ctx);
+
+/* Number of instances in the context. */
+tdgl_status tdgl_size(const tdgl_ctx *ctx, int *n);
+
+/* Host-only helper: the field rounded to whole flux quanta through the
+ * periodic cross sections (Sec. 3.3.1, "Implications for the magnetic
+ * field"): Bz = 2 pi n_z / (Lx Ly) if x and y are periodic, Bx =
+ * 2 pi n_x / (Ly Lz) if y and z are periodic; other components unchanged. */
+tdgl_status tdgl_quantize_field(const tdgl_params *p, double Bx, double Bz,
+                                double *Bx_eff, double *Bz_eff);
+
+/* Sets the uniform field in the xz plane (Eq. B_xz) and rebuilds the link
+ * tables (Eq. link_variables, Sec. 3.3.1 phase jump).  quantize = 1 rounds
+ * as tdgl_quantize_field and reports the result; quantize = 0 requires the
+ * field to be quantised already (relative error 1e-9), else TDGL_EINVAL. */
+tdgl_status tdgl_set_field(tdgl_ctx *ctx, int inst, double Bx, double Bz, int quantize,
+                           double *Bx_eff, double *Bz_eff);
+
+/* Sets the applied current density J_x,ext (Eq. J_external).  Requires a
+ * driven instance unless J_ext == 0. */
+tdgl_status tdgl_set_current(tdgl_ctx *ctx, int inst, double J_ext);
+
+/* Copies eps (float[N], Eq. epsilon on the grid nodes, Sec. 3.4 (i)). */
+tdgl_status tdgl_set_eps(tdgl_ctx *ctx, int inst, const float *eps);
+
+/* Inclusion generator (Sec. 3.4): candidate spheres (centres double[3*nc]
+ * as x,y,z triples in xi_0; diameters double[nc]) are added in order until
+ * the covered node fraction reaches `target`; nodes inside an added sphere
+ * (any periodic image; open axes clipped; |r_m - c|^2 <= (d/2)^2 evaluated
+ * in double precision without fused multiply-add) get eps_in, all others
+ * eps_out.  Reports the number of spheres used and the covered fraction.
+ * Synchronising.  Uses the instance's scalar-potential arrays as scratch,
+ * so call it before stepping. */
+tdgl_status tdgl_gen_inclusions(tdgl_ctx *ctx, int inst, const double *centres,
+                                const double *diameters, int nc, double target,
+                                float eps_in, float eps_out, int *n_used, double *fraction);
+
+/* Copies the instance's eps (float[N]) out, e.g. after tdgl_gen_inclusions. */
+tdgl_status tdgl_get_eps(tdgl_ctx *ctx, int inst, float *eps);
+
+/* psi~ in/out: complex64[N].  mu~ in/out: float[N] (weighted mean removed
+ * on output). */
+tdgl_status tdgl_set_psi(tdgl_ctx *ctx, int inst, const void *psi);
+tdgl_status tdgl_get_psi(tdgl_ctx *ctx, int inst, void *psi);
+tdgl_status tdgl_set_mu(tdgl_ctx *ctx, int inst, const float *mu);
+tdgl_status tdgl_get_mu(tdgl_ctx *ctx, int inst, float *mu);
+
+/* Scalars for exact resume.  Synchronising. */
+tdgl_status tdgl_get_scalars(tdgl_ctx *ctx, int inst, tdgl_scalars *s);
+tdgl_status tdgl_set_scalars(tdgl_ctx *ctx, int inst, const tdgl_scalars *s);
+
+/* Starts a new voltage-averaging window (V_sum = n_avg = 0). */
+tdgl_status tdgl_voltage_window_reset(tdgl_ctx *ctx, int inst);
+
+/*
+ * Advances every instance by nsteps implicit time steps.  One step
+ * (Sec. 3.1, 3.2 and the kernel sequence of Sec. 4.1):
+ *   1. assemble b and diag(M) of Eq. GL_linearized / Eq. b from psi^-,
+ *      eps, mu~ and the links at K (|psi|^2 lagged, Eq. GL_numCN);
+ *   2. Jacobi iterations of Eq. final from psi^(0) = psi^- until the input
+ *      residual of a sweep satisfies Eq. convergence (max|r|^2 < tol) or
+ *      max_iter; that sweep's output is the new psi~;
+ *   3. driven only: J_av (Sec. 3.1.1), E_x = J_ext - J_av, K += dt E_x,
+ *      voltage sum, phase rewind K -> K - (2 pi/hx) floor(K hx / 2 pi)
+ *      (Sec. 2.2);
+ *   4. driven only: Poisson equation of Sec. 3.2 for mu~ with the links at
+ *      the new K, solved by multigrid V-cycles whose smoother is the
+ *      pseudo-time relaxation of Sec. 3.2 (damped Jacobi) until
+ *      max|Delta mu~ - f| < mu_tol; weighted mean of mu~ fixed to zero.
+ * Enqueues work and waits on small device-to-host copies of the
+ * convergence words.  stats may be NULL.  With strict = 1, returns
+ * TDGL_ENOCONV after the first step whose Jacobi solve hit max_iter.
+ */
+tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats);
+
+/* Observables of one instance: F is the discrete GL free energy
+ *   hx hy hz [ sum_m w_m (-eps_m |psi_m|^2 + |psi_m|^4 / 2)
+ *              + sum_edges w_e |U_e psi_{m+a} - psi_m|^2 / (g_a^2 h_a^2) ]
+ * (w: 1/2 per open face containing the node or edge), whose derivative by
+ * psi*_m is -w_m hx hy hz times the right side of Eq. GL_dimensionless.
+ * Synchronising. */
+tdgl_status tdgl_observables(tdgl_ctx *ctx, int inst, tdgl_obs *obs);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TDGL_H */

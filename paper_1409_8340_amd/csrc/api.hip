@@ -1,0 +1,1024 @@
+// api.hip -- host side of the libtdgl C ABI (see include/tdgl.h).
+//
+// The host validates parameters, lays out the caller's workspace, builds the
+// small coefficient tables of the multigrid hierarchy in double precision,
+// and enqueues the kernels of each step.  Convergence of the Jacobi and
+// multigrid loops is decided on the device (every launch first checks the
+// previous iteration's residual word and exits when the solve has
+// finished); the host only decides how many launches to enqueue, reading the
+// residual words one iteration behind the device so that the GPU never waits
+// for the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "tdgl.h"
+
+using namespace tdgl;
+
+namespace {
+
+thread_local std::string g_err;
+
+tdgl_status fail(tdgl_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIPCHK(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(TDGL_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));  \
+    } while (0)
+
+#define LAUNCHCHK()                                                                    \
+    do {                                                                               \
+        hipError_t e_ = hipGetLastError();                                             \
+        if (e_ != hipSuccess)                                                          \
+            return fail(TDGL_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr float kOmega = 6.0f / 7.0f;  // smoother damping (pseudo time step)
+constexpr int kCoarsestMax = 4096;     // nodes the one-work-group coarse solve accepts
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// multigrid hierarchy (host description)
+struct AxisLevel {
+    int n = 0;
+    bool per = false;
+    std::vector<double> pos;  // node positions (open axes)
+    std::vector<double> am, ap, vol;
+    bool can = false;         // can be coarsened further
+};
+
+// One axis through all levels: periodic axes halve while even and >= 4;
+// open axes keep nodes {0, 2, 4, ...} plus the last one while n >= 3.
+std::vector<AxisLevel> axis_levels(int n, double h, bool per, double cf) {
+    std::vector<AxisLevel> out;
+    std::vector<double> pos(n);
+    for (int i = 0; i < n; ++i) pos[i] = i * h;
+    const double Lp = n * h;
+    for (;;) {
+        AxisLevel a;
+        a.n = (int)pos.size();
+        a.per = per;
+        a.pos = pos;
+        a.am.assign(a.n, 0.0);
+        a.ap.assign(a.n, 0.0);
+        a.vol.assign(a.n, 0.0);
+        if (per) {
+            const double hl = Lp / a.n;
+            for (int i = 0; i < a.n; ++i) { a.am[i] = a.ap[i] = cf / (hl * hl); a.vol[i] = hl; }
+            a.can = (a.n % 2 == 0) && a.n >= 4;
+        } else {
+            if (a.n == 1) {
+                a.vol[0] = 1.0;
+            } else {
+                for (int i = 0; i < a.n; ++i) {
+                    const double dm = i > 0 ? pos[i] - pos[i - 1] : 0.0;
+                    const double dp = i < a.n - 1 ? pos[i + 1] - pos[i] : 0.0;
+                    a.vol[i] = 0.5 * (dm + dp);
+                    a.am[i] = dm > 0 ? cf / (dm * a.vol[i]) : 0.0;
+                    a.ap[i] = dp > 0 ? cf / (dp * a.vol[i]) : 0.0;
+                }
+            }
+            a.can = a.n >= 3;
+        }
+        out.push_back(a);
+        if (!a.can) break;
+        std::vector<double> np;
+        if (per) {
+            for (int i = 0; i < a.n; i += 2) np.push_back(pos[i]);
+        } else {
+            for (int i = 0; i < a.n; i += 2) np.push_back(pos[i]);
+            if ((a.n - 1) % 2 != 0) np.push_back(pos[a.n - 1]);
+        }
+        pos = np;
+    }
+    return out;
+}
+
+// 1D transfer between a fine and a coarse axis level (coarse == fine when
+// the axis is not coarsened at this level).
+struct Transfer1D {
+    std::vector<int> pk;    // 2 per fine index
+    std::vector<float> pw;
+    std::vector<int> rk;    // 3 per coarse index
+    std::vector<float> rw;
+};
+
+Transfer1D make_transfer(const AxisLevel &f, const AxisLevel &c, bool coarsened) {
+    Transfer1D t;
+    const int nf = f.n, nc = c.n;
+    std::vector<std::vector<std::pair<int, double>>> P(nf);  // fine -> (coarse, w)
+    if (!coarsened) {
+        for (int k = 0; k < nf; ++k) P[k].push_back({k, 1.0});
+    } else if (f.per) {
+        for (int k = 0; k < nf; ++k) {
+            const int K = k / 2;
+            if (k % 2 == 0) P[k].push_back({K, 1.0});
+            else { P[k].push_back({K, 0.5}); P[k].push_back({(K + 1) % nc, 0.5}); }
+        }
+    } else {
+        for (int k = 0; k < nf; ++k) {
+            const double x = f.pos[k];
+            int j = (int)(std::lower_bound(c.pos.begin(), c.pos.end(), x - 1e-12) - c.pos.begin());
+            if (j < nc && std::fabs(c.pos[j] - x) < 1e-9) {
+                P[k].push_back({j, 1.0});
+            } else {
+                const int K0 = j - 1, K1 = j;
+                const double w1 = (x - c.pos[K0]) / (c.pos[K1] - c.pos[K0]);
+                P[k].push_back({K0, 1.0 - w1});
+                P[k].push_back({K1, w1});
+            }
+        }
+    }
+    t.pk.resize(2 * nf);
+    t.pw.resize(2 * nf);
+    for (int k = 0; k < nf; ++k) {
+        t.pk[2 * k] = P[k][0].first;
+        t.pw[2 * k] = (float)P[k][0].second;
+        t.pk[2 * k + 1] = P[k].size() > 1 ? P[k][1].first : P[k][0].first;
+        t.pw[2 * k + 1] = P[k].size() > 1 ? (float)P[k][1].second : 0.f;
+    }
+    // restriction R[K][k] = P[k][K] V_f[k] / V_c[K]
+    std::vector<std::vector<std::pair<int, double>>> R(nc);
+    for (int k = 0; k < nf; ++k)
+        for (auto &e : P[k]) R[e.first].push_back({k, e.second * f.vol[k] / c.vol[e.first]});
+    t.rk.resize(3 * nc);
+    t.rw.resize(3 * nc);
+    for (int K = 0; K < nc; ++K) {
+        if (R[K].size() > 3) { /* cannot happen for factor-2 coarsening */ }
+        for (int a = 0; a < 3; ++a) {
+            if (a < (int)R[K].size()) { t.rk[3 * K + a] = R[K][a].first; t.rw[3 * K + a] = (float)R[K][a].second; }
+            else { t.rk[3 * K + a] = R[K].empty() ? 0 : R[K][0].first; t.rw[3 * K + a] = 0.f; }
+        }
+    }
+    return t;
+}
+
+struct LevelHost {
+    int n[3];
+    AxisLevel ax[3];
+    Transfer1D tr[3];  // to the next coarser level
+    long N;
+};
+
+struct Hierarchy {
+    std::vector<LevelHost> lev;
+    bool ok = true;
+};
+
+Hierarchy build_hierarchy(const tdgl_params &p) {
+    Hierarchy H;
+    const int ns[3] = {p.nx, p.ny, p.nz};
+    const double hs[3] = {p.hx, p.hy, p.hz};
+    const double cf[3] = {1.0, 1.0, 1.0 / (p.g * p.g)};
+    std::vector<AxisLevel> A[3];
+    for (int a = 0; a < 3; ++a) A[a] = axis_levels(ns[a], hs[a], p.bc[a] == TDGL_PERIODIC, cf[a]);
+    int li[3] = {0, 0, 0};
+    for (;;) {
+        LevelHost L;
+        for (int a = 0; a < 3; ++a) { L.ax[a] = A[a][li[a]]; L.n[a] = L.ax[a].n; }
+        L.N = (long)L.n[0] * L.n[1] * L.n[2];
+        bool can[3];
+        bool any = false;
+        for (int a = 0; a < 3; ++a) { can[a] = L.ax[a].can; any = any || can[a]; }
+        if (!any || L.N <= 512 || (int)H.lev.size() == kMaxLevels - 1) {
+            H.lev.push_back(L);
+            break;
+        }
+        int nl[3];
+        for (int a = 0; a < 3; ++a) {
+            nl[a] = li[a] + (can[a] ? 1 : 0);
+            L.tr[a] = make_transfer(A[a][li[a]], A[a][nl[a]], can[a]);
+        }
+        H.lev.push_back(L);
+        for (int a = 0; a < 3; ++a) li[a] = nl[a];
+    }
+    if (H.lev.back().N > kCoarsestMax) H.ok = false;
+    return H;
+}
+
+// ---------------------------------------------------------------------------
+// validation and layout
+tdgl_status validate(const tdgl_params &p, int idx) {
+    if (p.nx < 1 || p.ny < 1 || p.nz < 1)
+        return fail(TDGL_EINVAL, "instance %d: grid sizes must be >= 1", idx);
+    if ((long)p.nx * p.ny * p.nz >= (1L << 31))
+        return fail(TDGL_EINVAL, "instance %d: nx*ny*nz must be < 2^31", idx);
+    if (!(p.hx > 0) || !(p.hy > 0) || !(p.hz > 0))
+        return fail(TDGL_EINVAL, "instance %d: mesh spacings must be > 0", idx);
+    for (int a = 0; a < 3; ++a)
+        if (p.bc[a] != TDGL_PERIODIC && p.bc[a] != TDGL_OPEN)
+            return fail(TDGL_EINVAL, "instance %d: bc[%d] must be TDGL_PERIODIC or TDGL_OPEN", idx, a);
+    if (!(p.g > 0) || !(p.u > 0) || !(p.dt > 0))
+        return fail(TDGL_EINVAL, "instance %d: g, u and dt must be > 0", idx);
+    if (!(p.tol > 0)) return fail(TDGL_EINVAL, "instance %d: tol must be > 0", idx);
+    if (p.max_iter < 1 || p.max_iter > TDGL_MAX_ITER)
+        return fail(TDGL_EINVAL, "instance %d: max_iter must be in [1, %d]", idx, TDGL_MAX_ITER);
+    if (p.driven != 0 && p.driven != 1) return fail(TDGL_EINVAL, "instance %d: driven must be 0 or 1", idx);
+    if (p.driven) {
+        if (p.bc[0] == TDGL_OPEN)
+            return fail(TDGL_EINVAL,
+                        "instance %d: a current along x needs a periodic x axis (open x with driven=1)", idx);
+        if (!(p.mu_tol > 0)) return fail(TDGL_EINVAL, "instance %d: mu_tol must be > 0", idx);
+        if (p.mu_max_cycles < 1 || p.mu_max_cycles > TDGL_MAX_CYCLES)
+            return fail(TDGL_EINVAL, "instance %d: mu_max_cycles must be in [1, %d]", idx, TDGL_MAX_CYCLES);
+        Hierarchy H = build_hierarchy(p);
+        if (!H.ok)
+            return fail(TDGL_EINVAL,
+                        "instance %d: the grid cannot be coarsened below %d nodes for the Poisson "
+                        "multigrid (periodic axes need even sizes)", idx, kCoarsestMax);
+    }
+    if (p.tile_cz < 0 || p.tile_cz > 1024) return fail(TDGL_EINVAL, "instance %d: tile_cz out of range", idx);
+    if (p.strict != 0 && p.strict != 1) return fail(TDGL_EINVAL, "instance %d: strict must be 0 or 1", idx);
+    for (int r = 0; r < 7; ++r)
+        if (p.reserved[r] != 0) return fail(TDGL_EINVAL, "instance %d: reserved fields must be zero", idx);
+    return TDGL_OK;
+}
+
+int auto_chunk(long tiles_xy, int nz, int req) {
+    if (req > 0) return std::min(req, nz);
+    // enough work-groups to fill 256 CUs several times, long enough z runs
+    long c = (long)nz * tiles_xy / 4096;
+    c = std::max(1L, std::min(32L, c));
+    return (int)std::min<long>(c, nz);
+}
+
+// Carves one context's workspace.  With base == nullptr only sizes are
+// computed.  Fills the host copies of the device descriptors.
+struct Carver {
+    char *base;
+    size_t off = 0;
+    template <class T>
+    T *take(size_t count) {
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off = align_up(off + count * sizeof(T));
+        return p;
+    }
+};
+
+struct InstHost {
+    tdgl_params p;
+    Inst d;
+    Hierarchy H;
+    int st_blocks = 0, flat_blocks = 0;
+    int mg_blocks[kMaxLevels] = {0};
+    double Bx = 0, Bz = 0, J = 0;
+};
+
+}  // namespace
+
+struct tdgl_ctx {
+    int n = 0;
+    std::vector<InstHost> inst;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    Inst *d_inst = nullptr;
+    // prefix tables of the batched launches; multigrid ones per level:
+    // "all" = instances that have level l, "mid" = instances for which level
+    // l is not the coarsest (kMaxLevels * (n+1) each)
+    int *d_pref_st = nullptr, *d_pref_flat = nullptr, *d_pref_mg = nullptr, *d_pref_mid = nullptr;
+    int *d_np_st = nullptr, *d_np_flat = nullptr, *d_np_mg0 = nullptr;
+    unsigned *d_res = nullptr, *d_mures = nullptr;
+    unsigned *h_res = nullptr, *h_mures = nullptr;  // pinned
+    std::vector<hipEvent_t> ev, evc;
+    int tot_st = 0, tot_flat = 0, tot_mg[kMaxLevels] = {0}, tot_mid[kMaxLevels] = {0};
+    int nlev_max = 0;
+    bool any_driven = false;
+    int max_iter = 1, max_cycles = 1;
+};
+
+namespace {
+
+size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
+    Carver cv{base};
+    std::vector<InstHost> local;
+    std::vector<InstHost> &ih = ctx ? ctx->inst : local;
+    ih.assign(n, InstHost());
+    int max_iter = 1, max_cycles = 1;
+    for (int i = 0; i < n; ++i) {
+        max_iter = std::max(max_iter, params[i].max_iter);
+        if (params[i].driven) max_cycles = std::max(max_cycles, params[i].mu_max_cycles);
+    }
+    // context-level arrays
+    Inst *d_inst = cv.take<Inst>(n);
+    int *pref_st = cv.take<int>(n + 1);
+    int *pref_flat = cv.take<int>(n + 1);
+    int *pref_mg = cv.take<int>((size_t)kMaxLevels * (n + 1));
+    int *pref_mid = cv.take<int>((size_t)kMaxLevels * (n + 1));
+    int *np_st = cv.take<int>(n);
+    int *np_flat = cv.take<int>(n);
+    int *np_mg0 = cv.take<int>(n);
+    unsigned *res = cv.take<unsigned>((size_t)max_iter * n);
+    unsigned *mures = cv.take<unsigned>((size_t)max_cycles * n);
+    for (int i = 0; i < n; ++i) {
+        const tdgl_params &p = params[i];
+        InstHost &h = ih[i];
+        h.p = p;
+        Inst &d = h.d;
+        memset(&d, 0, sizeof d);
+        d.nx = p.nx; d.ny = p.ny; d.nz = p.nz;
+        const long N = (long)p.nx * p.ny * p.nz;
+        d.N = (int)N;
+        for (int a = 0; a < 3; ++a) d.per[a] = p.bc[a] == TDGL_PERIODIC;
+        d.driven = p.driven;
+        const bool dx = !(p.bc[0] == TDGL_OPEN && p.nx == 1), dy = !(p.bc[1] == TDGL_OPEN && p.ny == 1),
+                   dz = !(p.bc[2] == TDGL_OPEN && p.nz == 1);
+        d.cx = dx ? (float)(1.0 / (p.hx * p.hx)) : 0.f;
+        d.cy = dy ? (float)(1.0 / (p.hy * p.hy)) : 0.f;
+        d.cz = dz ? (float)(1.0 / (p.g * p.g * p.hz * p.hz)) : 0.f;
+        const double S = (dx ? 1.0 / (p.hx * p.hx) : 0) + (dy ? 1.0 / (p.hy * p.hy) : 0) +
+                         (dz ? 1.0 / (p.g * p.g * p.hz * p.hz) : 0);
+        d.S2 = (float)(2.0 * S);
+        d.ht2 = (float)(0.5 * p.dt / p.u);
+        d.u = (float)p.u;
+        d.tol = (float)p.tol;
+        d.mu_tol = (float)p.mu_tol;
+        d.hx = p.hx; d.hy = p.hy; d.hz = p.hz; d.dt = p.dt;
+        {
+            auto wsum = [](int nn, bool open) { return open && nn > 1 ? nn - 1.0 : (double)nn; };
+            d.w_sum = wsum(p.nx, p.bc[0] == TDGL_OPEN) * wsum(p.ny, p.bc[1] == TDGL_OPEN) *
+                      wsum(p.nz, p.bc[2] == TDGL_OPEN);
+        }
+        d.psi[0] = cv.take<float2>(N);
+        d.psi[1] = cv.take<float2>(N);
+        d.bh = cv.take<float2>(N);
+        d.dh = cv.take<float2>(N);
+        d.eps = cv.take<float>(N);
+        d.ux = cv.take<float2>(p.ny);
+        d.uz = cv.take<float2>(p.ny);
+        d.P = cv.take<float2>((size_t)p.nx * p.nz);
+        d.st = cv.take<DevState>(1);
+        d.res = res ? res + i : nullptr;
+        d.mures = mures ? mures + i : nullptr;
+        d.rstride = n;
+        d.max_iter = p.max_iter;
+        d.mu_max_cycles = p.driven ? p.mu_max_cycles : 1;
+        // stencil tiling
+        const long txy = (long)cdiv(p.nx, TX) * cdiv(p.ny, TY);
+        d.tiles_x = cdiv(p.nx, TX);
+        d.tiles_y = cdiv(p.ny, TY);
+        d.chunk = auto_chunk(txy, p.nz, p.tile_cz);
+        d.tiles_z = cdiv(p.nz, d.chunk);
+        h.st_blocks = (int)(txy * d.tiles_z);
+        h.flat_blocks = cdiv(N, 256L * JAV_CPT);
+        int part_cap = std::max(h.st_blocks, h.flat_blocks);
+        // multigrid
+        if (p.driven) {
+            h.H = build_hierarchy(p);
+            d.nlev = (int)h.H.lev.size();
+            for (int l = 0; l < d.nlev; ++l) {
+                LevelHost &LH = h.H.lev[l];
+                MGLevel &L = d.lev[l];
+                L.nx = LH.n[0]; L.ny = LH.n[1]; L.nz = LH.n[2];
+                L.N = (int)LH.N;
+                for (int a = 0; a < 3; ++a) {
+                    L.per[a] = LH.ax[a].per;
+                    L.am[a] = cv.take<float>(LH.n[a]);
+                    L.ap[a] = cv.take<float>(LH.n[a]);
+                    L.vol[a] = cv.take<float>(LH.n[a]);
+                }
+                double vs = 1.0;
+                for (int a = 0; a < 3; ++a) {
+                    double s = 0;
+                    for (double v : LH.ax[a].vol) s += v;
+                    vs *= s;
+                }
+                L.vsum = vs;
+                if (l == 0) {
+                    L.rhs = cv.take<float>(N);
+                    L.mu[0] = cv.take<float>(N);
+                    L.mu[1] = cv.take<float>(N);
+                    L.r = cv.take<float>(N);
+                } else {
+                    L.rhs = cv.take<float>(LH.N);
+                    L.mu[0] = cv.take<float>(LH.N);
+                    L.mu[1] = cv.take<float>(LH.N);
+                    L.r = cv.take<float>(LH.N);
+                }
+                if (l + 1 < d.nlev) {
+                    for (int a = 0; a < 3; ++a) {
+                        L.pk[a] = cv.take<int>(2 * LH.n[a]);
+                        L.pw[a] = cv.take<float>(2 * LH.n[a]);
+                        L.rk[a] = cv.take<int>(3 * h.H.lev[l + 1].n[a]);
+                        L.rw[a] = cv.take<float>(3 * h.H.lev[l + 1].n[a]);
+                    }
+                }
+                const long mtxy = (long)cdiv(L.nx, MTX) * cdiv(L.ny, MTY);
+                L.tiles_x = cdiv(L.nx, MTX);
+                L.tiles_y = cdiv(L.ny, MTY);
+                L.chunk = auto_chunk(mtxy, L.nz, 0);
+                L.tiles_z = cdiv(L.nz, L.chunk);
+                h.mg_blocks[l] = (int)(mtxy * L.tiles_z);
+            }
+            d.mu = d.lev[0].mu[0];
+            d.f = d.lev[0].rhs;
+            part_cap = std::max(part_cap, h.mg_blocks[0]);
+        }
+        d.part = cv.take<double>(part_cap);
+        d.part_cap = part_cap;
+    }
+    if (ctx) {
+        ctx->n = n;
+        ctx->d_inst = d_inst;
+        ctx->d_pref_st = pref_st;
+        ctx->d_pref_flat = pref_flat;
+        ctx->d_pref_mg = pref_mg;
+        ctx->d_pref_mid = pref_mid;
+        ctx->d_np_st = np_st;
+        ctx->d_np_flat = np_flat;
+        ctx->d_np_mg0 = np_mg0;
+        ctx->d_res = res;
+        ctx->d_mures = mures;
+        ctx->max_iter = max_iter;
+        ctx->max_cycles = max_cycles;
+    }
+    return cv.off;
+}
+
+tdgl_status check_ctx(tdgl_ctx *ctx, int inst) {
+    if (!ctx) return fail(TDGL_EINVAL, "null context");
+    if (inst < 0 || inst >= ctx->n) return fail(TDGL_EINVAL, "instance index %d out of range [0, %d)", inst, ctx->n);
+    return TDGL_OK;
+}
+
+int fill_grid(long n) { return (int)std::min<long>(std::max<long>(cdiv(n, 256), 1), 8192); }
+
+tdgl_status upload_tables(tdgl_ctx *ctx) {
+    for (int i = 0; i < ctx->n; ++i) {
+        InstHost &h = ctx->inst[i];
+        if (!h.p.driven) continue;
+        for (int l = 0; l < h.d.nlev; ++l) {
+            LevelHost &LH = h.H.lev[l];
+            MGLevel &L = h.d.lev[l];
+            for (int a = 0; a < 3; ++a) {
+                std::vector<float> am(LH.ax[a].am.begin(), LH.ax[a].am.end());
+                std::vector<float> ap(LH.ax[a].ap.begin(), LH.ax[a].ap.end());
+                std::vector<float> vol(LH.ax[a].vol.begin(), LH.ax[a].vol.end());
+                HIPCHK(hipMemcpy((void *)L.am[a], am.data(), am.size() * 4, hipMemcpyHostToDevice));
+                HIPCHK(hipMemcpy((void *)L.ap[a], ap.data(), ap.size() * 4, hipMemcpyHostToDevice));
+                HIPCHK(hipMemcpy((void *)L.vol[a], vol.data(), vol.size() * 4, hipMemcpyHostToDevice));
+                if (l + 1 < h.d.nlev) {
+                    Transfer1D &t = LH.tr[a];
+                    HIPCHK(hipMemcpy((void *)L.pk[a], t.pk.data(), t.pk.size() * 4, hipMemcpyHostToDevice));
+                    HIPCHK(hipMemcpy((void *)L.pw[a], t.pw.data(), t.pw.size() * 4, hipMemcpyHostToDevice));
+                    HIPCHK(hipMemcpy((void *)L.rk[a], t.rk.data(), t.rk.size() * 4, hipMemcpyHostToDevice));
+                    HIPCHK(hipMemcpy((void *)L.rw[a], t.rw.data(), t.rw.size() * 4, hipMemcpyHostToDevice));
+                }
+            }
+        }
+    }
+    // prefix tables
+    const int n = ctx->n;
+    std::vector<int> ps(n + 1, 0), pf(n + 1, 0), pm((size_t)kMaxLevels * (n + 1), 0),
+        pmid((size_t)kMaxLevels * (n + 1), 0);
+    std::vector<int> nps(n), npf(n), npm(n);
+    for (int i = 0; i < n; ++i) {
+        InstHost &h = ctx->inst[i];
+        ps[i + 1] = ps[i] + h.st_blocks;
+        pf[i + 1] = pf[i] + h.flat_blocks;
+        nps[i] = h.st_blocks;
+        npf[i] = h.flat_blocks;
+        npm[i] = h.p.driven ? h.mg_blocks[0] : 0;
+        for (int l = 0; l < kMaxLevels; ++l) {
+            const size_t o = (size_t)l * (n + 1) + i;
+            const int b = (h.p.driven && l < h.d.nlev) ? h.mg_blocks[l] : 0;
+            const int bm = (h.p.driven && l + 1 < h.d.nlev) ? h.mg_blocks[l] : 0;
+            pm[o + 1] = pm[o] + b;
+            pmid[o + 1] = pmid[o] + bm;
+        }
+    }
+    ctx->tot_st = ps[n];
+    ctx->tot_flat = pf[n];
+    for (int l = 0; l < kMaxLevels; ++l) {
+        ctx->tot_mg[l] = pm[(size_t)l * (n + 1) + n];
+        ctx->tot_mid[l] = pmid[(size_t)l * (n + 1) + n];
+    }
+    HIPCHK(hipMemcpy(ctx->d_pref_mid, pmid.data(), pmid.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_pref_st, ps.data(), (n + 1) * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_pref_flat, pf.data(), (n + 1) * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_pref_mg, pm.data(), pm.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_np_st, nps.data(), n * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_np_flat, npf.data(), n * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_np_mg0, npm.data(), n * 4, hipMemcpyHostToDevice));
+    std::vector<Inst> di(n);
+    for (int i = 0; i < n; ++i) di[i] = ctx->inst[i].d;
+    HIPCHK(hipMemcpy(ctx->d_inst, di.data(), n * sizeof(Inst), hipMemcpyHostToDevice));
+    return TDGL_OK;
+}
+
+const int *pref_mg(tdgl_ctx *c, int l) { return c->d_pref_mg + (size_t)l * (c->n + 1); }
+const int *pref_mid(tdgl_ctx *c, int l) { return c->d_pref_mid + (size_t)l * (c->n + 1); }
+
+// One multigrid V-cycle for every driven instance (cycle index cyc).
+// Instances may have hierarchies of different depth: each per-level launch
+// covers only the instances the operation applies to (prefix tables with
+// zero blocks for the others), and the one-group coarse solve runs every
+// instance on its own coarsest level.  Per instance and level the sequence
+// is V(2,2) with damped-Jacobi smoothing; the finest level starts a cycle
+// with its residual (the convergence test) and ends it with four sweeps.
+tdgl_status enqueue_vcycle(tdgl_ctx *c, int cyc) {
+    hipStream_t s = c->stream;
+    const int n = c->n;
+    const int L = c->nlev_max;
+    auto grid = [](int b) { return dim3(std::max(b, 1)); };
+    hipLaunchKernelGGL(k_mg_residual, grid(c->tot_mg[0]), dim3(256), 0, s, c->d_inst, pref_mg(c, 0), n, 0, 0,
+                       cyc);
+    for (int l = 0; l + 1 < L; ++l) {
+        if (l >= 1) {
+            hipLaunchKernelGGL(k_mg_smooth, grid(c->tot_mid[l]), dim3(256), 0, s, c->d_inst, pref_mid(c, l), n,
+                               l, 0, 1, cyc, kOmega);
+            hipLaunchKernelGGL(k_mg_residual, grid(c->tot_mid[l]), dim3(256), 0, s, c->d_inst, pref_mid(c, l),
+                               n, l, 1, cyc);
+        }
+        // restrict into level l+1 for the instances that have it
+        hipLaunchKernelGGL(k_mg_restrict, grid(c->tot_mg[l + 1]), dim3(256), 0, s, c->d_inst,
+                           pref_mg(c, l + 1), n, l, cyc, kOmega);
+    }
+    hipLaunchKernelGGL(k_mg_coarsest, dim3(n), dim3(CO_THREADS), 0, s, c->d_inst, n, cyc);
+    for (int l = L - 2; l >= 0; --l) {
+        const int ifine = (l == 0) ? 0 : 1;
+        hipLaunchKernelGGL(k_mg_prolong, grid(c->tot_mid[l]), dim3(256), 0, s, c->d_inst, pref_mid(c, l), n, l,
+                           ifine, cyc);
+        const int nsm = (l == 0) ? 4 : 2;
+        for (int it = 0; it < nsm; ++it) {
+            const int a = (l == 0) ? (it & 1) : ((it & 1) ^ 1);
+            hipLaunchKernelGGL(k_mg_smooth, grid(c->tot_mid[l]), dim3(256), 0, s, c->d_inst, pref_mid(c, l), n,
+                               l, a, a ^ 1, cyc, kOmega);
+        }
+    }
+    LAUNCHCHK();
+    return TDGL_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+extern "C" {
+
+const char *tdgl_last_error(void) { return g_err.c_str(); }
+
+tdgl_status tdgl_plan(int n, const tdgl_params *params, size_t *ws_bytes) {
+    if (n < 1 || !params || !ws_bytes) return fail(TDGL_EINVAL, "tdgl_plan: need n >= 1 and non-null pointers");
+    for (int i = 0; i < n; ++i) {
+        tdgl_status s = validate(params[i], i);
+        if (s) return s;
+    }
+    *ws_bytes = layout(n, params, nullptr, nullptr);
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_create(int n, const tdgl_params *params, void *ws, size_t ws_bytes, void *stream,
+                        tdgl_ctx **out) {
+    if (!out) return fail(TDGL_EINVAL, "tdgl_create: null output pointer");
+    *out = nullptr;
+    size_t need = 0;
+    tdgl_status s = tdgl_plan(n, params, &need);
+    if (s) return s;
+    if (!ws || ((uintptr_t)ws % kAlign) != 0)
+        return fail(TDGL_EWS, "tdgl_create: workspace missing or not %zu-byte aligned", kAlign);
+    if (ws_bytes < need) return fail(TDGL_EWS, "tdgl_create: workspace has %zu bytes, needs %zu", ws_bytes, need);
+    tdgl_ctx *c = new tdgl_ctx();
+    c->ws = (char *)ws;
+    c->ws_bytes = ws_bytes;
+    c->stream = (hipStream_t)stream;
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; return fail(TDGL_EDEVICE, "hipGetDevice failed"); }
+    layout(n, params, (char *)ws, c);
+    c->nlev_max = 0;
+    for (auto &h : c->inst) {
+        c->any_driven = c->any_driven || h.p.driven;
+        c->nlev_max = std::max(c->nlev_max, h.d.nlev);
+    }
+    auto bail = [&](tdgl_status st) { tdgl_destroy(c); return st; };
+    if (hipHostMalloc((void **)&c->h_res, (size_t)c->max_iter * n * 4, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_mures, (size_t)c->max_cycles * n * 4, hipHostMallocDefault) != hipSuccess)
+        return bail(fail(TDGL_EDEVICE, "hipHostMalloc of the polling buffers failed"));
+    c->ev.resize(c->max_iter);
+    c->evc.resize(c->max_cycles);
+    for (auto &e : c->ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            return bail(fail(TDGL_EDEVICE, "hipEventCreate failed"));
+    for (auto &e : c->evc)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            return bail(fail(TDGL_EDEVICE, "hipEventCreate failed"));
+    if ((s = upload_tables(c))) return bail(s);
+    // initial state: psi = 1, eps = 1, mu = 0, B = 0, K = 0
+    hipStream_t st = c->stream;
+    for (int i = 0; i < n; ++i) {
+        Inst &d = c->inst[i].d;
+        const long N = d.N;
+        hipLaunchKernelGGL(k_fill_c, dim3(fill_grid(N)), dim3(256), 0, st, d.psi[0], N, 1.f, 0.f);
+        hipLaunchKernelGGL(k_fill_c, dim3(fill_grid(N)), dim3(256), 0, st, d.psi[1], N, 1.f, 0.f);
+        hipLaunchKernelGGL(k_fill_f, dim3(fill_grid(N)), dim3(256), 0, st, d.eps, N, 1.f);
+        if (d.driven)
+            for (int l = 0; l < d.nlev; ++l) {
+                MGLevel &L = d.lev[l];
+                hipLaunchKernelGGL(k_fill_f, dim3(fill_grid(L.N)), dim3(256), 0, st, L.mu[0], (long)L.N, 0.f);
+                hipLaunchKernelGGL(k_fill_f, dim3(fill_grid(L.N)), dim3(256), 0, st, L.mu[1], (long)L.N, 0.f);
+                hipLaunchKernelGGL(k_fill_f, dim3(fill_grid(L.N)), dim3(256), 0, st, L.rhs, (long)L.N, 0.f);
+                hipLaunchKernelGGL(k_fill_f, dim3(fill_grid(L.N)), dim3(256), 0, st, L.r, (long)L.N, 0.f);
+            }
+        HIPCHK(hipMemsetAsync(d.st, 0, sizeof(DevState), st));
+        hipLaunchKernelGGL(k_state_set, dim3(1), dim3(1), 0, st, c->d_inst, i, 11, 1.0);  // in window
+    }
+    hipLaunchKernelGGL(k_fill_u, dim3(1), dim3(256), 0, st, c->d_res, (long)c->max_iter * n, 0u);
+    hipLaunchKernelGGL(k_fill_u, dim3(1), dim3(256), 0, st, c->d_mures, (long)c->max_cycles * n, 0u);
+    hipLaunchKernelGGL(k_links, dim3(n), dim3(256), 0, st, c->d_inst, 0);
+    LAUNCHCHK();
+    if (hipStreamSynchronize(st) != hipSuccess) return bail(fail(TDGL_EDEVICE, "initialisation failed"));
+    *out = c;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_destroy(tdgl_ctx *ctx) {
+    if (!ctx) return TDGL_OK;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto &e : ctx->ev) if (e) (void)hipEventDestroy(e);
+    for (auto &e : ctx->evc) if (e) (void)hipEventDestroy(e);
+    if (ctx->h_res) (void)hipHostFree(ctx->h_res);
+    if (ctx->h_mures) (void)hipHostFree(ctx->h_mures);
+    delete ctx;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_size(const tdgl_ctx *ctx, int *n) {
+    if (!ctx || !n) return fail(TDGL_EINVAL, "null argument");
+    *n = ctx->n;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_quantize_field(const tdgl_params *p, double Bx, double Bz, double *Bx_eff, double *Bz_eff) {
+    if (!p || !Bx_eff || !Bz_eff) return fail(TDGL_EINVAL, "null argument");
+    const double twopi = 6.283185307179586476925286766559;
+    auto len = [](int n, double h, int bc) { return bc == TDGL_OPEN ? (n - 1) * h : n * h; };
+    const double Lx = len(p->nx, p->hx, p->bc[0]), Ly = len(p->ny, p->hy, p->bc[1]),
+                 Lz = len(p->nz, p->hz, p->bc[2]);
+    if (p->bc[0] == TDGL_PERIODIC && p->bc[1] == TDGL_PERIODIC)
+        Bz = twopi * std::nearbyint(Bz * Lx * Ly / twopi) / (Lx * Ly);
+    if (p->bc[1] == TDGL_PERIODIC && p->bc[2] == TDGL_PERIODIC)
+        Bx = twopi * std::nearbyint(Bx * Ly * Lz / twopi) / (Ly * Lz);
+    *Bx_eff = Bx;
+    *Bz_eff = Bz;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_set_field(tdgl_ctx *ctx, int inst, double Bx, double Bz, int quantize, double *Bx_eff,
+                           double *Bz_eff) {
+    tdgl_status s = check_ctx(ctx, inst);
+    if (s) return s;
+    if (!std::isfinite(Bx) || !std::isfinite(Bz)) return fail(TDGL_EINVAL, "field must be finite");
+    double qx, qz;
+    tdgl_quantize_field(&ctx->inst[inst].p, Bx, Bz, &qx, &qz);
+    if (!quantize) {
+        auto off = [](double a, double b) { return std::fabs(a - b) > 1e-9 * std::max(1.0, std::fabs(b)); };
+        if (off(Bx, qx) || off(Bz, qz))
+            return fail(TDGL_EINVAL,
+                        "field (%.9g, %.9g) is not a whole number of flux quanta through the periodic "
+                        "cross sections (nearest: %.9g, %.9g); pass quantize=1", Bx, Bz, qx, qz);
+        qx = Bx;
+        qz = Bz;
+    }
+    ctx->inst[inst].Bx = qx;
+    ctx->inst[inst].Bz = qz;
+    hipLaunchKernelGGL(k_state_set, dim3(1), dim3(1), 0, ctx->stream, ctx->d_inst, inst, 8, qx);
+    hipLaunchKernelGGL(k_state_set, dim3(1), dim3(1), 0, ctx->stream, ctx->d_inst, inst, 9, qz);
+    // rebuild the tables of this instance only: launch over all with a
+    // single-instance view (the kernel reads the descriptor by block index)
+    hipLaunchKernelGGL(k_links, dim3(1), dim3(256), 0, ctx->stream, ctx->d_inst + inst, 0);
+    LAUNCHCHK();
+    if (Bx_eff) *Bx_eff = qx;
+    if (Bz_eff) *Bz_eff = qz;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_set_current(tdgl_ctx *ctx, int inst, double J) {
+    tdgl_status s = check_ctx(ctx, inst);
+    if (s) return s;
+    if (!std::isfinite(J)) return fail(TDGL_EINVAL, "current must be finite");
+    if (J != 0.0 && !ctx->inst[inst].p.driven)
+        return fail(TDGL_EINVAL, "instance %d is not driven (driven=0): only J_ext = 0 is allowed", inst);
+    ctx->inst[inst].J = J;
+    hipLaunchKernelGGL(k_state_set, dim3(1), dim3(1), 0, ctx->stream, ctx->d_inst, inst, 7, J);
+    LAUNCHCHK();
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_set_eps(tdgl_ctx *ctx, int inst, const float *eps) {
+    tdgl_status s = check_ctx(ctx, inst);
+    if (s) return s;
+    if (!eps) return fail(TDGL_EINVAL, "null eps");
+    const Inst &d = ctx->inst[inst].d;
+    HIPCHK(hipMemcpyAsync(d.eps, eps, (size_t)d.N * 4, hipMemcpyDeviceToDevice, ctx->stream));
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_get_eps(tdgl_ctx *ctx, int inst, float *eps) {
+    tdgl_status s = check_ctx(ctx, inst);
+    if (s) return s;
+    if (!eps) return fail(TDGL_EINVAL, "null eps");
+    const Inst &d = ctx->inst[inst].d;
+    HIPCHK(hipMemcpyAsync(eps, d.eps, (size_t)d.N * 4, hipMemcpyDeviceToDevice, ctx->stream));
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_gen_inclusions(tdgl_ctx *ctx, int inst, const double *centres, const double *diameters,
+                                int nc, double target, float eps_in, float eps_out, int *n_used,
+                                double *fraction) {
+    tdgl_status s = check_ctx(ctx, inst);
+    if (s) return s;
+    const Inst &d = ctx->inst[inst].d;
+    if (nc < 0 || nc > d.N) return fail(TDGL_EINVAL, "candidate count must be in [0, N]");
+    if (nc > 0 && (!centres || !diameters)) return fail(TDGL_EINVAL, "null candidate arrays");
+    if (!(target >= 0.0 && target <= 1.0)) return fail(TDGL_EINVAL, "target fraction must be in [0, 1]");
+    // scratch: first covering index (N words) and histogram (nc words) in bh
+    unsigned *first = reinterpret_cast<unsigned *>(d.bh);
+    unsigned *cnt = first + d.N;
+    hipStream_t st = ctx->stream;
+    hipLaunchKernelGGL(k_fill_u, dim3(fill_grid(d.N)), dim3(256), 0, st, first, (long)d.N, 0xffffffffu);
+    if (nc > 0) {
+        hipLaunchKernelGGL(k_fill_u, dim3(fill_grid(nc)), dim3(256), 0, st, cnt, (long)nc, 0u);
+        hipLaunchKernelGGL(k_incl_first, dim3(nc), dim3(256), 0, st, ctx->d_inst, inst, centres, diameters, nc,
+                           first);
+        hipLaunchKernelGGL(k_incl_count, dim3(fill_grid(d.N)), dim3(256), 0, st, first, (long)d.N, nc, cnt);
+    }
+    hipLaunchKernelGGL(k_incl_scan, dim3(1), dim3(1024), 0, st, ctx->d_inst, inst, cnt, nc, target);
+    hipLaunchKernelGGL(k_incl_write, dim3(fill_grid(d.N)), dim3(256), 0, st, ctx->d_inst, inst, first, eps_in,
+                       eps_out);
+    LAUNCHCHK();
+    DevState h;
+    HIPCHK(hipMemcpyAsync(&h, d.st, sizeof h, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (n_used) *n_used = h.n_used;
+    if (fraction) *fraction = h.frac;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_set_psi(tdgl_ctx *ctx, int inst, const void *psi) {
+    tdgl_status s = check_ctx(ctx, inst);
+    if (s) return s;
+    if (!psi) return fail(TDGL_EINVAL, "null psi");
+    hipLaunchKernelGGL(k_psi_io, dim3(fill_grid(ctx->inst[inst].d.N)), dim3(256), 0, ctx->stream, ctx->d_inst,
+                       inst, (float2 *)psi, 0);
+    LAUNCHCHK();
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_get_psi(tdgl_ctx *ctx, int inst, void *psi) {
+    tdgl_status s = check_ctx(ctx, inst);
+    if (s) return s;
+    if (!psi) return fail(TDGL_EINVAL, "null psi");
+    hipLaunchKernelGGL(k_psi_io, dim3(fill_grid(ctx->inst[inst].d.N)), dim3(256), 0, ctx->stream, ctx->d_inst,
+                       inst, (float2 *)psi, 1);
+    LAUNCHCHK();
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_set_mu(tdgl_ctx *ctx, int inst, const float *mu) {
+    tdgl_status s = check_ctx(ctx, inst);
+    if (s) return s;
+    if (!mu) return fail(TDGL_EINVAL, "null mu");
+    if (!ctx->inst[inst].p.driven) return fail(TDGL_ESTATE, "instance %d is not driven: mu is identically 0", inst);
+    hipLaunchKernelGGL(k_mu_io, dim3(fill_grid(ctx->inst[inst].d.N)), dim3(256), 0, ctx->stream, ctx->d_inst,
+                       inst, (float *)mu, 0);
+    hipLaunchKernelGGL(k_state_set, dim3(1), dim3(1), 0, ctx->stream, ctx->d_inst, inst, 10, 0.0);
+    LAUNCHCHK();
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_get_mu(tdgl_ctx *ctx, int inst, float *mu) {
+    tdgl_status s = check_ctx(ctx, inst);
+    if (s) return s;
+    if (!mu) return fail(TDGL_EINVAL, "null mu");
+    const Inst &d = ctx->inst[inst].d;
+    if (!d.driven) {
+        hipLaunchKernelGGL(k_fill_f, dim3(fill_grid(d.N)), dim3(256), 0, ctx->stream, mu, (long)d.N, 0.f);
+    } else {
+        hipLaunchKernelGGL(k_mu_io, dim3(fill_grid(d.N)), dim3(256), 0, ctx->stream, ctx->d_inst, inst, mu, 1);
+    }
+    LAUNCHCHK();
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_get_scalars(tdgl_ctx *ctx, int inst, tdgl_scalars *sc) {
+    tdgl_status s = check_ctx(ctx, inst);
+    if (s) return s;
+    if (!sc) return fail(TDGL_EINVAL, "null scalars");
+    DevState h;
+    HIPCHK(hipMemcpyAsync(&h, ctx->inst[inst].d.st, sizeof h, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    sc->K = h.K;
+    sc->t = h.t;
+    sc->V_sum = h.V_sum;
+    sc->n = (long long)h.n;
+    sc->n_avg = (long long)h.n_avg;
+    sc->E_last = h.E_last;
+    sc->J_av_last = h.J_last;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_set_scalars(tdgl_ctx *ctx, int inst, const tdgl_scalars *sc) {
+    tdgl_status s = check_ctx(ctx, inst);
+    if (s) return s;
+    if (!sc) return fail(TDGL_EINVAL, "null scalars");
+    if (!ctx->inst[inst].p.driven && sc->K != 0.0) return fail(TDGL_EINVAL, "undriven instance: K must be 0");
+    const double v[7] = {sc->K, sc->t, sc->V_sum, (double)sc->n, (double)sc->n_avg, sc->E_last, sc->J_av_last};
+    for (int f = 0; f < 7; ++f)
+        hipLaunchKernelGGL(k_state_set, dim3(1), dim3(1), 0, ctx->stream, ctx->d_inst, inst, f, v[f]);
+    hipLaunchKernelGGL(k_links, dim3(1), dim3(256), 0, ctx->stream, ctx->d_inst + inst, 1);
+    LAUNCHCHK();
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_voltage_window_reset(tdgl_ctx *ctx, int inst) {
+    tdgl_status s = check_ctx(ctx, inst);
+    if (s) return s;
+    hipLaunchKernelGGL(k_state_set, dim3(1), dim3(1), 0, ctx->stream, ctx->d_inst, inst, 2, 0.0);
+    hipLaunchKernelGGL(k_state_set, dim3(1), dim3(1), 0, ctx->stream, ctx->d_inst, inst, 4, 0.0);
+    LAUNCHCHK();
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats) {
+    if (!ctx) return fail(TDGL_EINVAL, "null context");
+    if (nsteps < 0) return fail(TDGL_EINVAL, "nsteps must be >= 0");
+    const int n = ctx->n;
+    hipStream_t s = ctx->stream;
+    tdgl_step_stats acc;
+    memset(&acc, 0, sizeof acc);
+    acc.sweeps_min = 1 << 30;
+    std::vector<int> conv_at(n), mconv_at(n);
+    bool strict_fail = false;
+    for (int step = 0; step < nsteps; ++step) {
+        // ---- Jacobi solve (all instances) --------------------------------
+        hipLaunchKernelGGL(k_stencil<MODE_FIRST>, dim3(ctx->tot_st), dim3(WG), 0, s, ctx->d_inst,
+                           ctx->d_pref_st, n, 0);
+        LAUNCHCHK();
+        HIPCHK(hipMemcpyAsync(ctx->h_res, ctx->d_res, n * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(ctx->ev[0], s));
+        std::fill(conv_at.begin(), conv_at.end(), -1);
+        int remaining = n, launched = 1, polled = 0;
+        for (;;) {
+            // inspect the rows of all sweeps except the newest one
+            while (remaining > 0 && (polled < launched - 1 || launched == ctx->max_iter) && polled < launched) {
+                HIPCHK(hipEventSynchronize(ctx->ev[polled]));
+                for (int i = 0; i < n; ++i) {
+                    if (conv_at[i] >= 0) continue;
+                    const InstHost &h = ctx->inst[i];
+                    float r;
+                    memcpy(&r, &ctx->h_res[(size_t)polled * n + i], 4);
+                    if (r < (float)h.p.tol || polled + 1 >= h.p.max_iter) {
+                        conv_at[i] = polled;
+                        --remaining;
+                    }
+                }
+                ++polled;
+            }
+            if (remaining == 0 || launched == ctx->max_iter) break;
+            const int l = launched;
+            hipLaunchKernelGGL(k_stencil<MODE_SWEEP>, dim3(ctx->tot_st), dim3(WG), 0, s, ctx->d_inst,
+                               ctx->d_pref_st, n, l);
+            LAUNCHCHK();
+            HIPCHK(hipMemcpyAsync(ctx->h_res + (size_t)l * n, ctx->d_res + (size_t)l * n, n * 4,
+                                  hipMemcpyDeviceToHost, s));
+            HIPCHK(hipEventRecord(ctx->ev[l], s));
+            ++launched;
+        }
+        hipLaunchKernelGGL(k_solve_finalize, dim3(cdiv(n, 64)), dim3(64), 0, s, ctx->d_inst, n);
+        LAUNCHCHK();
+        for (int i = 0; i < n; ++i) {
+            const InstHost &h = ctx->inst[i];
+            float r;
+            memcpy(&r, &ctx->h_res[(size_t)conv_at[i] * n + i], 4);
+            const bool capped = !(r < (float)h.p.tol);
+            const int sw = capped ? h.p.max_iter : conv_at[i] + 1;
+            acc.sweeps_min = std::min(acc.sweeps_min, sw);
+            acc.sweeps_max = std::max(acc.sweeps_max, sw);
+            acc.sweeps_sum += sw;
+            acc.last_res2 = r;
+            if (capped) {
+                acc.capped_steps++;
+                if (h.p.strict) strict_fail = true;
+            }
+        }
+        // ---- current, K and the scalar potential (driven instances) -------
+        if (ctx->any_driven) {
+            hipLaunchKernelGGL(k_jav_partial, dim3(ctx->tot_flat), dim3(256), 0, s, ctx->d_inst,
+                               ctx->d_pref_flat, n);
+            hipLaunchKernelGGL(k_kupdate, dim3(n), dim3(256), 0, s, ctx->d_inst, ctx->d_np_flat);
+            hipLaunchKernelGGL(k_stencil<MODE_RHS>, dim3(ctx->tot_st), dim3(WG), 0, s, ctx->d_inst,
+                               ctx->d_pref_st, n, 0);
+            hipLaunchKernelGGL(k_reduce_to_state, dim3(n), dim3(256), 0, s, ctx->d_inst, ctx->d_np_st, 0, 1);
+            LAUNCHCHK();
+            std::fill(mconv_at.begin(), mconv_at.end(), -1);
+            int mrem = 0;
+            for (int i = 0; i < n; ++i) {
+                if (ctx->inst[i].p.driven) ++mrem;
+                else mconv_at[i] = 0;
+            }
+            int mlaunched = 0, mpolled = 0;
+            for (;;) {
+                while (mrem > 0 && (mpolled < mlaunched - 1 || mlaunched == ctx->max_cycles) &&
+                       mpolled < mlaunched) {
+                    HIPCHK(hipEventSynchronize(ctx->evc[mpolled]));
+                    for (int i = 0; i < n; ++i) {
+                        if (mconv_at[i] >= 0) continue;
+                        const InstHost &h = ctx->inst[i];
+                        float r;
+                        memcpy(&r, &ctx->h_mures[(size_t)mpolled * n + i], 4);
+                        if (r < (float)h.p.mu_tol || mpolled + 1 >= h.p.mu_max_cycles) {
+                            mconv_at[i] = mpolled;
+                            --mrem;
+                        }
+                    }
+                    ++mpolled;
+                }
+                if (mrem == 0 || mlaunched == ctx->max_cycles) break;
+                tdgl_status e = enqueue_vcycle(ctx, mlaunched);
+                if (e) return e;
+                HIPCHK(hipMemcpyAsync(ctx->h_mures + (size_t)mlaunched * n, ctx->d_mures + (size_t)mlaunched * n,
+                                      n * 4, hipMemcpyDeviceToHost, s));
+                HIPCHK(hipEventRecord(ctx->evc[mlaunched], s));
+                ++mlaunched;
+            }
+            hipLaunchKernelGGL(k_mg_finalize, dim3(cdiv(n, 64)), dim3(64), 0, s, ctx->d_inst, n);
+            hipLaunchKernelGGL(k_mu_mean_partial, dim3(std::max(ctx->tot_mg[0], 1)), dim3(256), 0, s,
+                               ctx->d_inst, pref_mg(ctx, 0), n);
+            hipLaunchKernelGGL(k_reduce_to_state, dim3(n), dim3(256), 0, s, ctx->d_inst, ctx->d_np_mg0, 1, 1);
+            LAUNCHCHK();
+            for (int i = 0; i < n; ++i) {
+                const InstHost &h = ctx->inst[i];
+                if (!h.p.driven) continue;
+                float r;
+                memcpy(&r, &ctx->h_mures[(size_t)mconv_at[i] * n + i], 4);
+                const bool capped = !(r < (float)h.p.mu_tol);
+                acc.mu_cycles_sum += capped ? h.p.mu_max_cycles : mconv_at[i];
+                if (capped) acc.mu_capped_steps++;
+                acc.mu_last_res = r;
+            }
+        }
+        acc.steps++;
+        if (strict_fail) break;
+    }
+    if (stats) {
+        HIPCHK(hipStreamSynchronize(s));
+        if (acc.steps == 0) acc.sweeps_min = 0;
+        *stats = acc;
+    }
+    if (strict_fail) return fail(TDGL_ENOCONV, "a Jacobi solve reached max_iter without meeting tol");
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_observables(tdgl_ctx *ctx, int inst, tdgl_obs *obs) {
+    tdgl_status s = check_ctx(ctx, inst);
+    if (s) return s;
+    if (!obs) return fail(TDGL_EINVAL, "null observables");
+    const int n = ctx->n;
+    hipStream_t st = ctx->stream;
+    hipLaunchKernelGGL(k_stencil<MODE_ENERGY>, dim3(ctx->tot_st), dim3(WG), 0, st, ctx->d_inst, ctx->d_pref_st,
+                       n, 0);
+    hipLaunchKernelGGL(k_reduce_to_state, dim3(n), dim3(256), 0, st, ctx->d_inst, ctx->d_np_st, 2, 0);
+    hipLaunchKernelGGL(k_psi2_partial, dim3(ctx->tot_flat), dim3(256), 0, st, ctx->d_inst, ctx->d_pref_flat, n);
+    hipLaunchKernelGGL(k_reduce_to_state, dim3(n), dim3(256), 0, st, ctx->d_inst, ctx->d_np_flat, 3, 0);
+    LAUNCHCHK();
+    DevState h;
+    HIPCHK(hipMemcpyAsync(&h, ctx->inst[inst].d.st, sizeof h, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const tdgl_params &p = ctx->inst[inst].p;
+    const double Lx = p.bc[0] == TDGL_OPEN ? (p.nx - 1) * p.hx : p.nx * p.hx;
+    obs->F = h.F;
+    obs->E_last = h.E_last;
+    obs->E_mean = h.n_avg > 0 ? h.V_sum / h.n_avg : 0.0;
+    obs->V_mean = Lx * obs->E_mean;
+    obs->J_av = h.J_last;
+    obs->K = h.K;
+    obs->res2_last = h.last_res2;
+    obs->mu_mean_w = h.mu_mean;
+    obs->psi2_mean = h.psi2;
+    obs->n = (long long)h.n;
+    obs->n_avg = (long long)h.n_avg;
+    return TDGL_OK;
+}
+
+}  // extern "C"

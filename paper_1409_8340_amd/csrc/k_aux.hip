@@ -1,0 +1,226 @@
+// k_aux.hip -- link tables, reductions, the K update and small state
+// kernels of libtdgl.
+#include "kernels.h"
+
+namespace tdgl {
+
+// exp(i phi) in double precision with the argument reduced to [-pi, pi]
+// first, rounded to complex64.
+__device__ __forceinline__ float2 expi(double phi) {
+    const double twopi = 6.283185307179586476925286766559;
+    phi -= twopi * rint(phi / twopi);
+    double s, c;
+    sincos(phi, &s, &c);
+    return make_float2((float)c, (float)s);
+}
+
+// Link tables of one instance for the xz-plane field in the Landau gauge
+// (Eq. A_xz, Eq. link_variables, Sec. 3.3.1):
+//   ux[j] = exp(+i hx (K + Bz ybar_j)),  uz[j] = exp(-i hz Bx ybar_j),
+//   P[k*nx + i] = exp(i (i hx Ly Bz - k hz Ly Bx)),
+// with ybar_j = j hy - Ly/2 and Ly the system size along y.
+// One work-group per instance (grid = ninst); `which` = 1 refreshes ux only.
+__global__ void k_links(const Inst *__restrict__ insts, int which) {
+    const Inst &I = insts[blockIdx.x];
+    const DevState *st = I.st;
+    const double Ly = I.per[1] ? I.ny * I.hy : (I.ny - 1) * I.hy;
+    const double K = I.driven ? st->K : 0.0, Bx = st->Bx, Bz = st->Bz;
+    for (int j = threadIdx.x; j < I.ny; j += blockDim.x) {
+        const double yb = j * I.hy - 0.5 * Ly;
+        I.ux[j] = expi(I.hx * (K + Bz * yb));
+        if (which == 0) I.uz[j] = expi(-I.hz * Bx * yb);
+    }
+    if (which == 0) {
+        const long n = (long)I.nx * I.nz;
+        for (long t = threadIdx.x; t < n; t += blockDim.x) {
+            const int i = (int)(t % I.nx), k = (int)(t / I.nx);
+            I.P[t] = expi(i * I.hx * Ly * Bz - k * I.hz * Ly * Bx);
+        }
+    }
+}
+
+// End of a Jacobi solve: the first sweep l whose input residual met tol ends
+// the solve with that sweep's output (Eq. convergence); otherwise the cap.
+// Updates the psi buffer index, step counters and clears the residual words
+// for the next step.  One thread per instance.
+__global__ void k_solve_finalize(const Inst *__restrict__ insts, int ninst) {
+    const int ii = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ii >= ninst) return;
+    const Inst &I = insts[ii];
+    DevState *st = I.st;
+    int sweeps = I.max_iter, capped = 1;
+    for (int l = 0; l < I.max_iter; ++l) {
+        if (__uint_as_float(I.res[l * I.rstride]) < I.tol) { sweeps = l + 1; capped = 0; break; }
+    }
+    st->sweeps = sweeps;
+    st->capped = capped;
+    st->cur ^= (sweeps & 1);
+    st->t += I.dt;
+    st->n += 1.0;
+    // keep the last tested residual, then clear the words for the next step
+    st->last_res2 = __uint_as_float(I.res[(sweeps - 1) * I.rstride]);
+    for (int l = 0; l < I.max_iter; ++l) I.res[l * I.rstride] = 0u;
+}
+
+// Partial sums of Im[psi_m^* U_x(j) psi_{m+x}] (periodic x) for J_av
+// (Sec. 3.1.1; the symmetric form of the paper equals twice this one-sided
+// sum when x is periodic).  Flat mapping: CPT consecutive cells per thread.
+__global__ __launch_bounds__(256) void k_jav_partial(const Inst *__restrict__ insts,
+                                                     const int *__restrict__ prefix, int ninst) {
+    __shared__ double red[4];
+    const int b = blockIdx.x;
+    const int ii = find_inst(prefix, ninst, b);
+    const Inst &I = insts[ii];
+    const int lb = b - prefix[ii];
+    const float2 *__restrict__ psi = I.psi[I.st->cur];
+    double acc = 0.0;
+    const long base = (long)lb * 256 * JAV_CPT;
+    for (int c = 0; c < JAV_CPT; ++c) {
+        const int m = (int)base + c * 256 + (int)threadIdx.x;
+        if (m < I.N) {
+            const int i = m % I.nx;
+            const int j = (m / I.nx) % I.ny;
+            const int mp = (i == I.nx - 1) ? m - (I.nx - 1) : m + 1;
+            const float2 a = psi[m], p = psi[mp];
+            const float2 up = cmul(I.ux[j], p);
+            acc += (double)(a.x * up.y - a.y * up.x);
+        }
+    }
+    const double s = wg_sum<256>(acc, red);
+    if (threadIdx.x == 0) I.part[lb] = s;
+}
+
+// Deterministic fixed-order sum of `n` partials by one work-group.
+__device__ double wg_reduce_parts(const double *__restrict__ part, int n, double *red) {
+    double a = 0.0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) a += part[t];
+    return wg_sum<256>(a, red);
+}
+
+// K update (Eq. K_ODE with dA/dt = 0, explicit Euler in real time dt):
+//   J_av = sum / (N hx), E = J_ext - J_av, K += dt E, V_sum += E,
+//   K -> K - (2 pi / hx) floor(K hx / 2 pi)  (phase rewind, Sec. 2.2),
+// then the x-link table is rebuilt for the new K.  One work-group per
+// instance; undriven instances are left alone.
+__global__ __launch_bounds__(256) void k_kupdate(const Inst *__restrict__ insts,
+                                                 const int *__restrict__ nparts) {
+    __shared__ double red[4];
+    __shared__ double Ks;
+    const Inst &I = insts[blockIdx.x];
+    if (!I.driven) return;
+    DevState *st = I.st;
+    const double s = wg_reduce_parts(I.part, nparts[blockIdx.x], red);
+    if (threadIdx.x == 0) {
+        const double twopi = 6.283185307179586476925286766559;
+        const double J = s / ((double)I.N * I.hx);
+        const double E = st->Jext - J;
+        double K = st->K + I.dt * E;
+        if (st->in_window) { st->V_sum += E; st->n_avg += 1.0; }
+        K = K - (twopi / I.hx) * floor(K * I.hx / twopi);
+        st->K = K;
+        st->E_last = E;
+        st->J_last = J;
+        Ks = K;
+    }
+    __syncthreads();
+    const double Ly = I.per[1] ? I.ny * I.hy : (I.ny - 1) * I.hy;
+    for (int j = threadIdx.x; j < I.ny; j += blockDim.x) {
+        const double yb = j * I.hy - 0.5 * Ly;
+        I.ux[j] = expi(I.hx * (Ks + st->Bz * yb));
+    }
+}
+
+// Reduce an instance's partials into a DevState field: dst = scale * sum.
+// field: 0 = f_mean, 1 = mu_mean, 2 = F, 3 = psi2 (mean |psi|^2).
+__global__ __launch_bounds__(256) void k_reduce_to_state(const Inst *__restrict__ insts,
+                                                         const int *__restrict__ nparts, int field,
+                                                         int driven_only) {
+    __shared__ double red[4];
+    const Inst &I = insts[blockIdx.x];
+    if (driven_only && !I.driven) return;
+    const double s = wg_reduce_parts(I.part, nparts[blockIdx.x], red);
+    if (threadIdx.x == 0) {
+        DevState *st = I.st;
+        if (field == 0) st->f_mean = s / I.w_sum;
+        else if (field == 1) st->mu_mean = s / I.lev[0].vsum;
+        else if (field == 2) st->F = s * I.hx * I.hy * I.hz;
+        else st->psi2 = s / (double)I.N;
+    }
+}
+
+// Partial sums of |psi|^2 (flat mapping).
+__global__ __launch_bounds__(256) void k_psi2_partial(const Inst *__restrict__ insts,
+                                                      const int *__restrict__ prefix, int ninst) {
+    __shared__ double red[4];
+    const int b = blockIdx.x;
+    const int ii = find_inst(prefix, ninst, b);
+    const Inst &I = insts[ii];
+    const int lb = b - prefix[ii];
+    const float2 *__restrict__ psi = I.psi[I.st->cur];
+    double acc = 0.0;
+    const long base = (long)lb * 256 * JAV_CPT;
+    for (int c = 0; c < JAV_CPT; ++c) {
+        const long m = base + (long)c * 256 + threadIdx.x;
+        if (m < I.N) acc += (double)cabs2(psi[m]);
+    }
+    const double s = wg_sum<256>(acc, red);
+    if (threadIdx.x == 0) I.part[lb] = s;
+}
+
+// ---------------------------------------------------------------------------
+// state and copy helpers
+__global__ void k_fill_c(float2 *p, long n, float re, float im) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        p[i] = make_float2(re, im);
+}
+__global__ void k_fill_f(float *p, long n, float v) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_u(unsigned *p, long n, unsigned v) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// psi in/out through the current buffer index (known only on the device).
+__global__ void k_psi_io(const Inst *__restrict__ insts, int inst, float2 *ext, int to_ext) {
+    const Inst &I = insts[inst];
+    float2 *psi = I.psi[I.st->cur];
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < I.N; i += (long)gridDim.x * blockDim.x) {
+        if (to_ext) ext[i] = psi[i];
+        else psi[i] = ext[i];
+    }
+}
+
+// mu out with the weighted mean removed; mu in (stored as given, mean 0 set).
+__global__ void k_mu_io(const Inst *__restrict__ insts, int inst, float *ext, int to_ext) {
+    const Inst &I = insts[inst];
+    const float mean = (float)I.st->mu_mean;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < I.N; i += (long)gridDim.x * blockDim.x) {
+        if (to_ext) ext[i] = I.mu[i] - mean;
+        else I.mu[i] = ext[i];
+    }
+}
+
+// Scalar state writes, ordered on the stream.
+__global__ void k_state_set(const Inst *__restrict__ insts, int inst, int field, double v) {
+    DevState *st = insts[inst].st;
+    switch (field) {
+        case 0: st->K = v; break;
+        case 1: st->t = v; break;
+        case 2: st->V_sum = v; break;
+        case 3: st->n = v; break;
+        case 4: st->n_avg = v; break;
+        case 5: st->E_last = v; break;
+        case 6: st->J_last = v; break;
+        case 7: st->Jext = v; break;
+        case 8: st->Bx = v; break;
+        case 9: st->Bz = v; break;
+        case 10: st->mu_mean = v; break;
+        case 11: st->in_window = (int)v; break;
+        case 12: st->cur = (int)v; break;
+        default: break;
+    }
+}
+
+}  // namespace tdgl

@@ -1,0 +1,139 @@
+// k_incl.hip -- inclusion generator of Sec. 3.4 on the GPU.
+//
+// Candidate spheres are added in order until the covered node fraction
+// reaches the target.  Instead of adding them one by one, every node records
+// the index of the FIRST candidate that covers it (atomicMin); the covered
+// count after s spheres is then the number of nodes whose first index is
+// below s, a prefix sum over a per-candidate histogram.  The smallest s whose
+// count reaches the target is the sequential answer, found in one pass.
+#include "kernels.h"
+
+namespace tdgl {
+
+// One work-group per candidate sphere: visit the integer bounding box of
+// the sphere (one node margin), test each node image exactly and record the
+// smallest covering index.  The membership test
+//     ((dx*dx + dy*dy) + dz*dz) <= (d/2)*(d/2),  dx = u*hx - cx,
+// is evaluated in double precision with contraction into fused multiply-add
+// disabled, so it is bit-reproducible.  u is the unwrapped integer node
+// coordinate; periodic axes wrap it onto the grid, open axes clip.
+__global__ __launch_bounds__(256) void k_incl_first(const Inst *__restrict__ insts, int inst,
+                                                    const double *__restrict__ centres,
+                                                    const double *__restrict__ diam, int nc,
+                                                    unsigned *__restrict__ first) {
+#pragma clang fp contract(off)
+    const Inst &I = insts[inst];
+    const int s = blockIdx.x;
+    if (s >= nc) return;
+    const double h[3] = {I.hx, I.hy, I.hz};
+    const int n[3] = {I.nx, I.ny, I.nz};
+    const double r = 0.5 * diam[s];
+    const double r2 = r * r;
+    // non-finite or negative input: the sphere covers nothing
+    if (!(r >= 0.0) || !(r < 1e30)) return;
+    long lo[3], cnt[3];
+    for (int a = 0; a < 3; ++a) {
+        const double c = centres[3 * s + a];
+        if (!(fabs(c) < 1e30)) return;
+        long l0 = (long)floor((c - r) / h[a]) - 1;
+        long h0 = (long)ceil((c + r) / h[a]) + 1;
+        if (!I.per[a]) {
+            if (l0 < 0) l0 = 0;
+            if (h0 > n[a] - 1) h0 = n[a] - 1;
+        } else {
+            // one period around the centre holds the nearest image of every
+            // node, and a node is inside iff its nearest image is
+            const long cc = (long)floor(c / h[a]);
+            if (l0 < cc - n[a] - 1) l0 = cc - n[a] - 1;
+            if (h0 > cc + n[a] + 1) h0 = cc + n[a] + 1;
+        }
+        lo[a] = l0;
+        cnt[a] = h0 - l0 + 1;
+        if (cnt[a] <= 0) return;
+    }
+    const double cx = centres[3 * s], cy = centres[3 * s + 1], cz = centres[3 * s + 2];
+    const long tot = cnt[0] * cnt[1] * cnt[2];
+    for (long t = threadIdx.x; t < tot; t += blockDim.x) {
+        const long ux = lo[0] + t % cnt[0];
+        const long uy = lo[1] + (t / cnt[0]) % cnt[1];
+        const long uz = lo[2] + t / (cnt[0] * cnt[1]);
+        const double dx = (double)ux * h[0] - cx;
+        const double dy = (double)uy * h[1] - cy;
+        const double dz = (double)uz * h[2] - cz;
+        const double d2 = (dx * dx + dy * dy) + dz * dz;
+        if (d2 <= r2) {
+            const long ix = ((ux % n[0]) + n[0]) % n[0];
+            const long iy = ((uy % n[1]) + n[1]) % n[1];
+            const long iz = ((uz % n[2]) + n[2]) % n[2];
+            atomicMin(&first[(iz * n[1] + iy) * n[0] + ix], (unsigned)s);
+        }
+    }
+}
+
+// Histogram of first covering indices.
+__global__ void k_incl_count(const unsigned *__restrict__ first, long N, int nc,
+                             unsigned *__restrict__ cnt) {
+    for (long m = blockIdx.x * (long)blockDim.x + threadIdx.x; m < N; m += (long)gridDim.x * blockDim.x) {
+        const unsigned f = first[m];
+        if (f < (unsigned)nc) atomicAdd(&cnt[f], 1u);
+    }
+}
+
+// Smallest s with sum_{t <= s} cnt[t] >= need; one work-group of 1024.
+// Writes the sphere count (s + 1) and the covered fraction into the state.
+__global__ __launch_bounds__(1024) void k_incl_scan(const Inst *__restrict__ insts, int inst,
+                                                    const unsigned *__restrict__ cnt, int nc,
+                                                    double target) {
+    __shared__ unsigned long long tsum[1024];
+    __shared__ int found;
+    const Inst &I = insts[inst];
+    const double need = target * (double)I.N;
+    const int per = (nc + 1023) / 1024;
+    const int b0 = threadIdx.x * per, b1 = min(b0 + per, nc);
+    unsigned long long s = 0;
+    for (int t = b0; t < b1; ++t) s += cnt[t];
+    tsum[threadIdx.x] = s;
+    if (threadIdx.x == 0) found = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // sequential exclusive scan over the 1024 thread sums
+        unsigned long long acc = 0;
+        for (int i = 0; i < 1024; ++i) {
+            const unsigned long long v = tsum[i];
+            tsum[i] = acc;
+            acc += v;
+        }
+    }
+    __syncthreads();
+    DevState *st = I.st;
+    if (need <= 0.0) {
+        if (threadIdx.x == 0) { st->n_used = 0; st->frac = 0.0; }
+        return;
+    }
+    unsigned long long acc = tsum[threadIdx.x];
+    for (int t = b0; t < b1; ++t) {
+        const unsigned long long next = acc + cnt[t];
+        if ((double)acc < need && (double)next >= need) {
+            // exactly one thread sees the crossing
+            st->n_used = t + 1;
+            st->frac = (double)next / (double)I.N;
+            found = 1;
+        }
+        acc = next;
+    }
+    __syncthreads();
+    if (threadIdx.x == 1023 && !found) {
+        st->n_used = nc;
+        st->frac = (double)acc / (double)I.N;
+    }
+}
+
+__global__ void k_incl_write(const Inst *__restrict__ insts, int inst,
+                             const unsigned *__restrict__ first, float eps_in, float eps_out) {
+    const Inst &I = insts[inst];
+    const unsigned used = (unsigned)I.st->n_used;
+    for (long m = blockIdx.x * (long)blockDim.x + threadIdx.x; m < I.N; m += (long)gridDim.x * blockDim.x)
+        I.eps[m] = first[m] < used ? eps_in : eps_out;
+}
+
+}  // namespace tdgl

@@ -1,0 +1,46 @@
+// kernels.h -- declarations of the libtdgl kernels (defined in k_*.hip).
+#pragma once
+#include "tdgl_dev.h"
+
+namespace tdgl {
+
+enum { MODE_FIRST = 0, MODE_SWEEP = 1, MODE_RHS = 2, MODE_ENERGY = 3 };
+constexpr int JAV_CPT = 16;     // cells per thread of the flat reductions
+constexpr int CO_THREADS = 1024;
+
+template <int MODE>
+__global__ void k_stencil(const Inst *insts, const int *prefix, int ninst, int l);
+
+__global__ void k_links(const Inst *insts, int which);
+__global__ void k_solve_finalize(const Inst *insts, int ninst);
+__global__ void k_jav_partial(const Inst *insts, const int *prefix, int ninst);
+__global__ void k_kupdate(const Inst *insts, const int *nparts);
+__global__ void k_reduce_to_state(const Inst *insts, const int *nparts, int field, int driven_only);
+__global__ void k_psi2_partial(const Inst *insts, const int *prefix, int ninst);
+__global__ void k_fill_c(float2 *p, long n, float re, float im);
+__global__ void k_fill_f(float *p, long n, float v);
+__global__ void k_fill_u(unsigned *p, long n, unsigned v);
+__global__ void k_psi_io(const Inst *insts, int inst, float2 *ext, int to_ext);
+__global__ void k_mu_io(const Inst *insts, int inst, float *ext, int to_ext);
+__global__ void k_state_set(const Inst *insts, int inst, int field, double v);
+
+__global__ void k_mg_smooth(const Inst *insts, const int *prefix, int ninst, int lv, int isrc,
+                            int idst, int cyc, float omega);
+__global__ void k_mg_residual(const Inst *insts, const int *prefix, int ninst, int lv, int isrc,
+                              int cyc);
+__global__ void k_mg_restrict(const Inst *insts, const int *prefix, int ninst, int lv, int cyc,
+                              float omega);
+__global__ void k_mg_prolong(const Inst *insts, const int *prefix, int ninst, int lv, int ifine,
+                             int cyc);
+__global__ void k_mg_coarsest(const Inst *insts, int ninst, int cyc);
+__global__ void k_mg_finalize(const Inst *insts, int ninst);
+__global__ void k_mu_mean_partial(const Inst *insts, const int *prefix, int ninst);
+
+__global__ void k_incl_first(const Inst *insts, int inst, const double *centres, const double *diam,
+                             int nc, unsigned *first);
+__global__ void k_incl_count(const unsigned *first, long N, int nc, unsigned *cnt);
+__global__ void k_incl_scan(const Inst *insts, int inst, const unsigned *cnt, int nc, double target);
+__global__ void k_incl_write(const Inst *insts, int inst, const unsigned *first, float eps_in,
+                             float eps_out);
+
+}  // namespace tdgl

@@ -1,0 +1,198 @@
+// tdgl_dev.h -- device-side data structures and helpers of libtdgl (gfx950).
+//
+// One "instance" is one independent TDGL system.  Its device descriptor
+// (Inst) carries sizes, coefficients and pointers into the caller's
+// workspace; kernels receive the array of descriptors of a context and map
+// their work-groups onto instances through a prefix table, so a single
+// launch advances every instance of a batch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tdgl {
+
+constexpr int kMaxIter = 256;    // Jacobi sweeps per step (cap)
+constexpr int kMaxCycles = 64;   // multigrid cycles per step (cap)
+constexpr int kMaxLevels = 16;   // multigrid levels
+
+// Tile of the 2.5D stencil kernels: 64 x-columns (one wavefront wide) by
+// 16 y-rows; 256 threads, each owning 4 consecutive rows of one column, march
+// through a chunk of z planes.
+constexpr int TX = 64;
+constexpr int TY = 16;
+constexpr int ROWS = 4;          // rows per thread (TY / waves)
+constexpr int WG = 256;
+constexpr int HALO = 2 * TX + 2 * TY;  // halo cells of one plane (no corners)
+constexpr int LDX = TX + 2;            // LDS plane pitch (float2 units)
+constexpr int LDY = TY + 2;
+
+// Tile of the multigrid kernels: 64 x 4 columns, z chunk.
+constexpr int MTX = 64;
+constexpr int MTY = 4;
+
+// Scalar state of one instance, kept in device memory so that a whole step
+// runs without host round trips.  FP64 for everything that accumulates.
+struct DevState {
+    double K;         // current phase (Sec. 2.2)
+    double t;         // simulated time
+    double V_sum;     // sum of E over the voltage window
+    double E_last;    // last E_x
+    double J_last;    // last J_av
+    double n;         // steps taken
+    double n_avg;     // steps in window
+    double f_mean;    // weighted mean of the last Poisson right side
+    double mu_mean;   // weighted mean of mu as stored after the last solve
+    double F;         // free energy (observables)
+    double psi2;      // mean |psi|^2 (observables)
+    double Jext;      // applied current
+    double Bx, Bz;    // field (quantised)
+    int cur;          // index of the psi buffer holding the current state
+    int sweeps;       // Jacobi sweeps of the last step
+    int capped;       // last solve hit the cap
+    int mu_cycles;    // multigrid cycles of the last step
+    int mu_capped;
+    int in_window;    // accumulate E into V_sum
+    int n_used;       // inclusion generator: spheres used
+    float last_res2;  // max |r|^2 tested by the last sweep of the last solve
+    double frac;      // inclusion generator: covered fraction
+    float mu_last_res;// Poisson residual max-norm at the end of the last solve
+    int pad2;
+};
+
+struct MGLevel {
+    int nx, ny, nz, N;
+    int per[3];
+    const float *am[3], *ap[3];   // FV coefficients to the -/+ neighbour, per axis index
+    const float *vol[3];          // control volume factors per axis index
+    float *mu[2];                 // ping-pong iterates (level 0: mu[0] is the solution)
+    float *rhs;                   // right side (level 0: f)
+    float *r;                     // residual
+    // transfer to the next coarser level (unused on the coarsest)
+    const int *pk[3];             // prolongation: per fine index two coarse indices
+    const float *pw[3];           //   and their weights
+    const int *rk[3];             // restriction: per coarse index three fine indices
+    const float *rw[3];           //   and their weights (volume-weighted)
+    double vsum;                  // sum of control volumes
+    int tiles_x, tiles_y, tiles_z, chunk;
+};
+
+struct Inst {
+    int nx, ny, nz, N;
+    int per[3];          // 1: periodic axis, 0: open
+    int driven;
+    float cx, cy, cz;    // 1/hx^2, 1/hy^2, 1/(g^2 hz^2); 0 on an open one-node axis
+    float S2;            // 2 (cx + cy + cz)
+    float ht2;           // ht / 2 with ht = dt / u
+    float u;
+    float tol;           // Jacobi stop threshold on max |r|^2
+    float mu_tol;
+    double hx, hy, hz, dt;
+    double w_sum;        // sum of node weights (1/2 per open face)
+    float2 *psi[2];
+    float2 *bh;          // b / M_mm
+    float2 *dh;          // (ht/2) / M_mm
+    float *eps;
+    float *mu;           // == lev[0].mu[0]
+    float *f;            // == lev[0].rhs
+    float2 *ux;          // x links per y index: exp(i hx (K + Bz ybar_j))
+    float2 *uz;          // z links per y index: exp(-i hz Bx ybar_j)
+    float2 *P;           // y wrap phase per (i,k): exp(i (i hx Ly Bz - k hz Ly Bx))
+    DevState *st;
+    // Convergence words, strided over the instances of a context so that one
+    // small copy polls a whole batch: sweep l of this instance uses
+    // res[l * rstride], multigrid cycle c uses mures[c * rstride].
+    unsigned *res;       // max |r|^2 of the input iterate of sweep l (float bits)
+    unsigned *mures;     // Poisson residual max-norm at the top of cycle c
+    int rstride;
+    int max_iter, mu_max_cycles;
+    double *part;        // per-work-group partial sums
+    int part_cap;
+    int tiles_x, tiles_y, tiles_z, chunk;   // stencil tiling (chunk: z planes per tile)
+    int nlev;
+    MGLevel lev[kMaxLevels];
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // conj(a) * b
+    return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscale(float s, float2 a) { return make_float2(s * a.x, s * a.y); }
+__device__ __forceinline__ float cabs2(float2 a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ float2 cdiv(float2 a, float2 b) {
+    float d = 1.0f / (b.x * b.x + b.y * b.y);
+    return make_float2((a.x * b.x + a.y * b.y) * d, (a.y * b.x - a.x * b.y) * d);
+}
+
+// Work-groups are dispatched round-robin over the 8 XCDs (blockIdx % 8).
+// Remap so that each XCD receives a contiguous range of logical tiles: tiles
+// that share halos then share that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7;
+    const int x = b & 7, l = b >> 3;
+    return x * q + (x < r ? x : r) + l;
+}
+
+// Instance owning logical block `b` of a batched launch (prefix has ninst+1
+// entries; instance i owns [prefix[i], prefix[i+1])).
+__device__ __forceinline__ int find_inst(const int *__restrict__ prefix, int ninst, int b) {
+    int lo = 0, hi = ninst - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Node weight: 1/2 per open face the node lies on (trapezoid rule).
+__device__ __forceinline__ float node_w(const Inst &I, int x, int y, int k) {
+    float w = 1.f;
+    if (!I.per[0] && I.nx > 1 && (x == 0 || x == I.nx - 1)) w *= 0.5f;
+    if (!I.per[1] && I.ny > 1 && (y == 0 || y == I.ny - 1)) w *= 0.5f;
+    if (!I.per[2] && I.nz > 1 && (k == 0 || k == I.nz - 1)) w *= 0.5f;
+    return w;
+}
+
+// Max-reduction of non-negative floats over a work-group into one word
+// (float bits compare as unsigned for non-negative values; a NaN's bits
+// exceed +inf's, so a NaN wins and is never taken for convergence).
+template <int NT>
+__device__ __forceinline__ void wg_max_to(unsigned *dst, float v, float *lds_scratch) {
+    unsigned u = __float_as_uint(v);
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned w = __shfl_xor(u, o, 64);
+        u = (w > u) ? w : u;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) lds_scratch[wv] = __uint_as_float(u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned m = 0;
+        for (int i = 0; i < NT / 64; ++i) {
+            unsigned w = __float_as_uint(lds_scratch[i]);
+            m = (w > m) ? w : m;
+        }
+        atomicMax(dst, m);
+    }
+}
+
+// Sum of doubles over a work-group; thread 0 returns the total.
+template <int NT>
+__device__ __forceinline__ double wg_sum(double v, double *lds_scratch) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds_scratch[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < NT / 64; ++i) s += lds_scratch[i];
+    return s;
+}
+
+}  // namespace tdgl

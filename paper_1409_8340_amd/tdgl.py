@@ -1,0 +1,289 @@
+"""ctypes binding of libtdgl (include/tdgl.h).
+
+Argument marshalling only: every step of the solver runs in the library's
+HIP kernels.  torch provides the device memory (the workspace and the user
+arrays) and the stream.  Loading fails loudly when the library has not been
+built; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtdgl.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "tdgl.h")
+
+TDGL_PERIODIC = 0
+TDGL_OPEN = 1
+STATUS = {0: "OK", 1: "EINVAL", 2: "EWS", 3: "ENOCONV", 4: "EDEVICE", 5: "ESTATE"}
+
+
+class TdglError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("hx", ctypes.c_double), ("hy", ctypes.c_double), ("hz", ctypes.c_double),
+                ("bc", ctypes.c_int * 3), ("g", ctypes.c_double), ("u", ctypes.c_double),
+                ("dt", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("driven", ctypes.c_int), ("mu_tol", ctypes.c_double),
+                ("mu_max_cycles", ctypes.c_int), ("strict", ctypes.c_int),
+                ("tile_cz", ctypes.c_int), ("reserved", ctypes.c_int * 7)]
+
+
+class StepStats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int), ("sweeps_min", ctypes.c_int),
+                ("sweeps_max", ctypes.c_int), ("sweeps_sum", ctypes.c_longlong),
+                ("capped_steps", ctypes.c_int), ("last_res2", ctypes.c_float),
+                ("mu_cycles_sum", ctypes.c_int), ("mu_capped_steps", ctypes.c_int),
+                ("mu_last_res", ctypes.c_float)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Scalars(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_double), ("t", ctypes.c_double), ("V_sum", ctypes.c_double),
+                ("n", ctypes.c_longlong), ("n_avg", ctypes.c_longlong),
+                ("E_last", ctypes.c_double), ("J_av_last", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Obs(ctypes.Structure):
+    _fields_ = [("F", ctypes.c_double), ("E_last", ctypes.c_double), ("E_mean", ctypes.c_double),
+                ("V_mean", ctypes.c_double), ("J_av", ctypes.c_double), ("K", ctypes.c_double),
+                ("res2_last", ctypes.c_double), ("mu_mean_w", ctypes.c_double),
+                ("psi2_mean", ctypes.c_double), ("n", ctypes.c_longlong),
+                ("n_avg", ctypes.c_longlong)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+_SIGS = {
+    "tdgl_last_error": ([], ctypes.c_char_p),
+    "tdgl_plan": ([ctypes.c_int, ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "tdgl_create": ([ctypes.c_int, ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_size_t,
+                     ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "tdgl_destroy": ([ctypes.c_void_p], ctypes.c_int),
+    "tdgl_size": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "tdgl_quantize_field": ([ctypes.POINTER(Params), ctypes.c_double, ctypes.c_double,
+                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+                            ctypes.c_int),
+    "tdgl_set_field": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "tdgl_set_current": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_double], ctypes.c_int),
+    "tdgl_set_eps": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "tdgl_get_eps": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "tdgl_gen_inclusions": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                             ctypes.c_double, ctypes.c_float, ctypes.c_float, ctypes.POINTER(ctypes.c_int),
+                             ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "tdgl_set_psi": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "tdgl_get_psi": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "tdgl_set_mu": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "tdgl_get_mu": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "tdgl_get_scalars": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(Scalars)], ctypes.c_int),
+    "tdgl_set_scalars": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(Scalars)], ctypes.c_int),
+    "tdgl_voltage_window_reset": ([ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
+    "tdgl_step": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(StepStats)], ctypes.c_int),
+    "tdgl_observables": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(Obs)], ctypes.c_int),
+}
+
+
+def header_symbols():
+    """Entry points declared in include/tdgl.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(tdgl_[a-z_]+)\s*\(", txt)))
+
+
+def load():
+    """Load libtdgl.so (must have been built; raises otherwise)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first "
+                               "(python -c 'import __graft_entry__ as g; g.build()')")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        msg = load().tdgl_last_error()
+        raise TdglError(status, msg.decode() if msg else "")
+
+
+def make_params(nx, ny, nz, h=0.5, hx=None, hy=None, hz=None, bc=(TDGL_PERIODIC, TDGL_PERIODIC, TDGL_OPEN),
+                g=1.0, u=1.0, dt=0.1, tol=1e-8, max_iter=100, driven=False, mu_tol=1e-5,
+                mu_max_cycles=20, strict=False, tile_cz=0) -> Params:
+    p = Params()
+    p.nx, p.ny, p.nz = nx, ny, nz
+    p.hx = h if hx is None else hx
+    p.hy = h if hy is None else hy
+    p.hz = h if hz is None else hz
+    for a in range(3):
+        p.bc[a] = int(bc[a])
+    p.g, p.u, p.dt, p.tol = g, u, dt, tol
+    p.max_iter = max_iter
+    p.driven = int(bool(driven))
+    p.mu_tol = mu_tol
+    p.mu_max_cycles = mu_max_cycles
+    p.strict = int(bool(strict))
+    p.tile_cz = tile_cz
+    return p
+
+
+def plan(params) -> int:
+    arr = (Params * len(params))(*params)
+    sz = ctypes.c_size_t()
+    _check(load().tdgl_plan(len(params), arr, ctypes.byref(sz)))
+    return sz.value
+
+
+def quantize_field(p: Params, Bx: float, Bz: float):
+    bx, bz = ctypes.c_double(), ctypes.c_double()
+    _check(load().tdgl_quantize_field(ctypes.byref(p), Bx, Bz, ctypes.byref(bx), ctypes.byref(bz)))
+    return bx.value, bz.value
+
+
+class Solver:
+    """A context of one or more instances on the current torch device."""
+
+    def __init__(self, params, stream=None):
+        import torch
+        if isinstance(params, Params):
+            params = [params]
+        self.params = list(params)
+        self.n = len(self.params)
+        lib = load()
+        ws_bytes = plan(self.params)
+        self._ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device="cuda")
+        base = self._ws.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        arr = (Params * self.n)(*self.params)
+        ctx = ctypes.c_void_p()
+        _check(lib.tdgl_create(self.n, arr, ctypes.c_void_p(self._ws_ptr), ctypes.c_size_t(ws_bytes),
+                               ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(ctx)))
+        self._ctx = ctx
+        self.ws_bytes = ws_bytes
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            load().tdgl_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers
+    def shape(self, inst=0):
+        p = self.params[inst]
+        return (p.nz, p.ny, p.nx)
+
+    def _dev(self, t, dtype):
+        import torch
+        assert t.device.type == "cuda" and t.dtype == dtype and t.is_contiguous(), (t.device, t.dtype)
+        return ctypes.c_void_p(t.data_ptr())
+
+    # -- setters / getters
+    def set_field(self, Bx, Bz, inst=0, quantize=True):
+        bx, bz = ctypes.c_double(), ctypes.c_double()
+        _check(load().tdgl_set_field(self._ctx, inst, Bx, Bz, int(quantize), ctypes.byref(bx),
+                                     ctypes.byref(bz)))
+        return bx.value, bz.value
+
+    def set_current(self, J, inst=0):
+        _check(load().tdgl_set_current(self._ctx, inst, J))
+
+    def set_eps(self, eps, inst=0):
+        import torch
+        eps = eps.to(device="cuda", dtype=torch.float32).contiguous()
+        _check(load().tdgl_set_eps(self._ctx, inst, self._dev(eps, torch.float32)))
+        self._keep = eps
+
+    def get_eps(self, inst=0):
+        import torch
+        out = torch.empty(self.shape(inst), dtype=torch.float32, device="cuda")
+        _check(load().tdgl_get_eps(self._ctx, inst, self._dev(out, torch.float32)))
+        self._stream.synchronize()
+        return out
+
+    def gen_inclusions(self, centres, diameters, target, eps_in=-1.0, eps_out=1.0, inst=0):
+        import torch
+        c = torch.as_tensor(centres, dtype=torch.float64).reshape(-1, 3).contiguous().cuda()
+        d = torch.as_tensor(diameters, dtype=torch.float64).reshape(-1).contiguous().cuda()
+        used, frac = ctypes.c_int(), ctypes.c_double()
+        _check(load().tdgl_gen_inclusions(self._ctx, inst, self._dev(c, torch.float64),
+                                          self._dev(d, torch.float64), int(d.numel()), float(target),
+                                          float(eps_in), float(eps_out), ctypes.byref(used),
+                                          ctypes.byref(frac)))
+        return used.value, frac.value
+
+    def set_psi(self, psi, inst=0):
+        import torch
+        psi = psi.to(device="cuda", dtype=torch.complex64).contiguous()
+        _check(load().tdgl_set_psi(self._ctx, inst, self._dev(psi, torch.complex64)))
+        self._stream.synchronize()
+
+    def get_psi(self, inst=0):
+        import torch
+        out = torch.empty(self.shape(inst), dtype=torch.complex64, device="cuda")
+        _check(load().tdgl_get_psi(self._ctx, inst, self._dev(out, torch.complex64)))
+        self._stream.synchronize()
+        return out
+
+    def set_mu(self, mu, inst=0):
+        import torch
+        mu = mu.to(device="cuda", dtype=torch.float32).contiguous()
+        _check(load().tdgl_set_mu(self._ctx, inst, self._dev(mu, torch.float32)))
+        self._stream.synchronize()
+
+    def get_mu(self, inst=0):
+        import torch
+        out = torch.empty(self.shape(inst), dtype=torch.float32, device="cuda")
+        _check(load().tdgl_get_mu(self._ctx, inst, self._dev(out, torch.float32)))
+        self._stream.synchronize()
+        return out
+
+    def get_scalars(self, inst=0):
+        s = Scalars()
+        _check(load().tdgl_get_scalars(self._ctx, inst, ctypes.byref(s)))
+        return s.as_dict()
+
+    def set_scalars(self, d, inst=0):
+        s = Scalars()
+        for k, v in d.items():
+            setattr(s, k, v)
+        _check(load().tdgl_set_scalars(self._ctx, inst, ctypes.byref(s)))
+
+    def window_reset(self, inst=0):
+        _check(load().tdgl_voltage_window_reset(self._ctx, inst))
+
+    def step(self, nsteps=1, stats=True):
+        st = StepStats()
+        _check(load().tdgl_step(self._ctx, int(nsteps), ctypes.byref(st) if stats else None))
+        return st.as_dict() if stats else None
+
+    def observables(self, inst=0):
+        o = Obs()
+        _check(load().tdgl_observables(self._ctx, inst, ctypes.byref(o)))
+        return o.as_dict()

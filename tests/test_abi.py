@@ -1,0 +1,113 @@
+"""The C-ABI library loads, exports every entry point its header declares,
+and its host-only logic (parameter validation, workspace planning, flux
+quantisation) behaves as documented.  No device calls: CPU only."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1409_8340_amd import tdgl
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return tdgl.load()
+
+
+def test_exports_every_header_symbol(lib):
+    syms = tdgl.header_symbols()
+    assert len(syms) >= 19
+    for s in syms:
+        assert hasattr(lib, s), s
+    # the binding declares exactly the header's entry points
+    assert sorted(tdgl._SIGS) == syms
+
+
+def test_plan_sizes_grow_with_grid(lib):
+    a = tdgl.plan([tdgl.make_params(32, 32, 16)])
+    b = tdgl.plan([tdgl.make_params(64, 64, 16)])
+    c = tdgl.plan([tdgl.make_params(64, 64, 16, driven=True)])
+    assert 0 < a < b < c
+    N = 64 * 64 * 16
+    assert b >= N * (8 * 4 + 4)        # psi x2, b/M, ht/2M, eps
+    assert c >= b + N * 4 * 4          # f, mu x2, r
+    batch = tdgl.plan([tdgl.make_params(32, 32, 16), tdgl.make_params(64, 64, 16)])
+    assert batch >= a + b - 4096
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(nx=0), "grid sizes"),
+    (dict(h=0.0), "spacings"),
+    (dict(dt=-1.0), "g, u and dt"),
+    (dict(tol=0.0), "tol"),
+    (dict(max_iter=0), "max_iter"),
+    (dict(max_iter=10_000), "max_iter"),
+    (dict(driven=True, bc=(1, 0, 1)), "periodic x"),
+    (dict(driven=True, mu_tol=0.0), "mu_tol"),
+    (dict(driven=True, nx=30, ny=30, nz=31), None),   # coarsens fine (even periodic)
+])
+def test_plan_validation(lib, kw, msg):
+    base = dict(nx=32, ny=32, nz=16)
+    base.update(kw)
+    p = tdgl.make_params(**base)
+    if msg is None:
+        assert tdgl.plan([p]) > 0
+        return
+    with pytest.raises(tdgl.TdglError) as e:
+        tdgl.plan([p])
+    assert e.value.status == 1 and msg in str(e.value)
+
+
+def test_plan_rejects_uncoarsenable_poisson_grid(lib):
+    p = tdgl.make_params(97, 97, 16, driven=True)  # odd periodic sizes: no multigrid
+    with pytest.raises(tdgl.TdglError) as e:
+        tdgl.plan([p])
+    assert "coarsened" in str(e.value)
+    # undriven: no Poisson solve, accepted
+    assert tdgl.plan([tdgl.make_params(97, 97, 16)]) > 0
+
+
+def test_reserved_fields_must_be_zero(lib):
+    p = tdgl.make_params(8, 8, 8)
+    p.reserved[3] = 1
+    with pytest.raises(tdgl.TdglError):
+        tdgl.plan([p])
+
+
+def test_create_rejects_bad_workspace_without_device(lib):
+    p = tdgl.make_params(8, 8, 8)
+    arr = (tdgl.Params * 1)(p)
+    ctx = ctypes.c_void_p()
+    # NULL workspace is rejected before any device call
+    st = lib.tdgl_create(1, arr, None, 0, None, ctypes.byref(ctx))
+    assert st == 2 and b"workspace" in lib.tdgl_last_error()
+    st = lib.tdgl_create(1, arr, ctypes.c_void_p(257), 1 << 30, None, ctypes.byref(ctx))
+    assert st == 2 and b"aligned" in lib.tdgl_last_error()
+
+
+@pytest.mark.parametrize("open_", [(False, False, True), (False, False, False), (True, False, True),
+                                   (False, True, False)])
+def test_flux_quantisation_matches_oracle(lib, open_):
+    """Host helper vs the oracle's rounding to whole flux quanta
+    (Sec. 3.3.1, implications for the magnetic field)."""
+    for (nx, ny, nz, Bx, Bz) in [(32, 32, 16, 0.0, 0.1), (256, 256, 64, 0.13, 0.1),
+                                 (1024, 1024, 128, 0.0, 0.2), (96, 96, 48, 0.21, 0.05)]:
+        bc = tuple(tdgl.TDGL_OPEN if o else tdgl.TDGL_PERIODIC for o in open_)
+        p = tdgl.make_params(nx, ny, nz, bc=bc)
+        g = O.Grid(nx, ny, nz, open_=open_)
+        qx, qz = tdgl.quantize_field(p, Bx, Bz)
+        ox, oz = O.quantize_field(g, Bx, Bz)
+        assert qx == pytest.approx(ox, rel=1e-15, abs=0)
+        assert qz == pytest.approx(oz, rel=1e-15, abs=0)
+
+
+def test_quantised_field_values_of_the_workloads(lib):
+    """B_eff of the measured workloads (n = round(B Lx Ly / 2 pi))."""
+    cases = [((32, 32, 16), 0.1, 4), ((256, 256, 64), 0.1, 261), ((128, 128, 32), 0.1, 65),
+             ((1024, 1024, 128), 0.2, 8344)]
+    for (nx, ny, nz), B, nq in cases:
+        p = tdgl.make_params(nx, ny, nz)
+        _, qz = tdgl.quantize_field(p, 0.0, B)
+        assert qz == pytest.approx(2 * math.pi * nq / (nx * 0.5 * ny * 0.5), rel=1e-14)

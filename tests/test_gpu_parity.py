@@ -1,0 +1,154 @@
+"""GPU (HIP through the C ABI) against the FP64 oracle on identical seeded
+inputs.  Tolerances: max-norm relative error <= 1e-5 after one step from an
+identical state and <= 1e-3 after 100 undriven steps (the stated targets);
+integer work (inclusion map, sphere count) bit-exact."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1409_8340_amd import inputs, tdgl
+from tests.harness import Case, rel_maxerr
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    tdgl.load()
+
+
+def _one_step(case, mode="exact", nsteps=1):
+    s = case.solver()
+    stats = s.step(nsteps)
+    psi = s.get_psi().cpu().numpy()
+    out = dict(psi=psi, stats=stats, sc=s.get_scalars())
+    if case.driven:
+        out["mu"] = s.get_mu().cpu().numpy()
+    st = case.oracle_state()
+    O.run(case.grid, case.oracle_params(mode=mode), case.eps.astype(np.float64), st, nsteps)
+    s.close()
+    return out, st
+
+
+def test_one_step_undriven_small():
+    """32x32x16, B = 0.1 along z, quasi-periodic x,y, open z, eps = 1: one
+    step from the same state vs the exact solution of the CN system."""
+    c = Case(32, 32, 16, Bz=0.1, tol=1e-12)
+    g, o = _one_step(c)
+    err = rel_maxerr(g["psi"], o.psi)
+    print("rel err", err, "sweeps", g["stats"])
+    assert err <= 1e-5
+    assert g["stats"]["capped_steps"] == 0
+
+
+def test_mirror_iteration_matches_paper_stop_rule():
+    """At the paper's stop rule (tol = 1e-8 on max|r|^2) the GPU takes the same
+    number of sweeps as the oracle's replay of the Jacobi iteration."""
+    c = Case(32, 32, 16, Bz=0.1, tol=1e-8)
+    g, o = _one_step(c, mode="mirror", nsteps=3)
+    assert g["stats"]["sweeps_sum"] == sum(o.sweeps_hist)
+    assert rel_maxerr(g["psi"], o.psi) <= 1e-5
+
+
+def test_hundred_undriven_steps():
+    c = Case(32, 32, 16, Bz=0.1, tol=1e-12)
+    g, o = _one_step(c, nsteps=100)
+    err = rel_maxerr(g["psi"], o.psi)
+    print("100-step rel err", err)
+    assert err <= 1e-3
+
+
+@pytest.mark.parametrize("shape,open_,g_,Bx", [
+    ((70, 37, 9), (False, False, True), 1.0, 0.0),     # ragged tiles in x and y
+    ((40, 24, 12), (True, True, True), 1.3, 0.2),      # open faces everywhere, anisotropy, tilted B
+    ((32, 32, 8), (False, False, False), 1.0, 0.0),    # fully periodic
+    ((48, 20, 1), (False, False, True), 1.0, 0.0),     # one-node z axis (2D film)
+    ((16, 16, 40), (False, True, False), 1.0, 0.15),   # open y, periodic z, Bx != 0
+])
+def test_one_step_boundary_variants(shape, open_, g_, Bx):
+    c = Case(*shape, open_=open_, g=g_, Bx=Bx, Bz=0.12, tol=1e-12)
+    eps = inputs.random_real(c.grid.shape, 5, 0.3, 1.0)
+    c.eps = eps
+    g, o = _one_step(c)
+    err = rel_maxerr(g["psi"], o.psi)
+    print(shape, open_, "rel err", err)
+    assert err <= 1e-5
+
+
+def test_one_step_driven_with_inclusions():
+    """Driven step (J, K, mu~) on a 64x64x16 grid with spherical inclusions:
+    psi after one step, the new K and E, and the new mu~ vs the oracle's exact
+    Poisson solution."""
+    c = Case(64, 64, 16, Bz=0.1, J=0.02, driven=True, tol=1e-12, mu_tol=1e-6, K0=0.37)
+    w = inputs.Workload("t", 64, 64, 16, fraction=0.10, d=4.0, incl_seed=77)
+    cen, dia = inputs.candidates_for(w)
+    eps, used, frac = O.gen_inclusions(c.grid, cen, dia, 0.10)
+    c.eps = eps.astype(np.float32)
+    c.mu0 = inputs.random_real(c.grid.shape, 9, -0.05, 0.05)
+    g, o = _one_step(c)
+    err = rel_maxerr(g["psi"], o.psi)
+    mu_err = float(np.max(np.abs(g["mu"] - o.mu)))
+    print("psi", err, "mu abs", mu_err, "max|mu|", np.max(np.abs(o.mu)), g["stats"], g["sc"], o.K, o.last_E)
+    assert err <= 1e-5
+    assert abs(g["sc"]["K"] - o.K) <= 1e-6
+    assert abs(g["sc"]["E_last"] - o.last_E) <= 1e-6
+    assert mu_err <= 1e-4 * max(1.0, float(np.max(np.abs(o.mu))))
+
+
+def test_inclusion_generator_bit_exact():
+    for (nx, ny, nz, law, frac, seed) in [(64, 64, 16, "fixed", 0.10, 3), (96, 96, 48, "uniform", 0.2, 4),
+                                          (128, 128, 32, "lognormal", 0.15, 5)]:
+        grid = O.Grid(nx, ny, nz)
+        w = inputs.Workload("t", nx, ny, nz, fraction=frac, law=law, d=4.0, incl_seed=seed,
+                            extra={"median": 3.0, "sigma": 0.3})
+        cen, dia = inputs.candidates_for(w)
+        eps_o, used_o, frac_o = O.gen_inclusions(grid, cen, dia, frac)
+        s = tdgl.Solver(tdgl.make_params(nx, ny, nz))
+        used, f = s.gen_inclusions(cen, dia, frac)
+        eps_g = s.get_eps().cpu().numpy()
+        assert used == used_o
+        assert f == frac_o
+        assert np.array_equal(eps_g, eps_o.astype(np.float32))
+        s.close()
+
+
+def test_free_energy_matches_oracle():
+    c = Case(40, 36, 12, Bz=0.15, tol=1e-12)
+    c.eps = inputs.random_real(c.grid.shape, 21, -1.0, 1.0)
+    s = c.solver()
+    s.step(2)
+    obs = s.observables()
+    psi = s.get_psi().cpu().numpy().astype(np.complex128)
+    links = O.landau_links(c.grid, c.Bx, c.Bz, 0.0)
+    F = O.free_energy(c.grid, links, c.eps.astype(np.float64), psi)
+    print("F gpu", obs["F"], "oracle", F)
+    assert abs(obs["F"] - F) <= 1e-5 * abs(F)
+    assert abs(obs["psi2_mean"] - np.mean(np.abs(psi) ** 2)) <= 1e-6
+    s.close()
+
+
+def test_batch_matches_single_instances():
+    """Three instances of different shapes in one context advance exactly
+    like three separate contexts (same kernels, same arithmetic order)."""
+    cases = [Case(32, 32, 16, Bz=0.1, tol=1e-10, psi_seed=1),
+             Case(48, 40, 12, Bz=0.2, tol=1e-10, psi_seed=2, driven=True, J=0.01),
+             Case(64, 16, 20, Bz=0.05, tol=1e-10, psi_seed=3, driven=True, J=0.03)]
+    singles = []
+    for c in cases:
+        s = c.solver()
+        s.step(5)
+        singles.append((s.get_psi().cpu().numpy(), s.get_scalars()))
+        s.close()
+    b = tdgl.Solver([c.params for c in cases])
+    for i, c in enumerate(cases):
+        c.load_into(b, i)
+    b.step(5)
+    for i, c in enumerate(cases):
+        psi = b.get_psi(i).cpu().numpy()
+        assert np.array_equal(psi, singles[i][0]), i
+        assert b.get_scalars(i)["K"] == singles[i][1]["K"]
+    b.close()
