@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Throughput of the implicit TDGL step on one MI355X.
+
+Workload (default): 1024 x 1024 x 128 nodes, h = 0.5 xi, B = 0.2 Hc2 along z
+(rounded to 8344 flux quanta), current J = 0.03 along x, 15 % random
+spherical inclusions with lognormal diameters (median 3 xi, sigma 0.3,
+eps = -1 inside, +1 outside), x periodic, y quasi-periodic, z open,
+dt = 0.1, Jacobi stop max|r|^2 < 1e-8.  Synthetic seeded inputs.
+
+A step is one full pass of the method: assemble, Jacobi sweeps to the stop
+rule, J_av / K update, Poisson right side and multigrid solve.  W untimed
+warm-up steps are followed by K timed steps bracketed by device
+synchronisation.  value = nodes * K / seconds (cell-updates per second).
+
+The roofline entry is for the dominant kernel, the Jacobi sweep: its launches
+are bracketed by HIP events on the solver's stream inside the timed region,
+and achieved = algorithmic bytes per launch (32 B per node: read psi, b/M and
+(ht/2)/M, write psi, complex64 each) / mean launch time.
+
+cpu_baseline times the FP64 oracle (test infrastructure, not the product)
+on a bounded sample of the same physics.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+SWEEP_BYTES_PER_NODE = 32      # psi in, b/M, (ht/2)/M, psi out (complex64)
+ASSEMBLE_BYTES_PER_NODE = 40   # psi^-, eps, mu in; b/M, (ht/2)/M, psi^(1) out
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stencil_sweep_c5_traffic.txt")
+SWEEP_SRC = os.path.join(ROOT, "paper_1409_8340_amd", "csrc", "k_gl.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_sha():
+    return hashlib.sha256(open(SWEEP_SRC, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic(n_nodes):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by the plain-copy
+    calibration factor), or None when absent or taken on another kernel."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        if kv.get("kernel_source_sha") != kernel_sha() or int(kv.get("nodes", -1)) != n_nodes:
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def setup(w, tdgl, inputs, torch, tol):
+    p = tdgl.make_params(w.nx, w.ny, w.nz, h=w.h, driven=w.driven, tol=tol, max_iter=100,
+                         mu_tol=1e-5, mu_max_cycles=20)
+    s = tdgl.Solver(p)
+    Bx, Bz = s.set_field(0.0, w.B, quantize=True)
+    if w.driven:
+        s.set_current(w.J)
+    used = frac = None
+    if w.fraction > 0:
+        cen, dia = inputs.candidates_for(w)
+        used, frac = s.gen_inclusions(cen, dia, w.fraction, w.eps_in, w.eps_out)
+    psi0 = inputs.psi_init(w.nx, w.ny, w.nz, w.psi_seed)
+    s.set_psi(torch.from_numpy(psi0).cuda())
+    del psi0
+    return s, Bz, used, frac
+
+
+def cpu_baseline(w, seconds_target=20.0):
+    """FP64 oracle on a bounded sample: the workload's physics (h, B, J,
+    inclusion law and fraction, psi init, Jacobi stop rule) on a
+    256 x 256 x min(nz, 128) sub-box, as many steps as fit the time target
+    (at least one).  Returns the entry for the JSON line."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_1409_8340_amd import inputs
+    nx, ny, nz = min(w.nx, 256), min(w.ny, 256), min(w.nz, 128)
+    grid = O.Grid(nx, ny, nz, w.h, w.h, w.h, w.open_)
+    Bx, Bz = O.quantize_field(grid, 0.0, w.B)
+    sub = inputs.Workload(w.name + "_sample", nx, ny, nz, h=w.h, B=w.B, J=w.J, driven=w.driven,
+                          fraction=w.fraction, law=w.law, d=w.d, psi_seed=w.psi_seed,
+                          incl_seed=w.incl_seed, extra=w.extra)
+    eps = np.ones(grid.shape)
+    if w.fraction > 0:
+        cen, dia = inputs.candidates_for(sub)
+        eps, _, _ = O.gen_inclusions(grid, cen, dia, w.fraction)
+    st = O.new_state(grid, inputs.psi_init(nx, ny, nz, w.psi_seed).astype(np.complex128))
+    p = O.Params(Bx=Bx, Bz=Bz, J_ext=w.J, dt=w.dt, tol=w.tol, mode="mirror", driven=w.driven)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        O.step(grid, p, eps, st)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds_target or steps >= 50:
+            break
+        if el / steps * (steps + 1) > 1.5 * seconds_target:
+            break
+    el = time.perf_counter() - t0
+    return {"value": grid.N * steps / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle, {nx}x{ny}x{nz} sub-box of the workload's physics, {steps} steps from "
+                      f"the seeded initial state, Jacobi stop rule max|r|^2<{w.tol:g} (same as GPU), exact "
+                      f"Poisson; {el:.1f} s on {threads} OpenMP threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c5_1024x1024x128")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--breakdown-steps", type=int, default=5,
+                    help="extra untimed steps profiled per kernel class")
+    ap.add_argument("--copy-calib-gib", type=float, default=0.0,
+                    help="run a plain device copy of this size (for counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this solver runs on one GPU; multi-GPU runs are not part of this build "
+              "(use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1409_8340_amd import inputs, tdgl
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w = inputs.WORKLOADS[args.workload]
+    N = w.nx * w.ny * w.nz
+
+    log(f"[bench] setting up {w.name} ({N} nodes)")
+    s, Bz, used, frac = setup(w, tdgl, inputs, torch, w.tol)
+    log(f"[bench] B_eff={Bz:.6f} inclusions={used} fraction={frac}")
+    if args.copy_calib_gib > 0:
+        nb = int(args.copy_calib_gib * (1 << 30))
+        a = torch.empty(nb, dtype=torch.uint8, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log(f"[bench] copy calibration: {nb} bytes copied")
+    for i in range(args.warmup):
+        s.step(1, stats=False)
+        if (i + 1) % 10 == 0:
+            torch.cuda.synchronize()
+            log(f"[bench] warmup {i + 1}/{args.warmup}")
+    torch.cuda.synchronize()
+
+    s.profile_start(["assemble", "sweep"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = s.step(args.steps, stats=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = s.profile_stop()
+    el = t1 - t0
+    log(f"[bench] timed {args.steps} steps in {el:.3f} s; sweeps {st['sweeps_sum']} "
+        f"(min {st['sweeps_min']} max {st['sweeps_max']}), mu cycles {st['mu_cycles_sum']}")
+
+    breakdown = None
+    if args.breakdown_steps > 0:
+        s.profile_start()
+        s.step(args.breakdown_steps, stats=True)
+        bd = s.profile_stop()
+        tot = sum(v["ms"] for v in bd.values())
+        breakdown = {k: {"launches": v["launches"], "ms": round(v["ms"], 4),
+                         "share": round(v["ms"] / tot, 4) if tot else 0.0} for k, v in bd.items()}
+    obs = s.observables()
+
+    sw = prof["sweep"]
+    sweep_ms = sw["ms"] / max(sw["launches"], 1)
+    achieved = SWEEP_BYTES_PER_NODE * N / (sweep_ms * 1e-3) / 1e9
+    asm = prof["assemble"]
+    asm_ms = asm["ms"] / max(asm["launches"], 1)
+    traffic = read_traffic(N)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 oracle on a bounded sample")
+        cpu = cpu_baseline(w, args.cpu_seconds)
+        log(f"[bench] oracle {cpu['value']:.3e} cell-updates/s")
+
+    out = {
+        "metric": "TDGL cell-updates/s + %HBM roofline; fwd+adjoint step time vs plain step",
+        "value": N * args.steps / el,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 (FP32 complex psi) + f64 reductions",
+        "data": "synthetic",
+        "config": {"workload": w.name, "grid": [w.nx, w.ny, w.nz], "h": w.h, "B_eff": Bz, "J": w.J,
+                   "inclusions": used, "inclusion_fraction": frac, "tol": w.tol, "dt": w.dt,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "tdgl::k_stencil<1> (Jacobi sweep)",
+                     "bytes_per_launch": SWEEP_BYTES_PER_NODE * N, "mean_launch_ms": sweep_ms,
+                     "launches": sw["launches"]},
+        "cpu_baseline": cpu,
+        "extra": {
+            "sweeps_per_step": st["sweeps_sum"] / max(st["steps"], 1),
+            "cell_sweeps_per_s": N * st["sweeps_sum"] / el,
+            "mu_cycles_per_step": st["mu_cycles_sum"] / max(st["steps"], 1),
+            "assemble_ms": asm_ms,
+            "assemble_GBps": ASSEMBLE_BYTES_PER_NODE * N / (asm_ms * 1e-3) / 1e9,
+            "kernel_breakdown": breakdown,
+            "E_mean": obs["E_mean"], "F": obs["F"], "psi2_mean": obs["psi2_mean"],
+            "kernel_source_sha": kernel_sha(),
+        },
+    }
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -218,6 +218,31 @@ tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats);
  * Synchronising. */
 tdgl_status tdgl_observables(tdgl_ctx *ctx, int inst, tdgl_obs *obs);
 
+/* Kernel classes of the per-kernel profile (the time profile of one step,
+ * kernel by kernel, as in the paper's performance section, Sec. 4.3). */
+#define TDGL_K_ASSEMBLE 0   /* assemble b, M_mm fused with the first Jacobi iteration */
+#define TDGL_K_SWEEP 1      /* one Jacobi iteration (all later sweeps)              */
+#define TDGL_K_CURRENT 2    /* J_av partial sums and the K update                   */
+#define TDGL_K_RHS 3        /* Poisson right side and its weighted mean              */
+#define TDGL_K_MG_FINE 4    /* multigrid work on the finest level                   */
+#define TDGL_K_MG_COARSE 5  /* multigrid work on coarser levels (incl. transfers)   */
+#define TDGL_K_OTHER 6      /* solve bookkeeping and the mu~ mean                   */
+#define TDGL_K_COUNT 7
+
+typedef struct tdgl_prof {
+    long long launches[TDGL_K_COUNT]; /* launches per class                          */
+    double ms[TDGL_K_COUNT];          /* summed device time per class (HIP events)  */
+} tdgl_prof;
+
+/* Starts timing the kernel classes whose bit is set in `mask` (bit c for
+ * class c): every launch of such a kernel inside tdgl_step is bracketed by
+ * two HIP events on the context's stream.  Resets the accumulators. */
+tdgl_status tdgl_profile_start(tdgl_ctx *ctx, unsigned mask);
+
+/* Stops timing and returns the per-class launch counts and summed event
+ * times since tdgl_profile_start.  Synchronising. */
+tdgl_status tdgl_profile_stop(tdgl_ctx *ctx, tdgl_prof *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -307,6 +307,13 @@ struct tdgl_ctx {
     int nlev_max = 0;
     bool any_driven = false;
     int max_iter = 1, max_cycles = 1;
+    // per-kernel-class timing (tdgl_profile_start/stop)
+    unsigned prof_mask = 0;
+    std::vector<hipEvent_t> prof_pool;
+    std::vector<std::pair<int, int>> prof_recs;  // (class, index of the first event of the pair)
+    size_t prof_used = 0;
+    long long prof_launches[TDGL_K_COUNT] = {0};
+    double prof_ms[TDGL_K_COUNT] = {0};
 };
 
 namespace {
@@ -531,6 +538,41 @@ tdgl_status upload_tables(tdgl_ctx *ctx) {
 const int *pref_mg(tdgl_ctx *c, int l) { return c->d_pref_mg + (size_t)l * (c->n + 1); }
 const int *pref_mid(tdgl_ctx *c, int l) { return c->d_pref_mid + (size_t)l * (c->n + 1); }
 
+// Resolve the recorded event pairs into the per-class sums (waits for the
+// last recorded event).
+tdgl_status prof_flush(tdgl_ctx *c) {
+    if (c->prof_recs.empty()) return TDGL_OK;
+    HIPCHK(hipEventSynchronize(c->prof_pool[c->prof_recs.back().second + 1]));
+    for (auto &r : c->prof_recs) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, c->prof_pool[r.second], c->prof_pool[r.second + 1]));
+        c->prof_ms[r.first] += ms;
+        c->prof_launches[r.first] += 1;
+    }
+    c->prof_recs.clear();
+    c->prof_used = 0;
+    return TDGL_OK;
+}
+
+// Bracket one launch of kernel class `cls` (no-op unless profiled).
+struct ProfScope {
+    tdgl_ctx *c;
+    int cls;
+    int idx = -1;
+    ProfScope(tdgl_ctx *c_, int cls_) : c(c_), cls(cls_) {
+        if (!(c->prof_mask & (1u << cls))) return;
+        if (c->prof_used + 2 > c->prof_pool.size()) prof_flush(c);
+        idx = (int)c->prof_used;
+        c->prof_used += 2;
+        (void)hipEventRecord(c->prof_pool[idx], c->stream);
+    }
+    ~ProfScope() {
+        if (idx < 0) return;
+        (void)hipEventRecord(c->prof_pool[idx + 1], c->stream);
+        c->prof_recs.push_back({cls, idx});
+    }
+};
+
 // One multigrid V-cycle for every driven instance (cycle index cyc).
 // Instances may have hierarchies of different depth: each per-level launch
 // covers only the instances the operation applies to (prefix tables with
@@ -543,9 +585,13 @@ tdgl_status enqueue_vcycle(tdgl_ctx *c, int cyc) {
     const int n = c->n;
     const int L = c->nlev_max;
     auto grid = [](int b) { return dim3(std::max(b, 1)); };
-    hipLaunchKernelGGL(k_mg_residual, grid(c->tot_mg[0]), dim3(256), 0, s, c->d_inst, pref_mg(c, 0), n, 0, 0,
-                       cyc);
+    {
+        ProfScope ps(c, TDGL_K_MG_FINE);
+        hipLaunchKernelGGL(k_mg_residual, grid(c->tot_mg[0]), dim3(256), 0, s, c->d_inst, pref_mg(c, 0), n, 0,
+                           0, cyc);
+    }
     for (int l = 0; l + 1 < L; ++l) {
+        ProfScope ps(c, TDGL_K_MG_COARSE);
         if (l >= 1) {
             hipLaunchKernelGGL(k_mg_smooth, grid(c->tot_mid[l]), dim3(256), 0, s, c->d_inst, pref_mid(c, l), n,
                                l, 0, 1, cyc, kOmega);
@@ -556,8 +602,12 @@ tdgl_status enqueue_vcycle(tdgl_ctx *c, int cyc) {
         hipLaunchKernelGGL(k_mg_restrict, grid(c->tot_mg[l + 1]), dim3(256), 0, s, c->d_inst,
                            pref_mg(c, l + 1), n, l, cyc, kOmega);
     }
-    hipLaunchKernelGGL(k_mg_coarsest, dim3(n), dim3(CO_THREADS), 0, s, c->d_inst, n, cyc);
+    {
+        ProfScope ps(c, TDGL_K_MG_COARSE);
+        hipLaunchKernelGGL(k_mg_coarsest, dim3(n), dim3(CO_THREADS), 0, s, c->d_inst, n, cyc);
+    }
     for (int l = L - 2; l >= 0; --l) {
+        ProfScope ps(c, l == 0 ? TDGL_K_MG_FINE : TDGL_K_MG_COARSE);
         const int ifine = (l == 0) ? 0 : 1;
         hipLaunchKernelGGL(k_mg_prolong, grid(c->tot_mid[l]), dim3(256), 0, s, c->d_inst, pref_mid(c, l), n, l,
                            ifine, cyc);
@@ -657,6 +707,7 @@ tdgl_status tdgl_destroy(tdgl_ctx *ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     for (auto &e : ctx->ev) if (e) (void)hipEventDestroy(e);
     for (auto &e : ctx->evc) if (e) (void)hipEventDestroy(e);
+    for (auto &e : ctx->prof_pool) if (e) (void)hipEventDestroy(e);
     if (ctx->h_res) (void)hipHostFree(ctx->h_res);
     if (ctx->h_mures) (void)hipHostFree(ctx->h_mures);
     delete ctx;
@@ -872,8 +923,11 @@ tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats) {
     bool strict_fail = false;
     for (int step = 0; step < nsteps; ++step) {
         // ---- Jacobi solve (all instances) --------------------------------
-        hipLaunchKernelGGL(k_stencil<MODE_FIRST>, dim3(ctx->tot_st), dim3(WG), 0, s, ctx->d_inst,
-                           ctx->d_pref_st, n, 0);
+        {
+            ProfScope ps(ctx, TDGL_K_ASSEMBLE);
+            hipLaunchKernelGGL(k_stencil<MODE_FIRST>, dim3(ctx->tot_st), dim3(WG), 0, s, ctx->d_inst,
+                               ctx->d_pref_st, n, 0);
+        }
         LAUNCHCHK();
         HIPCHK(hipMemcpyAsync(ctx->h_res, ctx->d_res, n * 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipEventRecord(ctx->ev[0], s));
@@ -897,15 +951,21 @@ tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats) {
             }
             if (remaining == 0 || launched == ctx->max_iter) break;
             const int l = launched;
-            hipLaunchKernelGGL(k_stencil<MODE_SWEEP>, dim3(ctx->tot_st), dim3(WG), 0, s, ctx->d_inst,
-                               ctx->d_pref_st, n, l);
+            {
+                ProfScope ps(ctx, TDGL_K_SWEEP);
+                hipLaunchKernelGGL(k_stencil<MODE_SWEEP>, dim3(ctx->tot_st), dim3(WG), 0, s, ctx->d_inst,
+                                   ctx->d_pref_st, n, l);
+            }
             LAUNCHCHK();
             HIPCHK(hipMemcpyAsync(ctx->h_res + (size_t)l * n, ctx->d_res + (size_t)l * n, n * 4,
                                   hipMemcpyDeviceToHost, s));
             HIPCHK(hipEventRecord(ctx->ev[l], s));
             ++launched;
         }
-        hipLaunchKernelGGL(k_solve_finalize, dim3(cdiv(n, 64)), dim3(64), 0, s, ctx->d_inst, n);
+        {
+            ProfScope ps(ctx, TDGL_K_OTHER);
+            hipLaunchKernelGGL(k_solve_finalize, dim3(cdiv(n, 64)), dim3(64), 0, s, ctx->d_inst, n);
+        }
         LAUNCHCHK();
         for (int i = 0; i < n; ++i) {
             const InstHost &h = ctx->inst[i];
@@ -924,12 +984,18 @@ tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats) {
         }
         // ---- current, K and the scalar potential (driven instances) -------
         if (ctx->any_driven) {
-            hipLaunchKernelGGL(k_jav_partial, dim3(ctx->tot_flat), dim3(256), 0, s, ctx->d_inst,
-                               ctx->d_pref_flat, n);
-            hipLaunchKernelGGL(k_kupdate, dim3(n), dim3(256), 0, s, ctx->d_inst, ctx->d_np_flat);
-            hipLaunchKernelGGL(k_stencil<MODE_RHS>, dim3(ctx->tot_st), dim3(WG), 0, s, ctx->d_inst,
-                               ctx->d_pref_st, n, 0);
-            hipLaunchKernelGGL(k_reduce_to_state, dim3(n), dim3(256), 0, s, ctx->d_inst, ctx->d_np_st, 0, 1);
+            {
+                ProfScope ps(ctx, TDGL_K_CURRENT);
+                hipLaunchKernelGGL(k_jav_partial, dim3(ctx->tot_flat), dim3(256), 0, s, ctx->d_inst,
+                                   ctx->d_pref_flat, n);
+                hipLaunchKernelGGL(k_kupdate, dim3(n), dim3(256), 0, s, ctx->d_inst, ctx->d_np_flat);
+            }
+            {
+                ProfScope ps(ctx, TDGL_K_RHS);
+                hipLaunchKernelGGL(k_stencil<MODE_RHS>, dim3(ctx->tot_st), dim3(WG), 0, s, ctx->d_inst,
+                                   ctx->d_pref_st, n, 0);
+                hipLaunchKernelGGL(k_reduce_to_state, dim3(n), dim3(256), 0, s, ctx->d_inst, ctx->d_np_st, 0, 1);
+            }
             LAUNCHCHK();
             std::fill(mconv_at.begin(), mconv_at.end(), -1);
             int mrem = 0;
@@ -962,10 +1028,14 @@ tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats) {
                 HIPCHK(hipEventRecord(ctx->evc[mlaunched], s));
                 ++mlaunched;
             }
-            hipLaunchKernelGGL(k_mg_finalize, dim3(cdiv(n, 64)), dim3(64), 0, s, ctx->d_inst, n);
-            hipLaunchKernelGGL(k_mu_mean_partial, dim3(std::max(ctx->tot_mg[0], 1)), dim3(256), 0, s,
-                               ctx->d_inst, pref_mg(ctx, 0), n);
-            hipLaunchKernelGGL(k_reduce_to_state, dim3(n), dim3(256), 0, s, ctx->d_inst, ctx->d_np_mg0, 1, 1);
+            {
+                ProfScope ps(ctx, TDGL_K_OTHER);
+                hipLaunchKernelGGL(k_mg_finalize, dim3(cdiv(n, 64)), dim3(64), 0, s, ctx->d_inst, n);
+                hipLaunchKernelGGL(k_mu_mean_partial, dim3(std::max(ctx->tot_mg[0], 1)), dim3(256), 0, s,
+                                   ctx->d_inst, pref_mg(ctx, 0), n);
+                hipLaunchKernelGGL(k_reduce_to_state, dim3(n), dim3(256), 0, s, ctx->d_inst, ctx->d_np_mg0, 1,
+                                   1);
+            }
             LAUNCHCHK();
             for (int i = 0; i < n; ++i) {
                 const InstHost &h = ctx->inst[i];
@@ -987,6 +1057,30 @@ tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats) {
         *stats = acc;
     }
     if (strict_fail) return fail(TDGL_ENOCONV, "a Jacobi solve reached max_iter without meeting tol");
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_profile_start(tdgl_ctx *ctx, unsigned mask) {
+    if (!ctx) return fail(TDGL_EINVAL, "null context");
+    if (mask >> TDGL_K_COUNT) return fail(TDGL_EINVAL, "profile mask has bits beyond TDGL_K_COUNT");
+    if (ctx->prof_pool.empty()) {
+        ctx->prof_pool.resize(8192);
+        for (auto &e : ctx->prof_pool) HIPCHK(hipEventCreate(&e));
+    }
+    ctx->prof_recs.clear();
+    ctx->prof_used = 0;
+    for (int k = 0; k < TDGL_K_COUNT; ++k) { ctx->prof_ms[k] = 0; ctx->prof_launches[k] = 0; }
+    ctx->prof_mask = mask;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_profile_stop(tdgl_ctx *ctx, tdgl_prof *out) {
+    if (!ctx) return fail(TDGL_EINVAL, "null context");
+    tdgl_status s = prof_flush(ctx);
+    if (s) return s;
+    ctx->prof_mask = 0;
+    if (out)
+        for (int k = 0; k < TDGL_K_COUNT; ++k) { out->launches[k] = ctx->prof_launches[k]; out->ms[k] = ctx->prof_ms[k]; }
     return TDGL_OK;
 }
 

@@ -68,6 +68,17 @@ class Obs(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+KERNEL_CLASSES = ["assemble", "sweep", "current", "rhs", "mg_fine", "mg_coarse", "other"]
+
+
+class Prof(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_longlong * 7), ("ms", ctypes.c_double * 7)]
+
+    def as_dict(self):
+        return {k: {"launches": self.launches[i], "ms": self.ms[i]}
+                for i, k in enumerate(KERNEL_CLASSES)}
+
+
 _lib = None
 
 _SIGS = {
@@ -97,6 +108,8 @@ _SIGS = {
     "tdgl_voltage_window_reset": ([ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
     "tdgl_step": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(StepStats)], ctypes.c_int),
     "tdgl_observables": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(Obs)], ctypes.c_int),
+    "tdgl_profile_start": ([ctypes.c_void_p, ctypes.c_uint], ctypes.c_int),
+    "tdgl_profile_stop": ([ctypes.c_void_p, ctypes.POINTER(Prof)], ctypes.c_int),
 }
 
 
@@ -282,6 +295,17 @@ class Solver:
         st = StepStats()
         _check(load().tdgl_step(self._ctx, int(nsteps), ctypes.byref(st) if stats else None))
         return st.as_dict() if stats else None
+
+    def profile_start(self, classes=None):
+        mask = 0
+        for c in (classes or KERNEL_CLASSES):
+            mask |= 1 << KERNEL_CLASSES.index(c)
+        _check(load().tdgl_profile_start(self._ctx, mask))
+
+    def profile_stop(self):
+        p = Prof()
+        _check(load().tdgl_profile_stop(self._ctx, ctypes.byref(p)))
+        return p.as_dict()
 
     def observables(self, inst=0):
         o = Obs()
