@@ -66,9 +66,9 @@ def read_traffic(n_nodes):
         return None
 
 
-def setup(w, tdgl, inputs, torch, tol):
+def setup(w, tdgl, inputs, torch, tol, mu_rtol):
     p = tdgl.make_params(w.nx, w.ny, w.nz, h=w.h, driven=w.driven, tol=tol, max_iter=100,
-                         mu_tol=1e-5, mu_max_cycles=20)
+                         mu_tol=1e-5, mu_rtol=mu_rtol, mu_max_cycles=20)
     s = tdgl.Solver(p)
     Bx, Bz = s.set_field(0.0, w.B, quantize=True)
     if w.driven:
@@ -131,6 +131,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--breakdown-steps", type=int, default=5,
                     help="extra untimed steps profiled per kernel class")
+    ap.add_argument("--mu-rtol", type=float, default=0.03,
+                    help="Poisson stop: residual below max(1e-5, mu_rtol * initial residual)")
     ap.add_argument("--copy-calib-gib", type=float, default=0.0,
                     help="run a plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -148,7 +150,7 @@ def main():
     N = w.nx * w.ny * w.nz
 
     log(f"[bench] setting up {w.name} ({N} nodes)")
-    s, Bz, used, frac = setup(w, tdgl, inputs, torch, w.tol)
+    s, Bz, used, frac = setup(w, tdgl, inputs, torch, w.tol, args.mu_rtol)
     log(f"[bench] B_eff={Bz:.6f} inclusions={used} fraction={frac}")
     if args.copy_calib_gib > 0:
         nb = int(args.copy_calib_gib * (1 << 30))
@@ -214,6 +216,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "grid": [w.nx, w.ny, w.nz], "h": w.h, "B_eff": Bz, "J": w.J,
                    "inclusions": used, "inclusion_fraction": frac, "tol": w.tol, "dt": w.dt,
+                   "mu_tol": 1e-5, "mu_rtol": args.mu_rtol,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

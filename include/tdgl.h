@@ -69,7 +69,8 @@ typedef struct tdgl_params {
     double tol;           /* stop when max_m |r_m|^2 < tol (Eq. convergence) */
     int max_iter;         /* Jacobi sweep cap per step (1..TDGL_MAX_ITER)    */
     int driven;           /* 1: solve K and mu~ (Sec. 2.2); 0: K = mu~ = 0    */
-    double mu_tol;        /* Poisson stop: max_m |Delta mu~ - f|_m < mu_tol  */
+    double mu_tol;        /* Poisson stop: max_m |Delta mu~ - f|_m below      */
+    double mu_rtol;       /*   max(mu_tol, mu_rtol * that residual at the start of the step's solve) */
     int mu_max_cycles;    /* multigrid cycle cap per step (1..TDGL_MAX_CYCLES) */
     int strict;           /* 1: tdgl_step returns TDGL_ENOCONV on a capped solve */
     int tile_cz;          /* z planes per stencil work-group; 0 = library default */
@@ -203,7 +204,8 @@ tdgl_status tdgl_voltage_window_reset(tdgl_ctx *ctx, int inst);
  *   4. driven only: Poisson equation of Sec. 3.2 for mu~ with the links at
  *      the new K, solved by multigrid V-cycles whose smoother is the
  *      pseudo-time relaxation of Sec. 3.2 (damped Jacobi) until
- *      max|Delta mu~ - f| < mu_tol; weighted mean of mu~ fixed to zero.
+ *      max|Delta mu~ - f| < max(mu_tol, mu_rtol * its value before the first
+ *      cycle); weighted mean of mu~ fixed to zero.
  * Enqueues work and waits on small device-to-host copies of the
  * convergence words.  stats may be NULL.  With strict = 1, returns
  * TDGL_ENOCONV after the first step whose Jacobi solve hit max_iter.

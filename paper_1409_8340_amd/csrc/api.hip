@@ -240,6 +240,7 @@ tdgl_status validate(const tdgl_params &p, int idx) {
             return fail(TDGL_EINVAL,
                         "instance %d: a current along x needs a periodic x axis (open x with driven=1)", idx);
         if (!(p.mu_tol > 0)) return fail(TDGL_EINVAL, "instance %d: mu_tol must be > 0", idx);
+        if (!(p.mu_rtol >= 0 && p.mu_rtol < 1)) return fail(TDGL_EINVAL, "instance %d: mu_rtol must be in [0, 1)", idx);
         if (p.mu_max_cycles < 1 || p.mu_max_cycles > TDGL_MAX_CYCLES)
             return fail(TDGL_EINVAL, "instance %d: mu_max_cycles must be in [1, %d]", idx, TDGL_MAX_CYCLES);
         Hierarchy H = build_hierarchy(p);
@@ -257,9 +258,11 @@ tdgl_status validate(const tdgl_params &p, int idx) {
 
 int auto_chunk(long tiles_xy, int nz, int req) {
     if (req > 0) return std::min(req, nz);
-    // enough work-groups to fill 256 CUs several times, long enough z runs
-    long c = (long)nz * tiles_xy / 4096;
-    c = std::max(1L, std::min(32L, c));
+    // about 1024 or more work-groups (four per CU) where the grid allows,
+    // and z runs of at least two planes so the two halo planes a run
+    // re-reads stay a bounded overhead
+    long c = (long)nz * tiles_xy / 1024;
+    c = std::max(2L, std::min(32L, c));
     return (int)std::min<long>(c, nz);
 }
 
@@ -302,6 +305,16 @@ struct tdgl_ctx {
     int *d_np_st = nullptr, *d_np_flat = nullptr, *d_np_mg0 = nullptr;
     unsigned *d_res = nullptr, *d_mures = nullptr;
     unsigned *h_res = nullptr, *h_mures = nullptr;  // pinned
+    int npad = 64;                                  // instance stride of a convergence row
+    size_t row_words() const { return (size_t)NSLOT * npad; }
+    // max over the slots of one polled row for one instance
+    float host_row_max(const unsigned *rows, int row, int inst) const {
+        unsigned m = 0;
+        for (int s = 0; s < NSLOT; ++s) m = std::max(m, rows[((size_t)row * NSLOT + s) * npad + inst]);
+        float f;
+        memcpy(&f, &m, 4);
+        return f;
+    }
     std::vector<hipEvent_t> ev, evc;
     int tot_st = 0, tot_flat = 0, tot_mg[kMaxLevels] = {0}, tot_mid[kMaxLevels] = {0};
     int nlev_max = 0;
@@ -337,8 +350,9 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
     int *np_st = cv.take<int>(n);
     int *np_flat = cv.take<int>(n);
     int *np_mg0 = cv.take<int>(n);
-    unsigned *res = cv.take<unsigned>((size_t)max_iter * n);
-    unsigned *mures = cv.take<unsigned>((size_t)max_cycles * n);
+    const int npad = (n + 63) / 64 * 64;
+    unsigned *res = cv.take<unsigned>((size_t)max_iter * NSLOT * npad);
+    unsigned *mures = cv.take<unsigned>((size_t)max_cycles * NSLOT * npad);
     for (int i = 0; i < n; ++i) {
         const tdgl_params &p = params[i];
         InstHost &h = ih[i];
@@ -379,7 +393,8 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
         d.st = cv.take<DevState>(1);
         d.res = res ? res + i : nullptr;
         d.mures = mures ? mures + i : nullptr;
-        d.rstride = n;
+        d.rstride = npad;
+        d.mu_rtol = (float)p.mu_rtol;
         d.max_iter = p.max_iter;
         d.mu_max_cycles = p.driven ? p.mu_max_cycles : 1;
         // stencil tiling
@@ -458,6 +473,7 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
         ctx->d_np_mg0 = np_mg0;
         ctx->d_res = res;
         ctx->d_mures = mures;
+        ctx->npad = npad;
         ctx->max_iter = max_iter;
         ctx->max_cycles = max_cycles;
     }
@@ -662,8 +678,9 @@ tdgl_status tdgl_create(int n, const tdgl_params *params, void *ws, size_t ws_by
         c->nlev_max = std::max(c->nlev_max, h.d.nlev);
     }
     auto bail = [&](tdgl_status st) { tdgl_destroy(c); return st; };
-    if (hipHostMalloc((void **)&c->h_res, (size_t)c->max_iter * n * 4, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&c->h_mures, (size_t)c->max_cycles * n * 4, hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc((void **)&c->h_res, c->max_iter * c->row_words() * 4, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_mures, c->max_cycles * c->row_words() * 4, hipHostMallocDefault) !=
+            hipSuccess)
         return bail(fail(TDGL_EDEVICE, "hipHostMalloc of the polling buffers failed"));
     c->ev.resize(c->max_iter);
     c->evc.resize(c->max_cycles);
@@ -693,8 +710,9 @@ tdgl_status tdgl_create(int n, const tdgl_params *params, void *ws, size_t ws_by
         HIPCHK(hipMemsetAsync(d.st, 0, sizeof(DevState), st));
         hipLaunchKernelGGL(k_state_set, dim3(1), dim3(1), 0, st, c->d_inst, i, 11, 1.0);  // in window
     }
-    hipLaunchKernelGGL(k_fill_u, dim3(1), dim3(256), 0, st, c->d_res, (long)c->max_iter * n, 0u);
-    hipLaunchKernelGGL(k_fill_u, dim3(1), dim3(256), 0, st, c->d_mures, (long)c->max_cycles * n, 0u);
+    hipLaunchKernelGGL(k_fill_u, dim3(64), dim3(256), 0, st, c->d_res, (long)(c->max_iter * c->row_words()), 0u);
+    hipLaunchKernelGGL(k_fill_u, dim3(64), dim3(256), 0, st, c->d_mures, (long)(c->max_cycles * c->row_words()),
+                       0u);
     hipLaunchKernelGGL(k_links, dim3(n), dim3(256), 0, st, c->d_inst, 0);
     LAUNCHCHK();
     if (hipStreamSynchronize(st) != hipSuccess) return bail(fail(TDGL_EDEVICE, "initialisation failed"));
@@ -929,7 +947,8 @@ tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats) {
                                ctx->d_pref_st, n, 0);
         }
         LAUNCHCHK();
-        HIPCHK(hipMemcpyAsync(ctx->h_res, ctx->d_res, n * 4, hipMemcpyDeviceToHost, s));
+        const size_t RW = ctx->row_words();
+        HIPCHK(hipMemcpyAsync(ctx->h_res, ctx->d_res, RW * 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipEventRecord(ctx->ev[0], s));
         std::fill(conv_at.begin(), conv_at.end(), -1);
         int remaining = n, launched = 1, polled = 0;
@@ -940,8 +959,7 @@ tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats) {
                 for (int i = 0; i < n; ++i) {
                     if (conv_at[i] >= 0) continue;
                     const InstHost &h = ctx->inst[i];
-                    float r;
-                    memcpy(&r, &ctx->h_res[(size_t)polled * n + i], 4);
+                    const float r = ctx->host_row_max(ctx->h_res, polled, i);
                     if (r < (float)h.p.tol || polled + 1 >= h.p.max_iter) {
                         conv_at[i] = polled;
                         --remaining;
@@ -957,7 +975,7 @@ tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats) {
                                    ctx->d_pref_st, n, l);
             }
             LAUNCHCHK();
-            HIPCHK(hipMemcpyAsync(ctx->h_res + (size_t)l * n, ctx->d_res + (size_t)l * n, n * 4,
+            HIPCHK(hipMemcpyAsync(ctx->h_res + (size_t)l * RW, ctx->d_res + (size_t)l * RW, RW * 4,
                                   hipMemcpyDeviceToHost, s));
             HIPCHK(hipEventRecord(ctx->ev[l], s));
             ++launched;
@@ -969,8 +987,7 @@ tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats) {
         LAUNCHCHK();
         for (int i = 0; i < n; ++i) {
             const InstHost &h = ctx->inst[i];
-            float r;
-            memcpy(&r, &ctx->h_res[(size_t)conv_at[i] * n + i], 4);
+            const float r = ctx->host_row_max(ctx->h_res, conv_at[i], i);
             const bool capped = !(r < (float)h.p.tol);
             const int sw = capped ? h.p.max_iter : conv_at[i] + 1;
             acc.sweeps_min = std::min(acc.sweeps_min, sw);
@@ -1011,9 +1028,10 @@ tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats) {
                     for (int i = 0; i < n; ++i) {
                         if (mconv_at[i] >= 0) continue;
                         const InstHost &h = ctx->inst[i];
-                        float r;
-                        memcpy(&r, &ctx->h_mures[(size_t)mpolled * n + i], 4);
-                        if (r < (float)h.p.mu_tol || mpolled + 1 >= h.p.mu_max_cycles) {
+                        const float r = ctx->host_row_max(ctx->h_mures, mpolled, i);
+                        const float thr = std::max((float)h.p.mu_tol,
+                                                   (float)h.p.mu_rtol * ctx->host_row_max(ctx->h_mures, 0, i));
+                        if (r < thr || mpolled + 1 >= h.p.mu_max_cycles) {
                             mconv_at[i] = mpolled;
                             --mrem;
                         }
@@ -1023,8 +1041,8 @@ tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats) {
                 if (mrem == 0 || mlaunched == ctx->max_cycles) break;
                 tdgl_status e = enqueue_vcycle(ctx, mlaunched);
                 if (e) return e;
-                HIPCHK(hipMemcpyAsync(ctx->h_mures + (size_t)mlaunched * n, ctx->d_mures + (size_t)mlaunched * n,
-                                      n * 4, hipMemcpyDeviceToHost, s));
+                HIPCHK(hipMemcpyAsync(ctx->h_mures + (size_t)mlaunched * RW, ctx->d_mures + (size_t)mlaunched * RW,
+                                      RW * 4, hipMemcpyDeviceToHost, s));
                 HIPCHK(hipEventRecord(ctx->evc[mlaunched], s));
                 ++mlaunched;
             }
@@ -1040,9 +1058,10 @@ tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats) {
             for (int i = 0; i < n; ++i) {
                 const InstHost &h = ctx->inst[i];
                 if (!h.p.driven) continue;
-                float r;
-                memcpy(&r, &ctx->h_mures[(size_t)mconv_at[i] * n + i], 4);
-                const bool capped = !(r < (float)h.p.mu_tol);
+                const float r = ctx->host_row_max(ctx->h_mures, mconv_at[i], i);
+                const float thr = std::max((float)h.p.mu_tol,
+                                           (float)h.p.mu_rtol * ctx->host_row_max(ctx->h_mures, 0, i));
+                const bool capped = !(r < thr);
                 acc.mu_cycles_sum += capped ? h.p.mu_max_cycles : mconv_at[i];
                 if (capped) acc.mu_capped_steps++;
                 acc.mu_last_res = r;

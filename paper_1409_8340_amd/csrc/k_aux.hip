@@ -49,8 +49,10 @@ __global__ void k_solve_finalize(const Inst *__restrict__ insts, int ninst) {
     const Inst &I = insts[ii];
     DevState *st = I.st;
     int sweeps = I.max_iter, capped = 1;
+    float last = 0.f;
     for (int l = 0; l < I.max_iter; ++l) {
-        if (__uint_as_float(I.res[l * I.rstride]) < I.tol) { sweeps = l + 1; capped = 0; break; }
+        last = row_max(I.res, I.rstride, l);
+        if (last < I.tol) { sweeps = l + 1; capped = 0; break; }
     }
     st->sweeps = sweeps;
     st->capped = capped;
@@ -58,8 +60,8 @@ __global__ void k_solve_finalize(const Inst *__restrict__ insts, int ninst) {
     st->t += I.dt;
     st->n += 1.0;
     // keep the last tested residual, then clear the words for the next step
-    st->last_res2 = __uint_as_float(I.res[(sweeps - 1) * I.rstride]);
-    for (int l = 0; l < I.max_iter; ++l) I.res[l * I.rstride] = 0u;
+    st->last_res2 = last;
+    for (int l = 0; l < I.max_iter; ++l) row_clear(I.res, I.rstride, l);
 }
 
 // Partial sums of Im[psi_m^* U_x(j) psi_{m+x}] (periodic x) for J_av

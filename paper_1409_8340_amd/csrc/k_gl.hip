@@ -101,7 +101,7 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
         // instance's cap is reached): its solve is complete and the launch
         // is a no-op for it.
         if (l >= I.max_iter) return;
-        const float prev = __uint_as_float(I.res[(l - 1) * I.rstride]);
+        const float prev = row_max(I.res, I.rstride, l - 1);
         if (prev < I.tol) return;
     }
     if ((MODE == MODE_RHS) && !I.driven) return;
@@ -278,7 +278,7 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
 
     if (MODE == MODE_FIRST || MODE == MODE_SWEEP) {
         __syncthreads();
-        wg_max_to<WG>(&I.res[l * I.rstride], rmax, reinterpret_cast<float *>(red));
+        wg_max_to<WG>(row_slot(I.res, I.rstride, l, b), rmax, reinterpret_cast<float *>(red));
     } else {
         const double s = wg_sum<WG>(acc, red);
         if (threadIdx.x == 0) I.part[b - prefix[ii]] = s;

@@ -48,12 +48,15 @@ __device__ __forceinline__ int wrapi(int i, int n, int per) {
     return i;
 }
 
-// Poisson residual words: the solve of this step ended at cycle c (or an
-// earlier one) when mures[c] < mu_tol.  mures[c] is written by the finest
-// residual of cycle c.
+// Poisson residual rows: the solve of this step ended at cycle c (or an
+// earlier one) when row c is below max(mu_tol, mu_rtol * row 0).  Row c is
+// written by the finest residual of cycle c.
+__device__ __forceinline__ float mg_threshold(const Inst &I) {
+    return fmaxf(I.mu_tol, I.mu_rtol * row_max(I.mures, I.rstride, 0));
+}
 __device__ __forceinline__ bool mg_done(const Inst &I, int c) {
     if (c >= I.mu_max_cycles) return true;
-    return __uint_as_float(I.mures[c * I.rstride]) < I.mu_tol;
+    return row_max(I.mures, I.rstride, c) < mg_threshold(I);
 }
 
 // Shared column context: coefficient values of the column and its x/y
@@ -161,7 +164,7 @@ __global__ __launch_bounds__(256) void k_mg_residual(const Inst *__restrict__ in
             mc = mnext;
         }
     }
-    if (lv == 0) wg_max_to<256>(&I.mures[cyc * I.rstride], rmax, red);
+    if (lv == 0) wg_max_to<256>(row_slot(I.mures, I.rstride, cyc, blockIdx.x), rmax, red);
 }
 
 // Restriction of the residual of level lv to the right side of level lv+1
@@ -353,15 +356,16 @@ __global__ void k_mg_finalize(const Inst *__restrict__ insts, int ninst) {
     if (!I.driven) return;
     DevState *st = I.st;
     int cycles = I.mu_max_cycles, capped = 1;
-    float last = __uint_as_float(I.mures[(I.mu_max_cycles - 1) * I.rstride]);
+    const float thr = mg_threshold(I);
+    float last = row_max(I.mures, I.rstride, I.mu_max_cycles - 1);
     for (int c = 0; c < I.mu_max_cycles; ++c) {
-        const float r = __uint_as_float(I.mures[c * I.rstride]);
-        if (r < I.mu_tol) { cycles = c; capped = 0; last = r; break; }
+        const float r = row_max(I.mures, I.rstride, c);
+        if (r < thr) { cycles = c; capped = 0; last = r; break; }
     }
     st->mu_cycles = cycles;
     st->mu_capped = capped;
     st->mu_last_res = last;
-    for (int c = 0; c < I.mu_max_cycles; ++c) I.mures[c * I.rstride] = 0u;
+    for (int c = 0; c < I.mu_max_cycles; ++c) row_clear(I.mures, I.rstride, c);
 }
 
 // Partial sums of V mu on level 0 for its weighted mean.

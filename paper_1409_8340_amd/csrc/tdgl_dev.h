@@ -14,6 +14,7 @@ namespace tdgl {
 constexpr int kMaxIter = 256;    // Jacobi sweeps per step (cap)
 constexpr int kMaxCycles = 64;   // multigrid cycles per step (cap)
 constexpr int kMaxLevels = 16;   // multigrid levels
+constexpr int NSLOT = 32;        // atomic slots per convergence row
 
 // Tile of the 2.5D stencil kernels: 64 x-columns (one wavefront wide) by
 // 16 y-rows; 256 threads, each owning 4 consecutive rows of one column, march
@@ -98,12 +99,16 @@ struct Inst {
     float2 *uz;          // z links per y index: exp(-i hz Bx ybar_j)
     float2 *P;           // y wrap phase per (i,k): exp(i (i hx Ly Bz - k hz Ly Bx))
     DevState *st;
-    // Convergence words, strided over the instances of a context so that one
-    // small copy polls a whole batch: sweep l of this instance uses
-    // res[l * rstride], multigrid cycle c uses mures[c * rstride].
-    unsigned *res;       // max |r|^2 of the input iterate of sweep l (float bits)
-    unsigned *mures;     // Poisson residual max-norm at the top of cycle c
+    // Convergence words.  Work-groups reduce their maxima with atomics into
+    // one of NSLOT slots (chosen by block index) placed in separate cache
+    // lines, so that thousands of groups do not serialise on one address;
+    // readers take the max over the slots.  Word (row l, slot s) of this
+    // instance is res[(l * NSLOT + s) * rstride]; the instances of a context
+    // are interleaved (rstride >= instance count) so one copy polls a batch.
+    unsigned *res;       // row l: max |r|^2 of the input iterate of sweep l (float bits)
+    unsigned *mures;     // row c: Poisson residual max-norm at the top of cycle c
     int rstride;
+    float mu_rtol;       // Poisson stop relative to the residual at the top of cycle 0
     int max_iter, mu_max_cycles;
     double *part;        // per-work-group partial sums
     int part_cap;
@@ -147,6 +152,23 @@ __device__ __forceinline__ int find_inst(const int *__restrict__ prefix, int nin
         if (prefix[mid] <= b) lo = mid; else hi = mid - 1;
     }
     return lo;
+}
+
+// Convergence rows: slot word for an atomic update and the row maximum.
+__device__ __forceinline__ unsigned *row_slot(unsigned *base, int rstride, int row, int block) {
+    return base + ((size_t)row * NSLOT + (block & (NSLOT - 1))) * rstride;
+}
+__device__ __forceinline__ float row_max(const unsigned *base, int rstride, int row) {
+    unsigned m = 0;
+#pragma unroll 8
+    for (int s = 0; s < NSLOT; ++s) {
+        const unsigned w = base[((size_t)row * NSLOT + s) * rstride];
+        m = w > m ? w : m;
+    }
+    return __uint_as_float(m);
+}
+__device__ __forceinline__ void row_clear(unsigned *base, int rstride, int row) {
+    for (int s = 0; s < NSLOT; ++s) base[((size_t)row * NSLOT + s) * rstride] = 0u;
 }
 
 // Node weight: 1/2 per open face the node lies on (trapezoid rule).

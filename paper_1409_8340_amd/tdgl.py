@@ -32,7 +32,7 @@ class Params(ctypes.Structure):
                 ("hx", ctypes.c_double), ("hy", ctypes.c_double), ("hz", ctypes.c_double),
                 ("bc", ctypes.c_int * 3), ("g", ctypes.c_double), ("u", ctypes.c_double),
                 ("dt", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
-                ("driven", ctypes.c_int), ("mu_tol", ctypes.c_double),
+                ("driven", ctypes.c_int), ("mu_tol", ctypes.c_double), ("mu_rtol", ctypes.c_double),
                 ("mu_max_cycles", ctypes.c_int), ("strict", ctypes.c_int),
                 ("tile_cz", ctypes.c_int), ("reserved", ctypes.c_int * 7)]
 
@@ -143,7 +143,7 @@ def _check(status):
 
 def make_params(nx, ny, nz, h=0.5, hx=None, hy=None, hz=None, bc=(TDGL_PERIODIC, TDGL_PERIODIC, TDGL_OPEN),
                 g=1.0, u=1.0, dt=0.1, tol=1e-8, max_iter=100, driven=False, mu_tol=1e-5,
-                mu_max_cycles=20, strict=False, tile_cz=0) -> Params:
+                mu_rtol=0.0, mu_max_cycles=20, strict=False, tile_cz=0) -> Params:
     p = Params()
     p.nx, p.ny, p.nz = nx, ny, nz
     p.hx = h if hx is None else hx
@@ -155,6 +155,7 @@ def make_params(nx, ny, nz, h=0.5, hx=None, hy=None, hz=None, bc=(TDGL_PERIODIC,
     p.max_iter = max_iter
     p.driven = int(bool(driven))
     p.mu_tol = mu_tol
+    p.mu_rtol = mu_rtol
     p.mu_max_cycles = mu_max_cycles
     p.strict = int(bool(strict))
     p.tile_cz = tile_cz
