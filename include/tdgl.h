@@ -74,7 +74,12 @@ typedef struct tdgl_params {
     int mu_max_cycles;    /* multigrid cycle cap per step (1..TDGL_MAX_CYCLES) */
     int strict;           /* 1: tdgl_step returns TDGL_ENOCONV on a capped solve */
     int tile_cz;          /* z planes per stencil work-group; 0 = library default */
-    int reserved[7];      /* must be zero */
+    int tile_rows;        /* y rows per stencil thread: 0 (default 4), 2 or 4;
+                             every instance of a context must agree */
+    int poisson;          /* 0: direct spectral solve where the box allows it
+                             (periodic x and y, open z, sizes with factors 2,3,5),
+                             multigrid otherwise; 1: always multigrid */
+    int reserved[5];      /* must be zero */
 } tdgl_params;
 
 /* Per-call statistics of tdgl_step (filled only when a pointer is given;
@@ -220,13 +225,22 @@ tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats);
  * Synchronising. */
 tdgl_status tdgl_observables(tdgl_ctx *ctx, int inst, tdgl_obs *obs);
 
+/* Solves the Poisson equation of Sec. 3.2, Delta_h mu = f (7-point stencil,
+ * plain wrap on periodic axes, Neumann reflection on open faces), for a
+ * given right side with the instance's solver (spectral or multigrid, as
+ * for a step) and returns mu with zero weighted mean.  f and mu are
+ * float[N] device arrays; the weighted mean of f is projected out first.
+ * The context must hold exactly one driven instance.  Overwrites the
+ * instance's stored mu~ (the next step starts from this solution). */
+tdgl_status tdgl_poisson_solve(tdgl_ctx *ctx, const float *f, float *mu);
+
 /* Kernel classes of the per-kernel profile (the time profile of one step,
  * kernel by kernel, as in the paper's performance section, Sec. 4.3). */
 #define TDGL_K_ASSEMBLE 0   /* assemble b, M_mm fused with the first Jacobi iteration */
 #define TDGL_K_SWEEP 1      /* one Jacobi iteration (all later sweeps)              */
 #define TDGL_K_CURRENT 2    /* J_av partial sums and the K update                   */
 #define TDGL_K_RHS 3        /* Poisson right side and its weighted mean              */
-#define TDGL_K_MG_FINE 4    /* multigrid work on the finest level                   */
+#define TDGL_K_MG_FINE 4    /* Poisson solve on the full grid (FFT passes, or multigrid finest level) */
 #define TDGL_K_MG_COARSE 5  /* multigrid work on coarser levels (incl. transfers)   */
 #define TDGL_K_OTHER 6      /* solve bookkeeping and the mu~ mean                   */
 #define TDGL_K_COUNT 7

@@ -217,6 +217,27 @@ Hierarchy build_hierarchy(const tdgl_params &p) {
     return H;
 }
 
+// Radix plan of an FFT length (radices 4, 2, 3, 5); false if n has another
+// prime factor.
+bool radix_plan(int n, int *rad, int *nrad) {
+    int k = 0;
+    while (n % 4 == 0 && k < 16) { rad[k++] = 4; n /= 4; }
+    while (n % 2 == 0 && k < 16) { rad[k++] = 2; n /= 2; }
+    while (n % 3 == 0 && k < 16) { rad[k++] = 3; n /= 3; }
+    while (n % 5 == 0 && k < 16) { rad[k++] = 5; n /= 5; }
+    *nrad = k;
+    return n == 1;
+}
+
+// The direct spectral Poisson solve applies to periodic x and y, open z,
+// FFT-friendly x and y sizes and nz within the z-solve's tile.
+bool fft_eligible(const tdgl_params &p) {
+    int r[16], k;
+    return p.driven && p.poisson == 0 && p.bc[0] == TDGL_PERIODIC && p.bc[1] == TDGL_PERIODIC &&
+           p.bc[2] == TDGL_OPEN && p.nz <= FFT_ZMAX && p.nx <= FFT_MAXN / 2 && p.ny <= FFT_MAXN &&
+           radix_plan(p.nx, r, &k) && radix_plan(p.ny, r, &k);
+}
+
 // ---------------------------------------------------------------------------
 // validation and layout
 tdgl_status validate(const tdgl_params &p, int idx) {
@@ -243,15 +264,19 @@ tdgl_status validate(const tdgl_params &p, int idx) {
         if (!(p.mu_rtol >= 0 && p.mu_rtol < 1)) return fail(TDGL_EINVAL, "instance %d: mu_rtol must be in [0, 1)", idx);
         if (p.mu_max_cycles < 1 || p.mu_max_cycles > TDGL_MAX_CYCLES)
             return fail(TDGL_EINVAL, "instance %d: mu_max_cycles must be in [1, %d]", idx, TDGL_MAX_CYCLES);
+        if (p.poisson != 0 && p.poisson != 1)
+            return fail(TDGL_EINVAL, "instance %d: poisson must be 0 (auto) or 1 (multigrid)", idx);
         Hierarchy H = build_hierarchy(p);
-        if (!H.ok)
+        if (!fft_eligible(p) && !H.ok)
             return fail(TDGL_EINVAL,
                         "instance %d: the grid cannot be coarsened below %d nodes for the Poisson "
                         "multigrid (periodic axes need even sizes)", idx, kCoarsestMax);
     }
     if (p.tile_cz < 0 || p.tile_cz > 1024) return fail(TDGL_EINVAL, "instance %d: tile_cz out of range", idx);
+    if (p.tile_rows != 0 && p.tile_rows != 2 && p.tile_rows != 4)
+        return fail(TDGL_EINVAL, "instance %d: tile_rows must be 0, 2 or 4", idx);
     if (p.strict != 0 && p.strict != 1) return fail(TDGL_EINVAL, "instance %d: strict must be 0 or 1", idx);
-    for (int r = 0; r < 7; ++r)
+    for (size_t r = 0; r < sizeof(p.reserved) / sizeof(p.reserved[0]); ++r)
         if (p.reserved[r] != 0) return fail(TDGL_EINVAL, "instance %d: reserved fields must be zero", idx);
     return TDGL_OK;
 }
@@ -264,6 +289,14 @@ int auto_chunk(long tiles_xy, int nz, int req) {
     long c = (long)nz * tiles_xy / 1024;
     c = std::max(2L, std::min(32L, c));
     return (int)std::min<long>(c, nz);
+}
+
+// Rows per thread of the stencil tiles, shared by every instance of a
+// context (one launch covers them all): the first non-zero request, else 4.
+int ctx_rows(int n, const tdgl_params *params) {
+    for (int i = 0; i < n; ++i)
+        if (params[i].tile_rows) return params[i].tile_rows;
+    return 4;
 }
 
 // Carves one context's workspace.  With base == nullptr only sizes are
@@ -285,6 +318,7 @@ struct InstHost {
     Hierarchy H;
     int st_blocks = 0, flat_blocks = 0;
     int mg_blocks[kMaxLevels] = {0};
+    int fx_blocks = 0, fy_blocks = 0, fz_blocks = 0;  // spectral Poisson passes
     double Bx = 0, Bz = 0, J = 0;
 };
 
@@ -318,8 +352,14 @@ struct tdgl_ctx {
     std::vector<hipEvent_t> ev, evc;
     int tot_st = 0, tot_flat = 0, tot_mg[kMaxLevels] = {0}, tot_mid[kMaxLevels] = {0};
     int nlev_max = 0;
+    // spectral Poisson path: prefix tables of its three kernels and LDS sizes
+    int *d_pref_fx = nullptr, *d_pref_fy = nullptr, *d_pref_fz = nullptr;
+    int tot_fx = 0, tot_fy = 0, tot_fz = 0;
+    size_t fx_lds = 0, fy_lds = 0;
+    bool any_fft = false, any_mg = false;
     bool any_driven = false;
     int max_iter = 1, max_cycles = 1;
+    int rows = 4;  // stencil rows per thread
     // per-kernel-class timing (tdgl_profile_start/stop)
     unsigned prof_mask = 0;
     std::vector<hipEvent_t> prof_pool;
@@ -347,6 +387,9 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
     int *pref_flat = cv.take<int>(n + 1);
     int *pref_mg = cv.take<int>((size_t)kMaxLevels * (n + 1));
     int *pref_mid = cv.take<int>((size_t)kMaxLevels * (n + 1));
+    int *pref_fx = cv.take<int>(n + 1);
+    int *pref_fy = cv.take<int>(n + 1);
+    int *pref_fz = cv.take<int>(n + 1);
     int *np_st = cv.take<int>(n);
     int *np_flat = cv.take<int>(n);
     int *np_mg0 = cv.take<int>(n);
@@ -398,9 +441,11 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
         d.max_iter = p.max_iter;
         d.mu_max_cycles = p.driven ? p.mu_max_cycles : 1;
         // stencil tiling
-        const long txy = (long)cdiv(p.nx, TX) * cdiv(p.ny, TY);
+        const int rows = ctx_rows(n, params);
+        d.rows = rows;
+        const long txy = (long)cdiv(p.nx, TX) * cdiv(p.ny, 4 * rows);
         d.tiles_x = cdiv(p.nx, TX);
-        d.tiles_y = cdiv(p.ny, TY);
+        d.tiles_y = cdiv(p.ny, 4 * rows);
         d.chunk = auto_chunk(txy, p.nz, p.tile_cz);
         d.tiles_z = cdiv(p.nz, d.chunk);
         h.st_blocks = (int)(txy * d.tiles_z);
@@ -409,6 +454,7 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
         // multigrid
         if (p.driven) {
             h.H = build_hierarchy(p);
+            if (fft_eligible(p)) h.H.lev.resize(1);  // level 0 arrays only
             d.nlev = (int)h.H.lev.size();
             for (int l = 0; l < d.nlev; ++l) {
                 LevelHost &LH = h.H.lev[l];
@@ -456,6 +502,16 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
             }
             d.mu = d.lev[0].mu[0];
             d.f = d.lev[0].rhs;
+            if (fft_eligible(p)) {
+                d.fft = 1;
+                radix_plan(p.nx, d.xrad, &d.nxrad);
+                radix_plan(p.ny, d.yrad, &d.nyrad);
+                const int P = p.nx / 2 + 1;
+                d.spec = cv.take<float2>((size_t)p.nz * p.ny * P);
+                h.fx_blocks = cdiv((long)p.ny * p.nz, 2L * fft_x_pairs(p.nx));
+                h.fy_blocks = p.nz * cdiv(P, fft_y_cols(p.ny));
+                h.fz_blocks = p.ny * cdiv(P, FFT_ZTK);
+            }
             part_cap = std::max(part_cap, h.mg_blocks[0]);
         }
         d.part = cv.take<double>(part_cap);
@@ -468,12 +524,16 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
         ctx->d_pref_flat = pref_flat;
         ctx->d_pref_mg = pref_mg;
         ctx->d_pref_mid = pref_mid;
+        ctx->d_pref_fx = pref_fx;
+        ctx->d_pref_fy = pref_fy;
+        ctx->d_pref_fz = pref_fz;
         ctx->d_np_st = np_st;
         ctx->d_np_flat = np_flat;
         ctx->d_np_mg0 = np_mg0;
         ctx->d_res = res;
         ctx->d_mures = mures;
         ctx->npad = npad;
+        ctx->rows = ctx_rows(n, params);
         ctx->max_iter = max_iter;
         ctx->max_cycles = max_cycles;
     }
@@ -515,7 +575,7 @@ tdgl_status upload_tables(tdgl_ctx *ctx) {
     // prefix tables
     const int n = ctx->n;
     std::vector<int> ps(n + 1, 0), pf(n + 1, 0), pm((size_t)kMaxLevels * (n + 1), 0),
-        pmid((size_t)kMaxLevels * (n + 1), 0);
+        pmid((size_t)kMaxLevels * (n + 1), 0), pfx(n + 1, 0), pfy(n + 1, 0), pfz(n + 1, 0);
     std::vector<int> nps(n), npf(n), npm(n);
     for (int i = 0; i < n; ++i) {
         InstHost &h = ctx->inst[i];
@@ -524,12 +584,24 @@ tdgl_status upload_tables(tdgl_ctx *ctx) {
         nps[i] = h.st_blocks;
         npf[i] = h.flat_blocks;
         npm[i] = h.p.driven ? h.mg_blocks[0] : 0;
+        const bool mg = h.p.driven && !h.d.fft;
         for (int l = 0; l < kMaxLevels; ++l) {
             const size_t o = (size_t)l * (n + 1) + i;
-            const int b = (h.p.driven && l < h.d.nlev) ? h.mg_blocks[l] : 0;
-            const int bm = (h.p.driven && l + 1 < h.d.nlev) ? h.mg_blocks[l] : 0;
+            // level 0 "all" also drives the mean of mu for every driven instance
+            const int b = (h.p.driven && l < h.d.nlev && (mg || l == 0)) ? h.mg_blocks[l] : 0;
+            const int bm = (mg && l + 1 < h.d.nlev) ? h.mg_blocks[l] : 0;
             pm[o + 1] = pm[o] + b;
             pmid[o + 1] = pmid[o] + bm;
+        }
+        pfx[i + 1] = pfx[i] + h.fx_blocks;
+        pfy[i + 1] = pfy[i] + h.fy_blocks;
+        pfz[i + 1] = pfz[i] + h.fz_blocks;
+        if (h.d.fft) {
+            ctx->any_fft = true;
+            ctx->fx_lds = std::max(ctx->fx_lds, (size_t)fft_x_pairs(h.p.nx) * h.p.nx * 8);
+            ctx->fy_lds = std::max(ctx->fy_lds, (size_t)fft_y_cols(h.p.ny) * h.p.ny * 8);
+        } else if (h.p.driven) {
+            ctx->any_mg = true;
         }
     }
     ctx->tot_st = ps[n];
@@ -539,6 +611,18 @@ tdgl_status upload_tables(tdgl_ctx *ctx) {
         ctx->tot_mid[l] = pmid[(size_t)l * (n + 1) + n];
     }
     HIPCHK(hipMemcpy(ctx->d_pref_mid, pmid.data(), pmid.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_pref_fx, pfx.data(), (n + 1) * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_pref_fy, pfy.data(), (n + 1) * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_pref_fz, pfz.data(), (n + 1) * 4, hipMemcpyHostToDevice));
+    ctx->tot_fx = pfx[n];
+    ctx->tot_fy = pfy[n];
+    ctx->tot_fz = pfz[n];
+    if (ctx->any_fft) {
+        HIPCHK(hipFuncSetAttribute((const void *)k_fft_x, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)ctx->fx_lds));
+        HIPCHK(hipFuncSetAttribute((const void *)k_fft_y, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)ctx->fy_lds));
+    }
     HIPCHK(hipMemcpy(ctx->d_pref_st, ps.data(), (n + 1) * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_pref_flat, pf.data(), (n + 1) * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_pref_mg, pm.data(), pm.size() * 4, hipMemcpyHostToDevice));
@@ -589,6 +673,17 @@ struct ProfScope {
     }
 };
 
+// Launch one stencil pass over every instance with the context's tile.
+template <int MODE>
+void launch_stencil(tdgl_ctx *c, int l) {
+    if (c->rows == 2)
+        hipLaunchKernelGGL((k_stencil<MODE, 2>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst, c->d_pref_st,
+                           c->n, l);
+    else
+        hipLaunchKernelGGL((k_stencil<MODE, 4>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst, c->d_pref_st,
+                           c->n, l);
+}
+
 // One multigrid V-cycle for every driven instance (cycle index cyc).
 // Instances may have hierarchies of different depth: each per-level launch
 // covers only the instances the operation applies to (prefix tables with
@@ -638,6 +733,88 @@ tdgl_status enqueue_vcycle(tdgl_ctx *c, int cyc) {
     return TDGL_OK;
 }
 
+// Solve the Poisson equation of every driven instance: right side I.f,
+// solution into I.mu (level-0 mu[0]), then the weighted mean of mu.  Spectral
+// instances take the five FFT / z-solve passes; multigrid instances take
+// V-cycles until their stop rule, decided on the device and polled by the
+// host one cycle behind.  Statistics are accumulated into acc.
+tdgl_status enqueue_poisson(tdgl_ctx *ctx, tdgl_step_stats *acc) {
+    const int n = ctx->n;
+    hipStream_t s = ctx->stream;
+    const size_t RW = ctx->row_words();
+    if (ctx->any_fft) {
+        ProfScope ps(ctx, TDGL_K_MG_FINE);
+        const float *nf = nullptr;
+        float *nm = nullptr;
+        hipLaunchKernelGGL(k_fft_x, dim3(std::max(ctx->tot_fx, 1)), dim3(256), ctx->fx_lds, s, ctx->d_inst,
+                           ctx->d_pref_fx, n, -1, nf, nm);
+        hipLaunchKernelGGL(k_fft_y, dim3(std::max(ctx->tot_fy, 1)), dim3(256), ctx->fy_lds, s, ctx->d_inst,
+                           ctx->d_pref_fy, n, -1);
+        hipLaunchKernelGGL(k_fft_zsolve, dim3(std::max(ctx->tot_fz, 1)), dim3(256), 0, s, ctx->d_inst,
+                           ctx->d_pref_fz, n);
+        hipLaunchKernelGGL(k_fft_y, dim3(std::max(ctx->tot_fy, 1)), dim3(256), ctx->fy_lds, s, ctx->d_inst,
+                           ctx->d_pref_fy, n, +1);
+        hipLaunchKernelGGL(k_fft_x, dim3(std::max(ctx->tot_fx, 1)), dim3(256), ctx->fx_lds, s, ctx->d_inst,
+                           ctx->d_pref_fx, n, +1, nf, nm);
+        LAUNCHCHK();
+    }
+    std::vector<int> mconv_at(n, 0);
+    if (ctx->any_mg) {
+        int mrem = 0;
+        for (int i = 0; i < n; ++i) {
+            const InstHost &h = ctx->inst[i];
+            if (h.p.driven && !h.d.fft) { ++mrem; mconv_at[i] = -1; }
+        }
+        int mlaunched = 0, mpolled = 0;
+        for (;;) {
+            while (mrem > 0 && (mpolled < mlaunched - 1 || mlaunched == ctx->max_cycles) && mpolled < mlaunched) {
+                HIPCHK(hipEventSynchronize(ctx->evc[mpolled]));
+                for (int i = 0; i < n; ++i) {
+                    if (mconv_at[i] >= 0) continue;
+                    const InstHost &h = ctx->inst[i];
+                    const float r = ctx->host_row_max(ctx->h_mures, mpolled, i);
+                    const float thr = std::max((float)h.p.mu_tol,
+                                               (float)h.p.mu_rtol * ctx->host_row_max(ctx->h_mures, 0, i));
+                    if (r < thr || mpolled + 1 >= h.p.mu_max_cycles) {
+                        mconv_at[i] = mpolled;
+                        --mrem;
+                    }
+                }
+                ++mpolled;
+            }
+            if (mrem == 0 || mlaunched == ctx->max_cycles) break;
+            tdgl_status e = enqueue_vcycle(ctx, mlaunched);
+            if (e) return e;
+            HIPCHK(hipMemcpyAsync(ctx->h_mures + (size_t)mlaunched * RW, ctx->d_mures + (size_t)mlaunched * RW,
+                                  RW * 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipEventRecord(ctx->evc[mlaunched], s));
+            ++mlaunched;
+        }
+    }
+    {
+        ProfScope ps(ctx, TDGL_K_OTHER);
+        if (ctx->any_mg) hipLaunchKernelGGL(k_mg_finalize, dim3(cdiv(n, 64)), dim3(64), 0, s, ctx->d_inst, n);
+        hipLaunchKernelGGL(k_mu_mean_partial, dim3(std::max(ctx->tot_mg[0], 1)), dim3(256), 0, s, ctx->d_inst,
+                           pref_mg(ctx, 0), n, 0);
+        hipLaunchKernelGGL(k_reduce_to_state, dim3(n), dim3(256), 0, s, ctx->d_inst, ctx->d_np_mg0, 1, 1);
+    }
+    LAUNCHCHK();
+    if (acc && ctx->any_mg) {
+        for (int i = 0; i < n; ++i) {
+            const InstHost &h = ctx->inst[i];
+            if (!h.p.driven || h.d.fft) continue;
+            const float r = ctx->host_row_max(ctx->h_mures, mconv_at[i], i);
+            const float thr = std::max((float)h.p.mu_tol,
+                                       (float)h.p.mu_rtol * ctx->host_row_max(ctx->h_mures, 0, i));
+            const bool capped = !(r < thr);
+            acc->mu_cycles_sum += capped ? h.p.mu_max_cycles : mconv_at[i];
+            if (capped) acc->mu_capped_steps++;
+            acc->mu_last_res = r;
+        }
+    }
+    return TDGL_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -651,6 +828,8 @@ tdgl_status tdgl_plan(int n, const tdgl_params *params, size_t *ws_bytes) {
     for (int i = 0; i < n; ++i) {
         tdgl_status s = validate(params[i], i);
         if (s) return s;
+        if (params[i].tile_rows && params[i].tile_rows != ctx_rows(n, params))
+            return fail(TDGL_EINVAL, "instances of one context must request the same tile_rows");
     }
     *ws_bytes = layout(n, params, nullptr, nullptr);
     return TDGL_OK;
@@ -675,7 +854,7 @@ tdgl_status tdgl_create(int n, const tdgl_params *params, void *ws, size_t ws_by
     c->nlev_max = 0;
     for (auto &h : c->inst) {
         c->any_driven = c->any_driven || h.p.driven;
-        c->nlev_max = std::max(c->nlev_max, h.d.nlev);
+        if (!h.d.fft) c->nlev_max = std::max(c->nlev_max, h.d.nlev);
     }
     auto bail = [&](tdgl_status st) { tdgl_destroy(c); return st; };
     if (hipHostMalloc((void **)&c->h_res, c->max_iter * c->row_words() * 4, hipHostMallocDefault) != hipSuccess ||
@@ -937,14 +1116,13 @@ tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats) {
     tdgl_step_stats acc;
     memset(&acc, 0, sizeof acc);
     acc.sweeps_min = 1 << 30;
-    std::vector<int> conv_at(n), mconv_at(n);
+    std::vector<int> conv_at(n);
     bool strict_fail = false;
     for (int step = 0; step < nsteps; ++step) {
         // ---- Jacobi solve (all instances) --------------------------------
         {
             ProfScope ps(ctx, TDGL_K_ASSEMBLE);
-            hipLaunchKernelGGL(k_stencil<MODE_FIRST>, dim3(ctx->tot_st), dim3(WG), 0, s, ctx->d_inst,
-                               ctx->d_pref_st, n, 0);
+            launch_stencil<MODE_FIRST>(ctx, 0);
         }
         LAUNCHCHK();
         const size_t RW = ctx->row_words();
@@ -971,8 +1149,7 @@ tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats) {
             const int l = launched;
             {
                 ProfScope ps(ctx, TDGL_K_SWEEP);
-                hipLaunchKernelGGL(k_stencil<MODE_SWEEP>, dim3(ctx->tot_st), dim3(WG), 0, s, ctx->d_inst,
-                                   ctx->d_pref_st, n, l);
+                launch_stencil<MODE_SWEEP>(ctx, l);
             }
             LAUNCHCHK();
             HIPCHK(hipMemcpyAsync(ctx->h_res + (size_t)l * RW, ctx->d_res + (size_t)l * RW, RW * 4,
@@ -1009,63 +1186,12 @@ tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats) {
             }
             {
                 ProfScope ps(ctx, TDGL_K_RHS);
-                hipLaunchKernelGGL(k_stencil<MODE_RHS>, dim3(ctx->tot_st), dim3(WG), 0, s, ctx->d_inst,
-                                   ctx->d_pref_st, n, 0);
+                launch_stencil<MODE_RHS>(ctx, 0);
                 hipLaunchKernelGGL(k_reduce_to_state, dim3(n), dim3(256), 0, s, ctx->d_inst, ctx->d_np_st, 0, 1);
             }
             LAUNCHCHK();
-            std::fill(mconv_at.begin(), mconv_at.end(), -1);
-            int mrem = 0;
-            for (int i = 0; i < n; ++i) {
-                if (ctx->inst[i].p.driven) ++mrem;
-                else mconv_at[i] = 0;
-            }
-            int mlaunched = 0, mpolled = 0;
-            for (;;) {
-                while (mrem > 0 && (mpolled < mlaunched - 1 || mlaunched == ctx->max_cycles) &&
-                       mpolled < mlaunched) {
-                    HIPCHK(hipEventSynchronize(ctx->evc[mpolled]));
-                    for (int i = 0; i < n; ++i) {
-                        if (mconv_at[i] >= 0) continue;
-                        const InstHost &h = ctx->inst[i];
-                        const float r = ctx->host_row_max(ctx->h_mures, mpolled, i);
-                        const float thr = std::max((float)h.p.mu_tol,
-                                                   (float)h.p.mu_rtol * ctx->host_row_max(ctx->h_mures, 0, i));
-                        if (r < thr || mpolled + 1 >= h.p.mu_max_cycles) {
-                            mconv_at[i] = mpolled;
-                            --mrem;
-                        }
-                    }
-                    ++mpolled;
-                }
-                if (mrem == 0 || mlaunched == ctx->max_cycles) break;
-                tdgl_status e = enqueue_vcycle(ctx, mlaunched);
-                if (e) return e;
-                HIPCHK(hipMemcpyAsync(ctx->h_mures + (size_t)mlaunched * RW, ctx->d_mures + (size_t)mlaunched * RW,
-                                      RW * 4, hipMemcpyDeviceToHost, s));
-                HIPCHK(hipEventRecord(ctx->evc[mlaunched], s));
-                ++mlaunched;
-            }
-            {
-                ProfScope ps(ctx, TDGL_K_OTHER);
-                hipLaunchKernelGGL(k_mg_finalize, dim3(cdiv(n, 64)), dim3(64), 0, s, ctx->d_inst, n);
-                hipLaunchKernelGGL(k_mu_mean_partial, dim3(std::max(ctx->tot_mg[0], 1)), dim3(256), 0, s,
-                                   ctx->d_inst, pref_mg(ctx, 0), n);
-                hipLaunchKernelGGL(k_reduce_to_state, dim3(n), dim3(256), 0, s, ctx->d_inst, ctx->d_np_mg0, 1,
-                                   1);
-            }
-            LAUNCHCHK();
-            for (int i = 0; i < n; ++i) {
-                const InstHost &h = ctx->inst[i];
-                if (!h.p.driven) continue;
-                const float r = ctx->host_row_max(ctx->h_mures, mconv_at[i], i);
-                const float thr = std::max((float)h.p.mu_tol,
-                                           (float)h.p.mu_rtol * ctx->host_row_max(ctx->h_mures, 0, i));
-                const bool capped = !(r < thr);
-                acc.mu_cycles_sum += capped ? h.p.mu_max_cycles : mconv_at[i];
-                if (capped) acc.mu_capped_steps++;
-                acc.mu_last_res = r;
-            }
+            tdgl_status e = enqueue_poisson(ctx, &acc);
+            if (e) return e;
         }
         acc.steps++;
         if (strict_fail) break;
@@ -1076,6 +1202,26 @@ tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats) {
         *stats = acc;
     }
     if (strict_fail) return fail(TDGL_ENOCONV, "a Jacobi solve reached max_iter without meeting tol");
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_poisson_solve(tdgl_ctx *ctx, const float *f, float *mu) {
+    if (!ctx) return fail(TDGL_EINVAL, "null context");
+    if (ctx->n != 1) return fail(TDGL_EINVAL, "tdgl_poisson_solve needs a context with one instance");
+    if (!f || !mu) return fail(TDGL_EINVAL, "null array");
+    const Inst &d = ctx->inst[0].d;
+    if (!d.driven) return fail(TDGL_ESTATE, "the instance is not driven: it has no Poisson solver");
+    hipStream_t s = ctx->stream;
+    HIPCHK(hipMemcpyAsync(d.f, f, (size_t)d.N * 4, hipMemcpyDeviceToDevice, s));
+    // weighted mean of f for the multigrid right side
+    hipLaunchKernelGGL(k_mu_mean_partial, dim3(std::max(ctx->tot_mg[0], 1)), dim3(256), 0, s, ctx->d_inst,
+                       pref_mg(ctx, 0), 1, 1);
+    hipLaunchKernelGGL(k_reduce_to_state, dim3(1), dim3(256), 0, s, ctx->d_inst, ctx->d_np_mg0, 4, 1);
+    LAUNCHCHK();
+    tdgl_status e = enqueue_poisson(ctx, nullptr);
+    if (e) return e;
+    hipLaunchKernelGGL(k_mu_io, dim3(fill_grid(d.N)), dim3(256), 0, s, ctx->d_inst, 0, mu, 1);
+    LAUNCHCHK();
     return TDGL_OK;
 }
 
@@ -1109,8 +1255,7 @@ tdgl_status tdgl_observables(tdgl_ctx *ctx, int inst, tdgl_obs *obs) {
     if (!obs) return fail(TDGL_EINVAL, "null observables");
     const int n = ctx->n;
     hipStream_t st = ctx->stream;
-    hipLaunchKernelGGL(k_stencil<MODE_ENERGY>, dim3(ctx->tot_st), dim3(WG), 0, st, ctx->d_inst, ctx->d_pref_st,
-                       n, 0);
+    launch_stencil<MODE_ENERGY>(ctx, 0);
     hipLaunchKernelGGL(k_reduce_to_state, dim3(n), dim3(256), 0, st, ctx->d_inst, ctx->d_np_st, 2, 0);
     hipLaunchKernelGGL(k_psi2_partial, dim3(ctx->tot_flat), dim3(256), 0, st, ctx->d_inst, ctx->d_pref_flat, n);
     hipLaunchKernelGGL(k_reduce_to_state, dim3(n), dim3(256), 0, st, ctx->d_inst, ctx->d_np_flat, 3, 0);

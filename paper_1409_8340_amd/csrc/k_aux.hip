@@ -133,7 +133,8 @@ __global__ __launch_bounds__(256) void k_kupdate(const Inst *__restrict__ insts,
 }
 
 // Reduce an instance's partials into a DevState field: dst = scale * sum.
-// field: 0 = f_mean, 1 = mu_mean, 2 = F, 3 = psi2 (mean |psi|^2).
+// field: 0 = f_mean (from node-weighted sums), 1 = mu_mean, 2 = F,
+// 3 = psi2 (mean |psi|^2), 4 = f_mean (from volume-weighted sums).
 __global__ __launch_bounds__(256) void k_reduce_to_state(const Inst *__restrict__ insts,
                                                          const int *__restrict__ nparts, int field,
                                                          int driven_only) {
@@ -145,6 +146,7 @@ __global__ __launch_bounds__(256) void k_reduce_to_state(const Inst *__restrict_
         DevState *st = I.st;
         if (field == 0) st->f_mean = s / I.w_sum;
         else if (field == 1) st->mu_mean = s / I.lev[0].vsum;
+        else if (field == 4) st->f_mean = s / I.lev[0].vsum;
         else if (field == 2) st->F = s * I.hx * I.hy * I.hz;
         else st->psi2 = s / (double)I.N;
     }

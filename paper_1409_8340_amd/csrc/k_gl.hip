@@ -20,45 +20,79 @@
 
 namespace tdgl {
 
-// Value of psi at (gx, gy) of plane k as the 7-point stencil sees it, for
-// gx in [-1, nx] and gy in [-1, ny]: interior nodes are loaded, one-cell
-// ghosts follow the boundary rules of Sec. 3.3 -- plain wrap on a periodic
-// x axis, the quasi-periodic phase jump psi_{i,-1,k} = P_{i,k} psi_{i,ny-1,k}
-// on a periodic y axis, and the Neumann ghost (U^* psi_{-1} = U psi_1) on an
-// open face.  Anything else (corners, beyond a ragged tile) is zero.
-__device__ __forceinline__ float2 psi_at(const Inst &I, const float2 *__restrict__ src,
-                                         int gx, int gy, int k) {
+// Global-address-space views: pointers read out of the descriptor are
+// generic, which would make every access a FLAT instruction.  Complex values
+// move as native two-float vectors.
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) v2f gf2;
+typedef __attribute__((address_space(1))) float gf1;
+__device__ __forceinline__ float2 ld2(const gf2 *p, unsigned i) {
+    const v2f v = p[i];
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void st2(gf2 *p, unsigned i, float2 a) {
+    v2f v;
+    v.x = a.x;
+    v.y = a.y;
+    p[i] = v;
+}
+
+// Where the value of one LDS slot comes from in every plane.  The slot at
+// (gx, gy), gx in [-1, nx], gy in [-1, ny], holds psi as the 7-point stencil
+// sees it: interior nodes are loaded; one-cell ghosts follow the boundary
+// rules of Sec. 3.3 -- plain wrap on a periodic x axis, the quasi-periodic
+// phase jump psi_{i,-1,k} = P_{i,k} psi_{i,ny-1,k} (and psi_{i,ny,k} =
+// P*_{i,k} psi_{i,0,k}) on a periodic y axis, and the Neumann ghost
+// U^* psi_{-1} = U psi_1 on an open face.  Corners and slots beyond a ragged
+// tile are zero.  The description does not depend on the plane, so it is
+// computed once per thread.
+enum { SRC_PLAIN = 0, SRC_P = 1, SRC_PCONJ = 2, SRC_FAC = 3, SRC_ZERO = 4 };
+struct CellSrc {
+    int off;      // element offset within a plane
+    int mode;
+    int px;       // x index of the phase P_{px,k}
+    float2 fac;   // constant factor (open-x ghost)
+};
+
+__device__ __forceinline__ CellSrc cell_src(const Inst &I, int gx, int gy) {
     const int nx = I.nx, ny = I.ny;
-    const long plane = (long)k * nx * ny;
     const bool xin = (unsigned)gx < (unsigned)nx, yin = (unsigned)gy < (unsigned)ny;
-    if (xin && yin) return src[plane + (long)gy * nx + gx];
+    CellSrc s{0, SRC_ZERO, 0, make_float2(1.f, 0.f)};
+    if (xin && yin) { s.off = gy * nx + gx; s.mode = SRC_PLAIN; return s; }
     if (xin) {
         if (gy == -1) {
-            if (I.per[1]) return cmul(I.P[(long)k * nx + gx], src[plane + (long)(ny - 1) * nx + gx]);
-            return ny >= 2 ? src[plane + (long)nx + gx] : make_float2(0.f, 0.f);
+            if (I.per[1]) { s.off = (ny - 1) * nx + gx; s.mode = SRC_P; s.px = gx; }
+            else if (ny >= 2) { s.off = nx + gx; s.mode = SRC_PLAIN; }
+        } else if (gy == ny) {
+            if (I.per[1]) { s.off = gx; s.mode = SRC_PCONJ; s.px = gx; }
+            else if (ny >= 2) { s.off = (ny - 2) * nx + gx; s.mode = SRC_PLAIN; }
         }
-        if (gy == ny) {
-            if (I.per[1]) return cmulc(I.P[(long)k * nx + gx], src[plane + gx]);
-            return ny >= 2 ? src[plane + (long)(ny - 2) * nx + gx] : make_float2(0.f, 0.f);
-        }
-        return make_float2(0.f, 0.f);
+        return s;
     }
     if (yin) {
-        const long row = plane + (long)gy * nx;
+        const float2 u = I.ux[gy];
         if (gx == -1) {
-            if (I.per[0]) return src[row + nx - 1];
-            if (nx < 2) return make_float2(0.f, 0.f);
-            float2 u = I.ux[gy];
-            return cmul(cmul(u, u), src[row + 1]);
-        }
-        if (gx == nx) {
-            if (I.per[0]) return src[row];
-            if (nx < 2) return make_float2(0.f, 0.f);
-            float2 u = I.ux[gy];
-            return cmulc(cmul(u, u), src[row + nx - 2]);
+            if (I.per[0]) { s.off = gy * nx + nx - 1; s.mode = SRC_PLAIN; }
+            else if (nx >= 2) { s.off = gy * nx + 1; s.mode = SRC_FAC; s.fac = cmul(u, u); }
+        } else if (gx == nx) {
+            if (I.per[0]) { s.off = gy * nx; s.mode = SRC_PLAIN; }
+            else if (nx >= 2) {
+                const float2 u2 = cmul(u, u);
+                s.off = gy * nx + nx - 2; s.mode = SRC_FAC; s.fac = make_float2(u2.x, -u2.y);
+            }
         }
     }
-    return make_float2(0.f, 0.f);
+    return s;
+}
+
+__device__ __forceinline__ float2 fetch(const gf2 *__restrict__ src, const gf2 *__restrict__ P,
+                                        unsigned pbase, int k, int nx, const CellSrc &s) {
+    if (s.mode == SRC_PLAIN) return ld2(src, pbase + (unsigned)s.off);
+    if (s.mode == SRC_ZERO) return make_float2(0.f, 0.f);
+    const float2 v = ld2(src, pbase + (unsigned)s.off);
+    if (s.mode == SRC_FAC) return cmul(s.fac, v);
+    const float2 ph = ld2(P, (unsigned)k * nx + s.px);
+    return s.mode == SRC_P ? cmul(ph, v) : cmulc(ph, v);
 }
 
 // z neighbour plane index of plane p in direction d (+1/-1), or -1 if none.
@@ -69,27 +103,26 @@ __device__ __forceinline__ int zplane(const Inst &I, int p, int d) {
     return q < 0 ? I.nz - 1 : 0;
 }
 
-// Own cell value of a thread for plane p (p may be -1: none -> 0).
-__device__ __forceinline__ float2 own_at(const Inst &I, const float2 *__restrict__ src, int x,
-                                         int y, int p) {
-    if (p < 0) return make_float2(0.f, 0.f);
-    if (x < I.nx && y < I.ny) return src[((long)p * I.ny + y) * I.nx + x];
-    return psi_at(I, src, x, y, p);
-}
-
-// Halo cell handled by thread t (t < HALO) of the tile at (x0, y0):
-// rows y0-1 and y0+TY (64 cells each), columns x0-1 and x0+TX (16 each).
+// Halo cell handled by thread t (t < 2 TX + 2 TYv) of a TX x TYv tile at
+// (x0, y0): rows y0-1 and y0+TYv (TX cells each), columns x0-1 and x0+TX.
+template <int TYv>
 __device__ __forceinline__ void halo_cell(int t, int x0, int y0, int &gx, int &gy, int &lx, int &ly) {
     if (t < TX) { gx = x0 + t; gy = y0 - 1; lx = t + 1; ly = 0; }
-    else if (t < 2 * TX) { gx = x0 + t - TX; gy = y0 + TY; lx = t - TX + 1; ly = TY + 1; }
-    else if (t < 2 * TX + TY) { gx = x0 - 1; gy = y0 + t - 2 * TX; lx = 0; ly = t - 2 * TX + 1; }
-    else { gx = x0 + TX; gy = y0 + t - 2 * TX - TY; lx = TX + 1; ly = t - 2 * TX - TY + 1; }
+    else if (t < 2 * TX) { gx = x0 + t - TX; gy = y0 + TYv; lx = t - TX + 1; ly = TYv + 1; }
+    else if (t < 2 * TX + TYv) { gx = x0 - 1; gy = y0 + t - 2 * TX; lx = 0; ly = t - 2 * TX + 1; }
+    else { gx = x0 + TX; gy = y0 + t - 2 * TX - TYv; lx = TX + 1; ly = t - 2 * TX - TYv + 1; }
 }
 
-template <int MODE>
+// MODE selects the pass; R is the number of consecutive rows a thread owns
+// (tile 64 x 4R: R = 4 streams more per thread, R = 2 keeps more waves
+// resident).
+template <int MODE, int R>
 __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
                                                 const int *__restrict__ prefix, int ninst, int l) {
-    __shared__ float2 lds[2][LDY][LDX];
+    constexpr int ROWS = R;
+    constexpr int TYv = 4 * R;
+    constexpr int HALOv = 2 * TX + 2 * TYv;
+    __shared__ float2 lds[2][TYv + 2][LDX];
     __shared__ double red[WG / 64];
 
     const int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -111,83 +144,111 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
     t /= I.tiles_x;
     const int tyi = t % I.tiles_y;
     const int tzi = t / I.tiles_y;
-    const int x0 = txi * TX, y0 = tyi * TY;
+    const int x0 = txi * TX, y0 = tyi * TYv;
     const int k0 = tzi * I.chunk;
     const int k1 = min(k0 + I.chunk, I.nz);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int x = x0 + lane;
-    const int nx = I.nx, ny = I.ny;
-    const long NXY = (long)nx * ny;
+    const int nx = I.nx, ny = I.ny, nz = I.nz;
+    const unsigned NXY = (unsigned)nx * (unsigned)ny;
 
     const int cur = st->cur;
-    const float2 *__restrict__ src =
-        (MODE == MODE_FIRST || MODE == MODE_RHS || MODE == MODE_ENERGY) ? I.psi[cur]
-                                                                        : I.psi[cur ^ (l & 1)];
-    float2 *__restrict__ dst = I.psi[cur ^ ((l + 1) & 1)];
+    const gf2 *__restrict__ src =
+        (const gf2 *)((MODE == MODE_SWEEP) ? I.psi[cur ^ (l & 1)] : I.psi[cur]);
+    gf2 *__restrict__ dst = (gf2 *)I.psi[cur ^ ((l + 1) & 1)];
+    const gf2 *__restrict__ Pt = (const gf2 *)I.P;
+    const gf2 *__restrict__ bhp = (const gf2 *)I.bh;
+    const gf2 *__restrict__ dhp = (const gf2 *)I.dh;
+    gf2 *__restrict__ bhw = (gf2 *)I.bh;
+    gf2 *__restrict__ dhw = (gf2 *)I.dh;
+    const gf1 *__restrict__ epsp = (const gf1 *)I.eps;
+    const gf1 *__restrict__ mup = (const gf1 *)I.mu;
+    gf1 *__restrict__ fw = (gf1 *)I.f;
 
     const float cx = I.cx, cy = I.cy, cz = I.cz;
     float2 ux[ROWS], uz[ROWS];
     bool vy[ROWS];
+    CellSrc own[ROWS];
+    bool all_plain = true;
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
         const int y = y0 + w * ROWS + r;
         vy[r] = (x < nx) && (y < ny);
         ux[r] = (y < ny) ? I.ux[y] : make_float2(1.f, 0.f);
         uz[r] = (y < ny) ? I.uz[y] : make_float2(1.f, 0.f);
+        own[r] = cell_src(I, x, y);
+        all_plain = all_plain && own[r].mode == SRC_PLAIN;
     }
-
-    // halo bookkeeping
-    const bool hthr = threadIdx.x < HALO;
+    const bool hthr = threadIdx.x < HALOv;
     int hgx = 0, hgy = 0, hlx = 0, hly = 0;
-    if (hthr) halo_cell(threadIdx.x, x0, y0, hgx, hgy, hlx, hly);
+    CellSrc hs{0, SRC_ZERO, 0, make_float2(1.f, 0.f)};
+    if (hthr) {
+        halo_cell<TYv>(threadIdx.x, x0, y0, hgx, hgy, hlx, hly);
+        hs = cell_src(I, hgx, hgy);
+    }
+    auto own_plane = [&](int p, float2 *out) {
+        // own cells of plane p (p = -1: no such plane -> zeros)
+        if (p < 0) {
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) out[r] = make_float2(0.f, 0.f);
+            return;
+        }
+        const unsigned pb = (unsigned)p * NXY;
+        if (all_plain) {
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) out[r] = ld2(src, pb + (unsigned)own[r].off);
+        } else {
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) out[r] = fetch(src, Pt, pb, p, nx, own[r]);
+        }
+    };
 
     // prologue: registers for planes k0-1, k0, k0+1; LDS buffer 0 = plane k0
     float2 pm[ROWS], pc[ROWS], pn[ROWS];
-    {
-        const int pp = zplane(I, k0, -1), pq = zplane(I, k0, +1);
+    own_plane(zplane(I, k0, -1), pm);
+    own_plane(k0, pc);
+    own_plane(zplane(I, k0, +1), pn);
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) lds[0][1 + w * ROWS + r][1 + lane] = pc[r];
+    if (hthr) lds[0][hly][hlx] = fetch(src, Pt, (unsigned)k0 * NXY, k0, nx, hs);
+    float2 hv = make_float2(0.f, 0.f);
+    if (hthr && k0 + 1 < k1) hv = fetch(src, Pt, (unsigned)(k0 + 1) * NXY, k0 + 1, nx, hs);
+
+    // per-plane streams of the first plane
+    float2 bh[ROWS], dh[ROWS];
+    float ep[ROWS], mu[ROWS];
+    const float mu_mean = (MODE == MODE_FIRST && I.driven) ? (float)st->mu_mean : 0.f;
+    auto load_streams = [&](int k, float2 *bh_, float2 *dh_, float *ep_, float *mu_) {
+        const unsigned pb = (unsigned)k * NXY;
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
-            const int y = y0 + w * ROWS + r;
-            pc[r] = own_at(I, src, x, y, k0);
-            pm[r] = own_at(I, src, x, y, pp);
-            pn[r] = own_at(I, src, x, y, pq);
+            const unsigned m = pb + (unsigned)own[r].off;
+            if (MODE == MODE_SWEEP) {
+                bh_[r] = vy[r] ? ld2(bhp, m) : make_float2(0.f, 0.f);
+                dh_[r] = vy[r] ? ld2(dhp, m) : make_float2(0.f, 0.f);
+            }
+            if (MODE == MODE_FIRST || MODE == MODE_ENERGY) ep_[r] = vy[r] ? float(epsp[m]) : 0.f;
+            if (MODE == MODE_FIRST) mu_[r] = (vy[r] && I.driven) ? float(mup[m]) - mu_mean : 0.f;
         }
-#pragma unroll
-        for (int r = 0; r < ROWS; ++r) lds[0][1 + w * ROWS + r][1 + lane] = pc[r];
-        if (hthr) lds[0][hly][hlx] = psi_at(I, src, hgx, hgy, k0);
-    }
-    float2 hv = make_float2(0.f, 0.f);
-    if (hthr && k0 + 1 < k1) hv = psi_at(I, src, hgx, hgy, k0 + 1);
+    };
+    load_streams(k0, bh, dh, ep, mu);
 
     const float ht2 = I.ht2, S2 = I.S2, u = I.u;
     const bool zper = I.per[2] != 0;
-    const float mu_mean = (MODE == MODE_FIRST && I.driven) ? (float)st->mu_mean : 0.f;
     float rmax = 0.f;
     double acc = 0.0;
 
     for (int k = k0; k < k1; ++k) {
         const int buf = (k - k0) & 1;
-        const long pbase = (long)k * NXY;
-        // issue this plane's streams and the next planes' loads early
-        float2 bh[ROWS], dh[ROWS];
-        float ep[ROWS], mu[ROWS];
-#pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
-            const long m = pbase + (long)(y0 + w * ROWS + r) * nx + x;
-            if (MODE == MODE_SWEEP) {
-                bh[r] = vy[r] ? I.bh[m] : make_float2(0.f, 0.f);
-                dh[r] = vy[r] ? I.dh[m] : make_float2(0.f, 0.f);
-            }
-            if (MODE == MODE_FIRST || MODE == MODE_ENERGY) ep[r] = vy[r] ? I.eps[m] : 0.f;
-            if (MODE == MODE_FIRST) mu[r] = (vy[r] && I.driven) ? I.mu[m] - mu_mean : 0.f;
-        }
-        float2 pnn[ROWS];
+        const unsigned pbase = (unsigned)k * NXY;
+        // issue the next planes' loads before the barrier
+        float2 pnn[ROWS], bhn[ROWS], dhn[ROWS];
+        float epn[ROWS], mun[ROWS];
         float2 hvn = make_float2(0.f, 0.f);
         if (k + 1 < k1) {
-            const int pq = zplane(I, k + 1, +1);
-#pragma unroll
-            for (int r = 0; r < ROWS; ++r) pnn[r] = own_at(I, src, x, y0 + w * ROWS + r, pq);
-            if (hthr && k + 2 < k1) hvn = psi_at(I, src, hgx, hgy, k + 2);
+            own_plane(zplane(I, k + 1, +1), pnn);
+            load_streams(k + 1, bhn, dhn, epn, mun);
+            if (hthr && k + 2 < k1) hvn = fetch(src, Pt, (unsigned)(k + 2) * NXY, k + 2, nx, hs);
         }
         __syncthreads();  // plane k staged; the other buffer is free
         if (k + 1 < k1) {
@@ -195,7 +256,7 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
             for (int r = 0; r < ROWS; ++r) lds[buf ^ 1][1 + w * ROWS + r][1 + lane] = pn[r];
             if (hthr) lds[buf ^ 1][hly][hlx] = hv;
         }
-        const bool zm = (k > 0) || zper, zp = (k < I.nz - 1) || zper;
+        const bool zm = (k > 0) || zper, zp = (k < nz - 1) || zper;
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             const int ly = 1 + w * ROWS + r;
@@ -203,7 +264,7 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
             const float2 xm = lds[buf][ly][lane], xp = lds[buf][ly][lane + 2];
             const float2 ym = lds[buf][ly - 1][lane + 1], yp = lds[buf][ly + 1][lane + 1];
             if (!vy[r]) continue;
-            const long m = pbase + (long)(y0 + w * ROWS + r) * nx + x;
+            const unsigned m = pbase + (unsigned)own[r].off;
             if (MODE == MODE_ENERGY) {
                 // forward edges only; an edge beyond an open face does not exist.
                 const float a2 = cabs2(c);
@@ -211,12 +272,11 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
                 const bool fx = I.per[0] || x < nx - 1, fy = I.per[1] || y < ny - 1;
                 const float wxn = (!I.per[0] && nx > 1 && (x == 0 || x == nx - 1)) ? 0.5f : 1.f;
                 const float wyn = (!I.per[1] && ny > 1 && (y == 0 || y == ny - 1)) ? 0.5f : 1.f;
-                const float wzn = (!zper && I.nz > 1 && (k == 0 || k == I.nz - 1)) ? 0.5f : 1.f;
+                const float wzn = (!zper && nz > 1 && (k == 0 || k == nz - 1)) ? 0.5f : 1.f;
                 double e = (double)(wxn * wyn * wzn) * (double)(-ep[r] * a2 + 0.5f * a2 * a2);
                 if (fx) e += (double)(wyn * wzn * cx) * (double)cabs2(csub(cmul(ux[r], xp), c));
                 if (fy) e += (double)(wxn * wzn * cy) * (double)cabs2(csub(yp, c));
-                if (zp)
-                    e += (double)(wxn * wyn * cz) * (double)cabs2(csub(cmul(uz[r], pn[r]), c));
+                if (zp) e += (double)(wxn * wyn * cz) * (double)cabs2(csub(cmul(uz[r], pn[r]), c));
                 acc += e;
                 continue;
             }
@@ -234,7 +294,7 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
             if (MODE == MODE_RHS) {
                 // f = sum_a (1/h_a^2) Im[psi^* (U psi_+ + U^* psi_-)] = Im[psi^* NS]
                 const float f = c.x * ns.y - c.y * ns.x;
-                I.f[m] = f;
+                fw[m] = f;
                 acc += (double)f * (double)node_w(I, x, y0 + w * ROWS + r, k);
                 continue;
             }
@@ -253,8 +313,8 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
                 const float2 Mi = make_float2(M.x * inv, -M.y * inv);
                 const float2 bhv = cmul(bb, Mi);
                 const float2 dhv = cscale(ht2, Mi);
-                I.bh[m] = bhv;
-                I.dh[m] = dhv;
+                st2(bhw, m, bhv);
+                st2(dhw, m, dhv);
                 nw = cadd(bhv, cmul(dhv, ns));
                 const float2 d = csub(nw, c);
                 const float r2 = cabs2(M) * cabs2(d);
@@ -265,13 +325,19 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
                 const float r2 = cabs2(d) * (ht2 * ht2) / cabs2(dh[r]);
                 rmax = (r2 > rmax || r2 != r2) ? r2 : rmax;
             }
-            dst[m] = nw;
+            st2(dst, m, nw);
         }
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             pm[r] = pc[r];
             pc[r] = pn[r];
-            if (k + 1 < k1) pn[r] = pnn[r];
+            if (k + 1 < k1) {
+                pn[r] = pnn[r];
+                bh[r] = bhn[r];
+                dh[r] = dhn[r];
+                ep[r] = epn[r];
+                mu[r] = mun[r];
+            }
         }
         hv = hvn;
     }
@@ -285,9 +351,15 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
     }
 }
 
-template __global__ void k_stencil<MODE_FIRST>(const Inst *, const int *, int, int);
-template __global__ void k_stencil<MODE_SWEEP>(const Inst *, const int *, int, int);
-template __global__ void k_stencil<MODE_RHS>(const Inst *, const int *, int, int);
-template __global__ void k_stencil<MODE_ENERGY>(const Inst *, const int *, int, int);
+#define TDGL_INST(M, R) template __global__ void k_stencil<M, R>(const Inst *, const int *, int, int);
+TDGL_INST(MODE_FIRST, 2)
+TDGL_INST(MODE_SWEEP, 2)
+TDGL_INST(MODE_RHS, 2)
+TDGL_INST(MODE_ENERGY, 2)
+TDGL_INST(MODE_FIRST, 4)
+TDGL_INST(MODE_SWEEP, 4)
+TDGL_INST(MODE_RHS, 4)
+TDGL_INST(MODE_ENERGY, 4)
+#undef TDGL_INST
 
 }  // namespace tdgl

@@ -353,7 +353,7 @@ __global__ void k_mg_finalize(const Inst *__restrict__ insts, int ninst) {
     const int ii = blockIdx.x * blockDim.x + threadIdx.x;
     if (ii >= ninst) return;
     const Inst &I = insts[ii];
-    if (!I.driven) return;
+    if (!I.driven || I.fft) return;
     DevState *st = I.st;
     int cycles = I.mu_max_cycles, capped = 1;
     const float thr = mg_threshold(I);
@@ -368,9 +368,11 @@ __global__ void k_mg_finalize(const Inst *__restrict__ insts, int ninst) {
     for (int c = 0; c < I.mu_max_cycles; ++c) row_clear(I.mures, I.rstride, c);
 }
 
-// Partial sums of V mu on level 0 for its weighted mean.
+// Partial sums of V mu (which = 0) or V f (which = 1) on level 0 for the
+// weighted mean.
 __global__ __launch_bounds__(256) void k_mu_mean_partial(const Inst *__restrict__ insts,
-                                                         const int *__restrict__ prefix, int ninst) {
+                                                         const int *__restrict__ prefix, int ninst,
+                                                         int which) {
     __shared__ double red[4];
     const int ii = find_inst(prefix, ninst, blockIdx.x);
     const Inst &I = insts[ii];
@@ -381,7 +383,8 @@ __global__ __launch_bounds__(256) void k_mu_mean_partial(const Inst *__restrict_
     if (q.valid) {
         const double vxy = (double)L.vol[0][q.x] * L.vol[1][q.y];
         const long nxy = (long)L.nx * L.ny, col = (long)q.y * L.nx + q.x;
-        for (int k = q.k0; k < q.k1; ++k) acc += vxy * L.vol[2][k] * (double)L.mu[0][k * nxy + col];
+        const float *src = which ? L.rhs : L.mu[0];
+        for (int k = q.k0; k < q.k1; ++k) acc += vxy * L.vol[2][k] * (double)src[k * nxy + col];
     }
     const double s = wg_sum<256>(acc, red);
     if (threadIdx.x == 0) I.part[lb] = s;

@@ -8,7 +8,7 @@ enum { MODE_FIRST = 0, MODE_SWEEP = 1, MODE_RHS = 2, MODE_ENERGY = 3 };
 constexpr int JAV_CPT = 16;     // cells per thread of the flat reductions
 constexpr int CO_THREADS = 1024;
 
-template <int MODE>
+template <int MODE, int R>
 __global__ void k_stencil(const Inst *insts, const int *prefix, int ninst, int l);
 
 __global__ void k_links(const Inst *insts, int which);
@@ -34,7 +34,17 @@ __global__ void k_mg_prolong(const Inst *insts, const int *prefix, int ninst, in
                              int cyc);
 __global__ void k_mg_coarsest(const Inst *insts, int ninst, int cyc);
 __global__ void k_mg_finalize(const Inst *insts, int ninst);
-__global__ void k_mu_mean_partial(const Inst *insts, const int *prefix, int ninst);
+__global__ void k_mu_mean_partial(const Inst *insts, const int *prefix, int ninst, int which);
+
+__global__ void k_fft_x(const Inst *insts, const int *prefix, int ninst, int dir, const float *in_ext,
+                        float *out_ext);
+__global__ void k_fft_y(const Inst *insts, const int *prefix, int ninst, int dir);
+__global__ void k_fft_zsolve(const Inst *insts, const int *prefix, int ninst);
+__host__ __device__ int fft_x_pairs(int nx);
+__host__ __device__ int fft_y_cols(int ny);
+constexpr int FFT_ZTK = 32;     // kx columns per work-group of the z solve
+constexpr int FFT_ZMAX = 256;   // largest nz of the spectral path
+constexpr int FFT_MAXN = 8192;  // points per work-group of the x and y passes
 
 __global__ void k_incl_first(const Inst *insts, int inst, const double *centres, const double *diam,
                              int nc, unsigned *first);

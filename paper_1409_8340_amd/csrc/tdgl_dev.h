@@ -17,15 +17,11 @@ constexpr int kMaxLevels = 16;   // multigrid levels
 constexpr int NSLOT = 32;        // atomic slots per convergence row
 
 // Tile of the 2.5D stencil kernels: 64 x-columns (one wavefront wide) by
-// 16 y-rows; 256 threads, each owning 4 consecutive rows of one column, march
-// through a chunk of z planes.
+// 4R y-rows; 256 threads, each owning R consecutive rows of one column, march
+// through a chunk of z planes.  R = 2 or 4 (chosen per context).
 constexpr int TX = 64;
-constexpr int TY = 16;
-constexpr int ROWS = 4;          // rows per thread (TY / waves)
 constexpr int WG = 256;
-constexpr int HALO = 2 * TX + 2 * TY;  // halo cells of one plane (no corners)
 constexpr int LDX = TX + 2;            // LDS plane pitch (float2 units)
-constexpr int LDY = TY + 2;
 
 // Tile of the multigrid kernels: 64 x 4 columns, z chunk.
 constexpr int MTX = 64;
@@ -113,8 +109,14 @@ struct Inst {
     double *part;        // per-work-group partial sums
     int part_cap;
     int tiles_x, tiles_y, tiles_z, chunk;   // stencil tiling (chunk: z planes per tile)
+    int rows;                               // rows per thread R (tile 64 x 4R)
     int nlev;
     MGLevel lev[kMaxLevels];
+    // direct spectral Poisson solve (periodic x and y, open z)
+    int fft;             // 1: the Poisson equation is solved by FFT, 0: by multigrid
+    int nxrad, nyrad;    // FFT radix plans along x and y
+    int xrad[16], yrad[16];
+    float2 *spec;        // half spectrum, nz * ny * (nx/2 + 1)
 };
 
 // ---------------------------------------------------------------------------

@@ -34,7 +34,8 @@ class Params(ctypes.Structure):
                 ("dt", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("driven", ctypes.c_int), ("mu_tol", ctypes.c_double), ("mu_rtol", ctypes.c_double),
                 ("mu_max_cycles", ctypes.c_int), ("strict", ctypes.c_int),
-                ("tile_cz", ctypes.c_int), ("reserved", ctypes.c_int * 7)]
+                ("tile_cz", ctypes.c_int), ("tile_rows", ctypes.c_int), ("poisson", ctypes.c_int),
+                ("reserved", ctypes.c_int * 5)]
 
 
 class StepStats(ctypes.Structure):
@@ -108,6 +109,7 @@ _SIGS = {
     "tdgl_voltage_window_reset": ([ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
     "tdgl_step": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(StepStats)], ctypes.c_int),
     "tdgl_observables": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(Obs)], ctypes.c_int),
+    "tdgl_poisson_solve": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "tdgl_profile_start": ([ctypes.c_void_p, ctypes.c_uint], ctypes.c_int),
     "tdgl_profile_stop": ([ctypes.c_void_p, ctypes.POINTER(Prof)], ctypes.c_int),
 }
@@ -143,7 +145,8 @@ def _check(status):
 
 def make_params(nx, ny, nz, h=0.5, hx=None, hy=None, hz=None, bc=(TDGL_PERIODIC, TDGL_PERIODIC, TDGL_OPEN),
                 g=1.0, u=1.0, dt=0.1, tol=1e-8, max_iter=100, driven=False, mu_tol=1e-5,
-                mu_rtol=0.0, mu_max_cycles=20, strict=False, tile_cz=0) -> Params:
+                mu_rtol=0.0, mu_max_cycles=20, strict=False, tile_cz=0, tile_rows=0,
+                poisson=0) -> Params:
     p = Params()
     p.nx, p.ny, p.nz = nx, ny, nz
     p.hx = h if hx is None else hx
@@ -159,6 +162,8 @@ def make_params(nx, ny, nz, h=0.5, hx=None, hy=None, hz=None, bc=(TDGL_PERIODIC,
     p.mu_max_cycles = mu_max_cycles
     p.strict = int(bool(strict))
     p.tile_cz = tile_cz
+    p.tile_rows = tile_rows
+    p.poisson = poisson
     return p
 
 
@@ -296,6 +301,15 @@ class Solver:
         st = StepStats()
         _check(load().tdgl_step(self._ctx, int(nsteps), ctypes.byref(st) if stats else None))
         return st.as_dict() if stats else None
+
+    def poisson_solve(self, f):
+        import torch
+        f = f.to(device="cuda", dtype=torch.float32).contiguous()
+        out = torch.empty(self.shape(0), dtype=torch.float32, device="cuda")
+        _check(load().tdgl_poisson_solve(self._ctx, self._dev(f, torch.float32),
+                                         self._dev(out, torch.float32)))
+        self._stream.synchronize()
+        return out
 
     def profile_start(self, classes=None):
         mask = 0
