@@ -1,0 +1,108 @@
+"""Pins of the oracle's adjoint: dot-product tests of every transposed
+operator, the one-step vector-Jacobian product against central finite
+differences of the exact step, and dVbar/deps against central finite
+differences of the whole run.  CPU only."""
+import numpy as np
+import pytest
+
+from oracle import adjoint as A
+from oracle import oracle as O
+from paper_1409_8340_amd import inputs
+
+
+def _c(shape, seed, scale=1.0):
+    return inputs.random_complex(shape, seed, scale).astype(np.complex128)
+
+
+def _r(shape, seed, lo=-1.0, hi=1.0):
+    return inputs.random_real(shape, seed, lo, hi).astype(np.float64)
+
+
+GRIDS = [O.Grid(6, 5, 4, open_=(False, False, True)),
+         O.Grid(6, 4, 5, open_=(False, True, True), g=1.2),
+         O.Grid(4, 6, 4, open_=(False, False, False))]
+
+
+@pytest.mark.parametrize("grid", GRIDS)
+def test_ns_adjoint_dot_product(grid):
+    Bx, Bz = 0.17, 0.23
+    links = O.with_K(O.landau_links(grid, Bx, Bz, 0.0), grid.hx, 0.3)
+    w = O.node_weights(grid)
+    v, u = _c(grid.shape, 1), _c(grid.shape, 2)
+    lhs = np.vdot(u, A.ns(grid, links, v))
+    rhs = np.vdot(A.ns_h(grid, links, w, u), v)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+@pytest.mark.parametrize("grid", GRIDS)
+def test_poisson_transpose_dot_product(grid):
+    w = O.node_weights(grid)
+    f, g = _r(grid.shape, 3), _r(grid.shape, 4)
+    lhs = np.dot(g.ravel(), O.poisson_exact(grid, f).ravel())
+    rhs = np.dot(A.poisson_T(grid, w, g).ravel(), f.ravel())
+    assert abs(lhs - rhs) < 1e-11 * max(1.0, abs(lhs))
+
+
+def _step_functional(grid, p, eps, prev, bars, base):
+    st = O.State(psi=prev[0].copy(), mu=prev[1].copy(), K=prev[2])
+    q = O.Params(**{**p.__dict__, "mode": "exact"})
+    O.step(grid, q, eps, st, base_links=base)
+    psibar, mubar, Kbar, ew = bars
+    val = np.real(np.vdot(psibar, st.psi)) + np.dot(mubar.ravel(), st.mu.ravel()) + Kbar * st.K
+    return val + ew * st.last_E, (st.psi.copy(), st.mu.copy(), st.K)
+
+
+@pytest.mark.parametrize("grid,driven", [(GRIDS[0], True), (GRIDS[2], True), (GRIDS[1], False)])
+def test_step_vjp_against_finite_differences(grid, driven):
+    Bx, Bz = O.quantize_field(grid, 0.0, 0.5)
+    if grid.open_[1]:
+        Bx, Bz = 0.2, 0.3
+    p = O.Params(Bx=Bx, Bz=Bz, J_ext=0.05, u=1.3, dt=0.1, driven=driven, mode="exact")
+    base = O.landau_links(grid, Bx, Bz, 0.0)
+    w = O.node_weights(grid)
+    eps = _r(grid.shape, 5, 0.2, 1.0)
+    prev = (inputs.psi_init(grid.nx, grid.ny, grid.nz, 6).astype(np.complex128) * 0.8
+            + 0.2 * _c(grid.shape, 7), _r(grid.shape, 8, -0.1, 0.1) if driven else np.zeros(grid.shape),
+            0.4 if driven else 0.0)
+    bars = (_c(grid.shape, 9), _r(grid.shape, 10) if driven else np.zeros(grid.shape),
+            0.7 if driven else 0.0, 1.3 if driven else 0.0)
+    _, nxt = _step_functional(grid, p, eps, prev, bars, base)
+    pb, mb, kb, eb = A.step_vjp(grid, p, eps, prev, nxt, bars[0], bars[1], bars[2], bars[3], base, w)
+    # random direction in (psi^-, mu^-, K^-, eps)
+    dpsi, dmu = _c(grid.shape, 11), _r(grid.shape, 12) if driven else np.zeros(grid.shape)
+    dK = 0.3 if driven else 0.0
+    deps = _r(grid.shape, 13)
+    h = 1e-6
+    plus = (prev[0] + h * dpsi, prev[1] + h * dmu, prev[2] + h * dK)
+    minus = (prev[0] - h * dpsi, prev[1] - h * dmu, prev[2] - h * dK)
+    fp, _ = _step_functional(grid, p, eps + h * deps, plus, bars, base)
+    fm, _ = _step_functional(grid, p, eps - h * deps, minus, bars, base)
+    fd = (fp - fm) / (2 * h)
+    ad = (np.real(np.vdot(pb, dpsi)) + np.dot(mb.ravel(), dmu.ravel()) + kb * dK
+          + np.dot(eb.ravel(), deps.ravel()))
+    assert abs(fd - ad) < 1e-6 * max(1.0, abs(fd)), (fd, ad)
+
+
+def test_voltage_gradient_against_finite_differences():
+    """dVbar/deps on a small driven vortex system (exact forward, central
+    differences with delta = 1e-4 on 8 random cells)."""
+    grid = O.Grid(8, 8, 4, open_=(False, False, True))
+    Bx, Bz = O.quantize_field(grid, 0.0, 0.4)
+    p = O.Params(Bx=Bx, Bz=Bz, J_ext=0.08, dt=0.1, driven=True, mode="exact")
+    eps = _r(grid.shape, 21, 0.3, 1.0)
+    st0 = O.new_state(grid, inputs.psi_init(8, 8, 4, 22).astype(np.complex128))
+    nsteps, wb = 6, 2
+    V, grad = A.voltage_grad(grid, p, eps, st0, nsteps, wb)
+    rng = np.random.default_rng(3)
+    cells = rng.choice(grid.N, 8, replace=False)
+    d = 1e-4
+    for m in cells:
+        idx = np.unravel_index(m, grid.shape)
+        vals = []
+        for sgn in (+1, -1):
+            e2 = eps.copy()
+            e2[idx] += sgn * d
+            _, Es = A.forward(grid, p, e2, st0, nsteps)
+            vals.append(np.mean(Es[wb:]))
+        fd = (vals[0] - vals[1]) / (2 * d)
+        assert abs(fd - grad[idx]) <= 1e-4 * max(abs(fd), 1e-3 * np.max(np.abs(grad))), (m, fd, grad[idx])
