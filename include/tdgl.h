@@ -234,6 +234,29 @@ tdgl_status tdgl_observables(tdgl_ctx *ctx, int inst, tdgl_obs *obs);
  * instance's stored mu~ (the next step starts from this solution). */
 tdgl_status tdgl_poisson_solve(tdgl_ctx *ctx, const float *f, float *mu);
 
+/* Bytes of the caller-owned workspace tdgl_voltage_grad needs for nsteps
+ * steps with a checkpoint every ckpt_every steps: ceil(nsteps/ckpt_every)
+ * checkpoints and one segment of ckpt_every+1 states of psi~ (complex64) and
+ * mu~ (float) plus a few node arrays.  Host only. */
+tdgl_status tdgl_adjoint_plan(const tdgl_ctx *ctx, int nsteps, int ckpt_every, size_t *bytes);
+
+/* Advances the context's single driven instance by nsteps steps, exactly as
+ * tdgl_step(ctx, nsteps) would, and returns the time-averaged electric field
+ *     Vbar = (1/W) sum_{n = window_begin}^{nsteps-1} E_n,
+ *     E_n = J_ext - J_av (Sec. 3.1.1, Eq. K_ODE),  W = nsteps - window_begin,
+ * (steps counted from 0 within this call) together with its gradient
+ * d Vbar / d eps_m at every node (float[N], device memory, overwritten).  The
+ * gradient is that of the implicit step itself -- Crank-Nicolson system,
+ * J_av, K update and Poisson solve differentiated exactly (implicit-function
+ * adjoint, Sec. 3.1-3.2), the phase rewind having derivative one -- so it
+ * matches finite differences when the solves are converged tightly (small
+ * tol and mu_tol).  Reverse sweep over the steps; the states of each segment
+ * of ckpt_every steps are recomputed from a checkpoint.  ws/ws_bytes: the
+ * workspace of tdgl_adjoint_plan (256-byte aligned).  The context ends in
+ * the state after nsteps steps.  Synchronising. */
+tdgl_status tdgl_voltage_grad(tdgl_ctx *ctx, int nsteps, int window_begin, int ckpt_every, void *ws,
+                              size_t ws_bytes, double *vbar, float *grad_eps);
+
 /* Kernel classes of the per-kernel profile (the time profile of one step,
  * kernel by kernel, as in the paper's performance section, Sec. 4.3). */
 #define TDGL_K_ASSEMBLE 0   /* assemble b, M_mm fused with the first Jacobi iteration */

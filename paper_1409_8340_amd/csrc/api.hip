@@ -675,13 +675,13 @@ struct ProfScope {
 
 // Launch one stencil pass over every instance with the context's tile.
 template <int MODE>
-void launch_stencil(tdgl_ctx *c, int l) {
+void launch_stencil(tdgl_ctx *c, int l, const float2 *in = nullptr, float2 *out = nullptr) {
     if (c->rows == 2)
         hipLaunchKernelGGL((k_stencil<MODE, 2>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst, c->d_pref_st,
-                           c->n, l);
+                           c->n, l, in, out);
     else
         hipLaunchKernelGGL((k_stencil<MODE, 4>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst, c->d_pref_st,
-                           c->n, l);
+                           c->n, l, in, out);
 }
 
 // One multigrid V-cycle for every driven instance (cycle index cyc).
@@ -730,6 +730,69 @@ tdgl_status enqueue_vcycle(tdgl_ctx *c, int cyc) {
         }
     }
     LAUNCHCHK();
+    return TDGL_OK;
+}
+
+// The Jacobi iterations after the first sweep (already enqueued, its input
+// residual in row 0): sweep l reads row l-1 on the device and is a no-op
+// for instances whose solve has ended; the host reads the rows one sweep
+// behind and stops enqueueing once every instance has met its stop rule or
+// cap.  Then the per-instance result buffer is fixed on the device
+// (count_step: also advance the step counters).  Accumulates statistics.
+tdgl_status jacobi_loop(tdgl_ctx *ctx, tdgl_step_stats *acc, bool *strict_fail, int count_step) {
+    const int n = ctx->n;
+    hipStream_t s = ctx->stream;
+    const size_t RW = ctx->row_words();
+    HIPCHK(hipMemcpyAsync(ctx->h_res, ctx->d_res, RW * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(ctx->ev[0], s));
+    std::vector<int> conv_at(n, -1);
+    int remaining = n, launched = 1, polled = 0;
+    for (;;) {
+        // inspect the rows of all sweeps except the newest one
+        while (remaining > 0 && (polled < launched - 1 || launched == ctx->max_iter) && polled < launched) {
+            HIPCHK(hipEventSynchronize(ctx->ev[polled]));
+            for (int i = 0; i < n; ++i) {
+                if (conv_at[i] >= 0) continue;
+                const InstHost &h = ctx->inst[i];
+                const float r = ctx->host_row_max(ctx->h_res, polled, i);
+                if (r < (float)h.p.tol || polled + 1 >= h.p.max_iter) {
+                    conv_at[i] = polled;
+                    --remaining;
+                }
+            }
+            ++polled;
+        }
+        if (remaining == 0 || launched == ctx->max_iter) break;
+        const int l = launched;
+        {
+            ProfScope ps(ctx, TDGL_K_SWEEP);
+            launch_stencil<MODE_SWEEP>(ctx, l);
+        }
+        LAUNCHCHK();
+        HIPCHK(hipMemcpyAsync(ctx->h_res + (size_t)l * RW, ctx->d_res + (size_t)l * RW, RW * 4,
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(ctx->ev[l], s));
+        ++launched;
+    }
+    {
+        ProfScope ps(ctx, TDGL_K_OTHER);
+        hipLaunchKernelGGL(k_solve_finalize, dim3(cdiv(n, 64)), dim3(64), 0, s, ctx->d_inst, n, count_step);
+    }
+    LAUNCHCHK();
+    for (int i = 0; acc && i < n; ++i) {
+        const InstHost &h = ctx->inst[i];
+        const float r = ctx->host_row_max(ctx->h_res, conv_at[i], i);
+        const bool capped = !(r < (float)h.p.tol);
+        const int sw = capped ? h.p.max_iter : conv_at[i] + 1;
+        acc->sweeps_min = std::min(acc->sweeps_min, sw);
+        acc->sweeps_max = std::max(acc->sweeps_max, sw);
+        acc->sweeps_sum += sw;
+        acc->last_res2 = r;
+        if (capped) {
+            acc->capped_steps++;
+            if (h.p.strict && strict_fail) *strict_fail = true;
+        }
+    }
     return TDGL_OK;
 }
 
@@ -1116,7 +1179,6 @@ tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats) {
     tdgl_step_stats acc;
     memset(&acc, 0, sizeof acc);
     acc.sweeps_min = 1 << 30;
-    std::vector<int> conv_at(n);
     bool strict_fail = false;
     for (int step = 0; step < nsteps; ++step) {
         // ---- Jacobi solve (all instances) --------------------------------
@@ -1125,57 +1187,8 @@ tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats) {
             launch_stencil<MODE_FIRST>(ctx, 0);
         }
         LAUNCHCHK();
-        const size_t RW = ctx->row_words();
-        HIPCHK(hipMemcpyAsync(ctx->h_res, ctx->d_res, RW * 4, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipEventRecord(ctx->ev[0], s));
-        std::fill(conv_at.begin(), conv_at.end(), -1);
-        int remaining = n, launched = 1, polled = 0;
-        for (;;) {
-            // inspect the rows of all sweeps except the newest one
-            while (remaining > 0 && (polled < launched - 1 || launched == ctx->max_iter) && polled < launched) {
-                HIPCHK(hipEventSynchronize(ctx->ev[polled]));
-                for (int i = 0; i < n; ++i) {
-                    if (conv_at[i] >= 0) continue;
-                    const InstHost &h = ctx->inst[i];
-                    const float r = ctx->host_row_max(ctx->h_res, polled, i);
-                    if (r < (float)h.p.tol || polled + 1 >= h.p.max_iter) {
-                        conv_at[i] = polled;
-                        --remaining;
-                    }
-                }
-                ++polled;
-            }
-            if (remaining == 0 || launched == ctx->max_iter) break;
-            const int l = launched;
-            {
-                ProfScope ps(ctx, TDGL_K_SWEEP);
-                launch_stencil<MODE_SWEEP>(ctx, l);
-            }
-            LAUNCHCHK();
-            HIPCHK(hipMemcpyAsync(ctx->h_res + (size_t)l * RW, ctx->d_res + (size_t)l * RW, RW * 4,
-                                  hipMemcpyDeviceToHost, s));
-            HIPCHK(hipEventRecord(ctx->ev[l], s));
-            ++launched;
-        }
-        {
-            ProfScope ps(ctx, TDGL_K_OTHER);
-            hipLaunchKernelGGL(k_solve_finalize, dim3(cdiv(n, 64)), dim3(64), 0, s, ctx->d_inst, n);
-        }
-        LAUNCHCHK();
-        for (int i = 0; i < n; ++i) {
-            const InstHost &h = ctx->inst[i];
-            const float r = ctx->host_row_max(ctx->h_res, conv_at[i], i);
-            const bool capped = !(r < (float)h.p.tol);
-            const int sw = capped ? h.p.max_iter : conv_at[i] + 1;
-            acc.sweeps_min = std::min(acc.sweeps_min, sw);
-            acc.sweeps_max = std::max(acc.sweeps_max, sw);
-            acc.sweeps_sum += sw;
-            acc.last_res2 = r;
-            if (capped) {
-                acc.capped_steps++;
-                if (h.p.strict) strict_fail = true;
-            }
-        }
+        tdgl_status e = jacobi_loop(ctx, &acc, &strict_fail, 1);
+        if (e) return e;
         // ---- current, K and the scalar potential (driven instances) -------
         if (ctx->any_driven) {
             {
@@ -1222,6 +1235,176 @@ tdgl_status tdgl_poisson_solve(tdgl_ctx *ctx, const float *f, float *mu) {
     if (e) return e;
     hipLaunchKernelGGL(k_mu_io, dim3(fill_grid(d.N)), dim3(256), 0, s, ctx->d_inst, 0, mu, 1);
     LAUNCHCHK();
+    return TDGL_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct AdjLayout {
+    float2 *ck_psi, *seg_psi, *fin_psi, *psibar, *t1, *t2, *t3;
+    float *ck_mu, *seg_mu, *fin_mu, *mubar;
+    double *ck_K, *seg_K, *fin_K, *Elog;
+    DevState *fin_st;
+    AdjState *adj;
+};
+
+size_t adj_layout(long N, int nsteps, int C, char *base, AdjLayout *L) {
+    Carver cv{base};
+    const int ncp = (nsteps + C - 1) / C;
+    AdjLayout l;
+    l.ck_psi = cv.take<float2>((size_t)ncp * N);
+    l.ck_mu = cv.take<float>((size_t)ncp * N);
+    l.ck_K = cv.take<double>(2 * (size_t)ncp);
+    l.seg_psi = cv.take<float2>((size_t)(C + 1) * N);
+    l.seg_mu = cv.take<float>((size_t)(C + 1) * N);
+    l.seg_K = cv.take<double>(C + 1);
+    l.fin_psi = cv.take<float2>(N);
+    l.fin_mu = cv.take<float>(N);
+    l.fin_K = cv.take<double>(2);
+    l.fin_st = cv.take<DevState>(1);
+    l.psibar = cv.take<float2>(N);
+    l.mubar = cv.take<float>(N);
+    l.t1 = cv.take<float2>(N);
+    l.t2 = cv.take<float2>(N);
+    l.t3 = cv.take<float2>(N);
+    l.Elog = cv.take<double>(nsteps);
+    l.adj = cv.take<AdjState>(1);
+    if (L) *L = l;
+    return cv.off;
+}
+
+// Reverse of one step: prev = state n-1, nxt = state n (segment slots).
+tdgl_status adjoint_step(tdgl_ctx *c, const AdjLayout &L, int iprev, int inext, double ew, float *grad) {
+    const Inst &d = c->inst[0].d;
+    const long N = d.N;
+    hipStream_t s = c->stream;
+    const int G = std::max(1, std::min(d.part_cap, 2048));
+    const float2 *psim = L.seg_psi + (size_t)iprev * N, *psin = L.seg_psi + (size_t)inext * N;
+    const float *mum = L.seg_mu + (size_t)iprev * N;
+    const double *Km = L.seg_K + iprev, *Kn = L.seg_K + inext;
+    // Poisson transpose: fbar = W G(W^-1 mubar)
+    hipLaunchKernelGGL(k_adj_prep_f, dim3(G), dim3(256), 0, s, c->d_inst, L.mubar);
+    hipLaunchKernelGGL(k_mu_mean_partial, dim3(std::max(c->tot_mg[0], 1)), dim3(256), 0, s, c->d_inst,
+                       pref_mg(c, 0), 1, 1);
+    hipLaunchKernelGGL(k_reduce_to_state, dim3(1), dim3(256), 0, s, c->d_inst, c->d_np_mg0, 4, 1);
+    LAUNCHCHK();
+    tdgl_status e = enqueue_poisson(c, nullptr);
+    if (e) return e;
+    // adjoint of the Poisson right side, links at K_n
+    hipLaunchKernelGGL(k_adj_setK, dim3(1), dim3(64), 0, s, c->d_inst, Kn);
+    hipLaunchKernelGGL(k_links, dim3(1), dim3(256), 0, s, c->d_inst, 1);
+    hipLaunchKernelGGL(k_adj_g, dim3(G), dim3(256), 0, s, c->d_inst, psin, L.t1);
+    launch_stencil<MODE_NS>(c, 0, psin, L.t2);
+    launch_stencil<MODE_NS>(c, 0, L.t1, L.t3);
+    hipLaunchKernelGGL(k_adj_facc, dim3(G), dim3(256), 0, s, c->d_inst, L.psibar, L.t2, L.t3);
+    hipLaunchKernelGGL(k_adj_edge_f, dim3(G), dim3(256), 0, s, c->d_inst, psin);
+    hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(256), 0, s, c->d_inst, G, 0, ew, L.adj);
+    // J_av(psi_n, K_{n-1}) and the K update
+    hipLaunchKernelGGL(k_adj_setK, dim3(1), dim3(64), 0, s, c->d_inst, Km);
+    hipLaunchKernelGGL(k_links, dim3(1), dim3(256), 0, s, c->d_inst, 1);
+    hipLaunchKernelGGL(k_adj_jterm, dim3(G), dim3(256), 0, s, c->d_inst, L.psibar, psin, L.adj);
+    hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(256), 0, s, c->d_inst, G, 1, 0.0, L.adj);
+    // the Crank-Nicolson system transposed
+    hipLaunchKernelGGL(k_adj_maxabs, dim3(G), dim3(256), 0, s, c->d_inst, L.psibar);
+    hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(256), 0, s, c->d_inst, G, 3, 0.0, L.adj);
+    hipLaunchKernelGGL(k_adj_assemble, dim3(G), dim3(256), 0, s, c->d_inst, L.psibar, psim, mum, L.adj);
+    LAUNCHCHK();
+    e = jacobi_loop(c, nullptr, nullptr, 0);
+    if (e) return e;
+    // sources: eps gradient, mubar^-, K terms and psibar^-
+    hipLaunchKernelGGL(k_adj_scale_nu, dim3(G), dim3(256), 0, s, c->d_inst, L.adj, L.t1);
+    launch_stencil<MODE_NS>(c, 0, L.t1, L.t2);
+    hipLaunchKernelGGL(k_adj_edge_s, dim3(G), dim3(256), 0, s, c->d_inst, psim, psin, L.adj);
+    hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(256), 0, s, c->d_inst, G, 2, 0.0, L.adj);
+    hipLaunchKernelGGL(k_adj_sources, dim3(G), dim3(256), 0, s, c->d_inst, L.psibar, L.mubar, grad, psim, psin,
+                       mum, L.t2, L.adj);
+    LAUNCHCHK();
+    return TDGL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tdgl_status tdgl_adjoint_plan(const tdgl_ctx *ctx, int nsteps, int ckpt_every, size_t *bytes) {
+    if (!ctx || !bytes) return fail(TDGL_EINVAL, "null argument");
+    if (nsteps < 1 || ckpt_every < 1) return fail(TDGL_EINVAL, "nsteps and ckpt_every must be >= 1");
+    *bytes = adj_layout(ctx->inst[0].d.N, nsteps, std::min(ckpt_every, nsteps), nullptr, nullptr);
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_voltage_grad(tdgl_ctx *ctx, int nsteps, int window_begin, int ckpt_every, void *ws,
+                              size_t ws_bytes, double *vbar, float *grad) {
+    if (!ctx) return fail(TDGL_EINVAL, "null context");
+    if (ctx->n != 1) return fail(TDGL_EINVAL, "tdgl_voltage_grad needs a context with one instance");
+    const InstHost &h = ctx->inst[0];
+    if (!h.p.driven) return fail(TDGL_EINVAL, "the voltage needs a driven instance (driven = 1)");
+    if (nsteps < 1 || window_begin < 0 || window_begin >= nsteps || ckpt_every < 1)
+        return fail(TDGL_EINVAL, "need nsteps >= 1, 0 <= window_begin < nsteps, ckpt_every >= 1");
+    if (!grad || !vbar) return fail(TDGL_EINVAL, "null output");
+    const int C = std::min(ckpt_every, nsteps);
+    const long N = h.d.N;
+    const size_t need = adj_layout(N, nsteps, C, nullptr, nullptr);
+    if (!ws || ((uintptr_t)ws % kAlign) != 0 || ws_bytes < need)
+        return fail(TDGL_EWS, "adjoint workspace missing, misaligned or below %zu bytes", need);
+    AdjLayout L;
+    adj_layout(N, nsteps, C, (char *)ws, &L);
+    hipStream_t s = ctx->stream;
+    const int G = std::max(1, std::min(h.d.part_cap, 2048));
+    hipLaunchKernelGGL(k_fill_f, dim3(fill_grid(N)), dim3(256), 0, s, grad, N, 0.f);
+    hipLaunchKernelGGL(k_fill_c, dim3(fill_grid(N)), dim3(256), 0, s, L.psibar, N, 0.f, 0.f);
+    hipLaunchKernelGGL(k_fill_f, dim3(fill_grid(N)), dim3(256), 0, s, L.mubar, N, 0.f);
+    hipLaunchKernelGGL(k_adj_zero, dim3(1), dim3(64), 0, s, L.adj);
+    LAUNCHCHK();
+    // forward with checkpoints
+    for (int n = 0; n < nsteps; ++n) {
+        if (n % C == 0) {
+            const int q = n / C;
+            hipLaunchKernelGGL(k_adj_save, dim3(G), dim3(256), 0, s, ctx->d_inst, L.ck_psi + (size_t)q * N,
+                               L.ck_mu + (size_t)q * N, L.ck_K + 2 * q, 1);
+        }
+        tdgl_status e = tdgl_step(ctx, 1, nullptr);
+        if (e) return e;
+        hipLaunchKernelGGL(k_adj_logE, dim3(1), dim3(64), 0, s, ctx->d_inst, L.Elog, n);
+    }
+    hipLaunchKernelGGL(k_adj_save, dim3(G), dim3(256), 0, s, ctx->d_inst, L.fin_psi, L.fin_mu, L.fin_K, 1);
+    HIPCHK(hipMemcpyAsync(L.fin_st, h.d.st, sizeof(DevState), hipMemcpyDeviceToDevice, s));
+    LAUNCHCHK();
+    // reverse sweep, segment by segment
+    const int ncp = (nsteps + C - 1) / C;
+    const double W = (double)(nsteps - window_begin);
+    for (int q = ncp - 1; q >= 0; --q) {
+        const int s0 = q * C, s1 = std::min(s0 + C, nsteps);
+        hipLaunchKernelGGL(k_adj_load, dim3(G), dim3(256), 0, s, ctx->d_inst, L.ck_psi + (size_t)q * N,
+                           L.ck_mu + (size_t)q * N, L.ck_K + 2 * q);
+        hipLaunchKernelGGL(k_links, dim3(1), dim3(256), 0, s, ctx->d_inst, 1);
+        hipLaunchKernelGGL(k_adj_save, dim3(G), dim3(256), 0, s, ctx->d_inst, L.seg_psi, L.seg_mu, L.seg_K, 0);
+        LAUNCHCHK();
+        for (int j = 1; j <= s1 - s0; ++j) {
+            tdgl_status e = tdgl_step(ctx, 1, nullptr);
+            if (e) return e;
+            hipLaunchKernelGGL(k_adj_save, dim3(G), dim3(256), 0, s, ctx->d_inst, L.seg_psi + (size_t)j * N,
+                               L.seg_mu + (size_t)j * N, L.seg_K + j, 0);
+        }
+        for (int n = s1; n > s0; --n) {
+            const double ew = (n - 1 >= window_begin) ? 1.0 / W : 0.0;
+            tdgl_status e = adjoint_step(ctx, L, n - 1 - s0, n - s0, ew, grad);
+            if (e) return e;
+        }
+    }
+    // back to the state after the forward run
+    HIPCHK(hipMemcpyAsync(h.d.st, L.fin_st, sizeof(DevState), hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_adj_load, dim3(G), dim3(256), 0, s, ctx->d_inst, L.fin_psi, L.fin_mu, L.fin_K);
+    hipLaunchKernelGGL(k_links, dim3(1), dim3(256), 0, s, ctx->d_inst, 1);
+    LAUNCHCHK();
+    std::vector<double> E(nsteps);
+    HIPCHK(hipMemcpyAsync(E.data(), L.Elog, nsteps * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double acc = 0.0;
+    for (int n = window_begin; n < nsteps; ++n) acc += E[n];
+    *vbar = acc / W;
     return TDGL_OK;
 }
 

@@ -43,7 +43,7 @@ __global__ void k_links(const Inst *__restrict__ insts, int which) {
 // the solve with that sweep's output (Eq. convergence); otherwise the cap.
 // Updates the psi buffer index, step counters and clears the residual words
 // for the next step.  One thread per instance.
-__global__ void k_solve_finalize(const Inst *__restrict__ insts, int ninst) {
+__global__ void k_solve_finalize(const Inst *__restrict__ insts, int ninst, int count_step) {
     const int ii = blockIdx.x * blockDim.x + threadIdx.x;
     if (ii >= ninst) return;
     const Inst &I = insts[ii];
@@ -57,8 +57,10 @@ __global__ void k_solve_finalize(const Inst *__restrict__ insts, int ninst) {
     st->sweeps = sweeps;
     st->capped = capped;
     st->cur ^= (sweeps & 1);
-    st->t += I.dt;
-    st->n += 1.0;
+    if (count_step) {
+        st->t += I.dt;
+        st->n += 1.0;
+    }
     // keep the last tested residual, then clear the words for the next step
     st->last_res2 = last;
     for (int l = 0; l < I.max_iter; ++l) row_clear(I.res, I.rstride, l);

@@ -13,7 +13,10 @@
 //               writing b/M_mm, (ht/2)/M_mm and psi^(1);
 //   MODE_SWEEP  one Jacobi iteration psi^(l+1) = b/M + (ht/2)/M * NS(psi^(l));
 //   MODE_RHS    right side of the Poisson equation (Sec. 3.2);
-//   MODE_ENERGY free-energy density summed in FP64.
+//   MODE_ENERGY free-energy density summed in FP64;
+//   MODE_NS     the neighbour sum NS(x) of an arbitrary complex field x (the
+//               off-diagonal part of the covariant Laplacian; used by the
+//               adjoint).
 // FIRST and SWEEP also reduce max_m |r_m|^2 of their input iterate
 // (Eq. convergence) through r = M_mm (psi^(l+1) - psi^(l)).
 #include "kernels.h"
@@ -118,7 +121,8 @@ __device__ __forceinline__ void halo_cell(int t, int x0, int y0, int &gx, int &g
 // resident).
 template <int MODE, int R>
 __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
-                                                const int *__restrict__ prefix, int ninst, int l) {
+                                                const int *__restrict__ prefix, int ninst, int l,
+                                                const float2 *ext_in, float2 *ext_out) {
     constexpr int ROWS = R;
     constexpr int TYv = 4 * R;
     constexpr int HALOv = 2 * TX + 2 * TYv;
@@ -154,7 +158,8 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
 
     const int cur = st->cur;
     const gf2 *__restrict__ src =
-        (const gf2 *)((MODE == MODE_SWEEP) ? I.psi[cur ^ (l & 1)] : I.psi[cur]);
+        (const gf2 *)((MODE == MODE_NS) ? ext_in : (MODE == MODE_SWEEP) ? I.psi[cur ^ (l & 1)] : I.psi[cur]);
+    gf2 *__restrict__ nsout = (gf2 *)ext_out;
     gf2 *__restrict__ dst = (gf2 *)I.psi[cur ^ ((l + 1) & 1)];
     const gf2 *__restrict__ Pt = (const gf2 *)I.P;
     const gf2 *__restrict__ bhp = (const gf2 *)I.bh;
@@ -291,6 +296,10 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
             const float2 yt = cadd(yp, ym);
             const float2 ns = make_float2(cx * xt.x + cy * yt.x + cz * zt.x,
                                           cx * xt.y + cy * yt.y + cz * zt.y);
+            if (MODE == MODE_NS) {
+                st2(nsout, m, ns);
+                continue;
+            }
             if (MODE == MODE_RHS) {
                 // f = sum_a (1/h_a^2) Im[psi^* (U psi_+ + U^* psi_-)] = Im[psi^* NS]
                 const float f = c.x * ns.y - c.y * ns.x;
@@ -342,7 +351,9 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
         hv = hvn;
     }
 
-    if (MODE == MODE_FIRST || MODE == MODE_SWEEP) {
+    if (MODE == MODE_NS) {
+        return;
+    } else if (MODE == MODE_FIRST || MODE == MODE_SWEEP) {
         __syncthreads();
         wg_max_to<WG>(row_slot(I.res, I.rstride, l, b), rmax, reinterpret_cast<float *>(red));
     } else {
@@ -351,15 +362,18 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
     }
 }
 
-#define TDGL_INST(M, R) template __global__ void k_stencil<M, R>(const Inst *, const int *, int, int);
+#define TDGL_INST(M, R) \
+    template __global__ void k_stencil<M, R>(const Inst *, const int *, int, int, const float2 *, float2 *);
 TDGL_INST(MODE_FIRST, 2)
 TDGL_INST(MODE_SWEEP, 2)
 TDGL_INST(MODE_RHS, 2)
 TDGL_INST(MODE_ENERGY, 2)
+TDGL_INST(MODE_NS, 2)
 TDGL_INST(MODE_FIRST, 4)
 TDGL_INST(MODE_SWEEP, 4)
 TDGL_INST(MODE_RHS, 4)
 TDGL_INST(MODE_ENERGY, 4)
+TDGL_INST(MODE_NS, 4)
 #undef TDGL_INST
 
 }  // namespace tdgl

@@ -4,15 +4,16 @@
 
 namespace tdgl {
 
-enum { MODE_FIRST = 0, MODE_SWEEP = 1, MODE_RHS = 2, MODE_ENERGY = 3 };
+enum { MODE_FIRST = 0, MODE_SWEEP = 1, MODE_RHS = 2, MODE_ENERGY = 3, MODE_NS = 4 };
 constexpr int JAV_CPT = 16;     // cells per thread of the flat reductions
 constexpr int CO_THREADS = 1024;
 
 template <int MODE, int R>
-__global__ void k_stencil(const Inst *insts, const int *prefix, int ninst, int l);
+__global__ void k_stencil(const Inst *insts, const int *prefix, int ninst, int l, const float2 *ext_in,
+                          float2 *ext_out);
 
 __global__ void k_links(const Inst *insts, int which);
-__global__ void k_solve_finalize(const Inst *insts, int ninst);
+__global__ void k_solve_finalize(const Inst *insts, int ninst, int count_step);
 __global__ void k_jav_partial(const Inst *insts, const int *prefix, int ninst);
 __global__ void k_kupdate(const Inst *insts, const int *nparts);
 __global__ void k_reduce_to_state(const Inst *insts, const int *nparts, int field, int driven_only);
@@ -45,6 +46,25 @@ __host__ __device__ int fft_y_cols(int ny);
 constexpr int FFT_ZTK = 32;     // kx columns per work-group of the z solve
 constexpr int FFT_ZMAX = 256;   // largest nz of the spectral path
 constexpr int FFT_MAXN = 8192;  // points per work-group of the x and y passes
+
+__global__ void k_adj_save(const Inst *insts, float2 *dpsi, float *dmu, double *dK, int raw);
+__global__ void k_adj_load(const Inst *insts, const float2 *spsi, const float *smu, const double *sK);
+__global__ void k_adj_setK(const Inst *insts, const double *Kp);
+__global__ void k_adj_logE(const Inst *insts, double *Elog, int n);
+__global__ void k_adj_zero(AdjState *adj);
+__global__ void k_adj_prep_f(const Inst *insts, const float *mubar);
+__global__ void k_adj_g(const Inst *insts, const float2 *psin, float2 *g);
+__global__ void k_adj_facc(const Inst *insts, float2 *psibar, const float2 *ns_psi, const float2 *ns_g);
+__global__ void k_adj_edge_f(const Inst *insts, const float2 *psin);
+__global__ void k_adj_jterm(const Inst *insts, float2 *psibar, const float2 *psin, const AdjState *adj);
+__global__ void k_adj_maxabs(const Inst *insts, const float2 *psibar);
+__global__ void k_adj_assemble(const Inst *insts, const float2 *psibar, const float2 *psim, const float *mum,
+                               const AdjState *adj);
+__global__ void k_adj_scale_nu(const Inst *insts, const AdjState *adj, float2 *tmp);
+__global__ void k_adj_sources(const Inst *insts, float2 *psibar, float *mubar, float *epsbar, const float2 *psim,
+                              const float2 *psin, const float *mum, const float2 *ns_l, const AdjState *adj);
+__global__ void k_adj_edge_s(const Inst *insts, const float2 *psim, const float2 *psin, const AdjState *adj);
+__global__ void k_adj_reduce(const Inst *insts, int nparts, int which, double ew, AdjState *adj);
 
 __global__ void k_incl_first(const Inst *insts, int inst, const double *centres, const double *diam,
                              int nc, unsigned *first);

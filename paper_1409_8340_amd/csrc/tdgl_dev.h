@@ -56,6 +56,14 @@ struct DevState {
     int pad2;
 };
 
+// Scalars of the adjoint sweep over one step (device resident).
+struct AdjState {
+    double Kbar;   // adjoint of K, accumulated backwards through the steps
+    double Jbar;   // adjoint of J_av of the current step
+    double scale;  // normalisation of the adjoint Crank-Nicolson system
+    double pad;
+};
+
 struct MGLevel {
     int nx, ny, nz, N;
     int per[3];

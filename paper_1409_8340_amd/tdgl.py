@@ -110,6 +110,10 @@ _SIGS = {
     "tdgl_step": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(StepStats)], ctypes.c_int),
     "tdgl_observables": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(Obs)], ctypes.c_int),
     "tdgl_poisson_solve": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "tdgl_adjoint_plan": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
+                          ctypes.c_int),
+    "tdgl_voltage_grad": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                          ctypes.c_size_t, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p], ctypes.c_int),
     "tdgl_profile_start": ([ctypes.c_void_p, ctypes.c_uint], ctypes.c_int),
     "tdgl_profile_stop": ([ctypes.c_void_p, ctypes.POINTER(Prof)], ctypes.c_int),
 }
@@ -311,6 +315,21 @@ class Solver:
         self._stream.synchronize()
         return out
 
+    def voltage_grad(self, nsteps, window_begin=0, ckpt_every=50):
+        """(Vbar, dVbar/deps) over nsteps steps; see tdgl_voltage_grad."""
+        import torch
+        nb = ctypes.c_size_t()
+        _check(load().tdgl_adjoint_plan(self._ctx, nsteps, ckpt_every, ctypes.byref(nb)))
+        torch.cuda.current_stream().synchronize()
+        ws = torch.empty(nb.value + 256, dtype=torch.uint8, device="cuda")
+        ptr = (ws.data_ptr() + 255) // 256 * 256
+        grad = torch.empty(self.shape(0), dtype=torch.float32, device="cuda")
+        v = ctypes.c_double()
+        _check(load().tdgl_voltage_grad(self._ctx, nsteps, window_begin, ckpt_every, ctypes.c_void_p(ptr),
+                                        nb.value, ctypes.byref(v), self._dev(grad, torch.float32)))
+        del ws
+        return v.value, grad
+
     def profile_start(self, classes=None):
         mask = 0
         for c in (classes or KERNEL_CLASSES):
@@ -326,3 +345,49 @@ class Solver:
         o = Obs()
         _check(load().tdgl_observables(self._ctx, inst, ctypes.byref(o)))
         return o.as_dict()
+
+
+_VOLTAGE_FN = None
+
+
+def _voltage_fn():
+    global _VOLTAGE_FN
+    if _VOLTAGE_FN is None:
+        import torch
+
+        class VoltageFn(torch.autograd.Function):
+            """Vbar(eps) of a driven one-instance solver as a torch function.
+
+            The forward runs nsteps implicit steps from the solver's current
+            state and, when eps needs a gradient, the checkpointed reverse
+            sweep in the same call (the step states exist only while the
+            solver replays them), keeping dVbar/deps for the backward."""
+
+            @staticmethod
+            def forward(ctx, eps, solver, nsteps, window_begin, ckpt_every):
+                solver.set_eps(eps.detach())
+                if ctx.needs_input_grad[0]:
+                    v, g = solver.voltage_grad(nsteps, window_begin, ckpt_every)
+                    ctx.save_for_backward(g)
+                else:
+                    if window_begin > 0:
+                        solver.step(window_begin, stats=False)
+                    solver.window_reset()
+                    solver.step(nsteps - window_begin, stats=False)
+                    v = solver.observables()["E_mean"]
+                return torch.tensor(v, dtype=torch.float64, device=eps.device)
+
+            @staticmethod
+            def backward(ctx, gout):
+                (g,) = ctx.saved_tensors
+                return gout.to(g.dtype) * g, None, None, None, None
+
+        _VOLTAGE_FN = VoltageFn
+    return _VOLTAGE_FN
+
+
+def voltage(solver, eps, nsteps, window_begin=0, ckpt_every=50):
+    """Time-averaged E_x over steps window_begin..nsteps-1 of a run from the
+    solver's current state, differentiable with respect to eps (float32,
+    shape (nz, ny, nx), CUDA).  Advances the solver by nsteps steps."""
+    return _voltage_fn().apply(eps, solver, nsteps, window_begin, ckpt_every)

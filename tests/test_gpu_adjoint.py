@@ -1,0 +1,107 @@
+"""GPU adjoint dVbar/deps (tdgl_voltage_grad) against the FP64 oracle's
+adjoint, which is itself pinned to finite differences of the exact step.
+The GPU forward is FP32 with iterative solves, so the comparison is
+normwise (relative L2 error and cosine) rather than element by element."""
+import numpy as np
+import pytest
+
+from oracle import adjoint as A
+from paper_1409_8340_amd import inputs, tdgl
+from tests.harness import Case
+
+pytestmark = pytest.mark.gpu
+
+
+def _eps(shape, seed):
+    # inclusion-like landscape: eps in [0.2, 1] with a few deep cells
+    e = inputs.random_real(shape, seed, 0.2, 1.0)
+    e[inputs.random_real(shape, seed + 1, 0.0, 1.0) < 0.1] = -0.5
+    return e
+
+
+CASES = {
+    # x, y periodic, z open: spectral Poisson path
+    "spectral": dict(nx=16, ny=12, nz=8, open_=(False, False, True), Bz=0.3),
+    # y and z open: multigrid Poisson path
+    "multigrid": dict(nx=16, ny=10, nz=6, open_=(False, True, True), Bz=0.25, Bx=0.1),
+}
+
+
+def _make(name, **kw):
+    c = CASES[name]
+    shape = (c["nz"], c["ny"], c["nx"])
+    case = Case(c["nx"], c["ny"], c["nz"], open_=c["open_"], Bz=c["Bz"], Bx=c.get("Bx", 0.0), J=0.06,
+                driven=True, tol=1e-12, max_iter=300, mu_tol=1e-7, mu_max_cycles=60, eps=_eps(shape, 31),
+                psi_seed=32, **kw)
+    return case
+
+
+def _compare(g_gpu, g_orc):
+    a = np.asarray(g_gpu, np.float64).ravel()
+    b = np.asarray(g_orc, np.float64).ravel()
+    rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+    cos = np.dot(a, b) / (np.linalg.norm(a) * np.linalg.norm(b))
+    return rel, cos
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_voltage_grad_vs_oracle(name):
+    case = _make(name)
+    nsteps, wb = 6, 2
+    s = case.solver()
+    v, g = s.voltage_grad(nsteps, wb, ckpt_every=4)
+    g = g.cpu().numpy()
+    s.close()
+    V_o, g_o = A.voltage_grad(case.grid, case.oracle_params("exact"), case.eps.astype(np.float64),
+                              case.oracle_state(), nsteps, wb)
+    rel, cos = _compare(g, g_o)
+    print(f"[adjoint {name}] Vbar gpu {v:.8e} oracle {V_o:.8e}; grad rel L2 {rel:.3e} cos {cos:.6f}")
+    assert abs(v - V_o) <= 1e-3 * abs(case.J)
+    assert rel <= 1e-2 and cos >= 0.9999
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_checkpoint_spacing_and_final_state(name):
+    """The result does not depend on the checkpoint spacing, and the solver
+    ends in the state that plain steps reach."""
+    case = _make(name)
+    nsteps = 7
+    s1 = case.solver()
+    v1, g1 = s1.voltage_grad(nsteps, 1, ckpt_every=2)
+    psi1, mu1, sc1 = s1.get_psi().cpu().numpy(), s1.get_mu().cpu().numpy(), s1.get_scalars()
+    s1.close()
+    s2 = case.solver()
+    v2, g2 = s2.voltage_grad(nsteps, 1, ckpt_every=nsteps)
+    s2.close()
+    s3 = case.solver()
+    s3.step(nsteps)
+    psi3, mu3, sc3 = s3.get_psi().cpu().numpy(), s3.get_mu().cpu().numpy(), s3.get_scalars()
+    s3.close()
+    assert v1 == v2
+    # checkpoints replay the steps bit for bit and every reverse solve starts
+    # from zero, so the spacing changes nothing
+    assert np.array_equal(g1.cpu().numpy(), g2.cpu().numpy())
+    assert np.array_equal(psi1, psi3)
+    assert np.array_equal(mu1, mu3)
+    assert sc1["K"] == sc3["K"] and sc1["n"] == sc3["n"]
+
+
+def test_autograd_function():
+    import torch
+    case = _make("spectral")
+    s = case.solver()
+    eps = torch.from_numpy(case.eps).cuda().requires_grad_(True)
+    V = tdgl.voltage(s, eps, 5, window_begin=1, ckpt_every=3)
+    (2.0 * V).backward()
+    s.close()
+    s2 = case.solver()
+    v2, g2 = s2.voltage_grad(5, 1, ckpt_every=3)
+    s2.close()
+    assert float(V) == v2
+    np.testing.assert_allclose(eps.grad.cpu().numpy(), 2.0 * g2.cpu().numpy(), rtol=1e-6, atol=0)
+    # without a gradient the forward is the plain run
+    s3 = case.solver()
+    with torch.no_grad():
+        V3 = tdgl.voltage(s3, eps.detach(), 5, window_begin=1)
+    s3.close()
+    assert abs(float(V3) - v2) <= 1e-12 * max(1.0, abs(v2))
