@@ -15,7 +15,8 @@ synchronisation.  value = nodes * K / seconds (cell-updates per second).
 The roofline entry is for the dominant kernel, the Jacobi sweep: its launches
 are bracketed by HIP events on the solver's stream inside the timed region,
 and achieved = algorithmic bytes per launch (32 B per node: read psi, b/M and
-(ht/2)/M, write psi, complex64 each) / mean launch time.
+(ht/2)/M, write psi, complex64 each) / mean time of a full sweep (total sweep
+time over the launches that did a full pass).
 
 cpu_baseline times the FP64 oracle (test infrastructure, not the product)
 on a bounded sample of the same physics.
@@ -121,6 +122,35 @@ def cpu_baseline(w, seconds_target=20.0):
                       f"Poisson; {el:.1f} s on {threads} OpenMP threads"}
 
 
+def adjoint_ratio(tdgl, inputs, torch, nsteps, ckpt, warmup):
+    """(forward + adjoint time) / (plain forward time) on the c4 workload
+    (128 x 128 x 32, B = 0.1, J = 0.03, 8 % d = 4 inclusions): nsteps
+    steps with the voltage averaged over all of them, checkpoint every
+    ckpt steps, both timed from the same state after warmup steps."""
+    w = inputs.WORKLOADS["c4_adjoint_128x128x32"]
+    s, _, _, _ = setup(w, tdgl, inputs, torch, w.tol, 0.0)
+    s.step(warmup, stats=False)
+    torch.cuda.synchronize()
+    psi, mu, sc = s.get_psi(), s.get_mu(), s.get_scalars()
+    t0 = time.perf_counter()
+    s.step(nsteps, stats=True)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    s.set_psi(psi)
+    s.set_mu(mu)
+    s.set_scalars(sc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    v, g = s.voltage_grad(nsteps, 0, ckpt)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    gn = float(torch.linalg.vector_norm(g.double()))
+    s.close()
+    return {"workload": w.name, "steps": nsteps, "ckpt_every": ckpt, "warmup": warmup,
+            "plain_ms_per_step": 1e3 * t_fwd / nsteps, "fwd_adj_ms_per_step": 1e3 * t_adj / nsteps,
+            "ratio": t_adj / t_fwd, "Vbar": v, "grad_l2": gn}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +163,8 @@ def main():
                     help="extra untimed steps profiled per kernel class")
     ap.add_argument("--mu-rtol", type=float, default=0.03,
                     help="Poisson stop: residual below max(1e-5, mu_rtol * initial residual)")
+    ap.add_argument("--adjoint-steps", type=int, default=500,
+                    help="steps of the c4 forward+adjoint comparison (0 skips it)")
     ap.add_argument("--copy-calib-gib", type=float, default=0.0,
                     help="run a plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -153,13 +185,15 @@ def main():
     s, Bz, used, frac = setup(w, tdgl, inputs, torch, w.tol, args.mu_rtol)
     log(f"[bench] B_eff={Bz:.6f} inclusions={used} fraction={frac}")
     if args.copy_calib_gib > 0:
-        nb = int(args.copy_calib_gib * (1 << 30))
-        a = torch.empty(nb, dtype=torch.uint8, device="cuda").fill_(1)
+        # one elementwise kernel that reads nb bytes and writes nb bytes
+        nb = int(args.copy_calib_gib * (1 << 30)) // 4 * 4
+        a = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
-        b.copy_(a)
+        torch.cuda.synchronize()
+        torch.mul(a, 2.0, out=b)
         torch.cuda.synchronize()
         del a, b
-        log(f"[bench] copy calibration: {nb} bytes copied")
+        log(f"[bench] copy calibration: {nb} bytes read and {nb} bytes written by one mul kernel")
     for i in range(args.warmup):
         s.step(1, stats=False)
         if (i + 1) % 10 == 0:
@@ -189,11 +223,22 @@ def main():
     obs = s.observables()
 
     sw = prof["sweep"]
-    sweep_ms = sw["ms"] / max(sw["launches"], 1)
+    # Sweep-class launches that did a full pass: the first iterate of every
+    # step comes from the assemble kernel, and the launch that starts before
+    # the host has seen convergence exits at once.  Its few microseconds stay
+    # in the total, so the mean below errs on the slow side.
+    full = max(st["sweeps_sum"] - st["steps"], 1)
+    sweep_ms = sw["ms"] / full
     achieved = SWEEP_BYTES_PER_NODE * N / (sweep_ms * 1e-3) / 1e9
     asm = prof["assemble"]
     asm_ms = asm["ms"] / max(asm["launches"], 1)
     traffic = read_traffic(N)
+
+    adj = None
+    if args.adjoint_steps > 0:
+        log(f"[bench] c4 forward+adjoint over {args.adjoint_steps} steps")
+        adj = adjoint_ratio(tdgl, inputs, torch, args.adjoint_steps, 50, 100)
+        log(f"[bench] adjoint ratio {adj['ratio']:.3f}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -222,7 +267,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "tdgl::k_stencil<1> (Jacobi sweep)",
                      "bytes_per_launch": SWEEP_BYTES_PER_NODE * N, "mean_launch_ms": sweep_ms,
-                     "launches": sw["launches"]},
+                     "full_launches": full, "launches": sw["launches"]},
         "cpu_baseline": cpu,
         "extra": {
             "sweeps_per_step": st["sweeps_sum"] / max(st["steps"], 1),
@@ -231,6 +276,7 @@ def main():
             "assemble_ms": asm_ms,
             "assemble_GBps": ASSEMBLE_BYTES_PER_NODE * N / (asm_ms * 1e-3) / 1e9,
             "kernel_breakdown": breakdown,
+            "adjoint": adj,
             "E_mean": obs["E_mean"], "F": obs["F"], "psi2_mean": obs["psi2_mean"],
             "kernel_source_sha": kernel_sha(),
         },

@@ -355,7 +355,7 @@ struct tdgl_ctx {
     // spectral Poisson path: prefix tables of its three kernels and LDS sizes
     int *d_pref_fx = nullptr, *d_pref_fy = nullptr, *d_pref_fz = nullptr;
     int tot_fx = 0, tot_fy = 0, tot_fz = 0;
-    size_t fx_lds = 0, fy_lds = 0;
+    size_t fx_lds = 0, fy_lds = 0, fz_lds = 0;
     bool any_fft = false, any_mg = false;
     bool any_driven = false;
     int max_iter = 1, max_cycles = 1;
@@ -507,7 +507,11 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
                 radix_plan(p.nx, d.xrad, &d.nxrad);
                 radix_plan(p.ny, d.yrad, &d.nyrad);
                 const int P = p.nx / 2 + 1;
-                d.spec = cv.take<float2>((size_t)p.nz * p.ny * P);
+                d.sp = fft_pitch(p.nx);
+                d.spec = cv.take<float2>((size_t)p.nz * p.ny * d.sp);
+                d.twx = cv.take<float2>(p.nx);
+                d.twy = cv.take<float2>(p.ny);
+                d.zip = cv.take<double>((size_t)p.ny * P * p.nz);
                 h.fx_blocks = cdiv((long)p.ny * p.nz, 2L * fft_x_pairs(p.nx));
                 h.fy_blocks = p.nz * cdiv(P, fft_y_cols(p.ny));
                 h.fz_blocks = p.ny * cdiv(P, FFT_ZTK);
@@ -600,6 +604,7 @@ tdgl_status upload_tables(tdgl_ctx *ctx) {
             ctx->any_fft = true;
             ctx->fx_lds = std::max(ctx->fx_lds, (size_t)fft_x_pairs(h.p.nx) * h.p.nx * 8);
             ctx->fy_lds = std::max(ctx->fy_lds, (size_t)fft_y_cols(h.p.ny) * h.p.ny * 8);
+            ctx->fz_lds = std::max(ctx->fz_lds, fft_z_lds(h.p.nz));
         } else if (h.p.driven) {
             ctx->any_mg = true;
         }
@@ -622,6 +627,8 @@ tdgl_status upload_tables(tdgl_ctx *ctx) {
                                    (int)ctx->fx_lds));
         HIPCHK(hipFuncSetAttribute((const void *)k_fft_y, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)ctx->fy_lds));
+        HIPCHK(hipFuncSetAttribute((const void *)k_fft_zsolve, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)ctx->fz_lds));
     }
     HIPCHK(hipMemcpy(ctx->d_pref_st, ps.data(), (n + 1) * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_pref_flat, pf.data(), (n + 1) * 4, hipMemcpyHostToDevice));
@@ -809,15 +816,15 @@ tdgl_status enqueue_poisson(tdgl_ctx *ctx, tdgl_step_stats *acc) {
         ProfScope ps(ctx, TDGL_K_MG_FINE);
         const float *nf = nullptr;
         float *nm = nullptr;
-        hipLaunchKernelGGL(k_fft_x, dim3(std::max(ctx->tot_fx, 1)), dim3(256), ctx->fx_lds, s, ctx->d_inst,
+        hipLaunchKernelGGL(k_fft_x, dim3(std::max(ctx->tot_fx, 1)), dim3(FFT_XY_THREADS), ctx->fx_lds, s, ctx->d_inst,
                            ctx->d_pref_fx, n, -1, nf, nm);
-        hipLaunchKernelGGL(k_fft_y, dim3(std::max(ctx->tot_fy, 1)), dim3(256), ctx->fy_lds, s, ctx->d_inst,
+        hipLaunchKernelGGL(k_fft_y, dim3(std::max(ctx->tot_fy, 1)), dim3(FFT_XY_THREADS), ctx->fy_lds, s, ctx->d_inst,
                            ctx->d_pref_fy, n, -1);
-        hipLaunchKernelGGL(k_fft_zsolve, dim3(std::max(ctx->tot_fz, 1)), dim3(256), 0, s, ctx->d_inst,
+        hipLaunchKernelGGL(k_fft_zsolve, dim3(std::max(ctx->tot_fz, 1)), dim3(256), ctx->fz_lds, s, ctx->d_inst,
                            ctx->d_pref_fz, n);
-        hipLaunchKernelGGL(k_fft_y, dim3(std::max(ctx->tot_fy, 1)), dim3(256), ctx->fy_lds, s, ctx->d_inst,
+        hipLaunchKernelGGL(k_fft_y, dim3(std::max(ctx->tot_fy, 1)), dim3(FFT_XY_THREADS), ctx->fy_lds, s, ctx->d_inst,
                            ctx->d_pref_fy, n, +1);
-        hipLaunchKernelGGL(k_fft_x, dim3(std::max(ctx->tot_fx, 1)), dim3(256), ctx->fx_lds, s, ctx->d_inst,
+        hipLaunchKernelGGL(k_fft_x, dim3(std::max(ctx->tot_fx, 1)), dim3(FFT_XY_THREADS), ctx->fx_lds, s, ctx->d_inst,
                            ctx->d_pref_fx, n, +1, nf, nm);
         LAUNCHCHK();
     }
@@ -956,6 +963,12 @@ tdgl_status tdgl_create(int n, const tdgl_params *params, void *ws, size_t ws_by
     hipLaunchKernelGGL(k_fill_u, dim3(64), dim3(256), 0, st, c->d_mures, (long)(c->max_cycles * c->row_words()),
                        0u);
     hipLaunchKernelGGL(k_links, dim3(n), dim3(256), 0, st, c->d_inst, 0);
+    for (int i = 0; i < n; ++i) {
+        const tdgl_params &p = c->inst[i].p;
+        if (!c->inst[i].d.fft) continue;
+        const long cols = std::max<long>(std::max(p.nx, p.ny), (long)p.ny * (p.nx / 2 + 1));
+        hipLaunchKernelGGL(k_fft_tables, dim3((unsigned)cdiv(cols, 256L)), dim3(256), 0, st, c->d_inst, i);
+    }
     LAUNCHCHK();
     if (hipStreamSynchronize(st) != hipSuccess) return bail(fail(TDGL_EDEVICE, "initialisation failed"));
     *out = c;

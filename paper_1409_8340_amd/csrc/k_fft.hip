@@ -87,34 +87,49 @@ __device__ __forceinline__ void dft<5>(float2 *v, float sign) {
     v[3] = csub(m2, j2);
 }
 
-constexpr int FFT_THREADS = 256;
+constexpr int FFT_THREADS = FFT_XY_THREADS;  // threads of the x and y passes
+constexpr int ZS_THREADS = 256;              // threads of the z solve (4 wavefronts)
 constexpr int FFT_MAXPTS = FFT_MAXN;  // points per work-group (all sequences)
+
+// q = floor(t / d) for 0 <= t < 2^20 and 1 <= d <= 2^13, from a float
+// reciprocal: (t + 1/2) / d stays at least 1/(2d) away from an integer,
+// far more than the rounding of the product.
+__device__ __forceinline__ int fdiv(int t, float inv_d) { return (int)(((float)t + 0.5f) * inv_d); }
 
 // One Stockham pass of radix R over `nseq` sequences of length n stored in
 // LDS at buf[s * sstride + e] (element e).  Ns = product of the radices of
-// the previous passes.
+// the previous passes.  tw[k] = exp(-2 pi i k / n) (conjugated for the
+// inverse transform, sign = +1).
 template <int R>
-__device__ void fft_pass(float2 *buf, int n, int Ns, int nseq, int sstride, float sign) {
+__device__ __forceinline__ void fft_pass(float2 *buf, int n, int Ns, int nseq, int sstride, const float2 *__restrict__ tw,
+                         float sign) {
     constexpr int MAXBF = (FFT_MAXPTS / R + FFT_THREADS - 1) / FFT_THREADS;
     const int nb = n / R;
     const int total = nb * nseq;
+    const float inv_nb = 1.0f / (float)nb, inv_ns = 1.0f / (float)Ns;
+    const int tstep = n / (Ns * R);
     float2 v[MAXBF][R];
     int dst[MAXBF];
 #pragma unroll
     for (int i = 0; i < MAXBF; ++i) {
         const int t = threadIdx.x + i * FFT_THREADS;
         if (t < total) {
-            const int s = t / nb, j = t - s * nb;
-            const int jm = j % Ns;
-            const float x = sign * 2.0f * (float)jm / (float)(Ns * R);
-            float2 *row = buf + s * sstride;
+            const int s = fdiv(t, inv_nb), j = t - s * nb;
+            const int jq = fdiv(j, inv_ns), jm = j - jq * Ns;
+            const float2 *row = buf + s * sstride;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const float2 a = row[j + r * nb];
-                v[i][r] = (r == 0 || jm == 0) ? a : cmul(a, expi_pi(x * r));
+                if (r == 0 || jm == 0) {
+                    v[i][r] = a;
+                } else {
+                    float2 w = tw[jm * r * tstep];
+                    w.y *= -sign;
+                    v[i][r] = cmul(a, w);
+                }
             }
             dft<R>(v[i], sign);
-            dst[i] = s * sstride + (j / Ns) * Ns * R + jm;
+            dst[i] = s * sstride + jq * Ns * R + jm;
         }
     }
     __syncthreads();
@@ -130,16 +145,27 @@ __device__ void fft_pass(float2 *buf, int n, int Ns, int nseq, int sstride, floa
 }
 
 // Full transform of nseq sequences in LDS (natural order in and out).
-__device__ void fft_lds(float2 *buf, int n, const int *rad, int nrad, int nseq, int sstride, float sign) {
+__device__ __forceinline__ void fft_lds(float2 *buf, int n, const int *rad, int nrad, int nseq, int sstride,
+                        const float2 *__restrict__ tw, float sign) {
     int Ns = 1;
     for (int p = 0; p < nrad; ++p) {
         const int R = rad[p];
-        if (R == 4) fft_pass<4>(buf, n, Ns, nseq, sstride, sign);
-        else if (R == 2) fft_pass<2>(buf, n, Ns, nseq, sstride, sign);
-        else if (R == 3) fft_pass<3>(buf, n, Ns, nseq, sstride, sign);
-        else fft_pass<5>(buf, n, Ns, nseq, sstride, sign);
+        if (R == 4) fft_pass<4>(buf, n, Ns, nseq, sstride, tw, sign);
+        else if (R == 2) fft_pass<2>(buf, n, Ns, nseq, sstride, tw, sign);
+        else if (R == 3) fft_pass<3>(buf, n, Ns, nseq, sstride, tw, sign);
+        else fft_pass<5>(buf, n, Ns, nseq, sstride, tw, sign);
         Ns *= R;
     }
+}
+
+// Coefficients of row k of the z system of column (kx, ky):
+//   a_k mu_{k-1} + b_k mu_k + c_k mu_{k+1} = d_k.
+// Face rows carry the doubled inner neighbour (Neumann reflection); the
+// singular (0, 0) column has row 0 replaced by mu_0 = 0.
+__device__ __forceinline__ void zrow(int k, int nz, double cz, bool singular, double &a, double &c) {
+    if (nz == 1 || (singular && k == 0)) { a = 0.0; c = 0.0; return; }
+    a = (k == 0) ? 0.0 : (k == nz - 1 ? 2.0 * cz : cz);
+    c = (k == nz - 1) ? 0.0 : (k == 0 ? 2.0 * cz : cz);
 }
 
 }  // namespace
@@ -154,6 +180,9 @@ __host__ __device__ int fft_y_cols(int ny) {
     int t = FFT_MAXPTS / ny;
     return t < 1 ? 1 : (t > 16 ? 16 : t);
 }
+// Row pitch (complex elements) of the half spectrum: nx/2 + 1 rounded up to
+// 16 elements, so that every row starts on a 128-byte line.
+__host__ __device__ int fft_pitch(int nx) { return (nx / 2 + 1 + 15) & ~15; }
 
 // Forward real-to-complex FFT along x of `in` (real rows of length nx) into
 // spec (nx/2+1 bins per row).  Two real rows a, b travel as one complex row
@@ -167,53 +196,54 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x(const Inst *__restrict__ 
     extern __shared__ float2 sm[];
     const int ii = find_inst(prefix, ninst, blockIdx.x);
     const Inst &I = insts[ii];
-    const int nx = I.nx, P = nx / 2 + 1;
+    const int nx = I.nx, P = nx / 2 + 1, sp = I.sp;
     const int rows = I.ny * I.nz;
     const int pairs = fft_x_pairs(nx);
     const int row0 = (blockIdx.x - prefix[ii]) * 2 * pairs;
     const float *in = in_ext ? in_ext : I.f;
     float *out = out_ext ? out_ext : I.mu;
     float2 *spec = I.spec;
+    const float inv_nx = 1.0f / (float)nx, inv_p = 1.0f / (float)P;
     // sequence s (pair) holds rows row0 + 2 s (real part) and row0 + 2 s + 1
     if (dir < 0) {
         for (int t = threadIdx.x; t < pairs * nx; t += FFT_THREADS) {
-            const int s = t / nx, e = t - s * nx;
+            const int s = fdiv(t, inv_nx), e = t - s * nx;
             const int ra = row0 + 2 * s, rb = ra + 1;
             const float a = ra < rows ? in[(size_t)ra * nx + e] : 0.f;
             const float b = rb < rows ? in[(size_t)rb * nx + e] : 0.f;
-            sm[s * nx + e] = make_float2(a, b);
+            sm[t] = make_float2(a, b);
         }
         __syncthreads();
-        fft_lds(sm, nx, I.xrad, I.nxrad, pairs, nx, -1.f);
+        fft_lds(sm, nx, I.xrad, I.nxrad, pairs, nx, I.twx, -1.f);
         for (int t = threadIdx.x; t < pairs * P; t += FFT_THREADS) {
-            const int s = t / P, k = t - s * P;
+            const int s = fdiv(t, inv_p), k = t - s * P;
             const float2 z = sm[s * nx + k];
             const float2 zc = sm[s * nx + (k == 0 ? 0 : nx - k)];
             // A = (z + conj zc)/2, B = (z - conj zc)/(2i)
             const float2 A = make_float2(0.5f * (z.x + zc.x), 0.5f * (z.y - zc.y));
             const float2 B = make_float2(0.5f * (z.y + zc.y), -0.5f * (z.x - zc.x));
             const int ra = row0 + 2 * s, rb = ra + 1;
-            if (ra < rows) spec[(size_t)ra * P + k] = A;
-            if (rb < rows) spec[(size_t)rb * P + k] = B;
+            if (ra < rows) spec[(size_t)ra * sp + k] = A;
+            if (rb < rows) spec[(size_t)rb * sp + k] = B;
         }
     } else {
         for (int t = threadIdx.x; t < pairs * nx; t += FFT_THREADS) {
-            const int s = t / nx, k = t - s * nx;
+            const int s = fdiv(t, inv_nx), k = t - s * nx;
             const int ra = row0 + 2 * s, rb = ra + 1;
             const bool lo = k < P;
             const int kk = lo ? k : nx - k;
-            float2 A = ra < rows ? spec[(size_t)ra * P + kk] : make_float2(0.f, 0.f);
-            float2 B = rb < rows ? spec[(size_t)rb * P + kk] : make_float2(0.f, 0.f);
+            float2 A = ra < rows ? spec[(size_t)ra * sp + kk] : make_float2(0.f, 0.f);
+            float2 B = rb < rows ? spec[(size_t)rb * sp + kk] : make_float2(0.f, 0.f);
             if (!lo) { A.y = -A.y; B.y = -B.y; }
             // W = A + i B
-            sm[s * nx + k] = make_float2(A.x - B.y, A.y + B.x);
+            sm[t] = make_float2(A.x - B.y, A.y + B.x);
         }
         __syncthreads();
-        fft_lds(sm, nx, I.xrad, I.nxrad, pairs, nx, +1.f);
+        fft_lds(sm, nx, I.xrad, I.nxrad, pairs, nx, I.twx, +1.f);
         for (int t = threadIdx.x; t < pairs * nx; t += FFT_THREADS) {
-            const int s = t / nx, e = t - s * nx;
+            const int s = fdiv(t, inv_nx), e = t - s * nx;
             const int ra = row0 + 2 * s, rb = ra + 1;
-            const float2 w = sm[s * nx + e];
+            const float2 w = sm[t];
             if (ra < rows) out[(size_t)ra * nx + e] = w.x;
             if (rb < rows) out[(size_t)rb * nx + e] = w.y;
         }
@@ -221,154 +251,138 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x(const Inst *__restrict__ 
 }
 
 // FFT along y of the half spectrum, forward (dir = -1) or inverse (+1):
-// a work-group takes TK consecutive kx at one z, all y.
+// a work-group takes TK consecutive kx at one z, all y.  Consecutive tiles
+// share 128-byte lines, so neighbouring logical tiles run on one XCD.
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(const Inst *__restrict__ insts,
                                                        const int *__restrict__ prefix, int ninst,
                                                        int dir) {
     extern __shared__ float2 sm[];
     const int ii = find_inst(prefix, ninst, blockIdx.x);
     const Inst &I = insts[ii];
-    const int nx = I.nx, ny = I.ny, P = nx / 2 + 1;
+    const int nx = I.nx, ny = I.ny, P = nx / 2 + 1, sp = I.sp;
     const int TK = fft_y_cols(ny);
     const int ntk = (P + TK - 1) / TK;
-    const int lb = blockIdx.x - prefix[ii];
+    const int nblk = prefix[ii + 1] - prefix[ii];
+    const int lb = xcd_remap(blockIdx.x - prefix[ii], nblk);
     const int z = lb / ntk, kx0 = (lb - z * ntk) * TK;
     const int tk = min(TK, P - kx0);
-    float2 *spec = I.spec + (size_t)z * ny * P;
+    float2 *spec = I.spec + (size_t)z * ny * sp;
+    const float inv_tk = 1.0f / (float)TK;
     for (int t = threadIdx.x; t < ny * TK; t += FFT_THREADS) {
-        const int y = t / TK, c = t - y * TK;
-        sm[c * ny + y] = c < tk ? spec[(size_t)y * P + kx0 + c] : make_float2(0.f, 0.f);
+        const int y = fdiv(t, inv_tk), c = t - y * TK;
+        sm[c * ny + y] = c < tk ? spec[(size_t)y * sp + kx0 + c] : make_float2(0.f, 0.f);
     }
     __syncthreads();
-    fft_lds(sm, ny, I.yrad, I.nyrad, TK, ny, (float)dir);
+    fft_lds(sm, ny, I.yrad, I.nyrad, TK, ny, I.twy, (float)dir);
     for (int t = threadIdx.x; t < ny * TK; t += FFT_THREADS) {
-        const int y = t / TK, c = t - y * TK;
-        if (c < tk) spec[(size_t)y * P + kx0 + c] = sm[c * ny + y];
+        const int y = fdiv(t, inv_tk), c = t - y * TK;
+        if (c < tk) spec[(size_t)y * sp + kx0 + c] = sm[c * ny + y];
     }
 }
 
-// The z systems, one per (kx, ky), by parallel cyclic reduction in double
-// precision.  A work-group loads a tile of ZTK consecutive kx at one ky and
-// all z; each wavefront then solves columns of the tile one at a time, its
-// 64 lanes owning rows k = lane + 64 i.  The result is scaled by 1/(nx ny)
-// (the two inverse FFTs are unnormalised).
+// Set-up of the spectral solver of instance `inst`: twiddle tables
+// exp(-2 pi i k / n) for x and y (FP64 arguments, rounded once to FP32), and
+// for every z system its Thomas pivots ip_k = 1 / (b_k - a_k c'_{k-1}),
+// c'_k = c_k ip_k, in FP64, stored column by column at ((ky P + kx) nz + k).
+// The operator does not change between steps, so this runs once.
+__global__ void k_fft_tables(const Inst *__restrict__ insts, int inst) {
+    const Inst &I = insts[inst];
+    const int nx = I.nx, ny = I.ny, nz = I.nz, P = nx / 2 + 1;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nx) {
+        double s, c;
+        sincospi(-2.0 * (double)t / (double)nx, &s, &c);
+        I.twx[t] = make_float2((float)c, (float)s);
+    }
+    if (t < ny) {
+        double s, c;
+        sincospi(-2.0 * (double)t / (double)ny, &s, &c);
+        I.twy[t] = make_float2((float)c, (float)s);
+    }
+    if (t < ny * P) {
+        const int ky = t / P, kx = t - ky * P;
+        const double cz = I.cz, cx = I.cx, cy = I.cy;
+        const double lam = cx * (2.0 - 2.0 * cospi(2.0 * kx / (double)nx)) +
+                           cy * (2.0 - 2.0 * cospi(2.0 * ky / (double)ny));
+        const bool singular = (kx == 0 && ky == 0);
+        double cprev = 0.0;
+        double *ip = I.zip + (size_t)t * nz;
+        for (int k = 0; k < nz; ++k) {
+            double a, c;
+            zrow(k, nz, cz, singular, a, c);
+            double b = (nz == 1) ? -lam : -(lam + 2.0 * cz);
+            if (singular && k == 0) b = 1.0;
+            const double p = 1.0 / (b - a * cprev);
+            ip[k] = p;
+            cprev = c * p;
+        }
+    }
+}
+
+// The z systems, one per (kx, ky), in double precision.  A work-group loads
+// a tile of ZTK consecutive kx at one ky and all z (coalesced rows); each
+// wavefront then solves the columns of the tile one at a time.  With the
+// pivots of the set-up, Thomas' two sweeps are first-order linear
+// recurrences,
+//   y_k = -a_k ip_k y_{k-1} + ip_k d_k,   mu_k = -c_k ip_k mu_{k+1} + y_k,
+// i.e. compositions of affine maps, which the 64 lanes evaluate as a
+// prefix scan (lane l owns rows l RPL .. l RPL + RPL - 1): compose the
+// lane's maps, scan the lane maps across the wavefront with shuffles, then
+// replay the rows from the lane's incoming value.  The result is scaled by
+// 1/(nx ny) (the two inverse FFTs are unnormalised).
 constexpr int ZTK = FFT_ZTK;
-constexpr int ZMAX = FFT_ZMAX;
-__global__ __launch_bounds__(FFT_THREADS) void k_fft_zsolve(const Inst *__restrict__ insts,
+constexpr int ZPAD = ZTK + 1;  // LDS row stride (float2): spreads the column reads over banks
+__host__ __device__ size_t fft_z_lds(int nz) { return (size_t)nz * ZPAD * sizeof(float2); }
+
+__global__ __launch_bounds__(ZS_THREADS) void k_fft_zsolve(const Inst *__restrict__ insts,
                                                             const int *__restrict__ prefix,
                                                             int ninst) {
-    __shared__ float2 tile[ZMAX * ZTK];
-    __shared__ double pa[4][ZMAX], pb[4][ZMAX], pc[4][ZMAX], pdr[4][ZMAX], pdi[4][ZMAX];
+    extern __shared__ float2 tile[];
     const int ii = find_inst(prefix, ninst, blockIdx.x);
     const Inst &I = insts[ii];
-    const int nx = I.nx, ny = I.ny, nz = I.nz, P = nx / 2 + 1;
+    const int nx = I.nx, ny = I.ny, nz = I.nz, P = nx / 2 + 1, sp = I.sp;
     const int ntk = (P + ZTK - 1) / ZTK;
     const int lb = blockIdx.x - prefix[ii];
     const int ky = lb / ntk, kx0 = (lb - ky * ntk) * ZTK;
     const int tk = min(ZTK, P - kx0);
-    const size_t zstride = (size_t)ny * P;
-    float2 *spec = I.spec + (size_t)ky * P + kx0;
-    for (int t = threadIdx.x; t < nz * ZTK; t += FFT_THREADS) {
+    const size_t zstride = (size_t)ny * sp;
+    float2 *spec = I.spec + (size_t)ky * sp + kx0;
+    for (int t = threadIdx.x; t < nz * ZTK; t += ZS_THREADS) {
         const int k = t / ZTK, c = t - k * ZTK;
-        tile[k * ZTK + c] = c < tk ? spec[(size_t)k * zstride + c] : make_float2(0.f, 0.f);
+        tile[k * ZPAD + c] = c < tk ? spec[(size_t)k * zstride + c] : make_float2(0.f, 0.f);
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const double cz = I.cz, cx = I.cx, cy = I.cy;
+    const double cz = I.cz;
     const double scale = 1.0 / ((double)nx * (double)ny);
-    const double lam_y = cy * (2.0 - 2.0 * cospi(2.0 * ky / (double)ny));
-    constexpr int RPL = ZMAX / 64;  // rows per lane
+    constexpr int RMAX = FFT_ZMAX / 64;
+    const int rpl = (nz + 63) >> 6;
+    const int k0 = lane * rpl;
     for (int c = w; c < tk; c += 4) {
         const int kx = kx0 + c;
-        const double lam = cx * (2.0 - 2.0 * cospi(2.0 * kx / (double)nx)) + lam_y;
         const bool singular = (kx == 0 && ky == 0);
-        double a[RPL], b[RPL], cc[RPL], dr[RPL], di[RPL];
-        // compatibility projection of the singular column
-        double mr = 0.0, mi = 0.0;
+        const double *ipc = I.zip + ((size_t)ky * P + kx) * nz;
+        double yr[RMAX], yi[RMAX], ip[RMAX];
+#pragma unroll
+        for (int q = 0; q < RMAX; ++q) {
+            const int k = k0 + q;
+            const bool ok = q < rpl && k < nz;
+            const float2 v = ok ? tile[k * ZPAD + c] : make_float2(0.f, 0.f);
+            yr[q] = v.x;
+            yi[q] = v.y;
+            ip[q] = ok ? ipc[k] : 0.0;
+        }
+        // the singular column: project the right side onto the range
+        // (zero weighted mean) and pin row 0
         if (singular) {
             double sr = 0.0, si = 0.0, sw = 0.0;
-            for (int k = lane; k < nz; k += 64) {
-                const double wk = (nz > 1 && (k == 0 || k == nz - 1)) ? 0.5 : 1.0;
-                const float2 v = tile[k * ZTK + c];
-                sr += wk * v.x;
-                si += wk * v.y;
-                sw += wk;
-            }
-            for (int o = 32; o > 0; o >>= 1) {
-                sr += __shfl_xor(sr, o, 64);
-                si += __shfl_xor(si, o, 64);
-                sw += __shfl_xor(sw, o, 64);
-            }
-            mr = sr / sw;
-            mi = si / sw;
-        }
 #pragma unroll
-        for (int q = 0; q < RPL; ++q) {
-            const int k = lane + 64 * q;
-            if (k < nz) {
-                const float2 v = tile[k * ZTK + c];
-                a[q] = (k == 0) ? 0.0 : (k == nz - 1 ? 2.0 * cz : cz);
-                cc[q] = (k == nz - 1) ? 0.0 : (k == 0 ? 2.0 * cz : cz);
-                b[q] = -(lam + 2.0 * cz);
-                dr[q] = (v.x - mr) * scale;
-                di[q] = (v.y - mi) * scale;
-                if (nz == 1) { a[q] = 0.0; cc[q] = 0.0; b[q] = -lam; }
-                if (singular && k == 0) { a[q] = 0.0; cc[q] = 0.0; b[q] = 1.0; dr[q] = 0.0; di[q] = 0.0; }
-            } else {
-                a[q] = 0.0; cc[q] = 0.0; b[q] = 1.0; dr[q] = 0.0; di[q] = 0.0;
-            }
-        }
-        for (int s = 1; s < nz; s <<= 1) {
-#pragma unroll
-            for (int q = 0; q < RPL; ++q) {
-                const int k = lane + 64 * q;
-                if (k < nz) { pa[w][k] = a[q]; pb[w][k] = b[q]; pc[w][k] = cc[q]; pdr[w][k] = dr[q]; pdi[w][k] = di[q]; }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-#pragma unroll
-            for (int q = 0; q < RPL; ++q) {
-                const int k = lane + 64 * q;
-                if (k < nz) {
-                    double na = 0.0, nc = 0.0, nb = b[q], ndr = dr[q], ndi = di[q];
-                    if (k - s >= 0) {
-                        const double al = -a[q] / pb[w][k - s];
-                        na = al * pa[w][k - s];
-                        nb += al * pc[w][k - s];
-                        ndr += al * pdr[w][k - s];
-                        ndi += al * pdi[w][k - s];
-                    }
-                    if (k + s < nz) {
-                        const double ga = -cc[q] / pb[w][k + s];
-                        nc = ga * pc[w][k + s];
-                        nb += ga * pa[w][k + s];
-                        ndr += ga * pdr[w][k + s];
-                        ndi += ga * pdi[w][k + s];
-                    }
-                    a[q] = na; cc[q] = nc; b[q] = nb; dr[q] = ndr; di[q] = ndi;
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        }
-        double xr[RPL], xi[RPL];
-#pragma unroll
-        for (int q = 0; q < RPL; ++q) {
-            xr[q] = dr[q] / b[q];
-            xi[q] = di[q] / b[q];
-        }
-        if (singular) {
-            // shift the constant mode to zero weighted mean
-            double sr = 0.0, si = 0.0, sw = 0.0;
-#pragma unroll
-            for (int q = 0; q < RPL; ++q) {
-                const int k = lane + 64 * q;
-                if (k < nz) {
+            for (int q = 0; q < RMAX; ++q) {
+                const int k = k0 + q;
+                if (q < rpl && k < nz) {
                     const double wk = (nz > 1 && (k == 0 || k == nz - 1)) ? 0.5 : 1.0;
-                    sr += wk * xr[q];
-                    si += wk * xi[q];
+                    sr += wk * yr[q];
+                    si += wk * yi[q];
                     sw += wk;
                 }
             }
@@ -378,21 +392,121 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_zsolve(const Inst *__restri
                 sw += __shfl_xor(sw, o, 64);
             }
 #pragma unroll
-            for (int q = 0; q < RPL; ++q) {
-                xr[q] -= sr / sw;
-                xi[q] -= si / sw;
+            for (int q = 0; q < RMAX; ++q) {
+                yr[q] -= sr / sw;
+                yi[q] -= si / sw;
+                if (k0 + q == 0) { yr[q] = 0.0; yi[q] = 0.0; }
+            }
+        }
+        // forward sweep: lane map y_out = A y_in + B
+        double A = 1.0, Br = 0.0, Bi = 0.0;
+#pragma unroll
+        for (int q = 0; q < RMAX; ++q) {
+            const int k = k0 + q;
+            if (q < rpl && k < nz) {
+                double a, cc;
+                zrow(k, nz, cz, singular, a, cc);
+                const double Ak = -a * ip[q], s = ip[q] * scale;
+                Br = Ak * Br + s * yr[q];
+                Bi = Ak * Bi + s * yi[q];
+                A = Ak * A;
+            }
+        }
+        for (int o = 1; o < 64; o <<= 1) {
+            const double pA = __shfl_up(A, o, 64), pr = __shfl_up(Br, o, 64), pi = __shfl_up(Bi, o, 64);
+            if (lane >= o) {
+                Br = A * pr + Br;
+                Bi = A * pi + Bi;
+                A = A * pA;
+            }
+        }
+        double ur = __shfl_up(Br, 1, 64), ui = __shfl_up(Bi, 1, 64);
+        if (lane == 0) { ur = 0.0; ui = 0.0; }
+#pragma unroll
+        for (int q = 0; q < RMAX; ++q) {
+            const int k = k0 + q;
+            if (q < rpl && k < nz) {
+                double a, cc;
+                zrow(k, nz, cz, singular, a, cc);
+                const double Ak = -a * ip[q], s = ip[q] * scale;
+                ur = Ak * ur + s * yr[q];
+                ui = Ak * ui + s * yi[q];
+                yr[q] = ur;
+                yi[q] = ui;
+            }
+        }
+        // backward sweep: lane map x_first = C x_in + D, x_in = mu of the
+        // next lane's first row
+        double C = 1.0, Dr = 0.0, Di = 0.0;
+#pragma unroll
+        for (int q = RMAX - 1; q >= 0; --q) {
+            const int k = k0 + q;
+            if (q < rpl && k < nz) {
+                double a, cc;
+                zrow(k, nz, cz, singular, a, cc);
+                const double Ck = -cc * ip[q];
+                Dr = Ck * Dr + yr[q];
+                Di = Ck * Di + yi[q];
+                C = Ck * C;
+            }
+        }
+        for (int o = 1; o < 64; o <<= 1) {
+            const double nC = __shfl_down(C, o, 64), nr = __shfl_down(Dr, o, 64), ni = __shfl_down(Di, o, 64);
+            if (lane + o < 64) {
+                Dr = C * nr + Dr;
+                Di = C * ni + Di;
+                C = C * nC;
+            }
+        }
+        double xr = __shfl_down(Dr, 1, 64), xi = __shfl_down(Di, 1, 64);
+        if (lane == 63) { xr = 0.0; xi = 0.0; }
+#pragma unroll
+        for (int q = RMAX - 1; q >= 0; --q) {
+            const int k = k0 + q;
+            if (q < rpl && k < nz) {
+                double a, cc;
+                zrow(k, nz, cz, singular, a, cc);
+                const double Ck = -cc * ip[q];
+                xr = Ck * xr + yr[q];
+                xi = Ck * xi + yi[q];
+                yr[q] = xr;
+                yi[q] = xi;
+            }
+        }
+        if (singular) {
+            // shift the constant mode to zero weighted mean
+            double sr = 0.0, si = 0.0, sw = 0.0;
+#pragma unroll
+            for (int q = 0; q < RMAX; ++q) {
+                const int k = k0 + q;
+                if (q < rpl && k < nz) {
+                    const double wk = (nz > 1 && (k == 0 || k == nz - 1)) ? 0.5 : 1.0;
+                    sr += wk * yr[q];
+                    si += wk * yi[q];
+                    sw += wk;
+                }
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                sr += __shfl_xor(sr, o, 64);
+                si += __shfl_xor(si, o, 64);
+                sw += __shfl_xor(sw, o, 64);
+            }
+#pragma unroll
+            for (int q = 0; q < RMAX; ++q) {
+                yr[q] -= sr / sw;
+                yi[q] -= si / sw;
             }
         }
 #pragma unroll
-        for (int q = 0; q < RPL; ++q) {
-            const int k = lane + 64 * q;
-            if (k < nz) tile[k * ZTK + c] = make_float2((float)xr[q], (float)xi[q]);
+        for (int q = 0; q < RMAX; ++q) {
+            const int k = k0 + q;
+            if (q < rpl && k < nz) tile[k * ZPAD + c] = make_float2((float)yr[q], (float)yi[q]);
         }
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < nz * ZTK; t += FFT_THREADS) {
+    for (int t = threadIdx.x; t < nz * ZTK; t += ZS_THREADS) {
         const int k = t / ZTK, c = t - k * ZTK;
-        if (c < tk) spec[(size_t)k * zstride + c] = tile[k * ZTK + c];
+        if (c < tk) spec[(size_t)k * zstride + c] = tile[k * ZPAD + c];
     }
 }
 

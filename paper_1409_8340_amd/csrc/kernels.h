@@ -41,11 +41,15 @@ __global__ void k_fft_x(const Inst *insts, const int *prefix, int ninst, int dir
                         float *out_ext);
 __global__ void k_fft_y(const Inst *insts, const int *prefix, int ninst, int dir);
 __global__ void k_fft_zsolve(const Inst *insts, const int *prefix, int ninst);
+__global__ void k_fft_tables(const Inst *insts, int inst);
 __host__ __device__ int fft_x_pairs(int nx);
 __host__ __device__ int fft_y_cols(int ny);
+__host__ __device__ int fft_pitch(int nx);
+__host__ __device__ size_t fft_z_lds(int nz);
 constexpr int FFT_ZTK = 32;     // kx columns per work-group of the z solve
 constexpr int FFT_ZMAX = 256;   // largest nz of the spectral path
 constexpr int FFT_MAXN = 8192;  // points per work-group of the x and y passes
+constexpr int FFT_XY_THREADS = 1024;  // threads per work-group of the x and y passes
 
 __global__ void k_adj_save(const Inst *insts, float2 *dpsi, float *dmu, double *dK, int raw);
 __global__ void k_adj_load(const Inst *insts, const float2 *spsi, const float *smu, const double *sK);

@@ -124,7 +124,10 @@ struct Inst {
     int fft;             // 1: the Poisson equation is solved by FFT, 0: by multigrid
     int nxrad, nyrad;    // FFT radix plans along x and y
     int xrad[16], yrad[16];
-    float2 *spec;        // half spectrum, nz * ny * (nx/2 + 1)
+    float2 *spec;        // half spectrum, nz * ny rows of pitch sp >= nx/2 + 1
+    int sp;              // row pitch of spec (complex elements)
+    float2 *twx, *twy;   // twiddles exp(-2 pi i k / n) along x and y
+    double *zip;         // Thomas pivots of the z systems, ny * (nx/2 + 1) columns of nz
 };
 
 // ---------------------------------------------------------------------------

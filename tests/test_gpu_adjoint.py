@@ -31,7 +31,7 @@ def _make(name, **kw):
     c = CASES[name]
     shape = (c["nz"], c["ny"], c["nx"])
     case = Case(c["nx"], c["ny"], c["nz"], open_=c["open_"], Bz=c["Bz"], Bx=c.get("Bx", 0.0), J=0.06,
-                driven=True, tol=1e-12, max_iter=300, mu_tol=1e-7, mu_max_cycles=60, eps=_eps(shape, 31),
+                driven=True, tol=1e-12, max_iter=250, mu_tol=1e-7, mu_max_cycles=60, eps=_eps(shape, 31),
                 psi_seed=32, **kw)
     return case
 
