@@ -8,7 +8,8 @@ eps = -1 inside, +1 outside), x periodic, y quasi-periodic, z open,
 dt = 0.1, Jacobi stop max|r|^2 < 1e-8.  Synthetic seeded inputs.
 
 A step is one full pass of the method: assemble, Jacobi sweeps to the stop
-rule, J_av / K update, Poisson right side and multigrid solve.  W untimed
+rule, J_av / K update, Poisson right side and Poisson solve (spectral for
+this box).  The stencil tiling is chosen by tdgl_autotune during set-up.  W untimed
 warm-up steps are followed by K timed steps bracketed by device
 synchronisation.  value = nodes * K / seconds (cell-updates per second).
 
@@ -129,6 +130,7 @@ def adjoint_ratio(tdgl, inputs, torch, nsteps, ckpt, warmup):
     ckpt steps, both timed from the same state after warmup steps."""
     w = inputs.WORKLOADS["c4_adjoint_128x128x32"]
     s, _, _, _ = setup(w, tdgl, inputs, torch, w.tol, 0.0)
+    s.autotune()
     s.step(warmup, stats=False)
     torch.cuda.synchronize()
     psi, mu, sc = s.get_psi(), s.get_mu(), s.get_scalars()
@@ -184,6 +186,8 @@ def main():
     log(f"[bench] setting up {w.name} ({N} nodes)")
     s, Bz, used, frac = setup(w, tdgl, inputs, torch, w.tol, args.mu_rtol)
     log(f"[bench] B_eff={Bz:.6f} inclusions={used} fraction={frac}")
+    tiling = s.autotune()
+    log(f"[bench] stencil tiling {tiling}")
     if args.copy_calib_gib > 0:
         # one elementwise kernel that reads nb bytes and writes nb bytes
         nb = int(args.copy_calib_gib * (1 << 30)) // 4 * 4
@@ -262,6 +266,7 @@ def main():
         "config": {"workload": w.name, "grid": [w.nx, w.ny, w.nz], "h": w.h, "B_eff": Bz, "J": w.J,
                    "inclusions": used, "inclusion_fraction": frac, "tol": w.tol, "dt": w.dt,
                    "mu_tol": 1e-5, "mu_rtol": args.mu_rtol,
+                   "tiling": {"rows": tiling["rows"], "chunk": tiling["chunk"]},
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

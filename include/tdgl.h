@@ -74,8 +74,9 @@ typedef struct tdgl_params {
     int mu_max_cycles;    /* multigrid cycle cap per step (1..TDGL_MAX_CYCLES) */
     int strict;           /* 1: tdgl_step returns TDGL_ENOCONV on a capped solve */
     int tile_cz;          /* z planes per stencil work-group; 0 = library default */
-    int tile_rows;        /* y rows per stencil thread: 0 (default 4), 2 or 4;
-                             every instance of a context must agree */
+    int tile_rows;        /* y rows per stencil thread: 0 (default 2), 1, 2 or 4;
+                             every instance of a context must agree
+                             (tdgl_autotune may change both tile fields) */
     int poisson;          /* 0: direct spectral solve where the box allows it
                              (periodic x and y, open z, sizes with factors 2,3,5),
                              multigrid otherwise; 1: always multigrid */
@@ -233,6 +234,30 @@ tdgl_status tdgl_observables(tdgl_ctx *ctx, int inst, tdgl_obs *obs);
  * The context must hold exactly one driven instance.  Overwrites the
  * instance's stored mu~ (the next step starts from this solution). */
 tdgl_status tdgl_poisson_solve(tdgl_ctx *ctx, const float *f, float *mu);
+
+/* Stencil tiling: work-groups of 64 x 4*rows grid columns marching through
+ * z runs of `chunk` planes. */
+typedef struct tdgl_tiling {
+    int rows;        /* rows of the tile per thread: 1, 2 or 4               */
+    int chunk;       /* z planes per work-group (instance 0 for tdgl_autotune) */
+    double sweep_us; /* measured time of one Jacobi sweep of the whole context
+                        (tdgl_autotune; 0 from tdgl_get_tiling)             */
+} tdgl_tiling;
+
+/* Picks the stencil tiling of the context by timing one Jacobi sweep for
+ * each candidate (rows in {1, 2, 4} x chunk in {heuristic, 4, 8, 16, 32,
+ * 64}) on the context's stream and keeping the fastest.  The timing sweeps
+ * read the current psi~ and b/M, (ht/2)/M arrays and write only the spare
+ * psi~ buffer, so the solver state is unchanged; results of later steps do
+ * not depend on the tiling beyond the summation order of FP64 partial sums.
+ * The choice is cached in the process per context shape (every instance's
+ * grid, boundary kinds and driven flag) and, when cache_path is not NULL,
+ * in that text file (read first, appended after a search).  No device
+ * allocation.  chosen may be NULL.  Synchronising. */
+tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *chosen);
+
+/* Current tiling of instance inst (rows are shared by the context). */
+tdgl_status tdgl_get_tiling(const tdgl_ctx *ctx, int inst, tdgl_tiling *out);
 
 /* Bytes of the caller-owned workspace tdgl_voltage_grad needs for nsteps
  * steps with a checkpoint every ckpt_every steps: ceil(nsteps/ckpt_every)

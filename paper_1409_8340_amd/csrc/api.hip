@@ -15,6 +15,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -273,8 +275,8 @@ tdgl_status validate(const tdgl_params &p, int idx) {
                         "multigrid (periodic axes need even sizes)", idx, kCoarsestMax);
     }
     if (p.tile_cz < 0 || p.tile_cz > 1024) return fail(TDGL_EINVAL, "instance %d: tile_cz out of range", idx);
-    if (p.tile_rows != 0 && p.tile_rows != 2 && p.tile_rows != 4)
-        return fail(TDGL_EINVAL, "instance %d: tile_rows must be 0, 2 or 4", idx);
+    if (p.tile_rows != 0 && p.tile_rows != 1 && p.tile_rows != 2 && p.tile_rows != 4)
+        return fail(TDGL_EINVAL, "instance %d: tile_rows must be 0, 1, 2 or 4", idx);
     if (p.strict != 0 && p.strict != 1) return fail(TDGL_EINVAL, "instance %d: strict must be 0 or 1", idx);
     for (size_t r = 0; r < sizeof(p.reserved) / sizeof(p.reserved[0]); ++r)
         if (p.reserved[r] != 0) return fail(TDGL_EINVAL, "instance %d: reserved fields must be zero", idx);
@@ -296,8 +298,13 @@ int auto_chunk(long tiles_xy, int nz, int req) {
 int ctx_rows(int n, const tdgl_params *params) {
     for (int i = 0; i < n; ++i)
         if (params[i].tile_rows) return params[i].tile_rows;
-    return 4;
+    return 2;
 }
+
+// Largest stencil grid of one instance over every tiling (one row per
+// thread, one-plane z runs): the partial-sum buffer is sized for it so that
+// re-tiling allocates nothing.
+long max_st_blocks(const tdgl_params &p) { return (long)cdiv(p.nx, TX) * cdiv(p.ny, 4) * p.nz; }
 
 // Carves one context's workspace.  With base == nullptr only sizes are
 // computed.  Fills the host copies of the device descriptors.
@@ -321,6 +328,20 @@ struct InstHost {
     int fx_blocks = 0, fy_blocks = 0, fz_blocks = 0;  // spectral Poisson passes
     double Bx = 0, Bz = 0, J = 0;
 };
+
+// Stencil tiling of one instance: work-groups of 64 x 4 rows columns
+// marching through z runs of `chunk` planes (chunk_req = 0: heuristic).
+void set_tiling(InstHost &h, int rows, int chunk_req) {
+    Inst &d = h.d;
+    const tdgl_params &p = h.p;
+    d.rows = rows;
+    d.tiles_x = cdiv(p.nx, TX);
+    d.tiles_y = cdiv(p.ny, 4 * rows);
+    const long txy = (long)d.tiles_x * d.tiles_y;
+    d.chunk = auto_chunk(txy, p.nz, chunk_req);
+    d.tiles_z = cdiv(p.nz, d.chunk);
+    h.st_blocks = (int)(txy * d.tiles_z);
+}
 
 }  // namespace
 
@@ -441,16 +462,9 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
         d.max_iter = p.max_iter;
         d.mu_max_cycles = p.driven ? p.mu_max_cycles : 1;
         // stencil tiling
-        const int rows = ctx_rows(n, params);
-        d.rows = rows;
-        const long txy = (long)cdiv(p.nx, TX) * cdiv(p.ny, 4 * rows);
-        d.tiles_x = cdiv(p.nx, TX);
-        d.tiles_y = cdiv(p.ny, 4 * rows);
-        d.chunk = auto_chunk(txy, p.nz, p.tile_cz);
-        d.tiles_z = cdiv(p.nz, d.chunk);
-        h.st_blocks = (int)(txy * d.tiles_z);
+        set_tiling(h, ctx_rows(n, params), p.tile_cz);
         h.flat_blocks = cdiv(N, 256L * JAV_CPT);
-        int part_cap = std::max(h.st_blocks, h.flat_blocks);
+        int part_cap = (int)std::max<long>(max_st_blocks(p), h.flat_blocks);
         // multigrid
         if (p.driven) {
             h.H = build_hierarchy(p);
@@ -683,7 +697,10 @@ struct ProfScope {
 // Launch one stencil pass over every instance with the context's tile.
 template <int MODE>
 void launch_stencil(tdgl_ctx *c, int l, const float2 *in = nullptr, float2 *out = nullptr) {
-    if (c->rows == 2)
+    if (c->rows == 1)
+        hipLaunchKernelGGL((k_stencil<MODE, 1>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst, c->d_pref_st,
+                           c->n, l, in, out);
+    else if (c->rows == 2)
         hipLaunchKernelGGL((k_stencil<MODE, 2>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst, c->d_pref_st,
                            c->n, l, in, out);
     else
@@ -1248,6 +1265,162 @@ tdgl_status tdgl_poisson_solve(tdgl_ctx *ctx, const float *f, float *mu) {
     if (e) return e;
     hipLaunchKernelGGL(k_mu_io, dim3(fill_grid(d.N)), dim3(256), 0, s, ctx->d_inst, 0, mu, 1);
     LAUNCHCHK();
+    return TDGL_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Re-uploads what a change of stencil tiling touches: the instance
+// descriptors and the stencil prefix and partial-count tables.  The stream
+// must be idle.
+tdgl_status upload_tiling(tdgl_ctx *ctx) {
+    const int n = ctx->n;
+    std::vector<int> ps(n + 1, 0), nps(n);
+    std::vector<Inst> di(n);
+    for (int i = 0; i < n; ++i) {
+        ps[i + 1] = ps[i] + ctx->inst[i].st_blocks;
+        nps[i] = ctx->inst[i].st_blocks;
+        di[i] = ctx->inst[i].d;
+    }
+    HIPCHK(hipMemcpy(ctx->d_pref_st, ps.data(), (n + 1) * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_np_st, nps.data(), n * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_inst, di.data(), n * sizeof(Inst), hipMemcpyHostToDevice));
+    ctx->tot_st = ps[n];
+    return TDGL_OK;
+}
+
+struct Tiling {
+    int rows = 2;
+    int chunk = 0;  // 0: heuristic
+};
+
+tdgl_status apply_tiling(tdgl_ctx *ctx, const Tiling &t) {
+    ctx->rows = t.rows;
+    for (auto &h : ctx->inst) set_tiling(h, t.rows, t.chunk);
+    return upload_tiling(ctx);
+}
+
+// Key of a context's shape for the tiling cache: every instance's grid,
+// boundary kinds and driven flag.
+std::string tiling_key(const tdgl_ctx *ctx) {
+    std::string k;
+    char buf[96];
+    for (const auto &h : ctx->inst) {
+        snprintf(buf, sizeof buf, "%dx%dx%d/%d%d%d/%d;", h.p.nx, h.p.ny, h.p.nz, h.p.bc[0], h.p.bc[1], h.p.bc[2],
+                 h.p.driven);
+        k += buf;
+    }
+    return k;
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<Tiling, double>> g_tune_cache;
+
+bool tune_file_lookup(const char *path, const std::string &key, Tiling *t, double *us) {
+    if (!path) return false;
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char line[4096];
+    bool found = false;
+    while (fgets(line, sizeof line, f)) {
+        char k[4000];
+        int r, c;
+        double u;
+        if (sscanf(line, "%3999s %d %d %lf", k, &r, &c, &u) == 4 && key == k && (r == 1 || r == 2 || r == 4) &&
+            c >= 0) {
+            t->rows = r;
+            t->chunk = c;
+            *us = u;
+            found = true;  // the last entry wins
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+}  // namespace
+
+extern "C" {
+
+tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *chosen) {
+    if (!ctx) return fail(TDGL_EINVAL, "null context");
+    hipStream_t s = ctx->stream;
+    HIPCHK(hipStreamSynchronize(s));
+    const std::string key = tiling_key(ctx);
+    Tiling best;
+    double best_us = 0.0;
+    bool have = false;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            best = it->second.first;
+            best_us = it->second.second;
+            have = true;
+        }
+    }
+    if (!have) have = tune_file_lookup(cache_path, key, &best, &best_us);
+    if (!have) {
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        const int chunks[] = {0, 4, 8, 16, 32, 64};
+        const int rows[] = {1, 2, 4};
+        best_us = 1e300;
+        for (int r : rows)
+            for (int c : chunks) {
+                Tiling t;
+                t.rows = r;
+                t.chunk = c;
+                tdgl_status e = apply_tiling(ctx, t);
+                if (e) return e;
+                launch_stencil<MODE_SWEEP>(ctx, -1);  // warm-up
+                HIPCHK(hipEventRecord(e0, s));
+                const int reps = 4;
+                for (int q = 0; q < reps; ++q) launch_stencil<MODE_SWEEP>(ctx, -1);
+                HIPCHK(hipEventRecord(e1, s));
+                LAUNCHCHK();
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                const double us = 1e3 * ms / reps;
+                if (us < best_us) {
+                    best_us = us;
+                    best = t;
+                }
+            }
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        if (cache_path) {
+            FILE *f = fopen(cache_path, "a");
+            if (f) {
+                fprintf(f, "%s %d %d %.3f\n", key.c_str(), best.rows, best.chunk, best_us);
+                fclose(f);
+            }
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = {best, best_us};
+    }
+    tdgl_status e = apply_tiling(ctx, best);
+    if (e) return e;
+    if (chosen) {
+        chosen->rows = best.rows;
+        chosen->chunk = ctx->inst[0].d.chunk;
+        chosen->sweep_us = best_us;
+    }
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_get_tiling(const tdgl_ctx *ctx, int inst, tdgl_tiling *out) {
+    if (!ctx || !out) return fail(TDGL_EINVAL, "null argument");
+    if (inst < 0 || inst >= ctx->n) return fail(TDGL_EINVAL, "instance %d out of range", inst);
+    out->rows = ctx->rows;
+    out->chunk = ctx->inst[inst].d.chunk;
+    out->sweep_us = 0.0;
     return TDGL_OK;
 }
 

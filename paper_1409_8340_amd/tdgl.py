@@ -72,6 +72,13 @@ class Obs(ctypes.Structure):
 KERNEL_CLASSES = ["assemble", "sweep", "current", "rhs", "mg_fine", "mg_coarse", "other"]
 
 
+class Tiling(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int), ("chunk", ctypes.c_int), ("sweep_us", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class Prof(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_longlong * 7), ("ms", ctypes.c_double * 7)]
 
@@ -114,6 +121,8 @@ _SIGS = {
                           ctypes.c_int),
     "tdgl_voltage_grad": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                           ctypes.c_size_t, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p], ctypes.c_int),
+    "tdgl_autotune": ([ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(Tiling)], ctypes.c_int),
+    "tdgl_get_tiling": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(Tiling)], ctypes.c_int),
     "tdgl_profile_start": ([ctypes.c_void_p, ctypes.c_uint], ctypes.c_int),
     "tdgl_profile_stop": ([ctypes.c_void_p, ctypes.POINTER(Prof)], ctypes.c_int),
 }
@@ -314,6 +323,18 @@ class Solver:
                                          self._dev(out, torch.float32)))
         self._stream.synchronize()
         return out
+
+    def autotune(self, cache_path=None):
+        """Pick the stencil tiling by timing (tdgl_autotune); returns it."""
+        t = Tiling()
+        path = None if cache_path is None else str(cache_path).encode()
+        _check(load().tdgl_autotune(self._ctx, path, ctypes.byref(t)))
+        return t.as_dict()
+
+    def tiling(self, inst=0):
+        t = Tiling()
+        _check(load().tdgl_get_tiling(self._ctx, inst, ctypes.byref(t)))
+        return t.as_dict()
 
     def voltage_grad(self, nsteps, window_begin=0, ckpt_every=50):
         """(Vbar, dVbar/deps) over nsteps steps; see tdgl_voltage_grad."""

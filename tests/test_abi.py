@@ -48,6 +48,9 @@ def test_plan_sizes_grow_with_grid(lib):
     (dict(driven=True, bc=(1, 0, 1)), "periodic x"),
     (dict(driven=True, mu_tol=0.0), "mu_tol"),
     (dict(driven=True, nx=30, ny=30, nz=31), None),   # coarsens fine (even periodic)
+    (dict(tile_rows=3), "tile_rows"),
+    (dict(tile_rows=1), None),
+    (dict(tile_cz=-1), "tile_cz"),
 ])
 def test_plan_validation(lib, kw, msg):
     base = dict(nx=32, ny=32, nz=16)

@@ -154,6 +154,41 @@ def test_batch_matches_single_instances():
     b.close()
 
 
+def test_autotune_keeps_state_and_results(tmp_path):
+    """tdgl_autotune leaves the state alone, picks a valid tiling, and later
+    steps match a context with the default tiling (the per-node arithmetic
+    does not depend on the tiling); a second context of the same shape takes
+    the choice from the cache file."""
+    cases = [Case(48, 40, 12, Bz=0.2, tol=1e-10, psi_seed=2, driven=True, J=0.01),
+             Case(64, 16, 20, Bz=0.05, tol=1e-10, psi_seed=3, driven=True, J=0.03, open_=(False, True, True))]
+    ref = []
+    for c in cases:
+        s = c.solver()
+        s.step(3)
+        ref.append(s.get_psi().cpu().numpy())
+        s.close()
+    b = tdgl.Solver([c.params for c in cases])
+    for i, c in enumerate(cases):
+        c.load_into(b, i)
+    before = [b.get_psi(i).cpu().numpy() for i in range(2)]
+    path = tmp_path / "tiles.txt"
+    t = b.autotune(path)
+    print("[autotune]", t, b.tiling(1))
+    assert t["rows"] in (1, 2, 4) and t["chunk"] >= 1 and t["sweep_us"] > 0
+    for i in range(2):
+        assert np.array_equal(b.get_psi(i).cpu().numpy(), before[i])
+    b.step(3)
+    for i in range(2):
+        assert rel_maxerr(b.get_psi(i).cpu().numpy(), ref[i]) <= 1e-6, i
+    b.close()
+    assert path.read_text().count("\n") == 1
+    b2 = tdgl.Solver([c.params for c in cases])
+    t2 = b2.autotune(path)
+    assert (t2["rows"], t2["chunk"]) == (t["rows"], t["chunk"])
+    b2.close()
+    assert path.read_text().count("\n") == 1
+
+
 @pytest.mark.parametrize("shape,open_,solver", [
     ((64, 64, 16), (False, False, True), 0),    # spectral, radix 4
     ((96, 48, 12), (False, False, True), 0),    # spectral, radix 3
