@@ -153,6 +153,65 @@ def adjoint_ratio(tdgl, inputs, torch, nsteps, ckpt, warmup):
             "ratio": t_adj / t_fwd, "Vbar": v, "grad_l2": gn}
 
 
+def batch_bench(tdgl, inputs, torch, steps, warmup, n=64):
+    """Batched form against single-instance steps on the same GPU: n
+    instances with shapes drawn from {64^3, 96x96x48, 128x128x32}, per
+    instance B, J, inclusion diameter and fraction, in one context advanced
+    by graph-replayed steps (one captured launch sequence per step for all
+    instances); then the same instances, each in its own context, advanced by
+    plain tdgl_step from the same state.  Rates are nodes x steps / s."""
+    ws = inputs.batch_workloads(n)
+    params = [tdgl.make_params(w.nx, w.ny, w.nz, h=w.h, driven=True, tol=w.tol, max_iter=100,
+                               mu_tol=1e-5, mu_rtol=0.03) for w in ws]
+
+    def load(s, i, w, inst):
+        s.set_field(0.0, w.B, inst=inst, quantize=True)
+        s.set_current(w.J, inst=inst)
+        cen, dia = inputs.candidates_for(w)
+        s.gen_inclusions(cen, dia, w.fraction, w.eps_in, w.eps_out, inst=inst)
+        s.set_psi(torch.from_numpy(inputs.psi_init(w.nx, w.ny, w.nz, w.psi_seed)).cuda(), inst=inst)
+
+    nodes = sum(w.nx * w.ny * w.nz for w in ws)
+    b = tdgl.Solver(params)
+    for i, w in enumerate(ws):
+        load(b, i, w, i)
+    tiling = b.autotune()
+    wst = b.step(warmup, stats=True)
+    budget = min(100, wst["sweeps_max"] + max(4, wst["sweeps_max"] // 2))
+    states = [(b.get_psi(i), b.get_mu(i), b.get_scalars(i)) for i in range(n)]
+    b.step_graph(1, budget, stats=False)  # capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = b.step_graph(steps, budget, stats=True)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    b.close()
+    t_s = 0.0
+    sweeps_s = 0
+    for i, w in enumerate(ws):
+        s = tdgl.Solver([params[i]])
+        load(s, i, w, 0)
+        s.autotune()
+        s.set_psi(states[i][0])
+        s.set_mu(states[i][1])
+        s.set_scalars(states[i][2])
+        s.step(1, stats=False)
+        # the comparison starts one step later than the batch: the same work
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ss = s.step(steps, stats=True)
+        torch.cuda.synchronize()
+        t_s += time.perf_counter() - t0
+        sweeps_s += ss["sweeps_sum"]
+        s.close()
+    return {"instances": n, "nodes": nodes, "steps": steps, "warmup": warmup, "sweep_budget": budget,
+            "tiling": {"rows": tiling["rows"], "chunk": tiling["chunk"]},
+            "batched_rate": nodes * steps / t_b, "batched_ms_per_step": 1e3 * t_b / steps,
+            "sequential_rate": nodes * steps / t_s, "sequential_ms_per_step": 1e3 * t_s / steps,
+            "speedup": t_s / t_b, "batched_sweeps_sum": st["sweeps_sum"], "capped_steps": st["capped_steps"],
+            "sequential_sweeps_sum": sweeps_s}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,6 +226,8 @@ def main():
                     help="Poisson stop: residual below max(1e-5, mu_rtol * initial residual)")
     ap.add_argument("--adjoint-steps", type=int, default=500,
                     help="steps of the c4 forward+adjoint comparison (0 skips it)")
+    ap.add_argument("--batch-steps", type=int, default=20,
+                    help="steps of the 64-instance batched comparison (0 skips it)")
     ap.add_argument("--copy-calib-gib", type=float, default=0.0,
                     help="run a plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -244,6 +305,13 @@ def main():
         adj = adjoint_ratio(tdgl, inputs, torch, args.adjoint_steps, 50, 100)
         log(f"[bench] adjoint ratio {adj['ratio']:.3f}")
 
+    batch = None
+    if args.batch_steps > 0:
+        log(f"[bench] 64-instance batch over {args.batch_steps} steps")
+        batch = batch_bench(tdgl, inputs, torch, args.batch_steps, 10)
+        log(f"[bench] batch {batch['batched_rate']:.3e} vs sequential {batch['sequential_rate']:.3e} "
+            f"cell-updates/s (x{batch['speedup']:.2f})")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a bounded sample")
@@ -282,6 +350,7 @@ def main():
             "assemble_GBps": ASSEMBLE_BYTES_PER_NODE * N / (asm_ms * 1e-3) / 1e9,
             "kernel_breakdown": breakdown,
             "adjoint": adj,
+            "batch": batch,
             "E_mean": obs["E_mean"], "F": obs["F"], "psi2_mean": obs["psi2_mean"],
             "kernel_source_sha": kernel_sha(),
         },

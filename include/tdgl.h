@@ -226,6 +226,22 @@ tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats);
  * Synchronising. */
 tdgl_status tdgl_observables(tdgl_ctx *ctx, int inst, tdgl_obs *obs);
 
+/* Advances every instance by nsteps steps exactly as tdgl_step does, as
+ * replays of one captured HIP graph per step: the step is issued as a fixed
+ * sequence -- the assemble kernel, budget - 1 Jacobi sweep launches (a sweep
+ * whose instance has already met the tolerance exits at once), the current,
+ * K and Poisson right side, and the Poisson solve with every multigrid cycle
+ * launched (converged or capped instances skip the rest) -- so no step waits
+ * on the host.  A solve that needs more than `budget` sweeps (1 <= budget <=
+ * the largest max_iter) stops there and counts as capped; with budget >= the
+ * sweeps a solve needs, results are bit-identical to tdgl_step.  The graph is
+ * captured on a private stream on the first call (and again after the
+ * budget or the tiling changes) and launched on the context's stream.
+ * stats (nullable; makes the call synchronising) come from counters kept on
+ * the device.  Not available while per-kernel profiling is active
+ * (TDGL_ESTATE). */
+tdgl_status tdgl_step_graph(tdgl_ctx *ctx, int nsteps, int budget, tdgl_step_stats *stats);
+
 /* Solves the Poisson equation of Sec. 3.2, Delta_h mu = f (7-point stencil,
  * plain wrap on periodic axes, Neumann reflection on open faces), for a
  * given right side with the instance's solver (spectral or multigrid, as

@@ -380,7 +380,13 @@ struct tdgl_ctx {
     bool any_fft = false, any_mg = false;
     bool any_driven = false;
     int max_iter = 1, max_cycles = 1;
-    int rows = 4;  // stencil rows per thread
+    int rows = 2;  // stencil rows per thread
+    // captured step of tdgl_step_graph (rebuilt when the budget or the
+    // tiling changes)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_budget = 0;
+    hipStream_t cap_stream = nullptr;  // private stream the step is captured on
     // per-kernel-class timing (tdgl_profile_start/stop)
     unsigned prof_mask = 0;
     std::vector<hipEvent_t> prof_pool;
@@ -800,7 +806,8 @@ tdgl_status jacobi_loop(tdgl_ctx *ctx, tdgl_step_stats *acc, bool *strict_fail, 
     }
     {
         ProfScope ps(ctx, TDGL_K_OTHER);
-        hipLaunchKernelGGL(k_solve_finalize, dim3(cdiv(n, 64)), dim3(64), 0, s, ctx->d_inst, n, count_step);
+        hipLaunchKernelGGL(k_solve_finalize, dim3(cdiv(n, 64)), dim3(64), 0, s, ctx->d_inst, n, count_step,
+                           launched);
     }
     LAUNCHCHK();
     for (int i = 0; acc && i < n; ++i) {
@@ -825,26 +832,34 @@ tdgl_status jacobi_loop(tdgl_ctx *ctx, tdgl_step_stats *acc, bool *strict_fail, 
 // instances take the five FFT / z-solve passes; multigrid instances take
 // V-cycles until their stop rule, decided on the device and polled by the
 // host one cycle behind.  Statistics are accumulated into acc.
+// The five passes of the spectral solve for every instance that uses it.
+tdgl_status enqueue_fft(tdgl_ctx *ctx) {
+    if (!ctx->any_fft) return TDGL_OK;
+    const int n = ctx->n;
+    hipStream_t s = ctx->stream;
+    ProfScope ps(ctx, TDGL_K_MG_FINE);
+    const float *nf = nullptr;
+    float *nm = nullptr;
+    hipLaunchKernelGGL(k_fft_x, dim3(std::max(ctx->tot_fx, 1)), dim3(FFT_XY_THREADS), ctx->fx_lds, s, ctx->d_inst,
+                       ctx->d_pref_fx, n, -1, nf, nm);
+    hipLaunchKernelGGL(k_fft_y, dim3(std::max(ctx->tot_fy, 1)), dim3(FFT_XY_THREADS), ctx->fy_lds, s, ctx->d_inst,
+                       ctx->d_pref_fy, n, -1);
+    hipLaunchKernelGGL(k_fft_zsolve, dim3(std::max(ctx->tot_fz, 1)), dim3(256), ctx->fz_lds, s, ctx->d_inst,
+                       ctx->d_pref_fz, n);
+    hipLaunchKernelGGL(k_fft_y, dim3(std::max(ctx->tot_fy, 1)), dim3(FFT_XY_THREADS), ctx->fy_lds, s, ctx->d_inst,
+                       ctx->d_pref_fy, n, +1);
+    hipLaunchKernelGGL(k_fft_x, dim3(std::max(ctx->tot_fx, 1)), dim3(FFT_XY_THREADS), ctx->fx_lds, s, ctx->d_inst,
+                       ctx->d_pref_fx, n, +1, nf, nm);
+    LAUNCHCHK();
+    return TDGL_OK;
+}
+
 tdgl_status enqueue_poisson(tdgl_ctx *ctx, tdgl_step_stats *acc) {
     const int n = ctx->n;
     hipStream_t s = ctx->stream;
     const size_t RW = ctx->row_words();
-    if (ctx->any_fft) {
-        ProfScope ps(ctx, TDGL_K_MG_FINE);
-        const float *nf = nullptr;
-        float *nm = nullptr;
-        hipLaunchKernelGGL(k_fft_x, dim3(std::max(ctx->tot_fx, 1)), dim3(FFT_XY_THREADS), ctx->fx_lds, s, ctx->d_inst,
-                           ctx->d_pref_fx, n, -1, nf, nm);
-        hipLaunchKernelGGL(k_fft_y, dim3(std::max(ctx->tot_fy, 1)), dim3(FFT_XY_THREADS), ctx->fy_lds, s, ctx->d_inst,
-                           ctx->d_pref_fy, n, -1);
-        hipLaunchKernelGGL(k_fft_zsolve, dim3(std::max(ctx->tot_fz, 1)), dim3(256), ctx->fz_lds, s, ctx->d_inst,
-                           ctx->d_pref_fz, n);
-        hipLaunchKernelGGL(k_fft_y, dim3(std::max(ctx->tot_fy, 1)), dim3(FFT_XY_THREADS), ctx->fy_lds, s, ctx->d_inst,
-                           ctx->d_pref_fy, n, +1);
-        hipLaunchKernelGGL(k_fft_x, dim3(std::max(ctx->tot_fx, 1)), dim3(FFT_XY_THREADS), ctx->fx_lds, s, ctx->d_inst,
-                           ctx->d_pref_fx, n, +1, nf, nm);
-        LAUNCHCHK();
-    }
+    tdgl_status fe = enqueue_fft(ctx);
+    if (fe) return fe;
     std::vector<int> mconv_at(n, 0);
     if (ctx->any_mg) {
         int mrem = 0;
@@ -880,7 +895,8 @@ tdgl_status enqueue_poisson(tdgl_ctx *ctx, tdgl_step_stats *acc) {
     }
     {
         ProfScope ps(ctx, TDGL_K_OTHER);
-        if (ctx->any_mg) hipLaunchKernelGGL(k_mg_finalize, dim3(cdiv(n, 64)), dim3(64), 0, s, ctx->d_inst, n);
+        if (ctx->any_mg)
+            hipLaunchKernelGGL(k_mg_finalize, dim3(cdiv(n, 64)), dim3(64), 0, s, ctx->d_inst, n, acc ? 1 : 0);
         hipLaunchKernelGGL(k_mu_mean_partial, dim3(std::max(ctx->tot_mg[0], 1)), dim3(256), 0, s, ctx->d_inst,
                            pref_mg(ctx, 0), n, 0);
         hipLaunchKernelGGL(k_reduce_to_state, dim3(n), dim3(256), 0, s, ctx->d_inst, ctx->d_np_mg0, 1, 1);
@@ -899,6 +915,50 @@ tdgl_status enqueue_poisson(tdgl_ctx *ctx, tdgl_step_stats *acc) {
             acc->mu_last_res = r;
         }
     }
+    return TDGL_OK;
+}
+
+// Releases the captured step (after a change of the launch sequence).
+void drop_graph(tdgl_ctx *ctx) {
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->graph_exec = nullptr;
+    ctx->graph = nullptr;
+    ctx->graph_budget = 0;
+}
+
+// One whole step of every instance as a fixed launch sequence with no host
+// synchronisation, for graph capture: the assemble kernel and budget - 1
+// sweep launches (a launch whose instance has converged or reached its cap
+// exits at once; the finalize kernel picks the first converged sweep), the
+// current and K update, the Poisson right side and a solve with every
+// multigrid cycle launched (each instance's cycles stop by themselves).
+tdgl_status enqueue_step_fixed(tdgl_ctx *ctx, int budget) {
+    const int n = ctx->n;
+    hipStream_t s = ctx->stream;
+    launch_stencil<MODE_FIRST>(ctx, 0);
+    for (int l = 1; l < budget; ++l) launch_stencil<MODE_SWEEP>(ctx, l);
+    hipLaunchKernelGGL(k_solve_finalize, dim3(cdiv(n, 64)), dim3(64), 0, s, ctx->d_inst, n, 1, budget);
+    LAUNCHCHK();
+    if (!ctx->any_driven) return TDGL_OK;
+    hipLaunchKernelGGL(k_jav_partial, dim3(ctx->tot_flat), dim3(256), 0, s, ctx->d_inst, ctx->d_pref_flat, n);
+    hipLaunchKernelGGL(k_kupdate, dim3(n), dim3(256), 0, s, ctx->d_inst, ctx->d_np_flat);
+    launch_stencil<MODE_RHS>(ctx, 0);
+    hipLaunchKernelGGL(k_reduce_to_state, dim3(n), dim3(256), 0, s, ctx->d_inst, ctx->d_np_st, 0, 1);
+    LAUNCHCHK();
+    tdgl_status e = enqueue_fft(ctx);
+    if (e) return e;
+    if (ctx->any_mg) {
+        for (int cyc = 0; cyc < ctx->max_cycles; ++cyc) {
+            e = enqueue_vcycle(ctx, cyc);
+            if (e) return e;
+        }
+        hipLaunchKernelGGL(k_mg_finalize, dim3(cdiv(n, 64)), dim3(64), 0, s, ctx->d_inst, n, 1);
+    }
+    hipLaunchKernelGGL(k_mu_mean_partial, dim3(std::max(ctx->tot_mg[0], 1)), dim3(256), 0, s, ctx->d_inst,
+                       pref_mg(ctx, 0), n, 0);
+    hipLaunchKernelGGL(k_reduce_to_state, dim3(n), dim3(256), 0, s, ctx->d_inst, ctx->d_np_mg0, 1, 1);
+    LAUNCHCHK();
     return TDGL_OK;
 }
 
@@ -974,6 +1034,7 @@ tdgl_status tdgl_create(int n, const tdgl_params *params, void *ws, size_t ws_by
                 hipLaunchKernelGGL(k_fill_f, dim3(fill_grid(L.N)), dim3(256), 0, st, L.r, (long)L.N, 0.f);
             }
         HIPCHK(hipMemsetAsync(d.st, 0, sizeof(DevState), st));
+        hipLaunchKernelGGL(k_acc_reset, dim3(1), dim3(64), 0, st, c->d_inst + i, 1);
         hipLaunchKernelGGL(k_state_set, dim3(1), dim3(1), 0, st, c->d_inst, i, 11, 1.0);  // in window
     }
     hipLaunchKernelGGL(k_fill_u, dim3(64), dim3(256), 0, st, c->d_res, (long)(c->max_iter * c->row_words()), 0u);
@@ -998,6 +1059,9 @@ tdgl_status tdgl_destroy(tdgl_ctx *ctx) {
     for (auto &e : ctx->ev) if (e) (void)hipEventDestroy(e);
     for (auto &e : ctx->evc) if (e) (void)hipEventDestroy(e);
     for (auto &e : ctx->prof_pool) if (e) (void)hipEventDestroy(e);
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->h_res) (void)hipHostFree(ctx->h_res);
     if (ctx->h_mures) (void)hipHostFree(ctx->h_mures);
     delete ctx;
@@ -1248,6 +1312,72 @@ tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats) {
     return TDGL_OK;
 }
 
+tdgl_status tdgl_step_graph(tdgl_ctx *ctx, int nsteps, int budget, tdgl_step_stats *stats) {
+    if (!ctx) return fail(TDGL_EINVAL, "null context");
+    if (nsteps < 0) return fail(TDGL_EINVAL, "nsteps must be >= 0");
+    if (budget < 1 || budget > ctx->max_iter)
+        return fail(TDGL_EINVAL, "sweep budget must be in [1, %d] (the largest max_iter)", ctx->max_iter);
+    if (ctx->prof_mask)
+        return fail(TDGL_ESTATE, "per-kernel profiling is active; graph-replayed steps are not profiled");
+    const int n = ctx->n;
+    hipStream_t s = ctx->stream;
+    if (!ctx->graph_exec || ctx->graph_budget != budget) {
+        drop_graph(ctx);
+        if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+        HIPCHK(hipStreamSynchronize(s));
+        ctx->stream = ctx->cap_stream;
+        hipError_t be = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (be != hipSuccess) {
+            ctx->stream = s;
+            return fail(TDGL_EDEVICE, "hipStreamBeginCapture failed: %s", hipGetErrorString(be));
+        }
+        tdgl_status e = enqueue_step_fixed(ctx, budget);
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &g);
+        ctx->stream = s;
+        if (e || ce != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return e ? e : fail(TDGL_EDEVICE, "step capture failed: %s", hipGetErrorString(ce));
+        }
+        hipGraphExec_t ge = nullptr;
+        const hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return fail(TDGL_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(ie));
+        }
+        ctx->graph = g;
+        ctx->graph_exec = ge;
+        ctx->graph_budget = budget;
+    }
+    if (stats) {
+        hipLaunchKernelGGL(k_acc_reset, dim3(cdiv(n, 64)), dim3(64), 0, s, ctx->d_inst, n);
+        LAUNCHCHK();
+    }
+    for (int q = 0; q < nsteps; ++q) HIPCHK(hipGraphLaunch(ctx->graph_exec, s));
+    if (stats) {
+        HIPCHK(hipStreamSynchronize(s));
+        tdgl_step_stats a;
+        memset(&a, 0, sizeof a);
+        a.steps = nsteps;
+        a.sweeps_min = 1 << 30;
+        for (int i = 0; i < n; ++i) {
+            DevState d;
+            HIPCHK(hipMemcpy(&d, ctx->inst[i].d.st, sizeof d, hipMemcpyDeviceToHost));
+            a.sweeps_sum += (long long)d.acc_sweeps;
+            a.capped_steps += (int)d.acc_capped;
+            a.mu_cycles_sum += (int)d.acc_mu_cycles;
+            a.mu_capped_steps += (int)d.acc_mu_capped;
+            a.sweeps_min = std::min(a.sweeps_min, d.acc_sw_min);
+            a.sweeps_max = std::max(a.sweeps_max, d.acc_sw_max);
+            a.last_res2 = d.last_res2;
+            a.mu_last_res = d.mu_last_res;
+        }
+        if (nsteps == 0) a.sweeps_min = 0;
+        *stats = a;
+    }
+    return TDGL_OK;
+}
+
 tdgl_status tdgl_poisson_solve(tdgl_ctx *ctx, const float *f, float *mu) {
     if (!ctx) return fail(TDGL_EINVAL, "null context");
     if (ctx->n != 1) return fail(TDGL_EINVAL, "tdgl_poisson_solve needs a context with one instance");
@@ -1297,6 +1427,7 @@ struct Tiling {
 };
 
 tdgl_status apply_tiling(tdgl_ctx *ctx, const Tiling &t) {
+    drop_graph(ctx);
     ctx->rows = t.rows;
     for (auto &h : ctx->inst) set_tiling(h, t.rows, t.chunk);
     return upload_tiling(ctx);
@@ -1391,8 +1522,8 @@ tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *ch
                     best = t;
                 }
             }
-        hipEventDestroy(e0);
-        hipEventDestroy(e1);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
         if (cache_path) {
             FILE *f = fopen(cache_path, "a");
             if (f) {

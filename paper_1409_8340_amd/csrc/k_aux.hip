@@ -40,17 +40,19 @@ __global__ void k_links(const Inst *__restrict__ insts, int which) {
 }
 
 // End of a Jacobi solve: the first sweep l whose input residual met tol ends
-// the solve with that sweep's output (Eq. convergence); otherwise the cap.
-// Updates the psi buffer index, step counters and clears the residual words
-// for the next step.  One thread per instance.
-__global__ void k_solve_finalize(const Inst *__restrict__ insts, int ninst, int count_step) {
+// the solve with that sweep's output (Eq. convergence); otherwise the cap,
+// which is the instance's max_iter or the nl sweeps launched, whichever is
+// smaller.  Updates the psi buffer index, step counters and clears the
+// residual words for the next step.  One thread per instance.
+__global__ void k_solve_finalize(const Inst *__restrict__ insts, int ninst, int count_step, int nl) {
     const int ii = blockIdx.x * blockDim.x + threadIdx.x;
     if (ii >= ninst) return;
     const Inst &I = insts[ii];
     DevState *st = I.st;
-    int sweeps = I.max_iter, capped = 1;
+    const int cap = min(I.max_iter, nl);
+    int sweeps = cap, capped = 1;
     float last = 0.f;
-    for (int l = 0; l < I.max_iter; ++l) {
+    for (int l = 0; l < cap; ++l) {
         last = row_max(I.res, I.rstride, l);
         if (last < I.tol) { sweeps = l + 1; capped = 0; break; }
     }
@@ -60,6 +62,10 @@ __global__ void k_solve_finalize(const Inst *__restrict__ insts, int ninst, int 
     if (count_step) {
         st->t += I.dt;
         st->n += 1.0;
+        st->acc_sweeps += sweeps;
+        st->acc_capped += capped;
+        st->acc_sw_min = min(st->acc_sw_min, sweeps);
+        st->acc_sw_max = max(st->acc_sw_max, sweeps);
     }
     // keep the last tested residual, then clear the words for the next step
     st->last_res2 = last;
@@ -206,6 +212,19 @@ __global__ void k_mu_io(const Inst *__restrict__ insts, int inst, float *ext, in
         if (to_ext) ext[i] = I.mu[i] - mean;
         else I.mu[i] = ext[i];
     }
+}
+
+// Clears the device step-statistics accumulators of every instance.
+__global__ void k_acc_reset(const Inst *__restrict__ insts, int ninst) {
+    const int ii = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ii >= ninst) return;
+    DevState *st = insts[ii].st;
+    st->acc_sweeps = 0.0;
+    st->acc_capped = 0.0;
+    st->acc_mu_cycles = 0.0;
+    st->acc_mu_capped = 0.0;
+    st->acc_sw_min = 1 << 30;
+    st->acc_sw_max = 0;
 }
 
 // Scalar state writes, ordered on the stream.

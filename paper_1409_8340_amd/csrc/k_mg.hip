@@ -349,7 +349,7 @@ __global__ __launch_bounds__(CO_THREADS) void k_mg_coarsest(const Inst *__restri
 
 // End of a Poisson solve: number of cycles and final residual; clears the
 // cycle words.  One thread per instance.
-__global__ void k_mg_finalize(const Inst *__restrict__ insts, int ninst) {
+__global__ void k_mg_finalize(const Inst *__restrict__ insts, int ninst, int count_step) {
     const int ii = blockIdx.x * blockDim.x + threadIdx.x;
     if (ii >= ninst) return;
     const Inst &I = insts[ii];
@@ -365,6 +365,10 @@ __global__ void k_mg_finalize(const Inst *__restrict__ insts, int ninst) {
     st->mu_cycles = cycles;
     st->mu_capped = capped;
     st->mu_last_res = last;
+    if (count_step) {
+        st->acc_mu_cycles += cycles;
+        st->acc_mu_capped += capped;
+    }
     for (int c = 0; c < I.mu_max_cycles; ++c) row_clear(I.mures, I.rstride, c);
 }
 

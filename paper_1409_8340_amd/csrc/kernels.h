@@ -13,7 +13,8 @@ __global__ void k_stencil(const Inst *insts, const int *prefix, int ninst, int l
                           float2 *ext_out);
 
 __global__ void k_links(const Inst *insts, int which);
-__global__ void k_solve_finalize(const Inst *insts, int ninst, int count_step);
+__global__ void k_solve_finalize(const Inst *insts, int ninst, int count_step, int nl);
+__global__ void k_acc_reset(const Inst *insts, int ninst);
 __global__ void k_jav_partial(const Inst *insts, const int *prefix, int ninst);
 __global__ void k_kupdate(const Inst *insts, const int *nparts);
 __global__ void k_reduce_to_state(const Inst *insts, const int *nparts, int field, int driven_only);
@@ -34,7 +35,7 @@ __global__ void k_mg_restrict(const Inst *insts, const int *prefix, int ninst, i
 __global__ void k_mg_prolong(const Inst *insts, const int *prefix, int ninst, int lv, int ifine,
                              int cyc);
 __global__ void k_mg_coarsest(const Inst *insts, int ninst, int cyc);
-__global__ void k_mg_finalize(const Inst *insts, int ninst);
+__global__ void k_mg_finalize(const Inst *insts, int ninst, int count_step);
 __global__ void k_mu_mean_partial(const Inst *insts, const int *prefix, int ninst, int which);
 
 __global__ void k_fft_x(const Inst *insts, const int *prefix, int ninst, int dir, const float *in_ext,

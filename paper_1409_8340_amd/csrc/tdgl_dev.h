@@ -54,6 +54,9 @@ struct DevState {
     double frac;      // inclusion generator: covered fraction
     float mu_last_res;// Poisson residual max-norm at the end of the last solve
     int pad2;
+    // step statistics accumulated on the device (graph-replayed steps)
+    double acc_sweeps, acc_capped, acc_mu_cycles, acc_mu_capped;
+    int acc_sw_min, acc_sw_max;
 };
 
 // Scalars of the adjoint sweep over one step (device resident).

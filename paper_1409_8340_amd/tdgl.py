@@ -117,6 +117,7 @@ _SIGS = {
     "tdgl_step": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(StepStats)], ctypes.c_int),
     "tdgl_observables": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(Obs)], ctypes.c_int),
     "tdgl_poisson_solve": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "tdgl_step_graph": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(StepStats)], ctypes.c_int),
     "tdgl_adjoint_plan": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
                           ctypes.c_int),
     "tdgl_voltage_grad": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
@@ -313,6 +314,15 @@ class Solver:
     def step(self, nsteps=1, stats=True):
         st = StepStats()
         _check(load().tdgl_step(self._ctx, int(nsteps), ctypes.byref(st) if stats else None))
+        return st.as_dict() if stats else None
+
+    def step_graph(self, nsteps=1, budget=None, stats=True):
+        """nsteps steps as replays of one captured graph (tdgl_step_graph);
+        budget defaults to the largest max_iter of the context."""
+        if budget is None:
+            budget = max(p.max_iter for p in self.params)
+        st = StepStats()
+        _check(load().tdgl_step_graph(self._ctx, int(nsteps), int(budget), ctypes.byref(st) if stats else None))
         return st.as_dict() if stats else None
 
     def poisson_solve(self, f):

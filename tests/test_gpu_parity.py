@@ -154,6 +154,50 @@ def test_batch_matches_single_instances():
     b.close()
 
 
+def _batch3():
+    return [Case(32, 32, 16, Bz=0.1, tol=1e-10, psi_seed=1),
+            Case(48, 40, 12, Bz=0.2, tol=1e-10, psi_seed=2, driven=True, J=0.01),
+            Case(64, 16, 20, Bz=0.05, tol=1e-10, psi_seed=3, driven=True, J=0.03, open_=(False, True, True))]
+
+
+def _batch_solver(cases):
+    b = tdgl.Solver([c.params for c in cases])
+    for i, c in enumerate(cases):
+        c.load_into(b, i)
+    return b
+
+
+def test_step_graph_matches_eager_steps():
+    """Graph-replayed steps (fixed launch sequence, device-side early exit)
+    give bit-identical states and the same statistics as host-driven steps,
+    replay after replay with eager work in between."""
+    cases = _batch3()
+    a = _batch_solver(cases)
+    g = _batch_solver(cases)
+    for rep in range(3):
+        sa = a.step(2)
+        sg = g.step_graph(2)
+        for k in ("steps", "sweeps_sum", "sweeps_min", "sweeps_max", "capped_steps", "mu_cycles_sum"):
+            assert sa[k] == sg[k], (rep, k, sa, sg)
+        for i in range(3):
+            assert np.array_equal(a.get_psi(i).cpu().numpy(), g.get_psi(i).cpu().numpy()), (rep, i)
+            assert a.get_scalars(i)["K"] == g.get_scalars(i)["K"]
+        # eager work on the graph's context between replays
+        a.step(1)
+        g.step(1)
+    print("[graph] stats", sg)
+    a.close()
+    g.close()
+
+
+def test_step_graph_budget_caps_solves():
+    cases = _batch3()
+    g = _batch_solver(cases)
+    st = g.step_graph(2, budget=2)
+    assert st["sweeps_max"] <= 2 and st["capped_steps"] == 2 * 3, st
+    g.close()
+
+
 def test_autotune_keeps_state_and_results(tmp_path):
     """tdgl_autotune leaves the state alone, picks a valid tiling, and later
     steps match a context with the default tiling (the per-node arithmetic
