@@ -205,7 +205,7 @@ def batch_bench(tdgl, inputs, torch, steps, warmup, n=64):
         sweeps_s += ss["sweeps_sum"]
         s.close()
     return {"instances": n, "nodes": nodes, "steps": steps, "warmup": warmup, "sweep_budget": budget,
-            "tiling": {"rows": tiling["rows"], "chunk": tiling["chunk"]},
+            "tiling": {"rows": tiling["rows"], "chunk": tiling["chunk"], "streaming": tiling["streaming"]},
             "batched_rate": nodes * steps / t_b, "batched_ms_per_step": 1e3 * t_b / steps,
             "sequential_rate": nodes * steps / t_s, "sequential_ms_per_step": 1e3 * t_s / steps,
             "speedup": t_s / t_b, "batched_sweeps_sum": st["sweeps_sum"], "capped_steps": st["capped_steps"],
@@ -334,7 +334,7 @@ def main():
         "config": {"workload": w.name, "grid": [w.nx, w.ny, w.nz], "h": w.h, "B_eff": Bz, "J": w.J,
                    "inclusions": used, "inclusion_fraction": frac, "tol": w.tol, "dt": w.dt,
                    "mu_tol": 1e-5, "mu_rtol": args.mu_rtol,
-                   "tiling": {"rows": tiling["rows"], "chunk": tiling["chunk"]},
+                   "tiling": {"rows": tiling["rows"], "chunk": tiling["chunk"], "streaming": tiling["streaming"]},
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

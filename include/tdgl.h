@@ -256,13 +256,17 @@ tdgl_status tdgl_poisson_solve(tdgl_ctx *ctx, const float *f, float *mu);
 typedef struct tdgl_tiling {
     int rows;        /* rows of the tile per thread: 1, 2 or 4               */
     int chunk;       /* z planes per work-group (instance 0 for tdgl_autotune) */
+    int streaming;   /* 1: non-temporal hints on the read-once streams of the
+                        sweep and assemble passes (default: on when the
+                        context's sweep arrays exceed 256 MB)               */
     double sweep_us; /* measured time of one Jacobi sweep of the whole context
                         (tdgl_autotune; 0 from tdgl_get_tiling)             */
 } tdgl_tiling;
 
 /* Picks the stencil tiling of the context by timing one Jacobi sweep for
  * each candidate (rows in {1, 2, 4} x chunk in {heuristic, 4, 8, 16, 32,
- * 64}) on the context's stream and keeping the fastest.  The timing sweeps
+ * 64} x streaming hints off/on) on the context's stream and keeping the
+ * fastest.  The timing sweeps
  * read the current psi~ and b/M, (ht/2)/M arrays and write only the spare
  * psi~ buffer, so the solver state is unchanged; results of later steps do
  * not depend on the tiling beyond the summation order of FP64 partial sums.

@@ -377,10 +377,12 @@ struct tdgl_ctx {
     int *d_pref_fx = nullptr, *d_pref_fy = nullptr, *d_pref_fz = nullptr;
     int tot_fx = 0, tot_fy = 0, tot_fz = 0;
     size_t fx_lds = 0, fy_lds = 0, fz_lds = 0;
+    bool fx_p2 = true, fy_p2 = true;  // every spectral instance has power-of-two nx (ny)
     bool any_fft = false, any_mg = false;
     bool any_driven = false;
     int max_iter = 1, max_cycles = 1;
-    int rows = 2;  // stencil rows per thread
+    int rows = 2;     // stencil rows per thread
+    bool nt = false;  // streaming (non-temporal) hints in the sweep and assemble passes
     // captured step of tdgl_step_graph (rebuilt when the budget or the
     // tiling changes)
     hipGraph_t graph = nullptr;
@@ -558,6 +560,11 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
         ctx->d_mures = mures;
         ctx->npad = npad;
         ctx->rows = ctx_rows(n, params);
+        // streaming hints by default when the sweep's arrays (32 B per node)
+        // exceed the 256 MB last-level cache; tdgl_autotune measures it
+        double bytes = 0.0;
+        for (int i = 0; i < n; ++i) bytes += 32.0 * params[i].nx * params[i].ny * params[i].nz;
+        ctx->nt = bytes > 256.0 * 1024 * 1024;
         ctx->max_iter = max_iter;
         ctx->max_cycles = max_cycles;
     }
@@ -622,8 +629,10 @@ tdgl_status upload_tables(tdgl_ctx *ctx) {
         pfz[i + 1] = pfz[i] + h.fz_blocks;
         if (h.d.fft) {
             ctx->any_fft = true;
-            ctx->fx_lds = std::max(ctx->fx_lds, (size_t)fft_x_pairs(h.p.nx) * h.p.nx * 8);
-            ctx->fy_lds = std::max(ctx->fy_lds, (size_t)fft_y_cols(h.p.ny) * h.p.ny * 8);
+            ctx->fx_lds = std::max(ctx->fx_lds, (size_t)(fft_x_pairs(h.p.nx) + 1) * h.p.nx * 8);
+            ctx->fy_lds = std::max(ctx->fy_lds, (size_t)(fft_y_cols(h.p.ny) + 1) * h.p.ny * 8);
+            ctx->fx_p2 = ctx->fx_p2 && (h.p.nx & (h.p.nx - 1)) == 0;
+            ctx->fy_p2 = ctx->fy_p2 && (h.p.ny & (h.p.ny - 1)) == 0;
             ctx->fz_lds = std::max(ctx->fz_lds, fft_z_lds(h.p.nz));
         } else if (h.p.driven) {
             ctx->any_mg = true;
@@ -643,9 +652,13 @@ tdgl_status upload_tables(tdgl_ctx *ctx) {
     ctx->tot_fy = pfy[n];
     ctx->tot_fz = pfz[n];
     if (ctx->any_fft) {
-        HIPCHK(hipFuncSetAttribute((const void *)k_fft_x, hipFuncAttributeMaxDynamicSharedMemorySize,
+        HIPCHK(hipFuncSetAttribute((const void *)k_fft_x<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)ctx->fx_lds));
-        HIPCHK(hipFuncSetAttribute((const void *)k_fft_y, hipFuncAttributeMaxDynamicSharedMemorySize,
+        HIPCHK(hipFuncSetAttribute((const void *)k_fft_x<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)ctx->fx_lds));
+        HIPCHK(hipFuncSetAttribute((const void *)k_fft_y<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)ctx->fy_lds));
+        HIPCHK(hipFuncSetAttribute((const void *)k_fft_y<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)ctx->fy_lds));
         HIPCHK(hipFuncSetAttribute((const void *)k_fft_zsolve, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)ctx->fz_lds));
@@ -700,18 +713,23 @@ struct ProfScope {
     }
 };
 
-// Launch one stencil pass over every instance with the context's tile.
+// Launch one stencil pass over every instance with the context's tile
+// (rows per thread; streaming hints for the sweep and assemble passes).
+template <int MODE, int R>
+void launch_stencil_r(tdgl_ctx *c, int l, const float2 *in, float2 *out) {
+    constexpr bool can_nt = (MODE == MODE_SWEEP || MODE == MODE_FIRST);
+    if (can_nt && c->nt)
+        hipLaunchKernelGGL((k_stencil<MODE, R, can_nt>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst,
+                           c->d_pref_st, c->n, l, in, out);
+    else
+        hipLaunchKernelGGL((k_stencil<MODE, R, false>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst,
+                           c->d_pref_st, c->n, l, in, out);
+}
 template <int MODE>
 void launch_stencil(tdgl_ctx *c, int l, const float2 *in = nullptr, float2 *out = nullptr) {
-    if (c->rows == 1)
-        hipLaunchKernelGGL((k_stencil<MODE, 1>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst, c->d_pref_st,
-                           c->n, l, in, out);
-    else if (c->rows == 2)
-        hipLaunchKernelGGL((k_stencil<MODE, 2>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst, c->d_pref_st,
-                           c->n, l, in, out);
-    else
-        hipLaunchKernelGGL((k_stencil<MODE, 4>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst, c->d_pref_st,
-                           c->n, l, in, out);
+    if (c->rows == 1) launch_stencil_r<MODE, 1>(c, l, in, out);
+    else if (c->rows == 2) launch_stencil_r<MODE, 2>(c, l, in, out);
+    else launch_stencil_r<MODE, 4>(c, l, in, out);
 }
 
 // One multigrid V-cycle for every driven instance (cycle index cyc).
@@ -840,16 +858,21 @@ tdgl_status enqueue_fft(tdgl_ctx *ctx) {
     ProfScope ps(ctx, TDGL_K_MG_FINE);
     const float *nf = nullptr;
     float *nm = nullptr;
-    hipLaunchKernelGGL(k_fft_x, dim3(std::max(ctx->tot_fx, 1)), dim3(FFT_XY_THREADS), ctx->fx_lds, s, ctx->d_inst,
-                       ctx->d_pref_fx, n, -1, nf, nm);
-    hipLaunchKernelGGL(k_fft_y, dim3(std::max(ctx->tot_fy, 1)), dim3(FFT_XY_THREADS), ctx->fy_lds, s, ctx->d_inst,
-                       ctx->d_pref_fy, n, -1);
+    const dim3 gx(std::max(ctx->tot_fx, 1)), gy(std::max(ctx->tot_fy, 1)), bt(FFT_XY_THREADS);
+    auto xpass = [&](int dir) {
+        if (ctx->fx_p2) hipLaunchKernelGGL(k_fft_x<true>, gx, bt, ctx->fx_lds, s, ctx->d_inst, ctx->d_pref_fx, n, dir, nf, nm);
+        else hipLaunchKernelGGL(k_fft_x<false>, gx, bt, ctx->fx_lds, s, ctx->d_inst, ctx->d_pref_fx, n, dir, nf, nm);
+    };
+    auto ypass = [&](int dir) {
+        if (ctx->fy_p2) hipLaunchKernelGGL(k_fft_y<true>, gy, bt, ctx->fy_lds, s, ctx->d_inst, ctx->d_pref_fy, n, dir);
+        else hipLaunchKernelGGL(k_fft_y<false>, gy, bt, ctx->fy_lds, s, ctx->d_inst, ctx->d_pref_fy, n, dir);
+    };
+    xpass(-1);
+    ypass(-1);
     hipLaunchKernelGGL(k_fft_zsolve, dim3(std::max(ctx->tot_fz, 1)), dim3(256), ctx->fz_lds, s, ctx->d_inst,
                        ctx->d_pref_fz, n);
-    hipLaunchKernelGGL(k_fft_y, dim3(std::max(ctx->tot_fy, 1)), dim3(FFT_XY_THREADS), ctx->fy_lds, s, ctx->d_inst,
-                       ctx->d_pref_fy, n, +1);
-    hipLaunchKernelGGL(k_fft_x, dim3(std::max(ctx->tot_fx, 1)), dim3(FFT_XY_THREADS), ctx->fx_lds, s, ctx->d_inst,
-                       ctx->d_pref_fx, n, +1, nf, nm);
+    ypass(+1);
+    xpass(+1);
     LAUNCHCHK();
     return TDGL_OK;
 }
@@ -1424,11 +1447,13 @@ tdgl_status upload_tiling(tdgl_ctx *ctx) {
 struct Tiling {
     int rows = 2;
     int chunk = 0;  // 0: heuristic
+    int nt = 0;     // streaming hints
 };
 
 tdgl_status apply_tiling(tdgl_ctx *ctx, const Tiling &t) {
     drop_graph(ctx);
     ctx->rows = t.rows;
+    ctx->nt = t.nt != 0;
     for (auto &h : ctx->inst) set_tiling(h, t.rows, t.chunk);
     return upload_tiling(ctx);
 }
@@ -1457,12 +1482,13 @@ bool tune_file_lookup(const char *path, const std::string &key, Tiling *t, doubl
     bool found = false;
     while (fgets(line, sizeof line, f)) {
         char k[4000];
-        int r, c;
+        int r, c, nt;
         double u;
-        if (sscanf(line, "%3999s %d %d %lf", k, &r, &c, &u) == 4 && key == k && (r == 1 || r == 2 || r == 4) &&
-            c >= 0) {
+        if (sscanf(line, "%3999s %d %d %d %lf", k, &r, &c, &nt, &u) == 5 && key == k &&
+            (r == 1 || r == 2 || r == 4) && c >= 0 && (nt == 0 || nt == 1)) {
             t->rows = r;
             t->chunk = c;
+            t->nt = nt;
             *us = u;
             found = true;  // the last entry wins
         }
@@ -1500,11 +1526,13 @@ tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *ch
         const int chunks[] = {0, 4, 8, 16, 32, 64};
         const int rows[] = {1, 2, 4};
         best_us = 1e300;
+        for (int nt = 0; nt < 2; ++nt)
         for (int r : rows)
             for (int c : chunks) {
                 Tiling t;
                 t.rows = r;
                 t.chunk = c;
+                t.nt = nt;
                 tdgl_status e = apply_tiling(ctx, t);
                 if (e) return e;
                 launch_stencil<MODE_SWEEP>(ctx, -1);  // warm-up
@@ -1527,7 +1555,7 @@ tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *ch
         if (cache_path) {
             FILE *f = fopen(cache_path, "a");
             if (f) {
-                fprintf(f, "%s %d %d %.3f\n", key.c_str(), best.rows, best.chunk, best_us);
+                fprintf(f, "%s %d %d %d %.3f\n", key.c_str(), best.rows, best.chunk, best.nt, best_us);
                 fclose(f);
             }
         }
@@ -1541,6 +1569,7 @@ tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *ch
     if (chosen) {
         chosen->rows = best.rows;
         chosen->chunk = ctx->inst[0].d.chunk;
+        chosen->streaming = best.nt;
         chosen->sweep_us = best_us;
     }
     return TDGL_OK;
@@ -1551,6 +1580,7 @@ tdgl_status tdgl_get_tiling(const tdgl_ctx *ctx, int inst, tdgl_tiling *out) {
     if (inst < 0 || inst >= ctx->n) return fail(TDGL_EINVAL, "instance %d out of range", inst);
     out->rows = ctx->rows;
     out->chunk = ctx->inst[inst].d.chunk;
+    out->streaming = ctx->nt ? 1 : 0;
     out->sweep_us = 0.0;
     return TDGL_OK;
 }

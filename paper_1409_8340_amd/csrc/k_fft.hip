@@ -101,8 +101,8 @@ __device__ __forceinline__ int fdiv(int t, float inv_d) { return (int)(((float)t
 // the previous passes.  tw[k] = exp(-2 pi i k / n) (conjugated for the
 // inverse transform, sign = +1).
 template <int R>
-__device__ __forceinline__ void fft_pass(float2 *buf, int n, int Ns, int nseq, int sstride, const float2 *__restrict__ tw,
-                         float sign) {
+__device__ __forceinline__ void fft_pass(float2 *buf, int n, int Ns, int nseq, int sstride, const float2 *tw,
+                                         float sign) {
     constexpr int MAXBF = (FFT_MAXPTS / R + FFT_THREADS - 1) / FFT_THREADS;
     const int nb = n / R;
     const int total = nb * nseq;
@@ -145,13 +145,16 @@ __device__ __forceinline__ void fft_pass(float2 *buf, int n, int Ns, int nseq, i
 }
 
 // Full transform of nseq sequences in LDS (natural order in and out).
+// P2: the length is a power of two (radices 4 and 2 only), which keeps the
+// kernels small enough for two 1024-thread work-groups per CU.
+template <bool P2>
 __device__ __forceinline__ void fft_lds(float2 *buf, int n, const int *rad, int nrad, int nseq, int sstride,
-                        const float2 *__restrict__ tw, float sign) {
+                                        const float2 *tw, float sign) {
     int Ns = 1;
     for (int p = 0; p < nrad; ++p) {
         const int R = rad[p];
         if (R == 4) fft_pass<4>(buf, n, Ns, nseq, sstride, tw, sign);
-        else if (R == 2) fft_pass<2>(buf, n, Ns, nseq, sstride, tw, sign);
+        else if (P2 || R == 2) fft_pass<2>(buf, n, Ns, nseq, sstride, tw, sign);
         else if (R == 3) fft_pass<3>(buf, n, Ns, nseq, sstride, tw, sign);
         else fft_pass<5>(buf, n, Ns, nseq, sstride, tw, sign);
         Ns *= R;
@@ -185,11 +188,13 @@ __host__ __device__ int fft_y_cols(int ny) {
 __host__ __device__ int fft_pitch(int nx) { return (nx / 2 + 1 + 15) & ~15; }
 
 // Forward real-to-complex FFT along x of `in` (real rows of length nx) into
-// spec (nx/2+1 bins per row).  Two real rows a, b travel as one complex row
+// spec (nx/2+1 bins per row).  The twiddles are staged in LDS after the
+// data (dynamic LDS: (2 pairs + 1) nx complex values).  Two real rows a, b travel as one complex row
 // a + i b; their spectra are separated with the conjugate symmetry
 //   A_k = (Z_k + conj Z_{n-k}) / 2,  B_k = (Z_k - conj Z_{n-k}) / (2 i).
 // Also the inverse (complex-to-real) along x: dir = +1 reads spec, writes
 // `out`.
+template <bool P2>
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_x(const Inst *__restrict__ insts,
                                                        const int *__restrict__ prefix, int ninst,
                                                        int dir, const float *in_ext, float *out_ext) {
@@ -199,6 +204,8 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x(const Inst *__restrict__ 
     const int nx = I.nx, P = nx / 2 + 1, sp = I.sp;
     const int rows = I.ny * I.nz;
     const int pairs = fft_x_pairs(nx);
+    float2 *stw = sm + pairs * nx;
+    for (int t = threadIdx.x; t < nx; t += FFT_THREADS) stw[t] = I.twx[t];
     const int row0 = (blockIdx.x - prefix[ii]) * 2 * pairs;
     const float *in = in_ext ? in_ext : I.f;
     float *out = out_ext ? out_ext : I.mu;
@@ -214,7 +221,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x(const Inst *__restrict__ 
             sm[t] = make_float2(a, b);
         }
         __syncthreads();
-        fft_lds(sm, nx, I.xrad, I.nxrad, pairs, nx, I.twx, -1.f);
+        fft_lds<P2>(sm, nx, I.xrad, I.nxrad, pairs, nx, stw, -1.f);
         for (int t = threadIdx.x; t < pairs * P; t += FFT_THREADS) {
             const int s = fdiv(t, inv_p), k = t - s * P;
             const float2 z = sm[s * nx + k];
@@ -239,7 +246,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x(const Inst *__restrict__ 
             sm[t] = make_float2(A.x - B.y, A.y + B.x);
         }
         __syncthreads();
-        fft_lds(sm, nx, I.xrad, I.nxrad, pairs, nx, I.twx, +1.f);
+        fft_lds<P2>(sm, nx, I.xrad, I.nxrad, pairs, nx, stw, +1.f);
         for (int t = threadIdx.x; t < pairs * nx; t += FFT_THREADS) {
             const int s = fdiv(t, inv_nx), e = t - s * nx;
             const int ra = row0 + 2 * s, rb = ra + 1;
@@ -253,6 +260,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x(const Inst *__restrict__ 
 // FFT along y of the half spectrum, forward (dir = -1) or inverse (+1):
 // a work-group takes TK consecutive kx at one z, all y.  Consecutive tiles
 // share 128-byte lines, so neighbouring logical tiles run on one XCD.
+template <bool P2>
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(const Inst *__restrict__ insts,
                                                        const int *__restrict__ prefix, int ninst,
                                                        int dir) {
@@ -268,12 +276,14 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(const Inst *__restrict__ 
     const int tk = min(TK, P - kx0);
     float2 *spec = I.spec + (size_t)z * ny * sp;
     const float inv_tk = 1.0f / (float)TK;
+    float2 *stw = sm + TK * ny;
+    for (int t = threadIdx.x; t < ny; t += FFT_THREADS) stw[t] = I.twy[t];
     for (int t = threadIdx.x; t < ny * TK; t += FFT_THREADS) {
         const int y = fdiv(t, inv_tk), c = t - y * TK;
         sm[c * ny + y] = c < tk ? spec[(size_t)y * sp + kx0 + c] : make_float2(0.f, 0.f);
     }
     __syncthreads();
-    fft_lds(sm, ny, I.yrad, I.nyrad, TK, ny, I.twy, (float)dir);
+    fft_lds<P2>(sm, ny, I.yrad, I.nyrad, TK, ny, stw, (float)dir);
     for (int t = threadIdx.x; t < ny * TK; t += FFT_THREADS) {
         const int y = fdiv(t, inv_tk), c = t - y * TK;
         if (c < tk) spec[(size_t)y * sp + kx0 + c] = sm[c * ny + y];
@@ -318,6 +328,11 @@ __global__ void k_fft_tables(const Inst *__restrict__ insts, int inst) {
         }
     }
 }
+
+template __global__ void k_fft_x<false>(const Inst *, const int *, int, int, const float *, float *);
+template __global__ void k_fft_x<true>(const Inst *, const int *, int, int, const float *, float *);
+template __global__ void k_fft_y<false>(const Inst *, const int *, int, int);
+template __global__ void k_fft_y<true>(const Inst *, const int *, int, int);
 
 // The z systems, one per (kx, ky), in double precision.  A work-group loads
 // a tile of ZTK consecutive kx at one ky and all z (coalesced rows); each

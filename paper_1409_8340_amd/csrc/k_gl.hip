@@ -33,6 +33,22 @@ __device__ __forceinline__ float2 ld2(const gf2 *p, unsigned i) {
     const v2f v = p[i];
     return make_float2(v.x, v.y);
 }
+// Streams read or written once per pass (b/M, (ht/2)/M, eps, mu, the new
+// iterate) can bypass the caches' retention with non-temporal hints, so that
+// L2 keeps the psi rows the neighbouring tiles re-read as halos.  That pays
+// when the arrays do not fit the last-level cache; for grids that stay
+// cache-resident between sweeps the hints cost time, so they are a template
+// option (NT) chosen per context.
+__device__ __forceinline__ float2 ld2nt(const gf2 *p, unsigned i) {
+    const v2f v = __builtin_nontemporal_load(&p[i]);
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void st2nt(gf2 *p, unsigned i, float2 a) {
+    v2f v;
+    v.x = a.x;
+    v.y = a.y;
+    __builtin_nontemporal_store(v, &p[i]);
+}
 __device__ __forceinline__ void st2(gf2 *p, unsigned i, float2 a) {
     v2f v;
     v.x = a.x;
@@ -119,7 +135,7 @@ __device__ __forceinline__ void halo_cell(int t, int x0, int y0, int &gx, int &g
 // MODE selects the pass; R is the number of consecutive rows a thread owns
 // (tile 64 x 4R: a larger R streams more per thread, a smaller one keeps
 // more waves resident; the autotuner picks R and the z chunk).
-template <int MODE, int R>
+template <int MODE, int R, bool NT>
 __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
                                                 const int *__restrict__ prefix, int ninst, int l,
                                                 const float2 *ext_in, float2 *ext_out) {
@@ -234,11 +250,13 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
         for (int r = 0; r < ROWS; ++r) {
             const unsigned m = pb + (unsigned)own[r].off;
             if (MODE == MODE_SWEEP) {
-                bh_[r] = vy[r] ? ld2(bhp, m) : make_float2(0.f, 0.f);
-                dh_[r] = vy[r] ? ld2(dhp, m) : make_float2(0.f, 0.f);
+                bh_[r] = vy[r] ? (NT ? ld2nt(bhp, m) : ld2(bhp, m)) : make_float2(0.f, 0.f);
+                dh_[r] = vy[r] ? (NT ? ld2nt(dhp, m) : ld2(dhp, m)) : make_float2(0.f, 0.f);
             }
-            if (MODE == MODE_FIRST || MODE == MODE_ENERGY) ep_[r] = vy[r] ? float(epsp[m]) : 0.f;
-            if (MODE == MODE_FIRST) mu_[r] = (vy[r] && I.driven) ? float(mup[m]) - mu_mean : 0.f;
+            if (MODE == MODE_FIRST || MODE == MODE_ENERGY)
+                ep_[r] = vy[r] ? (NT ? __builtin_nontemporal_load(&epsp[m]) : float(epsp[m])) : 0.f;
+            if (MODE == MODE_FIRST)
+                mu_[r] = (vy[r] && I.driven) ? (NT ? __builtin_nontemporal_load(&mup[m]) : float(mup[m])) - mu_mean : 0.f;
         }
     };
     load_streams(k0, bh, dh, ep, mu);
@@ -327,8 +345,13 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
                 const float2 Mi = make_float2(M.x * inv, -M.y * inv);
                 const float2 bhv = cmul(bb, Mi);
                 const float2 dhv = cscale(ht2, Mi);
-                st2(bhw, m, bhv);
-                st2(dhw, m, dhv);
+                if (NT) {
+                    st2nt(bhw, m, bhv);
+                    st2nt(dhw, m, dhv);
+                } else {
+                    st2(bhw, m, bhv);
+                    st2(dhw, m, dhv);
+                }
                 nw = cadd(bhv, cmul(dhv, ns));
                 const float2 d = csub(nw, c);
                 const float r2 = cabs2(M) * cabs2(d);
@@ -339,7 +362,8 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
                 const float r2 = cabs2(d) * (ht2 * ht2) / cabs2(dh[r]);
                 rmax = (r2 > rmax || r2 != r2) ? r2 : rmax;
             }
-            st2(dst, m, nw);
+            if (NT) st2nt(dst, m, nw);
+            else st2(dst, m, nw);
         }
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
@@ -368,23 +392,20 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
     }
 }
 
-#define TDGL_INST(M, R) \
-    template __global__ void k_stencil<M, R>(const Inst *, const int *, int, int, const float2 *, float2 *);
-TDGL_INST(MODE_FIRST, 1)
-TDGL_INST(MODE_SWEEP, 1)
-TDGL_INST(MODE_RHS, 1)
-TDGL_INST(MODE_ENERGY, 1)
-TDGL_INST(MODE_NS, 1)
-TDGL_INST(MODE_FIRST, 2)
-TDGL_INST(MODE_SWEEP, 2)
-TDGL_INST(MODE_RHS, 2)
-TDGL_INST(MODE_ENERGY, 2)
-TDGL_INST(MODE_NS, 2)
-TDGL_INST(MODE_FIRST, 4)
-TDGL_INST(MODE_SWEEP, 4)
-TDGL_INST(MODE_RHS, 4)
-TDGL_INST(MODE_ENERGY, 4)
-TDGL_INST(MODE_NS, 4)
+#define TDGL_INST(M, R, NT) \
+    template __global__ void k_stencil<M, R, NT>(const Inst *, const int *, int, int, const float2 *, float2 *);
+#define TDGL_INST_R(R)                 \
+    TDGL_INST(MODE_FIRST, R, false)    \
+    TDGL_INST(MODE_FIRST, R, true)     \
+    TDGL_INST(MODE_SWEEP, R, false)    \
+    TDGL_INST(MODE_SWEEP, R, true)     \
+    TDGL_INST(MODE_RHS, R, false)      \
+    TDGL_INST(MODE_ENERGY, R, false)   \
+    TDGL_INST(MODE_NS, R, false)
+TDGL_INST_R(1)
+TDGL_INST_R(2)
+TDGL_INST_R(4)
+#undef TDGL_INST_R
 #undef TDGL_INST
 
 }  // namespace tdgl

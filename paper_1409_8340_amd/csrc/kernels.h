@@ -8,7 +8,7 @@ enum { MODE_FIRST = 0, MODE_SWEEP = 1, MODE_RHS = 2, MODE_ENERGY = 3, MODE_NS = 
 constexpr int JAV_CPT = 16;     // cells per thread of the flat reductions
 constexpr int CO_THREADS = 1024;
 
-template <int MODE, int R>
+template <int MODE, int R, bool NT>
 __global__ void k_stencil(const Inst *insts, const int *prefix, int ninst, int l, const float2 *ext_in,
                           float2 *ext_out);
 
@@ -38,8 +38,10 @@ __global__ void k_mg_coarsest(const Inst *insts, int ninst, int cyc);
 __global__ void k_mg_finalize(const Inst *insts, int ninst, int count_step);
 __global__ void k_mu_mean_partial(const Inst *insts, const int *prefix, int ninst, int which);
 
+template <bool P2>
 __global__ void k_fft_x(const Inst *insts, const int *prefix, int ninst, int dir, const float *in_ext,
                         float *out_ext);
+template <bool P2>
 __global__ void k_fft_y(const Inst *insts, const int *prefix, int ninst, int dir);
 __global__ void k_fft_zsolve(const Inst *insts, const int *prefix, int ninst);
 __global__ void k_fft_tables(const Inst *insts, int inst);

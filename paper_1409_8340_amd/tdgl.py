@@ -73,7 +73,8 @@ KERNEL_CLASSES = ["assemble", "sweep", "current", "rhs", "mg_fine", "mg_coarse",
 
 
 class Tiling(ctypes.Structure):
-    _fields_ = [("rows", ctypes.c_int), ("chunk", ctypes.c_int), ("sweep_us", ctypes.c_double)]
+    _fields_ = [("rows", ctypes.c_int), ("chunk", ctypes.c_int), ("streaming", ctypes.c_int),
+                ("sweep_us", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -105,3 +105,49 @@ def test_autograd_function():
         V3 = tdgl.voltage(s3, eps.detach(), 5, window_begin=1)
     s3.close()
     assert abs(float(V3) - v2) <= 1e-12 * max(1.0, abs(v2))
+
+
+def test_directional_derivative_at_c4_size():
+    """At the 128 x 128 x 32 adjoint workload's size (its inclusions, field and
+    current): <dVbar/deps, d> from tdgl_voltage_grad against central
+    differences of the GPU forward along a dense random +-1 direction d
+    (per-cell differences drown in FP32 noise at this size; the directional
+    derivative sums ~500k cells and stands far above it).  Tight Jacobi
+    tolerance so that sweep-count changes between the +-delta runs stay
+    negligible."""
+    import torch
+    w = inputs.WORKLOADS["c4_adjoint_128x128x32"]
+    p = tdgl.make_params(w.nx, w.ny, w.nz, h=w.h, driven=True, tol=1e-12, max_iter=250, dt=w.dt)
+    s = tdgl.Solver(p)
+    s.set_field(0.0, w.B, quantize=True)
+    s.set_current(w.J)
+    cen, dia = inputs.candidates_for(w)
+    s.gen_inclusions(cen, dia, w.fraction, w.eps_in, w.eps_out)
+    eps0 = s.get_eps().clone()
+    s.set_psi(torch.from_numpy(inputs.psi_init(w.nx, w.ny, w.nz, w.psi_seed)).cuda())
+    s.step(20, stats=False)
+    state = (s.get_psi().clone(), s.get_mu().clone(), s.get_scalars())
+    nsteps = 30
+
+    def restore(eps):
+        s.set_eps(eps)
+        s.set_psi(state[0])
+        s.set_mu(state[1])
+        s.set_scalars(state[2])
+
+    restore(eps0)
+    v, g = s.voltage_grad(nsteps, 0, ckpt_every=10)
+    d = torch.from_numpy(np.sign(inputs.random_real(eps0.shape, 77, -1.0, 1.0))).cuda()
+    ad = float(torch.sum(g.double() * d.double()))
+    delta = 1e-2
+    vals = []
+    for sgn in (+1.0, -1.0):
+        restore((eps0 + sgn * delta * d).float().contiguous())
+        s.window_reset()
+        s.step(nsteps, stats=False)
+        vals.append(s.observables()["E_mean"])
+    s.close()
+    fd = (vals[0] - vals[1]) / (2 * delta)
+    print(f"[adjoint c4] Vbar {v:.6e}; directional derivative adjoint {ad:.6e} fd {fd:.6e} "
+          f"rel {abs(fd - ad) / abs(fd):.3e}")
+    assert abs(fd - ad) <= 2e-2 * abs(fd)
