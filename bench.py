@@ -15,9 +15,10 @@ synchronisation.  value = nodes * K / seconds (cell-updates per second).
 
 The roofline entry is for the dominant kernel, the Jacobi sweep: its launches
 are bracketed by HIP events on the solver's stream inside the timed region,
-and achieved = algorithmic bytes per launch (32 B per node: read psi, b/M and
-(ht/2)/M, write psi, complex64 each) / mean time of a full sweep (total sweep
-time over the launches that did a full pass).
+and achieved = algorithmic bytes per pass (32 B per node: read psi, b/M and
+(ht/2)/M, write psi, complex64 each; a two-sweep pass makes two iterates
+from the same bytes) / mean time of a full pass (total sweep-class time over
+the launches that did a full pass).
 
 cpu_baseline times the FP64 oracle (test infrastructure, not the product)
 on a bounded sample of the same physics.
@@ -37,8 +38,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 SWEEP_BYTES_PER_NODE = 32      # psi in, b/M, (ht/2)/M, psi out (complex64)
 ASSEMBLE_BYTES_PER_NODE = 40   # psi^-, eps, mu in; b/M, (ht/2)/M, psi^(1) out
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stencil_sweep_c5_traffic.txt")
-SWEEP_SRC = os.path.join(ROOT, "paper_1409_8340_amd", "csrc", "k_gl.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_c5_traffic.txt")
+SWEEP_SRCS = [os.path.join(ROOT, "paper_1409_8340_amd", "csrc", f) for f in ("k_gl.hip", "k_gl2.hip", "stencil.h")]
 
 
 def log(*a):
@@ -46,10 +47,14 @@ def log(*a):
 
 
 def kernel_sha():
-    return hashlib.sha256(open(SWEEP_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of the sources of the two sweep kernels (single and two-sweep)."""
+    h = hashlib.sha256()
+    for f in SWEEP_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
-def read_traffic(n_nodes):
+def read_traffic(n_nodes, kernel):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by the plain-copy
     calibration factor), or None when absent or taken on another kernel."""
@@ -61,7 +66,8 @@ def read_traffic(n_nodes):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     try:
-        if kv.get("kernel_source_sha") != kernel_sha() or int(kv.get("nodes", -1)) != n_nodes:
+        if (kv.get("kernel_source_sha") != kernel_sha() or int(kv.get("nodes", -1)) != n_nodes
+                or kv.get("kernel") != kernel):
             return None
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
@@ -205,7 +211,8 @@ def batch_bench(tdgl, inputs, torch, steps, warmup, n=64):
         sweeps_s += ss["sweeps_sum"]
         s.close()
     return {"instances": n, "nodes": nodes, "steps": steps, "warmup": warmup, "sweep_budget": budget,
-            "tiling": {"rows": tiling["rows"], "chunk": tiling["chunk"], "streaming": tiling["streaming"]},
+            "tiling": {"rows": tiling["rows"], "chunk": tiling["chunk"], "streaming": tiling["streaming"],
+                       "fused": tiling["fused"]},
             "batched_rate": nodes * steps / t_b, "batched_ms_per_step": 1e3 * t_b / steps,
             "sequential_rate": nodes * steps / t_s, "sequential_ms_per_step": 1e3 * t_s / steps,
             "speedup": t_s / t_b, "batched_sweeps_sum": st["sweeps_sum"], "capped_steps": st["capped_steps"],
@@ -288,16 +295,18 @@ def main():
     obs = s.observables()
 
     sw = prof["sweep"]
-    # Sweep-class launches that did a full pass: the first iterate of every
-    # step comes from the assemble kernel, and the launch that starts before
-    # the host has seen convergence exits at once.  Its few microseconds stay
-    # in the total, so the mean below errs on the slow side.
-    full = max(st["sweeps_sum"] - st["steps"], 1)
+    # Sweep-class launches that did a full pass over the grid (the library
+    # counts them: the first iterate of a step comes from the assemble kernel,
+    # a two-sweep pass makes two iterates, and the launch that starts before
+    # the host has seen convergence exits at once; its few microseconds stay
+    # in the total, so the mean below errs on the slow side).  A pass of
+    # either kind reads psi, b/M and (ht/2)/M and writes psi once: 32 B/node.
+    full = max(st["sweep_passes"], 1)
     sweep_ms = sw["ms"] / full
     achieved = SWEEP_BYTES_PER_NODE * N / (sweep_ms * 1e-3) / 1e9
     asm = prof["assemble"]
     asm_ms = asm["ms"] / max(asm["launches"], 1)
-    traffic = read_traffic(N)
+    traffic = read_traffic(N, "k_sweep2" if tiling["fused"] else "k_stencil_sweep")
 
     adj = None
     if args.adjoint_steps > 0:
@@ -334,11 +343,14 @@ def main():
         "config": {"workload": w.name, "grid": [w.nx, w.ny, w.nz], "h": w.h, "B_eff": Bz, "J": w.J,
                    "inclusions": used, "inclusion_fraction": frac, "tol": w.tol, "dt": w.dt,
                    "mu_tol": 1e-5, "mu_rtol": args.mu_rtol,
-                   "tiling": {"rows": tiling["rows"], "chunk": tiling["chunk"], "streaming": tiling["streaming"]},
+                   "tiling": {"rows": tiling["rows"], "chunk": tiling["chunk"], "streaming": tiling["streaming"],
+                              "fused": tiling["fused"]},
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "tdgl::k_stencil<1> (Jacobi sweep)",
+                     "kernel": ("tdgl::k_sweep2 (two Jacobi sweeps per pass)" if tiling["fused"]
+                                else "tdgl::k_stencil<1> (Jacobi sweep)"),
+                     "sweeps_per_pass": 2 if tiling["fused"] else 1,
                      "bytes_per_launch": SWEEP_BYTES_PER_NODE * N, "mean_launch_ms": sweep_ms,
                      "full_launches": full, "launches": sw["launches"]},
         "cpu_baseline": cpu,

@@ -94,6 +94,11 @@ typedef struct tdgl_step_stats {
     int mu_cycles_sum;      /* multigrid cycles over all steps                 */
     int mu_capped_steps;    /* steps whose Poisson solve hit mu_max_cycles      */
     float mu_last_res;      /* last Poisson residual max-norm                  */
+    long long sweep_passes; /* Jacobi-kernel passes that did a full pass over
+                               the grid: sweeps - 1 per step (the first
+                               iterate comes from the assemble pass), or
+                               sweeps / 2 with two-sweep passes; launches that
+                               exit at once and corrective sweeps excluded */
 } tdgl_step_stats;
 
 /* Scalars that, with psi~ and mu~, make up the full state (exact resume). */
@@ -259,14 +264,17 @@ typedef struct tdgl_tiling {
     int streaming;   /* 1: non-temporal hints on the read-once streams of the
                         sweep and assemble passes (default: on when the
                         context's sweep arrays exceed 256 MB)               */
+    int fused;       /* 1: Jacobi sweeps run two per pass over HBM (the
+                        second iterate on the tile from the first on the tile
+                        and its one-node ring); results are bit-identical */
     double sweep_us; /* measured time of one Jacobi sweep of the whole context
                         (tdgl_autotune; 0 from tdgl_get_tiling)             */
 } tdgl_tiling;
 
 /* Picks the stencil tiling of the context by timing one Jacobi sweep for
  * each candidate (rows in {1, 2, 4} x chunk in {heuristic, 4, 8, 16, 32,
- * 64} x streaming hints off/on) on the context's stream and keeping the
- * fastest.  The timing sweeps
+ * 64} x streaming hints off/on x one or two sweeps per pass) on the
+ * context's stream and keeping the fastest per iteration.  The timing sweeps
  * read the current psi~ and b/M, (ht/2)/M arrays and write only the spare
  * psi~ buffer, so the solver state is unchanged; results of later steps do
  * not depend on the tiling beyond the summation order of FP64 partial sums.
@@ -275,6 +283,11 @@ typedef struct tdgl_tiling {
  * in that text file (read first, appended after a search).  No device
  * allocation.  chosen may be NULL.  Synchronising. */
 tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *chosen);
+
+/* Sets the tiling of every instance without timing (rows in {1, 2, 4};
+ * chunk 0 = heuristic, else z planes per work-group; streaming and fused 0
+ * or 1; sweep_us ignored).  No allocation; synchronises the stream. */
+tdgl_status tdgl_set_tiling(tdgl_ctx *ctx, const tdgl_tiling *t);
 
 /* Current tiling of instance inst (rows are shared by the context). */
 tdgl_status tdgl_get_tiling(const tdgl_ctx *ctx, int inst, tdgl_tiling *out);

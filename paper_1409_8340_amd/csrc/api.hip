@@ -383,6 +383,7 @@ struct tdgl_ctx {
     int max_iter = 1, max_cycles = 1;
     int rows = 2;     // stencil rows per thread
     bool nt = false;  // streaming (non-temporal) hints in the sweep and assemble passes
+    bool fused = false;  // Jacobi sweeps after the first run as two-sweep passes
     // captured step of tdgl_step_graph (rebuilt when the budget or the
     // tiling changes)
     hipGraph_t graph = nullptr;
@@ -725,6 +726,22 @@ void launch_stencil_r(tdgl_ctx *c, int l, const float2 *in, float2 *out) {
         hipLaunchKernelGGL((k_stencil<MODE, R, false>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst,
                            c->d_pref_st, c->n, l, in, out);
 }
+// One two-sweep pass (l odd; l = -1: timing pass).
+template <int R>
+void launch_sweep2_r(tdgl_ctx *c, int l) {
+    if (c->nt)
+        hipLaunchKernelGGL((k_sweep2<R, true>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst, c->d_pref_st,
+                           c->n, l);
+    else
+        hipLaunchKernelGGL((k_sweep2<R, false>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst, c->d_pref_st,
+                           c->n, l);
+}
+void launch_sweep2(tdgl_ctx *c, int l) {
+    if (c->rows == 1) launch_sweep2_r<1>(c, l);
+    else if (c->rows == 2) launch_sweep2_r<2>(c, l);
+    else launch_sweep2_r<4>(c, l);
+}
+
 template <int MODE>
 void launch_stencil(tdgl_ctx *c, int l, const float2 *in = nullptr, float2 *out = nullptr) {
     if (c->rows == 1) launch_stencil_r<MODE, 1>(c, l, in, out);
@@ -794,10 +811,13 @@ tdgl_status jacobi_loop(tdgl_ctx *ctx, tdgl_step_stats *acc, bool *strict_fail, 
     HIPCHK(hipMemcpyAsync(ctx->h_res, ctx->d_res, RW * 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipEventRecord(ctx->ev[0], s));
     std::vector<int> conv_at(n, -1);
-    int remaining = n, launched = 1, polled = 0;
+    const int MI = ctx->max_iter;
+    // residual rows produced so far (row l: input residual of sweep l) and
+    // rows of the newest launch (two for a two-sweep pass)
+    int remaining = n, launched = 1, polled = 0, newest = 1;
     for (;;) {
-        // inspect the rows of all sweeps except the newest one
-        while (remaining > 0 && (polled < launched - 1 || launched == ctx->max_iter) && polled < launched) {
+        // inspect the rows of all launches except the newest one
+        while (remaining > 0 && polled < launched && (polled < launched - newest || launched >= MI)) {
             HIPCHK(hipEventSynchronize(ctx->ev[polled]));
             for (int i = 0; i < n; ++i) {
                 if (conv_at[i] >= 0) continue;
@@ -810,22 +830,26 @@ tdgl_status jacobi_loop(tdgl_ctx *ctx, tdgl_step_stats *acc, bool *strict_fail, 
             }
             ++polled;
         }
-        if (remaining == 0 || launched == ctx->max_iter) break;
+        if (remaining == 0 || launched >= MI) break;
         const int l = launched;
+        const int nr = ctx->fused ? std::min(2, MI - l) : 1;
         {
             ProfScope ps(ctx, TDGL_K_SWEEP);
-            launch_stencil<MODE_SWEEP>(ctx, l);
+            if (ctx->fused) launch_sweep2(ctx, l);
+            else launch_stencil<MODE_SWEEP>(ctx, l);
         }
         LAUNCHCHK();
-        HIPCHK(hipMemcpyAsync(ctx->h_res + (size_t)l * RW, ctx->d_res + (size_t)l * RW, RW * 4,
+        HIPCHK(hipMemcpyAsync(ctx->h_res + (size_t)l * RW, ctx->d_res + (size_t)l * RW, (size_t)nr * RW * 4,
                               hipMemcpyDeviceToHost, s));
-        HIPCHK(hipEventRecord(ctx->ev[l], s));
-        ++launched;
+        for (int q = 0; q < nr; ++q) HIPCHK(hipEventRecord(ctx->ev[l + q], s));
+        launched += nr;
+        newest = nr;
     }
     {
         ProfScope ps(ctx, TDGL_K_OTHER);
         hipLaunchKernelGGL(k_solve_finalize, dim3(cdiv(n, 64)), dim3(64), 0, s, ctx->d_inst, n, count_step,
-                           launched);
+                           launched, ctx->fused ? 1 : 0);
+        if (ctx->fused) launch_stencil<MODE_SWEEP>(ctx, -2);  // corrective sweep where needed
     }
     LAUNCHCHK();
     for (int i = 0; acc && i < n; ++i) {
@@ -833,6 +857,7 @@ tdgl_status jacobi_loop(tdgl_ctx *ctx, tdgl_step_stats *acc, bool *strict_fail, 
         const float r = ctx->host_row_max(ctx->h_res, conv_at[i], i);
         const bool capped = !(r < (float)h.p.tol);
         const int sw = capped ? h.p.max_iter : conv_at[i] + 1;
+        acc->sweep_passes += ctx->fused ? sw / 2 : sw - 1;
         acc->sweeps_min = std::min(acc->sweeps_min, sw);
         acc->sweeps_max = std::max(acc->sweeps_max, sw);
         acc->sweeps_sum += sw;
@@ -960,8 +985,13 @@ tdgl_status enqueue_step_fixed(tdgl_ctx *ctx, int budget) {
     const int n = ctx->n;
     hipStream_t s = ctx->stream;
     launch_stencil<MODE_FIRST>(ctx, 0);
-    for (int l = 1; l < budget; ++l) launch_stencil<MODE_SWEEP>(ctx, l);
-    hipLaunchKernelGGL(k_solve_finalize, dim3(cdiv(n, 64)), dim3(64), 0, s, ctx->d_inst, n, 1, budget);
+    if (ctx->fused)
+        for (int l = 1; l < budget; l += 2) launch_sweep2(ctx, l);
+    else
+        for (int l = 1; l < budget; ++l) launch_stencil<MODE_SWEEP>(ctx, l);
+    hipLaunchKernelGGL(k_solve_finalize, dim3(cdiv(n, 64)), dim3(64), 0, s, ctx->d_inst, n, 1, budget,
+                       ctx->fused ? 1 : 0);
+    if (ctx->fused) launch_stencil<MODE_SWEEP>(ctx, -2);
     LAUNCHCHK();
     if (!ctx->any_driven) return TDGL_OK;
     hipLaunchKernelGGL(k_jav_partial, dim3(ctx->tot_flat), dim3(256), 0, s, ctx->d_inst, ctx->d_pref_flat, n);
@@ -1387,6 +1417,7 @@ tdgl_status tdgl_step_graph(tdgl_ctx *ctx, int nsteps, int budget, tdgl_step_sta
             DevState d;
             HIPCHK(hipMemcpy(&d, ctx->inst[i].d.st, sizeof d, hipMemcpyDeviceToHost));
             a.sweeps_sum += (long long)d.acc_sweeps;
+            a.sweep_passes += (long long)d.acc_passes;
             a.capped_steps += (int)d.acc_capped;
             a.mu_cycles_sum += (int)d.acc_mu_cycles;
             a.mu_capped_steps += (int)d.acc_mu_capped;
@@ -1448,12 +1479,14 @@ struct Tiling {
     int rows = 2;
     int chunk = 0;  // 0: heuristic
     int nt = 0;     // streaming hints
+    int fused = 0;  // two-sweep passes
 };
 
 tdgl_status apply_tiling(tdgl_ctx *ctx, const Tiling &t) {
     drop_graph(ctx);
     ctx->rows = t.rows;
     ctx->nt = t.nt != 0;
+    ctx->fused = t.fused != 0;
     for (auto &h : ctx->inst) set_tiling(h, t.rows, t.chunk);
     return upload_tiling(ctx);
 }
@@ -1482,13 +1515,14 @@ bool tune_file_lookup(const char *path, const std::string &key, Tiling *t, doubl
     bool found = false;
     while (fgets(line, sizeof line, f)) {
         char k[4000];
-        int r, c, nt;
+        int r, c, nt, fu;
         double u;
-        if (sscanf(line, "%3999s %d %d %d %lf", k, &r, &c, &nt, &u) == 5 && key == k &&
-            (r == 1 || r == 2 || r == 4) && c >= 0 && (nt == 0 || nt == 1)) {
+        if (sscanf(line, "%3999s %d %d %d %d %lf", k, &r, &c, &nt, &fu, &u) == 6 && key == k &&
+            (r == 1 || r == 2 || r == 4) && c >= 0 && (nt == 0 || nt == 1) && (fu == 0 || fu == 1)) {
             t->rows = r;
             t->chunk = c;
             t->nt = nt;
+            t->fused = fu;
             *us = u;
             found = true;  // the last entry wins
         }
@@ -1526,6 +1560,7 @@ tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *ch
         const int chunks[] = {0, 4, 8, 16, 32, 64};
         const int rows[] = {1, 2, 4};
         best_us = 1e300;
+        for (int fu = 0; fu < 2; ++fu)
         for (int nt = 0; nt < 2; ++nt)
         for (int r : rows)
             for (int c : chunks) {
@@ -1533,18 +1568,24 @@ tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *ch
                 t.rows = r;
                 t.chunk = c;
                 t.nt = nt;
+                t.fused = fu;
                 tdgl_status e = apply_tiling(ctx, t);
                 if (e) return e;
-                launch_stencil<MODE_SWEEP>(ctx, -1);  // warm-up
+                auto pass = [&]() {
+                    if (fu) launch_sweep2(ctx, -1);
+                    else launch_stencil<MODE_SWEEP>(ctx, -1);
+                };
+                pass();  // warm-up
                 HIPCHK(hipEventRecord(e0, s));
                 const int reps = 4;
-                for (int q = 0; q < reps; ++q) launch_stencil<MODE_SWEEP>(ctx, -1);
+                for (int q = 0; q < reps; ++q) pass();
                 HIPCHK(hipEventRecord(e1, s));
                 LAUNCHCHK();
                 HIPCHK(hipEventSynchronize(e1));
                 float ms = 0.f;
                 HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                const double us = 1e3 * ms / reps;
+                // time per Jacobi iteration (a two-sweep pass makes two)
+                const double us = 1e3 * ms / reps / (fu ? 2 : 1);
                 if (us < best_us) {
                     best_us = us;
                     best = t;
@@ -1555,7 +1596,7 @@ tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *ch
         if (cache_path) {
             FILE *f = fopen(cache_path, "a");
             if (f) {
-                fprintf(f, "%s %d %d %d %.3f\n", key.c_str(), best.rows, best.chunk, best.nt, best_us);
+                fprintf(f, "%s %d %d %d %d %.3f\n", key.c_str(), best.rows, best.chunk, best.nt, best.fused, best_us);
                 fclose(f);
             }
         }
@@ -1570,9 +1611,25 @@ tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *ch
         chosen->rows = best.rows;
         chosen->chunk = ctx->inst[0].d.chunk;
         chosen->streaming = best.nt;
+        chosen->fused = best.fused;
         chosen->sweep_us = best_us;
     }
     return TDGL_OK;
+}
+
+tdgl_status tdgl_set_tiling(tdgl_ctx *ctx, const tdgl_tiling *t) {
+    if (!ctx || !t) return fail(TDGL_EINVAL, "null argument");
+    if (t->rows != 1 && t->rows != 2 && t->rows != 4) return fail(TDGL_EINVAL, "rows must be 1, 2 or 4");
+    if (t->chunk < 0 || t->chunk > 1024) return fail(TDGL_EINVAL, "chunk must be in [0, 1024]");
+    if ((t->streaming != 0 && t->streaming != 1) || (t->fused != 0 && t->fused != 1))
+        return fail(TDGL_EINVAL, "streaming and fused must be 0 or 1");
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    Tiling s;
+    s.rows = t->rows;
+    s.chunk = t->chunk;
+    s.nt = t->streaming;
+    s.fused = t->fused;
+    return apply_tiling(ctx, s);
 }
 
 tdgl_status tdgl_get_tiling(const tdgl_ctx *ctx, int inst, tdgl_tiling *out) {
@@ -1581,6 +1638,7 @@ tdgl_status tdgl_get_tiling(const tdgl_ctx *ctx, int inst, tdgl_tiling *out) {
     out->rows = ctx->rows;
     out->chunk = ctx->inst[inst].d.chunk;
     out->streaming = ctx->nt ? 1 : 0;
+    out->fused = ctx->fused ? 1 : 0;
     out->sweep_us = 0.0;
     return TDGL_OK;
 }

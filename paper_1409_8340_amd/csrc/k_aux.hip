@@ -42,9 +42,9 @@ __global__ void k_links(const Inst *__restrict__ insts, int which) {
 // End of a Jacobi solve: the first sweep l whose input residual met tol ends
 // the solve with that sweep's output (Eq. convergence); otherwise the cap,
 // which is the instance's max_iter or the nl sweeps launched, whichever is
-// smaller.  Updates the psi buffer index, step counters and clears the
+// smaller.  fused: the sweeps after the first ran as two-sweep passes.  Updates the psi buffer index, step counters and clears the
 // residual words for the next step.  One thread per instance.
-__global__ void k_solve_finalize(const Inst *__restrict__ insts, int ninst, int count_step, int nl) {
+__global__ void k_solve_finalize(const Inst *__restrict__ insts, int ninst, int count_step, int nl, int fused) {
     const int ii = blockIdx.x * blockDim.x + threadIdx.x;
     if (ii >= ninst) return;
     const Inst &I = insts[ii];
@@ -58,11 +58,23 @@ __global__ void k_solve_finalize(const Inst *__restrict__ insts, int ninst, int 
     }
     st->sweeps = sweeps;
     st->capped = capped;
-    st->cur ^= (sweeps & 1);
+    if (!fused) {
+        st->cur ^= (sweeps & 1);
+        st->fix = 0;
+    } else {
+        // two-sweep passes store the odd iterates: psi^(s), s odd, sits in
+        // cur ^ ((s + 1) / 2 & 1); an even s is recomputed from psi^(s-1)
+        // into the other buffer by the corrective sweep
+        const int so = (sweeps & 1) ? sweeps : sweeps - 1;
+        const int bo = st->cur ^ (((so + 1) >> 1) & 1);
+        st->fix = (sweeps & 1) ? 0 : 1;
+        st->cur = (sweeps & 1) ? bo : (bo ^ 1);
+    }
     if (count_step) {
         st->t += I.dt;
         st->n += 1.0;
         st->acc_sweeps += sweeps;
+        st->acc_passes += fused ? sweeps / 2 : sweeps - 1;
         st->acc_capped += capped;
         st->acc_sw_min = min(st->acc_sw_min, sweeps);
         st->acc_sw_max = max(st->acc_sw_max, sweeps);
@@ -223,6 +235,7 @@ __global__ void k_acc_reset(const Inst *__restrict__ insts, int ninst) {
     st->acc_capped = 0.0;
     st->acc_mu_cycles = 0.0;
     st->acc_mu_capped = 0.0;
+    st->acc_passes = 0.0;
     st->acc_sw_min = 1 << 30;
     st->acc_sw_max = 0;
 }

@@ -20,117 +20,9 @@
 // FIRST and SWEEP also reduce max_m |r_m|^2 of their input iterate
 // (Eq. convergence) through r = M_mm (psi^(l+1) - psi^(l)).
 #include "kernels.h"
+#include "stencil.h"
 
 namespace tdgl {
-
-// Global-address-space views: pointers read out of the descriptor are
-// generic, which would make every access a FLAT instruction.  Complex values
-// move as native two-float vectors.
-typedef float v2f __attribute__((ext_vector_type(2)));
-typedef __attribute__((address_space(1))) v2f gf2;
-typedef __attribute__((address_space(1))) float gf1;
-__device__ __forceinline__ float2 ld2(const gf2 *p, unsigned i) {
-    const v2f v = p[i];
-    return make_float2(v.x, v.y);
-}
-// Streams read or written once per pass (b/M, (ht/2)/M, eps, mu, the new
-// iterate) can bypass the caches' retention with non-temporal hints, so that
-// L2 keeps the psi rows the neighbouring tiles re-read as halos.  That pays
-// when the arrays do not fit the last-level cache; for grids that stay
-// cache-resident between sweeps the hints cost time, so they are a template
-// option (NT) chosen per context.
-__device__ __forceinline__ float2 ld2nt(const gf2 *p, unsigned i) {
-    const v2f v = __builtin_nontemporal_load(&p[i]);
-    return make_float2(v.x, v.y);
-}
-__device__ __forceinline__ void st2nt(gf2 *p, unsigned i, float2 a) {
-    v2f v;
-    v.x = a.x;
-    v.y = a.y;
-    __builtin_nontemporal_store(v, &p[i]);
-}
-__device__ __forceinline__ void st2(gf2 *p, unsigned i, float2 a) {
-    v2f v;
-    v.x = a.x;
-    v.y = a.y;
-    p[i] = v;
-}
-
-// Where the value of one LDS slot comes from in every plane.  The slot at
-// (gx, gy), gx in [-1, nx], gy in [-1, ny], holds psi as the 7-point stencil
-// sees it: interior nodes are loaded; one-cell ghosts follow the boundary
-// rules of Sec. 3.3 -- plain wrap on a periodic x axis, the quasi-periodic
-// phase jump psi_{i,-1,k} = P_{i,k} psi_{i,ny-1,k} (and psi_{i,ny,k} =
-// P*_{i,k} psi_{i,0,k}) on a periodic y axis, and the Neumann ghost
-// U^* psi_{-1} = U psi_1 on an open face.  Corners and slots beyond a ragged
-// tile are zero.  The description does not depend on the plane, so it is
-// computed once per thread.
-enum { SRC_PLAIN = 0, SRC_P = 1, SRC_PCONJ = 2, SRC_FAC = 3, SRC_ZERO = 4 };
-struct CellSrc {
-    int off;      // element offset within a plane
-    int mode;
-    int px;       // x index of the phase P_{px,k}
-    float2 fac;   // constant factor (open-x ghost)
-};
-
-__device__ __forceinline__ CellSrc cell_src(const Inst &I, int gx, int gy) {
-    const int nx = I.nx, ny = I.ny;
-    const bool xin = (unsigned)gx < (unsigned)nx, yin = (unsigned)gy < (unsigned)ny;
-    CellSrc s{0, SRC_ZERO, 0, make_float2(1.f, 0.f)};
-    if (xin && yin) { s.off = gy * nx + gx; s.mode = SRC_PLAIN; return s; }
-    if (xin) {
-        if (gy == -1) {
-            if (I.per[1]) { s.off = (ny - 1) * nx + gx; s.mode = SRC_P; s.px = gx; }
-            else if (ny >= 2) { s.off = nx + gx; s.mode = SRC_PLAIN; }
-        } else if (gy == ny) {
-            if (I.per[1]) { s.off = gx; s.mode = SRC_PCONJ; s.px = gx; }
-            else if (ny >= 2) { s.off = (ny - 2) * nx + gx; s.mode = SRC_PLAIN; }
-        }
-        return s;
-    }
-    if (yin) {
-        const float2 u = I.ux[gy];
-        if (gx == -1) {
-            if (I.per[0]) { s.off = gy * nx + nx - 1; s.mode = SRC_PLAIN; }
-            else if (nx >= 2) { s.off = gy * nx + 1; s.mode = SRC_FAC; s.fac = cmul(u, u); }
-        } else if (gx == nx) {
-            if (I.per[0]) { s.off = gy * nx; s.mode = SRC_PLAIN; }
-            else if (nx >= 2) {
-                const float2 u2 = cmul(u, u);
-                s.off = gy * nx + nx - 2; s.mode = SRC_FAC; s.fac = make_float2(u2.x, -u2.y);
-            }
-        }
-    }
-    return s;
-}
-
-__device__ __forceinline__ float2 fetch(const gf2 *__restrict__ src, const gf2 *__restrict__ P,
-                                        unsigned pbase, int k, int nx, const CellSrc &s) {
-    if (s.mode == SRC_PLAIN) return ld2(src, pbase + (unsigned)s.off);
-    if (s.mode == SRC_ZERO) return make_float2(0.f, 0.f);
-    const float2 v = ld2(src, pbase + (unsigned)s.off);
-    if (s.mode == SRC_FAC) return cmul(s.fac, v);
-    const float2 ph = ld2(P, (unsigned)k * nx + s.px);
-    return s.mode == SRC_P ? cmul(ph, v) : cmulc(ph, v);
-}
-
-// z neighbour plane index of plane p in direction d (+1/-1), or -1 if none.
-__device__ __forceinline__ int zplane(const Inst &I, int p, int d) {
-    int q = p + d;
-    if (q >= 0 && q < I.nz) return q;
-    if (!I.per[2]) return -1;
-    return q < 0 ? I.nz - 1 : 0;
-}
-
-// Halo cell handled by thread t (t < 2 TX + 2 TYv) of a TX x TYv tile at
-// (x0, y0): rows y0-1 and y0+TYv (TX cells each), columns x0-1 and x0+TX.
-template <int TYv>
-__device__ __forceinline__ void halo_cell(int t, int x0, int y0, int &gx, int &gy, int &lx, int &ly) {
-    if (t < TX) { gx = x0 + t; gy = y0 - 1; lx = t + 1; ly = 0; }
-    else if (t < 2 * TX) { gx = x0 + t - TX; gy = y0 + TYv; lx = t - TX + 1; ly = TYv + 1; }
-    else if (t < 2 * TX + TYv) { gx = x0 - 1; gy = y0 + t - 2 * TX; lx = 0; ly = t - 2 * TX + 1; }
-    else { gx = x0 + TX; gy = y0 + t - 2 * TX - TYv; lx = TX + 1; ly = t - 2 * TX - TYv + 1; }
-}
 
 // MODE selects the pass; R is the number of consecutive rows a thread owns
 // (tile 64 x 4R: a larger R streams more per thread, a smaller one keeps
@@ -149,12 +41,18 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
     const int ii = find_inst(prefix, ninst, b);
     const Inst &I = insts[ii];
     DevState *st = I.st;
-    // l < 0 (sweep only): a timing pass for the tile autotuner -- reads the
+    // l = -1 (sweep only): a timing pass for the tile autotuner -- reads the
     // current psi, writes the spare buffer, skips the convergence test and
     // records no residual, so the solver state is left as it was.
-    const bool timing = (MODE == MODE_SWEEP) && l < 0;
+    // l = -2: the corrective sweep of two-sweep mode -- when the solve ended
+    // on an even iterate, recompute it from the odd one in psi[cur ^ 1] into
+    // psi[cur] (no residual row).
+    const bool timing = (MODE == MODE_SWEEP) && l == -1;
+    const bool fixp = (MODE == MODE_SWEEP) && l == -2;
+    if (fixp && !st->fix) return;
     if (timing) l = 0;
-    if (MODE == MODE_SWEEP && !timing) {
+    if (fixp) l = 1;
+    if (MODE == MODE_SWEEP && !timing && !fixp) {
         // The previous sweep's input residual met the tolerance (or this
         // instance's cap is reached): its solve is complete and the launch
         // is a no-op for it.
@@ -310,15 +208,7 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
             }
             // off-diagonal neighbour sum NS of the covariant Laplacian
             // (Eq. LaplUV_xz), open faces doubling the inner neighbour.
-            float2 zt;
-            if (zm && zp) zt = cadd(cmul(uz[r], pn[r]), cmulc(uz[r], pm[r]));
-            else if (zp) zt = cscale(2.f, cmul(uz[r], pn[r]));
-            else if (zm) zt = cscale(2.f, cmulc(uz[r], pm[r]));
-            else zt = make_float2(0.f, 0.f);
-            const float2 xt = cadd(cmul(ux[r], xp), cmulc(ux[r], xm));
-            const float2 yt = cadd(yp, ym);
-            const float2 ns = make_float2(cx * xt.x + cy * yt.x + cz * zt.x,
-                                          cx * xt.y + cy * yt.y + cz * zt.y);
+            const float2 ns = nsum(ux[r], uz[r], xm, xp, ym, yp, pm[r], pn[r], zm, zp, cx, cy, cz);
             if (MODE == MODE_NS) {
                 st2(nsout, m, ns);
                 continue;
@@ -357,9 +247,8 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
                 const float r2 = cabs2(M) * cabs2(d);
                 rmax = (r2 > rmax || r2 != r2) ? r2 : rmax;
             } else {
-                nw = cadd(bh[r], cmul(dh[r], ns));
-                const float2 d = csub(nw, c);
-                const float r2 = cabs2(d) * (ht2 * ht2) / cabs2(dh[r]);
+                nw = jacobi(bh[r], dh[r], ns);
+                const float r2 = resid2(nw, c, dh[r], ht2);
                 rmax = (r2 > rmax || r2 != r2) ? r2 : rmax;
             }
             if (NT) st2nt(dst, m, nw);
@@ -383,7 +272,7 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
     if (MODE == MODE_NS) {
         return;
     } else if (MODE == MODE_FIRST || MODE == MODE_SWEEP) {
-        if (timing) return;
+        if (timing || fixp) return;
         __syncthreads();
         wg_max_to<WG>(row_slot(I.res, I.rstride, l, b), rmax, reinterpret_cast<float *>(red));
     } else {

@@ -8,12 +8,14 @@ enum { MODE_FIRST = 0, MODE_SWEEP = 1, MODE_RHS = 2, MODE_ENERGY = 3, MODE_NS = 
 constexpr int JAV_CPT = 16;     // cells per thread of the flat reductions
 constexpr int CO_THREADS = 1024;
 
+template <int R, bool NT>
+__global__ void k_sweep2(const Inst *insts, const int *prefix, int ninst, int l);
 template <int MODE, int R, bool NT>
 __global__ void k_stencil(const Inst *insts, const int *prefix, int ninst, int l, const float2 *ext_in,
                           float2 *ext_out);
 
 __global__ void k_links(const Inst *insts, int which);
-__global__ void k_solve_finalize(const Inst *insts, int ninst, int count_step, int nl);
+__global__ void k_solve_finalize(const Inst *insts, int ninst, int count_step, int nl, int fused);
 __global__ void k_acc_reset(const Inst *insts, int ninst);
 __global__ void k_jav_partial(const Inst *insts, const int *prefix, int ninst);
 __global__ void k_kupdate(const Inst *insts, const int *nparts);

@@ -1,0 +1,174 @@
+// stencil.h -- device helpers shared by the stencil kernels (k_gl.hip,
+// k_gl2.hip): global-address-space vector loads and stores, the boundary
+// description of a halo slot and the halo-slot mapping of a tile.
+#pragma once
+#include "kernels.h"
+
+namespace tdgl {
+
+// Global-address-space views: pointers read out of the descriptor are
+// generic, which would make every access a FLAT instruction.  Complex values
+// move as native two-float vectors.
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) v2f gf2;
+typedef __attribute__((address_space(1))) float gf1;
+__device__ __forceinline__ float2 ld2(const gf2 *p, unsigned i) {
+    const v2f v = p[i];
+    return make_float2(v.x, v.y);
+}
+// Streams read or written once per pass (b/M, (ht/2)/M, eps, mu, the new
+// iterate) can bypass the caches' retention with non-temporal hints, so that
+// L2 keeps the psi rows the neighbouring tiles re-read as halos.  That pays
+// when the arrays do not fit the last-level cache; for grids that stay
+// cache-resident between sweeps the hints cost time, so they are a template
+// option (NT) chosen per context.
+__device__ __forceinline__ float2 ld2nt(const gf2 *p, unsigned i) {
+    const v2f v = __builtin_nontemporal_load(&p[i]);
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void st2nt(gf2 *p, unsigned i, float2 a) {
+    v2f v;
+    v.x = a.x;
+    v.y = a.y;
+    __builtin_nontemporal_store(v, &p[i]);
+}
+__device__ __forceinline__ void st2(gf2 *p, unsigned i, float2 a) {
+    v2f v;
+    v.x = a.x;
+    v.y = a.y;
+    p[i] = v;
+}
+
+// The Jacobi update below is written with explicit fused multiply-adds and
+// with contraction of the remaining products and sums switched off, so that
+// no compiler contraction choice -- which can differ between the places the
+// code is inlined into -- changes a bit: every kernel that recomputes a value
+// (the two-sweep kernel's ring) gets the same one.
+__device__ __forceinline__ float2 xcmul(float2 a, float2 b) {  // a b
+#pragma clang fp contract(off)
+    return make_float2(__builtin_fmaf(a.x, b.x, -(a.y * b.y)), __builtin_fmaf(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ float2 xcmulc(float2 a, float2 b) {  // conj(a) b
+#pragma clang fp contract(off)
+    return make_float2(__builtin_fmaf(a.x, b.x, a.y * b.y), __builtin_fmaf(a.x, b.y, -(a.y * b.x)));
+}
+__device__ __forceinline__ float2 xcadd(float2 a, float2 b) {
+#pragma clang fp contract(off)
+    return make_float2(a.x + b.x, a.y + b.y);
+}
+
+// Where the value of one LDS slot comes from in every plane.  The slot at
+// (gx, gy), gx in [-1, nx], gy in [-1, ny], holds psi as the 7-point stencil
+// sees it: interior nodes are loaded; one-cell ghosts follow the boundary
+// rules of Sec. 3.3 -- plain wrap on a periodic x axis, the quasi-periodic
+// phase jump psi_{i,-1,k} = P_{i,k} psi_{i,ny-1,k} (and psi_{i,ny,k} =
+// P*_{i,k} psi_{i,0,k}) on a periodic y axis, and the Neumann ghost
+// U^* psi_{-1} = U psi_1 on an open face.  Corners and slots beyond a ragged
+// tile are zero.  The description does not depend on the plane, so it is
+// computed once per thread.
+enum { SRC_PLAIN = 0, SRC_P = 1, SRC_PCONJ = 2, SRC_FAC = 3, SRC_ZERO = 4 };
+struct CellSrc {
+    int off;      // element offset within a plane
+    int mode;
+    int px;       // x index of the phase P_{px,k}
+    float2 fac;   // constant factor (open-x ghost)
+};
+
+__device__ __forceinline__ CellSrc cell_src(const Inst &I, int gx, int gy) {
+    const int nx = I.nx, ny = I.ny;
+    const bool xin = (unsigned)gx < (unsigned)nx, yin = (unsigned)gy < (unsigned)ny;
+    CellSrc s{0, SRC_ZERO, 0, make_float2(1.f, 0.f)};
+    if (xin && yin) { s.off = gy * nx + gx; s.mode = SRC_PLAIN; return s; }
+    if (xin) {
+        if (gy == -1) {
+            if (I.per[1]) { s.off = (ny - 1) * nx + gx; s.mode = SRC_P; s.px = gx; }
+            else if (ny >= 2) { s.off = nx + gx; s.mode = SRC_PLAIN; }
+        } else if (gy == ny) {
+            if (I.per[1]) { s.off = gx; s.mode = SRC_PCONJ; s.px = gx; }
+            else if (ny >= 2) { s.off = (ny - 2) * nx + gx; s.mode = SRC_PLAIN; }
+        }
+        return s;
+    }
+    if (yin) {
+        const float2 u = I.ux[gy];
+        if (gx == -1) {
+            if (I.per[0]) { s.off = gy * nx + nx - 1; s.mode = SRC_PLAIN; }
+            else if (nx >= 2) { s.off = gy * nx + 1; s.mode = SRC_FAC; s.fac = xcmul(u, u); }
+        } else if (gx == nx) {
+            if (I.per[0]) { s.off = gy * nx; s.mode = SRC_PLAIN; }
+            else if (nx >= 2) {
+                const float2 u2 = xcmul(u, u);
+                s.off = gy * nx + nx - 2; s.mode = SRC_FAC; s.fac = make_float2(u2.x, -u2.y);
+            }
+        }
+    }
+    return s;
+}
+
+__device__ __forceinline__ float2 fetch(const gf2 *__restrict__ src, const gf2 *__restrict__ P,
+                                        unsigned pbase, int k, int nx, const CellSrc &s) {
+    if (s.mode == SRC_PLAIN) return ld2(src, pbase + (unsigned)s.off);
+    if (s.mode == SRC_ZERO) return make_float2(0.f, 0.f);
+    const float2 v = ld2(src, pbase + (unsigned)s.off);
+    if (s.mode == SRC_FAC) return xcmul(s.fac, v);
+    const float2 ph = ld2(P, (unsigned)k * nx + s.px);
+    return s.mode == SRC_P ? xcmul(ph, v) : xcmulc(ph, v);
+}
+
+// z neighbour plane index of plane p in direction d (+1/-1), or -1 if none.
+__device__ __forceinline__ int zplane(const Inst &I, int p, int d) {
+    int q = p + d;
+    if (q >= 0 && q < I.nz) return q;
+    if (!I.per[2]) return -1;
+    return q < 0 ? I.nz - 1 : 0;
+}
+
+// Halo cell handled by thread t (t < 2 TX + 2 TYv) of a TX x TYv tile at
+// (x0, y0): rows y0-1 and y0+TYv (TX cells each), columns x0-1 and x0+TX.
+template <int TYv>
+__device__ __forceinline__ void halo_cell(int t, int x0, int y0, int &gx, int &gy, int &lx, int &ly) {
+    if (t < TX) { gx = x0 + t; gy = y0 - 1; lx = t + 1; ly = 0; }
+    else if (t < 2 * TX) { gx = x0 + t - TX; gy = y0 + TYv; lx = t - TX + 1; ly = TYv + 1; }
+    else if (t < 2 * TX + TYv) { gx = x0 - 1; gy = y0 + t - 2 * TX; lx = 0; ly = t - 2 * TX + 1; }
+    else { gx = x0 + TX; gy = y0 + t - 2 * TX - TYv; lx = TX + 1; ly = t - 2 * TX - TYv + 1; }
+}
+
+// Off-diagonal neighbour sum NS of the covariant Laplacian at one node
+// (Eq. LaplUV_xz): x and z links of the node's row, in-plane neighbours as
+// the stencil sees them (ghosts by the boundary rules), z neighbours with
+// the open-face doubling (zm / zp: whether the plane below / above exists).
+// Every stencil kernel goes through this one function.
+__device__ __forceinline__ float2 nsum(float2 ux, float2 uz, float2 xm, float2 xp, float2 ym, float2 yp,
+                                       float2 zmv, float2 zpv, bool zm, bool zp, float cx, float cy, float cz) {
+#pragma clang fp contract(off)
+    float2 zt;
+    if (zm && zp) {
+        zt = xcadd(xcmul(uz, zpv), xcmulc(uz, zmv));
+    } else if (zp) {
+        zt = xcmul(uz, zpv);
+        zt = make_float2(2.f * zt.x, 2.f * zt.y);
+    } else if (zm) {
+        zt = xcmulc(uz, zmv);
+        zt = make_float2(2.f * zt.x, 2.f * zt.y);
+    } else {
+        zt = make_float2(0.f, 0.f);
+    }
+    const float2 xt = xcadd(xcmul(ux, xp), xcmulc(ux, xm));
+    const float2 yt = xcadd(yp, ym);
+    return make_float2(__builtin_fmaf(cx, xt.x, __builtin_fmaf(cy, yt.x, cz * zt.x)),
+                       __builtin_fmaf(cx, xt.y, __builtin_fmaf(cy, yt.y, cz * zt.y)));
+}
+
+// One Jacobi iterate (Eq. final): b/M + (ht/2)/M * NS.
+__device__ __forceinline__ float2 jacobi(float2 bh, float2 dh, float2 ns) { return xcadd(bh, xcmul(dh, ns)); }
+
+// |r|^2 of the iterate's input, r = M (new - old), |M|^2 = (ht/2)^2 / |(ht/2)/M|^2.
+__device__ __forceinline__ float resid2(float2 nw, float2 old, float2 dh, float ht2) {
+#pragma clang fp contract(off)
+    const float dx = nw.x - old.x, dy = nw.y - old.y;
+    const float d2 = __builtin_fmaf(dx, dx, dy * dy);
+    const float m2 = __builtin_fmaf(dh.x, dh.x, dh.y * dh.y);
+    return (d2 * (ht2 * ht2)) / m2;
+}
+
+}  // namespace tdgl

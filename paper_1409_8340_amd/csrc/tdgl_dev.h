@@ -54,8 +54,10 @@ struct DevState {
     double frac;      // inclusion generator: covered fraction
     float mu_last_res;// Poisson residual max-norm at the end of the last solve
     int pad2;
+    int fix;          // two-sweep mode: the result needs the corrective sweep
+    int pad3;
     // step statistics accumulated on the device (graph-replayed steps)
-    double acc_sweeps, acc_capped, acc_mu_cycles, acc_mu_capped;
+    double acc_sweeps, acc_capped, acc_mu_cycles, acc_mu_capped, acc_passes;
     int acc_sw_min, acc_sw_max;
 };
 

@@ -43,7 +43,7 @@ class StepStats(ctypes.Structure):
                 ("sweeps_max", ctypes.c_int), ("sweeps_sum", ctypes.c_longlong),
                 ("capped_steps", ctypes.c_int), ("last_res2", ctypes.c_float),
                 ("mu_cycles_sum", ctypes.c_int), ("mu_capped_steps", ctypes.c_int),
-                ("mu_last_res", ctypes.c_float)]
+                ("mu_last_res", ctypes.c_float), ("sweep_passes", ctypes.c_longlong)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -74,7 +74,7 @@ KERNEL_CLASSES = ["assemble", "sweep", "current", "rhs", "mg_fine", "mg_coarse",
 
 class Tiling(ctypes.Structure):
     _fields_ = [("rows", ctypes.c_int), ("chunk", ctypes.c_int), ("streaming", ctypes.c_int),
-                ("sweep_us", ctypes.c_double)]
+                ("fused", ctypes.c_int), ("sweep_us", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -125,6 +125,7 @@ _SIGS = {
                           ctypes.c_size_t, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p], ctypes.c_int),
     "tdgl_autotune": ([ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(Tiling)], ctypes.c_int),
     "tdgl_get_tiling": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(Tiling)], ctypes.c_int),
+    "tdgl_set_tiling": ([ctypes.c_void_p, ctypes.POINTER(Tiling)], ctypes.c_int),
     "tdgl_profile_start": ([ctypes.c_void_p, ctypes.c_uint], ctypes.c_int),
     "tdgl_profile_stop": ([ctypes.c_void_p, ctypes.POINTER(Prof)], ctypes.c_int),
 }
@@ -341,6 +342,10 @@ class Solver:
         path = None if cache_path is None else str(cache_path).encode()
         _check(load().tdgl_autotune(self._ctx, path, ctypes.byref(t)))
         return t.as_dict()
+
+    def set_tiling(self, rows=2, chunk=0, streaming=0, fused=0):
+        t = Tiling(rows=rows, chunk=chunk, streaming=streaming, fused=fused, sweep_us=0.0)
+        _check(load().tdgl_set_tiling(self._ctx, ctypes.byref(t)))
 
     def tiling(self, inst=0):
         t = Tiling()

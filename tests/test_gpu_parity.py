@@ -259,3 +259,58 @@ def test_poisson_solver_vs_exact(shape, open_, solver):
     err = rel_maxerr(mu, ref)
     print(shape, open_, solver, "rel err", err)
     assert err <= (2e-5 if solver == 0 and not open_[1] and open_[2] else 2e-4)
+
+
+FUSED_CASES = [
+    # shape, open, Bx, Bz, driven
+    ((70, 37, 9), (False, False, True), 0.0, 0.1, True),     # ragged x and y tiles, quasi-periodic y
+    ((40, 24, 12), (True, True, True), 0.2, 0.3, False),     # open x, y, z with a tilted field
+    ((32, 32, 8), (False, False, False), 0.0, 0.1, True),    # periodic z
+    ((48, 20, 1), (False, False, True), 0.0, 0.1, False),    # one plane
+    ((16, 16, 40), (False, True, False), 0.15, 0.0, False),  # open y, periodic z, field along x
+    ((65, 9, 5), (True, False, True), 0.0, 0.2, False),      # a one-column tile at the open x face
+]
+
+
+@pytest.mark.parametrize("shape,open_,Bx,Bz,driven", FUSED_CASES)
+@pytest.mark.parametrize("rows", [1, 2])
+def test_two_sweep_passes_bit_identical(shape, open_, Bx, Bz, driven, rows):
+    """Two Jacobi sweeps per pass (ring recomputed from global memory, odd
+    iterates stored, corrective sweep for even endings) give the iterates of
+    single sweeps bit for bit, with the same statistics, also through graph
+    replays and with capped solves."""
+    nx, ny, nz = shape
+    eps = inputs.random_real((nz, ny, nx), 5, 0.4, 1.0)
+    kw = dict(open_=open_, Bx=Bx, Bz=Bz, eps=eps, tol=1e-10, psi_seed=9, driven=driven,
+              J=0.02 if driven else 0.0)
+    c = Case(nx, ny, nz, **kw)
+    a = c.solver()
+    f = c.solver()
+    a.set_tiling(rows=rows, chunk=4, fused=0)
+    f.set_tiling(rows=rows, chunk=4, fused=1)
+    for rep in range(3):
+        sa = a.step(2)
+        sf = f.step(2)
+        for k in ("sweeps_sum", "sweeps_min", "sweeps_max", "capped_steps"):
+            assert sa[k] == sf[k], (rep, k, sa, sf)
+        assert np.array_equal(a.get_psi().cpu().numpy(), f.get_psi().cpu().numpy()), rep
+    sg = f.step_graph(2)
+    sa = a.step(2)
+    assert sa["sweeps_sum"] == sg["sweeps_sum"]
+    assert np.array_equal(a.get_psi().cpu().numpy(), f.get_psi().cpu().numpy())
+    # capped solves with an even and an odd cap
+    for cap in (4, 5):
+        ca = Case(nx, ny, nz, **{**kw, "tol": 1e-30})
+        ca.params.max_iter = cap
+        x = ca.solver()
+        y = ca.solver()
+        x.set_tiling(rows=rows, chunk=4, fused=0)
+        y.set_tiling(rows=rows, chunk=4, fused=1)
+        sx, sy = x.step(1), y.step(1)
+        assert sx["capped_steps"] == sy["capped_steps"] == 1 and sy["sweeps_sum"] == cap
+        assert np.array_equal(x.get_psi().cpu().numpy(), y.get_psi().cpu().numpy()), cap
+        x.close()
+        y.close()
+    print(f"[fused] {shape} {open_} rows={rows} sweeps {sa['sweeps_sum']} passes {sf['sweep_passes']}")
+    a.close()
+    f.close()
