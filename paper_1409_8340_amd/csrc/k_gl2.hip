@@ -77,13 +77,36 @@ __device__ __forceinline__ float2 slot_update(const Inst &I, const gf2 *__restri
 
 }  // namespace
 
+// Slot h of the two-node halo of a TX x TYv tile at (x0, y0): rows y0-2,
+// y0-1 and y0+TYv, y0+TYv+1 (TX + 4 wide), then columns x0-2, x0-1, x0+TX,
+// x0+TX+1 of the tile's rows.  (lx, ly): index in the (TX+4) x (TYv+4) LDS
+// plane.
+template <int TYv>
+__device__ __forceinline__ void halo2_cell(int h, int x0, int y0, int &gx, int &gy, int &lx, int &ly) {
+    constexpr int LX = TX + 4;
+    if (h < 4 * LX) {
+        const int rr = h / LX, c = h - rr * LX;
+        ly = rr < 2 ? rr : TYv + rr;
+        lx = c;
+    } else {
+        const int q = h - 4 * LX, cc = q / TYv, r = q - cc * TYv;
+        lx = cc < 2 ? cc : TX + cc;
+        ly = r + 2;
+    }
+    gx = x0 + lx - 2;
+    gy = y0 + ly - 2;
+}
+
 template <int R, bool NT>
 __global__ __launch_bounds__(WG) void k_sweep2(const Inst *__restrict__ insts, const int *__restrict__ prefix,
                                                int ninst, int l) {
     constexpr int TYv = 4 * R;
-    constexpr int HALOv = 2 * TX + 2 * TYv;
-    __shared__ float2 la[2][TYv + 2][LDX];  // psi^(l) of one plane, one-cell halo
-    __shared__ float2 lb[2][TYv + 2][LDX];  // psi^(l+1) of one plane, tile + ring
+    constexpr int LX = TX + 4, LY = TYv + 4;
+    constexpr int NH2 = LX * LY - TX * TYv;   // two-node halo slots of psi^(l)
+    constexpr int HALOv = 2 * TX + 2 * TYv;   // one-node ring of psi^(l+1)
+    static_assert(NH2 <= 2 * WG, "two halo slots per thread at most");
+    __shared__ float2 la[4][LY][LX];          // psi^(l) planes v-1 .. v+2, two-node halo
+    __shared__ float2 lb[2][TYv + 2][LDX];    // psi^(l+1) planes v-1, v: tile + ring
     __shared__ float red[WG / 64];
 
     const int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -127,6 +150,7 @@ __global__ __launch_bounds__(WG) void k_sweep2(const Inst *__restrict__ insts, c
     const gf2 *__restrict__ dhp = (const gf2 *)I.dh;
     const float cx = I.cx, cy = I.cy, cz = I.cz, ht2 = I.ht2;
 
+    // own nodes
     float2 ux[R], uz[R];
     bool vy[R];
     CellSrc own[R];
@@ -136,17 +160,57 @@ __global__ __launch_bounds__(WG) void k_sweep2(const Inst *__restrict__ insts, c
         vy[r] = (x < nx) && (y < ny);
         ux[r] = (y < ny) ? I.ux[y] : make_float2(1.f, 0.f);
         uz[r] = (y < ny) ? I.uz[y] : make_float2(1.f, 0.f);
-        own[r] = cell_src(I, x, y);
+        // the two-node rules: a ring slot's tile path may read an own slot
+        // two nodes beyond the grid in a ragged tile
+        own[r] = cell_src2(I, x, y);
     }
-    // halo / ring slot of this thread; the slot index is spread over the
-    // wavefronts so that the ring's extra updates balance between them
+    // two-node halo slots of psi^(l) this thread stages (h = tid, tid + WG)
+    CellSrc h2s[2];
+    int h2lx[2], h2ly[2];
+    bool h2on[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int h = threadIdx.x + q * WG;
+        h2on[q] = h < NH2;
+        int gx = 0, gy = 0;
+        h2lx[q] = h2ly[q] = 0;
+        h2s[q] = CellSrc{0, SRC_ZERO, 0, make_float2(1.f, 0.f)};
+        if (h2on[q]) {
+            halo2_cell<TYv>(h, x0, y0, gx, gy, h2lx[q], h2ly[q]);
+            h2s[q] = cell_src2(I, gx, gy);
+        }
+    }
+    // ring slot of psi^(l+1) (index spread over the wavefronts).  Ring
+    // values follow their slot's boundary rule from a real source node.
+    // Tile path: the source's neighbourhood is in the LDS planes (in-range
+    // nodes, x wraps taken at the slot's own position, open-face mirrors at
+    // the mirror node); global path: slots carrying the quasi-periodic y
+    // phase, computed from global memory.
     const int hidx = lane * 4 + w;
     const bool hthr = hidx < HALOv;
-    int hgx = 0, hgy = 0, hlx = 0, hly = 0;
-    CellSrc hs{0, SRC_ZERO, 0, make_float2(1.f, 0.f)};
+    int rlx = 0, rly = 0;               // slot in lb
+    int rmode = 0;                      // 0: zero, 1: tile path, 2: global path
+    int tlx = 0, tly = 0;               // tile-path source in la
+    unsigned rso = 0;                   // source node's in-plane offset
+    float2 rux = make_float2(1.f, 0.f), ruz = make_float2(1.f, 0.f), rfac = make_float2(1.f, 0.f);
+    CellSrc rs{0, SRC_ZERO, 0, make_float2(1.f, 0.f)};
     if (hthr) {
-        halo_cell<TYv>(hidx, x0, y0, hgx, hgy, hlx, hly);
-        hs = cell_src(I, hgx, hgy);
+        int gx, gy;
+        halo_cell<TYv>(hidx, x0, y0, gx, gy, rlx, rly);
+        rs = cell_src(I, gx, gy);
+        if (rs.mode == SRC_P || rs.mode == SRC_PCONJ) {
+            rmode = 2;
+        } else if (rs.mode != SRC_ZERO) {
+            rmode = 1;
+            rso = (unsigned)rs.off;
+            const int sy = rs.off / nx, sx = rs.off - sy * nx;
+            const bool xwrap = (gx < 0 || gx >= nx) && I.per[0];
+            tlx = (xwrap ? gx : sx) - x0 + 2;
+            tly = sy - y0 + 2;
+            rux = I.ux[sy];
+            ruz = I.uz[sy];
+            rfac = rs.mode == SRC_FAC ? rs.fac : make_float2(1.f, 0.f);
+        }
     }
 
     // virtual plane v -> stored plane (-1: none)
@@ -155,11 +219,23 @@ __global__ __launch_bounds__(WG) void k_sweep2(const Inst *__restrict__ insts, c
         if (!zper) return -1;
         return ((v % nz) + nz) % nz;
     };
-    auto own_plane = [&](int p, float2 *out) {
+    // psi^(l) of plane p: own values and halo values into registers
+    auto load_a = [&](int p, float2 *ao, float2 *hv) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) out[r] = (p < 0) ? make_float2(0.f, 0.f) : fetch(src, Pt, (unsigned)p * NXY, p, nx, own[r]);
+        for (int r = 0; r < R; ++r) ao[r] = (p < 0) ? make_float2(0.f, 0.f) : fetch(src, Pt, (unsigned)p * NXY, p, nx, own[r]);
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            hv[q] = (p < 0 || !h2on[q]) ? make_float2(0.f, 0.f) : fetch(src, Pt, (unsigned)p * NXY, p, nx, h2s[q]);
     };
-    auto load_bd = [&](int p, float2 *bh_, float2 *dh_) {
+    auto stage_a = [&](int v, const float2 *ao, const float2 *hv) {
+        float2 (*L)[LX] = la[v & 3];
+#pragma unroll
+        for (int r = 0; r < R; ++r) L[2 + w * R + r][2 + lane] = ao[r];
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            if (h2on[q]) L[h2ly[q]][h2lx[q]] = hv[q];
+    };
+    auto load_bd = [&](int p, float2 *bh_, float2 *dh_, float2 &rbh, float2 &rdh) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (p >= 0 && vy[r]) {
@@ -171,78 +247,89 @@ __global__ __launch_bounds__(WG) void k_sweep2(const Inst *__restrict__ insts, c
                 dh_[r] = make_float2(1.f, 0.f);
             }
         }
+        if (p >= 0 && rmode == 1) {
+            rbh = ld2(bhp, (unsigned)p * NXY + rso);
+            rdh = ld2(dhp, (unsigned)p * NXY + rso);
+        } else {
+            rbh = make_float2(0.f, 0.f);
+            rdh = make_float2(1.f, 0.f);
+        }
     };
 
-    // psi^(l+1) planes v-1 .. k1 feed psi^(l+2) on k0 .. k1-1
+    // psi^(l+1) planes vb0 .. k1 feed psi^(l+2) on k0 .. k1-1; psi^(l) is
+    // needed on vb0-1 .. k1+1
     const int vb0 = (pz(k0 - 1) >= 0) ? k0 - 1 : k0;
-    const int ve = k1;  // last step (psi^(l+1) only if that plane exists)
+    const int ve = k1;
+    auto needed_a = [&](int v) { return v >= vb0 - 1 && v <= k1 + 1 && pz(v) >= 0; };
 
-    float2 am[R], ac[R], an[R];  // psi^(l) own: planes v-1, v, v+1
-    float2 b2[R], b1[R];         // psi^(l+1) own: planes v-2, v-1
-    float2 bhc[R], dhc[R];       // b/M, (ht/2)/M of plane v
-    float2 bhq[R], dhq[R];       // ... of plane v-1
-    own_plane(pz(vb0 - 1), am);
-    own_plane(pz(vb0), ac);
-    own_plane(pz(vb0 + 1), an);
-    load_bd(pz(vb0), bhc, dhc);
+    {
+        float2 ao[R], hv[2];
+        for (int v = vb0 - 1; v <= vb0 + 1; ++v)
+            if (needed_a(v)) {
+                load_a(pz(v), ao, hv);
+                stage_a(v, ao, hv);
+            }
+    }
+    float2 an2[R], hn2[2];  // psi^(l) of plane v + 2 (staged in step v)
+    load_a(needed_a(vb0 + 2) ? pz(vb0 + 2) : -1, an2, hn2);
+    float2 bhc[R], dhc[R], rbhc, rdhc;  // b/M, (ht/2)/M of plane v (own, ring source)
+    load_bd(pz(vb0), bhc, dhc, rbhc, rdhc);
+    float2 b2[R], b1[R], bhq[R], dhq[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         b2[r] = b1[r] = make_float2(0.f, 0.f);
         bhq[r] = make_float2(0.f, 0.f);
         dhq[r] = make_float2(1.f, 0.f);
     }
-    {
-        const int p = pz(vb0);
-        if (p >= 0) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) la[vb0 & 1][1 + w * R + r][1 + lane] = ac[r];
-            if (hthr) la[vb0 & 1][hly][hlx] = fetch(src, Pt, (unsigned)p * NXY, p, nx, hs);
-        }
-    }
-    float2 hv = make_float2(0.f, 0.f);
-    if (hthr && pz(vb0 + 1) >= 0) hv = fetch(src, Pt, (unsigned)pz(vb0 + 1) * NXY, pz(vb0 + 1), nx, hs);
 
     float rmax1 = 0.f, rmax2 = 0.f;
     for (int v = vb0; v <= ve; ++v) {
         const int p = pz(v);
-        const bool stageA = (p >= 0) && v <= k1;
+        const bool stageA = (p >= 0);
         const bool stageB = (v - 1 >= k0) && (v - 1 < k1);
-        const int pn1 = pz(v + 1), pn2 = pz(v + 2);
-        // next planes' loads, issued before the barrier
-        float2 ann[R], bhn[R], dhn[R];
-        float2 hvn = make_float2(0.f, 0.f);
-        own_plane(v + 2 <= k1 + 1 ? pn2 : -1, ann);
-        load_bd(v + 1 <= k1 ? pn1 : -1, bhn, dhn);
-        if (hthr && v + 2 <= k1 && pn2 >= 0) hvn = fetch(src, Pt, (unsigned)pn2 * NXY, pn2, nx, hs);
-        __syncthreads();  // la[v] and lb[v - 1] complete; the other buffers are free
-        if (v + 1 <= k1 && pn1 >= 0) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) la[(v + 1) & 1][1 + w * R + r][1 + lane] = an[r];
-            if (hthr) la[(v + 1) & 1][hly][hlx] = hv;
-        }
+        // next loads, issued before the barrier
+        float2 an3[R], hn3[2], bhn[R], dhn[R], rbhn, rdhn;
+        load_a(needed_a(v + 3) ? pz(v + 3) : -1, an3, hn3);
+        load_bd(v + 1 <= k1 ? pz(v + 1) : -1, bhn, dhn, rbhn, rdhn);
+        __syncthreads();  // planes v-1 .. v+1 of psi^(l) and plane v-1 of psi^(l+1) complete
+        if (needed_a(v + 2)) stage_a(v + 2, an2, hn2);
         float2 b0[R];
         if (stageA) {
-            // psi^(l+1) on plane v: own nodes from LDS ...
-            const int lb_ = v & 1;
+            const float2 (*L)[LX] = la[v & 3];
+            const float2 (*Lm)[LX] = la[(v + 3) & 3];  // plane v - 1
+            const float2 (*Lp)[LX] = la[(v + 1) & 3];  // plane v + 1
+            const int lq = v & 1;
             const bool zm = (p > 0) || zper, zp = (p < nz - 1) || zper;
+            // psi^(l+1) on the tile
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const int ly = 1 + w * R + r;
-                const float2 xm = la[lb_][ly][lane], xp = la[lb_][ly][lane + 2];
-                const float2 ym = la[lb_][ly - 1][lane + 1], yp = la[lb_][ly + 1][lane + 1];
+                const int ly = 2 + w * R + r, lx = 2 + lane;
                 if (vy[r]) {
-                    const float2 ns = nsum(ux[r], uz[r], xm, xp, ym, yp, am[r], an[r], zm, zp, cx, cy, cz);
+                    const float2 c = L[ly][lx];
+                    const float2 ns = nsum(ux[r], uz[r], L[ly][lx - 1], L[ly][lx + 1], L[ly - 1][lx], L[ly + 1][lx],
+                                           Lm[ly][lx], Lp[ly][lx], zm, zp, cx, cy, cz);
                     b0[r] = jacobi(bhc[r], dhc[r], ns);
-                    const float r2 = resid2(b0[r], ac[r], dhc[r], ht2);
+                    const float r2 = resid2(b0[r], c, dhc[r], ht2);
                     rmax1 = (r2 > rmax1 || r2 != r2) ? r2 : rmax1;
                 } else {
                     // a node outside the grid in a ragged tile: its ghost value
                     b0[r] = slot_update(I, src, Pt, bhp, dhp, own[r], p, NXY, zper);
                 }
-                lb[lb_][ly][1 + lane] = b0[r];
+                lb[lq][ly - 1][lx - 1] = b0[r];
             }
-            // ... and the ring from the source nodes' updates
-            if (hthr) lb[lb_][hly][hlx] = slot_update(I, src, Pt, bhp, dhp, hs, p, NXY, zper);
+            // ... and on the ring
+            if (hthr) {
+                float2 val = make_float2(0.f, 0.f);
+                if (rmode == 1) {
+                    const float2 ns = nsum(rux, ruz, L[tly][tlx - 1], L[tly][tlx + 1], L[tly - 1][tlx],
+                                           L[tly + 1][tlx], Lm[tly][tlx], Lp[tly][tlx], zm, zp, cx, cy, cz);
+                    val = jacobi(rbhc, rdhc, ns);
+                    if (rs.mode == SRC_FAC) val = xcmul(rfac, val);
+                } else if (rmode == 2) {
+                    val = slot_update(I, src, Pt, bhp, dhp, rs, p, NXY, zper);
+                }
+                lb[lq][rly][rlx] = val;
+            }
         } else {
 #pragma unroll
             for (int r = 0; r < R; ++r) b0[r] = make_float2(0.f, 0.f);
@@ -257,10 +344,9 @@ __global__ __launch_bounds__(WG) void k_sweep2(const Inst *__restrict__ insts, c
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int ly = 1 + w * R + r;
-                const float2 xm = lb[lq][ly][lane], xp = lb[lq][ly][lane + 2];
-                const float2 ym = lb[lq][ly - 1][lane + 1], yp = lb[lq][ly + 1][lane + 1];
                 if (!vy[r]) continue;
-                const float2 ns = nsum(ux[r], uz[r], xm, xp, ym, yp, b2[r], b0[r], zm, zp, cx, cy, cz);
+                const float2 ns = nsum(ux[r], uz[r], lb[lq][ly][lane], lb[lq][ly][lane + 2], lb[lq][ly - 1][lane + 1],
+                                       lb[lq][ly + 1][lane + 1], b2[r], b0[r], zm, zp, cx, cy, cz);
                 const float2 c2 = jacobi(bhq[r], dhq[r], ns);
                 const float r2 = resid2(c2, b1[r], dhq[r], ht2);
                 rmax2 = (r2 > rmax2 || r2 != r2) ? r2 : rmax2;
@@ -271,9 +357,7 @@ __global__ __launch_bounds__(WG) void k_sweep2(const Inst *__restrict__ insts, c
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            am[r] = ac[r];
-            ac[r] = an[r];
-            an[r] = ann[r];
+            an2[r] = an3[r];
             b2[r] = b1[r];
             b1[r] = b0[r];
             bhq[r] = bhc[r];
@@ -281,7 +365,10 @@ __global__ __launch_bounds__(WG) void k_sweep2(const Inst *__restrict__ insts, c
             bhc[r] = bhn[r];
             dhc[r] = dhn[r];
         }
-        hv = hvn;
+        hn2[0] = hn3[0];
+        hn2[1] = hn3[1];
+        rbhc = rbhn;
+        rdhc = rdhn;
     }
     if (timing) return;
     __syncthreads();

@@ -115,6 +115,43 @@ __device__ __forceinline__ float2 fetch(const gf2 *__restrict__ src, const gf2 *
     return s.mode == SRC_P ? xcmul(ph, v) : xcmulc(ph, v);
 }
 
+// Like cell_src, for slots up to two nodes outside the grid and the corners
+// of the one-node ring, as the two-sweep kernel's two-node halo needs them:
+// each axis maps on its own (periodic: wrap at any distance, the y wrap
+// with its phase P; open: the Neumann mirror at distance one, nothing
+// beyond).  A corner that would need both an x mirror and a y ghost is
+// never read and is left ZERO.  On the slots cell_src covers, both agree.
+__device__ __forceinline__ CellSrc cell_src2(const Inst &I, int gx, int gy) {
+    const int nx = I.nx, ny = I.ny;
+    CellSrc s{0, SRC_ZERO, 0, make_float2(1.f, 0.f)};
+    int sx = gx, sy = gy, xmir = 0, ymode = SRC_PLAIN;
+    if (gx < 0 || gx >= nx) {
+        if (I.per[0]) sx = ((gx % nx) + nx) % nx;
+        else if (nx >= 2 && gx == -1) { sx = 1; xmir = -1; }
+        else if (nx >= 2 && gx == nx) { sx = nx - 2; xmir = 1; }
+        else return s;
+    }
+    if (gy < 0 || gy >= ny) {
+        if (xmir) return s;
+        if (I.per[1]) { sy = ((gy % ny) + ny) % ny; ymode = gy < 0 ? SRC_P : SRC_PCONJ; }
+        else if (ny >= 2 && gy == -1) sy = 1;
+        else if (ny >= 2 && gy == ny) sy = ny - 2;
+        else return s;
+    }
+    s.off = sy * nx + sx;
+    if (xmir) {
+        const float2 u2 = xcmul(I.ux[sy], I.ux[sy]);
+        s.mode = SRC_FAC;
+        s.fac = xmir < 0 ? u2 : make_float2(u2.x, -u2.y);
+    } else if (ymode != SRC_PLAIN) {
+        s.mode = ymode;
+        s.px = sx;
+    } else {
+        s.mode = SRC_PLAIN;
+    }
+    return s;
+}
+
 // z neighbour plane index of plane p in direction d (+1/-1), or -1 if none.
 __device__ __forceinline__ int zplane(const Inst &I, int p, int d) {
     int q = p + d;
