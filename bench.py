@@ -235,6 +235,8 @@ def main():
                     help="steps of the c4 forward+adjoint comparison (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=20,
                     help="steps of the 64-instance batched comparison (0 skips it)")
+    ap.add_argument("--tiling", default=None,
+                    help="rows,chunk,streaming,fused: set the stencil tiling instead of tdgl_autotune")
     ap.add_argument("--copy-calib-gib", type=float, default=0.0,
                     help="run a plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -254,7 +256,12 @@ def main():
     log(f"[bench] setting up {w.name} ({N} nodes)")
     s, Bz, used, frac = setup(w, tdgl, inputs, torch, w.tol, args.mu_rtol)
     log(f"[bench] B_eff={Bz:.6f} inclusions={used} fraction={frac}")
-    tiling = s.autotune()
+    if args.tiling:
+        r_, c_, nt_, fu_ = (int(v) for v in args.tiling.split(","))
+        s.set_tiling(rows=r_, chunk=c_, streaming=nt_, fused=fu_)
+        tiling = s.tiling()
+    else:
+        tiling = s.autotune()
     log(f"[bench] stencil tiling {tiling}")
     if args.copy_calib_gib > 0:
         # one elementwise kernel that reads nb bytes and writes nb bytes
