@@ -212,7 +212,7 @@ def batch_bench(tdgl, inputs, torch, steps, warmup, n=64):
         s.close()
     return {"instances": n, "nodes": nodes, "steps": steps, "warmup": warmup, "sweep_budget": budget,
             "tiling": {"rows": tiling["rows"], "chunk": tiling["chunk"], "streaming": tiling["streaming"],
-                       "fused": tiling["fused"]},
+                       "fused": tiling["fused"], "persistent": tiling["persistent"]},
             "batched_rate": nodes * steps / t_b, "batched_ms_per_step": 1e3 * t_b / steps,
             "sequential_rate": nodes * steps / t_s, "sequential_ms_per_step": 1e3 * t_s / steps,
             "speedup": t_s / t_b, "batched_sweeps_sum": st["sweeps_sum"], "capped_steps": st["capped_steps"],
@@ -236,7 +236,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=20,
                     help="steps of the 64-instance batched comparison (0 skips it)")
     ap.add_argument("--tiling", default=None,
-                    help="rows,chunk,streaming,fused: set the stencil tiling instead of tdgl_autotune")
+                    help="rows,chunk,streaming,fused[,persistent]: set the stencil tiling instead of tdgl_autotune")
     ap.add_argument("--copy-calib-gib", type=float, default=0.0,
                     help="run a plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -257,8 +257,8 @@ def main():
     s, Bz, used, frac = setup(w, tdgl, inputs, torch, w.tol, args.mu_rtol)
     log(f"[bench] B_eff={Bz:.6f} inclusions={used} fraction={frac}")
     if args.tiling:
-        r_, c_, nt_, fu_ = (int(v) for v in args.tiling.split(","))
-        s.set_tiling(rows=r_, chunk=c_, streaming=nt_, fused=fu_)
+        v_ = [int(v) for v in args.tiling.split(",")] + [0]
+        s.set_tiling(rows=v_[0], chunk=v_[1], streaming=v_[2], fused=v_[3], persistent=v_[4])
         tiling = s.tiling()
     else:
         tiling = s.autotune()
@@ -351,7 +351,7 @@ def main():
                    "inclusions": used, "inclusion_fraction": frac, "tol": w.tol, "dt": w.dt,
                    "mu_tol": 1e-5, "mu_rtol": args.mu_rtol,
                    "tiling": {"rows": tiling["rows"], "chunk": tiling["chunk"], "streaming": tiling["streaming"],
-                              "fused": tiling["fused"]},
+                              "fused": tiling["fused"], "persistent": tiling["persistent"]},
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

@@ -267,6 +267,12 @@ typedef struct tdgl_tiling {
     int fused;       /* 1: Jacobi sweeps run two per pass over HBM (the
                         second iterate on the tile from the first on the tile
                         and its one-node ring); results are bit-identical */
+    int persistent;  /* 1: each Jacobi solve is one cooperative launch that
+                        loops over the sweeps with grid-wide barriers (no
+                        host round trip per sweep; single sweeps only; step
+                        statistics then come from device counters and a
+                        strict failure is reported at the end of the call).
+                        tdgl_autotune picks it when a sweep takes < 60 us. */
     double sweep_us; /* measured time of one Jacobi sweep of the whole context
                         (tdgl_autotune; 0 from tdgl_get_tiling)             */
 } tdgl_tiling;
@@ -274,7 +280,8 @@ typedef struct tdgl_tiling {
 /* Picks the stencil tiling of the context by timing one Jacobi sweep for
  * each candidate (rows in {1, 2, 4} x chunk in {heuristic, 4, 8, 16, 32,
  * 64} x streaming hints off/on x one or two sweeps per pass) on the
- * context's stream and keeping the fastest per iteration.  The timing sweeps
+ * context's stream and keeping the fastest per iteration; sweeps that short
+ * (< 60 us) get persistent solves.  The timing sweeps
  * read the current psi~ and b/M, (ht/2)/M arrays and write only the spare
  * psi~ buffer, so the solver state is unchanged; results of later steps do
  * not depend on the tiling beyond the summation order of FP64 partial sums.
@@ -285,8 +292,10 @@ typedef struct tdgl_tiling {
 tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *chosen);
 
 /* Sets the tiling of every instance without timing (rows in {1, 2, 4};
- * chunk 0 = heuristic, else z planes per work-group; streaming and fused 0
- * or 1; sweep_us ignored).  No allocation; synchronises the stream. */
+ * chunk 0 = heuristic, else z planes per work-group; streaming, fused and
+ * persistent 0 or 1, not fused and persistent together; sweep_us ignored).
+ * No allocation; synchronises the stream.  tdgl_step_graph always uses
+ * separate sweep launches. */
 tdgl_status tdgl_set_tiling(tdgl_ctx *ctx, const tdgl_tiling *t);
 
 /* Current tiling of instance inst (rows are shared by the context). */

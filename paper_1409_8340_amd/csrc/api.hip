@@ -384,6 +384,8 @@ struct tdgl_ctx {
     int rows = 2;     // stencil rows per thread
     bool nt = false;  // streaming (non-temporal) hints in the sweep and assemble passes
     bool fused = false;  // Jacobi sweeps after the first run as two-sweep passes
+    bool persist = false;  // the Jacobi solve as one cooperative launch
+    int num_cu = 0;        // compute units of the device
     // captured step of tdgl_step_graph (rebuilt when the budget or the
     // tiling changes)
     hipGraph_t graph = nullptr;
@@ -742,6 +744,34 @@ void launch_sweep2(tdgl_ctx *c, int l) {
     else launch_sweep2_r<4>(c, l);
 }
 
+// The whole Jacobi solve (sweeps 1 .. max_iter-1 of every instance) as one
+// cooperative launch: as many work-groups as can be resident at once (a
+// multiple of 8 for the XCD-aware tile order), never more than tiles.
+// l0 = -1: lcap timing sweeps instead (state untouched).
+template <int R, bool NT>
+tdgl_status launch_persist_r(tdgl_ctx *c, int l0, int lcap) {
+    const void *fn = (const void *)k_jacobi_persist<R, NT>;
+    int per_cu = 0;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, WG, 0));
+    if (per_cu < 1) return fail(TDGL_EDEVICE, "the persistent Jacobi kernel cannot be resident");
+    int grid = std::min(per_cu * c->num_cu, c->tot_st);
+    if (grid >= 8) grid -= grid % 8;
+    grid = std::max(grid, 1);
+    const Inst *ins = c->d_inst;
+    const int *pref = c->d_pref_st;
+    int n = c->n, nt = c->tot_st;
+    void *args[] = {(void *)&ins, (void *)&pref, (void *)&n, (void *)&l0, (void *)&lcap, (void *)&nt};
+    HIPCHK(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(WG), args, 0, c->stream));
+    return TDGL_OK;
+}
+tdgl_status launch_persist(tdgl_ctx *c, int l0, int lcap) {
+    if (c->rows == 1)
+        return c->nt ? launch_persist_r<1, true>(c, l0, lcap) : launch_persist_r<1, false>(c, l0, lcap);
+    if (c->rows == 2)
+        return c->nt ? launch_persist_r<2, true>(c, l0, lcap) : launch_persist_r<2, false>(c, l0, lcap);
+    return c->nt ? launch_persist_r<4, true>(c, l0, lcap) : launch_persist_r<4, false>(c, l0, lcap);
+}
+
 template <int MODE>
 void launch_stencil(tdgl_ctx *c, int l, const float2 *in = nullptr, float2 *out = nullptr) {
     if (c->rows == 1) launch_stencil_r<MODE, 1>(c, l, in, out);
@@ -808,6 +838,20 @@ tdgl_status jacobi_loop(tdgl_ctx *ctx, tdgl_step_stats *acc, bool *strict_fail, 
     const int n = ctx->n;
     hipStream_t s = ctx->stream;
     const size_t RW = ctx->row_words();
+    if (ctx->persist) {
+        // one launch, no host round trip; the statistics come from the
+        // device counters (tdgl_step reads them)
+        {
+            ProfScope ps(ctx, TDGL_K_SWEEP);
+            tdgl_status e = launch_persist(ctx, 1, ctx->max_iter);
+            if (e) return e;
+        }
+        ProfScope ps(ctx, TDGL_K_OTHER);
+        hipLaunchKernelGGL(k_solve_finalize, dim3(n), dim3(FIN_THREADS), 0, s, ctx->d_inst, n, count_step,
+                           ctx->max_iter, 0);
+        LAUNCHCHK();
+        return TDGL_OK;
+    }
     HIPCHK(hipMemcpyAsync(ctx->h_res, ctx->d_res, RW * 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipEventRecord(ctx->ev[0], s));
     std::vector<int> conv_at(n, -1);
@@ -847,7 +891,7 @@ tdgl_status jacobi_loop(tdgl_ctx *ctx, tdgl_step_stats *acc, bool *strict_fail, 
     }
     {
         ProfScope ps(ctx, TDGL_K_OTHER);
-        hipLaunchKernelGGL(k_solve_finalize, dim3(cdiv(n, 64)), dim3(64), 0, s, ctx->d_inst, n, count_step,
+        hipLaunchKernelGGL(k_solve_finalize, dim3(n), dim3(FIN_THREADS), 0, s, ctx->d_inst, n, count_step,
                            launched, ctx->fused ? 1 : 0);
         if (ctx->fused) launch_stencil<MODE_SWEEP>(ctx, -2);  // corrective sweep where needed
     }
@@ -944,7 +988,7 @@ tdgl_status enqueue_poisson(tdgl_ctx *ctx, tdgl_step_stats *acc) {
     {
         ProfScope ps(ctx, TDGL_K_OTHER);
         if (ctx->any_mg)
-            hipLaunchKernelGGL(k_mg_finalize, dim3(cdiv(n, 64)), dim3(64), 0, s, ctx->d_inst, n, acc ? 1 : 0);
+            hipLaunchKernelGGL(k_mg_finalize, dim3(n), dim3(FIN_THREADS), 0, s, ctx->d_inst, n, acc ? 1 : 0);
         hipLaunchKernelGGL(k_mu_mean_partial, dim3(std::max(ctx->tot_mg[0], 1)), dim3(256), 0, s, ctx->d_inst,
                            pref_mg(ctx, 0), n, 0);
         hipLaunchKernelGGL(k_reduce_to_state, dim3(n), dim3(256), 0, s, ctx->d_inst, ctx->d_np_mg0, 1, 1);
@@ -989,7 +1033,7 @@ tdgl_status enqueue_step_fixed(tdgl_ctx *ctx, int budget) {
         for (int l = 1; l < budget; l += 2) launch_sweep2(ctx, l);
     else
         for (int l = 1; l < budget; ++l) launch_stencil<MODE_SWEEP>(ctx, l);
-    hipLaunchKernelGGL(k_solve_finalize, dim3(cdiv(n, 64)), dim3(64), 0, s, ctx->d_inst, n, 1, budget,
+    hipLaunchKernelGGL(k_solve_finalize, dim3(n), dim3(FIN_THREADS), 0, s, ctx->d_inst, n, 1, budget,
                        ctx->fused ? 1 : 0);
     if (ctx->fused) launch_stencil<MODE_SWEEP>(ctx, -2);
     LAUNCHCHK();
@@ -1006,7 +1050,7 @@ tdgl_status enqueue_step_fixed(tdgl_ctx *ctx, int budget) {
             e = enqueue_vcycle(ctx, cyc);
             if (e) return e;
         }
-        hipLaunchKernelGGL(k_mg_finalize, dim3(cdiv(n, 64)), dim3(64), 0, s, ctx->d_inst, n, 1);
+        hipLaunchKernelGGL(k_mg_finalize, dim3(n), dim3(FIN_THREADS), 0, s, ctx->d_inst, n, 1);
     }
     hipLaunchKernelGGL(k_mu_mean_partial, dim3(std::max(ctx->tot_mg[0], 1)), dim3(256), 0, s, ctx->d_inst,
                        pref_mg(ctx, 0), n, 0);
@@ -1050,6 +1094,11 @@ tdgl_status tdgl_create(int n, const tdgl_params *params, void *ws, size_t ws_by
     c->ws_bytes = ws_bytes;
     c->stream = (hipStream_t)stream;
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return fail(TDGL_EDEVICE, "hipGetDevice failed"); }
+    if (hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
+        c->num_cu < 1) {
+        delete c;
+        return fail(TDGL_EDEVICE, "cannot read the number of compute units");
+    }
     layout(n, params, (char *)ws, c);
     c->nlev_max = 0;
     for (auto &h : c->inst) {
@@ -1327,6 +1376,13 @@ tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats) {
     memset(&acc, 0, sizeof acc);
     acc.sweeps_min = 1 << 30;
     bool strict_fail = false;
+    bool any_strict = false;
+    for (int i = 0; i < n; ++i) any_strict = any_strict || ctx->inst[i].p.strict;
+    const bool dev_stats = ctx->persist && (stats || any_strict);
+    if (dev_stats) {
+        hipLaunchKernelGGL(k_acc_reset, dim3(cdiv(n, 64)), dim3(64), 0, s, ctx->d_inst, n);
+        LAUNCHCHK();
+    }
     for (int step = 0; step < nsteps; ++step) {
         // ---- Jacobi solve (all instances) --------------------------------
         {
@@ -1355,6 +1411,22 @@ tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats) {
         }
         acc.steps++;
         if (strict_fail) break;
+    }
+    if (dev_stats) {
+        // persistent solves: the sweep statistics of the call from the
+        // device counters; a strict instance's capped solve shows here
+        HIPCHK(hipStreamSynchronize(s));
+        for (int i = 0; i < n; ++i) {
+            DevState d;
+            HIPCHK(hipMemcpy(&d, ctx->inst[i].d.st, sizeof d, hipMemcpyDeviceToHost));
+            acc.sweeps_sum += (long long)d.acc_sweeps;
+            acc.sweep_passes += (long long)d.acc_passes;
+            acc.capped_steps += (int)d.acc_capped;
+            acc.sweeps_min = std::min(acc.sweeps_min, d.acc_sw_min);
+            acc.sweeps_max = std::max(acc.sweeps_max, d.acc_sw_max);
+            acc.last_res2 = d.last_res2;
+            if (ctx->inst[i].p.strict && d.acc_capped > 0) strict_fail = true;
+        }
     }
     if (stats) {
         HIPCHK(hipStreamSynchronize(s));
@@ -1478,8 +1550,9 @@ tdgl_status upload_tiling(tdgl_ctx *ctx) {
 struct Tiling {
     int rows = 2;
     int chunk = 0;  // 0: heuristic
-    int nt = 0;     // streaming hints
-    int fused = 0;  // two-sweep passes
+    int nt = 0;       // streaming hints
+    int fused = 0;    // two-sweep passes
+    int persist = 0;  // one cooperative launch per Jacobi solve
 };
 
 tdgl_status apply_tiling(tdgl_ctx *ctx, const Tiling &t) {
@@ -1487,6 +1560,7 @@ tdgl_status apply_tiling(tdgl_ctx *ctx, const Tiling &t) {
     ctx->rows = t.rows;
     ctx->nt = t.nt != 0;
     ctx->fused = t.fused != 0;
+    ctx->persist = t.persist != 0 && !ctx->fused;
     for (auto &h : ctx->inst) set_tiling(h, t.rows, t.chunk);
     return upload_tiling(ctx);
 }
@@ -1515,14 +1589,16 @@ bool tune_file_lookup(const char *path, const std::string &key, Tiling *t, doubl
     bool found = false;
     while (fgets(line, sizeof line, f)) {
         char k[4000];
-        int r, c, nt, fu;
+        int r, c, nt, fu, pe;
         double u;
-        if (sscanf(line, "%3999s %d %d %d %d %lf", k, &r, &c, &nt, &fu, &u) == 6 && key == k &&
-            (r == 1 || r == 2 || r == 4) && c >= 0 && (nt == 0 || nt == 1) && (fu == 0 || fu == 1)) {
+        if (sscanf(line, "%3999s %d %d %d %d %d %lf", k, &r, &c, &nt, &fu, &pe, &u) == 7 && key == k &&
+            (r == 1 || r == 2 || r == 4) && c >= 0 && (nt == 0 || nt == 1) && (fu == 0 || fu == 1) &&
+            (pe == 0 || pe == 1)) {
             t->rows = r;
             t->chunk = c;
             t->nt = nt;
             t->fused = fu;
+            t->persist = pe;
             *us = u;
             found = true;  // the last entry wins
         }
@@ -1591,12 +1667,34 @@ tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *ch
                     best = t;
                 }
             }
+        // the best single-sweep tiling as one persistent launch: chosen when
+        // its sweeps, barrier included, beat separate launches by 10 %
+        if (!best.fused) {
+            tdgl_status e = apply_tiling(ctx, best);
+            if (e) return e;
+            const int K = 16;
+            e = launch_persist(ctx, -1, K);  // warm-up
+            if (e) return e;
+            HIPCHK(hipEventRecord(e0, s));
+            e = launch_persist(ctx, -1, K);
+            if (e) return e;
+            HIPCHK(hipEventRecord(e1, s));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            const double pus = 1e3 * ms / K;
+            if (pus < 0.9 * best_us) {
+                best.persist = 1;
+                best_us = pus;
+            }
+        }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (cache_path) {
             FILE *f = fopen(cache_path, "a");
             if (f) {
-                fprintf(f, "%s %d %d %d %d %.3f\n", key.c_str(), best.rows, best.chunk, best.nt, best.fused, best_us);
+                fprintf(f, "%s %d %d %d %d %d %.3f\n", key.c_str(), best.rows, best.chunk, best.nt, best.fused,
+                        best.persist, best_us);
                 fclose(f);
             }
         }
@@ -1612,6 +1710,7 @@ tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *ch
         chosen->chunk = ctx->inst[0].d.chunk;
         chosen->streaming = best.nt;
         chosen->fused = best.fused;
+        chosen->persistent = ctx->persist ? 1 : 0;
         chosen->sweep_us = best_us;
     }
     return TDGL_OK;
@@ -1621,14 +1720,17 @@ tdgl_status tdgl_set_tiling(tdgl_ctx *ctx, const tdgl_tiling *t) {
     if (!ctx || !t) return fail(TDGL_EINVAL, "null argument");
     if (t->rows != 1 && t->rows != 2 && t->rows != 4) return fail(TDGL_EINVAL, "rows must be 1, 2 or 4");
     if (t->chunk < 0 || t->chunk > 1024) return fail(TDGL_EINVAL, "chunk must be in [0, 1024]");
-    if ((t->streaming != 0 && t->streaming != 1) || (t->fused != 0 && t->fused != 1))
-        return fail(TDGL_EINVAL, "streaming and fused must be 0 or 1");
+    if ((t->streaming != 0 && t->streaming != 1) || (t->fused != 0 && t->fused != 1) ||
+        (t->persistent != 0 && t->persistent != 1))
+        return fail(TDGL_EINVAL, "streaming, fused and persistent must be 0 or 1");
+    if (t->fused && t->persistent) return fail(TDGL_EINVAL, "persistent solves use single sweeps (fused = 0)");
     HIPCHK(hipStreamSynchronize(ctx->stream));
     Tiling s;
     s.rows = t->rows;
     s.chunk = t->chunk;
     s.nt = t->streaming;
     s.fused = t->fused;
+    s.persist = t->persistent;
     return apply_tiling(ctx, s);
 }
 
@@ -1639,6 +1741,7 @@ tdgl_status tdgl_get_tiling(const tdgl_ctx *ctx, int inst, tdgl_tiling *out) {
     out->chunk = ctx->inst[inst].d.chunk;
     out->streaming = ctx->nt ? 1 : 0;
     out->fused = ctx->fused ? 1 : 0;
+    out->persistent = ctx->persist ? 1 : 0;
     out->sweep_us = 0.0;
     return TDGL_OK;
 }

@@ -44,44 +44,54 @@ __global__ void k_links(const Inst *__restrict__ insts, int which) {
 // which is the instance's max_iter or the nl sweeps launched, whichever is
 // smaller.  fused: the sweeps after the first ran as two-sweep passes.  Updates the psi buffer index, step counters and clears the
 // residual words for the next step.  One thread per instance.
-__global__ void k_solve_finalize(const Inst *__restrict__ insts, int ninst, int count_step, int nl, int fused) {
-    const int ii = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(FIN_THREADS) void k_solve_finalize(const Inst *__restrict__ insts, int ninst,
+                                                                  int count_step, int nl, int fused) {
+    // one work-group per instance: the first wavefront scans the rows, then
+    // all threads clear them
+    const int ii = blockIdx.x;
     if (ii >= ninst) return;
     const Inst &I = insts[ii];
     DevState *st = I.st;
-    const int cap = min(I.max_iter, nl);
-    int sweeps = cap, capped = 1;
-    float last = 0.f;
-    for (int l = 0; l < cap; ++l) {
-        last = row_max(I.res, I.rstride, l);
-        if (last < I.tol) { sweeps = l + 1; capped = 0; break; }
+    if (threadIdx.x < 64) {
+        const int cap = min(I.max_iter, nl);
+        int sweeps = cap, capped = 1;
+        float last = 0.f;
+        for (int l = 0; l < cap; ++l) {
+            last = row_max_wave(I.res, I.rstride, l);
+            if (last < I.tol) { sweeps = l + 1; capped = 0; break; }
+        }
+        if (threadIdx.x == 0) {
+            st->sweeps = sweeps;
+            st->capped = capped;
+            if (!fused) {
+                st->cur ^= (sweeps & 1);
+                st->fix = 0;
+            } else {
+                // two-sweep passes store the odd iterates: psi^(s), s odd,
+                // sits in cur ^ ((s + 1) / 2 & 1); an even s is recomputed
+                // from psi^(s-1) into the other buffer by the corrective sweep
+                const int so = (sweeps & 1) ? sweeps : sweeps - 1;
+                const int bo = st->cur ^ (((so + 1) >> 1) & 1);
+                st->fix = (sweeps & 1) ? 0 : 1;
+                st->cur = (sweeps & 1) ? bo : (bo ^ 1);
+            }
+            if (count_step) {
+                st->t += I.dt;
+                st->n += 1.0;
+                st->acc_sweeps += sweeps;
+                st->acc_passes += fused ? sweeps / 2 : sweeps - 1;
+                st->acc_capped += capped;
+                st->acc_sw_min = min(st->acc_sw_min, sweeps);
+                st->acc_sw_max = max(st->acc_sw_max, sweeps);
+            }
+            // keep the last tested residual
+            st->last_res2 = last;
+        }
     }
-    st->sweeps = sweeps;
-    st->capped = capped;
-    if (!fused) {
-        st->cur ^= (sweeps & 1);
-        st->fix = 0;
-    } else {
-        // two-sweep passes store the odd iterates: psi^(s), s odd, sits in
-        // cur ^ ((s + 1) / 2 & 1); an even s is recomputed from psi^(s-1)
-        // into the other buffer by the corrective sweep
-        const int so = (sweeps & 1) ? sweeps : sweeps - 1;
-        const int bo = st->cur ^ (((so + 1) >> 1) & 1);
-        st->fix = (sweeps & 1) ? 0 : 1;
-        st->cur = (sweeps & 1) ? bo : (bo ^ 1);
-    }
-    if (count_step) {
-        st->t += I.dt;
-        st->n += 1.0;
-        st->acc_sweeps += sweeps;
-        st->acc_passes += fused ? sweeps / 2 : sweeps - 1;
-        st->acc_capped += capped;
-        st->acc_sw_min = min(st->acc_sw_min, sweeps);
-        st->acc_sw_max = max(st->acc_sw_max, sweeps);
-    }
-    // keep the last tested residual, then clear the words for the next step
-    st->last_res2 = last;
-    for (int l = 0; l < I.max_iter; ++l) row_clear(I.res, I.rstride, l);
+    __syncthreads();
+    // clear the words for the next step
+    const int words = I.max_iter * NSLOT;
+    for (int w = threadIdx.x; w < words; w += FIN_THREADS) I.res[(size_t)w * I.rstride] = 0u;
 }
 
 // Partial sums of Im[psi_m^* U_x(j) psi_{m+x}] (periodic x) for J_av

@@ -22,22 +22,25 @@
 #include "kernels.h"
 #include "stencil.h"
 
+#include <hip/hip_cooperative_groups.h>
+
 namespace tdgl {
 
 // MODE selects the pass; R is the number of consecutive rows a thread owns
 // (tile 64 x 4R: a larger R streams more per thread, a smaller one keeps
 // more waves resident; the autotuner picks R and the z chunk).
+// One pass of MODE over tile b of the batched grid (see k_stencil); used by
+// the ordinary launch (one tile per work-group) and by the persistent Jacobi
+// solve (tiles in a grid-stride loop).
 template <int MODE, int R, bool NT>
-__global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
-                                                const int *__restrict__ prefix, int ninst, int l,
-                                                const float2 *ext_in, float2 *ext_out) {
+__device__ __forceinline__ void stencil_tile(const Inst *__restrict__ insts, const int *__restrict__ prefix,
+                                             int ninst, int l, const float2 *ext_in, float2 *ext_out, int b) {
     constexpr int ROWS = R;
     constexpr int TYv = 4 * R;
     constexpr int HALOv = 2 * TX + 2 * TYv;
     __shared__ float2 lds[2][TYv + 2][LDX];
     __shared__ double red[WG / 64];
 
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int ii = find_inst(prefix, ninst, b);
     const Inst &I = insts[ii];
     DevState *st = I.st;
@@ -57,7 +60,7 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
         // instance's cap is reached): its solve is complete and the launch
         // is a no-op for it.
         if (l >= I.max_iter) return;
-        const float prev = row_max(I.res, I.rstride, l - 1);
+        const float prev = row_max_wave(I.res, I.rstride, l - 1);
         if (prev < I.tol) return;
     }
     if ((MODE == MODE_RHS) && !I.driven) return;
@@ -215,26 +218,16 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
             }
             if (MODE == MODE_RHS) {
                 // f = sum_a (1/h_a^2) Im[psi^* (U psi_+ + U^* psi_-)] = Im[psi^* NS]
-                const float f = c.x * ns.y - c.y * ns.x;
+                const float f = rhs_node(c, ns);
                 fw[m] = f;
                 acc += (double)f * (double)node_w(I, x, y0 + w * ROWS + r, k);
                 continue;
             }
             float2 nw;
             if (MODE == MODE_FIRST) {
-                // b = psi^- + ht/2 [ (eps - i u mu) psi^- - |psi^-|^2 psi^- + L psi^- ]
-                // M = 1 + ht/2 [ |psi^-|^2 + 2S + i u mu - eps ]
-                const float a2 = cabs2(c);
-                const float e = ep[r], um = u * mu[r];
-                const float2 lap = make_float2(ns.x - S2 * c.x, ns.y - S2 * c.y);
-                const float2 src_t = make_float2(e * c.x + um * c.y - a2 * c.x + lap.x,
-                                                 e * c.y - um * c.x - a2 * c.y + lap.y);
-                const float2 bb = make_float2(c.x + ht2 * src_t.x, c.y + ht2 * src_t.y);
-                const float2 M = make_float2(1.f + ht2 * (a2 + S2 - e), ht2 * um);
-                const float inv = 1.f / cabs2(M);
-                const float2 Mi = make_float2(M.x * inv, -M.y * inv);
-                const float2 bhv = cmul(bb, Mi);
-                const float2 dhv = cscale(ht2, Mi);
+                float2 bhv, dhv;
+                float r2;
+                assemble_node(c, ep[r], u * mu[r], ns, S2, ht2, bhv, dhv, nw, r2);
                 if (NT) {
                     st2nt(bhw, m, bhv);
                     st2nt(dhw, m, dhv);
@@ -242,9 +235,6 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
                     st2(bhw, m, bhv);
                     st2(dhw, m, dhv);
                 }
-                nw = cadd(bhv, cmul(dhv, ns));
-                const float2 d = csub(nw, c);
-                const float r2 = cabs2(M) * cabs2(d);
                 rmax = (r2 > rmax || r2 != r2) ? r2 : rmax;
             } else {
                 nw = jacobi(bh[r], dh[r], ns);
@@ -281,6 +271,52 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
     }
 }
 
+template <int MODE, int R, bool NT>
+__global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
+                                                const int *__restrict__ prefix, int ninst, int l,
+                                                const float2 *ext_in, float2 *ext_out) {
+    stencil_tile<MODE, R, NT>(insts, prefix, ninst, l, ext_in, ext_out, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// The whole Jacobi solve of every instance in one cooperative launch: sweeps
+// l = l0, l0+1, ... over all tiles (grid-stride loop, XCD-aware order), a
+// grid-wide barrier between sweeps, and the convergence words read after
+// the barrier -- the same words by every work-group, so the decision to go
+// on is uniform.  A sweep does what the separate launch l does (tiles of an
+// instance whose solve has ended exit at once); the loop ends once no
+// instance's solve is open or at lcap.  The barrier releases this
+// work-group's stores at device scope before it arrives and acquires the
+// others' after it leaves (one L2 write-back and invalidate per work-group
+// and sweep).  l0 = -1: lcap timing sweeps (l = -1 each, no convergence
+// test, state untouched) for the tile autotuner.
+template <int R, bool NT>
+__global__ __launch_bounds__(WG) void k_jacobi_persist(const Inst *__restrict__ insts,
+                                                       const int *__restrict__ prefix, int ninst, int l0,
+                                                       int lcap, int ntiles) {
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    __shared__ int go;
+    const bool timing = l0 < 0;
+    const int l_begin = timing ? 0 : l0;
+    for (int l = l_begin; l < lcap; ++l) {
+        if (!timing) {
+            if (threadIdx.x < 64) {
+                int open = 0;
+                for (int i = 0; i < ninst && !open; ++i) {
+                    const Inst &I = insts[i];
+                    if (l < I.max_iter && !(row_max_wave(I.res, I.rstride, l - 1) < I.tol)) open = 1;
+                }
+                if (threadIdx.x == 0) go = open;
+            }
+            __syncthreads();
+            if (!go) break;
+        }
+        for (int t = blockIdx.x; t < ntiles; t += gridDim.x)
+            stencil_tile<MODE_SWEEP, R, NT>(insts, prefix, ninst, timing ? -1 : l, nullptr, nullptr,
+                                            xcd_remap(t, ntiles));
+        grid.sync();
+    }
+}
+
 #define TDGL_INST(M, R, NT) \
     template __global__ void k_stencil<M, R, NT>(const Inst *, const int *, int, int, const float2 *, float2 *);
 #define TDGL_INST_R(R)                 \
@@ -294,6 +330,15 @@ __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
 TDGL_INST_R(1)
 TDGL_INST_R(2)
 TDGL_INST_R(4)
+#define TDGL_INSTP(R, NT) \
+    template __global__ void k_jacobi_persist<R, NT>(const Inst *, const int *, int, int, int, int);
+TDGL_INSTP(1, false)
+TDGL_INSTP(1, true)
+TDGL_INSTP(2, false)
+TDGL_INSTP(2, true)
+TDGL_INSTP(4, false)
+TDGL_INSTP(4, true)
+#undef TDGL_INSTP
 #undef TDGL_INST_R
 #undef TDGL_INST
 

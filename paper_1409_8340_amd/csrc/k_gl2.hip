@@ -122,8 +122,8 @@ __global__ __launch_bounds__(WG) void k_sweep2(const Inst *__restrict__ insts, c
         // here too), and the buffer of psi^(l-1) must survive for the
         // corrective sweep
         if (l >= I.max_iter) return;
-        if (row_max(I.res, I.rstride, l - 1) < I.tol) return;
-        if (l >= 2 && row_max(I.res, I.rstride, l - 2) < I.tol) return;
+        if (row_max_wave(I.res, I.rstride, l - 1) < I.tol) return;
+        if (l >= 2 && row_max_wave(I.res, I.rstride, l - 2) < I.tol) return;
     }
     const bool rec2 = !timing && (l + 1 < I.max_iter);
 

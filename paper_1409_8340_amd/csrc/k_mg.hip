@@ -50,13 +50,14 @@ __device__ __forceinline__ int wrapi(int i, int n, int per) {
 
 // Poisson residual rows: the solve of this step ended at cycle c (or an
 // earlier one) when row c is below max(mu_tol, mu_rtol * row 0).  Row c is
-// written by the finest residual of cycle c.
+// written by the finest residual of cycle c.  Read by whole wavefronts
+// (uniform control flow, full waves).
 __device__ __forceinline__ float mg_threshold(const Inst &I) {
-    return fmaxf(I.mu_tol, I.mu_rtol * row_max(I.mures, I.rstride, 0));
+    return fmaxf(I.mu_tol, I.mu_rtol * row_max_wave(I.mures, I.rstride, 0));
 }
 __device__ __forceinline__ bool mg_done(const Inst &I, int c) {
     if (c >= I.mu_max_cycles) return true;
-    return row_max(I.mures, I.rstride, c) < mg_threshold(I);
+    return row_max_wave(I.mures, I.rstride, c) < mg_threshold(I);
 }
 
 // Shared column context: coefficient values of the column and its x/y
@@ -349,27 +350,36 @@ __global__ __launch_bounds__(CO_THREADS) void k_mg_coarsest(const Inst *__restri
 
 // End of a Poisson solve: number of cycles and final residual; clears the
 // cycle words.  One thread per instance.
-__global__ void k_mg_finalize(const Inst *__restrict__ insts, int ninst, int count_step) {
-    const int ii = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(FIN_THREADS) void k_mg_finalize(const Inst *__restrict__ insts, int ninst,
+                                                               int count_step) {
+    // one work-group per instance: the first wavefront scans the rows, then
+    // all threads clear them
+    const int ii = blockIdx.x;
     if (ii >= ninst) return;
     const Inst &I = insts[ii];
     if (!I.driven || I.fft) return;
     DevState *st = I.st;
-    int cycles = I.mu_max_cycles, capped = 1;
-    const float thr = mg_threshold(I);
-    float last = row_max(I.mures, I.rstride, I.mu_max_cycles - 1);
-    for (int c = 0; c < I.mu_max_cycles; ++c) {
-        const float r = row_max(I.mures, I.rstride, c);
-        if (r < thr) { cycles = c; capped = 0; last = r; break; }
+    if (threadIdx.x < 64) {
+        int cycles = I.mu_max_cycles, capped = 1;
+        const float thr = mg_threshold(I);
+        float last = row_max_wave(I.mures, I.rstride, I.mu_max_cycles - 1);
+        for (int c = 0; c < I.mu_max_cycles; ++c) {
+            const float r = row_max_wave(I.mures, I.rstride, c);
+            if (r < thr) { cycles = c; capped = 0; last = r; break; }
+        }
+        if (threadIdx.x == 0) {
+            st->mu_cycles = cycles;
+            st->mu_capped = capped;
+            st->mu_last_res = last;
+            if (count_step) {
+                st->acc_mu_cycles += cycles;
+                st->acc_mu_capped += capped;
+            }
+        }
     }
-    st->mu_cycles = cycles;
-    st->mu_capped = capped;
-    st->mu_last_res = last;
-    if (count_step) {
-        st->acc_mu_cycles += cycles;
-        st->acc_mu_capped += capped;
-    }
-    for (int c = 0; c < I.mu_max_cycles; ++c) row_clear(I.mures, I.rstride, c);
+    __syncthreads();
+    const int words = I.mu_max_cycles * NSLOT;
+    for (int w = threadIdx.x; w < words; w += FIN_THREADS) I.mures[(size_t)w * I.rstride] = 0u;
 }
 
 // Partial sums of V mu (which = 0) or V f (which = 1) on level 0 for the

@@ -7,9 +7,12 @@ namespace tdgl {
 enum { MODE_FIRST = 0, MODE_SWEEP = 1, MODE_RHS = 2, MODE_ENERGY = 3, MODE_NS = 4 };
 constexpr int JAV_CPT = 16;     // cells per thread of the flat reductions
 constexpr int CO_THREADS = 1024;
+constexpr int FIN_THREADS = 256;  // threads per instance of the solve finalizers
 
 template <int R, bool NT>
 __global__ void k_sweep2(const Inst *insts, const int *prefix, int ninst, int l);
+template <int R, bool NT>
+__global__ void k_jacobi_persist(const Inst *insts, const int *prefix, int ninst, int l0, int lcap, int ntiles);
 template <int MODE, int R, bool NT>
 __global__ void k_stencil(const Inst *insts, const int *prefix, int ninst, int l, const float2 *ext_in,
                           float2 *ext_out);

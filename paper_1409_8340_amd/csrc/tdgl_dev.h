@@ -176,17 +176,23 @@ __device__ __forceinline__ int find_inst(const int *__restrict__ prefix, int nin
 __device__ __forceinline__ unsigned *row_slot(unsigned *base, int rstride, int row, int block) {
     return base + ((size_t)row * NSLOT + (block & (NSLOT - 1))) * rstride;
 }
-__device__ __forceinline__ float row_max(const unsigned *base, int rstride, int row) {
-    unsigned m = 0;
-#pragma unroll 8
-    for (int s = 0; s < NSLOT; ++s) {
-        const unsigned w = base[((size_t)row * NSLOT + s) * rstride];
-        m = w > m ? w : m;
+// The words are read with device-scope atomic loads: in a persistent
+// kernel they were written by other work-groups' atomics since this
+// work-group last looked, and no cached copy may answer.  The whole
+// wavefront reads a row at once: lane s loads slot s mod NSLOT, a butterfly
+// over each half-wave combines them, and every lane returns the row
+// maximum.  All 64 lanes must be active.
+__device__ __forceinline__ float row_max_wave(const unsigned *base, int rstride, int row) {
+    static_assert(NSLOT == 32, "one slot per lane of a half-wave");
+    const int s = (int)(threadIdx.x & (NSLOT - 1));
+    unsigned m = __hip_atomic_load(base + ((size_t)row * NSLOT + s) * rstride, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int o = NSLOT / 2; o >= 1; o >>= 1) {
+        const unsigned v = (unsigned)__shfl_xor((int)m, o, 64);
+        m = v > m ? v : m;
     }
     return __uint_as_float(m);
-}
-__device__ __forceinline__ void row_clear(unsigned *base, int rstride, int row) {
-    for (int s = 0; s < NSLOT; ++s) base[((size_t)row * NSLOT + s) * rstride] = 0u;
 }
 
 // Node weight: 1/2 per open face the node lies on (trapezoid rule).

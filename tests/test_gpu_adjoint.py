@@ -151,3 +151,18 @@ def test_directional_derivative_at_c4_size():
     print(f"[adjoint c4] Vbar {v:.6e}; directional derivative adjoint {ad:.6e} fd {fd:.6e} "
           f"rel {abs(fd - ad) / abs(fd):.3e}")
     assert abs(fd - ad) <= 2e-2 * abs(fd)
+
+
+def test_adjoint_with_persistent_solves():
+    """tdgl_voltage_grad gives the same gradient when every Jacobi solve
+    (forward replays and adjoint systems) runs as one persistent launch."""
+    case = _make("spectral")
+    s1 = case.solver()
+    v1, g1 = s1.voltage_grad(5, 1, ckpt_every=2)
+    s1.close()
+    s2 = case.solver()
+    s2.set_tiling(rows=2, persistent=1)
+    v2, g2 = s2.voltage_grad(5, 1, ckpt_every=2)
+    s2.close()
+    assert v1 == v2
+    assert np.array_equal(g1.cpu().numpy(), g2.cpu().numpy())

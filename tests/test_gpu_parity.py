@@ -314,3 +314,68 @@ def test_two_sweep_passes_bit_identical(shape, open_, Bx, Bz, driven, rows):
     print(f"[fused] {shape} {open_} rows={rows} sweeps {sa['sweeps_sum']} passes {sf['sweep_passes']}")
     a.close()
     f.close()
+
+
+@pytest.mark.parametrize("shape,open_,Bx,Bz,driven", FUSED_CASES[:2])
+def test_tilings_bit_identical(shape, open_, Bx, Bz, driven):
+    """The node arithmetic of the assemble, the sweeps and the Poisson right
+    side is contraction-proof, so rows per tile, z chunk and streaming hints
+    change the order of work, never the bits of psi, mu or the statistics."""
+    nx, ny, nz = shape
+    eps = inputs.random_real((nz, ny, nx), 5, 0.4, 1.0)
+    c = Case(nx, ny, nz, open_=open_, Bx=Bx, Bz=Bz, eps=eps, tol=1e-10, psi_seed=9, driven=driven,
+             J=0.02 if driven else 0.0)
+    ref = c.solver()
+    ref.set_tiling(rows=2, chunk=0)
+    sr = ref.step(3)
+    want_psi, want_mu = ref.get_psi().cpu().numpy(), ref.get_mu().cpu().numpy()
+    ref.close()
+    for rows, chunk, nt in ((1, 4, 0), (1, 0, 1), (4, 2, 0), (4, 0, 1), (2, 1, 1)):
+        s = c.solver()
+        s.set_tiling(rows=rows, chunk=chunk, streaming=nt)
+        st = s.step(3)
+        assert st["sweeps_sum"] == sr["sweeps_sum"], (rows, chunk, nt)
+        assert np.array_equal(s.get_psi().cpu().numpy(), want_psi), (rows, chunk, nt)
+        assert np.array_equal(s.get_mu().cpu().numpy(), want_mu), (rows, chunk, nt)
+        s.close()
+
+
+def test_persistent_solve_bit_identical():
+    """The Jacobi solve as one cooperative launch (sweeps in a loop with
+    grid-wide barriers) gives the host-driven iterates bit for bit, with the
+    same statistics, for a batch of uneven instances."""
+    cases = _batch3()
+    a = _batch_solver(cases)
+    p = _batch_solver(cases)
+    p.set_tiling(rows=2, chunk=0, persistent=1)
+    assert p.tiling()["persistent"] == 1
+    for rep in range(3):
+        sa = a.step(2)
+        sp = p.step(2)
+        for k in ("sweeps_sum", "sweeps_min", "sweeps_max", "capped_steps", "sweep_passes", "mu_cycles_sum"):
+            assert sa[k] == sp[k], (rep, k, sa, sp)
+        for i in range(3):
+            assert np.array_equal(a.get_psi(i).cpu().numpy(), p.get_psi(i).cpu().numpy()), (rep, i)
+    print("[persistent] stats", sp)
+    a.close()
+    p.close()
+
+
+def test_persistent_solve_caps_and_strict():
+    c = Case(40, 24, 12, tol=1e-30, psi_seed=4)
+    c.params.max_iter = 5
+    x = c.solver()
+    y = c.solver()
+    y.set_tiling(rows=1, chunk=4, persistent=1)
+    sx, sy = x.step(2), y.step(2)
+    assert sx["capped_steps"] == sy["capped_steps"] == 2 and sy["sweeps_sum"] == 10
+    assert np.array_equal(x.get_psi().cpu().numpy(), y.get_psi().cpu().numpy())
+    x.close()
+    y.close()
+    c.params.strict = 1
+    z = c.solver()
+    z.set_tiling(rows=2, persistent=1)
+    with pytest.raises(tdgl.TdglError) as e:
+        z.step(1, stats=False)
+    assert tdgl.STATUS[e.value.status] == "ENOCONV"
+    z.close()
