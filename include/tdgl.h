@@ -272,7 +272,8 @@ typedef struct tdgl_tiling {
                         host round trip per sweep; single sweeps only; step
                         statistics then come from device counters and a
                         strict failure is reported at the end of the call).
-                        tdgl_autotune picks it when a sweep takes < 60 us. */
+                        tdgl_autotune picks it only when its timed sweeps,
+                        barriers included, beat separate launches by 10 %. */
     double sweep_us; /* measured time of one Jacobi sweep of the whole context
                         (tdgl_autotune; 0 from tdgl_get_tiling)             */
 } tdgl_tiling;
@@ -280,11 +281,14 @@ typedef struct tdgl_tiling {
 /* Picks the stencil tiling of the context by timing one Jacobi sweep for
  * each candidate (rows in {1, 2, 4} x chunk in {heuristic, 4, 8, 16, 32,
  * 64} x streaming hints off/on x one or two sweeps per pass) on the
- * context's stream and keeping the fastest per iteration; sweeps that short
- * (< 60 us) get persistent solves.  The timing sweeps
+ * context's stream and keeping the fastest per iteration; then 16 sweeps of
+ * that tiling in one persistent launch are timed, and persistent solves are
+ * chosen when they are at least 10 % faster per sweep.  The timing sweeps
  * read the current psi~ and b/M, (ht/2)/M arrays and write only the spare
- * psi~ buffer, so the solver state is unchanged; results of later steps do
- * not depend on the tiling beyond the summation order of FP64 partial sums.
+ * psi~ buffer, so the solver state is unchanged.  psi~, mu~ and the step
+ * statistics of later steps are the same bits for every tiling (the node
+ * arithmetic is written contraction-proof); only F, a sum of per-tile FP64
+ * partials, depends on the tiling through its summation order.
  * The choice is cached in the process per context shape (every instance's
  * grid, boundary kinds and driven flag) and, when cache_path is not NULL,
  * in that text file (read first, appended after a search).  No device

@@ -359,8 +359,17 @@ struct tdgl_ctx {
     int *d_pref_st = nullptr, *d_pref_flat = nullptr, *d_pref_mg = nullptr, *d_pref_mid = nullptr;
     int *d_np_st = nullptr, *d_np_flat = nullptr, *d_np_mg0 = nullptr;
     unsigned *d_res = nullptr, *d_mures = nullptr;
-    unsigned *h_res = nullptr, *h_mures = nullptr;  // pinned
-    int npad = 64;                                  // instance stride of a convergence row
+    unsigned *h_mures = nullptr;  // pinned copy of the Poisson rows
+    // Jacobi convergence words handed over by the sweeps themselves (pinned,
+    // mapped): word (row, inst) at h_pub[row * n + inst] for rows 0 ..
+    // max_iter - 1, then the finalize kernel's iteration counts and last
+    // residuals (2n words).  The high half of a word is the solve's sequence
+    // number pub_seq.
+    unsigned long long *h_pub = nullptr, *d_pub = nullptr;
+    unsigned pub_seq = 0;
+    bool pub_on = false;  // sweeps being launched belong to a host-driven solve
+    int poll_lag = 1;     // launches between the newest one and the one whose row the host waits for
+    int npad = 64;        // instance stride of a convergence row
     size_t row_words() const { return (size_t)NSLOT * npad; }
     // max over the slots of one polled row for one instance
     float host_row_max(const unsigned *rows, int row, int inst) const {
@@ -370,7 +379,7 @@ struct tdgl_ctx {
         memcpy(&f, &m, 4);
         return f;
     }
-    std::vector<hipEvent_t> ev, evc;
+    std::vector<hipEvent_t> evc;
     int tot_st = 0, tot_flat = 0, tot_mg[kMaxLevels] = {0}, tot_mid[kMaxLevels] = {0};
     int nlev_max = 0;
     // spectral Poisson path: prefix tables of its three kernels and LDS sizes
@@ -721,22 +730,24 @@ struct ProfScope {
 template <int MODE, int R>
 void launch_stencil_r(tdgl_ctx *c, int l, const float2 *in, float2 *out) {
     constexpr bool can_nt = (MODE == MODE_SWEEP || MODE == MODE_FIRST);
+    unsigned long long *pub = (MODE == MODE_SWEEP && c->pub_on && l > 0) ? c->d_pub : nullptr;
     if (can_nt && c->nt)
         hipLaunchKernelGGL((k_stencil<MODE, R, can_nt>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst,
-                           c->d_pref_st, c->n, l, in, out);
+                           c->d_pref_st, c->n, l, in, out, pub, c->pub_seq);
     else
         hipLaunchKernelGGL((k_stencil<MODE, R, false>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst,
-                           c->d_pref_st, c->n, l, in, out);
+                           c->d_pref_st, c->n, l, in, out, pub, c->pub_seq);
 }
 // One two-sweep pass (l odd; l = -1: timing pass).
 template <int R>
 void launch_sweep2_r(tdgl_ctx *c, int l) {
+    unsigned long long *pub = (c->pub_on && l > 0) ? c->d_pub : nullptr;
     if (c->nt)
         hipLaunchKernelGGL((k_sweep2<R, true>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst, c->d_pref_st,
-                           c->n, l);
+                           c->n, l, pub, c->pub_seq);
     else
         hipLaunchKernelGGL((k_sweep2<R, false>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst, c->d_pref_st,
-                           c->n, l);
+                           c->n, l, pub, c->pub_seq);
 }
 void launch_sweep2(tdgl_ctx *c, int l) {
     if (c->rows == 1) launch_sweep2_r<1>(c, l);
@@ -828,16 +839,50 @@ tdgl_status enqueue_vcycle(tdgl_ctx *c, int cyc) {
     return TDGL_OK;
 }
 
+// Contexts with fewer nodes than this keep two sweep launches in flight.
+constexpr long long kPollLag2Nodes = 4ll << 20;
+
+// Host wait for the word of this solve at w: spins on the pinned word and,
+// now and then, asks whether the stream has drained or failed, so a word
+// that can no longer come ends in an error instead of a hang.
+tdgl_status wait_pub(tdgl_ctx *ctx, const unsigned long long *w, unsigned *bits) {
+    for (unsigned it = 1;; ++it) {
+        const unsigned long long v = __atomic_load_n(w, __ATOMIC_ACQUIRE);
+        if ((unsigned)(v >> 32) == ctx->pub_seq) {
+            *bits = (unsigned)v;
+            return TDGL_OK;
+        }
+        if ((it & 255u) == 0u) {
+            const hipError_t q = hipStreamQuery(ctx->stream);
+            if (q == hipSuccess) {
+                const unsigned long long v2 = __atomic_load_n(w, __ATOMIC_ACQUIRE);
+                if ((unsigned)(v2 >> 32) == ctx->pub_seq) {
+                    *bits = (unsigned)v2;
+                    return TDGL_OK;
+                }
+                return fail(TDGL_EDEVICE, "a convergence word was never handed over");
+            }
+            if (q != hipErrorNotReady) return fail(TDGL_EDEVICE, "HIP error: %s", hipGetErrorString(q));
+        }
+        __builtin_ia32_pause();
+    }
+}
+
 // The Jacobi iterations after the first sweep (already enqueued, its input
 // residual in row 0): sweep l reads row l-1 on the device and is a no-op
-// for instances whose solve has ended; the host reads the rows one sweep
-// behind and stops enqueueing once every instance has met its stop rule or
-// cap.  Then the per-instance result buffer is fixed on the device
-// (count_step: also advance the step counters).  Accumulates statistics.
+// for instances whose solve has ended.  The work-group of each instance's
+// first tile also hands the row it read to pinned host memory, so row r
+// reaches the host when the launch after the one that wrote it starts; the
+// host waits for the rows of the launch poll_lag launches behind the newest
+// and stops enqueueing once every instance has met its stop rule.  A row that
+// no sweep hands over (an instance's cap row, the last rows before the
+// context's cap) leaves that instance to the finalize kernel, which fixes the
+// per-instance result buffer on the device (count_step: also advances the
+// step counters) and hands its iteration count and last residual over;
+// the host waits for those only when statistics or a strict stop need them.
 tdgl_status jacobi_loop(tdgl_ctx *ctx, tdgl_step_stats *acc, bool *strict_fail, int count_step) {
     const int n = ctx->n;
     hipStream_t s = ctx->stream;
-    const size_t RW = ctx->row_words();
     if (ctx->persist) {
         // one launch, no host round trip; the statistics come from the
         // device counters (tdgl_step reads them)
@@ -848,27 +893,50 @@ tdgl_status jacobi_loop(tdgl_ctx *ctx, tdgl_step_stats *acc, bool *strict_fail, 
         }
         ProfScope ps(ctx, TDGL_K_OTHER);
         hipLaunchKernelGGL(k_solve_finalize, dim3(n), dim3(FIN_THREADS), 0, s, ctx->d_inst, n, count_step,
-                           ctx->max_iter, 0);
+                           ctx->max_iter, 0, nullptr, 0u);
         LAUNCHCHK();
         return TDGL_OK;
     }
-    HIPCHK(hipMemcpyAsync(ctx->h_res, ctx->d_res, RW * 4, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipEventRecord(ctx->ev[0], s));
+    ++ctx->pub_seq;
+    ctx->pub_on = true;
+    struct PubOff {  // sweeps launched after this loop hand nothing over
+        tdgl_ctx *c;
+        ~PubOff() { c->pub_on = false; }
+    } pub_off{ctx};
+    // per instance: the row that ended the solve (-1: undecided), or
+    // deferred to the finalize kernel's report
     std::vector<int> conv_at(n, -1);
+    std::vector<float> conv_r(n, 0.f);
+    std::vector<char> deferred(n, 0);
     const int MI = ctx->max_iter;
-    // residual rows produced so far (row l: input residual of sweep l) and
-    // rows of the newest launch (two for a two-sweep pass)
-    int remaining = n, launched = 1, polled = 0, newest = 1;
+    // start index of every launch so far (0: the assemble kernel); launch k
+    // hands over the rows below starts[k] not handed over before
+    std::vector<int> starts{0};
+    starts.reserve(MI + 1);
+    int remaining = n, launched = 1, polled = 0;
     for (;;) {
-        // inspect the rows of all launches except the newest one
-        while (remaining > 0 && polled < launched && (polled < launched - newest || launched >= MI)) {
-            HIPCHK(hipEventSynchronize(ctx->ev[polled]));
+        // rows handed over by launches at least poll_lag behind the newest
+        // (all of them once no launch can follow)
+        const int nk = (int)starts.size();
+        const int kk = (launched >= MI) ? nk - 1 : nk - ctx->poll_lag;
+        const int avail = (kk >= 1) ? starts[kk] : 0;  // rows < avail are handed over
+        while (remaining > 0 && polled < avail) {
             for (int i = 0; i < n; ++i) {
-                if (conv_at[i] >= 0) continue;
+                if (conv_at[i] >= 0 || deferred[i]) continue;
                 const InstHost &h = ctx->inst[i];
-                const float r = ctx->host_row_max(ctx->h_res, polled, i);
-                if (r < (float)h.p.tol || polled + 1 >= h.p.max_iter) {
+                if (polled + 1 >= h.p.max_iter) {  // the cap row: no sweep hands it over
+                    deferred[i] = 1;
+                    --remaining;
+                    continue;
+                }
+                unsigned bits;
+                tdgl_status e = wait_pub(ctx, ctx->h_pub + (size_t)polled * n + i, &bits);
+                if (e) return e;
+                float r;
+                memcpy(&r, &bits, 4);
+                if (r < (float)h.p.tol) {
                     conv_at[i] = polled;
+                    conv_r[i] = r;
                     --remaining;
                 }
             }
@@ -883,33 +951,46 @@ tdgl_status jacobi_loop(tdgl_ctx *ctx, tdgl_step_stats *acc, bool *strict_fail, 
             else launch_stencil<MODE_SWEEP>(ctx, l);
         }
         LAUNCHCHK();
-        HIPCHK(hipMemcpyAsync(ctx->h_res + (size_t)l * RW, ctx->d_res + (size_t)l * RW, (size_t)nr * RW * 4,
-                              hipMemcpyDeviceToHost, s));
-        for (int q = 0; q < nr; ++q) HIPCHK(hipEventRecord(ctx->ev[l + q], s));
+        starts.push_back(l);
         launched += nr;
-        newest = nr;
     }
+    for (int i = 0; i < n; ++i)
+        if (conv_at[i] < 0 && !deferred[i]) deferred[i] = 1;  // rows past the last hand-over
+    unsigned long long *fin = ctx->d_pub + (size_t)MI * n;
     {
         ProfScope ps(ctx, TDGL_K_OTHER);
         hipLaunchKernelGGL(k_solve_finalize, dim3(n), dim3(FIN_THREADS), 0, s, ctx->d_inst, n, count_step,
-                           launched, ctx->fused ? 1 : 0);
+                           launched, ctx->fused ? 1 : 0, fin, ctx->pub_seq);
         if (ctx->fused) launch_stencil<MODE_SWEEP>(ctx, -2);  // corrective sweep where needed
     }
     LAUNCHCHK();
-    for (int i = 0; acc && i < n; ++i) {
+    bool need_strict = false;
+    for (int i = 0; i < n; ++i) need_strict = need_strict || (deferred[i] && ctx->inst[i].p.strict);
+    if (!acc && !(need_strict && strict_fail)) return TDGL_OK;
+    for (int i = 0; i < n; ++i) {
         const InstHost &h = ctx->inst[i];
-        const float r = ctx->host_row_max(ctx->h_res, conv_at[i], i);
+        int sw;
+        float r;
+        if (!deferred[i]) {
+            sw = conv_at[i] + 1;
+            r = conv_r[i];
+        } else {
+            unsigned sb, rb;
+            tdgl_status e = wait_pub(ctx, ctx->h_pub + (size_t)MI * n + i, &sb);
+            if (!e) e = wait_pub(ctx, ctx->h_pub + (size_t)MI * n + n + i, &rb);
+            if (e) return e;
+            sw = (int)sb;
+            memcpy(&r, &rb, 4);
+        }
         const bool capped = !(r < (float)h.p.tol);
-        const int sw = capped ? h.p.max_iter : conv_at[i] + 1;
+        if (capped && h.p.strict && strict_fail) *strict_fail = true;
+        if (!acc) continue;
         acc->sweep_passes += ctx->fused ? sw / 2 : sw - 1;
         acc->sweeps_min = std::min(acc->sweeps_min, sw);
         acc->sweeps_max = std::max(acc->sweeps_max, sw);
         acc->sweeps_sum += sw;
         acc->last_res2 = r;
-        if (capped) {
-            acc->capped_steps++;
-            if (h.p.strict && strict_fail) *strict_fail = true;
-        }
+        if (capped) acc->capped_steps++;
     }
     return TDGL_OK;
 }
@@ -1034,7 +1115,7 @@ tdgl_status enqueue_step_fixed(tdgl_ctx *ctx, int budget) {
     else
         for (int l = 1; l < budget; ++l) launch_stencil<MODE_SWEEP>(ctx, l);
     hipLaunchKernelGGL(k_solve_finalize, dim3(n), dim3(FIN_THREADS), 0, s, ctx->d_inst, n, 1, budget,
-                       ctx->fused ? 1 : 0);
+                       ctx->fused ? 1 : 0, nullptr, 0u);
     if (ctx->fused) launch_stencil<MODE_SWEEP>(ctx, -2);
     LAUNCHCHK();
     if (!ctx->any_driven) return TDGL_OK;
@@ -1106,15 +1187,22 @@ tdgl_status tdgl_create(int n, const tdgl_params *params, void *ws, size_t ws_by
         if (!h.d.fft) c->nlev_max = std::max(c->nlev_max, h.d.nlev);
     }
     auto bail = [&](tdgl_status st) { tdgl_destroy(c); return st; };
-    if (hipHostMalloc((void **)&c->h_res, c->max_iter * c->row_words() * 4, hipHostMallocDefault) != hipSuccess ||
+    // sweeps of a few microseconds finish before the host has reacted to a
+    // launch's start: keep one more launch queued for small contexts
+    {
+        long long nodes = 0;
+        for (auto &h : c->inst) nodes += (long long)h.d.N;
+        c->poll_lag = nodes < kPollLag2Nodes ? 2 : 1;
+    }
+    const size_t pub_words = ((size_t)c->max_iter + 2) * n;
+    if (hipHostMalloc((void **)&c->h_pub, pub_words * 8, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&c->h_mures, c->max_cycles * c->row_words() * 4, hipHostMallocDefault) !=
             hipSuccess)
         return bail(fail(TDGL_EDEVICE, "hipHostMalloc of the polling buffers failed"));
-    c->ev.resize(c->max_iter);
+    memset(c->h_pub, 0, pub_words * 8);  // sequence 0 is never a solve's
+    if (hipHostGetDevicePointer((void **)&c->d_pub, c->h_pub, 0) != hipSuccess)
+        return bail(fail(TDGL_EDEVICE, "hipHostGetDevicePointer of the convergence words failed"));
     c->evc.resize(c->max_cycles);
-    for (auto &e : c->ev)
-        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
-            return bail(fail(TDGL_EDEVICE, "hipEventCreate failed"));
     for (auto &e : c->evc)
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
             return bail(fail(TDGL_EDEVICE, "hipEventCreate failed"));
@@ -1158,13 +1246,12 @@ tdgl_status tdgl_create(int n, const tdgl_params *params, void *ws, size_t ws_by
 tdgl_status tdgl_destroy(tdgl_ctx *ctx) {
     if (!ctx) return TDGL_OK;
     (void)hipStreamSynchronize(ctx->stream);
-    for (auto &e : ctx->ev) if (e) (void)hipEventDestroy(e);
     for (auto &e : ctx->evc) if (e) (void)hipEventDestroy(e);
     for (auto &e : ctx->prof_pool) if (e) (void)hipEventDestroy(e);
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
-    if (ctx->h_res) (void)hipHostFree(ctx->h_res);
+    if (ctx->h_pub) (void)hipHostFree(ctx->h_pub);
     if (ctx->h_mures) (void)hipHostFree(ctx->h_mures);
     delete ctx;
     return TDGL_OK;

@@ -42,12 +42,16 @@ __global__ void k_links(const Inst *__restrict__ insts, int which) {
 // End of a Jacobi solve: the first sweep l whose input residual met tol ends
 // the solve with that sweep's output (Eq. convergence); otherwise the cap,
 // which is the instance's max_iter or the nl sweeps launched, whichever is
-// smaller.  fused: the sweeps after the first ran as two-sweep passes.  Updates the psi buffer index, step counters and clears the
-// residual words for the next step.  One thread per instance.
+// smaller.  fused: the sweeps after the first ran as two-sweep passes.
+// Updates the psi buffer index and step counters and clears the residual
+// words for the next step.
 __global__ __launch_bounds__(FIN_THREADS) void k_solve_finalize(const Inst *__restrict__ insts, int ninst,
-                                                                  int count_step, int nl, int fused) {
+                                                                  int count_step, int nl, int fused,
+                                                                  unsigned long long *pub, unsigned seq) {
     // one work-group per instance: the first wavefront scans the rows, then
-    // all threads clear them
+    // all threads clear them.  pub (host-driven solves): the iteration count
+    // and the last tested residual go to the host at pub[ii] and
+    // pub[ninst + ii], tagged seq.
     const int ii = blockIdx.x;
     if (ii >= ninst) return;
     const Inst &I = insts[ii];
@@ -86,6 +90,10 @@ __global__ __launch_bounds__(FIN_THREADS) void k_solve_finalize(const Inst *__re
             }
             // keep the last tested residual
             st->last_res2 = last;
+            if (pub) {
+                publish(pub + ii, seq, __int_as_float(sweeps));
+                publish(pub + ninst + ii, seq, last);
+            }
         }
     }
     __syncthreads();

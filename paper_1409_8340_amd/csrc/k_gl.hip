@@ -31,10 +31,13 @@ namespace tdgl {
 // more waves resident; the autotuner picks R and the z chunk).
 // One pass of MODE over tile b of the batched grid (see k_stencil); used by
 // the ordinary launch (one tile per work-group) and by the persistent Jacobi
-// solve (tiles in a grid-stride loop).
+// solve (tiles in a grid-stride loop).  pub (sweeps of a host-driven solve,
+// else null): the work-group of each instance's first tile hands the row
+// l - 1 it has read to the host, tagged seq.
 template <int MODE, int R, bool NT>
 __device__ __forceinline__ void stencil_tile(const Inst *__restrict__ insts, const int *__restrict__ prefix,
-                                             int ninst, int l, const float2 *ext_in, float2 *ext_out, int b) {
+                                             int ninst, int l, const float2 *ext_in, float2 *ext_out, int b,
+                                             unsigned long long *pub, unsigned seq) {
     constexpr int ROWS = R;
     constexpr int TYv = 4 * R;
     constexpr int HALOv = 2 * TX + 2 * TYv;
@@ -61,6 +64,7 @@ __device__ __forceinline__ void stencil_tile(const Inst *__restrict__ insts, con
         // is a no-op for it.
         if (l >= I.max_iter) return;
         const float prev = row_max_wave(I.res, I.rstride, l - 1);
+        if (pub && b == prefix[ii] && threadIdx.x == 0) publish(pub + (size_t)(l - 1) * ninst + ii, seq, prev);
         if (prev < I.tol) return;
     }
     if ((MODE == MODE_RHS) && !I.driven) return;
@@ -274,8 +278,10 @@ __device__ __forceinline__ void stencil_tile(const Inst *__restrict__ insts, con
 template <int MODE, int R, bool NT>
 __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
                                                 const int *__restrict__ prefix, int ninst, int l,
-                                                const float2 *ext_in, float2 *ext_out) {
-    stencil_tile<MODE, R, NT>(insts, prefix, ninst, l, ext_in, ext_out, xcd_remap(blockIdx.x, gridDim.x));
+                                                const float2 *ext_in, float2 *ext_out, unsigned long long *pub,
+                                                unsigned seq) {
+    stencil_tile<MODE, R, NT>(insts, prefix, ninst, l, ext_in, ext_out, xcd_remap(blockIdx.x, gridDim.x), pub,
+                              seq);
 }
 
 // The whole Jacobi solve of every instance in one cooperative launch: sweeps
@@ -312,13 +318,14 @@ __global__ __launch_bounds__(WG) void k_jacobi_persist(const Inst *__restrict__ 
         }
         for (int t = blockIdx.x; t < ntiles; t += gridDim.x)
             stencil_tile<MODE_SWEEP, R, NT>(insts, prefix, ninst, timing ? -1 : l, nullptr, nullptr,
-                                            xcd_remap(t, ntiles));
+                                            xcd_remap(t, ntiles), nullptr, 0u);
         grid.sync();
     }
 }
 
 #define TDGL_INST(M, R, NT) \
-    template __global__ void k_stencil<M, R, NT>(const Inst *, const int *, int, int, const float2 *, float2 *);
+    template __global__ void k_stencil<M, R, NT>(const Inst *, const int *, int, int, const float2 *, float2 *, \
+                                                 unsigned long long *, unsigned);
 #define TDGL_INST_R(R)                 \
     TDGL_INST(MODE_FIRST, R, false)    \
     TDGL_INST(MODE_FIRST, R, true)     \

@@ -99,7 +99,7 @@ __device__ __forceinline__ void halo2_cell(int h, int x0, int y0, int &gx, int &
 
 template <int R, bool NT>
 __global__ __launch_bounds__(WG) void k_sweep2(const Inst *__restrict__ insts, const int *__restrict__ prefix,
-                                               int ninst, int l) {
+                                               int ninst, int l, unsigned long long *pub, unsigned seq) {
     constexpr int TYv = 4 * R;
     constexpr int LX = TX + 4, LY = TYv + 4;
     constexpr int NH2 = LX * LY - TX * TYv;   // two-node halo slots of psi^(l)
@@ -122,8 +122,15 @@ __global__ __launch_bounds__(WG) void k_sweep2(const Inst *__restrict__ insts, c
         // here too), and the buffer of psi^(l-1) must survive for the
         // corrective sweep
         if (l >= I.max_iter) return;
-        if (row_max_wave(I.res, I.rstride, l - 1) < I.tol) return;
-        if (l >= 2 && row_max_wave(I.res, I.rstride, l - 2) < I.tol) return;
+        const float p1 = row_max_wave(I.res, I.rstride, l - 1);
+        const float p2 = (l >= 2) ? row_max_wave(I.res, I.rstride, l - 2) : 1.f;
+        // hand rows l - 1 and l - 2 (written by the previous pass) to the host
+        if (pub && b == prefix[ii] && threadIdx.x == 0) {
+            publish(pub + (size_t)(l - 1) * ninst + ii, seq, p1);
+            if (l >= 2) publish(pub + (size_t)(l - 2) * ninst + ii, seq, p2);
+        }
+        if (p1 < I.tol) return;
+        if (l >= 2 && p2 < I.tol) return;
     }
     const bool rec2 = !timing && (l + 1 < I.max_iter);
 
@@ -380,7 +387,7 @@ __global__ __launch_bounds__(WG) void k_sweep2(const Inst *__restrict__ insts, c
 }
 
 #define TDGL_INST2(R, NT) \
-    template __global__ void k_sweep2<R, NT>(const Inst *, const int *, int, int);
+    template __global__ void k_sweep2<R, NT>(const Inst *, const int *, int, int, unsigned long long *, unsigned);
 TDGL_INST2(1, false)
 TDGL_INST2(1, true)
 TDGL_INST2(2, false)

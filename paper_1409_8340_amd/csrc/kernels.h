@@ -10,15 +10,17 @@ constexpr int CO_THREADS = 1024;
 constexpr int FIN_THREADS = 256;  // threads per instance of the solve finalizers
 
 template <int R, bool NT>
-__global__ void k_sweep2(const Inst *insts, const int *prefix, int ninst, int l);
+__global__ void k_sweep2(const Inst *insts, const int *prefix, int ninst, int l, unsigned long long *pub,
+                         unsigned seq);
 template <int R, bool NT>
 __global__ void k_jacobi_persist(const Inst *insts, const int *prefix, int ninst, int l0, int lcap, int ntiles);
 template <int MODE, int R, bool NT>
 __global__ void k_stencil(const Inst *insts, const int *prefix, int ninst, int l, const float2 *ext_in,
-                          float2 *ext_out);
+                          float2 *ext_out, unsigned long long *pub, unsigned seq);
 
 __global__ void k_links(const Inst *insts, int which);
-__global__ void k_solve_finalize(const Inst *insts, int ninst, int count_step, int nl, int fused);
+__global__ void k_solve_finalize(const Inst *insts, int ninst, int count_step, int nl, int fused,
+                                 unsigned long long *pub, unsigned seq);
 __global__ void k_acc_reset(const Inst *insts, int ninst);
 __global__ void k_jav_partial(const Inst *insts, const int *prefix, int ninst);
 __global__ void k_kupdate(const Inst *insts, const int *nparts);

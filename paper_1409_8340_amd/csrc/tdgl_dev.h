@@ -195,6 +195,15 @@ __device__ __forceinline__ float row_max_wave(const unsigned *base, int rstride,
     return __uint_as_float(m);
 }
 
+// Convergence value v of one (row, instance) handed to the host: one
+// 64-bit system-scope store into pinned host memory, the high word the
+// solve's sequence number so that the host tells this solve's value from an
+// older one without clearing the buffer.
+__device__ __forceinline__ void publish(unsigned long long *w, unsigned seq, float v) {
+    const unsigned long long x = ((unsigned long long)seq << 32) | (unsigned long long)__float_as_uint(v);
+    __hip_atomic_store(w, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Node weight: 1/2 per open face the node lies on (trapezoid rule).
 __device__ __forceinline__ float node_w(const Inst &I, int x, int y, int k) {
     float w = 1.f;
