@@ -322,7 +322,10 @@ tdgl_status tdgl_adjoint_plan(const tdgl_ctx *ctx, int nsteps, int ckpt_every, s
  * adjoint, Sec. 3.1-3.2), the phase rewind having derivative one -- so it
  * matches finite differences when the solves are converged tightly (small
  * tol and mu_tol).  Reverse sweep over the steps; the states of each segment
- * of ckpt_every steps are recomputed from a checkpoint.  ws/ws_bytes: the
+ * of ckpt_every steps but the last are recomputed from a checkpoint (the
+ * last segment's states are kept from the forward run, so ckpt_every >=
+ * nsteps recomputes nothing: the whole trajectory sits in the workspace,
+ * 12 bytes per node and step).  ws/ws_bytes: the
  * workspace of tdgl_adjoint_plan (256-byte aligned).  The context ends in
  * the state after nsteps steps.  Synchronising. */
 tdgl_status tdgl_voltage_grad(tdgl_ctx *ctx, int nsteps, int window_begin, int ckpt_every, void *ws,

@@ -1838,7 +1838,7 @@ tdgl_status tdgl_get_tiling(const tdgl_ctx *ctx, int inst, tdgl_tiling *out) {
 namespace {
 
 struct AdjLayout {
-    float2 *ck_psi, *seg_psi, *fin_psi, *psibar, *t1, *t2, *t3;
+    float2 *ck_psi, *seg_psi, *fin_psi, *psibar, *t1, *t2, *t3, *lamW;
     float *ck_mu, *seg_mu, *fin_mu, *mubar;
     double *ck_K, *seg_K, *fin_K, *Elog;
     DevState *fin_st;
@@ -1864,6 +1864,7 @@ size_t adj_layout(long N, int nsteps, int C, char *base, AdjLayout *L) {
     l.t1 = cv.take<float2>(N);
     l.t2 = cv.take<float2>(N);
     l.t3 = cv.take<float2>(N);
+    l.lamW = cv.take<float2>(N);
     l.Elog = cv.take<double>(nsteps);
     l.adj = cv.take<AdjState>(1);
     if (L) *L = l;
@@ -1904,13 +1905,13 @@ tdgl_status adjoint_step(tdgl_ctx *c, const AdjLayout &L, int iprev, int inext, 
     // the Crank-Nicolson system transposed
     hipLaunchKernelGGL(k_adj_maxabs, dim3(G), dim3(256), 0, s, c->d_inst, L.psibar);
     hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(256), 0, s, c->d_inst, G, 3, 0.0, L.adj);
-    hipLaunchKernelGGL(k_adj_assemble, dim3(G), dim3(256), 0, s, c->d_inst, L.psibar, psim, mum, L.adj);
+    hipLaunchKernelGGL(k_adj_assemble, dim3(G), dim3(256), 0, s, c->d_inst, L.psibar, psim, mum, L.lamW, L.adj);
     LAUNCHCHK();
     e = jacobi_loop(c, nullptr, nullptr, 0);
     if (e) return e;
     // sources: eps gradient, mubar^-, K terms and psibar^-
-    hipLaunchKernelGGL(k_adj_scale_nu, dim3(G), dim3(256), 0, s, c->d_inst, L.adj, L.t1);
-    launch_stencil<MODE_NS>(c, 0, L.t1, L.t2);
+    hipLaunchKernelGGL(k_adj_scale_nu, dim3(G), dim3(256), 0, s, c->d_inst, L.adj, L.lamW);
+    launch_stencil<MODE_NS>(c, 0, L.lamW, L.t2);
     hipLaunchKernelGGL(k_adj_edge_s, dim3(G), dim3(256), 0, s, c->d_inst, psim, psin, L.adj);
     hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(256), 0, s, c->d_inst, G, 2, 0.0, L.adj);
     hipLaunchKernelGGL(k_adj_sources, dim3(G), dim3(256), 0, s, c->d_inst, L.psibar, L.mubar, grad, psim, psin,
@@ -1950,38 +1951,52 @@ tdgl_status tdgl_voltage_grad(tdgl_ctx *ctx, int nsteps, int window_begin, int c
     const int G = std::max(1, std::min(h.d.part_cap, 2048));
     hipLaunchKernelGGL(k_fill_f, dim3(fill_grid(N)), dim3(256), 0, s, grad, N, 0.f);
     hipLaunchKernelGGL(k_fill_c, dim3(fill_grid(N)), dim3(256), 0, s, L.psibar, N, 0.f, 0.f);
+    hipLaunchKernelGGL(k_fill_c, dim3(fill_grid(N)), dim3(256), 0, s, L.lamW, N, 0.f, 0.f);
     hipLaunchKernelGGL(k_fill_f, dim3(fill_grid(N)), dim3(256), 0, s, L.mubar, N, 0.f);
     hipLaunchKernelGGL(k_adj_zero, dim3(1), dim3(64), 0, s, L.adj);
     LAUNCHCHK();
-    // forward with checkpoints
+    // forward with checkpoints; the states of the last segment go straight
+    // into the segment buffer, so that segment is not recomputed (with
+    // ckpt_every >= nsteps nothing is)
+    const int ncp = (nsteps + C - 1) / C;
+    const int s0_last = (ncp - 1) * C;
     for (int n = 0; n < nsteps; ++n) {
         if (n % C == 0) {
             const int q = n / C;
             hipLaunchKernelGGL(k_adj_save, dim3(G), dim3(256), 0, s, ctx->d_inst, L.ck_psi + (size_t)q * N,
                                L.ck_mu + (size_t)q * N, L.ck_K + 2 * q, 1);
         }
+        if (n == s0_last)
+            hipLaunchKernelGGL(k_adj_save, dim3(G), dim3(256), 0, s, ctx->d_inst, L.seg_psi, L.seg_mu, L.seg_K, 0);
         tdgl_status e = tdgl_step(ctx, 1, nullptr);
         if (e) return e;
         hipLaunchKernelGGL(k_adj_logE, dim3(1), dim3(64), 0, s, ctx->d_inst, L.Elog, n);
+        if (n >= s0_last) {
+            const int j = n + 1 - s0_last;
+            hipLaunchKernelGGL(k_adj_save, dim3(G), dim3(256), 0, s, ctx->d_inst, L.seg_psi + (size_t)j * N,
+                               L.seg_mu + (size_t)j * N, L.seg_K + j, 0);
+        }
     }
     hipLaunchKernelGGL(k_adj_save, dim3(G), dim3(256), 0, s, ctx->d_inst, L.fin_psi, L.fin_mu, L.fin_K, 1);
     HIPCHK(hipMemcpyAsync(L.fin_st, h.d.st, sizeof(DevState), hipMemcpyDeviceToDevice, s));
     LAUNCHCHK();
-    // reverse sweep, segment by segment
-    const int ncp = (nsteps + C - 1) / C;
+    // reverse sweep, segment by segment (the last one is already stored)
     const double W = (double)(nsteps - window_begin);
     for (int q = ncp - 1; q >= 0; --q) {
         const int s0 = q * C, s1 = std::min(s0 + C, nsteps);
-        hipLaunchKernelGGL(k_adj_load, dim3(G), dim3(256), 0, s, ctx->d_inst, L.ck_psi + (size_t)q * N,
-                           L.ck_mu + (size_t)q * N, L.ck_K + 2 * q);
-        hipLaunchKernelGGL(k_links, dim3(1), dim3(256), 0, s, ctx->d_inst, 1);
-        hipLaunchKernelGGL(k_adj_save, dim3(G), dim3(256), 0, s, ctx->d_inst, L.seg_psi, L.seg_mu, L.seg_K, 0);
-        LAUNCHCHK();
-        for (int j = 1; j <= s1 - s0; ++j) {
-            tdgl_status e = tdgl_step(ctx, 1, nullptr);
-            if (e) return e;
-            hipLaunchKernelGGL(k_adj_save, dim3(G), dim3(256), 0, s, ctx->d_inst, L.seg_psi + (size_t)j * N,
-                               L.seg_mu + (size_t)j * N, L.seg_K + j, 0);
+        if (q != ncp - 1) {
+            hipLaunchKernelGGL(k_adj_load, dim3(G), dim3(256), 0, s, ctx->d_inst, L.ck_psi + (size_t)q * N,
+                               L.ck_mu + (size_t)q * N, L.ck_K + 2 * q);
+            hipLaunchKernelGGL(k_links, dim3(1), dim3(256), 0, s, ctx->d_inst, 1);
+            hipLaunchKernelGGL(k_adj_save, dim3(G), dim3(256), 0, s, ctx->d_inst, L.seg_psi, L.seg_mu, L.seg_K,
+                               0);
+            LAUNCHCHK();
+            for (int j = 1; j <= s1 - s0; ++j) {
+                tdgl_status e = tdgl_step(ctx, 1, nullptr);
+                if (e) return e;
+                hipLaunchKernelGGL(k_adj_save, dim3(G), dim3(256), 0, s, ctx->d_inst, L.seg_psi + (size_t)j * N,
+                                   L.seg_mu + (size_t)j * N, L.seg_K + j, 0);
+            }
         }
         for (int n = s1; n > s0; --n) {
             const double ew = (n - 1 >= window_begin) ? 1.0 / W : 0.0;

@@ -172,17 +172,20 @@ __global__ __launch_bounds__(256) void k_adj_maxabs(const Inst *__restrict__ ins
 }
 
 // Adjoint system of step n: M~ nu = W^-1 psibar / scale with M from
-// (psi^-, mu^-, eps).  Writes b/M~, (ht/2)/M~, the first iterate nu^(1) = b/M~
-// (from nu^(0) = 0) and the residual of nu^(0) into convergence row 0.
+// (psi^-, mu^-, eps).  Writes b/M~ and (ht/2)/M~.  The solve starts warm
+// from the previous reverse step's solution: lamW holds scale' nu' of that
+// step (zero before the first), so nu^(0) = lamW / scale.  No sweep has
+// produced that iterate, so it is stored as iterate 1 and convergence row 0
+// is marked open (+inf): sweep 1 then measures the residual of nu^(0) and
+// the solve proceeds as usual, one iteration index later.
 __global__ __launch_bounds__(256) void k_adj_assemble(const Inst *__restrict__ insts, const float2 *psibar,
                                                       const float2 *psim, const float *mum,
-                                                      const AdjState *adj) {
+                                                      const float2 *lamW, const AdjState *adj) {
     __shared__ float red[4];
     const Inst &I = insts[0];
     const float inv_s = (float)(1.0 / adj->scale);
     const float ht2 = I.ht2, S2 = I.S2, u = I.u;
     float2 *nu1 = I.psi[I.st->cur ^ 1];
-    float rmax = 0.f;
     FLAT_LOOP(m) {
         const float2 p = psim[m];
         const float a2 = cabs2(p);
@@ -192,17 +195,14 @@ __global__ __launch_bounds__(256) void k_adj_assemble(const Inst *__restrict__ i
         const float inv = 1.f / cabs2(Mc);
         const float2 Mi = make_float2(Mc.x * inv, -Mc.y * inv);
         const float2 rhs = cscale(inv_s / node_wm(I, m), psibar[m]);
-        const float2 bh = cmul(rhs, Mi);
-        I.bh[m] = bh;
+        I.bh[m] = cmul(rhs, Mi);
         I.dh[m] = cscale(ht2, Mi);
-        nu1[m] = bh;
-        const float r2 = cabs2(rhs);
-        rmax = (r2 > rmax || r2 != r2) ? r2 : rmax;
+        nu1[m] = cscale(inv_s, lamW[m]);
     }
-    wg_max_to<256>(row_slot(I.res, I.rstride, 0, blockIdx.x), rmax, red);
+    wg_max_to<256>(row_slot(I.res, I.rstride, 0, blockIdx.x), __int_as_float(0x7f800000), red);
 }
 
-// tmp = lambda / W = scale * nu
+// lamW = lambda / W = scale * nu (also the next reverse step's warm start)
 __global__ void k_adj_scale_nu(const Inst *__restrict__ insts, const AdjState *adj, float2 *tmp) {
     const Inst &I = insts[0];
     const float s = (float)adj->scale;
