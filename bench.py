@@ -319,7 +319,11 @@ def main():
     if args.adjoint_steps > 0:
         log(f"[bench] c4 forward+adjoint over {args.adjoint_steps} steps")
         adj = adjoint_ratio(tdgl, inputs, torch, args.adjoint_steps, 50, 100)
-        log(f"[bench] adjoint ratio {adj['ratio']:.3f}")
+        # the same with every state of the window kept in HBM (no recompute)
+        full = adjoint_ratio(tdgl, inputs, torch, args.adjoint_steps, args.adjoint_steps, 100)
+        adj["whole_trajectory"] = {k: full[k] for k in ("ckpt_every", "fwd_adj_ms_per_step", "plain_ms_per_step",
+                                                         "ratio")}
+        log(f"[bench] adjoint ratio {adj['ratio']:.3f} (checkpoint every 50), {full['ratio']:.3f} (whole trajectory)")
 
     batch = None
     if args.batch_steps > 0:

@@ -357,6 +357,8 @@ struct tdgl_ctx {
     // "all" = instances that have level l, "mid" = instances for which level
     // l is not the coarsest (kMaxLevels * (n+1) each)
     int *d_pref_st = nullptr, *d_pref_flat = nullptr, *d_pref_mg = nullptr, *d_pref_mid = nullptr;
+    int *d_pref_b = nullptr;  // blocks of the two-sweep boundary kernel per instance
+    int tot_b = 0;
     int *d_np_st = nullptr, *d_np_flat = nullptr, *d_np_mg0 = nullptr;
     unsigned *d_res = nullptr, *d_mures = nullptr;
     unsigned *h_mures = nullptr;  // pinned copy of the Poisson rows
@@ -401,6 +403,10 @@ struct tdgl_ctx {
     hipGraphExec_t graph_exec = nullptr;
     int graph_budget = 0;
     hipStream_t cap_stream = nullptr;  // private stream the step is captured on
+    // two-sweep passes: the boundary tiles' kernel runs on aux, forked from
+    // and joined back into the context's stream around the interior kernel
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // per-kernel-class timing (tdgl_profile_start/stop)
     unsigned prof_mask = 0;
     std::vector<hipEvent_t> prof_pool;
@@ -431,6 +437,7 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
     int *pref_fx = cv.take<int>(n + 1);
     int *pref_fy = cv.take<int>(n + 1);
     int *pref_fz = cv.take<int>(n + 1);
+    int *pref_b = cv.take<int>(n + 1);
     int *np_st = cv.take<int>(n);
     int *np_flat = cv.take<int>(n);
     int *np_mg0 = cv.take<int>(n);
@@ -474,6 +481,7 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
         d.ux = cv.take<float2>(p.ny);
         d.uz = cv.take<float2>(p.ny);
         d.P = cv.take<float2>((size_t)p.nx * p.nz);
+        d.btile = cv.take<int>((size_t)cdiv(p.nx, TX) * cdiv(p.ny, 4));  // room for any rows per thread
         d.st = cv.take<DevState>(1);
         d.res = res ? res + i : nullptr;
         d.mures = mures ? mures + i : nullptr;
@@ -565,6 +573,7 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
         ctx->d_pref_fx = pref_fx;
         ctx->d_pref_fy = pref_fy;
         ctx->d_pref_fz = pref_fz;
+        ctx->d_pref_b = pref_b;
         ctx->d_np_st = np_st;
         ctx->d_np_flat = np_flat;
         ctx->d_np_mg0 = np_mg0;
@@ -741,13 +750,27 @@ void launch_stencil_r(tdgl_ctx *c, int l, const float2 *in, float2 *out) {
 // One two-sweep pass (l odd; l = -1: timing pass).
 template <int R>
 void launch_sweep2_r(tdgl_ctx *c, int l) {
+    // boundary tiles by the general kernel (which also hands the rows
+    // over) on the aux stream, interior tiles by the plain-load kernel on
+    // the context's stream at the same time: the two write disjoint tiles
+    // and read only psi^(l), b/M and (ht/2)/M.  The few boundary groups are
+    // latency-bound and would otherwise form a tail of their own.
     unsigned long long *pub = (c->pub_on && l > 0) ? c->d_pub : nullptr;
-    if (c->nt)
-        hipLaunchKernelGGL((k_sweep2<R, true>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst, c->d_pref_st,
+    (void)hipEventRecord(c->ev_fork, c->stream);
+    (void)hipStreamWaitEvent(c->aux, c->ev_fork, 0);
+    if (c->nt) {
+        hipLaunchKernelGGL((k_sweep2<R, true>), dim3(c->tot_b), dim3(WG), 0, c->aux, c->d_inst, c->d_pref_b,
                            c->n, l, pub, c->pub_seq);
-    else
-        hipLaunchKernelGGL((k_sweep2<R, false>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst, c->d_pref_st,
+        hipLaunchKernelGGL((k_sweep2i<R, true>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst, c->d_pref_st,
+                           c->n, l);
+    } else {
+        hipLaunchKernelGGL((k_sweep2<R, false>), dim3(c->tot_b), dim3(WG), 0, c->aux, c->d_inst, c->d_pref_b,
                            c->n, l, pub, c->pub_seq);
+        hipLaunchKernelGGL((k_sweep2i<R, false>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst,
+                           c->d_pref_st, c->n, l);
+    }
+    (void)hipEventRecord(c->ev_join, c->aux);
+    (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
 }
 void launch_sweep2(tdgl_ctx *c, int l) {
     if (c->rows == 1) launch_sweep2_r<1>(c, l);
@@ -1140,6 +1163,9 @@ tdgl_status enqueue_step_fixed(tdgl_ctx *ctx, int budget) {
     return TDGL_OK;
 }
 
+// defined with the tiling entry points below
+tdgl_status upload_tiling(tdgl_ctx *ctx);
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1202,11 +1228,16 @@ tdgl_status tdgl_create(int n, const tdgl_params *params, void *ws, size_t ws_by
     memset(c->h_pub, 0, pub_words * 8);  // sequence 0 is never a solve's
     if (hipHostGetDevicePointer((void **)&c->d_pub, c->h_pub, 0) != hipSuccess)
         return bail(fail(TDGL_EDEVICE, "hipHostGetDevicePointer of the convergence words failed"));
+    if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
+        return bail(fail(TDGL_EDEVICE, "cannot create the auxiliary stream or its events"));
     c->evc.resize(c->max_cycles);
     for (auto &e : c->evc)
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
             return bail(fail(TDGL_EDEVICE, "hipEventCreate failed"));
     if ((s = upload_tables(c))) return bail(s);
+    if ((s = upload_tiling(c))) return bail(s);
     // initial state: psi = 1, eps = 1, mu = 0, B = 0, K = 0
     hipStream_t st = c->stream;
     for (int i = 0; i < n; ++i) {
@@ -1251,6 +1282,12 @@ tdgl_status tdgl_destroy(tdgl_ctx *ctx) {
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->aux) {
+        (void)hipStreamSynchronize(ctx->aux);
+        (void)hipStreamDestroy(ctx->aux);
+    }
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     if (ctx->h_pub) (void)hipHostFree(ctx->h_pub);
     if (ctx->h_mures) (void)hipHostFree(ctx->h_mures);
     delete ctx;
@@ -1618,19 +1655,38 @@ namespace {
 // Re-uploads what a change of stencil tiling touches: the instance
 // descriptors and the stencil prefix and partial-count tables.  The stream
 // must be idle.
+// Z planes per work-group of the two-sweep boundary kernel: short runs, so
+// that its few, latency-bound groups end well within the interior kernel.
+constexpr int kBoundaryChunk = 4;
+
 tdgl_status upload_tiling(tdgl_ctx *ctx) {
     const int n = ctx->n;
-    std::vector<int> ps(n + 1, 0), nps(n);
+    std::vector<int> ps(n + 1, 0), nps(n), pb(n + 1, 0);
     std::vector<Inst> di(n);
     for (int i = 0; i < n; ++i) {
-        ps[i + 1] = ps[i] + ctx->inst[i].st_blocks;
-        nps[i] = ctx->inst[i].st_blocks;
-        di[i] = ctx->inst[i].d;
+        InstHost &h = ctx->inst[i];
+        Inst &d = h.d;
+        // the (x, y) tiles the plain-load two-sweep kernel does not take
+        std::vector<int> bt;
+        const int tyv = 4 * d.rows;
+        for (int ty = 0; ty < d.tiles_y; ++ty)
+            for (int tx = 0; tx < d.tiles_x; ++tx)
+                if (!tile_interior2(tx * TX, ty * tyv, tyv, d.nx, d.ny, d.per[0] != 0))
+                    bt.push_back(tx + d.tiles_x * ty);
+        HIPCHK(hipMemcpy(d.btile, bt.data(), bt.size() * 4, hipMemcpyHostToDevice));
+        d.nbt = (int)bt.size();
+        d.bchunk = std::min(d.chunk, kBoundaryChunk);
+        ps[i + 1] = ps[i] + h.st_blocks;
+        nps[i] = h.st_blocks;
+        pb[i + 1] = pb[i] + d.nbt * cdiv(d.nz, d.bchunk);
+        di[i] = d;
     }
     HIPCHK(hipMemcpy(ctx->d_pref_st, ps.data(), (n + 1) * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_np_st, nps.data(), n * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_pref_b, pb.data(), (n + 1) * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_inst, di.data(), n * sizeof(Inst), hipMemcpyHostToDevice));
     ctx->tot_st = ps[n];
+    ctx->tot_b = pb[n];
     return TDGL_OK;
 }
 

@@ -109,10 +109,19 @@ __global__ __launch_bounds__(WG) void k_sweep2(const Inst *__restrict__ insts, c
     __shared__ float2 lb[2][TYv + 2][LDX];    // psi^(l+1) planes v-1, v: tile + ring
     __shared__ float red[WG / 64];
 
+    // work-groups over the instance's non-interior (x, y) tiles, bchunk
+    // planes each (prefix: blocks per instance); the first is tile (0, 0)
+    // from plane 0, which hands the rows over
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int ii = find_inst(prefix, ninst, b);
     const Inst &I = insts[ii];
     const DevState *st = I.st;
+    const int q = b - prefix[ii];
+    const int nzb = (I.nz + I.bchunk - 1) / I.bchunk;
+    const int xyi = q / nzb, zsub = q - xyi * nzb;
+    const int tile = I.btile[xyi];
+    const int txi = tile % I.tiles_x, tyi = tile / I.tiles_x;
+    const int x0 = txi * TX, y0 = tyi * TYv;
     // l < 0: timing pass of the autotuner (psi[cur] -> psi[cur ^ 1], no
     // residual rows, no convergence test)
     const bool timing = l < 0;
@@ -125,7 +134,7 @@ __global__ __launch_bounds__(WG) void k_sweep2(const Inst *__restrict__ insts, c
         const float p1 = row_max_wave(I.res, I.rstride, l - 1);
         const float p2 = (l >= 2) ? row_max_wave(I.res, I.rstride, l - 2) : 1.f;
         // hand rows l - 1 and l - 2 (written by the previous pass) to the host
-        if (pub && b == prefix[ii] && threadIdx.x == 0) {
+        if (pub && q == 0 && threadIdx.x == 0) {
             publish(pub + (size_t)(l - 1) * ninst + ii, seq, p1);
             if (l >= 2) publish(pub + (size_t)(l - 2) * ninst + ii, seq, p2);
         }
@@ -134,14 +143,8 @@ __global__ __launch_bounds__(WG) void k_sweep2(const Inst *__restrict__ insts, c
     }
     const bool rec2 = !timing && (l + 1 < I.max_iter);
 
-    int t = b - prefix[ii];
-    const int txi = t % I.tiles_x;
-    t /= I.tiles_x;
-    const int tyi = t % I.tiles_y;
-    const int tzi = t / I.tiles_y;
-    const int x0 = txi * TX, y0 = tyi * TYv;
-    const int k0 = tzi * I.chunk;
-    const int k1 = min(k0 + I.chunk, I.nz);
+    const int k0 = zsub * I.bchunk;
+    const int k1 = min(k0 + I.bchunk, I.nz);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int x = x0 + lane;
     const int nx = I.nx, ny = I.ny, nz = I.nz;
@@ -386,8 +389,253 @@ __global__ __launch_bounds__(WG) void k_sweep2(const Inst *__restrict__ insts, c
     }
 }
 
-#define TDGL_INST2(R, NT) \
-    template __global__ void k_sweep2<R, NT>(const Inst *, const int *, int, int, unsigned long long *, unsigned);
+// The two-sweep pass on interior tiles (tile_interior2): the tile, its
+// two-node halo of psi^(l) and its ring of psi^(l+1) are real nodes with
+// real neighbours (or their plain images across a periodic x wrap), so
+// every load is a plain load at a fixed in-plane offset,
+// issued unconditionally (a plane outside the grid reads a real plane whose
+// values are never used).  With no loads under branches the prefetched
+// planes stay in flight across the barrier.  The update arithmetic is that
+// of k_sweep2's tile path (same functions, same operands), so both kernels
+// give the same bits; k_sweep2 takes the other tiles.
+template <int R, bool NT>
+__global__ __launch_bounds__(WG) void k_sweep2i(const Inst *__restrict__ insts, const int *__restrict__ prefix,
+                                                int ninst, int l) {
+    constexpr int TYv = 4 * R;
+    constexpr int LX = TX + 4, LY = TYv + 4;
+    constexpr int NH2 = LX * LY - TX * TYv;
+    constexpr int HALOv = 2 * TX + 2 * TYv;
+    static_assert(NH2 <= 2 * WG, "two halo slots per thread at most");
+    __shared__ float2 la[4][LY][LX];          // psi^(l) planes v-1 .. v+2, two-node halo
+    __shared__ float2 lb[2][TYv + 2][LDX];    // psi^(l+1) planes v-1, v: tile + ring
+    __shared__ float red[WG / 64];
+
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int ii = find_inst(prefix, ninst, b);
+    const Inst &I = insts[ii];
+    const int nx = I.nx, ny = I.ny, nz = I.nz;
+    int t = b - prefix[ii];
+    const int txi = t % I.tiles_x;
+    t /= I.tiles_x;
+    const int tyi = t % I.tiles_y;
+    const int tzi = t / I.tiles_y;
+    const int x0 = txi * TX, y0 = tyi * TYv;
+    const bool xper = I.per[0] != 0;
+    if (!tile_interior2(x0, y0, TYv, nx, ny, xper)) return;
+    const bool timing = l < 0;
+    if (!timing) {
+        if (l >= I.max_iter) return;
+        if (row_max_wave(I.res, I.rstride, l - 1) < I.tol) return;
+        if (l >= 2 && row_max_wave(I.res, I.rstride, l - 2) < I.tol) return;
+    }
+    const bool rec2 = !timing && (l + 1 < I.max_iter);
+    const int k0 = tzi * I.chunk;
+    const int k1 = min(k0 + I.chunk, nz);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int x = x0 + lane;
+    const unsigned NXY = (unsigned)nx * (unsigned)ny;
+    const bool zper = I.per[2] != 0;
+
+    const int cur = I.st->cur;
+    const int xs = timing ? 0 : (((l + 1) >> 1) & 1);
+    const gf2 *__restrict__ src = (const gf2 *)I.psi[cur ^ xs];
+    gf2 *__restrict__ dst = (gf2 *)I.psi[cur ^ xs ^ 1];
+    const gf2 *__restrict__ bhp = (const gf2 *)I.bh;
+    const gf2 *__restrict__ dhp = (const gf2 *)I.dh;
+    const float cx = I.cx, cy = I.cy, cz = I.cz, ht2 = I.ht2;
+
+    // own nodes
+    float2 ux[R], uz[R];
+    unsigned oo[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int y = y0 + w * R + r;
+        ux[r] = I.ux[y];
+        uz[r] = I.uz[y];
+        oo[r] = (unsigned)(y * nx + x);
+    }
+    // two-node halo slots this thread stages (h = tid, tid + WG)
+    unsigned h2o[2];
+    int h2l[2];
+    bool h2on[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int h = threadIdx.x + q * WG;
+        h2on[q] = h < NH2;
+        h2o[q] = oo[0];
+        h2l[q] = 0;
+        if (h2on[q]) {
+            int gx, gy, lx, ly;
+            halo2_cell<TYv>(h, x0, y0, gx, gy, lx, ly);
+            const int sx = xper ? ((gx % nx) + nx) % nx : gx;
+            h2o[q] = (unsigned)(gy * nx + sx);
+            h2l[q] = ly * LX + lx;
+        }
+    }
+    // ring slot of psi^(l+1): a real node (or its plain x image) whose
+    // neighbourhood is in la around the slot's own position
+    const int hidx = lane * 4 + w;
+    const bool hthr = hidx < HALOv;
+    int rlx = 0, rly = 0, tlx = 2, tly = 2;
+    unsigned rso = oo[0];
+    float2 rux = make_float2(1.f, 0.f), ruz = make_float2(1.f, 0.f);
+    if (hthr) {
+        int gx, gy;
+        halo_cell<TYv>(hidx, x0, y0, gx, gy, rlx, rly);
+        const int sx = xper ? ((gx % nx) + nx) % nx : gx;
+        rso = (unsigned)(gy * nx + sx);
+        tlx = gx - x0 + 2;
+        tly = gy - y0 + 2;
+        rux = I.ux[gy];
+        ruz = I.uz[gy];
+    }
+
+    auto pz = [&](int v) -> int {
+        if (v >= 0 && v < nz) return v;
+        if (!zper) return -1;
+        return ((v % nz) + nz) % nz;
+    };
+    auto load_a = [&](int p, float2 *ao, float2 *hv) {
+        const unsigned pb = (unsigned)(p < 0 ? 0 : p) * NXY;
+#pragma unroll
+        for (int r = 0; r < R; ++r) ao[r] = ld2(src, pb + oo[r]);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) hv[q] = ld2(src, pb + h2o[q]);
+    };
+    auto stage_a = [&](int v, const float2 *ao, const float2 *hv) {
+        float2 (*L)[LX] = la[v & 3];
+        float2 *Lf = &la[v & 3][0][0];
+#pragma unroll
+        for (int r = 0; r < R; ++r) L[2 + w * R + r][2 + lane] = ao[r];
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            if (h2on[q]) Lf[h2l[q]] = hv[q];
+    };
+    auto load_bd = [&](int p, float2 *bh_, float2 *dh_, float2 &rbh, float2 &rdh) {
+        const unsigned pb = (unsigned)(p < 0 ? 0 : p) * NXY;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            bh_[r] = NT ? ld2nt(bhp, pb + oo[r]) : ld2(bhp, pb + oo[r]);
+            dh_[r] = NT ? ld2nt(dhp, pb + oo[r]) : ld2(dhp, pb + oo[r]);
+        }
+        rbh = ld2(bhp, pb + rso);
+        rdh = ld2(dhp, pb + rso);
+    };
+
+    const int vb0 = (pz(k0 - 1) >= 0) ? k0 - 1 : k0;
+    const int ve = k1;
+    auto needed_a = [&](int v) { return v >= vb0 - 1 && v <= k1 + 1 && pz(v) >= 0; };
+
+    {
+        float2 ao[R], hv[2];
+        for (int v = vb0 - 1; v <= vb0 + 1; ++v)
+            if (needed_a(v)) {
+                load_a(pz(v), ao, hv);
+                stage_a(v, ao, hv);
+            }
+    }
+    // two register sets for the prefetched planes, swapping roles every
+    // plane (the loop body runs twice per trip), so that no register a load
+    // is still filling is ever copied and the loads stay in flight across
+    // the barrier and the compute of the plane before
+    float2 aA[R], hA[2], aB[R], hB[2];       // psi^(l) of a plane two ahead
+    float2 bA[R], dA[R], bB[R], dB[R];       // b/M, (ht/2)/M of the next plane
+    float2 rbA, rdA, rbB, rdB;               // ... at the ring source
+    load_a(needed_a(vb0 + 2) ? pz(vb0 + 2) : -1, aA, hA);
+    load_bd(pz(vb0), bA, dA, rbA, rdA);
+    float2 b2[R], b1[R], bhq[R], dhq[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        b2[r] = b1[r] = make_float2(0.f, 0.f);
+        bhq[r] = make_float2(0.f, 0.f);
+        dhq[r] = make_float2(1.f, 0.f);
+    }
+
+    float rmax1 = 0.f, rmax2 = 0.f;
+    // plane v: stage psi^(l) of v + 2 (an2), sweep 1 on v with b/M of v
+    // (bhc), sweep 2 on v - 1; loads of plane v + 3 into an3 and of b/M of
+    // v + 1 into bhn.  v > ve: a padding step (loads only) that makes the
+    // trip count even.
+    auto body = [&](int v, float2 (&an2)[R], float2 (&hn2)[2], float2 (&an3)[R], float2 (&hn3)[2],
+                    float2 (&bhc)[R], float2 (&dhc)[R], float2 &rbhc, float2 &rdhc, float2 (&bhn)[R],
+                    float2 (&dhn)[R], float2 &rbhn, float2 &rdhn) __attribute__((always_inline)) {
+        const bool live = v <= ve;
+        const int p = pz(v);
+        const bool stageA = live && (p >= 0);
+        const bool stageB = live && (v - 1 >= k0) && (v - 1 < k1);
+        load_a(needed_a(v + 3) ? pz(v + 3) : -1, an3, hn3);
+        load_bd(v + 1 <= k1 ? pz(v + 1) : -1, bhn, dhn, rbhn, rdhn);
+        __syncthreads();
+        if (live && needed_a(v + 2)) stage_a(v + 2, an2, hn2);
+        float2 b0[R];
+        if (stageA) {
+            const float2 (*L)[LX] = la[v & 3];
+            const float2 (*Lm)[LX] = la[(v + 3) & 3];
+            const float2 (*Lp)[LX] = la[(v + 1) & 3];
+            const int lq = v & 1;
+            const bool zm = (p > 0) || zper, zp = (p < nz - 1) || zper;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int ly = 2 + w * R + r, lx = 2 + lane;
+                const float2 c = L[ly][lx];
+                const float2 ns = nsum(ux[r], uz[r], L[ly][lx - 1], L[ly][lx + 1], L[ly - 1][lx], L[ly + 1][lx],
+                                       Lm[ly][lx], Lp[ly][lx], zm, zp, cx, cy, cz);
+                b0[r] = jacobi(bhc[r], dhc[r], ns);
+                const float r2 = resid2(b0[r], c, dhc[r], ht2);
+                rmax1 = (r2 > rmax1 || r2 != r2) ? r2 : rmax1;
+                lb[lq][ly - 1][lx - 1] = b0[r];
+            }
+            if (hthr) {
+                const float2 ns = nsum(rux, ruz, L[tly][tlx - 1], L[tly][tlx + 1], L[tly - 1][tlx], L[tly + 1][tlx],
+                                       Lm[tly][tlx], Lp[tly][tlx], zm, zp, cx, cy, cz);
+                lb[lq][rly][rlx] = jacobi(rbhc, rdhc, ns);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) b0[r] = make_float2(0.f, 0.f);
+        }
+        if (stageB) {
+            const int k = v - 1;
+            const int pk = pz(k);
+            const int lq = k & 1;
+            const bool zm = (pk > 0) || zper, zp = (pk < nz - 1) || zper;
+            const unsigned pbase = (unsigned)pk * NXY;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int ly = 1 + w * R + r;
+                const float2 ns = nsum(ux[r], uz[r], lb[lq][ly][lane], lb[lq][ly][lane + 2], lb[lq][ly - 1][lane + 1],
+                                       lb[lq][ly + 1][lane + 1], b2[r], b0[r], zm, zp, cx, cy, cz);
+                const float2 c2 = jacobi(bhq[r], dhq[r], ns);
+                const float r2 = resid2(c2, b1[r], dhq[r], ht2);
+                rmax2 = (r2 > rmax2 || r2 != r2) ? r2 : rmax2;
+                if (NT) st2nt(dst, pbase + oo[r], c2);
+                else st2(dst, pbase + oo[r], c2);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            b2[r] = b1[r];
+            b1[r] = b0[r];
+            bhq[r] = bhc[r];
+            dhq[r] = dhc[r];
+        }
+    };
+    for (int v = vb0; v <= ve; v += 2) {
+        body(v, aA, hA, aB, hB, bA, dA, rbA, rdA, bB, dB, rbB, rdB);
+        body(v + 1, aB, hB, aA, hA, bB, dB, rbB, rdB, bA, dA, rbA, rdA);
+    }
+    if (timing) return;
+    __syncthreads();
+    wg_max_to<WG>(row_slot(I.res, I.rstride, l, b), rmax1, red);
+    if (rec2) {
+        __syncthreads();
+        wg_max_to<WG>(row_slot(I.res, I.rstride, l + 1, b), rmax2, red);
+    }
+}
+
+#define TDGL_INST2(R, NT)                                                                                   \
+    template __global__ void k_sweep2<R, NT>(const Inst *, const int *, int, int, unsigned long long *, unsigned); \
+    template __global__ void k_sweep2i<R, NT>(const Inst *, const int *, int, int);
 TDGL_INST2(1, false)
 TDGL_INST2(1, true)
 TDGL_INST2(2, false)

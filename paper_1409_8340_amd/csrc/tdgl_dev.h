@@ -123,6 +123,11 @@ struct Inst {
     int part_cap;
     int tiles_x, tiles_y, tiles_z, chunk;   // stencil tiling (chunk: z planes per tile)
     int rows;                               // rows per thread R (tile 64 x 4R)
+    // two-sweep passes: (x, y) tiles that are not interior (tile_interior2),
+    // as txi + tiles_x tyi in increasing order, and the z planes per
+    // work-group of their kernel
+    int *btile;
+    int nbt, bchunk;
     int nlev;
     MGLevel lev[kMaxLevels];
     // direct spectral Poisson solve (periodic x and y, open z)
@@ -155,6 +160,16 @@ __device__ __forceinline__ float2 cdiv(float2 a, float2 b) {
 // Work-groups are dispatched round-robin over the 8 XCDs (blockIdx % 8).
 // Remap so that each XCD receives a contiguous range of logical tiles: tiles
 // that share halos then share that XCD's L2.
+// A tile every node of which, with its two-node halo, is a real node or a
+// plain periodic image in x: full in x, and its halo inside the grid in y
+// and (unless x is periodic) in x -- no quasi-periodic phase, no open-face
+// ghost, no node outside the grid.  Such tiles take the plain-load
+// two-sweep kernel.
+__host__ __device__ inline bool tile_interior2(int x0, int y0, int tyv, int nx, int ny, bool xper) {
+    const bool xin = xper ? (x0 + TX <= nx) : (x0 >= 2 && x0 + TX + 2 <= nx);
+    return xin && y0 >= 2 && y0 + tyv + 2 <= ny;
+}
+
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
     const int q = nb >> 3, r = nb & 7;
     const int x = b & 7, l = b >> 3;
