@@ -38,8 +38,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 SWEEP_BYTES_PER_NODE = 32      # psi in, b/M, (ht/2)/M, psi out (complex64)
 ASSEMBLE_BYTES_PER_NODE = 40   # psi^-, eps, mu in; b/M, (ht/2)/M, psi^(1) out
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_c5_traffic.txt")
-SWEEP_SRCS = [os.path.join(ROOT, "paper_1409_8340_amd", "csrc", f) for f in ("k_gl.hip", "k_gl2.hip", "stencil.h")]
+# committed rocprofv3 counter summaries, one per sweep kernel
+TRAFFIC_FILES = {"k_stencil_sweep": os.path.join(ROOT, "profiles", "sweep_c5_traffic.txt"),
+                 "k_sweep2": os.path.join(ROOT, "profiles", "sweep2_c5_traffic.txt")}
+SWEEP_SRCS = [os.path.join(ROOT, "paper_1409_8340_amd", "csrc", f)
+              for f in ("k_gl.hip", "k_gl2.hip", "stencil.h", "tdgl_dev.h")]
 
 
 def log(*a):
@@ -55,13 +58,16 @@ def kernel_sha():
 
 
 def read_traffic(n_nodes, kernel):
-    """HBM bytes per sweep launch from the committed rocprofv3 counter summary
-    (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by the plain-copy
-    calibration factor), or None when absent or taken on another kernel."""
-    if not os.path.exists(TRAFFIC_FILE):
+    """HBM bytes per full sweep pass (one launch of the single-sweep kernel,
+    or the two kernels of a two-sweep pass) from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by the
+    plain-copy calibration factor), or None when absent or taken on other
+    sources."""
+    path = TRAFFIC_FILES[kernel]
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
@@ -320,10 +326,10 @@ def main():
         log(f"[bench] c4 forward+adjoint over {args.adjoint_steps} steps")
         adj = adjoint_ratio(tdgl, inputs, torch, args.adjoint_steps, 50, 100)
         # the same with every state of the window kept in HBM (no recompute)
-        full = adjoint_ratio(tdgl, inputs, torch, args.adjoint_steps, args.adjoint_steps, 100)
-        adj["whole_trajectory"] = {k: full[k] for k in ("ckpt_every", "fwd_adj_ms_per_step", "plain_ms_per_step",
-                                                         "ratio")}
-        log(f"[bench] adjoint ratio {adj['ratio']:.3f} (checkpoint every 50), {full['ratio']:.3f} (whole trajectory)")
+        whole = adjoint_ratio(tdgl, inputs, torch, args.adjoint_steps, args.adjoint_steps, 100)
+        adj["whole_trajectory"] = {k: whole[k] for k in ("ckpt_every", "fwd_adj_ms_per_step", "plain_ms_per_step",
+                                                          "ratio")}
+        log(f"[bench] adjoint ratio {adj['ratio']:.3f} (checkpoint every 50), {whole['ratio']:.3f} (whole trajectory)")
 
     batch = None
     if args.batch_steps > 0:

@@ -358,7 +358,8 @@ struct tdgl_ctx {
     // l is not the coarsest (kMaxLevels * (n+1) each)
     int *d_pref_st = nullptr, *d_pref_flat = nullptr, *d_pref_mg = nullptr, *d_pref_mid = nullptr;
     int *d_pref_b = nullptr;  // blocks of the two-sweep boundary kernel per instance
-    int tot_b = 0;
+    int *d_pref_i = nullptr;  // ... and of the interior (super-tile) kernel
+    int tot_b = 0, tot_i = 0;
     int *d_np_st = nullptr, *d_np_flat = nullptr, *d_np_mg0 = nullptr;
     unsigned *d_res = nullptr, *d_mures = nullptr;
     unsigned *h_mures = nullptr;  // pinned copy of the Poisson rows
@@ -438,6 +439,7 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
     int *pref_fy = cv.take<int>(n + 1);
     int *pref_fz = cv.take<int>(n + 1);
     int *pref_b = cv.take<int>(n + 1);
+    int *pref_i = cv.take<int>(n + 1);
     int *np_st = cv.take<int>(n);
     int *np_flat = cv.take<int>(n);
     int *np_mg0 = cv.take<int>(n);
@@ -574,6 +576,7 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
         ctx->d_pref_fy = pref_fy;
         ctx->d_pref_fz = pref_fz;
         ctx->d_pref_b = pref_b;
+        ctx->d_pref_i = pref_i;
         ctx->d_np_st = np_st;
         ctx->d_np_flat = np_flat;
         ctx->d_np_mg0 = np_mg0;
@@ -761,13 +764,13 @@ void launch_sweep2_r(tdgl_ctx *c, int l) {
     if (c->nt) {
         hipLaunchKernelGGL((k_sweep2<R, true>), dim3(c->tot_b), dim3(WG), 0, c->aux, c->d_inst, c->d_pref_b,
                            c->n, l, pub, c->pub_seq);
-        hipLaunchKernelGGL((k_sweep2i<R, true>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst, c->d_pref_st,
-                           c->n, l);
+        hipLaunchKernelGGL((k_sweep2i<R, true>), dim3(c->tot_i), dim3(WG * sweep2i_mult(R)), 0, c->stream,
+                           c->d_inst, c->d_pref_i, c->n, l);
     } else {
         hipLaunchKernelGGL((k_sweep2<R, false>), dim3(c->tot_b), dim3(WG), 0, c->aux, c->d_inst, c->d_pref_b,
                            c->n, l, pub, c->pub_seq);
-        hipLaunchKernelGGL((k_sweep2i<R, false>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst,
-                           c->d_pref_st, c->n, l);
+        hipLaunchKernelGGL((k_sweep2i<R, false>), dim3(c->tot_i), dim3(WG * sweep2i_mult(R)), 0, c->stream,
+                           c->d_inst, c->d_pref_i, c->n, l);
     }
     (void)hipEventRecord(c->ev_join, c->aux);
     (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
@@ -1661,18 +1664,21 @@ constexpr int kBoundaryChunk = 4;
 
 tdgl_status upload_tiling(tdgl_ctx *ctx) {
     const int n = ctx->n;
-    std::vector<int> ps(n + 1, 0), nps(n), pb(n + 1, 0);
+    std::vector<int> ps(n + 1, 0), nps(n), pb(n + 1, 0), pi(n + 1, 0);
     std::vector<Inst> di(n);
     for (int i = 0; i < n; ++i) {
         InstHost &h = ctx->inst[i];
         Inst &d = h.d;
-        // the (x, y) tiles the plain-load two-sweep kernel does not take
+        // the 64 x 4R tiles of the super-tiles (M of them stacked in y) that
+        // the plain-load two-sweep kernel does not take
         std::vector<int> bt;
-        const int tyv = 4 * d.rows;
+        const int M = sweep2i_mult(d.rows);
+        const int nsy = cdiv(d.tiles_y, M);
         for (int ty = 0; ty < d.tiles_y; ++ty)
             for (int tx = 0; tx < d.tiles_x; ++tx)
-                if (!tile_interior2(tx * TX, ty * tyv, tyv, d.nx, d.ny, d.per[0] != 0))
+                if (!tile_interior2(tx * TX, (ty / M) * TYS, TYS, d.nx, d.ny, d.per[0] != 0))
                     bt.push_back(tx + d.tiles_x * ty);
+        pi[i + 1] = pi[i] + d.tiles_x * nsy * d.tiles_z;
         HIPCHK(hipMemcpy(d.btile, bt.data(), bt.size() * 4, hipMemcpyHostToDevice));
         d.nbt = (int)bt.size();
         d.bchunk = std::min(d.chunk, kBoundaryChunk);
@@ -1684,9 +1690,11 @@ tdgl_status upload_tiling(tdgl_ctx *ctx) {
     HIPCHK(hipMemcpy(ctx->d_pref_st, ps.data(), (n + 1) * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_np_st, nps.data(), n * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_pref_b, pb.data(), (n + 1) * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_pref_i, pi.data(), (n + 1) * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_inst, di.data(), n * sizeof(Inst), hipMemcpyHostToDevice));
     ctx->tot_st = ps[n];
     ctx->tot_b = pb[n];
+    ctx->tot_i = pi[n];
     return TDGL_OK;
 }
 

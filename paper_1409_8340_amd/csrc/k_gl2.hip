@@ -389,36 +389,44 @@ __global__ __launch_bounds__(WG) void k_sweep2(const Inst *__restrict__ insts, c
     }
 }
 
-// The two-sweep pass on interior tiles (tile_interior2): the tile, its
-// two-node halo of psi^(l) and its ring of psi^(l+1) are real nodes with
-// real neighbours (or their plain images across a periodic x wrap), so
-// every load is a plain load at a fixed in-plane offset,
-// issued unconditionally (a plane outside the grid reads a real plane whose
-// values are never used).  With no loads under branches the prefetched
-// planes stay in flight across the barrier.  The update arithmetic is that
-// of k_sweep2's tile path (same functions, same operands), so both kernels
-// give the same bits; k_sweep2 takes the other tiles.
+// The two-sweep pass on interior super-tiles (tile_interior2 with height
+// TYS): the tile, its two-node halo of psi^(l) and its ring of psi^(l+1)
+// are real nodes with real neighbours (or their plain images across a
+// periodic x wrap), so every load is a plain load at a fixed in-plane
+// offset, issued unconditionally (a plane outside the grid reads a real
+// plane whose values are never used).  With no loads under branches the
+// prefetched planes stay in flight across the barrier.  The update
+// arithmetic is that of k_sweep2's tile path (same functions, same
+// operands), so both kernels give the same bits; k_sweep2 takes the 64 x 4R
+// tiles of the other super-tiles.  NT: the new iterate is stored
+// non-temporally; b/M and (ht/2)/M stay cacheable, since the neighbours'
+// rings read them again.
 template <int R, bool NT>
-__global__ __launch_bounds__(WG) void k_sweep2i(const Inst *__restrict__ insts, const int *__restrict__ prefix,
-                                                int ninst, int l) {
-    constexpr int TYv = 4 * R;
+__global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(const Inst *__restrict__ insts,
+                                                               const int *__restrict__ prefix, int ninst, int l) {
+    constexpr int M = sweep2i_mult(R);
+    constexpr int WGI = WG * M;
+    constexpr int TYv = TYS;
     constexpr int LX = TX + 4, LY = TYv + 4;
     constexpr int NH2 = LX * LY - TX * TYv;
+    constexpr int NQ = (NH2 + WGI - 1) / WGI;  // two-node halo slots per thread
     constexpr int HALOv = 2 * TX + 2 * TYv;
-    static_assert(NH2 <= 2 * WG, "two halo slots per thread at most");
+    static_assert(HALOv <= WGI, "one ring slot per thread at most");
     __shared__ float2 la[4][LY][LX];          // psi^(l) planes v-1 .. v+2, two-node halo
     __shared__ float2 lb[2][TYv + 2][LDX];    // psi^(l+1) planes v-1, v: tile + ring
-    __shared__ float red[WG / 64];
+    __shared__ float red[WGI / 64];
 
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int ii = find_inst(prefix, ninst, b);
     const Inst &I = insts[ii];
     const int nx = I.nx, ny = I.ny, nz = I.nz;
+    // blocks: tiles_x x ceil(tiles_y / M) x tiles_z super-tiles
+    const int nsy = (I.tiles_y + M - 1) / M;
     int t = b - prefix[ii];
     const int txi = t % I.tiles_x;
     t /= I.tiles_x;
-    const int tyi = t % I.tiles_y;
-    const int tzi = t / I.tiles_y;
+    const int tyi = t % nsy;
+    const int tzi = t / nsy;
     const int x0 = txi * TX, y0 = tyi * TYv;
     const bool xper = I.per[0] != 0;
     if (!tile_interior2(x0, y0, TYv, nx, ny, xper)) return;
@@ -454,13 +462,13 @@ __global__ __launch_bounds__(WG) void k_sweep2i(const Inst *__restrict__ insts, 
         uz[r] = I.uz[y];
         oo[r] = (unsigned)(y * nx + x);
     }
-    // two-node halo slots this thread stages (h = tid, tid + WG)
-    unsigned h2o[2];
-    int h2l[2];
-    bool h2on[2];
+    // two-node halo slots this thread stages (h = tid + q WGI)
+    unsigned h2o[NQ];
+    int h2l[NQ];
+    bool h2on[NQ];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int h = threadIdx.x + q * WG;
+    for (int q = 0; q < NQ; ++q) {
+        const int h = threadIdx.x + q * WGI;
         h2on[q] = h < NH2;
         h2o[q] = oo[0];
         h2l[q] = 0;
@@ -474,7 +482,7 @@ __global__ __launch_bounds__(WG) void k_sweep2i(const Inst *__restrict__ insts, 
     }
     // ring slot of psi^(l+1): a real node (or its plain x image) whose
     // neighbourhood is in la around the slot's own position
-    const int hidx = lane * 4 + w;
+    const int hidx = lane * (4 * M) + w;
     const bool hthr = hidx < HALOv;
     int rlx = 0, rly = 0, tlx = 2, tly = 2;
     unsigned rso = oo[0];
@@ -500,7 +508,7 @@ __global__ __launch_bounds__(WG) void k_sweep2i(const Inst *__restrict__ insts, 
 #pragma unroll
         for (int r = 0; r < R; ++r) ao[r] = ld2(src, pb + oo[r]);
 #pragma unroll
-        for (int q = 0; q < 2; ++q) hv[q] = ld2(src, pb + h2o[q]);
+        for (int q = 0; q < NQ; ++q) hv[q] = ld2(src, pb + h2o[q]);
     };
     auto stage_a = [&](int v, const float2 *ao, const float2 *hv) {
         float2 (*L)[LX] = la[v & 3];
@@ -508,15 +516,15 @@ __global__ __launch_bounds__(WG) void k_sweep2i(const Inst *__restrict__ insts, 
 #pragma unroll
         for (int r = 0; r < R; ++r) L[2 + w * R + r][2 + lane] = ao[r];
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
+        for (int q = 0; q < NQ; ++q)
             if (h2on[q]) Lf[h2l[q]] = hv[q];
     };
     auto load_bd = [&](int p, float2 *bh_, float2 *dh_, float2 &rbh, float2 &rdh) {
         const unsigned pb = (unsigned)(p < 0 ? 0 : p) * NXY;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            bh_[r] = NT ? ld2nt(bhp, pb + oo[r]) : ld2(bhp, pb + oo[r]);
-            dh_[r] = NT ? ld2nt(dhp, pb + oo[r]) : ld2(dhp, pb + oo[r]);
+            bh_[r] = ld2(bhp, pb + oo[r]);
+            dh_[r] = ld2(dhp, pb + oo[r]);
         }
         rbh = ld2(bhp, pb + rso);
         rdh = ld2(dhp, pb + rso);
@@ -527,44 +535,44 @@ __global__ __launch_bounds__(WG) void k_sweep2i(const Inst *__restrict__ insts, 
     auto needed_a = [&](int v) { return v >= vb0 - 1 && v <= k1 + 1 && pz(v) >= 0; };
 
     {
-        float2 ao[R], hv[2];
+        float2 ao[R], hv[NQ];
         for (int v = vb0 - 1; v <= vb0 + 1; ++v)
             if (needed_a(v)) {
                 load_a(pz(v), ao, hv);
                 stage_a(v, ao, hv);
             }
     }
-    // two register sets for the prefetched planes, swapping roles every
-    // plane (the loop body runs twice per trip), so that no register a load
-    // is still filling is ever copied and the loads stay in flight across
-    // the barrier and the compute of the plane before
-    float2 aA[R], hA[2], aB[R], hB[2];       // psi^(l) of a plane two ahead
-    float2 bA[R], dA[R], bB[R], dB[R];       // b/M, (ht/2)/M of the next plane
-    float2 rbA, rdA, rbB, rdB;               // ... at the ring source
-    load_a(needed_a(vb0 + 2) ? pz(vb0 + 2) : -1, aA, hA);
-    load_bd(pz(vb0), bA, dA, rbA, rdA);
-    float2 b2[R], b1[R], bhq[R], dhq[R];
+    // three register sets for the prefetched planes, rotating every plane
+    // (the loop body runs three times per trip): psi^(l) of plane q sits in
+    // set q mod 3 from two steps before it is staged, b/M of plane q from
+    // two steps before its sweep, so that two planes of loads are in flight
+    // across each barrier and no register a load is still filling is ever
+    // copied.  Sets are indexed relative to vb0.
+    float2 aS0[R], hS0[NQ], aS1[R], hS1[NQ], aS2[R], hS2[NQ];  // psi^(l)
+    float2 bT0[R], dT0[R], bT1[R], dT1[R], bT2[R], dT2[R];     // b/M, (ht/2)/M
+    float2 rbT0, rdT0, rbT1, rdT1, rbT2, rdT2;                  // ... at the ring source
+    load_a(needed_a(vb0 + 2) ? pz(vb0 + 2) : -1, aS2, hS2);
+    load_a(needed_a(vb0 + 3) ? pz(vb0 + 3) : -1, aS0, hS0);
+    load_bd(pz(vb0), bT0, dT0, rbT0, rdT0);
+    load_bd(vb0 + 1 <= k1 ? pz(vb0 + 1) : -1, bT1, dT1, rbT1, rdT1);
+    float2 b2[R], b1[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        b2[r] = b1[r] = make_float2(0.f, 0.f);
-        bhq[r] = make_float2(0.f, 0.f);
-        dhq[r] = make_float2(1.f, 0.f);
-    }
+    for (int r = 0; r < R; ++r) b2[r] = b1[r] = make_float2(0.f, 0.f);
 
     float rmax1 = 0.f, rmax2 = 0.f;
     // plane v: stage psi^(l) of v + 2 (an2), sweep 1 on v with b/M of v
-    // (bhc), sweep 2 on v - 1; loads of plane v + 3 into an3 and of b/M of
-    // v + 1 into bhn.  v > ve: a padding step (loads only) that makes the
-    // trip count even.
-    auto body = [&](int v, float2 (&an2)[R], float2 (&hn2)[2], float2 (&an3)[R], float2 (&hn3)[2],
-                    float2 (&bhc)[R], float2 (&dhc)[R], float2 &rbhc, float2 &rdhc, float2 (&bhn)[R],
-                    float2 (&dhn)[R], float2 &rbhn, float2 &rdhn) __attribute__((always_inline)) {
+    // (bhc), sweep 2 on v - 1 with b/M of v - 1 (bh2, the set plane v + 2's
+    // b/M is loaded into afterwards); loads of plane v + 4 into an4.  v > ve:
+    // a padding step (loads only) that makes the trip count a multiple of
+    // three.
+    auto body = [&](int v, float2 (&an2)[R], float2 (&hn2)[NQ], float2 (&an4)[R], float2 (&hn4)[NQ],
+                    float2 (&bhc)[R], float2 (&dhc)[R], float2 &rbhc, float2 &rdhc, float2 (&bh2)[R],
+                    float2 (&dh2)[R], float2 &rbh2, float2 &rdh2) __attribute__((always_inline)) {
         const bool live = v <= ve;
         const int p = pz(v);
         const bool stageA = live && (p >= 0);
         const bool stageB = live && (v - 1 >= k0) && (v - 1 < k1);
-        load_a(needed_a(v + 3) ? pz(v + 3) : -1, an3, hn3);
-        load_bd(v + 1 <= k1 ? pz(v + 1) : -1, bhn, dhn, rbhn, rdhn);
+        load_a(needed_a(v + 4) ? pz(v + 4) : -1, an4, hn4);
         __syncthreads();
         if (live && needed_a(v + 2)) stage_a(v + 2, an2, hn2);
         float2 b0[R];
@@ -605,31 +613,31 @@ __global__ __launch_bounds__(WG) void k_sweep2i(const Inst *__restrict__ insts, 
                 const int ly = 1 + w * R + r;
                 const float2 ns = nsum(ux[r], uz[r], lb[lq][ly][lane], lb[lq][ly][lane + 2], lb[lq][ly - 1][lane + 1],
                                        lb[lq][ly + 1][lane + 1], b2[r], b0[r], zm, zp, cx, cy, cz);
-                const float2 c2 = jacobi(bhq[r], dhq[r], ns);
-                const float r2 = resid2(c2, b1[r], dhq[r], ht2);
+                const float2 c2 = jacobi(bh2[r], dh2[r], ns);
+                const float r2 = resid2(c2, b1[r], dh2[r], ht2);
                 rmax2 = (r2 > rmax2 || r2 != r2) ? r2 : rmax2;
                 if (NT) st2nt(dst, pbase + oo[r], c2);
                 else st2(dst, pbase + oo[r], c2);
             }
         }
+        load_bd(v + 2 <= k1 ? pz(v + 2) : -1, bh2, dh2, rbh2, rdh2);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             b2[r] = b1[r];
             b1[r] = b0[r];
-            bhq[r] = bhc[r];
-            dhq[r] = dhc[r];
         }
     };
-    for (int v = vb0; v <= ve; v += 2) {
-        body(v, aA, hA, aB, hB, bA, dA, rbA, rdA, bB, dB, rbB, rdB);
-        body(v + 1, aB, hB, aA, hA, bB, dB, rbB, rdB, bA, dA, rbA, rdA);
+    for (int v = vb0; v <= ve; v += 3) {
+        body(v, aS2, hS2, aS1, hS1, bT0, dT0, rbT0, rdT0, bT2, dT2, rbT2, rdT2);
+        body(v + 1, aS0, hS0, aS2, hS2, bT1, dT1, rbT1, rdT1, bT0, dT0, rbT0, rdT0);
+        body(v + 2, aS1, hS1, aS0, hS0, bT2, dT2, rbT2, rdT2, bT1, dT1, rbT1, rdT1);
     }
     if (timing) return;
     __syncthreads();
-    wg_max_to<WG>(row_slot(I.res, I.rstride, l, b), rmax1, red);
+    wg_max_to<WGI>(row_slot(I.res, I.rstride, l, b), rmax1, red);
     if (rec2) {
         __syncthreads();
-        wg_max_to<WG>(row_slot(I.res, I.rstride, l + 1, b), rmax2, red);
+        wg_max_to<WGI>(row_slot(I.res, I.rstride, l + 1, b), rmax2, red);
     }
 }
 

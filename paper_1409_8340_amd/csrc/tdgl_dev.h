@@ -160,6 +160,13 @@ __device__ __forceinline__ float2 cdiv(float2 a, float2 b) {
 // Work-groups are dispatched round-robin over the 8 XCDs (blockIdx % 8).
 // Remap so that each XCD receives a contiguous range of logical tiles: tiles
 // that share halos then share that XCD's L2.
+// The plain-load two-sweep kernel works on 64 x 16 super-tiles: M = 4 / R
+// wavefront groups of the 64 x 4R tile, so WG * M threads (R = 1: 1024,
+// R = 2: 512, R = 4: 256); the taller tile halves the share of halo and
+// ring nodes against 64 x 8.
+constexpr int TYS = 16;
+__host__ __device__ constexpr int sweep2i_mult(int rows) { return TYS / (4 * rows); }
+
 // A tile every node of which, with its two-node halo, is a real node or a
 // plain periodic image in x: full in x, and its halo inside the grid in y
 // and (unless x is periodic) in x -- no quasi-periodic phase, no open-face

@@ -271,7 +271,7 @@ FUSED_CASES = [
     ((65, 9, 5), (True, False, True), 0.0, 0.2, False),      # a one-column tile at the open x face
     # grids with interior tiles (the plain-load kernel) beside boundary ones
     ((200, 40, 12), (False, False, True), 0.0, 0.15, True),   # quasi-periodic y, ragged x, open z
-    ((160, 26, 7), (True, True, False), 0.1, 0.05, False),    # open x and y faces, periodic z
+    ((160, 42, 7), (True, True, False), 0.1, 0.05, False),    # open x and y faces, periodic z
 ]
 
 
