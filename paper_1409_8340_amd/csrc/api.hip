@@ -761,16 +761,20 @@ void launch_sweep2_r(tdgl_ctx *c, int l) {
     unsigned long long *pub = (c->pub_on && l > 0) ? c->d_pub : nullptr;
     (void)hipEventRecord(c->ev_fork, c->stream);
     (void)hipStreamWaitEvent(c->aux, c->ev_fork, 0);
+    // (tile (0, 0) is never interior, so the boundary grid is never empty;
+    // the interior one is for grids too small to hold a super-tile)
     if (c->nt) {
         hipLaunchKernelGGL((k_sweep2<R, true>), dim3(c->tot_b), dim3(WG), 0, c->aux, c->d_inst, c->d_pref_b,
                            c->n, l, pub, c->pub_seq);
-        hipLaunchKernelGGL((k_sweep2i<R, true>), dim3(c->tot_i), dim3(WG * sweep2i_mult(R)), 0, c->stream,
-                           c->d_inst, c->d_pref_i, c->n, l);
+        if (c->tot_i > 0)
+            hipLaunchKernelGGL((k_sweep2i<R, true>), dim3(c->tot_i), dim3(WG * sweep2i_mult(R)), 0, c->stream,
+                               c->d_inst, c->d_pref_i, c->n, l);
     } else {
         hipLaunchKernelGGL((k_sweep2<R, false>), dim3(c->tot_b), dim3(WG), 0, c->aux, c->d_inst, c->d_pref_b,
                            c->n, l, pub, c->pub_seq);
-        hipLaunchKernelGGL((k_sweep2i<R, false>), dim3(c->tot_i), dim3(WG * sweep2i_mult(R)), 0, c->stream,
-                           c->d_inst, c->d_pref_i, c->n, l);
+        if (c->tot_i > 0)
+            hipLaunchKernelGGL((k_sweep2i<R, false>), dim3(c->tot_i), dim3(WG * sweep2i_mult(R)), 0, c->stream,
+                               c->d_inst, c->d_pref_i, c->n, l);
     }
     (void)hipEventRecord(c->ev_join, c->aux);
     (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
@@ -1672,12 +1676,16 @@ tdgl_status upload_tiling(tdgl_ctx *ctx) {
         // the 64 x 4R tiles of the super-tiles (M of them stacked in y) that
         // the plain-load two-sweep kernel does not take
         std::vector<int> bt;
-        const int M = sweep2i_mult(d.rows);
-        const int nsy = cdiv(d.tiles_y, M);
+        const int M = sweep2i_mult(d.rows), ry = 4 * d.rows;
+        const int nsy = sweep2i_rows(d.ny, d.rows);
         for (int ty = 0; ty < d.tiles_y; ++ty)
-            for (int tx = 0; tx < d.tiles_x; ++tx)
-                if (!tile_interior2(tx * TX, (ty / M) * TYS, TYS, d.nx, d.ny, d.per[0] != 0))
-                    bt.push_back(tx + d.tiles_x * ty);
+            for (int tx = 0; tx < d.tiles_x; ++tx) {
+                // tile row ty >= 1 lies in super-tile row (ty - 1) / M
+                const int j = (ty - 1) / M;
+                const bool inner = ty >= 1 && j < nsy &&
+                                   tile_interior2(tx * TX, ry + j * TYS, TYS, d.nx, d.ny, d.per[0] != 0);
+                if (!inner) bt.push_back(tx + d.tiles_x * ty);
+            }
         pi[i + 1] = pi[i] + d.tiles_x * nsy * d.tiles_z;
         HIPCHK(hipMemcpy(d.btile, bt.data(), bt.size() * 4, hipMemcpyHostToDevice));
         d.nbt = (int)bt.size();

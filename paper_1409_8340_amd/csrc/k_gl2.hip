@@ -411,7 +411,7 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
     constexpr int NH2 = LX * LY - TX * TYv;
     constexpr int NQ = (NH2 + WGI - 1) / WGI;  // two-node halo slots per thread
     constexpr int HALOv = 2 * TX + 2 * TYv;
-    static_assert(HALOv <= WGI, "one ring slot per thread at most");
+    static_assert(HALOv % 4 == 0 && HALOv / 4 <= 64, "ring slots packed into four wavefronts");
     __shared__ float2 la[4][LY][LX];          // psi^(l) planes v-1 .. v+2, two-node halo
     __shared__ float2 lb[2][TYv + 2][LDX];    // psi^(l+1) planes v-1, v: tile + ring
     __shared__ float red[WGI / 64];
@@ -420,14 +420,14 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
     const int ii = find_inst(prefix, ninst, b);
     const Inst &I = insts[ii];
     const int nx = I.nx, ny = I.ny, nz = I.nz;
-    // blocks: tiles_x x ceil(tiles_y / M) x tiles_z super-tiles
-    const int nsy = (I.tiles_y + M - 1) / M;
+    // blocks: tiles_x x sweep2i_rows x tiles_z super-tiles
+    const int nsy = sweep2i_rows(ny, R);
     int t = b - prefix[ii];
     const int txi = t % I.tiles_x;
     t /= I.tiles_x;
     const int tyi = t % nsy;
     const int tzi = t / nsy;
-    const int x0 = txi * TX, y0 = tyi * TYv;
+    const int x0 = txi * TX, y0 = 4 * R + tyi * TYv;
     const bool xper = I.per[0] != 0;
     if (!tile_interior2(x0, y0, TYv, nx, ny, xper)) return;
     const bool timing = l < 0;
@@ -481,9 +481,11 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
         }
     }
     // ring slot of psi^(l+1): a real node (or its plain x image) whose
-    // neighbourhood is in la around the slot's own position
-    const int hidx = lane * (4 * M) + w;
-    const bool hthr = hidx < HALOv;
+    // neighbourhood is in la around the slot's own position.  The slots sit
+    // in the first HALOv / 4 lanes of wavefronts 0..3 (one per SIMD), so the
+    // other wavefronts skip the ring update as a whole.
+    const int hidx = w * (HALOv / 4) + lane;
+    const bool hthr = w < 4 && lane < HALOv / 4;
     int rlx = 0, rly = 0, tlx = 2, tly = 2;
     unsigned rso = oo[0];
     float2 rux = make_float2(1.f, 0.f), ruz = make_float2(1.f, 0.f);

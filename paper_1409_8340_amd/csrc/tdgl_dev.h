@@ -166,6 +166,13 @@ __device__ __forceinline__ float2 cdiv(float2 a, float2 b) {
 // ring nodes against 64 x 8.
 constexpr int TYS = 16;
 __host__ __device__ constexpr int sweep2i_mult(int rows) { return TYS / (4 * rows); }
+// Super-tile rows start one 64 x 4R tile row into the grid (y0 = 4R + TYS j,
+// j < sweep2i_rows), so that a quasi-periodic y seam leaves only the first
+// and the last tile row to the general kernel.
+__host__ __device__ inline int sweep2i_rows(int ny, int rows) {
+    const int r = ny - 4 * rows;
+    return r > 0 ? (r + TYS - 1) / TYS : 0;
+}
 
 // A tile every node of which, with its two-node halo, is a real node or a
 // plain periodic image in x: full in x, and its halo inside the grid in y
