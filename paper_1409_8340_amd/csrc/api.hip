@@ -404,10 +404,6 @@ struct tdgl_ctx {
     hipGraphExec_t graph_exec = nullptr;
     int graph_budget = 0;
     hipStream_t cap_stream = nullptr;  // private stream the step is captured on
-    // two-sweep passes: the boundary tiles' kernel runs on aux, forked from
-    // and joined back into the context's stream around the interior kernel
-    hipStream_t aux = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // per-kernel-class timing (tdgl_profile_start/stop)
     unsigned prof_mask = 0;
     std::vector<hipEvent_t> prof_pool;
@@ -754,30 +750,27 @@ void launch_stencil_r(tdgl_ctx *c, int l, const float2 *in, float2 *out) {
 template <int R>
 void launch_sweep2_r(tdgl_ctx *c, int l) {
     // boundary tiles by the general kernel (which also hands the rows
-    // over) on the aux stream, interior tiles by the plain-load kernel on
-    // the context's stream at the same time: the two write disjoint tiles
-    // and read only psi^(l), b/M and (ht/2)/M.  The few boundary groups are
-    // latency-bound and would otherwise form a tail of their own.
+    // over), then interior super-tiles by the plain-load kernel.  The two
+    // write disjoint tiles and read only psi^(l), b/M and (ht/2)/M; run
+    // side by side on two streams they were slower than in sequence, the
+    // boundary groups taking CU slots from the interior kernel for longer
+    // than the boundary kernel takes alone.
     unsigned long long *pub = (c->pub_on && l > 0) ? c->d_pub : nullptr;
-    (void)hipEventRecord(c->ev_fork, c->stream);
-    (void)hipStreamWaitEvent(c->aux, c->ev_fork, 0);
     // (tile (0, 0) is never interior, so the boundary grid is never empty;
     // the interior one is for grids too small to hold a super-tile)
     if (c->nt) {
-        hipLaunchKernelGGL((k_sweep2<R, true>), dim3(c->tot_b), dim3(WG), 0, c->aux, c->d_inst, c->d_pref_b,
+        hipLaunchKernelGGL((k_sweep2<R, true>), dim3(c->tot_b), dim3(WG), 0, c->stream, c->d_inst, c->d_pref_b,
                            c->n, l, pub, c->pub_seq);
         if (c->tot_i > 0)
             hipLaunchKernelGGL((k_sweep2i<R, true>), dim3(c->tot_i), dim3(WG * sweep2i_mult(R)), 0, c->stream,
                                c->d_inst, c->d_pref_i, c->n, l);
     } else {
-        hipLaunchKernelGGL((k_sweep2<R, false>), dim3(c->tot_b), dim3(WG), 0, c->aux, c->d_inst, c->d_pref_b,
+        hipLaunchKernelGGL((k_sweep2<R, false>), dim3(c->tot_b), dim3(WG), 0, c->stream, c->d_inst, c->d_pref_b,
                            c->n, l, pub, c->pub_seq);
         if (c->tot_i > 0)
             hipLaunchKernelGGL((k_sweep2i<R, false>), dim3(c->tot_i), dim3(WG * sweep2i_mult(R)), 0, c->stream,
                                c->d_inst, c->d_pref_i, c->n, l);
     }
-    (void)hipEventRecord(c->ev_join, c->aux);
-    (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
 }
 void launch_sweep2(tdgl_ctx *c, int l) {
     if (c->rows == 1) launch_sweep2_r<1>(c, l);
@@ -1235,10 +1228,6 @@ tdgl_status tdgl_create(int n, const tdgl_params *params, void *ws, size_t ws_by
     memset(c->h_pub, 0, pub_words * 8);  // sequence 0 is never a solve's
     if (hipHostGetDevicePointer((void **)&c->d_pub, c->h_pub, 0) != hipSuccess)
         return bail(fail(TDGL_EDEVICE, "hipHostGetDevicePointer of the convergence words failed"));
-    if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
-        return bail(fail(TDGL_EDEVICE, "cannot create the auxiliary stream or its events"));
     c->evc.resize(c->max_cycles);
     for (auto &e : c->evc)
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
@@ -1289,12 +1278,6 @@ tdgl_status tdgl_destroy(tdgl_ctx *ctx) {
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
-    if (ctx->aux) {
-        (void)hipStreamSynchronize(ctx->aux);
-        (void)hipStreamDestroy(ctx->aux);
-    }
-    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
-    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     if (ctx->h_pub) (void)hipHostFree(ctx->h_pub);
     if (ctx->h_mures) (void)hipHostFree(ctx->h_mures);
     delete ctx;
