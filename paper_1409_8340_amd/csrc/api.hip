@@ -390,6 +390,7 @@ struct tdgl_ctx {
     int tot_fx = 0, tot_fy = 0, tot_fz = 0;
     size_t fx_lds = 0, fy_lds = 0, fz_lds = 0;
     bool fx_p2 = true, fy_p2 = true;  // every spectral instance has power-of-two nx (ny)
+    bool fx_long = false;             // some spectral instance has nx > FFT_X_PTS
     bool any_fft = false, any_mg = false;
     bool any_driven = false;
     int max_iter = 1, max_cycles = 1;
@@ -652,6 +653,7 @@ tdgl_status upload_tables(tdgl_ctx *ctx) {
             ctx->fx_lds = std::max(ctx->fx_lds, (size_t)(fft_x_pairs(h.p.nx) + 1) * h.p.nx * 8);
             ctx->fy_lds = std::max(ctx->fy_lds, (size_t)(fft_y_cols(h.p.ny) + 1) * h.p.ny * 8);
             ctx->fx_p2 = ctx->fx_p2 && (h.p.nx & (h.p.nx - 1)) == 0;
+            ctx->fx_long = ctx->fx_long || h.p.nx > FFT_X_PTS;
             ctx->fy_p2 = ctx->fy_p2 && (h.p.ny & (h.p.ny - 1)) == 0;
             ctx->fz_lds = std::max(ctx->fz_lds, fft_z_lds(h.p.nz));
         } else if (h.p.driven) {
@@ -672,10 +674,9 @@ tdgl_status upload_tables(tdgl_ctx *ctx) {
     ctx->tot_fy = pfy[n];
     ctx->tot_fz = pfz[n];
     if (ctx->any_fft) {
-        HIPCHK(hipFuncSetAttribute((const void *)k_fft_x<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)ctx->fx_lds));
-        HIPCHK(hipFuncSetAttribute((const void *)k_fft_x<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)ctx->fx_lds));
+        for (const void *fn : {(const void *)k_fft_x<false, FFT_X_PTS>, (const void *)k_fft_x<true, FFT_X_PTS>,
+                                (const void *)k_fft_x<false, 4 * FFT_X_PTS>, (const void *)k_fft_x<true, 4 * FFT_X_PTS>})
+            HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ctx->fx_lds));
         HIPCHK(hipFuncSetAttribute((const void *)k_fft_y<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)ctx->fy_lds));
         HIPCHK(hipFuncSetAttribute((const void *)k_fft_y<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1031,10 +1032,17 @@ tdgl_status enqueue_fft(tdgl_ctx *ctx) {
     ProfScope ps(ctx, TDGL_K_MG_FINE);
     const float *nf = nullptr;
     float *nm = nullptr;
-    const dim3 gx(std::max(ctx->tot_fx, 1)), gy(std::max(ctx->tot_fy, 1)), bt(FFT_XY_THREADS);
+    const dim3 gx(std::max(ctx->tot_fx, 1)), gy(std::max(ctx->tot_fy, 1)), bt(FFT_XY_THREADS), bx(FFT_X_THREADS);
     auto xpass = [&](int dir) {
-        if (ctx->fx_p2) hipLaunchKernelGGL(k_fft_x<true>, gx, bt, ctx->fx_lds, s, ctx->d_inst, ctx->d_pref_fx, n, dir, nf, nm);
-        else hipLaunchKernelGGL(k_fft_x<false>, gx, bt, ctx->fx_lds, s, ctx->d_inst, ctx->d_pref_fx, n, dir, nf, nm);
+        const void *fn = ctx->fx_long ? (ctx->fx_p2 ? (const void *)k_fft_x<true, 4 * FFT_X_PTS>
+                                                    : (const void *)k_fft_x<false, 4 * FFT_X_PTS>)
+                                      : (ctx->fx_p2 ? (const void *)k_fft_x<true, FFT_X_PTS>
+                                                    : (const void *)k_fft_x<false, FFT_X_PTS>);
+        const Inst *ins = ctx->d_inst;
+        const int *pref = ctx->d_pref_fx;
+        int nn = n, d = dir;
+        void *args[] = {(void *)&ins, (void *)&pref, (void *)&nn, (void *)&d, (void *)&nf, (void *)&nm};
+        (void)hipLaunchKernel(fn, gx, bx, args, ctx->fx_lds, s);
     };
     auto ypass = [&](int dir) {
         if (ctx->fy_p2) hipLaunchKernelGGL(k_fft_y<true>, gy, bt, ctx->fy_lds, s, ctx->d_inst, ctx->d_pref_fy, n, dir);

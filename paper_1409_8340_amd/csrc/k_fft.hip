@@ -87,9 +87,10 @@ __device__ __forceinline__ void dft<5>(float2 *v, float sign) {
     v[3] = csub(m2, j2);
 }
 
-constexpr int FFT_THREADS = FFT_XY_THREADS;  // threads of the x and y passes
+constexpr int FFT_THREADS = FFT_XY_THREADS;  // threads of the y passes
 constexpr int ZS_THREADS = 256;              // threads of the z solve (4 wavefronts)
-constexpr int FFT_MAXPTS = FFT_MAXN;  // points per work-group (all sequences)
+constexpr int FFT_MAXPTS = FFT_MAXN;  // points per work-group of the y passes (all sequences)
+
 
 // q = floor(t / d) for 0 <= t < 2^20 and 1 <= d <= 2^13, from a float
 // reciprocal: (t + 1/2) / d stays at least 1/(2d) away from an integer,
@@ -97,13 +98,14 @@ constexpr int FFT_MAXPTS = FFT_MAXN;  // points per work-group (all sequences)
 __device__ __forceinline__ int fdiv(int t, float inv_d) { return (int)(((float)t + 0.5f) * inv_d); }
 
 // One Stockham pass of radix R over `nseq` sequences of length n stored in
-// LDS at buf[s * sstride + e] (element e).  Ns = product of the radices of
-// the previous passes.  tw[k] = exp(-2 pi i k / n) (conjugated for the
-// inverse transform, sign = +1).
-template <int R>
+// LDS at buf[s * sstride + e] (element e), by NT threads; MAXC bounds the
+// points n * nseq.  Ns = product of the radices of the previous passes.
+// tw[k] = exp(-2 pi i k / n) (conjugated for the inverse transform,
+// sign = +1).
+template <int R, int NT, int MAXC>
 __device__ __forceinline__ void fft_pass(float2 *buf, int n, int Ns, int nseq, int sstride, const float2 *tw,
                                          float sign) {
-    constexpr int MAXBF = (FFT_MAXPTS / R + FFT_THREADS - 1) / FFT_THREADS;
+    constexpr int MAXBF = (MAXC / R + NT - 1) / NT;
     const int nb = n / R;
     const int total = nb * nseq;
     const float inv_nb = 1.0f / (float)nb, inv_ns = 1.0f / (float)Ns;
@@ -112,7 +114,7 @@ __device__ __forceinline__ void fft_pass(float2 *buf, int n, int Ns, int nseq, i
     int dst[MAXBF];
 #pragma unroll
     for (int i = 0; i < MAXBF; ++i) {
-        const int t = threadIdx.x + i * FFT_THREADS;
+        const int t = threadIdx.x + i * NT;
         if (t < total) {
             const int s = fdiv(t, inv_nb), j = t - s * nb;
             const int jq = fdiv(j, inv_ns), jm = j - jq * Ns;
@@ -135,7 +137,7 @@ __device__ __forceinline__ void fft_pass(float2 *buf, int n, int Ns, int nseq, i
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < MAXBF; ++i) {
-        const int t = threadIdx.x + i * FFT_THREADS;
+        const int t = threadIdx.x + i * NT;
         if (t < total) {
 #pragma unroll
             for (int r = 0; r < R; ++r) buf[dst[i] + r * Ns] = v[i][r];
@@ -147,16 +149,16 @@ __device__ __forceinline__ void fft_pass(float2 *buf, int n, int Ns, int nseq, i
 // Full transform of nseq sequences in LDS (natural order in and out).
 // P2: the length is a power of two (radices 4 and 2 only), which keeps the
 // kernels small enough for two 1024-thread work-groups per CU.
-template <bool P2>
+template <bool P2, int NT, int MAXC>
 __device__ __forceinline__ void fft_lds(float2 *buf, int n, const int *rad, int nrad, int nseq, int sstride,
                                         const float2 *tw, float sign) {
     int Ns = 1;
     for (int p = 0; p < nrad; ++p) {
         const int R = rad[p];
-        if (R == 4) fft_pass<4>(buf, n, Ns, nseq, sstride, tw, sign);
-        else if (P2 || R == 2) fft_pass<2>(buf, n, Ns, nseq, sstride, tw, sign);
-        else if (R == 3) fft_pass<3>(buf, n, Ns, nseq, sstride, tw, sign);
-        else fft_pass<5>(buf, n, Ns, nseq, sstride, tw, sign);
+        if (R == 4) fft_pass<4, NT, MAXC>(buf, n, Ns, nseq, sstride, tw, sign);
+        else if (P2 || R == 2) fft_pass<2, NT, MAXC>(buf, n, Ns, nseq, sstride, tw, sign);
+        else if (R == 3) fft_pass<3, NT, MAXC>(buf, n, Ns, nseq, sstride, tw, sign);
+        else fft_pass<5, NT, MAXC>(buf, n, Ns, nseq, sstride, tw, sign);
         Ns *= R;
     }
 }
@@ -173,9 +175,10 @@ __device__ __forceinline__ void zrow(int k, int nz, double cz, bool singular, do
 
 }  // namespace
 
-// Row pairs per work-group of the x passes: 2 * pairs * nx <= FFT_MAXPTS.
+// Row pairs per work-group of the x passes: about FFT_X_PTS complex points
+// (one pair of 1024-point rows), at least one pair.
 __host__ __device__ int fft_x_pairs(int nx) {
-    int p = FFT_MAXPTS / (2 * nx);
+    int p = FFT_X_PTS / nx;
     return p < 1 ? 1 : (p > 32 ? 32 : p);
 }
 // kx columns per work-group of the y passes: TK * ny <= FFT_MAXPTS.
@@ -188,14 +191,17 @@ __host__ __device__ int fft_y_cols(int ny) {
 __host__ __device__ int fft_pitch(int nx) { return (nx / 2 + 1 + 15) & ~15; }
 
 // Forward real-to-complex FFT along x of `in` (real rows of length nx) into
-// spec (nx/2+1 bins per row).  The twiddles are staged in LDS after the
-// data (dynamic LDS: (2 pairs + 1) nx complex values).  Two real rows a, b travel as one complex row
+// spec (nx/2+1 bins per row), fft_x_pairs(nx) row pairs per work-group of
+// FFT_X_THREADS threads; XC bounds the complex points per group (FFT_X_PTS,
+// or 4 FFT_X_PTS for longer rows), which sizes the butterfly registers.
+// The twiddles are staged in LDS after the data (dynamic LDS: (pairs + 1)
+// nx complex values).  Two real rows a, b travel as one complex row
 // a + i b; their spectra are separated with the conjugate symmetry
 //   A_k = (Z_k + conj Z_{n-k}) / 2,  B_k = (Z_k - conj Z_{n-k}) / (2 i).
 // Also the inverse (complex-to-real) along x: dir = +1 reads spec, writes
 // `out`.
-template <bool P2>
-__global__ __launch_bounds__(FFT_THREADS) void k_fft_x(const Inst *__restrict__ insts,
+template <bool P2, int XC>
+__global__ __launch_bounds__(FFT_X_THREADS) void k_fft_x(const Inst *__restrict__ insts,
                                                        const int *__restrict__ prefix, int ninst,
                                                        int dir, const float *in_ext, float *out_ext) {
     extern __shared__ float2 sm[];
@@ -205,7 +211,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x(const Inst *__restrict__ 
     const int rows = I.ny * I.nz;
     const int pairs = fft_x_pairs(nx);
     float2 *stw = sm + pairs * nx;
-    for (int t = threadIdx.x; t < nx; t += FFT_THREADS) stw[t] = I.twx[t];
+    for (int t = threadIdx.x; t < nx; t += FFT_X_THREADS) stw[t] = I.twx[t];
     const int row0 = (blockIdx.x - prefix[ii]) * 2 * pairs;
     const float *in = in_ext ? in_ext : I.f;
     float *out = out_ext ? out_ext : I.mu;
@@ -213,7 +219,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x(const Inst *__restrict__ 
     const float inv_nx = 1.0f / (float)nx, inv_p = 1.0f / (float)P;
     // sequence s (pair) holds rows row0 + 2 s (real part) and row0 + 2 s + 1
     if (dir < 0) {
-        for (int t = threadIdx.x; t < pairs * nx; t += FFT_THREADS) {
+        for (int t = threadIdx.x; t < pairs * nx; t += FFT_X_THREADS) {
             const int s = fdiv(t, inv_nx), e = t - s * nx;
             const int ra = row0 + 2 * s, rb = ra + 1;
             const float a = ra < rows ? in[(size_t)ra * nx + e] : 0.f;
@@ -221,8 +227,8 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x(const Inst *__restrict__ 
             sm[t] = make_float2(a, b);
         }
         __syncthreads();
-        fft_lds<P2>(sm, nx, I.xrad, I.nxrad, pairs, nx, stw, -1.f);
-        for (int t = threadIdx.x; t < pairs * P; t += FFT_THREADS) {
+        fft_lds<P2, FFT_X_THREADS, XC>(sm, nx, I.xrad, I.nxrad, pairs, nx, stw, -1.f);
+        for (int t = threadIdx.x; t < pairs * P; t += FFT_X_THREADS) {
             const int s = fdiv(t, inv_p), k = t - s * P;
             const float2 z = sm[s * nx + k];
             const float2 zc = sm[s * nx + (k == 0 ? 0 : nx - k)];
@@ -234,7 +240,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x(const Inst *__restrict__ 
             if (rb < rows) spec[(size_t)rb * sp + k] = B;
         }
     } else {
-        for (int t = threadIdx.x; t < pairs * nx; t += FFT_THREADS) {
+        for (int t = threadIdx.x; t < pairs * nx; t += FFT_X_THREADS) {
             const int s = fdiv(t, inv_nx), k = t - s * nx;
             const int ra = row0 + 2 * s, rb = ra + 1;
             const bool lo = k < P;
@@ -246,8 +252,8 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x(const Inst *__restrict__ 
             sm[t] = make_float2(A.x - B.y, A.y + B.x);
         }
         __syncthreads();
-        fft_lds<P2>(sm, nx, I.xrad, I.nxrad, pairs, nx, stw, +1.f);
-        for (int t = threadIdx.x; t < pairs * nx; t += FFT_THREADS) {
+        fft_lds<P2, FFT_X_THREADS, XC>(sm, nx, I.xrad, I.nxrad, pairs, nx, stw, +1.f);
+        for (int t = threadIdx.x; t < pairs * nx; t += FFT_X_THREADS) {
             const int s = fdiv(t, inv_nx), e = t - s * nx;
             const int ra = row0 + 2 * s, rb = ra + 1;
             const float2 w = sm[t];
@@ -283,7 +289,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(const Inst *__restrict__ 
         sm[c * ny + y] = c < tk ? spec[(size_t)y * sp + kx0 + c] : make_float2(0.f, 0.f);
     }
     __syncthreads();
-    fft_lds<P2>(sm, ny, I.yrad, I.nyrad, TK, ny, stw, (float)dir);
+    fft_lds<P2, FFT_THREADS, FFT_MAXPTS>(sm, ny, I.yrad, I.nyrad, TK, ny, stw, (float)dir);
     for (int t = threadIdx.x; t < ny * TK; t += FFT_THREADS) {
         const int y = fdiv(t, inv_tk), c = t - y * TK;
         if (c < tk) spec[(size_t)y * sp + kx0 + c] = sm[c * ny + y];
@@ -329,8 +335,10 @@ __global__ void k_fft_tables(const Inst *__restrict__ insts, int inst) {
     }
 }
 
-template __global__ void k_fft_x<false>(const Inst *, const int *, int, int, const float *, float *);
-template __global__ void k_fft_x<true>(const Inst *, const int *, int, int, const float *, float *);
+template __global__ void k_fft_x<false, FFT_X_PTS>(const Inst *, const int *, int, int, const float *, float *);
+template __global__ void k_fft_x<true, FFT_X_PTS>(const Inst *, const int *, int, int, const float *, float *);
+template __global__ void k_fft_x<false, 4 * FFT_X_PTS>(const Inst *, const int *, int, int, const float *, float *);
+template __global__ void k_fft_x<true, 4 * FFT_X_PTS>(const Inst *, const int *, int, int, const float *, float *);
 template __global__ void k_fft_y<false>(const Inst *, const int *, int, int);
 template __global__ void k_fft_y<true>(const Inst *, const int *, int, int);
 

@@ -47,7 +47,7 @@ __global__ void k_mg_coarsest(const Inst *insts, int ninst, int cyc);
 __global__ void k_mg_finalize(const Inst *insts, int ninst, int count_step);
 __global__ void k_mu_mean_partial(const Inst *insts, const int *prefix, int ninst, int which);
 
-template <bool P2>
+template <bool P2, int XC>
 __global__ void k_fft_x(const Inst *insts, const int *prefix, int ninst, int dir, const float *in_ext,
                         float *out_ext);
 template <bool P2>
@@ -61,7 +61,9 @@ __host__ __device__ size_t fft_z_lds(int nz);
 constexpr int FFT_ZTK = 32;     // kx columns per work-group of the z solve
 constexpr int FFT_ZMAX = 256;   // largest nz of the spectral path
 constexpr int FFT_MAXN = 8192;  // points per work-group of the x and y passes
-constexpr int FFT_XY_THREADS = 1024;  // threads per work-group of the x and y passes
+constexpr int FFT_XY_THREADS = 1024;  // threads per work-group of the y passes
+constexpr int FFT_X_THREADS = 256;    // threads per work-group of the x passes
+constexpr int FFT_X_PTS = 1024;       // complex points per work-group of the x passes (target)
 
 __global__ void k_adj_save(const Inst *insts, float2 *dpsi, float *dmu, double *dK, int raw);
 __global__ void k_adj_load(const Inst *insts, const float2 *spsi, const float *smu, const double *sK);
