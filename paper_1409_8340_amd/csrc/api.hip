@@ -1653,9 +1653,10 @@ namespace {
 // Re-uploads what a change of stencil tiling touches: the instance
 // descriptors and the stencil prefix and partial-count tables.  The stream
 // must be idle.
-// Z planes per work-group of the two-sweep boundary kernel: short runs, so
-// that its few, latency-bound groups end well within the interior kernel.
-constexpr int kBoundaryChunk = 4;
+// Z planes per work-group of the two-sweep boundary kernel.  Measured at
+// 1024 x 1024 x 128 (boundary kernel alone before the interior one): 1, 2,
+// 4, 8, 16, 32 planes gave passes of 1057, 1007, 1001, 981, 1014, 1112 us.
+constexpr int kBoundaryChunk = 8;
 
 tdgl_status upload_tiling(tdgl_ctx *ctx) {
     const int n = ctx->n;
