@@ -80,7 +80,22 @@ typedef struct tdgl_params {
     int poisson;          /* 0: direct spectral solve where the box allows it
                              (periodic x and y, open z, sizes with factors 2,3,5),
                              multigrid otherwise; 1: always multigrid */
-    int reserved[5];      /* must be zero */
+    int reserved0;        /* must be zero */
+    double noise_T;       /* Langevin term of Eq. b (Sec. 3.1.2, noise terms):
+                             reduced temperature T-bar >= 0, 0 = off.  Every
+                             node and step draws zeta = zeta_1 + i zeta_2,
+                             both uniform on [-zeta_max, zeta_max] with
+                             zeta_max^2 = 3 T-bar u / (2 dt hx hy hz); b gains
+                             ht zeta.  The draws come from Philox4x32-10
+                             (Salmon et al., SC'11) with counter (m, n mod
+                             2^32, n / 2^32, 0) for node m = i + nx (j + ny k)
+                             and step counter n (the scalars' n before the
+                             step), key (seed mod 2^32, seed / 2^32); output
+                             words r0, r1 map to (2 (r >> 8) - (2^24 - 1))
+                             2^-24, exact in FP32.  A step therefore depends
+                             only on the state, the seed and n.            */
+    unsigned long long noise_seed; /* key of the noise generator            */
+    int reserved[2];      /* must be zero */
 } tdgl_params;
 
 /* Per-call statistics of tdgl_step (filled only when a pointer is given;

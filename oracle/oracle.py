@@ -347,6 +347,56 @@ def poisson_exact(grid: Grid, f: np.ndarray) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
+# Langevin noise (Sec. 3.1.2, "Noise terms"; Eq. b)
+# ---------------------------------------------------------------------------
+def philox4x32_10(c0, c1, c2, c3, k0, k1):
+    """Philox4x32-10 of Salmon, Moraes, Dror and Shaw (SC'11), elementwise over
+    numpy arrays: ten rounds; in each, the first and third counter words are
+    multiplied by 0xD2511F53 and 0xCD9E8D57 into 64 bits, the new words are
+    (hi(c2 M1) ^ c1 ^ k0, lo(c2 M1), hi(c0 M0) ^ c3 ^ k1, lo(c0 M0)), and the
+    key is advanced by (0x9E3779B9, 0xBB67AE85) before every round but the
+    first.  Returns the four output words as uint64 arrays below 2^32."""
+    mask = np.uint64(0xFFFFFFFF)
+    c = [np.asarray(x, dtype=np.uint64) & mask for x in (c0, c1, c2, c3)]
+    k0 = np.uint64(int(k0) & 0xFFFFFFFF)
+    k1 = np.uint64(int(k1) & 0xFFFFFFFF)
+    for r in range(10):
+        if r > 0:
+            k0 = (k0 + np.uint64(0x9E3779B9)) & mask
+            k1 = (k1 + np.uint64(0xBB67AE85)) & mask
+        p0 = c[0] * np.uint64(0xD2511F53)
+        p1 = c[2] * np.uint64(0xCD9E8D57)
+        c = [(p1 >> np.uint64(32)) ^ c[1] ^ k0, p1 & mask, (p0 >> np.uint64(32)) ^ c[3] ^ k1, p0 & mask]
+    return c
+
+
+def zeta_max(T: float, u: float, dt: float, hx: float, hy: float, hz: float) -> float:
+    """Amplitude of the uniform Langevin draws: zeta_max^2 = 3 T u /
+    (2 dt hx hy hz) (Sec. 3.1.2; dt is the reduced time step h_tbar)."""
+    return float(np.sqrt(3.0 * T * u / (2.0 * dt * hx * hy * hz)))
+
+
+def langevin_zeta(grid, T: float, u: float, dt: float, seed: int, n: int) -> np.ndarray:
+    """zeta_m(n) = zeta_1 + i zeta_2 at every node for step n: independent
+    uniform draws on [-zeta_max, zeta_max] (Sec. 3.1.2).
+
+    reading (generator): the paper names no generator; the draws come from
+    Philox4x32-10 with counter (m, n mod 2^32, n div 2^32, 0), m = i + nx (j +
+    ny k), key (seed mod 2^32, seed div 2^32), and output words r0, r1 mapped
+    to (2 (r >> 8) - (2^24 - 1)) 2^-24, an exact value in (-1, 1)."""
+    m = np.arange(grid.N, dtype=np.uint64)
+    n = int(n)
+    w = philox4x32_10(m, np.full_like(m, n & 0xFFFFFFFF), np.full_like(m, n >> 32), np.zeros_like(m),
+                      int(seed) & 0xFFFFFFFF, int(seed) >> 32)
+
+    def uni(r):
+        return (2.0 * (r >> np.uint64(8)).astype(np.float64) - (2.0 ** 24 - 1.0)) * 2.0 ** -24
+
+    zm = zeta_max(T, u, dt, grid.hx, grid.hy, grid.hz)
+    return (zm * (uni(w[0]) + 1j * uni(w[1]))).reshape(grid.shape)
+
+
+# ---------------------------------------------------------------------------
 # Time step
 # ---------------------------------------------------------------------------
 @dataclass
@@ -369,6 +419,8 @@ class Params:
     max_iter: int = 100
     mode: str = "mirror"
     driven: bool = False
+    noise_T: float = 0.0     # Langevin term (Sec. 3.1.2): reduced temperature, 0 = off
+    noise_seed: int = 0
 
 
 @dataclass
@@ -444,6 +496,9 @@ def step(grid: Grid, p: Params, eps: np.ndarray, st: State, in_window: bool = Tr
     links = with_K(base, grid.hx, st.K)
     mu = st.mu if p.driven else None
     b, d = assemble(grid, links, st.psi, eps, mu, p.u, ht)
+    if p.noise_T > 0:
+        # Eq. b: (ht/2) 2 zeta_m(t), drawn for the step counter before the step
+        b = b + ht * langevin_zeta(grid, p.noise_T, p.u, p.dt, p.noise_seed, st.n)
     psi, sweeps, r2 = gl_solve(grid, links, b, d, ht, st.psi, p.tol, p.max_iter, p.mode)
     st.psi = psi
     st.last_sweeps, st.last_res2 = sweeps, r2

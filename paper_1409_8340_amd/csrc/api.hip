@@ -278,6 +278,9 @@ tdgl_status validate(const tdgl_params &p, int idx) {
     if (p.tile_rows != 0 && p.tile_rows != 1 && p.tile_rows != 2 && p.tile_rows != 4)
         return fail(TDGL_EINVAL, "instance %d: tile_rows must be 0, 1, 2 or 4", idx);
     if (p.strict != 0 && p.strict != 1) return fail(TDGL_EINVAL, "instance %d: strict must be 0 or 1", idx);
+    if (!(p.noise_T >= 0 && std::isfinite(p.noise_T)))
+        return fail(TDGL_EINVAL, "instance %d: noise_T must be finite and >= 0", idx);
+    if (p.reserved0 != 0) return fail(TDGL_EINVAL, "instance %d: reserved fields must be zero", idx);
     for (size_t r = 0; r < sizeof(p.reserved) / sizeof(p.reserved[0]); ++r)
         if (p.reserved[r] != 0) return fail(TDGL_EINVAL, "instance %d: reserved fields must be zero", idx);
     return TDGL_OK;
@@ -465,6 +468,11 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
         d.ht2 = (float)(0.5 * p.dt / p.u);
         d.u = (float)p.u;
         d.tol = (float)p.tol;
+        // Langevin amplitude (Sec. 3.1.2): zeta_max^2 = 3 T u / (2 dt hx hy hz)
+        d.zeta_max = p.noise_T > 0 ? (float)std::sqrt(3.0 * p.noise_T * p.u / (2.0 * p.dt * p.hx * p.hy * p.hz))
+                                   : 0.f;
+        d.seed0 = (unsigned)(p.noise_seed & 0xffffffffull);
+        d.seed1 = (unsigned)(p.noise_seed >> 32);
         d.mu_tol = (float)p.mu_tol;
         d.hx = p.hx; d.hy = p.hy; d.hz = p.hz; d.dt = p.dt;
         {
@@ -1915,13 +1923,13 @@ size_t adj_layout(long N, int nsteps, int C, char *base, AdjLayout *L) {
     AdjLayout l;
     l.ck_psi = cv.take<float2>((size_t)ncp * N);
     l.ck_mu = cv.take<float>((size_t)ncp * N);
-    l.ck_K = cv.take<double>(2 * (size_t)ncp);
+    l.ck_K = cv.take<double>(3 * (size_t)ncp);  // K, mean of mu, step counter
     l.seg_psi = cv.take<float2>((size_t)(C + 1) * N);
     l.seg_mu = cv.take<float>((size_t)(C + 1) * N);
     l.seg_K = cv.take<double>(C + 1);
     l.fin_psi = cv.take<float2>(N);
     l.fin_mu = cv.take<float>(N);
-    l.fin_K = cv.take<double>(2);
+    l.fin_K = cv.take<double>(3);
     l.fin_st = cv.take<DevState>(1);
     l.psibar = cv.take<float2>(N);
     l.mubar = cv.take<float>(N);
@@ -2028,7 +2036,7 @@ tdgl_status tdgl_voltage_grad(tdgl_ctx *ctx, int nsteps, int window_begin, int c
         if (n % C == 0) {
             const int q = n / C;
             hipLaunchKernelGGL(k_adj_save, dim3(G), dim3(256), 0, s, ctx->d_inst, L.ck_psi + (size_t)q * N,
-                               L.ck_mu + (size_t)q * N, L.ck_K + 2 * q, 1);
+                               L.ck_mu + (size_t)q * N, L.ck_K + 3 * q, 1);
         }
         if (n == s0_last)
             hipLaunchKernelGGL(k_adj_save, dim3(G), dim3(256), 0, s, ctx->d_inst, L.seg_psi, L.seg_mu, L.seg_K, 0);
@@ -2050,7 +2058,7 @@ tdgl_status tdgl_voltage_grad(tdgl_ctx *ctx, int nsteps, int window_begin, int c
         const int s0 = q * C, s1 = std::min(s0 + C, nsteps);
         if (q != ncp - 1) {
             hipLaunchKernelGGL(k_adj_load, dim3(G), dim3(256), 0, s, ctx->d_inst, L.ck_psi + (size_t)q * N,
-                               L.ck_mu + (size_t)q * N, L.ck_K + 2 * q);
+                               L.ck_mu + (size_t)q * N, L.ck_K + 3 * q);
             hipLaunchKernelGGL(k_links, dim3(1), dim3(256), 0, s, ctx->d_inst, 1);
             hipLaunchKernelGGL(k_adj_save, dim3(G), dim3(256), 0, s, ctx->d_inst, L.seg_psi, L.seg_mu, L.seg_K,
                                0);

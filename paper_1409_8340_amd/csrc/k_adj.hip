@@ -42,8 +42,8 @@ __device__ __forceinline__ float node_wm(const Inst &I, int m) {
     for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < I.N; m += gridDim.x * blockDim.x)
 
 // State save / restore.  raw = 1 (checkpoints): psi, mu as stored and
-// dK[0] = K, dK[1] = weighted mean of mu, so that a restored step replays
-// bit for bit.  raw = 0 (states the reverse sweep reads): mu with its
+// dK[0] = K, dK[1] = weighted mean of mu, dK[2] = step counter (it keys the
+// Langevin draws), so that a restored step replays bit for bit.  raw = 0 (states the reverse sweep reads): mu with its
 // weighted mean removed, as the step uses it, and dK[0] = K.
 __global__ void k_adj_save(const Inst *__restrict__ insts, float2 *dpsi, float *dmu, double *dK, int raw) {
     const Inst &I = insts[0];
@@ -55,7 +55,10 @@ __global__ void k_adj_save(const Inst *__restrict__ insts, float2 *dpsi, float *
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         dK[0] = I.st->K;
-        if (raw) dK[1] = I.st->mu_mean;
+        if (raw) {
+            dK[1] = I.st->mu_mean;
+            dK[2] = I.st->n;  // the step counter keys the Langevin draws of the replay
+        }
     }
 }
 
@@ -71,6 +74,7 @@ __global__ void k_adj_load(const Inst *__restrict__ insts, const float2 *spsi, c
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         I.st->K = sK[0];
         I.st->mu_mean = sK[1];
+        I.st->n = sK[2];
     }
 }
 

@@ -114,16 +114,23 @@ __global__ __launch_bounds__(256) void k_jav_partial(const Inst *__restrict__ in
     const int lb = b - prefix[ii];
     const float2 *__restrict__ psi = I.psi[I.st->cur];
     double acc = 0.0;
-    const long base = (long)lb * 256 * JAV_CPT;
+    const int nx = I.nx, ny = I.ny;
+    // cell m = base + c 256 + tid: its x index i and y index j follow from
+    // one division for c = 0 and then by stepping 256 cells at a time
+    int m = (int)((long)lb * 256 * JAV_CPT) + (int)threadIdx.x;
+    int i = m % nx, j = (m / nx) % ny;
     for (int c = 0; c < JAV_CPT; ++c) {
-        const int m = (int)base + c * 256 + (int)threadIdx.x;
         if (m < I.N) {
-            const int i = m % I.nx;
-            const int j = (m / I.nx) % I.ny;
-            const int mp = (i == I.nx - 1) ? m - (I.nx - 1) : m + 1;
+            const int mp = (i == nx - 1) ? m - (nx - 1) : m + 1;
             const float2 a = psi[m], p = psi[mp];
             const float2 up = cmul(I.ux[j], p);
             acc += (double)(a.x * up.y - a.y * up.x);
+        }
+        m += 256;
+        i += 256;
+        while (i >= nx) {
+            i -= nx;
+            if (++j == ny) j = 0;
         }
     }
     const double s = wg_sum<256>(acc, red);

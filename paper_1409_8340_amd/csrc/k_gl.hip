@@ -168,6 +168,9 @@ __device__ __forceinline__ void stencil_tile(const Inst *__restrict__ insts, con
 
     const float ht2 = I.ht2, S2 = I.S2, u = I.u;
     const bool zper = I.per[2] != 0;
+    // Langevin draws of this step (assemble only): step counter before the step
+    const bool noise = (MODE == MODE_FIRST) && I.zeta_max > 0.f;
+    const unsigned long long nstep = noise ? (unsigned long long)st->n : 0ull;
     float rmax = 0.f;
     double acc = 0.0;
 
@@ -231,7 +234,8 @@ __device__ __forceinline__ void stencil_tile(const Inst *__restrict__ insts, con
             if (MODE == MODE_FIRST) {
                 float2 bhv, dhv;
                 float r2;
-                assemble_node(c, ep[r], u * mu[r], ns, S2, ht2, bhv, dhv, nw, r2);
+                const float2 zz = noise ? langevin2(I, m, nstep) : make_float2(0.f, 0.f);
+                assemble_node(c, ep[r], u * mu[r], ns, S2, ht2, noise, zz, bhv, dhv, nw, r2);
                 if (NT) {
                     st2nt(bhw, m, bhv);
                     st2nt(dhw, m, dhv);

@@ -209,19 +209,21 @@ __device__ __forceinline__ float resid2(float2 nw, float2 old, float2 dh, float 
 }
 
 // Assemble at one node (Eq. GL_linearized, Eq. b, with |psi|^2 lagged):
-//   b   = psi^- + ht/2 [ (eps - i u mu) psi^- - |psi^-|^2 psi^- + L psi^- ]
+//   b   = psi^- + ht/2 [ (eps - i u mu) psi^- - |psi^-|^2 psi^- + L psi^- + 2 zeta ]
 //   M   = 1 + ht/2 [ |psi^-|^2 + 2S + i u mu - eps ]
 // returns b/M, (ht/2)/M, the first iterate b/M + (ht/2)/M NS(psi^-) and
 // |r|^2 of psi^(0) = psi^-.  Contraction-proof like jacobi(), so that every
 // tiling of the grid gives the same bits.
 __device__ __forceinline__ void assemble_node(float2 c, float e, float um, float2 ns, float S2, float ht2,
-                                              float2 &bhv, float2 &dhv, float2 &nw, float &r2) {
+                                              bool noise, float2 zz, float2 &bhv, float2 &dhv, float2 &nw,
+                                              float &r2) {
 #pragma clang fp contract(off)
     const float a2 = __builtin_fmaf(c.x, c.x, c.y * c.y);
     const float2 lap = make_float2(__builtin_fmaf(-S2, c.x, ns.x), __builtin_fmaf(-S2, c.y, ns.y));
     const float ea = e - a2;
-    const float2 st = make_float2(__builtin_fmaf(ea, c.x, __builtin_fmaf(um, c.y, lap.x)),
-                                  __builtin_fmaf(ea, c.y, __builtin_fmaf(-um, c.x, lap.y)));
+    float2 st = make_float2(__builtin_fmaf(ea, c.x, __builtin_fmaf(um, c.y, lap.x)),
+                            __builtin_fmaf(ea, c.y, __builtin_fmaf(-um, c.x, lap.y)));
+    if (noise) st = make_float2(st.x + zz.x, st.y + zz.y);  // + 2 zeta (Eq. b)
     const float2 bb = make_float2(__builtin_fmaf(ht2, st.x, c.x), __builtin_fmaf(ht2, st.y, c.y));
     const float2 M = make_float2(__builtin_fmaf(ht2, (a2 + S2) - e, 1.f), ht2 * um);
     const float m2 = __builtin_fmaf(M.x, M.x, M.y * M.y);

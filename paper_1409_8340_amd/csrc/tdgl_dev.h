@@ -95,6 +95,8 @@ struct Inst {
     float ht2;           // ht / 2 with ht = dt / u
     float u;
     float tol;           // Jacobi stop threshold on max |r|^2
+    float zeta_max;      // Langevin amplitude (0: no noise)
+    unsigned seed0, seed1;  // key of the noise generator
     float mu_tol;
     double hx, hy, hz, dt;
     double w_sum;        // sum of node weights (1/2 per open face)
@@ -222,6 +224,39 @@ __device__ __forceinline__ float row_max_wave(const unsigned *base, int rstride,
         m = v > m ? v : m;
     }
     return __uint_as_float(m);
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds, each
+// two 32 x 32 -> 64-bit products of counter words with fixed multipliers,
+// the high halves mixed with the other two words and the key, the key
+// advanced by two Weyl constants between rounds.
+__device__ __forceinline__ void philox4x32_10(unsigned c[4], unsigned k0, unsigned k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const unsigned lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+        const unsigned lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        const unsigned n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+// 2 zeta_m of step n (the Langevin term of Eq. b enters as (ht/2) 2 zeta):
+// the first two words of Philox4x32-10 at counter (m, n lo, n hi, 0) under
+// the instance's key, each mapped to (2 (r >> 8) - (2^24 - 1)) 2^-24, an
+// exact FP32 value in (-1, 1), times 2 zeta_max (the doubling is exact).
+__device__ __forceinline__ float2 langevin2(const Inst &I, unsigned m, unsigned long long n) {
+    unsigned c[4] = {m, (unsigned)n, (unsigned)(n >> 32), 0u};
+    philox4x32_10(c, I.seed0, I.seed1);
+    const float s = 2.f * I.zeta_max;
+    const float a = (float)(2 * (int)(c[0] >> 8) - 16777215) * 0x1p-24f;
+    const float b = (float)(2 * (int)(c[1] >> 8) - 16777215) * 0x1p-24f;
+    return make_float2(s * a, s * b);
 }
 
 // Convergence value v of one (row, instance) handed to the host: one

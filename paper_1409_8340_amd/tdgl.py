@@ -35,7 +35,8 @@ class Params(ctypes.Structure):
                 ("driven", ctypes.c_int), ("mu_tol", ctypes.c_double), ("mu_rtol", ctypes.c_double),
                 ("mu_max_cycles", ctypes.c_int), ("strict", ctypes.c_int),
                 ("tile_cz", ctypes.c_int), ("tile_rows", ctypes.c_int), ("poisson", ctypes.c_int),
-                ("reserved", ctypes.c_int * 5)]
+                ("reserved0", ctypes.c_int), ("noise_T", ctypes.c_double), ("noise_seed", ctypes.c_ulonglong),
+                ("reserved", ctypes.c_int * 2)]
 
 
 class StepStats(ctypes.Structure):
@@ -162,7 +163,7 @@ def _check(status):
 def make_params(nx, ny, nz, h=0.5, hx=None, hy=None, hz=None, bc=(TDGL_PERIODIC, TDGL_PERIODIC, TDGL_OPEN),
                 g=1.0, u=1.0, dt=0.1, tol=1e-8, max_iter=100, driven=False, mu_tol=1e-5,
                 mu_rtol=0.0, mu_max_cycles=20, strict=False, tile_cz=0, tile_rows=0,
-                poisson=0) -> Params:
+                poisson=0, noise_T=0.0, noise_seed=0) -> Params:
     p = Params()
     p.nx, p.ny, p.nz = nx, ny, nz
     p.hx = h if hx is None else hx
@@ -180,6 +181,8 @@ def make_params(nx, ny, nz, h=0.5, hx=None, hy=None, hz=None, bc=(TDGL_PERIODIC,
     p.tile_cz = tile_cz
     p.tile_rows = tile_rows
     p.poisson = poisson
+    p.noise_T = noise_T
+    p.noise_seed = noise_seed
     return p
 
 

@@ -27,14 +27,16 @@ class Case:
     def __init__(self, nx, ny, nz, h=0.5, open_=(False, False, True), g=1.0, Bx=0.0, Bz=0.1,
                  J=0.0, driven=False, tol=1e-12, max_iter=200, mu_tol=1e-6, mu_max_cycles=40,
                  psi_seed=11, eps=None, mu0=None, K0=0.0, dt=0.1, u=1.0, hx=None, hy=None,
-                 hz=None, tile_cz=0):
+                 hz=None, tile_cz=0, noise_T=0.0, noise_seed=0):
         self.grid = O.Grid(nx, ny, nz, hx or h, hy or h, hz or h, tuple(open_), g)
         self.Bx, self.Bz = O.quantize_field(self.grid, Bx, Bz)
         self.J = J
         self.driven = driven
         self.params = tdgl.make_params(nx, ny, nz, h=h, hx=hx, hy=hy, hz=hz, bc=bc_codes(open_), g=g,
                                        u=u, dt=dt, tol=tol, max_iter=max_iter, driven=driven,
-                                       mu_tol=mu_tol, mu_max_cycles=mu_max_cycles, tile_cz=tile_cz)
+                                       mu_tol=mu_tol, mu_max_cycles=mu_max_cycles, tile_cz=tile_cz,
+                                       noise_T=noise_T, noise_seed=noise_seed)
+        self.noise_T, self.noise_seed = noise_T, noise_seed
         self.psi0 = inputs.psi_init(nx, ny, nz, psi_seed)
         self.eps = (np.ones(self.grid.shape, np.float32) if eps is None
                     else np.asarray(eps, np.float32).reshape(self.grid.shape))
@@ -46,7 +48,7 @@ class Case:
     def oracle_params(self, mode="exact", tol=None):
         return O.Params(Bx=self.Bx, Bz=self.Bz, J_ext=self.J, u=self.u, dt=self.dt,
                         tol=self.params.tol if tol is None else tol, max_iter=self.params.max_iter,
-                        mode=mode, driven=self.driven)
+                        mode=mode, driven=self.driven, noise_T=self.noise_T, noise_seed=self.noise_seed)
 
     def oracle_state(self):
         st = O.new_state(self.grid, self.psi0.astype(np.complex128))

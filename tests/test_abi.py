@@ -51,6 +51,9 @@ def test_plan_sizes_grow_with_grid(lib):
     (dict(tile_rows=3), "tile_rows"),
     (dict(tile_rows=1), None),
     (dict(tile_cz=-1), "tile_cz"),
+    (dict(noise_T=-0.1), "noise_T"),
+    (dict(noise_T=float("nan")), "noise_T"),
+    (dict(noise_T=0.5, noise_seed=2**64 - 1), None),
 ])
 def test_plan_validation(lib, kw, msg):
     base = dict(nx=32, ny=32, nz=16)
@@ -74,10 +77,14 @@ def test_plan_rejects_uncoarsenable_poisson_grid(lib):
 
 
 def test_reserved_fields_must_be_zero(lib):
-    p = tdgl.make_params(8, 8, 8)
-    p.reserved[3] = 1
-    with pytest.raises(tdgl.TdglError):
-        tdgl.plan([p])
+    for field in ("reserved0", "reserved"):
+        p = tdgl.make_params(8, 8, 8)
+        if field == "reserved0":
+            p.reserved0 = 1
+        else:
+            p.reserved[1] = 1
+        with pytest.raises(tdgl.TdglError):
+            tdgl.plan([p])
 
 
 def test_create_rejects_bad_workspace_without_device(lib):

@@ -489,3 +489,62 @@ def test_inclusion_generator_statistics():
     assert 0.10 <= frac1 < 0.10 + (np.pi / 6 * 64) / grid.N
     assert used1 > 10 and used1 < len(dia)
     assert set(np.unique(eps1)) == {-1.0, 1.0}
+
+
+# ---------------------------------------------------------------------------
+# Langevin noise (Sec. 3.1.2, "Noise terms"; Eq. b)
+# ---------------------------------------------------------------------------
+def test_philox_known_answers():
+    """The oracle's Philox4x32-10 reproduces the generator authors' known-answer
+    vectors (tests/golden/philox4x32_10_kat.json)."""
+    kat = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.json")))
+    for v in kat["vectors"]:
+        c = [np.array([int(x, 16)], dtype=np.uint64) for x in v["counter"]]
+        k = [int(x, 16) for x in v["key"]]
+        out = O.philox4x32_10(*c, *k)
+        assert [f"{int(w[0]):08x}" for w in out] == v["out"]
+
+
+def test_langevin_moments_match_the_paper():
+    """zeta_1, zeta_2 uniform on [-zeta_max, zeta_max]: mean 0, <zeta_1^2 +
+    zeta_2^2> = (2/3) zeta_max^2 (the paper's correlator), no correlation
+    between the two parts, between neighbouring nodes or between steps, and
+    the amplitude law zeta_max^2 = 3 T u / (2 dt hx hy hz)."""
+    grid = O.Grid(64, 64, 32, 0.5, 0.5, 0.5)
+    T, u, dt, seed = 0.7, 1.3, 0.05, 987654321123
+    zm = O.zeta_max(T, u, dt, 0.5, 0.5, 0.5)
+    assert abs(zm ** 2 - 3 * T * u / (2 * dt * 0.125)) <= 1e-12 * zm ** 2
+    z0 = O.langevin_zeta(grid, T, u, dt, seed, 41).ravel()
+    z1 = O.langevin_zeta(grid, T, u, dt, seed, 42).ravel()
+    n = z0.size
+    s = 1.0 / np.sqrt(n)
+    assert np.max(np.abs(z0.real)) <= zm and np.max(np.abs(z0.imag)) <= zm
+    assert abs(np.mean(z0.real)) / zm <= 5 * s and abs(np.mean(z0.imag)) / zm <= 5 * s
+    m2 = np.mean(np.abs(z0) ** 2) / ((2.0 / 3.0) * zm ** 2)
+    assert abs(m2 - 1.0) <= 5 * s * 1.2          # std of |zeta|^2 / mean is about 0.63
+    def corr(a, b):
+        return float(np.mean(a * b) / np.sqrt(np.mean(a * a) * np.mean(b * b)))
+    assert abs(corr(z0.real, z0.imag)) <= 5 * s
+    assert abs(corr(z0.real, np.roll(z0.real, 1))) <= 5 * s
+    assert abs(corr(z0.real, z1.real)) <= 5 * s
+    # a different seed gives different draws; the same (seed, n) the same ones
+    assert not np.array_equal(z0, O.langevin_zeta(grid, T, u, dt, seed + 1, 41).ravel())
+    assert np.array_equal(z0, O.langevin_zeta(grid, T, u, dt, seed, 41).ravel())
+
+
+def test_langevin_diffusion_law():
+    """With eps = 0 and a Laplacian too weak to matter (h = 1e3), psi only
+    collects the noise: psi_n = psi_{n-1} + ht zeta, so from psi = 0 the mean
+    |psi|^2 after n steps is T t / (u hx hy hz), t = n dt -- the discrete
+    correlator the paper equates with the continuum one to fix zeta_max."""
+    h = 1e3
+    grid = O.Grid(24, 24, 24, h, h, h, (False, False, True))
+    T, u, dt = 1.0, 1.0, 0.1
+    p = O.Params(Bz=0.0, u=u, dt=dt, tol=1e-40, max_iter=50, mode="mirror", noise_T=T, noise_seed=2024)
+    st = O.new_state(grid, np.zeros(grid.shape, np.complex128))
+    nsteps = 40
+    O.run(grid, p, np.zeros(grid.shape), st, nsteps)
+    want = T * nsteps * dt / (u * h ** 3)
+    got = float(np.mean(np.abs(st.psi) ** 2))
+    print("diffusion <|psi|^2>", got, "expected", want)
+    assert abs(got / want - 1.0) <= 5.0 / np.sqrt(grid.N)
