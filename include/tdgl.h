@@ -193,11 +193,47 @@ tdgl_status tdgl_set_eps(tdgl_ctx *ctx, int inst, const float *eps);
  * (any periodic image; open axes clipped; |r_m - c|^2 <= (d/2)^2 evaluated
  * in double precision without fused multiply-add) get eps_in, all others
  * eps_out.  Reports the number of spheres used and the covered fraction.
- * Synchronising.  Uses the instance's scalar-potential arrays as scratch,
- * so call it before stepping. */
+ * Synchronising.  Uses the instance's b/M array (rebuilt by every step) as
+ * scratch. */
 tdgl_status tdgl_gen_inclusions(tdgl_ctx *ctx, int inst, const double *centres,
                                 const double *diameters, int nc, double target,
                                 float eps_in, float eps_out, int *n_used, double *fraction);
+
+/* Inclusion generator for general convex candidates (Sec. 3.4; the
+ * ellipsoids and tilted columns of Fig. 2d/e): as tdgl_gen_inclusions, with
+ * candidate s given by 16 doubles of `shapes` (device memory, double[16*nc]):
+ *     c[3] | Q_xx Q_yy Q_zz Q_xy Q_xz Q_yz | n[3] | hlen | ext[3].
+ * A node image u (integer coordinates, d = u h - c) is inside iff
+ *     q = (((Qxx dx) dx + (Qyy dy) dy) + (Qzz dz) dz)
+ *         + 2 (((Qxy dx) dy + (Qxz dx) dz) + (Qyz dy) dz) <= 1
+ * and, when hlen >= 0, |(nx dx + ny dy) + nz dz| <= hlen, all in double
+ * precision without fused multiply-add.  A sphere of radius r is Q = I/r^2,
+ * an ellipsoid Q = R diag(a^-2, b^-2, c^-2) R^T, a column of radius rho
+ * along the unit vector n Q = (I - n n^T)/rho^2 with hlen its half length.
+ * ext: half-widths of an axis-aligned box around c that holds the shape;
+ * only images in that box (one node margin) are tested, clipped on open
+ * axes and kept within one period of the centre on periodic ones.  A
+ * candidate with a non-finite entry or a negative ext covers nothing.
+ * Synchronising; uses the b/M array (rebuilt by every step) as scratch. */
+tdgl_status tdgl_gen_shapes(tdgl_ctx *ctx, int inst, const double *shapes, int nc, double target,
+                            float eps_in, float eps_out, int *n_used, double *fraction);
+
+/* Tessellation pattern (Sec. 3.4; the Voronoi polycrystal of Fig. 2c):
+ * every node takes values[s] (float[ns], device memory) of its nearest seed
+ * s (seeds: double[3*ns] xyz positions, device memory).  The per-axis
+ * separation of node x = i h from seed c is |x - c| on an open axis and
+ * min(|d|, |d - L|, |d + L|), d = x - c, on a periodic axis of length
+ * L = n h (the nearest image for seeds inside the box); an axis whose bit
+ * (1 x, 2 y, 4 z) is not in `axes` contributes 0, e.g. axes = 3 for
+ * columnar crystallites.  metric 0: Euclidean, (dx^2 + dy^2) + dz^2;
+ * 1: absolute, (dx + dy) + dz; 2: maximum, max(max(dx, dy), dz); double
+ * precision without fused multiply-add.  Equal distances go to the lowest
+ * seed index; seeds with a non-finite coordinate are skipped; ns = 0 leaves
+ * eps as it is.  Combine with other patterns through tdgl_get_eps /
+ * tdgl_set_eps.  Cost O(N ns).  Synchronising.  TDGL_EINVAL for ns < 0,
+ * null arrays, metric outside 0..2 or axes outside 1..7. */
+tdgl_status tdgl_gen_voronoi(tdgl_ctx *ctx, int inst, const double *seeds, const float *values, int ns,
+                             int metric, int axes);
 
 /* Copies the instance's eps (float[N]) out, e.g. after tdgl_gen_inclusions. */
 tdgl_status tdgl_get_eps(tdgl_ctx *ctx, int inst, float *eps);

@@ -540,6 +540,134 @@ def mean_E(st: State) -> float:
 # ---------------------------------------------------------------------------
 # Inclusion generator (Sec. 3.4)
 # ---------------------------------------------------------------------------
+def gen_voronoi(grid: Grid, seeds: np.ndarray, values: np.ndarray, metric: int = 0, axes: int = 7,
+                eps: np.ndarray = None):
+    """Tessellation pattern (Sec. 3.4, the Voronoi polycrystal of Fig. 2c):
+    each node takes the value of its nearest seed.
+
+    reading: the distance is the standard Euclidean one (metric 0) or one of
+    the extensions the paper names, absolute (1) and maximum (2).  Per axis
+    the separation of x = i h from the seed coordinate c is |x - c| on an
+    open axis and the smallest of |d|, |d - L|, |d + L| (d = x - c, L = n h)
+    on a periodic one; axes outside the bit mask `axes` contribute 0.
+    Metric 0 compares (dx^2 + dy^2) + dz^2, metric 1 (dx + dy) + dz,
+    metric 2 max(max(dx, dy), dz), in double precision without fused
+    multiply-add.  Seeds are visited in index order and only a strictly
+    smaller distance replaces the nearest so far (ties go to the lowest
+    index).  Seeds with a non-finite coordinate are skipped; nodes with no
+    finite distance keep `eps` (default all ones).  Returns (eps, owner),
+    owner = -1 where no seed was taken.
+    """
+    nz, ny, nx = grid.shape
+    seeds = np.asarray(seeds, dtype=np.float64).reshape(-1, 3)
+    values = np.asarray(values, dtype=np.float64).reshape(-1)
+    out = np.ones(grid.shape) if eps is None else np.array(eps, dtype=np.float64)
+    best = np.full(grid.shape, np.inf)
+    owner = np.full(grid.shape, -1, dtype=np.int64)
+    ns = (nx, ny, nz)
+    hs = (grid.hx, grid.hy, grid.hz)
+    coord = [np.arange(ns[a], dtype=np.float64) * hs[a] for a in range(3)]
+    shape_of = [(1, 1, nx), (1, ny, 1), (nz, 1, 1)]
+    for s in range(seeds.shape[0]):
+        if not np.all(np.isfinite(seeds[s])):
+            continue
+        sep = []
+        for a in range(3):
+            if not (axes >> a) & 1:
+                sep.append(np.zeros(shape_of[a]))
+                continue
+            d = coord[a] - seeds[s, a]
+            sa = np.abs(d)
+            if not grid.open_[a]:
+                L = ns[a] * hs[a]
+                sa = np.minimum(sa, np.minimum(np.abs(d - L), np.abs(d + L)))
+            sep.append(sa.reshape(shape_of[a]))
+        dx, dy, dz = sep
+        if metric == 0:
+            dist = (dx * dx + dy * dy) + dz * dz
+        elif metric == 1:
+            dist = (dx + dy) + dz
+        else:
+            dist = np.maximum(np.maximum(dx, dy), dz)
+        closer = dist < best
+        best = np.where(closer, dist, best)
+        owner = np.where(closer, s, owner)
+    taken = owner >= 0
+    out[taken] = values[owner[taken]]
+    return out, owner
+
+
+# A candidate whose box reaches farther than 2^50 node spacings from the
+# origin (or holds a non-finite number) covers nothing.
+INCL_REACH = 2.0 ** 50
+
+
+def gen_shapes(grid: Grid, shapes: np.ndarray, target: float, eps_in: float = -1.0, eps_out: float = 1.0):
+    """Inclusions of general convex shape (Sec. 3.4; the ellipsoids and
+    tilted columns of Fig. 2d/e), added in order until the covered node
+    count reaches target * N, as for spheres.
+
+    reading: candidate s is (c, Q, n, hlen, ext) (16 doubles); a node image
+    u is inside iff, with d = u h - c,
+        q = (((Qxx dx) dx + (Qyy dy) dy) + (Qzz dz) dz)
+            + 2 (((Qxy dx) dy + (Qxz dx) dz) + (Qyz dy) dz) <= 1
+    and, when hlen >= 0, |(nx dx + ny dy) + nz dz| <= hlen, in double
+    precision without fused multiply-add.  The images tested are those of
+    the box c +- ext with a one-node margin, clipped on open axes and kept
+    within one period of the centre on periodic axes.  Returns (eps,
+    shapes_used, covered_fraction).
+    """
+    nz, ny, nx = grid.shape
+    N = grid.N
+    covered = np.zeros(grid.shape, dtype=bool)
+    count = 0
+    used = 0
+    ns = (nx, ny, nz)
+    hs = (grid.hx, grid.hy, grid.hz)
+    need = target * float(N)
+    shapes = np.asarray(shapes, dtype=np.float64).reshape(-1, 16)
+    if need > 0:
+        for s in range(shapes.shape[0]):
+            sh = shapes[s]
+            used = s + 1
+            if not (np.all(np.abs(sh) < 1e30) and np.all(sh[13:16] >= 0)
+                    and np.all(np.abs(sh[0:3]) + sh[13:16] <= INCL_REACH * np.asarray(hs))):
+                continue
+            idx, off = [], []
+            for a in range(3):
+                c, e = sh[a], sh[13 + a]
+                lo = int(np.floor((c - e) / hs[a])) - 1
+                hi = int(np.ceil((c + e) / hs[a])) + 1
+                if grid.open_[a]:
+                    lo, hi = max(lo, 0), min(hi, ns[a] - 1)
+                else:
+                    cc = int(np.floor(c / hs[a]))
+                    lo, hi = max(lo, cc - ns[a] - 1), min(hi, cc + ns[a] + 1)
+                uu = np.arange(lo, hi + 1, dtype=np.int64)
+                idx.append(np.mod(uu, ns[a]))
+                off.append(uu.astype(np.float64) * hs[a] - c)
+            if all(len(x) for x in idx):
+                dx = off[0][None, None, :]
+                dy = off[1][None, :, None]
+                dz = off[2][:, None, None]
+                qxx, qyy, qzz, qxy, qxz, qyz = sh[3:9]
+                q = (((qxx * dx) * dx + (qyy * dy) * dy) + (qzz * dz) * dz) + \
+                    2.0 * (((qxy * dx) * dy + (qxz * dx) * dz) + (qyz * dy) * dz)
+                inside = q <= 1.0
+                if sh[12] >= 0:
+                    inside &= np.abs((sh[9] * dx + sh[10] * dy) + sh[11] * dz) <= sh[12]
+                kk, jj, ii = np.nonzero(inside)
+                K_, J_, I_ = idx[2][kk], idx[1][jj], idx[0][ii]
+                newly = ~covered[K_, J_, I_]
+                sel = np.unique(np.stack([K_[newly], J_[newly], I_[newly]]), axis=1)
+                covered[sel[0], sel[1], sel[2]] = True
+                count += sel.shape[1]
+            if count >= need:
+                break
+    eps = np.where(covered, eps_in, eps_out).astype(np.float64)
+    return eps, used, count / N
+
+
 def gen_inclusions(grid: Grid, centers: np.ndarray, diameters: np.ndarray,
                    target: float, eps_in: float = -1.0, eps_out: float = 1.0):
     """Random spherical inclusions modulating eps (Sec. 3.4, item (i); random
@@ -566,10 +694,16 @@ def gen_inclusions(grid: Grid, centers: np.ndarray, diameters: np.ndarray,
             c = centers[s]
             r = 0.5 * float(diameters[s])
             r2 = r * r
+            used = s + 1
+            if not (r >= 0.0 and r < 1e30):
+                continue
             rng_idx = []
             rng_off = []
             ok = True
             for a in range(3):
+                if not abs(c[a]) + r <= INCL_REACH * hs[a]:
+                    ok = False
+                    break
                 lo = int(np.floor((c[a] - r) / hs[a])) - 1
                 hi = int(np.ceil((c[a] + r) / hs[a])) + 1
                 uu = np.arange(lo, hi + 1, dtype=np.int64)

@@ -394,6 +394,7 @@ struct tdgl_ctx {
     size_t fx_lds = 0, fy_lds = 0, fz_lds = 0;
     bool fx_p2 = true, fy_p2 = true;  // every spectral instance has power-of-two nx (ny)
     bool fx_long = false;             // some spectral instance has nx > FFT_X_PTS
+    bool noisy = false;               // some instance has a Langevin term
     bool any_fft = false, any_mg = false;
     bool any_driven = false;
     int max_iter = 1, max_cycles = 1;
@@ -656,6 +657,7 @@ tdgl_status upload_tables(tdgl_ctx *ctx) {
         pfx[i + 1] = pfx[i] + h.fx_blocks;
         pfy[i + 1] = pfy[i] + h.fy_blocks;
         pfz[i + 1] = pfz[i] + h.fz_blocks;
+        ctx->noisy = ctx->noisy || h.d.zeta_max > 0.f;
         if (h.d.fft) {
             ctx->any_fft = true;
             ctx->fx_lds = std::max(ctx->fx_lds, (size_t)(fft_x_pairs(h.p.nx) + 1) * h.p.nx * 8);
@@ -746,7 +748,7 @@ struct ProfScope {
 // (rows per thread; streaming hints for the sweep and assemble passes).
 template <int MODE, int R>
 void launch_stencil_r(tdgl_ctx *c, int l, const float2 *in, float2 *out) {
-    constexpr bool can_nt = (MODE == MODE_SWEEP || MODE == MODE_FIRST);
+    constexpr bool can_nt = (MODE == MODE_SWEEP || is_first_mode(MODE));
     unsigned long long *pub = (MODE == MODE_SWEEP && c->pub_on && l > 0) ? c->d_pub : nullptr;
     if (can_nt && c->nt)
         hipLaunchKernelGGL((k_stencil<MODE, R, can_nt>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst,
@@ -820,6 +822,13 @@ void launch_stencil(tdgl_ctx *c, int l, const float2 *in = nullptr, float2 *out 
     if (c->rows == 1) launch_stencil_r<MODE, 1>(c, l, in, out);
     else if (c->rows == 2) launch_stencil_r<MODE, 2>(c, l, in, out);
     else launch_stencil_r<MODE, 4>(c, l, in, out);
+}
+// The assemble pass, with the Langevin draws where some instance has them.
+void launch_assemble(tdgl_ctx *c) {
+    if (c->noisy)
+        launch_stencil<MODE_FIRSTN>(c, 0);
+    else
+        launch_stencil<MODE_FIRST>(c, 0);
 }
 
 // One multigrid V-cycle for every driven instance (cycle index cyc).
@@ -1148,7 +1157,7 @@ void drop_graph(tdgl_ctx *ctx) {
 tdgl_status enqueue_step_fixed(tdgl_ctx *ctx, int budget) {
     const int n = ctx->n;
     hipStream_t s = ctx->stream;
-    launch_stencil<MODE_FIRST>(ctx, 0);
+    launch_assemble(ctx);
     if (ctx->fused)
         for (int l = 1; l < budget; l += 2) launch_sweep2(ctx, l);
     else
@@ -1412,6 +1421,54 @@ tdgl_status tdgl_gen_inclusions(tdgl_ctx *ctx, int inst, const double *centres, 
     return TDGL_OK;
 }
 
+tdgl_status tdgl_gen_voronoi(tdgl_ctx *ctx, int inst, const double *seeds, const float *values, int ns,
+                             int metric, int axes) {
+    tdgl_status s = check_ctx(ctx, inst);
+    if (s) return s;
+    const Inst &d = ctx->inst[inst].d;
+    if (ns < 0) return fail(TDGL_EINVAL, "seed count must be >= 0");
+    if (ns > 0 && (!seeds || !values)) return fail(TDGL_EINVAL, "null seed or value array");
+    if (metric < 0 || metric > 2) return fail(TDGL_EINVAL, "metric must be 0 (Euclidean), 1 (absolute) or 2 (maximum)");
+    if (axes < 1 || axes > 7) return fail(TDGL_EINVAL, "axes must be a non-empty mask of bits 1 (x), 2 (y), 4 (z)");
+    if (ns == 0) return TDGL_OK;
+    hipStream_t st = ctx->stream;
+    hipLaunchKernelGGL(k_voronoi, dim3((unsigned)((d.N + 255) / 256)), dim3(256), 0, st, ctx->d_inst, inst, seeds,
+                       values, ns, metric, axes);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(st));
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_gen_shapes(tdgl_ctx *ctx, int inst, const double *shapes, int nc, double target, float eps_in,
+                            float eps_out, int *n_used, double *fraction) {
+    tdgl_status s = check_ctx(ctx, inst);
+    if (s) return s;
+    const Inst &d = ctx->inst[inst].d;
+    if (nc < 0 || nc > d.N) return fail(TDGL_EINVAL, "candidate count must be in [0, N]");
+    if (nc > 0 && !shapes) return fail(TDGL_EINVAL, "null shape array");
+    if (!(target >= 0.0 && target <= 1.0)) return fail(TDGL_EINVAL, "target fraction must be in [0, 1]");
+    // scratch as for spheres: first covering index (N words), histogram (nc words)
+    unsigned *first = reinterpret_cast<unsigned *>(d.bh);
+    unsigned *cnt = first + d.N;
+    hipStream_t st = ctx->stream;
+    hipLaunchKernelGGL(k_fill_u, dim3(fill_grid(d.N)), dim3(256), 0, st, first, (long)d.N, 0xffffffffu);
+    if (nc > 0) {
+        hipLaunchKernelGGL(k_fill_u, dim3(fill_grid(nc)), dim3(256), 0, st, cnt, (long)nc, 0u);
+        hipLaunchKernelGGL(k_incl_first_q, dim3(nc), dim3(256), 0, st, ctx->d_inst, inst, shapes, nc, first);
+        hipLaunchKernelGGL(k_incl_count, dim3(fill_grid(d.N)), dim3(256), 0, st, first, (long)d.N, nc, cnt);
+    }
+    hipLaunchKernelGGL(k_incl_scan, dim3(1), dim3(1024), 0, st, ctx->d_inst, inst, cnt, nc, target);
+    hipLaunchKernelGGL(k_incl_write, dim3(fill_grid(d.N)), dim3(256), 0, st, ctx->d_inst, inst, first, eps_in,
+                       eps_out);
+    LAUNCHCHK();
+    DevState h;
+    HIPCHK(hipMemcpyAsync(&h, d.st, sizeof h, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (n_used) *n_used = h.n_used;
+    if (fraction) *fraction = h.frac;
+    return TDGL_OK;
+}
+
 tdgl_status tdgl_set_psi(tdgl_ctx *ctx, int inst, const void *psi) {
     tdgl_status s = check_ctx(ctx, inst);
     if (s) return s;
@@ -1517,7 +1574,7 @@ tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats) {
         // ---- Jacobi solve (all instances) --------------------------------
         {
             ProfScope ps(ctx, TDGL_K_ASSEMBLE);
-            launch_stencil<MODE_FIRST>(ctx, 0);
+            launch_assemble(ctx);
         }
         LAUNCHCHK();
         tdgl_status e = jacobi_loop(ctx, &acc, &strict_fail, 1);

@@ -148,7 +148,7 @@ __device__ __forceinline__ void stencil_tile(const Inst *__restrict__ insts, con
     // per-plane streams of the first plane
     float2 bh[ROWS], dh[ROWS];
     float ep[ROWS], mu[ROWS];
-    const float mu_mean = (MODE == MODE_FIRST && I.driven) ? (float)st->mu_mean : 0.f;
+    const float mu_mean = (is_first_mode(MODE) && I.driven) ? (float)st->mu_mean : 0.f;
     auto load_streams = [&](int k, float2 *bh_, float2 *dh_, float *ep_, float *mu_) {
         const unsigned pb = (unsigned)k * NXY;
 #pragma unroll
@@ -158,9 +158,9 @@ __device__ __forceinline__ void stencil_tile(const Inst *__restrict__ insts, con
                 bh_[r] = vy[r] ? (NT ? ld2nt(bhp, m) : ld2(bhp, m)) : make_float2(0.f, 0.f);
                 dh_[r] = vy[r] ? (NT ? ld2nt(dhp, m) : ld2(dhp, m)) : make_float2(0.f, 0.f);
             }
-            if (MODE == MODE_FIRST || MODE == MODE_ENERGY)
+            if (is_first_mode(MODE) || MODE == MODE_ENERGY)
                 ep_[r] = vy[r] ? (NT ? __builtin_nontemporal_load(&epsp[m]) : float(epsp[m])) : 0.f;
-            if (MODE == MODE_FIRST)
+            if (is_first_mode(MODE))
                 mu_[r] = (vy[r] && I.driven) ? (NT ? __builtin_nontemporal_load(&mup[m]) : float(mup[m])) - mu_mean : 0.f;
         }
     };
@@ -169,7 +169,7 @@ __device__ __forceinline__ void stencil_tile(const Inst *__restrict__ insts, con
     const float ht2 = I.ht2, S2 = I.S2, u = I.u;
     const bool zper = I.per[2] != 0;
     // Langevin draws of this step (assemble only): step counter before the step
-    const bool noise = (MODE == MODE_FIRST) && I.zeta_max > 0.f;
+    const bool noise = (MODE == MODE_FIRSTN) && I.zeta_max > 0.f;
     const unsigned long long nstep = noise ? (unsigned long long)st->n : 0ull;
     float rmax = 0.f;
     double acc = 0.0;
@@ -231,7 +231,7 @@ __device__ __forceinline__ void stencil_tile(const Inst *__restrict__ insts, con
                 continue;
             }
             float2 nw;
-            if (MODE == MODE_FIRST) {
+            if (is_first_mode(MODE)) {
                 float2 bhv, dhv;
                 float r2;
                 const float2 zz = noise ? langevin2(I, m, nstep) : make_float2(0.f, 0.f);
@@ -269,7 +269,7 @@ __device__ __forceinline__ void stencil_tile(const Inst *__restrict__ insts, con
 
     if (MODE == MODE_NS) {
         return;
-    } else if (MODE == MODE_FIRST || MODE == MODE_SWEEP) {
+    } else if (is_first_mode(MODE) || MODE == MODE_SWEEP) {
         if (timing || fixp) return;
         __syncthreads();
         wg_max_to<WG>(row_slot(I.res, I.rstride, l, b), rmax, reinterpret_cast<float *>(red));
@@ -333,6 +333,8 @@ __global__ __launch_bounds__(WG) void k_jacobi_persist(const Inst *__restrict__ 
 #define TDGL_INST_R(R)                 \
     TDGL_INST(MODE_FIRST, R, false)    \
     TDGL_INST(MODE_FIRST, R, true)     \
+    TDGL_INST(MODE_FIRSTN, R, false)   \
+    TDGL_INST(MODE_FIRSTN, R, true)    \
     TDGL_INST(MODE_SWEEP, R, false)    \
     TDGL_INST(MODE_SWEEP, R, true)     \
     TDGL_INST(MODE_RHS, R, false)      \

@@ -10,6 +10,9 @@
 
 namespace tdgl {
 
+// Largest reach |c| + r (in node spacings) of a candidate's box: 2^50.
+constexpr double kInclReach = 1125899906842624.0;
+
 // One work-group per candidate sphere: visit the integer bounding box of
 // the sphere (one node margin), test each node image exactly and record the
 // smallest covering index.  The membership test
@@ -34,7 +37,9 @@ __global__ __launch_bounds__(256) void k_incl_first(const Inst *__restrict__ ins
     long lo[3], cnt[3];
     for (int a = 0; a < 3; ++a) {
         const double c = centres[3 * s + a];
-        if (!(fabs(c) < 1e30)) return;
+        // a box reaching beyond 2^50 node spacings (or non-finite) covers
+        // nothing; below that bound every box end is an exact integer
+        if (!(fabs(c) + r <= kInclReach * h[a])) return;
         long l0 = (long)floor((c - r) / h[a]) - 1;
         long h0 = (long)ceil((c + r) / h[a]) + 1;
         if (!I.per[a]) {
@@ -62,6 +67,70 @@ __global__ __launch_bounds__(256) void k_incl_first(const Inst *__restrict__ ins
         const double dz = (double)uz * h[2] - cz;
         const double d2 = (dx * dx + dy * dy) + dz * dz;
         if (d2 <= r2) {
+            const long ix = ((ux % n[0]) + n[0]) % n[0];
+            const long iy = ((uy % n[1]) + n[1]) % n[1];
+            const long iz = ((uz % n[2]) + n[2]) % n[2];
+            atomicMin(&first[(iz * n[1] + iy) * n[0] + ix], (unsigned)s);
+        }
+    }
+}
+
+// The same for general convex candidates (ellipsoids, columns): shape s is
+// 16 doubles,
+//     c[3] | Q_xx Q_yy Q_zz Q_xy Q_xz Q_yz | n[3] | hlen | ext[3],
+// and a node image is inside iff, with d = u h - c,
+//     q = (((Qxx dx) dx + (Qyy dy) dy) + (Qzz dz) dz)
+//         + 2 (((Qxy dx) dy + (Qxz dx) dz) + (Qyz dy) dz)  <=  1
+// and, when hlen >= 0, |(nx dx + ny dy) + nz dz| <= hlen; double precision,
+// no contraction.  The images tested are those of the box c +- ext (one node
+// margin), clipped on open axes and held within one period of the centre on
+// periodic ones.
+__global__ __launch_bounds__(256) void k_incl_first_q(const Inst *__restrict__ insts, int inst,
+                                                      const double *__restrict__ shapes, int nc,
+                                                      unsigned *__restrict__ first) {
+#pragma clang fp contract(off)
+    const Inst &I = insts[inst];
+    const int s = blockIdx.x;
+    if (s >= nc) return;
+    const double *sh = shapes + 16 * (size_t)s;
+    const double h[3] = {I.hx, I.hy, I.hz};
+    const int n[3] = {I.nx, I.ny, I.nz};
+    for (int k = 0; k < 16; ++k)
+        if (!(fabs(sh[k]) < 1e30)) return;  // non-finite input: the shape covers nothing
+    long lo[3], cnt[3];
+    for (int a = 0; a < 3; ++a) {
+        const double c = sh[a], e = sh[13 + a];
+        if (!(e >= 0.0) || !(fabs(c) + e <= kInclReach * h[a])) return;
+        long l0 = (long)floor((c - e) / h[a]) - 1;
+        long h0 = (long)ceil((c + e) / h[a]) + 1;
+        if (!I.per[a]) {
+            if (l0 < 0) l0 = 0;
+            if (h0 > n[a] - 1) h0 = n[a] - 1;
+        } else {
+            const long cc = (long)floor(c / h[a]);
+            if (l0 < cc - n[a] - 1) l0 = cc - n[a] - 1;
+            if (h0 > cc + n[a] + 1) h0 = cc + n[a] + 1;
+        }
+        lo[a] = l0;
+        cnt[a] = h0 - l0 + 1;
+        if (cnt[a] <= 0) return;
+    }
+    const double cx = sh[0], cy = sh[1], cz = sh[2];
+    const double qxx = sh[3], qyy = sh[4], qzz = sh[5], qxy = sh[6], qxz = sh[7], qyz = sh[8];
+    const double ax = sh[9], ay = sh[10], az = sh[11], hlen = sh[12];
+    const long tot = cnt[0] * cnt[1] * cnt[2];
+    for (long t = threadIdx.x; t < tot; t += blockDim.x) {
+        const long ux = lo[0] + t % cnt[0];
+        const long uy = lo[1] + (t / cnt[0]) % cnt[1];
+        const long uz = lo[2] + t / (cnt[0] * cnt[1]);
+        const double dx = (double)ux * h[0] - cx;
+        const double dy = (double)uy * h[1] - cy;
+        const double dz = (double)uz * h[2] - cz;
+        const double q = (((qxx * dx) * dx + (qyy * dy) * dy) + (qzz * dz) * dz) +
+                         2.0 * (((qxy * dx) * dy + (qxz * dx) * dz) + (qyz * dy) * dz);
+        bool in = q <= 1.0;
+        if (in && hlen >= 0.0) in = fabs((ax * dx + ay * dy) + az * dz) <= hlen;
+        if (in) {
             const long ix = ((ux % n[0]) + n[0]) % n[0];
             const long iy = ((uy % n[1]) + n[1]) % n[1];
             const long iz = ((uz % n[2]) + n[2]) % n[2];

@@ -4,7 +4,10 @@
 
 namespace tdgl {
 
-enum { MODE_FIRST = 0, MODE_SWEEP = 1, MODE_RHS = 2, MODE_ENERGY = 3, MODE_NS = 4 };
+enum { MODE_FIRST = 0, MODE_SWEEP = 1, MODE_RHS = 2, MODE_ENERGY = 3, MODE_NS = 4, MODE_FIRSTN = 5 };
+// MODE_FIRSTN: MODE_FIRST with the Langevin term (a separate instantiation,
+// so that the noiseless assemble carries none of the generator's registers).
+constexpr bool is_first_mode(int m) { return m == MODE_FIRST || m == MODE_FIRSTN; }
 constexpr int JAV_CPT = 16;     // cells per thread of the flat reductions
 constexpr int CO_THREADS = 1024;
 constexpr int FIN_THREADS = 256;  // threads per instance of the solve finalizers
@@ -86,6 +89,9 @@ __global__ void k_adj_reduce(const Inst *insts, int nparts, int which, double ew
 
 __global__ void k_incl_first(const Inst *insts, int inst, const double *centres, const double *diam,
                              int nc, unsigned *first);
+__global__ void k_voronoi(const Inst *insts, int inst, const double *seeds, const float *values, int ns,
+                          int metric, int axes);
+__global__ void k_incl_first_q(const Inst *insts, int inst, const double *shapes, int nc, unsigned *first);
 __global__ void k_incl_count(const unsigned *first, long N, int nc, unsigned *cnt);
 __global__ void k_incl_scan(const Inst *insts, int inst, const unsigned *cnt, int nc, double target);
 __global__ void k_incl_write(const Inst *insts, int inst, const unsigned *first, float eps_in,

@@ -60,6 +60,129 @@ def sphere_candidates(lengths, n: int, seed: int, law: str = "fixed", d: float =
     return np.ascontiguousarray(c), np.ascontiguousarray(dia)
 
 
+def ellipsoid_shape(centre, axes, rot=None) -> np.ndarray:
+    """One candidate for the general inclusion generator: the ellipsoid with
+    semi-axes `axes` along the columns of the rotation `rot` (default the
+    identity) around `centre`, as 16 doubles (centre, Q_xx Q_yy Q_zz Q_xy
+    Q_xz Q_yz, axis (unused, 0), hlen = -1, bounding half-widths)."""
+    R = np.eye(3) if rot is None else np.asarray(rot, dtype=np.float64)
+    a = np.asarray(axes, dtype=np.float64)
+    Q = R @ np.diag(1.0 / (a * a)) @ R.T
+    ext = np.sqrt((R * R) @ (a * a))
+    return np.array([*centre, Q[0, 0], Q[1, 1], Q[2, 2], Q[0, 1], Q[0, 2], Q[1, 2], 0.0, 0.0, 0.0, -1.0, *ext],
+                    dtype=np.float64)
+
+
+def column_shape(centre, axis, radius: float, length: float) -> np.ndarray:
+    """A columnar candidate: the cylinder of `radius` and `length` along the
+    unit vector `axis` through `centre` (Q = (I - n n^T) / radius^2, hlen =
+    length / 2), as 16 doubles."""
+    n = np.asarray(axis, dtype=np.float64)
+    n = n / np.sqrt(np.dot(n, n))
+    Q = (np.eye(3) - np.outer(n, n)) / (radius * radius)
+    hl = 0.5 * length
+    ext = hl * np.abs(n) + radius * np.sqrt(np.maximum(1.0 - n * n, 0.0))
+    return np.array([*centre, Q[0, 0], Q[1, 1], Q[2, 2], Q[0, 1], Q[0, 2], Q[1, 2], *n, hl, *ext],
+                    dtype=np.float64)
+
+
+def ellipsoid_candidates(lengths, n: int, seed: int, axes=(1.5, 1.5, 4.0), tilt_deg: float = 0.0,
+                         random_azimuth: bool = False) -> np.ndarray:
+    """Candidates like the paper's Fig. 2d: ellipsoids of fixed semi-axes and
+    one common orientation, centres uniform in the box.  The third axis is
+    tilted by tilt_deg from z towards x; with random_azimuth each candidate
+    is then turned about z by its own uniform random angle.  (n, 16)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = rng.random((n, 3)) * np.asarray(lengths, dtype=np.float64)[None, :]
+    phi = rng.random(n) * 2.0 * np.pi if random_azimuth else np.zeros(n)
+    t = np.deg2rad(tilt_deg)
+    Ry = np.array([[np.cos(t), 0.0, np.sin(t)], [0.0, 1.0, 0.0], [-np.sin(t), 0.0, np.cos(t)]])
+    out = np.empty((n, 16))
+    for s in range(n):
+        Rz = np.array([[np.cos(phi[s]), -np.sin(phi[s]), 0.0], [np.sin(phi[s]), np.cos(phi[s]), 0.0],
+                       [0.0, 0.0, 1.0]])
+        out[s] = ellipsoid_shape(c[s], axes, Rz @ Ry)
+    return np.ascontiguousarray(out)
+
+
+def column_candidates(lengths, n: int, seed: int, radius: float = 1.0, tilt_deg: float = 45.0) -> np.ndarray:
+    """Candidates like the paper's Fig. 2e: columns of `radius` crossing the
+    z extent, tilted by +tilt_deg or -tilt_deg (at random) from z in the xz
+    plane, centres uniform in the box.  (n, 16)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    L = np.asarray(lengths, dtype=np.float64)
+    c = rng.random((n, 3)) * L[None, :]
+    sgn = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    t = np.deg2rad(tilt_deg)
+    length = L[2] / np.cos(t)
+    out = np.empty((n, 16))
+    for s in range(n):
+        out[s] = column_shape(c[s], (sgn[s] * np.sin(t), 0.0, np.cos(t)), radius, length)
+    return np.ascontiguousarray(out)
+
+
+def lattice_centres(kind: str, lengths, a: float, z: float = None, offset=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """Centres of a regular arrangement of inclusions (Sec. 3.4): in 2D
+    (kind "square", "triangular", "honeycomb"; lattice constant a, every
+    centre at height z, default mid-box) or 3D ("rectangular": simple cubic
+    of constant a, "hexagonal": triangular layers stacked a apart).  Sites
+    fill the box [0, L) from `offset`; (n, 3)."""
+    Lx, Ly, Lz = (float(v) for v in lengths)
+    ox, oy, oz = offset
+    zc = 0.5 * Lz if z is None else z
+
+    def grid2(ax, ay, basis, stagger):
+        pts = []
+        nyr = int(np.floor(Ly / ay + 1e-9))
+        nxr = int(np.floor(Lx / ax + 1e-9))
+        for r in range(nyr):
+            sx = stagger * (r % 2)
+            for q in range(nxr):
+                for bx, by in basis:
+                    pts.append((ox + (q + sx) * ax + bx, oy + r * ay + by))
+        return pts
+
+    if kind == "square":
+        p2 = grid2(a, a, [(0.0, 0.0)], 0.0)
+    elif kind == "triangular":
+        p2 = grid2(a, a * np.sqrt(3.0) / 2.0, [(0.0, 0.0)], 0.5)
+    elif kind == "honeycomb":
+        # two sites per cell of the triangular lattice of constant a sqrt(3)
+        A = a * np.sqrt(3.0)
+        p2 = grid2(A, 1.5 * a, [(0.0, 0.0), (0.5 * A, 0.5 * a)], 0.5)
+    elif kind in ("rectangular", "hexagonal"):
+        if kind == "rectangular":
+            p2 = grid2(a, a, [(0.0, 0.0)], 0.0)
+        else:
+            p2 = grid2(a, a * np.sqrt(3.0) / 2.0, [(0.0, 0.0)], 0.5)
+        nzl = int(np.floor(Lz / a + 1e-9))
+        return np.array([(x % Lx, y % Ly, oz + l * a) for l in range(nzl) for x, y in p2], dtype=np.float64)
+    else:
+        raise ValueError(f"unknown lattice {kind!r}")
+    return np.array([(x % Lx, y % Ly, zc) for x, y in p2], dtype=np.float64)
+
+
+def voronoi_seeds(lengths, n: int, seed: int, lo: float = 0.5, hi: float = 1.0):
+    """Seeds of a polycrystal (Fig. 2c): n positions uniform in the box and
+    one eps per crystallite, uniform in [lo, hi)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pos = rng.random((n, 3)) * np.asarray(lengths, dtype=np.float64)[None, :]
+    vals = lo + (hi - lo) * rng.random(n)
+    return pos, vals.astype(np.float32)
+
+
+def random_checkerboard(shape, cell, seed: int, values=(1.0, 0.5)) -> np.ndarray:
+    """Random map of two eps values with equal probability per block of
+    cell[0] x cell[1] x cell[2] nodes (z, y, x order), as in Fig. 2a; float32
+    of `shape` (nz, ny, nx)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nb = [-(-shape[a] // cell[a]) for a in range(3)]
+    pick = rng.random(nb) < 0.5
+    full = np.repeat(np.repeat(np.repeat(pick, cell[0], 0), cell[1], 1), cell[2], 2)
+    full = full[:shape[0], :shape[1], :shape[2]]
+    return np.where(full, values[0], values[1]).astype(np.float32)
+
+
 def candidate_count(lengths, target: float, mean_volume: float, safety: float = 2.5) -> int:
     """Number of candidate spheres to draw: enough for the target covered
     fraction with overlaps (coverage 1 - exp(-n v / V)), times a safety

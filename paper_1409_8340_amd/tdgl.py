@@ -109,6 +109,11 @@ _SIGS = {
     "tdgl_gen_inclusions": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                              ctypes.c_double, ctypes.c_float, ctypes.c_float, ctypes.POINTER(ctypes.c_int),
                              ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "tdgl_gen_shapes": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
+                         ctypes.c_float, ctypes.c_float, ctypes.POINTER(ctypes.c_int),
+                         ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "tdgl_gen_voronoi": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                          ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "tdgl_set_psi": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "tdgl_get_psi": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "tdgl_set_mu": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
@@ -275,6 +280,28 @@ class Solver:
                                           float(eps_in), float(eps_out), ctypes.byref(used),
                                           ctypes.byref(frac)))
         return used.value, frac.value
+
+    def gen_shapes(self, shapes, target, eps_in=-1.0, eps_out=1.0, inst=0):
+        """shapes: (nc, 16) doubles per tdgl_gen_shapes (centre, Q, axis, hlen, ext)."""
+        import torch
+        sh = torch.as_tensor(shapes, dtype=torch.float64).reshape(-1, 16).contiguous().cuda()
+        used, frac = ctypes.c_int(), ctypes.c_double()
+        _check(load().tdgl_gen_shapes(self._ctx, inst, self._dev(sh, torch.float64), int(sh.shape[0]),
+                                      float(target), float(eps_in), float(eps_out), ctypes.byref(used),
+                                      ctypes.byref(frac)))
+        return used.value, frac.value
+
+    def gen_voronoi(self, seeds, values, metric=0, axes=7, inst=0):
+        """seeds: (ns, 3) positions; values: (ns,) eps per crystallite;
+        metric 0 Euclidean, 1 absolute, 2 maximum; axes: bit mask of the
+        axes in the distance (per tdgl_gen_voronoi)."""
+        import torch
+        sd = torch.as_tensor(seeds, dtype=torch.float64).reshape(-1, 3).contiguous().cuda()
+        vals = torch.as_tensor(values, dtype=torch.float32).reshape(-1).contiguous().cuda()
+        if vals.numel() != sd.shape[0]:
+            raise ValueError("one value per seed")
+        _check(load().tdgl_gen_voronoi(self._ctx, inst, self._dev(sd, torch.float64), self._dev(vals, torch.float32),
+                                       int(sd.shape[0]), int(metric), int(axes)))
 
     def set_psi(self, psi, inst=0):
         import torch

@@ -382,3 +382,80 @@ def test_persistent_solve_caps_and_strict():
         z.step(1, stats=False)
     assert tdgl.STATUS[e.value.status] == "ENOCONV"
     z.close()
+
+
+@pytest.mark.parametrize("nx,ny,nz,open_,kind,frac", [
+    (64, 64, 16, (False, False, False), "ellipsoid", 0.10),
+    (96, 80, 40, (False, False, True), "column", 0.12),
+    (70, 37, 9, (True, False, True), "mixed", 0.20),
+    (32, 24, 12, (False, False, False), "long", 0.95),     # wraps past one period; target out of reach
+])
+def test_shape_generator_bit_exact(nx, ny, nz, open_, kind, frac):
+    """General convex inclusions (ellipsoids, +-45 degree columns of Fig. 2d/e):
+    the GPU's first-covering-index construction equals the oracle's
+    sequential addition node for node, with the same count used."""
+    grid = O.Grid(nx, ny, nz, open_=open_)
+    L = [grid.length(a) for a in range(3)]
+    if kind == "ellipsoid":
+        sh = inputs.ellipsoid_candidates(L, 400, 11, axes=(1.5, 1.5, 4.0), tilt_deg=30.0, random_azimuth=True)
+    elif kind == "column":
+        sh = inputs.column_candidates(L, 300, 12, radius=1.5)
+    elif kind == "mixed":
+        e = inputs.ellipsoid_candidates(L, 100, 13, axes=(2.0, 1.0, 1.5))
+        c = inputs.column_candidates(L, 100, 14, radius=1.0)
+        bad = e[:3].copy()
+        bad[0, 5] = np.nan
+        bad[1, 14] = -1.0
+        bad[2, 1] = 1e300
+        sh = np.concatenate([bad, e[:50], c, e[50:]])
+    else:
+        sh = inputs.column_candidates(L, 6, 15, radius=2.0, tilt_deg=60.0)
+        sh[:, 12] *= 3.0        # columns longer than the box in z
+        sh[:, 13:16] = np.asarray(L) * 1.5
+    eps_o, used_o, frac_o = O.gen_shapes(grid, sh, frac)
+    bc = tuple(tdgl.TDGL_OPEN if o else tdgl.TDGL_PERIODIC for o in open_)
+    s = tdgl.Solver(tdgl.make_params(nx, ny, nz, bc=bc))
+    used, f = s.gen_shapes(sh, frac, -0.5, 1.0)
+    eps_g = s.get_eps().cpu().numpy()
+    s.close()
+    print(f"[shapes {kind}] used {used}/{len(sh)} fraction {f:.4f}")
+    assert used == used_o
+    assert f == frac_o
+    assert np.array_equal(eps_g, np.where(eps_o < 0, -0.5, 1.0).astype(np.float32))
+
+
+@pytest.mark.parametrize("nx,ny,nz,open_,ns,metric,axes", [
+    (64, 64, 16, (False, False, True), 40, 0, 7),
+    (64, 64, 16, (False, False, True), 40, 1, 7),
+    (64, 64, 16, (False, False, True), 40, 2, 7),
+    (70, 37, 9, (True, False, True), 1100, 0, 3),      # columnar grains; seeds span three LDS chunks
+    (48, 40, 24, (False, True, False), 300, 2, 5),
+])
+def test_voronoi_bit_exact(nx, ny, nz, open_, ns, metric, axes):
+    """Tessellation (Fig. 2c polycrystal, Euclidean / absolute / maximum
+    distance): every node's eps equals the oracle's nearest-seed value."""
+    grid = O.Grid(nx, ny, nz, open_=open_)
+    L = [grid.length(a) for a in range(3)]
+    pos, _ = inputs.voronoi_seeds(L, ns, 100 + ns + metric)
+    vals = (np.arange(ns, dtype=np.float32) + 1.0) / ns       # distinct: the value names the seed
+    pos[5] = [np.nan, 1.0, 1.0]                             # skipped
+    eps_o, owner = O.gen_voronoi(grid, pos, vals.astype(np.float64), metric, axes)
+    bc = tuple(tdgl.TDGL_OPEN if o else tdgl.TDGL_PERIODIC for o in open_)
+    s = tdgl.Solver(tdgl.make_params(nx, ny, nz, bc=bc))
+    s.gen_voronoi(pos, vals, metric, axes)
+    eps_g = s.get_eps().cpu().numpy()
+    s.close()
+    assert np.all(owner >= 0) and not np.any(owner == 5)
+    assert np.array_equal(eps_g, eps_o.astype(np.float32))
+
+
+def test_voronoi_keeps_eps_where_no_seed_and_rejects_bad_arguments():
+    s = tdgl.Solver(tdgl.make_params(16, 12, 8))
+    base = inputs.random_real((8, 12, 16), 3, 0.2, 1.0)
+    s.set_eps(torch.from_numpy(base).cuda())
+    s.gen_voronoi(np.full((3, 3), np.inf), np.ones(3, np.float32))
+    assert np.array_equal(s.get_eps().cpu().numpy(), base)
+    for kw in ({"metric": 3}, {"axes": 0}, {"axes": 8}):
+        with pytest.raises(tdgl.TdglError):
+            s.gen_voronoi(np.zeros((2, 3)), np.ones(2, np.float32), **kw)
+    s.close()

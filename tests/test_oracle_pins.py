@@ -491,6 +491,269 @@ def test_inclusion_generator_statistics():
     assert set(np.unique(eps1)) == {-1.0, 1.0}
 
 
+def _exact_q_inside(grid, sh):
+    """Brute force for one general candidate: every node, every image one
+    period either side on periodic axes, membership evaluated EXACTLY in
+    rational arithmetic from the given doubles.  Returns (inside, margin):
+    margin is the smallest exact distance of q from 1 (and of |n.d| from
+    hlen) over all tested images, the room a double evaluation has."""
+    from fractions import Fraction as F
+    ns = (grid.nx, grid.ny, grid.nz)
+    hs = [F(grid.hx), F(grid.hy), F(grid.hz)]
+    c = [F(float(x)) for x in sh[0:3]]
+    qxx, qyy, qzz, qxy, qxz, qyz = [F(float(x)) for x in sh[3:9]]
+    ax, ay, az = [F(float(x)) for x in sh[9:12]]
+    hlen = F(float(sh[12]))
+    out = np.zeros(grid.shape, bool)
+    margin = np.full(grid.shape, np.inf)
+    shifts = [[0] if grid.open_[a] else [-1, 0, 1] for a in range(3)]
+    for k in range(grid.nz):
+        for j in range(grid.ny):
+            for i in range(grid.nx):
+                for sx in shifts[0]:
+                    for sy in shifts[1]:
+                        for sz in shifts[2]:
+                            u = (i + sx * ns[0], j + sy * ns[1], k + sz * ns[2])
+                            dx, dy, dz = [u[a] * hs[a] - c[a] for a in range(3)]
+                            q = qxx * dx * dx + qyy * dy * dy + qzz * dz * dz + \
+                                2 * (qxy * dx * dy + qxz * dx * dz + qyz * dy * dz)
+                            m = abs(q - 1)
+                            ok = q <= 1
+                            if hlen >= 0:
+                                t = abs(ax * dx + ay * dy + az * dz)
+                                ok = ok and t <= hlen
+                                m = min(m, abs(t - hlen))
+                            out[k, j, i] |= ok
+                            margin[k, j, i] = min(margin[k, j, i], float(m))
+    return out, margin
+
+
+@pytest.mark.parametrize("kind", ["ellipsoid", "column"])
+def test_shape_generator_against_exact_brute_force(kind):
+    """The general-shape oracle (Sec. 3.4, Fig. 2d/e) covers exactly the
+    nodes that exact rational arithmetic puts inside the used candidates,
+    except nodes whose exact q lies within 1e-12 of the boundary, where the
+    rounding of a double evaluation decides.  Also: the sequential stop rule
+    (one candidate fewer misses the target)."""
+    grid = O.Grid(14, 12, 9, 0.5, 0.5, 0.5, open_=(False, False, True))
+    L = [grid.length(a) for a in range(3)]
+    if kind == "ellipsoid":
+        sh = inputs.ellipsoid_candidates(L, 12, 31, axes=(0.9, 0.7, 1.6), tilt_deg=40.0,
+                                        random_azimuth=True)
+    else:
+        sh = inputs.column_candidates(L, 12, 32, radius=0.6)
+    target = 0.15
+    eps, used, frac = O.gen_shapes(grid, sh, target)
+    cover = np.zeros(grid.shape, bool)
+    fuzzy = np.zeros(grid.shape, bool)
+    prev = None
+    for s in range(used):
+        if s == used - 1:
+            prev = cover.copy()
+        ins, mg = _exact_q_inside(grid, sh[s])
+        cover |= ins
+        fuzzy |= mg < 1e-12
+    got = eps < 0
+    assert np.array_equal(got[~fuzzy], cover[~fuzzy])
+    assert frac >= target and frac == got.sum() / grid.N
+    assert (prev | (fuzzy & got)).sum() < target * grid.N
+
+
+def test_shape_generator_dyadic_cases_are_exact():
+    """Dyadic centres, spacings and axes make every double operation exact:
+    axis-aligned ellipsoids and z columns then match the rational brute
+    force node for node, a sphere written as Q = I/r^2 matches the sphere
+    generator, and a column along z is a disc extruded over its length."""
+    grid = O.Grid(16, 12, 10, 0.5, 0.5, 0.5, open_=(False, True, False))
+    shapes = np.array([
+        inputs.ellipsoid_shape((1.25, 2.5, 0.75), (2.0, 1.0, 0.5)),
+        inputs.ellipsoid_shape((7.75, 0.25, 4.5), (1.0, 2.0, 1.0)),      # wraps in x and z
+        inputs.column_shape((4.0, 3.0, 2.5), (0.0, 0.0, 1.0), 1.0, 3.0),
+    ])
+    eps, used, frac = O.gen_shapes(grid, shapes, 1.0)
+    assert used == 3
+    cover = np.zeros(grid.shape, bool)
+    for sh in shapes:
+        ins, _ = _exact_q_inside(grid, sh)
+        cover |= ins
+    np.testing.assert_array_equal(eps < 0, cover)
+    # the column: |x - cx|^2 + |y - cy|^2 <= 1 and |z - cz| <= 1.5, z periodic
+    col, _, _ = O.gen_shapes(grid, shapes[2:3], 1.0)
+    k, j, i = np.meshgrid(np.arange(10), np.arange(12), np.arange(16), indexing="ij")
+    dz = np.minimum(np.abs(k * 0.5 - 2.5), 5.0 - np.abs(k * 0.5 - 2.5))
+    dx = np.minimum(np.abs(i * 0.5 - 4.0), 8.0 - np.abs(i * 0.5 - 4.0))
+    disc = (dx ** 2 + (j * 0.5 - 3.0) ** 2 <= 1.0) & (dz <= 1.5)
+    np.testing.assert_array_equal(col < 0, disc)
+    # spheres: Q = I / r^2 with r a power of two
+    cen = np.array([[3.0, 2.5, 1.5], [6.5, 5.0, 4.0]])
+    dia = np.array([2.0, 4.0])
+    sph = np.array([inputs.ellipsoid_shape(c, (d / 2,) * 3) for c, d in zip(cen, dia)])
+    e1, u1, f1 = O.gen_inclusions(grid, cen, dia, 1.0)
+    e2, u2, f2 = O.gen_shapes(grid, sph, 1.0)
+    assert u1 == u2 and f1 == f2
+    np.testing.assert_array_equal(e1, e2)
+
+
+def test_shape_builders():
+    """Q of an ellipsoid has eigenvalues a^-2 along the rotated axes, ext is
+    the exact half-width of its bounding box; a column's ext bounds every
+    point of it and is reached."""
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        A, _r = np.linalg.qr(rng.standard_normal((3, 3)))
+        a = rng.uniform(0.5, 3.0, 3)
+        sh = inputs.ellipsoid_shape((0, 0, 0), a, A)
+        Q = np.array([[sh[3], sh[6], sh[7]], [sh[6], sh[4], sh[8]], [sh[7], sh[8], sh[5]]])
+        np.testing.assert_allclose(A.T @ Q @ A, np.diag(a ** -2.0), atol=1e-12)
+        # support function of the ellipsoid along e_i: sqrt(e_i^T Q^-1 e_i)
+        np.testing.assert_allclose(sh[13:16], np.sqrt(np.diag(np.linalg.inv(Q))), rtol=1e-12)
+        n = rng.standard_normal(3)
+        n /= np.linalg.norm(n)
+        sh = inputs.column_shape((0, 0, 0), n, 0.7, 5.0)
+        # points of the column: t n + rho w, w orthonormal to n, |t| <= L/2
+        w1 = np.cross(n, [1.0, 0.0, 0.0] if abs(n[0]) < 0.9 else [0.0, 1.0, 0.0])
+        w1 /= np.linalg.norm(w1)
+        w2 = np.cross(n, w1)
+        th = np.linspace(0, 2 * np.pi, 721)
+        pts = np.concatenate([t * n[None, :] + 0.7 * (np.cos(th)[:, None] * w1 + np.sin(th)[:, None] * w2)
+                              for t in (-2.5, 2.5)])
+        far = np.max(np.abs(pts), axis=0)
+        assert np.all(far <= sh[13:16] + 1e-12)
+        np.testing.assert_allclose(far, sh[13:16], rtol=1e-4)
+
+
+def test_shape_volumes_and_invalid_candidates():
+    """One large candidate covers its volume (4 pi abc/3, pi rho^2 L) to a
+    few per cent; non-finite or negative-extent candidates cover nothing
+    but count as used; target 0 uses none."""
+    grid = O.Grid(64, 64, 64, 0.5, 0.5, 0.5)
+    R = np.linalg.qr(np.random.default_rng(9).standard_normal((3, 3)))[0]
+    e, _, f = O.gen_shapes(grid, inputs.ellipsoid_shape((16, 16, 16), (6.0, 4.0, 9.0), R)[None], 1.0)
+    vol = 4.0 / 3.0 * np.pi * 6 * 4 * 9 / 0.125
+    assert abs(f * grid.N / vol - 1) < 0.02
+    e, _, f = O.gen_shapes(grid, inputs.column_shape((16, 16, 16), (0.6, 0.0, 0.8), 3.0, 20.0)[None], 1.0)
+    vol = np.pi * 9.0 * 20.0 / 0.125
+    assert abs(f * grid.N / vol - 1) < 0.02
+    good = inputs.ellipsoid_shape((8, 8, 8), (2.0, 2.0, 2.0))
+    bad1 = good.copy()
+    bad1[3] = np.nan
+    bad2 = good.copy()
+    bad2[14] = -1.0
+    bad3 = good.copy()
+    bad3[0] = 1e300
+    e, used, f = O.gen_shapes(grid, np.stack([bad1, bad2, bad3, good]), 0.5)
+    assert used == 4 and 0 < f < 0.5
+    e2, _, f2 = O.gen_shapes(grid, good[None], 0.5)
+    assert f == f2 and np.array_equal(e, e2)
+    e, used, f = O.gen_shapes(grid, np.stack([good]), 0.0)
+    assert used == 0 and f == 0.0 and np.all(e == 1.0)
+
+
+def _exact_voronoi_owner(grid, seeds, metric, axes):
+    """Brute force in rational arithmetic: for each node the exact distance
+    to every seed, minimised over all combinations of the node's images one
+    period either side on periodic axes, and the lowest index among the
+    nearest seeds.  Also the exact gap to the next-nearest seed."""
+    from fractions import Fraction as F
+    ns = (grid.nx, grid.ny, grid.nz)
+    hs = [F(grid.hx), F(grid.hy), F(grid.hz)]
+    sd = [[F(float(v)) for v in row] for row in seeds]
+    owner = np.zeros(grid.shape, np.int64)
+    gap = np.zeros(grid.shape)
+    shifts = [[0] if grid.open_[a] or not (axes >> a) & 1 else [-1, 0, 1] for a in range(3)]
+    for k in range(grid.nz):
+        for j in range(grid.ny):
+            for i in range(grid.nx):
+                dists = []
+                for c in sd:
+                    best = None
+                    for sx in shifts[0]:
+                        for sy in shifts[1]:
+                            for sz in shifts[2]:
+                                u = (i + sx * ns[0], j + sy * ns[1], k + sz * ns[2])
+                                d = [abs(u[a] * hs[a] - c[a]) if (axes >> a) & 1 else F(0) for a in range(3)]
+                                v = (d[0] ** 2 + d[1] ** 2 + d[2] ** 2 if metric == 0 else
+                                     d[0] + d[1] + d[2] if metric == 1 else max(d))
+                                best = v if best is None else min(best, v)
+                    dists.append(best)
+                m = min(dists)
+                owner[k, j, i] = dists.index(m)
+                srt = sorted(dists)
+                gap[k, j, i] = float(srt[1] - srt[0]) if len(srt) > 1 else np.inf
+    return owner, gap
+
+
+@pytest.mark.parametrize("metric", [0, 1, 2])
+@pytest.mark.parametrize("axes,open_", [(7, (False, False, True)), (3, (False, False, False)),
+                                        (7, (True, False, False)), (5, (False, True, True))])
+def test_voronoi_against_exact_brute_force(metric, axes, open_):
+    """The tessellation oracle (Sec. 3.4, Fig. 2c) assigns every node to the
+    seed that exact arithmetic over all periodic images makes nearest,
+    except where the two nearest seeds are within 1e-12 (rounding decides)."""
+    grid = O.Grid(9, 8, 6, 0.5, 0.75, 0.5, open_=open_)
+    L = [grid.length(a) for a in range(3)]
+    pos, vals = inputs.voronoi_seeds(L, 7, 40 + metric)
+    vals = np.arange(7, dtype=np.float64) + 2.0
+    eps, owner = O.gen_voronoi(grid, pos, vals, metric, axes)
+    ref, gap = _exact_voronoi_owner(grid, pos, metric, axes)
+    sure = gap > 1e-12
+    assert sure.mean() > 0.95
+    np.testing.assert_array_equal(owner[sure], ref[sure])
+    np.testing.assert_array_equal(eps, vals[owner])
+
+
+def test_voronoi_exact_ties_and_special_cases():
+    """Dyadic seeds make every distance exact, so equidistant nodes occur and
+    go to the lower index, as in the rational brute force; one seed owns
+    everything; non-finite seeds are skipped and nodes with no seed keep
+    their eps."""
+    grid = O.Grid(8, 8, 4, 0.5, 0.5, 0.5, open_=(False, False, True))
+    pos = np.array([[1.0, 1.0, 0.5], [3.0, 1.0, 0.5], [1.0, 3.0, 1.0], [3.0, 3.0, 1.0]])
+    for metric in (0, 1, 2):
+        eps, owner = O.gen_voronoi(grid, pos, np.arange(4.0), metric)
+        ref, gap = _exact_voronoi_owner(grid, pos, metric, 7)
+        assert np.any(gap == 0)
+        np.testing.assert_array_equal(owner, ref)
+    eps, owner = O.gen_voronoi(grid, pos[:1], [0.25], 1)
+    assert np.all(eps == 0.25) and np.all(owner == 0)
+    bad = pos.copy()
+    bad[1, 0] = np.nan
+    bad[3, 2] = np.inf
+    e1, o1 = O.gen_voronoi(grid, bad, np.arange(4.0), 0)
+    e2, o2 = O.gen_voronoi(grid, pos[[0, 2]], np.array([0.0, 2.0]), 0)
+    np.testing.assert_array_equal(e1, e2)
+    e3, o3 = O.gen_voronoi(grid, np.full((2, 3), np.nan), [5.0, 6.0], 0, eps=np.full(grid.shape, 0.75))
+    assert np.all(e3 == 0.75) and np.all(o3 == -1)
+
+
+def test_voronoi_two_seed_bisector():
+    """Two seeds on an open x axis: the Euclidean owner changes at the
+    midpoint plane, the closed form of the two-cell tessellation."""
+    grid = O.Grid(20, 5, 3, 0.5, 0.5, 0.5, open_=(True, True, True))
+    pos = np.array([[1.3, 1.0, 0.5], [6.1, 0.2, 0.9]])
+    eps, owner = O.gen_voronoi(grid, pos, [1.0, 0.5], 0)
+    z, y, x = np.meshgrid(np.arange(3) * 0.5, np.arange(5) * 0.5, np.arange(20) * 0.5, indexing="ij")
+    n = pos[1] - pos[0]
+    side = (x - 0.5 * (pos[0, 0] + pos[1, 0])) * n[0] + (y - 0.5 * (pos[0, 1] + pos[1, 1])) * n[1] + \
+        (z - 0.5 * (pos[0, 2] + pos[1, 2])) * n[2]
+    np.testing.assert_array_equal(owner, (side > 0).astype(np.int64))
+
+
+def test_lattice_builders():
+    """Interior sites of the 2D lattices have the textbook coordination at
+    the lattice constant (square 4, triangular 6, honeycomb 3) and none
+    closer; the 3D ones 6 (simple cubic) and 8 (simple hexagonal)."""
+    for kind, zc in [("square", 4), ("triangular", 6), ("honeycomb", 3), ("rectangular", 6), ("hexagonal", 8)]:
+        c = inputs.lattice_centres(kind, (30.0, 30.0, 30.0), 2.0)
+        mid = np.all(np.abs(c - 15.0) < 6.0, axis=1) if kind in ("rectangular", "hexagonal") else \
+            np.all(np.abs(c[:, :2] - 15.0) < 6.0, axis=1)
+        assert mid.sum() > 5
+        d = np.linalg.norm(c[mid][:, None, :] - c[None, :, :], axis=2)
+        d[d < 1e-12] = np.inf
+        assert np.allclose(d.min(axis=1), 2.0)
+        assert np.all(np.sum(np.abs(d - 2.0) < 1e-9, axis=1) == zc)
+
+
 # ---------------------------------------------------------------------------
 # Langevin noise (Sec. 3.1.2, "Noise terms"; Eq. b)
 # ---------------------------------------------------------------------------
