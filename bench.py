@@ -225,6 +225,42 @@ def batch_bench(tdgl, inputs, torch, steps, warmup, n=64):
             "sequential_sweeps_sum": sweeps_s}
 
 
+def jacobi_study(tdgl, inputs, torch, steps, warmup):
+    """The paper's Fig. 5 study on this solver: Jacobi iterations per step
+    and time per step of a 2D free-flowing vortex film (one z plane, no
+    pinning, B = 0.1 along z, J = 0.02 along x) against the grid size
+    (h = 0.5, tol 1e-6), the spacing h (1024 x 1024, tol 1e-6) and the
+    stop tolerance (1024 x 1024, h = 0.5).  tol bounds max|r|^2, the
+    reading used everywhere in this library.  One JSON line per point."""
+    pts = [("N", n, 0.5, 1e-6) for n in (128, 256, 512, 1024, 2048, 4096)]
+    pts += [("h", 1024, h, 1e-6) for h in (0.2, 0.3, 0.4, 0.5, 0.7, 1.0)]
+    pts += [("tol", 1024, 0.5, t) for t in (1e-2, 1e-4, 1e-6, 1e-8, 1e-10, 1e-12)]
+    for axis, n, h, tol in pts:
+        p = tdgl.make_params(n, n, 1, h=h, driven=True, tol=tol, max_iter=256, mu_tol=1e-5, mu_rtol=0.03,
+                             mu_max_cycles=20)
+        s = tdgl.Solver(p)
+        Bx, Bz = s.set_field(0.0, 0.1, quantize=True)
+        s.set_current(0.02)
+        s.set_psi(torch.from_numpy(inputs.psi_init(n, n, 1, 1005)).cuda())
+        tiling = s.autotune()
+        s.step(warmup, stats=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = s.step(steps, stats=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        s.close()
+        rec = {"study": "jacobi_fig5", "vary": axis, "nx": n, "ny": n, "nz": 1, "h": h, "tol": tol,
+               "B_eff": Bz, "J": 0.02, "warmup": warmup, "steps": steps,
+               "sweeps_per_step": st["sweeps_sum"] / steps, "sweeps_min": st["sweeps_min"],
+               "sweeps_max": st["sweeps_max"], "capped_steps": st["capped_steps"],
+               "ms_per_step": 1e3 * el / steps, "cell_updates_per_s": n * n * steps / el,
+               "tiling": {k: tiling[k] for k in ("rows", "chunk", "streaming", "fused")}}
+        log(f"[study] {axis}: n={n} h={h} tol={tol:g}: {rec['sweeps_per_step']:.2f} sweeps/step, "
+            f"{rec['ms_per_step']:.4f} ms/step")
+        print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,6 +279,9 @@ def main():
                     help="steps of the 64-instance batched comparison (0 skips it)")
     ap.add_argument("--tiling", default=None,
                     help="rows,chunk,streaming,fused[,persistent]: set the stencil tiling instead of tdgl_autotune")
+    ap.add_argument("--study", choices=["jacobi"], default=None,
+                    help="instead of the benchmark line, run the Jacobi iteration study (2D film: iterations "
+                         "and time per step against grid size, spacing and tolerance), one JSON line per point")
     ap.add_argument("--copy-calib-gib", type=float, default=0.0,
                     help="run a plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -256,6 +295,9 @@ def main():
     from paper_1409_8340_amd import inputs, tdgl
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.study == "jacobi":
+        jacobi_study(tdgl, inputs, torch, args.steps, args.warmup)
+        return
     w = inputs.WORKLOADS[args.workload]
     N = w.nx * w.ny * w.nz
 

@@ -564,7 +564,7 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
                 d.zip = cv.take<double>((size_t)p.ny * P * p.nz);
                 h.fx_blocks = cdiv((long)p.ny * p.nz, 2L * fft_x_pairs(p.nx));
                 h.fy_blocks = p.nz * cdiv(P, fft_y_cols(p.ny));
-                h.fz_blocks = p.ny * cdiv(P, FFT_ZTK);
+                h.fz_blocks = p.nz <= FFT_ZSERIAL ? cdiv(p.ny * P, 256) : p.ny * cdiv(P, FFT_ZTK);
             }
             part_cap = std::max(part_cap, h.mg_blocks[0]);
         }

@@ -357,12 +357,104 @@ constexpr int ZTK = FFT_ZTK;
 constexpr int ZPAD = ZTK + 1;  // LDS row stride (float2): spreads the column reads over banks
 __host__ __device__ size_t fft_z_lds(int nz) { return (size_t)nz * ZPAD * sizeof(float2); }
 
+// Thin boxes (nz <= FFT_ZSERIAL, e.g. a film of one plane): the cost of the
+// scan is per system, not per row, so here one lane takes one (kx, ky)
+// system, with consecutive lanes on consecutive kx (coalesced rows), and runs
+// Thomas' two sweeps with the stored pivots in registers.
+__device__ __forceinline__ void zsolve_lane(const Inst &I, int lb) {
+    const int nx = I.nx, ny = I.ny, nz = I.nz, P = nx / 2 + 1;
+    const int col = lb * ZS_THREADS + threadIdx.x;
+    if (col >= ny * P) return;
+    const int ky = col / P, kx = col - ky * P;
+    const size_t zstride = (size_t)ny * I.sp;
+    float2 *spec = I.spec + (size_t)ky * I.sp + kx;
+    const double *ipc = I.zip + (size_t)col * nz;
+    const double cz = I.cz;
+    const double scale = 1.0 / ((double)nx * (double)ny);
+    const bool singular = (kx == 0 && ky == 0);
+    double yr[FFT_ZSERIAL], yi[FFT_ZSERIAL];
+#pragma unroll
+    for (int k = 0; k < FFT_ZSERIAL; ++k) {
+        const float2 v = k < nz ? spec[(size_t)k * zstride] : make_float2(0.f, 0.f);
+        yr[k] = v.x;
+        yi[k] = v.y;
+    }
+    // weighted mean over z (1/2 on the two end rows of an open axis)
+    auto wmean = [&](double &mr, double &mi) {
+        double sr = 0.0, si = 0.0, sw = 0.0;
+#pragma unroll
+        for (int k = 0; k < FFT_ZSERIAL; ++k)
+            if (k < nz) {
+                const double wk = (nz > 1 && (k == 0 || k == nz - 1)) ? 0.5 : 1.0;
+                sr += wk * yr[k];
+                si += wk * yi[k];
+                sw += wk;
+            }
+        mr = sr / sw;
+        mi = si / sw;
+    };
+    if (singular) {
+        // project the right side onto the range and pin row 0
+        double mr, mi;
+        wmean(mr, mi);
+#pragma unroll
+        for (int k = 0; k < FFT_ZSERIAL; ++k) {
+            yr[k] -= mr;
+            yi[k] -= mi;
+        }
+        yr[0] = 0.0;
+        yi[0] = 0.0;
+    }
+    double ur = 0.0, ui = 0.0;
+#pragma unroll
+    for (int k = 0; k < FFT_ZSERIAL; ++k)
+        if (k < nz) {
+            double a, cc;
+            zrow(k, nz, cz, singular, a, cc);
+            const double ip = ipc[k];
+            const double Ak = -a * ip, s = ip * scale;
+            ur = Ak * ur + s * yr[k];
+            ui = Ak * ui + s * yi[k];
+            yr[k] = ur;
+            yi[k] = ui;
+        }
+    double xr = 0.0, xi = 0.0;
+#pragma unroll
+    for (int k = FFT_ZSERIAL - 1; k >= 0; --k)
+        if (k < nz) {
+            double a, cc;
+            zrow(k, nz, cz, singular, a, cc);
+            const double Ck = -cc * ipc[k];
+            xr = Ck * xr + yr[k];
+            xi = Ck * xi + yi[k];
+            yr[k] = xr;
+            yi[k] = xi;
+        }
+    if (singular) {
+        // shift the constant mode to zero weighted mean
+        double mr, mi;
+        wmean(mr, mi);
+#pragma unroll
+        for (int k = 0; k < FFT_ZSERIAL; ++k) {
+            yr[k] -= mr;
+            yi[k] -= mi;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < FFT_ZSERIAL; ++k)
+        if (k < nz) spec[(size_t)k * zstride] = make_float2((float)yr[k], (float)yi[k]);
+}
+
 __global__ __launch_bounds__(ZS_THREADS) void k_fft_zsolve(const Inst *__restrict__ insts,
                                                             const int *__restrict__ prefix,
                                                             int ninst) {
     extern __shared__ float2 tile[];
     const int ii = find_inst(prefix, ninst, blockIdx.x);
     const Inst &I = insts[ii];
+    if (I.nz <= FFT_ZSERIAL) {
+        zsolve_lane(I, blockIdx.x - prefix[ii]);
+        return;
+    }
     const int nx = I.nx, ny = I.ny, nz = I.nz, P = nx / 2 + 1, sp = I.sp;
     const int ntk = (P + ZTK - 1) / ZTK;
     const int lb = blockIdx.x - prefix[ii];

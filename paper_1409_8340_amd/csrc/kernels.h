@@ -63,6 +63,7 @@ __host__ __device__ int fft_pitch(int nx);
 __host__ __device__ size_t fft_z_lds(int nz);
 constexpr int FFT_ZTK = 32;     // kx columns per work-group of the z solve
 constexpr int FFT_ZMAX = 256;   // largest nz of the spectral path
+constexpr int FFT_ZSERIAL = 16; // up to this nz one lane solves a whole z system (no wavefront scan)
 constexpr int FFT_MAXN = 8192;  // points per work-group of the x and y passes
 constexpr int FFT_XY_THREADS = 1024;  // threads per work-group of the y passes
 constexpr int FFT_X_THREADS = 256;    // threads per work-group of the x passes

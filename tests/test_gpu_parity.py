@@ -238,6 +238,9 @@ def test_autotune_keeps_state_and_results(tmp_path):
     ((96, 48, 12), (False, False, True), 0),    # spectral, radix 3
     ((40, 30, 9), (False, False, True), 0),     # spectral, radix 5 / odd sizes
     ((32, 32, 1), (False, False, True), 0),     # spectral, one-node z
+    ((16, 24, 16), (False, False, True), 0),    # spectral, the deepest box solved one system per lane
+    ((64, 48, 17), (False, False, True), 0),    # spectral, z systems by wavefront scans
+    ((32, 20, 130), (False, False, True), 0),   # spectral, several z rows per lane of the scan
     ((64, 64, 16), (False, False, True), 1),    # multigrid on the same box
     ((48, 33, 17), (False, True, True), 0),     # open y: multigrid fallback
     ((32, 32, 8), (False, False, False), 0),    # periodic z: multigrid fallback
