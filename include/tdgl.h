@@ -180,6 +180,29 @@ tdgl_status tdgl_quantize_field(const tdgl_params *p, double Bx, double Bz,
 tdgl_status tdgl_set_field(tdgl_ctx *ctx, int inst, double Bx, double Bz, int quantize,
                            double *Bx_eff, double *Bz_eff);
 
+/* Rounding for a field in the yz plane (Eq. B_yz): Bz = 2 pi n_z / (Lx Ly)
+ * if x and y are periodic; By unchanged (it is only allowed with an open z
+ * axis, which imposes no quantisation). */
+tdgl_status tdgl_quantize_field_yz(const tdgl_params *p, double By, double Bz,
+                                   double *By_eff, double *Bz_eff);
+
+/* Sets a uniform field in the yz plane, B = (0, By, Bz) (Eq. B_yz), and
+ * rebuilds the link tables.  The current stays along x.  The vector
+ * potential is A = (-y Bz + z By, 0, 0): every link variable but the x link
+ * is 1, the x link of node (i, j, k) is exp(i hx (K + Bz j hy - By k hz)),
+ * and the periodic y seam carries psi_{i,-1,k} = exp(i xbar_i Ly Bz)
+ * psi_{i,ny-1,k}, xbar_i = i hx - Lx/2.  This is the paper's field in
+ * another gauge: psi~ here relates to psi~ in the gauge of Eq. A_yz (x
+ * quasi-periodic, Sec. 3.3.1) by psi_paper = exp(i (j hy Bz - k hz By)
+ * xbar_i) psi, and every gauge-invariant quantity (|psi|^2, currents, mu~,
+ * E, F) is the same.  By != 0 requires an open z axis (TDGL_EINVAL
+ * otherwise).  A context holding a yz-plane field runs single Jacobi sweeps
+ * (two-sweep and persistent tilings are switched off and refused) and has
+ * no adjoint (tdgl_voltage_grad returns TDGL_EINVAL).  tdgl_set_field
+ * returns the instance to the xz plane.  quantize as for tdgl_set_field. */
+tdgl_status tdgl_set_field_yz(tdgl_ctx *ctx, int inst, double By, double Bz, int quantize,
+                              double *By_eff, double *Bz_eff);
+
 /* Sets the applied current density J_x,ext (Eq. J_external).  Requires a
  * driven instance unless J_ext == 0. */
 tdgl_status tdgl_set_current(tdgl_ctx *ctx, int inst, double J_ext);

@@ -43,8 +43,36 @@ def link(grid, axis, i, j, k, Bx, Bz, K):
     return 1.0 + 0j
 
 
+def link_yz(grid, axis, i, j, k, By, Bz, K):
+    """Link on the edge from node (i,j,k) to its +axis neighbour for the
+    yz-plane field, written from Eq. link_variables for
+    A~ = xbar [0, Bz, -By] - [K, 0, 0] (Eq. A_yz): U_x = exp(-i hx A~_x),
+    U_y = exp(-i hy A~_y), U_z = exp(-i hz A~_z), and on the x wrap edge the
+    conjugate phase jump conj(P_{j,k}) of the yz case of Sec. 3.3.1."""
+    Lx = grid.nx * grid.hx if not grid.open_[0] else (grid.nx - 1) * grid.hx
+    xbar = i * grid.hx - Lx / 2.0
+    if axis == 0:
+        U = np.exp(-1j * grid.hx * (-K))
+        if i == grid.nx - 1 and not grid.open_[0]:
+            P = np.exp(1j * (-j * grid.hy * Lx * Bz + k * grid.hz * Lx * By))
+            U = U * np.conj(P)
+        return U
+    if axis == 1:
+        return np.exp(-1j * grid.hy * (xbar * Bz))
+    return np.exp(-1j * grid.hz * (-xbar * By))
+
+
+def laplacian_matrix_yz(grid, By, Bz, K):
+    """Dense covariant Laplacian for the yz-plane field (Eq. LaplUV_yz)."""
+    return _laplacian(grid, lambda a, i, j, k: link_yz(grid, a, i, j, k, By, Bz, K))
+
+
 def laplacian_matrix(grid, Bx, Bz, K):
     """Dense matrix of the covariant Laplacian with all boundary forms."""
+    return _laplacian(grid, lambda a, i, j, k: link(grid, a, i, j, k, Bx, Bz, K))
+
+
+def _laplacian(grid, linkf):
     N = grid.N
     L = np.zeros((N, N), dtype=np.complex128)
     for k in range(grid.nz):
@@ -61,11 +89,11 @@ def laplacian_matrix(grid, Bx, Bz, K):
                     fwd = pos[a] + 1
                     bwd = pos[a] - 1
                     # forward neighbour, link on edge m -> m+a
-                    U_f = link(grid, a, *pos, Bx, Bz, K)
+                    U_f = linkf(a, *pos)
                     # backward neighbour, conj of the link on edge m-a -> m
                     pb = list(pos)
                     pb[a] = bwd % n
-                    U_b = np.conj(link(grid, a, *pb, Bx, Bz, K))
+                    U_b = np.conj(linkf(a, *pb))
                     pf = list(pos)
                     pf[a] = fwd % n
                     if op and pos[a] == 0:

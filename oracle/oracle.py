@@ -170,6 +170,58 @@ def landau_links(grid: Grid, Bx: float, Bz: float, K: float):
     return (np.ascontiguousarray(lx), np.ascontiguousarray(ly), np.ascontiguousarray(lz))
 
 
+def quantize_field_yz(grid: Grid, By: float, Bz: float):
+    """Rounding for the yz-plane field (Sec. 3.3.1, "Implications for the
+    magnetic field", applied to the x seam of the yz gauge): the phase jump
+    P_{j,k} must be periodic in j and k, so Bz = 2 pi n_z / (Lx Ly) when x
+    and y are both periodic and By = 2 pi n_y / (Lx Lz) when x and z are."""
+    Lx, Ly, Lz = grid.length(0), grid.length(1), grid.length(2)
+    if not grid.open_[0] and not grid.open_[1]:
+        Bz = 2 * np.pi * np.round(Bz * Lx * Ly / (2 * np.pi)) / (Lx * Ly)
+    if not grid.open_[0] and not grid.open_[2]:
+        By = 2 * np.pi * np.round(By * Lx * Lz / (2 * np.pi)) / (Lx * Lz)
+    return float(By), float(Bz)
+
+
+def landau_links_yz(grid: Grid, By: float, Bz: float, K: float):
+    """Link variables for the yz-plane field (Eq. B_yz) in the gauge of
+    Eq. A_yz, A = xbar [0, Bz, -By], with the current phase K on the x
+    links (Eq. link_variables with the index i, Eq. LaplUV_yz):
+
+      x links: exp(+i hx K), except the wrap edge i = nx-1 -> 0 of a
+               periodic x axis, which also carries conj(P_{j,k}),
+               P_{j,k} = exp(i (-j hy Lx Bz + k hz Lx By))  (Sec. 3.3.1,
+               "Magnetic field in yz plane"), so that
+               psi_{-1,j,k} = P_{j,k} psi_{nx-1,j,k};
+      y links: exp(-i hy Bz xbar_i);
+      z links: exp(+i hz By xbar_i);
+
+    reading: xbar_i = i hx - Lx/2 with Lx the system size of Sec. 3; the
+    index typos of the printed x-boundary formulas are read as corrected.
+    """
+    nz, ny, nx = grid.shape
+    Lx = grid.length(0)
+    i = np.arange(nx, dtype=np.float64)
+    xbar = i * grid.hx - Lx / 2.0
+    lx = np.full(grid.shape, np.exp(1j * grid.hx * K), dtype=np.complex128)
+    if not grid.open_[0]:
+        j = np.arange(ny, dtype=np.float64)[None, :]
+        k = np.arange(nz, dtype=np.float64)[:, None]
+        P = np.exp(1j * (-j * grid.hy * Lx * Bz + k * grid.hz * Lx * By))
+        lx[:, :, nx - 1] = lx[:, :, nx - 1] * np.conj(P)
+    ly = np.broadcast_to(np.exp(-1j * grid.hy * Bz * xbar)[None, None, :], grid.shape).astype(np.complex128)
+    lz = np.broadcast_to(np.exp(1j * grid.hz * By * xbar)[None, None, :], grid.shape).astype(np.complex128)
+    return (np.ascontiguousarray(lx), np.ascontiguousarray(ly), np.ascontiguousarray(lz))
+
+
+def base_links_of(grid: Grid, p) -> tuple:
+    """Links at K = 0 of the field in p: the xz-plane gauge (Eq. A_xz) or,
+    for p.plane == "yz", the yz-plane gauge (Eq. A_yz)."""
+    if getattr(p, "plane", "xz") == "yz":
+        return landau_links_yz(grid, p.By, p.Bz, 0.0)
+    return landau_links(grid, p.Bx, p.Bz, 0.0)
+
+
 def rewind_K(K: float, hx: float) -> float:
     """Phase rewind K -> K - (2 pi / hx) floor(K hx / 2 pi) (Sec. 2.2).
 
@@ -412,6 +464,8 @@ class Params:
     """
     Bx: float = 0.0
     Bz: float = 0.0
+    By: float = 0.0          # yz-plane field (plane == "yz")
+    plane: str = "xz"        # "xz": Eq. B_xz / A_xz; "yz": Eq. B_yz / A_yz
     J_ext: float = 0.0
     u: float = 1.0
     dt: float = 0.1
@@ -492,7 +546,7 @@ def step(grid: Grid, p: Params, eps: np.ndarray, st: State, in_window: bool = Tr
     keeps u, and K advances in real time dt.
     """
     ht = p.dt / p.u
-    base = base_links if base_links is not None else landau_links(grid, p.Bx, p.Bz, 0.0)
+    base = base_links if base_links is not None else base_links_of(grid, p)
     links = with_K(base, grid.hx, st.K)
     mu = st.mu if p.driven else None
     b, d = assemble(grid, links, st.psi, eps, mu, p.u, ht)
@@ -525,7 +579,7 @@ def run(grid, p, eps, st, nsteps, window_begin=0, base_links=None):
     base_links: links at K = 0 (default: Landau gauge of the field in p)."""
     n0 = st.n
     if base_links is None:
-        base_links = landau_links(grid, p.Bx, p.Bz, 0.0)
+        base_links = base_links_of(grid, p)
     for s in range(nsteps):
         step(grid, p, eps, st, in_window=(st.n - n0) >= window_begin, base_links=base_links)
     return st

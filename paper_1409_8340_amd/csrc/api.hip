@@ -330,6 +330,8 @@ struct InstHost {
     int mg_blocks[kMaxLevels] = {0};
     int fx_blocks = 0, fy_blocks = 0, fz_blocks = 0;  // spectral Poisson passes
     double Bx = 0, Bz = 0, J = 0;
+    double By = 0;
+    bool yz = false;  // field in the yz plane (tdgl_set_field_yz)
 };
 
 // Stencil tiling of one instance: work-groups of 64 x 4 rows columns
@@ -395,6 +397,7 @@ struct tdgl_ctx {
     bool fx_p2 = true, fy_p2 = true;  // every spectral instance has power-of-two nx (ny)
     bool fx_long = false;             // some spectral instance has nx > FFT_X_PTS
     bool noisy = false;               // some instance has a Langevin term
+    bool any_yz = false;              // some instance has a yz-plane field
     bool any_fft = false, any_mg = false;
     bool any_driven = false;
     int max_iter = 1, max_cycles = 1;
@@ -489,6 +492,7 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
         d.ux = cv.take<float2>(p.ny);
         d.uz = cv.take<float2>(p.ny);
         d.P = cv.take<float2>((size_t)p.nx * p.nz);
+        d.wz = cv.take<float2>(p.nz);
         d.btile = cv.take<int>((size_t)cdiv(p.nx, TX) * cdiv(p.ny, 4));  // room for any rows per thread
         d.st = cv.take<DevState>(1);
         d.res = res ? res + i : nullptr;
@@ -750,12 +754,23 @@ template <int MODE, int R>
 void launch_stencil_r(tdgl_ctx *c, int l, const float2 *in, float2 *out) {
     constexpr bool can_nt = (MODE == MODE_SWEEP || is_first_mode(MODE));
     unsigned long long *pub = (MODE == MODE_SWEEP && c->pub_on && l > 0) ? c->d_pub : nullptr;
-    if (can_nt && c->nt)
-        hipLaunchKernelGGL((k_stencil<MODE, R, can_nt>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst,
+    // a yz-plane field takes the variant with per-plane x links (the
+    // adjoint's NS mode has none: the adjoint rejects such contexts)
+    constexpr bool can_yz = MODE != MODE_NS;
+    if (can_yz && c->any_yz) {
+        if (can_nt && c->nt)
+            hipLaunchKernelGGL((k_stencil<MODE, R, can_nt, can_yz>), dim3(c->tot_st), dim3(WG), 0, c->stream,
+                               c->d_inst, c->d_pref_st, c->n, l, in, out, pub, c->pub_seq);
+        else
+            hipLaunchKernelGGL((k_stencil<MODE, R, false, can_yz>), dim3(c->tot_st), dim3(WG), 0, c->stream,
+                               c->d_inst, c->d_pref_st, c->n, l, in, out, pub, c->pub_seq);
+    } else if (can_nt && c->nt) {
+        hipLaunchKernelGGL((k_stencil<MODE, R, can_nt, false>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst,
                            c->d_pref_st, c->n, l, in, out, pub, c->pub_seq);
-    else
-        hipLaunchKernelGGL((k_stencil<MODE, R, false>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst,
+    } else {
+        hipLaunchKernelGGL((k_stencil<MODE, R, false, false>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst,
                            c->d_pref_st, c->n, l, in, out, pub, c->pub_seq);
+    }
 }
 // One two-sweep pass (l odd; l = -1: timing pass).
 template <int R>
@@ -1148,6 +1163,22 @@ void drop_graph(tdgl_ctx *ctx) {
     ctx->graph_budget = 0;
 }
 
+// Recompute whether some instance has a yz-plane field.  The stencil passes
+// then take their per-plane x-link variant and single sweeps (the two-sweep
+// and persistent forms have no such variant), and a captured step graph is
+// dropped because its launches change.
+void update_any_yz(tdgl_ctx *ctx) {
+    bool any = false;
+    for (const auto &h : ctx->inst) any = any || h.yz;
+    if (any != ctx->any_yz) drop_graph(ctx);
+    ctx->any_yz = any;
+    if (any && (ctx->fused || ctx->persist)) {
+        drop_graph(ctx);
+        ctx->fused = false;
+        ctx->persist = false;
+    }
+}
+
 // One whole step of every instance as a fixed launch sequence with no host
 // synchronisation, for graph capture: the assemble kernel and budget - 1
 // sweep launches (a launch whose instance has converged or reached its cap
@@ -1330,6 +1361,51 @@ tdgl_status tdgl_quantize_field(const tdgl_params *p, double Bx, double Bz, doub
     return TDGL_OK;
 }
 
+tdgl_status tdgl_quantize_field_yz(const tdgl_params *p, double By, double Bz, double *By_eff, double *Bz_eff) {
+    if (!p || !By_eff || !Bz_eff) return fail(TDGL_EINVAL, "null argument");
+    const double twopi = 6.283185307179586476925286766559;
+    auto len = [](int n, double h, int bc) { return bc == TDGL_OPEN ? (n - 1) * h : n * h; };
+    const double Lx = len(p->nx, p->hx, p->bc[0]), Ly = len(p->ny, p->hy, p->bc[1]);
+    if (p->bc[0] == TDGL_PERIODIC && p->bc[1] == TDGL_PERIODIC)
+        Bz = twopi * std::nearbyint(Bz * Lx * Ly / twopi) / (Lx * Ly);
+    *By_eff = By;
+    *Bz_eff = Bz;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_set_field_yz(tdgl_ctx *ctx, int inst, double By, double Bz, int quantize, double *By_eff,
+                              double *Bz_eff) {
+    tdgl_status s = check_ctx(ctx, inst);
+    if (s) return s;
+    if (!std::isfinite(By) || !std::isfinite(Bz)) return fail(TDGL_EINVAL, "field must be finite");
+    InstHost &h = ctx->inst[inst];
+    if (By != 0.0 && h.p.bc[2] != TDGL_OPEN)
+        return fail(TDGL_EINVAL, "a yz-plane field with By != 0 needs an open z axis");
+    double qy, qz;
+    tdgl_quantize_field_yz(&h.p, By, Bz, &qy, &qz);
+    if (!quantize) {
+        if (std::fabs(Bz - qz) > 1e-9 * std::max(1.0, std::fabs(qz)))
+            return fail(TDGL_EINVAL,
+                        "Bz = %.9g is not a whole number of flux quanta through the periodic xy cross section "
+                        "(nearest: %.9g); pass quantize=1", Bz, qz);
+        qz = Bz;
+    }
+    h.Bx = 0.0;
+    h.By = qy;
+    h.Bz = qz;
+    h.yz = true;
+    update_any_yz(ctx);
+    hipLaunchKernelGGL(k_state_set, dim3(1), dim3(1), 0, ctx->stream, ctx->d_inst, inst, 8, 0.0);
+    hipLaunchKernelGGL(k_state_set, dim3(1), dim3(1), 0, ctx->stream, ctx->d_inst, inst, 9, qz);
+    hipLaunchKernelGGL(k_state_set, dim3(1), dim3(1), 0, ctx->stream, ctx->d_inst, inst, 13, qy);
+    hipLaunchKernelGGL(k_state_set, dim3(1), dim3(1), 0, ctx->stream, ctx->d_inst, inst, 14, 1.0);
+    hipLaunchKernelGGL(k_links, dim3(1), dim3(256), 0, ctx->stream, ctx->d_inst + inst, 0);
+    LAUNCHCHK();
+    if (By_eff) *By_eff = qy;
+    if (Bz_eff) *Bz_eff = qz;
+    return TDGL_OK;
+}
+
 tdgl_status tdgl_set_field(tdgl_ctx *ctx, int inst, double Bx, double Bz, int quantize, double *Bx_eff,
                            double *Bz_eff) {
     tdgl_status s = check_ctx(ctx, inst);
@@ -1348,8 +1424,13 @@ tdgl_status tdgl_set_field(tdgl_ctx *ctx, int inst, double Bx, double Bz, int qu
     }
     ctx->inst[inst].Bx = qx;
     ctx->inst[inst].Bz = qz;
+    ctx->inst[inst].By = 0.0;
+    ctx->inst[inst].yz = false;
+    update_any_yz(ctx);
     hipLaunchKernelGGL(k_state_set, dim3(1), dim3(1), 0, ctx->stream, ctx->d_inst, inst, 8, qx);
     hipLaunchKernelGGL(k_state_set, dim3(1), dim3(1), 0, ctx->stream, ctx->d_inst, inst, 9, qz);
+    hipLaunchKernelGGL(k_state_set, dim3(1), dim3(1), 0, ctx->stream, ctx->d_inst, inst, 13, 0.0);
+    hipLaunchKernelGGL(k_state_set, dim3(1), dim3(1), 0, ctx->stream, ctx->d_inst, inst, 14, 0.0);
     // rebuild the tables of this instance only: launch over all with a
     // single-instance view (the kernel reads the descriptor by block index)
     hipLaunchKernelGGL(k_links, dim3(1), dim3(256), 0, ctx->stream, ctx->d_inst + inst, 0);
@@ -1775,8 +1856,8 @@ tdgl_status apply_tiling(tdgl_ctx *ctx, const Tiling &t) {
     drop_graph(ctx);
     ctx->rows = t.rows;
     ctx->nt = t.nt != 0;
-    ctx->fused = t.fused != 0;
-    ctx->persist = t.persist != 0 && !ctx->fused;
+    ctx->fused = t.fused != 0 && !ctx->any_yz;
+    ctx->persist = t.persist != 0 && !ctx->fused && !ctx->any_yz;
     for (auto &h : ctx->inst) set_tiling(h, t.rows, t.chunk);
     return upload_tiling(ctx);
 }
@@ -1787,8 +1868,8 @@ std::string tiling_key(const tdgl_ctx *ctx) {
     std::string k;
     char buf[96];
     for (const auto &h : ctx->inst) {
-        snprintf(buf, sizeof buf, "%dx%dx%d/%d%d%d/%d;", h.p.nx, h.p.ny, h.p.nz, h.p.bc[0], h.p.bc[1], h.p.bc[2],
-                 h.p.driven);
+        snprintf(buf, sizeof buf, "%dx%dx%d/%d%d%d/%d%s;", h.p.nx, h.p.ny, h.p.nz, h.p.bc[0], h.p.bc[1], h.p.bc[2],
+                 h.p.driven, h.yz ? "/yz" : "");
         k += buf;
     }
     return k;
@@ -1852,7 +1933,8 @@ tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *ch
         const int chunks[] = {0, 4, 8, 16, 32, 64};
         const int rows[] = {1, 2, 4};
         best_us = 1e300;
-        for (int fu = 0; fu < 2; ++fu)
+        // (a yz-plane field runs single sweeps only)
+        for (int fu = 0; fu < (ctx->any_yz ? 1 : 2); ++fu)
         for (int nt = 0; nt < 2; ++nt)
         for (int r : rows)
             for (int c : chunks) {
@@ -1885,7 +1967,7 @@ tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *ch
             }
         // the best single-sweep tiling as one persistent launch: chosen when
         // its sweeps, barrier included, beat separate launches by 10 %
-        if (!best.fused) {
+        if (!best.fused && !ctx->any_yz) {
             tdgl_status e = apply_tiling(ctx, best);
             if (e) return e;
             const int K = 16;
@@ -1940,6 +2022,8 @@ tdgl_status tdgl_set_tiling(tdgl_ctx *ctx, const tdgl_tiling *t) {
         (t->persistent != 0 && t->persistent != 1))
         return fail(TDGL_EINVAL, "streaming, fused and persistent must be 0 or 1");
     if (t->fused && t->persistent) return fail(TDGL_EINVAL, "persistent solves use single sweeps (fused = 0)");
+    if (ctx->any_yz && (t->fused || t->persistent))
+        return fail(TDGL_EINVAL, "a context with a yz-plane field runs single sweeps (fused = persistent = 0)");
     HIPCHK(hipStreamSynchronize(ctx->stream));
     Tiling s;
     s.rows = t->rows;
@@ -2066,6 +2150,7 @@ tdgl_status tdgl_voltage_grad(tdgl_ctx *ctx, int nsteps, int window_begin, int c
     if (ctx->n != 1) return fail(TDGL_EINVAL, "tdgl_voltage_grad needs a context with one instance");
     const InstHost &h = ctx->inst[0];
     if (!h.p.driven) return fail(TDGL_EINVAL, "the voltage needs a driven instance (driven = 1)");
+    if (h.yz) return fail(TDGL_EINVAL, "the adjoint supports the xz-plane field only");
     if (nsteps < 1 || window_begin < 0 || window_begin >= nsteps || ckpt_every < 1)
         return fail(TDGL_EINVAL, "need nsteps >= 1, 0 <= window_begin < nsteps, ckpt_every >= 1");
     if (!grad || !vbar) return fail(TDGL_EINVAL, "null output");

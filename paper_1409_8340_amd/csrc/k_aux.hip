@@ -1,6 +1,7 @@
 // k_aux.hip -- link tables, reductions, the K update and small state
 // kernels of libtdgl.
 #include "kernels.h"
+#include "stencil.h"
 
 namespace tdgl {
 
@@ -14,27 +15,48 @@ __device__ __forceinline__ float2 expi(double phi) {
     return make_float2((float)c, (float)s);
 }
 
-// Link tables of one instance for the xz-plane field in the Landau gauge
-// (Eq. A_xz, Eq. link_variables, Sec. 3.3.1):
+// y offset of the x links: ybar_j = j hy - y_ref with y_ref = Ly/2 for the
+// xz-plane field (Eq. A_xz) and 0 for the yz-plane field (see k_links).
+__device__ __forceinline__ double link_yref(const Inst &I, const DevState *st) {
+    const double Ly = I.per[1] ? I.ny * I.hy : (I.ny - 1) * I.hy;
+    return st->yz ? 0.0 : 0.5 * Ly;
+}
+
+// Link tables of one instance.  xz-plane field, Landau gauge (Eq. A_xz,
+// Eq. link_variables, Sec. 3.3.1):
 //   ux[j] = exp(+i hx (K + Bz ybar_j)),  uz[j] = exp(-i hz Bx ybar_j),
-//   P[k*nx + i] = exp(i (i hx Ly Bz - k hz Ly Bx)),
+//   P[k*nx + i] = exp(i (i hx Ly Bz - k hz Ly Bx)),  wz[k] = 1,
 // with ybar_j = j hy - Ly/2 and Ly the system size along y.
+// yz-plane field (Eq. B_yz): the vector potential A = (-y Bz + z By, 0, 0)
+// (curl A = (0, By, Bz)), which puts the whole field on the x links:
+//   ux[j] = exp(+i hx (K + Bz j hy)),  wz[k] = exp(-i hx By k hz),
+//   uz[j] = 1,  P[k*nx + i] = exp(i xbar_i Ly Bz),  xbar_i = i hx - Lx/2,
+// so the x link of node (i, j, k) is ux[j] wz[k].  It differs from the
+// paper's gauge of Eq. A_yz by the gauge transformation
+//   psi_paper = exp(i (j hy Bz - k hz By) xbar_i) psi
+// (same flux through every plaquette and the same phase around every
+// periodic loop; z must be open when By != 0).
 // One work-group per instance (grid = ninst); `which` = 1 refreshes ux only.
 __global__ void k_links(const Inst *__restrict__ insts, int which) {
     const Inst &I = insts[blockIdx.x];
     const DevState *st = I.st;
     const double Ly = I.per[1] ? I.ny * I.hy : (I.ny - 1) * I.hy;
-    const double K = I.driven ? st->K : 0.0, Bx = st->Bx, Bz = st->Bz;
+    const double Lx = I.per[0] ? I.nx * I.hx : (I.nx - 1) * I.hx;
+    const double K = I.driven ? st->K : 0.0, Bx = st->Bx, Bz = st->Bz, By = st->By;
+    const bool yz = st->yz != 0;
+    const double yref = link_yref(I, st);
     for (int j = threadIdx.x; j < I.ny; j += blockDim.x) {
-        const double yb = j * I.hy - 0.5 * Ly;
+        const double yb = j * I.hy - yref;
         I.ux[j] = expi(I.hx * (K + Bz * yb));
-        if (which == 0) I.uz[j] = expi(-I.hz * Bx * yb);
+        if (which == 0) I.uz[j] = yz ? make_float2(1.f, 0.f) : expi(-I.hz * Bx * yb);
     }
     if (which == 0) {
+        for (int k = threadIdx.x; k < I.nz; k += blockDim.x)
+            I.wz[k] = yz ? expi(-I.hx * By * (k * I.hz)) : make_float2(1.f, 0.f);
         const long n = (long)I.nx * I.nz;
         for (long t = threadIdx.x; t < n; t += blockDim.x) {
             const int i = (int)(t % I.nx), k = (int)(t / I.nx);
-            I.P[t] = expi(i * I.hx * Ly * Bz - k * I.hz * Ly * Bx);
+            I.P[t] = yz ? expi((i * I.hx - 0.5 * Lx) * Ly * Bz) : expi(i * I.hx * Ly * Bz - k * I.hz * Ly * Bx);
         }
     }
 }
@@ -115,22 +137,28 @@ __global__ __launch_bounds__(256) void k_jav_partial(const Inst *__restrict__ in
     const float2 *__restrict__ psi = I.psi[I.st->cur];
     double acc = 0.0;
     const int nx = I.nx, ny = I.ny;
-    // cell m = base + c 256 + tid: its x index i and y index j follow from
-    // one division for c = 0 and then by stepping 256 cells at a time
+    const bool yz = I.st->yz != 0;
+    // cell m = base + c 256 + tid: its x, y and z indices follow from one
+    // division for c = 0 and then by stepping 256 cells at a time
     int m = (int)((long)lb * 256 * JAV_CPT) + (int)threadIdx.x;
-    int i = m % nx, j = (m / nx) % ny;
+    int i = m % nx, j = (m / nx) % ny, k = m / (nx * ny);
     for (int c = 0; c < JAV_CPT; ++c) {
         if (m < I.N) {
             const int mp = (i == nx - 1) ? m - (nx - 1) : m + 1;
             const float2 a = psi[m], p = psi[mp];
-            const float2 up = cmul(I.ux[j], p);
+            float2 u = I.ux[j];
+            if (yz) u = xcmul(u, I.wz[k]);
+            const float2 up = cmul(u, p);
             acc += (double)(a.x * up.y - a.y * up.x);
         }
         m += 256;
         i += 256;
         while (i >= nx) {
             i -= nx;
-            if (++j == ny) j = 0;
+            if (++j == ny) {
+                j = 0;
+                ++k;
+            }
         }
     }
     const double s = wg_sum<256>(acc, red);
@@ -170,9 +198,9 @@ __global__ __launch_bounds__(256) void k_kupdate(const Inst *__restrict__ insts,
         Ks = K;
     }
     __syncthreads();
-    const double Ly = I.per[1] ? I.ny * I.hy : (I.ny - 1) * I.hy;
+    const double yref = link_yref(I, st);
     for (int j = threadIdx.x; j < I.ny; j += blockDim.x) {
-        const double yb = j * I.hy - 0.5 * Ly;
+        const double yb = j * I.hy - yref;
         I.ux[j] = expi(I.hx * (Ks + st->Bz * yb));
     }
 }
@@ -282,6 +310,8 @@ __global__ void k_state_set(const Inst *__restrict__ insts, int inst, int field,
         case 10: st->mu_mean = v; break;
         case 11: st->in_window = (int)v; break;
         case 12: st->cur = (int)v; break;
+        case 13: st->By = v; break;
+        case 14: st->yz = (int)v; break;
         default: break;
     }
 }

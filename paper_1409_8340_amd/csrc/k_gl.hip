@@ -34,7 +34,7 @@ namespace tdgl {
 // solve (tiles in a grid-stride loop).  pub (sweeps of a host-driven solve,
 // else null): the work-group of each instance's first tile hands the row
 // l - 1 it has read to the host, tagged seq.
-template <int MODE, int R, bool NT>
+template <int MODE, int R, bool NT, bool YZ>
 __device__ __forceinline__ void stencil_tile(const Inst *__restrict__ insts, const int *__restrict__ prefix,
                                              int ninst, int l, const float2 *ext_in, float2 *ext_out, int b,
                                              unsigned long long *pub, unsigned seq) {
@@ -130,7 +130,7 @@ __device__ __forceinline__ void stencil_tile(const Inst *__restrict__ insts, con
             for (int r = 0; r < ROWS; ++r) out[r] = ld2(src, pb + (unsigned)own[r].off);
         } else {
 #pragma unroll
-            for (int r = 0; r < ROWS; ++r) out[r] = fetch(src, Pt, pb, p, nx, own[r]);
+            for (int r = 0; r < ROWS; ++r) out[r] = fetch<YZ>(src, Pt, pb, p, nx, own[r], I.wz);
         }
     };
 
@@ -141,9 +141,9 @@ __device__ __forceinline__ void stencil_tile(const Inst *__restrict__ insts, con
     own_plane(zplane(I, k0, +1), pn);
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) lds[0][1 + w * ROWS + r][1 + lane] = pc[r];
-    if (hthr) lds[0][hly][hlx] = fetch(src, Pt, (unsigned)k0 * NXY, k0, nx, hs);
+    if (hthr) lds[0][hly][hlx] = fetch<YZ>(src, Pt, (unsigned)k0 * NXY, k0, nx, hs, I.wz);
     float2 hv = make_float2(0.f, 0.f);
-    if (hthr && k0 + 1 < k1) hv = fetch(src, Pt, (unsigned)(k0 + 1) * NXY, k0 + 1, nx, hs);
+    if (hthr && k0 + 1 < k1) hv = fetch<YZ>(src, Pt, (unsigned)(k0 + 1) * NXY, k0 + 1, nx, hs, I.wz);
 
     // per-plane streams of the first plane
     float2 bh[ROWS], dh[ROWS];
@@ -184,7 +184,7 @@ __device__ __forceinline__ void stencil_tile(const Inst *__restrict__ insts, con
         if (k + 1 < k1) {
             own_plane(zplane(I, k + 1, +1), pnn);
             load_streams(k + 1, bhn, dhn, epn, mun);
-            if (hthr && k + 2 < k1) hvn = fetch(src, Pt, (unsigned)(k + 2) * NXY, k + 2, nx, hs);
+            if (hthr && k + 2 < k1) hvn = fetch<YZ>(src, Pt, (unsigned)(k + 2) * NXY, k + 2, nx, hs, I.wz);
         }
         __syncthreads();  // plane k staged; the other buffer is free
         if (k + 1 < k1) {
@@ -193,6 +193,16 @@ __device__ __forceinline__ void stencil_tile(const Inst *__restrict__ insts, con
             if (hthr) lds[buf ^ 1][hly][hlx] = hv;
         }
         const bool zm = (k > 0) || zper, zp = (k < nz - 1) || zper;
+        // x links of this plane (a yz-plane field adds the factor wz[k])
+        float2 uxk[ROWS];
+        if (YZ) {
+            const float2 wk = I.wz[k];
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) uxk[r] = xcmul(ux[r], wk);
+        } else {
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) uxk[r] = ux[r];
+        }
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             const int ly = 1 + w * ROWS + r;
@@ -210,7 +220,7 @@ __device__ __forceinline__ void stencil_tile(const Inst *__restrict__ insts, con
                 const float wyn = (!I.per[1] && ny > 1 && (y == 0 || y == ny - 1)) ? 0.5f : 1.f;
                 const float wzn = (!zper && nz > 1 && (k == 0 || k == nz - 1)) ? 0.5f : 1.f;
                 double e = (double)(wxn * wyn * wzn) * (double)(-ep[r] * a2 + 0.5f * a2 * a2);
-                if (fx) e += (double)(wyn * wzn * cx) * (double)cabs2(csub(cmul(ux[r], xp), c));
+                if (fx) e += (double)(wyn * wzn * cx) * (double)cabs2(csub(cmul(uxk[r], xp), c));
                 if (fy) e += (double)(wxn * wzn * cy) * (double)cabs2(csub(yp, c));
                 if (zp) e += (double)(wxn * wyn * cz) * (double)cabs2(csub(cmul(uz[r], pn[r]), c));
                 acc += e;
@@ -218,7 +228,7 @@ __device__ __forceinline__ void stencil_tile(const Inst *__restrict__ insts, con
             }
             // off-diagonal neighbour sum NS of the covariant Laplacian
             // (Eq. LaplUV_xz), open faces doubling the inner neighbour.
-            const float2 ns = nsum(ux[r], uz[r], xm, xp, ym, yp, pm[r], pn[r], zm, zp, cx, cy, cz);
+            const float2 ns = nsum(uxk[r], uz[r], xm, xp, ym, yp, pm[r], pn[r], zm, zp, cx, cy, cz);
             if (MODE == MODE_NS) {
                 st2(nsout, m, ns);
                 continue;
@@ -279,12 +289,12 @@ __device__ __forceinline__ void stencil_tile(const Inst *__restrict__ insts, con
     }
 }
 
-template <int MODE, int R, bool NT>
+template <int MODE, int R, bool NT, bool YZ>
 __global__ __launch_bounds__(WG) void k_stencil(const Inst *__restrict__ insts,
                                                 const int *__restrict__ prefix, int ninst, int l,
                                                 const float2 *ext_in, float2 *ext_out, unsigned long long *pub,
                                                 unsigned seq) {
-    stencil_tile<MODE, R, NT>(insts, prefix, ninst, l, ext_in, ext_out, xcd_remap(blockIdx.x, gridDim.x), pub,
+    stencil_tile<MODE, R, NT, YZ>(insts, prefix, ninst, l, ext_in, ext_out, xcd_remap(blockIdx.x, gridDim.x), pub,
                               seq);
 }
 
@@ -321,25 +331,34 @@ __global__ __launch_bounds__(WG) void k_jacobi_persist(const Inst *__restrict__ 
             if (!go) break;
         }
         for (int t = blockIdx.x; t < ntiles; t += gridDim.x)
-            stencil_tile<MODE_SWEEP, R, NT>(insts, prefix, ninst, timing ? -1 : l, nullptr, nullptr,
+            stencil_tile<MODE_SWEEP, R, NT, false>(insts, prefix, ninst, timing ? -1 : l, nullptr, nullptr,
                                             xcd_remap(t, ntiles), nullptr, 0u);
         grid.sync();
     }
 }
 
-#define TDGL_INST(M, R, NT) \
-    template __global__ void k_stencil<M, R, NT>(const Inst *, const int *, int, int, const float2 *, float2 *, \
-                                                 unsigned long long *, unsigned);
-#define TDGL_INST_R(R)                 \
-    TDGL_INST(MODE_FIRST, R, false)    \
-    TDGL_INST(MODE_FIRST, R, true)     \
-    TDGL_INST(MODE_FIRSTN, R, false)   \
-    TDGL_INST(MODE_FIRSTN, R, true)    \
-    TDGL_INST(MODE_SWEEP, R, false)    \
-    TDGL_INST(MODE_SWEEP, R, true)     \
-    TDGL_INST(MODE_RHS, R, false)      \
-    TDGL_INST(MODE_ENERGY, R, false)   \
-    TDGL_INST(MODE_NS, R, false)
+#define TDGL_INST(M, R, NT, YZ)                                                                            \
+    template __global__ void k_stencil<M, R, NT, YZ>(const Inst *, const int *, int, int, const float2 *, float2 *, \
+                                                     unsigned long long *, unsigned);
+// YZ (a yz-plane field in the context): every mode but the adjoint's NS
+#define TDGL_INST_R(R)                      \
+    TDGL_INST(MODE_FIRST, R, false, false)  \
+    TDGL_INST(MODE_FIRST, R, true, false)   \
+    TDGL_INST(MODE_FIRSTN, R, false, false) \
+    TDGL_INST(MODE_FIRSTN, R, true, false)  \
+    TDGL_INST(MODE_SWEEP, R, false, false)  \
+    TDGL_INST(MODE_SWEEP, R, true, false)   \
+    TDGL_INST(MODE_RHS, R, false, false)    \
+    TDGL_INST(MODE_ENERGY, R, false, false) \
+    TDGL_INST(MODE_NS, R, false, false)     \
+    TDGL_INST(MODE_FIRST, R, false, true)   \
+    TDGL_INST(MODE_FIRST, R, true, true)    \
+    TDGL_INST(MODE_FIRSTN, R, false, true)  \
+    TDGL_INST(MODE_FIRSTN, R, true, true)   \
+    TDGL_INST(MODE_SWEEP, R, false, true)   \
+    TDGL_INST(MODE_SWEEP, R, true, true)    \
+    TDGL_INST(MODE_RHS, R, false, true)     \
+    TDGL_INST(MODE_ENERGY, R, false, true)
 TDGL_INST_R(1)
 TDGL_INST_R(2)
 TDGL_INST_R(4)

@@ -19,7 +19,7 @@ template <int R, bool NT>
 __global__ void k_sweep2i(const Inst *insts, const int *prefix, int ninst, int l);
 template <int R, bool NT>
 __global__ void k_jacobi_persist(const Inst *insts, const int *prefix, int ninst, int l0, int lcap, int ntiles);
-template <int MODE, int R, bool NT>
+template <int MODE, int R, bool NT, bool YZ>
 __global__ void k_stencil(const Inst *insts, const int *prefix, int ninst, int l, const float2 *ext_in,
                           float2 *ext_out, unsigned long long *pub, unsigned seq);
 

@@ -70,7 +70,7 @@ enum { SRC_PLAIN = 0, SRC_P = 1, SRC_PCONJ = 2, SRC_FAC = 3, SRC_ZERO = 4 };
 struct CellSrc {
     int off;      // element offset within a plane
     int mode;
-    int px;       // x index of the phase P_{px,k}
+    int px;       // x index of the phase P_{px,k}; SRC_FAC: 0 at x = -1, 1 at x = nx
     float2 fac;   // constant factor (open-x ghost)
 };
 
@@ -98,19 +98,30 @@ __device__ __forceinline__ CellSrc cell_src(const Inst &I, int gx, int gy) {
             if (I.per[0]) { s.off = gy * nx; s.mode = SRC_PLAIN; }
             else if (nx >= 2) {
                 const float2 u2 = xcmul(u, u);
-                s.off = gy * nx + nx - 2; s.mode = SRC_FAC; s.fac = make_float2(u2.x, -u2.y);
+                s.off = gy * nx + nx - 2; s.mode = SRC_FAC; s.fac = make_float2(u2.x, -u2.y); s.px = 1;
             }
         }
     }
     return s;
 }
 
+// YZ: the x link of plane k carries the factor wz[k] (yz-plane field), so
+// the open-x ghost factor U^2 (or its conjugate) gains wz[k]^2.
+template <bool YZ = false>
 __device__ __forceinline__ float2 fetch(const gf2 *__restrict__ src, const gf2 *__restrict__ P,
-                                        unsigned pbase, int k, int nx, const CellSrc &s) {
+                                        unsigned pbase, int k, int nx, const CellSrc &s,
+                                        const float2 *__restrict__ wz = nullptr) {
     if (s.mode == SRC_PLAIN) return ld2(src, pbase + (unsigned)s.off);
     if (s.mode == SRC_ZERO) return make_float2(0.f, 0.f);
     const float2 v = ld2(src, pbase + (unsigned)s.off);
-    if (s.mode == SRC_FAC) return xcmul(s.fac, v);
+    if (s.mode == SRC_FAC) {
+        if (YZ) {
+            float2 w2 = xcmul(wz[k], wz[k]);
+            if (s.px) w2.y = -w2.y;
+            return xcmul(xcmul(s.fac, w2), v);
+        }
+        return xcmul(s.fac, v);
+    }
     const float2 ph = ld2(P, (unsigned)k * nx + s.px);
     return s.mode == SRC_P ? xcmul(ph, v) : xcmulc(ph, v);
 }

@@ -59,6 +59,9 @@ struct DevState {
     // step statistics accumulated on the device (graph-replayed steps)
     double acc_sweeps, acc_capped, acc_mu_cycles, acc_mu_capped, acc_passes;
     int acc_sw_min, acc_sw_max;
+    double By;        // y component of a yz-plane field (quantised)
+    int yz;           // 1: the field lies in the yz plane (Eq. B_yz)
+    int pad4;
 };
 
 // Scalars of the adjoint sweep over one step (device resident).
@@ -109,6 +112,7 @@ struct Inst {
     float2 *ux;          // x links per y index: exp(i hx (K + Bz ybar_j))
     float2 *uz;          // z links per y index: exp(-i hz Bx ybar_j)
     float2 *P;           // y wrap phase per (i,k): exp(i (i hx Ly Bz - k hz Ly Bx))
+    float2 *wz;          // x-link factor per z plane: exp(-i hx By k hz) (yz field), else 1
     DevState *st;
     // Convergence words.  Work-groups reduce their maxima with atomics into
     // one of NSLOT slots (chosen by block index) placed in separate cache

@@ -101,6 +101,10 @@ _SIGS = {
     "tdgl_quantize_field": ([ctypes.POINTER(Params), ctypes.c_double, ctypes.c_double,
                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
                             ctypes.c_int),
+    "tdgl_quantize_field_yz": ([ctypes.POINTER(Params), ctypes.c_double, ctypes.c_double,
+                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "tdgl_set_field_yz": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "tdgl_set_field": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "tdgl_set_current": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_double], ctypes.c_int),
@@ -204,6 +208,12 @@ def quantize_field(p: Params, Bx: float, Bz: float):
     return bx.value, bz.value
 
 
+def quantize_field_yz(p: Params, By: float, Bz: float):
+    by, bz = ctypes.c_double(), ctypes.c_double()
+    _check(load().tdgl_quantize_field_yz(ctypes.byref(p), By, Bz, ctypes.byref(by), ctypes.byref(bz)))
+    return by.value, bz.value
+
+
 class Solver:
     """A context of one or more instances on the current torch device."""
 
@@ -253,6 +263,13 @@ class Solver:
         _check(load().tdgl_set_field(self._ctx, inst, Bx, Bz, int(quantize), ctypes.byref(bx),
                                      ctypes.byref(bz)))
         return bx.value, bz.value
+
+    def set_field_yz(self, By, Bz, inst=0, quantize=True):
+        """Field in the yz plane (tdgl_set_field_yz); returns (By, Bz) as set."""
+        by, bz = ctypes.c_double(), ctypes.c_double()
+        _check(load().tdgl_set_field_yz(self._ctx, inst, By, Bz, int(quantize), ctypes.byref(by),
+                                        ctypes.byref(bz)))
+        return by.value, bz.value
 
     def set_current(self, J, inst=0):
         _check(load().tdgl_set_current(self._ctx, inst, J))

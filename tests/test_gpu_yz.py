@@ -1,0 +1,187 @@
+"""The yz-plane field (Eq. B_yz) on the GPU against the FP64 oracle, which
+follows the paper's gauge (Eq. A_yz, x quasi-periodic).  The library stores
+psi in the gauge A = (-y Bz + z By, 0, 0); its psi relates to the paper's by
+psi_paper = exp(i chi) psi with chi = (j hy Bz - k hz By) xbar_i (the
+oracle-side pin of that equivalence is tests/test_oracle_yz.py).  Inputs go
+in transformed, outputs are compared transformed back; K, E and mu~ are
+gauge invariant and compared directly.  Tolerances as for the xz field."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1409_8340_amd import inputs, tdgl
+from tests.harness import Case, rel_maxerr
+from tests.test_oracle_yz import gauge_phase
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    tdgl.load()
+
+
+class YZCase(Case):
+    def __init__(self, *a, By=0.1, Bz=0.1, **kw):
+        super().__init__(*a, Bz=Bz, **kw)
+        self.Bx = 0.0
+        self.By, self.Bz = O.quantize_field_yz(self.grid, By, Bz)
+        self.chi = gauge_phase(self.grid, self.By, self.Bz)
+
+    def oracle_params(self, mode="exact", tol=None):
+        p = super().oracle_params(mode, tol)
+        p.Bx, p.By, p.Bz, p.plane = 0.0, self.By, self.Bz, "yz"
+        return p
+
+    def load_into(self, s, inst):
+        by, bz = s.set_field_yz(self.By, self.Bz, inst=inst, quantize=False)
+        assert by == self.By and bz == self.Bz
+        if self.driven:
+            s.set_current(self.J, inst=inst)
+        s.set_eps(torch.from_numpy(self.eps).cuda(), inst=inst)
+        g = (np.exp(-1j * self.chi) * self.psi0.astype(np.complex128)).astype(np.complex64)
+        s.set_psi(torch.from_numpy(g).cuda(), inst=inst)
+        if self.mu0 is not None:
+            s.set_mu(torch.from_numpy(self.mu0).cuda(), inst=inst)
+        if self.K0:
+            sc = s.get_scalars(inst)
+            sc["K"] = self.K0
+            s.set_scalars(sc, inst)
+
+
+def _run(c, nsteps, mode="exact"):
+    s = c.solver()
+    stats = s.step(nsteps)
+    out = dict(psi=s.get_psi().cpu().numpy(), stats=stats, sc=s.get_scalars())
+    if c.driven:
+        out["mu"] = s.get_mu().cpu().numpy()
+    s.close()
+    st = c.oracle_state()
+    O.run(c.grid, c.oracle_params(mode=mode), c.eps.astype(np.float64), st, nsteps)
+    return out, st
+
+
+@pytest.mark.parametrize("shape,open_,By,Bz", [
+    ((48, 40, 12), (False, False, True), 0.15, 0.1),
+    ((40, 33, 9), (True, False, True), 0.2, 0.12),    # open x: the ghost carries the plane's factor squared
+    ((36, 30, 8), (False, True, True), 0.1, 0.1),     # open y
+    ((70, 37, 1), (False, False, True), 0.0, 0.2),    # a film, Bz only
+])
+def test_yz_steps_vs_oracle(shape, open_, By, Bz):
+    c = YZCase(*shape, open_=open_, By=By, Bz=Bz, tol=1e-12)
+    c.eps = inputs.random_real(c.grid.shape, 5, 0.3, 1.0)
+    g1, o1 = _run(c, 1)
+    err1 = rel_maxerr(g1["psi"], np.exp(-1j * c.chi) * o1.psi)
+    g5, o5 = _run(c, 5)
+    err5 = rel_maxerr(g5["psi"], np.exp(-1j * c.chi) * o5.psi)
+    print(f"[yz {shape} open {open_}] one step {err1:.2e}, five steps {err5:.2e}")
+    assert err1 <= 1e-5
+    assert err5 <= 1e-4
+
+
+def test_yz_driven_steps_vs_oracle():
+    """Current along x with the field in the yz plane (full Lorentz force):
+    psi, K, E and mu~ after three steps."""
+    c = YZCase(48, 40, 12, By=0.12, Bz=0.1, J=0.03, driven=True, tol=1e-12, mu_tol=1e-6, K0=0.2)
+    c.eps = inputs.random_real(c.grid.shape, 9, 0.2, 1.0)
+    g, o = _run(c, 3)
+    err = rel_maxerr(g["psi"], np.exp(-1j * c.chi) * o.psi)
+    mu_err = float(np.max(np.abs(g["mu"] - o.mu)))
+    print("[yz driven] psi", err, "mu", mu_err, "K", g["sc"]["K"], o.K, "E", g["sc"]["E_last"], o.last_E)
+    assert err <= 1e-4
+    assert abs(g["sc"]["K"] - o.K) <= 1e-6
+    assert abs(g["sc"]["E_last"] - o.last_E) <= 1e-6
+    assert mu_err <= 1e-4 * max(1.0, float(np.max(np.abs(o.mu))))
+
+
+def test_yz_mirror_sweep_counts():
+    c = YZCase(64, 48, 16, By=0.1, Bz=0.08, tol=1e-8)
+    c.eps = inputs.random_real(c.grid.shape, 13, -0.5, 1.0)
+    g, o = _run(c, 3, mode="mirror")
+    assert g["stats"]["sweeps_sum"] == sum(o.sweeps_hist)
+    assert rel_maxerr(g["psi"], np.exp(-1j * c.chi) * o.psi) <= 1e-5
+
+
+def test_xz_instance_in_a_yz_context_is_unchanged():
+    """The per-plane x-link variant multiplies an xz instance's links by
+    exactly 1: in a context that also holds a yz instance it advances bit
+    for bit as alone."""
+    cx = Case(48, 40, 12, Bz=0.2, tol=1e-10, psi_seed=2, driven=True, J=0.01)
+    cy = YZCase(32, 32, 16, By=0.1, Bz=0.1, tol=1e-10, psi_seed=3)
+    s = cx.solver()
+    s.set_tiling(rows=2, chunk=4, streaming=1)
+    s.step(4)
+    ref = s.get_psi().cpu().numpy(), s.get_scalars()["K"]
+    s.close()
+    s = cy.solver()
+    s.set_tiling(rows=2, chunk=4, streaming=1)
+    s.step(4)
+    refy = s.get_psi().cpu().numpy()
+    s.close()
+    b = tdgl.Solver([cx.params, cy.params])
+    cx.load_into(b, 0)
+    cy.load_into(b, 1)
+    b.set_tiling(rows=2, chunk=4, streaming=1)
+    b.step(4)
+    assert np.array_equal(b.get_psi(0).cpu().numpy(), ref[0])
+    assert b.get_scalars(0)["K"] == ref[1]
+    assert np.array_equal(b.get_psi(1).cpu().numpy(), refy)
+    b.close()
+
+
+def test_yz_graph_steps_and_tilings():
+    """Graph-replayed steps equal eager steps; every single-sweep tiling
+    gives the same bits; two-sweep and persistent tilings and the adjoint
+    are refused; the autotuner keeps to single sweeps; a return to the xz
+    plane gives the xz results."""
+    c = YZCase(40, 36, 10, By=0.1, Bz=0.1, J=0.02, driven=True, tol=1e-10)
+    a = c.solver()
+    a.set_tiling(rows=2, chunk=0, streaming=0)
+    a.step(3)
+    ref = a.get_psi().cpu().numpy()
+    a.close()
+    for rows, chunk, nt in ((1, 4, 0), (4, 0, 1), (2, 1, 1)):
+        b = c.solver()
+        b.set_tiling(rows=rows, chunk=chunk, streaming=nt)
+        b.step(3)
+        assert np.array_equal(b.get_psi().cpu().numpy(), ref), (rows, chunk, nt)
+        b.close()
+    g = c.solver()
+    g.set_tiling(rows=2, chunk=0, streaming=0)
+    g.step_graph(3, 60)
+    assert np.array_equal(g.get_psi().cpu().numpy(), ref)
+    with pytest.raises(tdgl.TdglError):
+        g.set_tiling(rows=2, chunk=0, streaming=0, fused=1)
+    with pytest.raises(tdgl.TdglError):
+        g.set_tiling(rows=2, chunk=0, streaming=0, persistent=1)
+    with pytest.raises(tdgl.TdglError):
+        g.voltage_grad(4, 0, 2)
+    t = g.autotune()
+    assert t["fused"] == 0 and t["persistent"] == 0
+    g.close()
+    # back to the xz plane
+    x = Case(40, 36, 10, Bz=0.1, J=0.02, driven=True, tol=1e-10)
+    s1 = x.solver()
+    s1.set_tiling(rows=2, chunk=0, streaming=0)
+    s1.step(3)
+    s2 = c.solver()
+    x.load_into(s2, 0)
+    s2.set_tiling(rows=2, chunk=0, streaming=0, fused=1)
+    s2.set_tiling(rows=2, chunk=0, streaming=0)
+    s2.step(3)
+    assert np.array_equal(s1.get_psi().cpu().numpy(), s2.get_psi().cpu().numpy())
+    s1.close()
+    s2.close()
+
+
+def test_yz_needs_open_z_for_By():
+    s = tdgl.Solver(tdgl.make_params(16, 16, 8, bc=(tdgl.TDGL_PERIODIC,) * 3))
+    with pytest.raises(tdgl.TdglError):
+        s.set_field_yz(0.1, 0.0)
+    by, bz = s.set_field_yz(0.0, 0.3)
+    assert by == 0.0 and abs(bz * 8 * 8 / (2 * np.pi) - round(bz * 8 * 8 / (2 * np.pi))) < 1e-9
+    s.close()

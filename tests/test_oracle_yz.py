@@ -1,0 +1,125 @@
+"""Pins of the oracle's yz-plane field (Eq. B_yz, Eq. A_yz, Eq. LaplUV_yz and
+the x-quasi-periodic boundary of Sec. 3.3.1) against what the paper and the
+mathematics fix: the dense operator written element by element, its
+equivalence under a reflection x <-> y with the (separately pinned) xz-plane
+operator, Landau levels, and the gauge transformation to the layout the GPU
+library stores (all links on x).  CPU only."""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import brute
+from oracle import oracle as O
+from paper_1409_8340_amd import inputs
+
+
+def _rand_c(shape, seed):
+    return inputs.random_complex(shape, seed, 1.0).astype(np.complex128)
+
+
+def _grids():
+    for ox, oy, oz in itertools.product([False, True], repeat=3):
+        yield O.Grid(5, 4, 3, 0.5, 0.6, 0.45, (ox, oy, oz), g=1.2)
+
+
+@pytest.mark.parametrize("grid", list(_grids()), ids=lambda g: "open" + "".join(
+    "xyz"[a] for a in range(3) if g.open_[a]) or "periodic")
+def test_yz_laplacian_matches_dense(grid):
+    By, Bz = O.quantize_field_yz(grid, 0.37, 0.41)
+    K = 0.3
+    L = brute.laplacian_matrix_yz(grid, By, Bz, K)
+    links = O.with_K(O.landau_links_yz(grid, By, Bz, 0.0), grid.hx, K)
+    v = _rand_c(grid.shape, 3)
+    np.testing.assert_allclose(O.laplacian(grid, links, v).reshape(-1), L @ v.reshape(-1), atol=1e-12)
+
+
+@pytest.mark.parametrize("open_", [(False, False, True), (True, False, True), (False, True, True),
+                                   (False, False, False)])
+def test_yz_field_is_the_xz_field_reflected(open_):
+    """Reflecting x <-> y turns B = (0, By, Bz) into a field of the xz form;
+    a reflection flips a pseudovector and complex conjugation flips it back,
+    so the yz operator on (nx, ny, nz) has the spectrum of the xz operator
+    with Bx = By, the same Bz, on (ny, nx, nz) with the x and y boundaries
+    swapped.  This pins the yz links and the x-seam phase P_{j,k} against
+    the xz links and the y-seam phase P_{i,k}."""
+    g1 = O.Grid(6, 5, 4, 0.5, 0.7, 0.45, open_)
+    g2 = O.Grid(5, 6, 4, 0.7, 0.5, 0.45, (open_[1], open_[0], open_[2]))
+    By, Bz = O.quantize_field_yz(g1, 0.29, 0.53)
+    Bx2, Bz2 = O.quantize_field(g2, By, Bz)
+    assert abs(Bx2 - By) < 1e-12 and abs(Bz2 - Bz) < 1e-12
+    e1 = np.sort_complex(np.linalg.eigvals(brute.laplacian_matrix_yz(g1, By, Bz, 0.0)))
+    e2 = np.sort_complex(np.linalg.eigvals(brute.laplacian_matrix(g2, By, Bz, 0.0)))
+    assert np.max(np.abs(e1.imag)) < 1e-9
+    np.testing.assert_allclose(e1.real, e2.real, atol=1e-9)
+
+
+def test_yz_landau_levels():
+    """B along z in the yz gauge (x quasi-periodic): the lowest n_z
+    eigenvalues of -L sit at ~B, the next band near 3B."""
+    grid = O.Grid(24, 24, 1, 0.5, 0.5, 0.5, (False, False, True))
+    nq = 6
+    Bz = 2 * np.pi * nq / (grid.length(0) * grid.length(1))
+    L = brute.laplacian_matrix_yz(grid, 0.0, Bz, 0.0)
+    ev = np.sort(np.linalg.eigvalsh(-0.5 * (L + L.conj().T)))
+    assert np.all(np.abs(ev[:nq] / Bz - 1) < 0.02)
+    assert np.all(np.abs(ev[nq:2 * nq] / Bz - 3) < 0.06)
+
+
+def gpu_layout_links(grid, By, Bz):
+    """The links the GPU library stores for a yz-plane field, built here
+    from its documented formulas: x link exp(i hx (Bz j hy - By k hz)),
+    y and z links 1, the periodic y wrap edge conj(P_i) with
+    P_i = exp(i xbar_i Ly Bz)."""
+    nz, ny, nx = grid.shape
+    j = np.arange(ny)[None, :, None]
+    k = np.arange(nz)[:, None, None]
+    lx = np.broadcast_to(np.exp(1j * grid.hx * (Bz * j * grid.hy - By * k * grid.hz)), grid.shape)
+    ly = np.ones(grid.shape, np.complex128)
+    if not grid.open_[1]:
+        xbar = np.arange(nx) * grid.hx - grid.length(0) / 2.0
+        ly[:, ny - 1, :] = np.conj(np.exp(1j * xbar * grid.length(1) * Bz))[None, :]
+    lz = np.ones(grid.shape, np.complex128)
+    return tuple(np.ascontiguousarray(a, dtype=np.complex128) for a in (lx, ly, lz))
+
+
+def gauge_phase(grid, By, Bz):
+    """chi with psi_paper = exp(i chi) psi_gpu: chi = (j hy Bz - k hz By) xbar_i."""
+    nz, ny, nx = grid.shape
+    xbar = (np.arange(nx) * grid.hx - grid.length(0) / 2.0)[None, None, :]
+    j = np.arange(ny)[None, :, None]
+    k = np.arange(nz)[:, None, None]
+    return (j * grid.hy * Bz - k * grid.hz * By) * xbar
+
+
+@pytest.mark.parametrize("open_,driven", [((False, False, True), True), ((True, False, True), False),
+                                          ((False, True, True), True)])
+def test_gpu_layout_is_a_gauge_transform_of_the_paper(open_, driven):
+    """Steps taken with the GPU library's links equal the paper's steps up to
+    psi_paper = exp(i chi) psi: the same psi up to that phase, the same K, E
+    and mu~ (flux through every plaquette and phase around every periodic
+    loop agree)."""
+    grid = O.Grid(10, 8, 6, 0.5, 0.5, 0.5, open_)
+    By, Bz = O.quantize_field_yz(grid, 0.21, 0.33)
+    p = O.Params(By=By, Bz=Bz, plane="yz", J_ext=0.03 if driven else 0.0, tol=1e-12, mode="exact",
+                 driven=driven)
+    eps = inputs.random_real(grid.shape, 5, 0.3, 1.0).astype(np.float64)
+    psi0 = inputs.psi_init(10, 8, 6, 7).astype(np.complex128)
+    chi = gauge_phase(grid, By, Bz)
+    s1 = O.new_state(grid, psi0)
+    O.run(grid, p, eps, s1, 3)
+    s2 = O.new_state(grid, np.exp(-1j * chi) * psi0)
+    O.run(grid, p, eps, s2, 3, base_links=gpu_layout_links(grid, By, Bz))
+    np.testing.assert_allclose(np.exp(1j * chi) * s2.psi, s1.psi, atol=1e-10)
+    assert abs(s1.K - s2.K) < 1e-12 and abs(s1.V_sum - s2.V_sum) < 1e-12
+    np.testing.assert_allclose(s2.mu, s1.mu, atol=1e-10)
+    # and a wrong twist of the y seam (the centred coordinate dropped) is seen
+    if driven and not open_[1]:
+        bad = list(gpu_layout_links(grid, By, Bz))
+        nq = round(Bz * grid.length(0) * grid.length(1) / (2 * np.pi))
+        if nq % 2:
+            bad[1] = bad[1].copy()
+            bad[1][:, grid.ny - 1, :] *= -1.0
+            s3 = O.new_state(grid, np.exp(-1j * chi) * psi0)
+            O.run(grid, p, eps, s3, 3, base_links=tuple(bad))
+            assert np.max(np.abs(np.exp(1j * chi) * s3.psi - s1.psi)) > 1e-6
