@@ -181,3 +181,43 @@ def poisson_solve(grid, f):
     mu, *_ = np.linalg.lstsq(A, ff, rcond=None)
     mu -= (w @ mu) / w.sum()
     return mu
+
+
+def laplacian_matrix_cut(grid, Bx, Bz, K, mask):
+    """Dense covariant Laplacian (xz-plane field) with every edge that
+    touches an insulating node (mask != 0) cut out (Sec. 3.4, item (ii)),
+    written edge by edge: row m of a superconducting node sums
+    c_a (U psi_n - psi_m) over its remaining edges (an open face node's
+    single inner edge counted twice, as in Sec. 3.3.2); rows and columns of
+    insulating nodes are zero (psi = 0 there)."""
+    mask = np.asarray(mask).reshape(-1) != 0
+    N = grid.N
+    L = np.zeros((N, N), dtype=np.complex128)
+    for k in range(grid.nz):
+        for j in range(grid.ny):
+            for i in range(grid.nx):
+                m = _m(grid, i, j, k)
+                if mask[m]:
+                    continue
+                pos = (i, j, k)
+                for a, (n, h, op, cf) in enumerate(_axes(grid)):
+                    c = cf / (h * h)
+                    if op and n == 1:
+                        continue
+                    for d in (-1, 1):
+                        t = pos[a] + d
+                        if op and (t < 0 or t >= n):
+                            continue
+                        q = list(pos)
+                        q[a] = t % n
+                        nb = _m(grid, *q)
+                        if mask[nb]:
+                            continue
+                        if d == 1:
+                            U = link(grid, a, *pos, Bx, Bz, K)
+                        else:
+                            U = np.conj(link(grid, a, *q, Bx, Bz, K))
+                        w = 2.0 if (op and (pos[a] == 0 or pos[a] == n - 1)) else 1.0
+                        L[m, nb] += w * c * U
+                        L[m, m] -= w * c
+    return L

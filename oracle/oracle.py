@@ -651,6 +651,53 @@ def gen_voronoi(grid: Grid, seeds: np.ndarray, values: np.ndarray, metric: int =
     return out, owner
 
 
+def insulate(grid: Grid, mask: np.ndarray, eps: np.ndarray, psi: np.ndarray = None, g: float = None):
+    """Insulating inclusions (Sec. 3.4, item (ii)): no current across the
+    edges between a superconducting node and an insulating one.
+
+    reading: those edges are cut out of the covariant Laplacian and psi is
+    0 on insulating nodes (the mu~ equation is left unchanged).  For psi
+    with psi = 0 on the insulating nodes, the cut operator equals the
+    uncut one plus, on the diagonal of each superconducting node, the cut
+    shares c_a = 1/h_a^2 (1/(g h_z)^2 on z; 2 c_a for the doubled inner
+    neighbour of an open face node) -- the same as raising eps there by
+    them.  Returns (eps', psi'): eps' = eps + shares (float32 sums in the
+    order x-, x+, y-, y+, z-, z+, as the library stores eps), eps' = -2^50
+    on insulating nodes (a diagonal that keeps psi there at ~0), psi' = psi
+    with the insulating nodes zeroed."""
+    mask = np.asarray(mask).reshape(grid.shape) != 0
+    gg = grid.g if g is None else g
+    nz, ny, nx = grid.shape
+    n = (nx, ny, nz)
+    # per-axis edge coefficient as the stencil holds it (0 on a one-node open axis)
+    inv = (1.0 / (grid.hx * grid.hx), 1.0 / (grid.hy * grid.hy), 1.0 / (gg * gg * grid.hz * grid.hz))
+    c = [np.float32(0.0) if (grid.open_[a] and n[a] == 1) else np.float32(inv[a]) for a in range(3)]
+    out = np.asarray(eps, dtype=np.float32).reshape(grid.shape).copy()
+    axis_of = {0: 2, 1: 1, 2: 0}   # grid axis a -> numpy axis
+    for a in range(3):
+        if c[a] == 0:
+            continue
+        ax = axis_of[a]
+        for d in (-1, 1):
+            nb = np.roll(mask, -d, axis=ax)     # mask of the neighbour at offset d
+            share = np.full(grid.shape, c[a], dtype=np.float32)
+            if grid.open_[a]:
+                idx = np.arange(n[a])
+                exists = (idx + d >= 0) & (idx + d < n[a])
+                face = (idx == 0) | (idx == n[a] - 1)
+                shp = [1, 1, 1]
+                shp[ax] = n[a]
+                nb = nb & exists.reshape(shp)
+                share = np.where(face.reshape(shp), np.float32(2.0) * c[a], share).astype(np.float32)
+            out = np.where(nb & ~mask, (out + share).astype(np.float32), out)
+    out[mask] = np.float32(-1125899906842624.0)
+    p2 = None
+    if psi is not None:
+        p2 = np.array(psi, copy=True).reshape(grid.shape)
+        p2[mask] = 0
+    return out, p2
+
+
 # A candidate whose box reaches farther than 2^50 node spacings from the
 # origin (or holds a non-finite number) covers nothing.
 INCL_REACH = 2.0 ** 50

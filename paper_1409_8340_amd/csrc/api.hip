@@ -1502,6 +1502,17 @@ tdgl_status tdgl_gen_inclusions(tdgl_ctx *ctx, int inst, const double *centres, 
     return TDGL_OK;
 }
 
+tdgl_status tdgl_set_insulators(tdgl_ctx *ctx, int inst, const unsigned char *mask) {
+    tdgl_status s = check_ctx(ctx, inst);
+    if (s) return s;
+    if (!mask) return fail(TDGL_EINVAL, "null mask");
+    const Inst &d = ctx->inst[inst].d;
+    hipLaunchKernelGGL(k_insulate, dim3(fill_grid(d.N)), dim3(256), 0, ctx->stream, ctx->d_inst, inst, mask);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return TDGL_OK;
+}
+
 tdgl_status tdgl_gen_voronoi(tdgl_ctx *ctx, int inst, const double *seeds, const float *values, int ns,
                              int metric, int axes) {
     tdgl_status s = check_ctx(ctx, inst);

@@ -205,4 +205,52 @@ __global__ void k_incl_write(const Inst *__restrict__ insts, int inst,
         I.eps[m] = first[m] < used ? eps_in : eps_out;
 }
 
+// Insulating inclusions (Sec. 3.4, item (ii)): no current across the edges
+// between a superconducting node and an insulating one.  With psi = 0 held
+// on the insulating nodes, cutting those edges out of the covariant
+// Laplacian leaves the neighbour sum of every superconducting node as it
+// is and only removes the edge's share of the diagonal, c_a = 1/h_a^2
+// (1/(g h_z)^2 on z; 2 c_a for the doubled inner neighbour of an open face
+// node).  That is the same as raising eps at the node by the cut shares, so
+// the stencil passes need no mask: this kernel adds the shares to eps
+// (float, in the order x-, x+, y-, y+, z-, z+), and gives insulating nodes
+// eps = -2^50, whose diagonal keeps psi there at |psi| < 1e-14 once it
+// starts at zero, and zeroes psi on them.
+__global__ void k_insulate(const Inst *__restrict__ insts, int inst, const unsigned char *__restrict__ mask) {
+    const Inst &I = insts[inst];
+    const int nx = I.nx, ny = I.ny, nz = I.nz;
+    float2 *psi = I.psi[I.st->cur];
+    const float c[3] = {I.cx, I.cy, I.cz};
+    const int n[3] = {nx, ny, nz};
+    const long str[3] = {1, nx, (long)nx * ny};
+    for (long m = blockIdx.x * (long)blockDim.x + threadIdx.x; m < I.N; m += (long)gridDim.x * blockDim.x) {
+        if (mask[m]) {
+            I.eps[m] = -1125899906842624.0f;
+            psi[m] = make_float2(0.f, 0.f);
+            continue;
+        }
+        const int q[3] = {(int)(m % nx), (int)((m / nx) % ny), (int)(m / ((long)nx * ny))};
+        float e = I.eps[m];
+        for (int a = 0; a < 3; ++a) {
+            if (c[a] == 0.f) continue;  // one-node open axis: no edges
+            for (int d = -1; d <= 1; d += 2) {
+                const int t = q[a] + d;
+                long nb;
+                float share = c[a];
+                if (t >= 0 && t < n[a]) {
+                    nb = m + d * str[a];
+                    // open face node: its single inner neighbour counts twice
+                    if (!I.per[a] && (q[a] == 0 || q[a] == n[a] - 1)) share = 2.f * c[a];
+                } else if (I.per[a]) {
+                    nb = m + (t < 0 ? (long)(n[a] - 1) : -(long)(n[a] - 1)) * str[a];
+                } else {
+                    continue;
+                }
+                if (mask[nb]) e += share;
+            }
+        }
+        I.eps[m] = e;
+    }
+}
+
 }  // namespace tdgl

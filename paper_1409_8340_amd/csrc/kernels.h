@@ -92,6 +92,7 @@ __global__ void k_incl_first(const Inst *insts, int inst, const double *centres,
                              int nc, unsigned *first);
 __global__ void k_voronoi(const Inst *insts, int inst, const double *seeds, const float *values, int ns,
                           int metric, int axes);
+__global__ void k_insulate(const Inst *insts, int inst, const unsigned char *mask);
 __global__ void k_incl_first_q(const Inst *insts, int inst, const double *shapes, int nc, unsigned *first);
 __global__ void k_incl_count(const unsigned *first, long N, int nc, unsigned *cnt);
 __global__ void k_incl_scan(const Inst *insts, int inst, const unsigned *cnt, int nc, double target);

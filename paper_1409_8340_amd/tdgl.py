@@ -118,6 +118,7 @@ _SIGS = {
                          ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "tdgl_gen_voronoi": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                           ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "tdgl_set_insulators": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "tdgl_set_psi": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "tdgl_get_psi": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "tdgl_set_mu": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
@@ -319,6 +320,16 @@ class Solver:
             raise ValueError("one value per seed")
         _check(load().tdgl_gen_voronoi(self._ctx, inst, self._dev(sd, torch.float64), self._dev(vals, torch.float32),
                                        int(sd.shape[0]), int(metric), int(axes)))
+
+    def set_insulators(self, mask, inst=0):
+        """mask: array-like of the instance's shape (nz, ny, nx), nonzero =
+        insulating node (tdgl_set_insulators: rewrites eps, zeroes psi there)."""
+        import torch
+        m = torch.as_tensor(mask).to(dtype=torch.uint8).reshape(-1).contiguous().cuda()
+        if m.numel() != self.params[inst].nx * self.params[inst].ny * self.params[inst].nz:
+            raise ValueError("mask must have one entry per node")
+        torch.cuda.current_stream().synchronize()
+        _check(load().tdgl_set_insulators(self._ctx, inst, self._dev(m, torch.uint8)))
 
     def set_psi(self, psi, inst=0):
         import torch
