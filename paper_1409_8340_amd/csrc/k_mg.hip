@@ -131,6 +131,7 @@ __global__ __launch_bounds__(256) void k_mg_residual(const Inst *__restrict__ in
     __shared__ float red[4];
     const int ii = find_inst(prefix, ninst, blockIdx.x);
     const Inst &I = insts[ii];
+    if (I.fft) return;  // spectral instances (level 0 is launched over all driven ones)
     if (lv == 0) {
         if (cyc > 0 && mg_done(I, cyc - 1)) return;
     } else if (mg_done(I, cyc)) {
@@ -260,7 +261,7 @@ __global__ __launch_bounds__(CO_THREADS) void k_mg_coarsest(const Inst *__restri
     __shared__ double red[CO_THREADS / 64];
     __shared__ double sh_mean, sh_rmax;
     const Inst &I = insts[blockIdx.x];
-    if (!I.driven || mg_done(I, cyc)) return;
+    if (!I.driven || I.fft || mg_done(I, cyc)) return;
     const int lv = I.nlev - 1;
     const MGLevel &L = I.lev[lv];
     const int N = L.N;
