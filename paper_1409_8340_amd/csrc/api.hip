@@ -782,20 +782,23 @@ void launch_sweep2_r(tdgl_ctx *c, int l) {
     // boundary groups taking CU slots from the interior kernel for longer
     // than the boundary kernel takes alone.
     unsigned long long *pub = (c->pub_on && l > 0) ? c->d_pub : nullptr;
-    // (tile (0, 0) is never interior, so the boundary grid is never empty;
-    // the interior one is for grids too small to hold a super-tile)
+    // (either grid can be empty: no boundary tiles when super-tiles cover
+    // every tile, no super-tile on grids too small to hold one; an instance
+    // without boundary tiles hands its rows over from the interior kernel)
     if (c->nt) {
-        hipLaunchKernelGGL((k_sweep2<R, true>), dim3(c->tot_b), dim3(WG), 0, c->stream, c->d_inst, c->d_pref_b,
-                           c->n, l, pub, c->pub_seq);
+        if (c->tot_b > 0)
+            hipLaunchKernelGGL((k_sweep2<R, true>), dim3(c->tot_b), dim3(WG), 0, c->stream, c->d_inst, c->d_pref_b,
+                               c->n, l, pub, c->pub_seq);
         if (c->tot_i > 0)
             hipLaunchKernelGGL((k_sweep2i<R, true>), dim3(c->tot_i), dim3(WG * sweep2i_mult(R)), 0, c->stream,
-                               c->d_inst, c->d_pref_i, c->n, l);
+                               c->d_inst, c->d_pref_i, c->n, l, pub, c->pub_seq);
     } else {
-        hipLaunchKernelGGL((k_sweep2<R, false>), dim3(c->tot_b), dim3(WG), 0, c->stream, c->d_inst, c->d_pref_b,
-                           c->n, l, pub, c->pub_seq);
+        if (c->tot_b > 0)
+            hipLaunchKernelGGL((k_sweep2<R, false>), dim3(c->tot_b), dim3(WG), 0, c->stream, c->d_inst,
+                               c->d_pref_b, c->n, l, pub, c->pub_seq);
         if (c->tot_i > 0)
             hipLaunchKernelGGL((k_sweep2i<R, false>), dim3(c->tot_i), dim3(WG * sweep2i_mult(R)), 0, c->stream,
-                               c->d_inst, c->d_pref_i, c->n, l);
+                               c->d_inst, c->d_pref_i, c->n, l, pub, c->pub_seq);
     }
 }
 void launch_sweep2(tdgl_ctx *c, int l) {
@@ -1825,18 +1828,23 @@ tdgl_status upload_tiling(tdgl_ctx *ctx) {
         // the 64 x 4R tiles of the super-tiles (M of them stacked in y) that
         // the plain-load two-sweep kernel does not take
         std::vector<int> bt;
-        const int M = sweep2i_mult(d.rows), ry = 4 * d.rows;
-        const int nsy = sweep2i_rows(d.ny, d.rows);
+        const int M = sweep2i_mult(d.rows);
+        d.seam2 = seam2_ok(d.per[1] != 0, d.ny) ? 1 : 0;
+        const bool seam = d.seam2 != 0;
+        const int nsy = sweep2i_rows(d.ny, d.rows, seam);
         for (int ty = 0; ty < d.tiles_y; ++ty)
             for (int tx = 0; tx < d.tiles_x; ++tx) {
-                // tile row ty >= 1 lies in super-tile row (ty - 1) / M
-                const int j = (ty - 1) / M;
-                const bool inner = ty >= 1 && j < nsy &&
-                                   tile_interior2(tx * TX, ry + j * TYS, TYS, d.nx, d.ny, d.per[0] != 0);
+                // tile row ty lies in super-tile row ty / M (seam2) or, one
+                // tile row in, (ty - 1) / M
+                const int tr = seam ? ty : ty - 1;
+                const int j = tr / M;
+                const bool inner = tr >= 0 && j < nsy &&
+                                   tile_interior2(tx * TX, sweep2i_y0(j, d.rows, seam), TYS, d.nx, d.ny,
+                                                  d.per[0] != 0, seam);
                 if (!inner) bt.push_back(tx + d.tiles_x * ty);
             }
         pi[i + 1] = pi[i] + d.tiles_x * nsy * d.tiles_z;
-        HIPCHK(hipMemcpy(d.btile, bt.data(), bt.size() * 4, hipMemcpyHostToDevice));
+        if (!bt.empty()) HIPCHK(hipMemcpy(d.btile, bt.data(), bt.size() * 4, hipMemcpyHostToDevice));
         d.nbt = (int)bt.size();
         d.bchunk = std::min(d.chunk, kBoundaryChunk);
         ps[i + 1] = ps[i] + h.st_blocks;

@@ -403,7 +403,8 @@ __global__ __launch_bounds__(WG) void k_sweep2(const Inst *__restrict__ insts, c
 // rings read them again.
 template <int R, bool NT>
 __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(const Inst *__restrict__ insts,
-                                                               const int *__restrict__ prefix, int ninst, int l) {
+                                                               const int *__restrict__ prefix, int ninst, int l,
+                                                               unsigned long long *pub, unsigned seq) {
     constexpr int M = sweep2i_mult(R);
     constexpr int WGI = WG * M;
     constexpr int TYv = TYS;
@@ -421,21 +422,41 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
     const Inst &I = insts[ii];
     const int nx = I.nx, ny = I.ny, nz = I.nz;
     // blocks: tiles_x x sweep2i_rows x tiles_z super-tiles
-    const int nsy = sweep2i_rows(ny, R);
+    const bool seam2 = I.seam2 != 0;
+    const int nsy = sweep2i_rows(ny, R, seam2);
     int t = b - prefix[ii];
+    const bool first = t == 0;
     const int txi = t % I.tiles_x;
     t /= I.tiles_x;
-    const int tyi = t % nsy;
+    const int tyr = t % nsy;
     const int tzi = t / nsy;
-    const int x0 = txi * TX, y0 = 4 * R + tyi * TYv;
+    // seam2: the two seam rows (slower: their ring slots beyond the seam
+    // are computed from global memory) are taken first, so that they do not
+    // finish last: row order 0, nsy - 1, 1, 2, ..., nsy - 2
+    const int tyi = (!seam2 || tyr == 0) ? tyr : (tyr == 1 ? nsy - 1 : tyr - 1);
+    const int x0 = txi * TX, y0 = sweep2i_y0(tyi, R, seam2);
     const bool xper = I.per[0] != 0;
-    if (!tile_interior2(x0, y0, TYv, nx, ny, xper)) return;
     const bool timing = l < 0;
     if (!timing) {
         if (l >= I.max_iter) return;
-        if (row_max_wave(I.res, I.rstride, l - 1) < I.tol) return;
-        if (l >= 2 && row_max_wave(I.res, I.rstride, l - 2) < I.tol) return;
+        const float p1 = row_max_wave(I.res, I.rstride, l - 1);
+        const float p2 = (l >= 2) ? row_max_wave(I.res, I.rstride, l - 2) : 1.f;
+        // an instance with no boundary tiles hands rows l - 1 and l - 2 to
+        // the host from here (else the boundary kernel does)
+        if (pub && I.nbt == 0 && first && threadIdx.x == 0) {
+            publish(pub + (size_t)(l - 1) * ninst + ii, seq, p1);
+            if (l >= 2) publish(pub + (size_t)(l - 2) * ninst + ii, seq, p2);
+        }
+        if (p1 < I.tol) return;
+        if (l >= 2 && p2 < I.tol) return;
     }
+    if (!tile_interior2(x0, y0, TYv, nx, ny, xper, seam2)) return;
+    // a super-tile on the quasi-periodic y seam (seam2): its y halo rows
+    // beyond the grid are the wrapped rows times the phase P (or conj P),
+    // and its ring slots there are the wrapped nodes' updates with that
+    // phase, as cell_src2 / slot_update give them to the general kernel
+    const bool seam = seam2 && (y0 == 0 || y0 + TYv == ny);
+    const gf2 *__restrict__ Pt = (const gf2 *)I.P;
     const bool rec2 = !timing && (l + 1 < I.max_iter);
     const int k0 = tzi * I.chunk;
     const int k1 = min(k0 + I.chunk, nz);
@@ -462,9 +483,11 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
         uz[r] = I.uz[y];
         oo[r] = (unsigned)(y * nx + x);
     }
-    // two-node halo slots this thread stages (h = tid + q WGI)
+    // two-node halo slots this thread stages (h = tid + q WGI); h2m: 0
+    // plain, SRC_P / SRC_PCONJ across the seam, with the phase's x index
+    // in h2x (its table entry is loaded with the slot, for every tile)
     unsigned h2o[NQ];
-    int h2l[NQ];
+    int h2l[NQ], h2m[NQ], h2x[NQ];
     bool h2on[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -472,11 +495,16 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
         h2on[q] = h < NH2;
         h2o[q] = oo[0];
         h2l[q] = 0;
+        h2m[q] = SRC_PLAIN;
+        h2x[q] = 0;
         if (h2on[q]) {
             int gx, gy, lx, ly;
             halo2_cell<TYv>(h, x0, y0, gx, gy, lx, ly);
             const int sx = xper ? ((gx % nx) + nx) % nx : gx;
-            h2o[q] = (unsigned)(gy * nx + sx);
+            int sy = gy;
+            if (gy < 0) { sy = gy + ny; h2m[q] = SRC_P; h2x[q] = sx; }
+            else if (gy >= ny) { sy = gy - ny; h2m[q] = SRC_PCONJ; h2x[q] = sx; }
+            h2o[q] = (unsigned)(sy * nx + sx);
             h2l[q] = ly * LX + lx;
         }
     }
@@ -489,15 +517,20 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
     int rlx = 0, rly = 0, tlx = 2, tly = 2;
     unsigned rso = oo[0];
     float2 rux = make_float2(1.f, 0.f), ruz = make_float2(1.f, 0.f);
+    bool rcross = false;  // ring slot beyond the seam: computed from global memory
+    CellSrc rcs{0, SRC_ZERO, 0, make_float2(1.f, 0.f)};
     if (hthr) {
         int gx, gy;
         halo_cell<TYv>(hidx, x0, y0, gx, gy, rlx, rly);
         const int sx = xper ? ((gx % nx) + nx) % nx : gx;
-        rso = (unsigned)(gy * nx + sx);
+        rcross = gy < 0 || gy >= ny;
+        const int sy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
+        if (rcross) rcs = cell_src2(I, gx, gy);
+        rso = (unsigned)(sy * nx + sx);
         tlx = gx - x0 + 2;
         tly = gy - y0 + 2;
-        rux = I.ux[gy];
-        ruz = I.uz[gy];
+        rux = I.ux[sy];
+        ruz = I.uz[sy];
     }
 
     auto pz = [&](int v) -> int {
@@ -505,21 +538,35 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
         if (!zper) return -1;
         return ((v % nz) + nz) % nz;
     };
-    auto load_a = [&](int p, float2 *ao, float2 *hv) {
-        const unsigned pb = (unsigned)(p < 0 ? 0 : p) * NXY;
+    // (the phase entries are loaded by every tile, with the other loads and
+    // unconditionally, so that no load sits under a branch; only seam tiles
+    // use them)
+    auto load_a = [&](int p, float2 *ao, float2 *hv, float2 *ph) {
+        const int pp = p < 0 ? 0 : p;
+        const unsigned pb = (unsigned)pp * NXY;
 #pragma unroll
         for (int r = 0; r < R; ++r) ao[r] = ld2(src, pb + oo[r]);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) hv[q] = ld2(src, pb + h2o[q]);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) ph[q] = ld2(Pt, (unsigned)pp * nx + h2x[q]);
     };
-    auto stage_a = [&](int v, const float2 *ao, const float2 *hv) {
+    auto stage_a = [&](int v, const float2 *ao, const float2 *hv, const float2 *ph) {
         float2 (*L)[LX] = la[v & 3];
         float2 *Lf = &la[v & 3][0][0];
 #pragma unroll
         for (int r = 0; r < R; ++r) L[2 + w * R + r][2 + lane] = ao[r];
+        if (seam) {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q)
-            if (h2on[q]) Lf[h2l[q]] = hv[q];
+            for (int q = 0; q < NQ; ++q)
+                if (h2on[q])
+                    Lf[h2l[q]] = h2m[q] == SRC_P ? xcmul(ph[q], hv[q])
+                                                 : (h2m[q] == SRC_PCONJ ? xcmulc(ph[q], hv[q]) : hv[q]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+                if (h2on[q]) Lf[h2l[q]] = hv[q];
+        }
     };
     auto load_bd = [&](int p, float2 *bh_, float2 *dh_, float2 &rbh, float2 &rdh) {
         const unsigned pb = (unsigned)(p < 0 ? 0 : p) * NXY;
@@ -537,11 +584,11 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
     auto needed_a = [&](int v) { return v >= vb0 - 1 && v <= k1 + 1 && pz(v) >= 0; };
 
     {
-        float2 ao[R], hv[NQ];
+        float2 ao[R], hv[NQ], ph[NQ];
         for (int v = vb0 - 1; v <= vb0 + 1; ++v)
             if (needed_a(v)) {
-                load_a(pz(v), ao, hv);
-                stage_a(v, ao, hv);
+                load_a(pz(v), ao, hv, ph);
+                stage_a(v, ao, hv, ph);
             }
     }
     // three register sets for the prefetched planes, rotating every plane
@@ -551,10 +598,11 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
     // across each barrier and no register a load is still filling is ever
     // copied.  Sets are indexed relative to vb0.
     float2 aS0[R], hS0[NQ], aS1[R], hS1[NQ], aS2[R], hS2[NQ];  // psi^(l)
+    float2 pS0[NQ], pS1[NQ], pS2[NQ];                         // seam phases of the halo slots
     float2 bT0[R], dT0[R], bT1[R], dT1[R], bT2[R], dT2[R];     // b/M, (ht/2)/M
     float2 rbT0, rdT0, rbT1, rdT1, rbT2, rdT2;                  // ... at the ring source
-    load_a(needed_a(vb0 + 2) ? pz(vb0 + 2) : -1, aS2, hS2);
-    load_a(needed_a(vb0 + 3) ? pz(vb0 + 3) : -1, aS0, hS0);
+    load_a(needed_a(vb0 + 2) ? pz(vb0 + 2) : -1, aS2, hS2, pS2);
+    load_a(needed_a(vb0 + 3) ? pz(vb0 + 3) : -1, aS0, hS0, pS0);
     load_bd(pz(vb0), bT0, dT0, rbT0, rdT0);
     load_bd(vb0 + 1 <= k1 ? pz(vb0 + 1) : -1, bT1, dT1, rbT1, rdT1);
     float2 b2[R], b1[R];
@@ -567,16 +615,17 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
     // b/M is loaded into afterwards); loads of plane v + 4 into an4.  v > ve:
     // a padding step (loads only) that makes the trip count a multiple of
     // three.
-    auto body = [&](int v, float2 (&an2)[R], float2 (&hn2)[NQ], float2 (&an4)[R], float2 (&hn4)[NQ],
-                    float2 (&bhc)[R], float2 (&dhc)[R], float2 &rbhc, float2 &rdhc, float2 (&bh2)[R],
-                    float2 (&dh2)[R], float2 &rbh2, float2 &rdh2) __attribute__((always_inline)) {
+    auto body = [&](int v, float2 (&an2)[R], float2 (&hn2)[NQ], float2 (&pn2)[NQ], float2 (&an4)[R],
+                    float2 (&hn4)[NQ], float2 (&pn4)[NQ], float2 (&bhc)[R], float2 (&dhc)[R], float2 &rbhc,
+                    float2 &rdhc, float2 (&bh2)[R], float2 (&dh2)[R], float2 &rbh2,
+                    float2 &rdh2) __attribute__((always_inline)) {
         const bool live = v <= ve;
         const int p = pz(v);
         const bool stageA = live && (p >= 0);
         const bool stageB = live && (v - 1 >= k0) && (v - 1 < k1);
-        load_a(needed_a(v + 4) ? pz(v + 4) : -1, an4, hn4);
+        load_a(needed_a(v + 4) ? pz(v + 4) : -1, an4, hn4, pn4);
         __syncthreads();
-        if (live && needed_a(v + 2)) stage_a(v + 2, an2, hn2);
+        if (live && needed_a(v + 2)) stage_a(v + 2, an2, hn2, pn2);
         float2 b0[R];
         if (stageA) {
             const float2 (*L)[LX] = la[v & 3];
@@ -596,9 +645,13 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
                 lb[lq][ly - 1][lx - 1] = b0[r];
             }
             if (hthr) {
-                const float2 ns = nsum(rux, ruz, L[tly][tlx - 1], L[tly][tlx + 1], L[tly - 1][tlx], L[tly + 1][tlx],
-                                       Lm[tly][tlx], Lp[tly][tlx], zm, zp, cx, cy, cz);
-                lb[lq][rly][rlx] = jacobi(rbhc, rdhc, ns);
+                if (seam && rcross) {
+                    lb[lq][rly][rlx] = slot_update(I, src, Pt, bhp, dhp, rcs, p, NXY, zper);
+                } else {
+                    const float2 ns = nsum(rux, ruz, L[tly][tlx - 1], L[tly][tlx + 1], L[tly - 1][tlx],
+                                           L[tly + 1][tlx], Lm[tly][tlx], Lp[tly][tlx], zm, zp, cx, cy, cz);
+                    lb[lq][rly][rlx] = jacobi(rbhc, rdhc, ns);
+                }
             }
         } else {
 #pragma unroll
@@ -630,9 +683,9 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
         }
     };
     for (int v = vb0; v <= ve; v += 3) {
-        body(v, aS2, hS2, aS1, hS1, bT0, dT0, rbT0, rdT0, bT2, dT2, rbT2, rdT2);
-        body(v + 1, aS0, hS0, aS2, hS2, bT1, dT1, rbT1, rdT1, bT0, dT0, rbT0, rdT0);
-        body(v + 2, aS1, hS1, aS0, hS0, bT2, dT2, rbT2, rdT2, bT1, dT1, rbT1, rdT1);
+        body(v, aS2, hS2, pS2, aS1, hS1, pS1, bT0, dT0, rbT0, rdT0, bT2, dT2, rbT2, rdT2);
+        body(v + 1, aS0, hS0, pS0, aS2, hS2, pS2, bT1, dT1, rbT1, rdT1, bT0, dT0, rbT0, rdT0);
+        body(v + 2, aS1, hS1, pS1, aS0, hS0, pS0, bT2, dT2, rbT2, rdT2, bT1, dT1, rbT1, rdT1);
     }
     if (timing) return;
     __syncthreads();
@@ -645,7 +698,7 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
 
 #define TDGL_INST2(R, NT)                                                                                   \
     template __global__ void k_sweep2<R, NT>(const Inst *, const int *, int, int, unsigned long long *, unsigned); \
-    template __global__ void k_sweep2i<R, NT>(const Inst *, const int *, int, int);
+    template __global__ void k_sweep2i<R, NT>(const Inst *, const int *, int, int, unsigned long long *, unsigned);
 TDGL_INST2(1, false)
 TDGL_INST2(1, true)
 TDGL_INST2(2, false)

@@ -16,7 +16,8 @@ template <int R, bool NT>
 __global__ void k_sweep2(const Inst *insts, const int *prefix, int ninst, int l, unsigned long long *pub,
                          unsigned seq);
 template <int R, bool NT>
-__global__ void k_sweep2i(const Inst *insts, const int *prefix, int ninst, int l);
+__global__ void k_sweep2i(const Inst *insts, const int *prefix, int ninst, int l, unsigned long long *pub,
+                          unsigned seq);
 template <int R, bool NT>
 __global__ void k_jacobi_persist(const Inst *insts, const int *prefix, int ninst, int l0, int lcap, int ntiles);
 template <int MODE, int R, bool NT, bool YZ>

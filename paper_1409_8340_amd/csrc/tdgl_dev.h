@@ -134,6 +134,8 @@ struct Inst {
     // work-group of their kernel
     int *btile;
     int nbt, bchunk;
+    int seam2;           // super-tiles start at y = 0 and cover the quasi-periodic y seam
+                         // (periodic y, ny a multiple of TYS); else they start one tile row in
     int nlev;
     MGLevel lev[kMaxLevels];
     // direct spectral Poisson solve (periodic x and y, open z)
@@ -174,20 +176,27 @@ constexpr int TYS = 16;
 __host__ __device__ constexpr int sweep2i_mult(int rows) { return TYS / (4 * rows); }
 // Super-tile rows start one 64 x 4R tile row into the grid (y0 = 4R + TYS j,
 // j < sweep2i_rows), so that a quasi-periodic y seam leaves only the first
-// and the last tile row to the general kernel.
-__host__ __device__ inline int sweep2i_rows(int ny, int rows) {
+// and the last tile row to the general kernel -- unless the instance is
+// periodic in y with ny a multiple of TYS (seam2): then they start at
+// y0 = TYS j and the super-tiles on the seam apply its phase themselves.
+__host__ __device__ inline int sweep2i_rows(int ny, int rows, bool seam) {
+    if (seam) return ny / TYS;
     const int r = ny - 4 * rows;
     return r > 0 ? (r + TYS - 1) / TYS : 0;
 }
+__host__ __device__ inline int sweep2i_y0(int j, int rows, bool seam) { return (seam ? 0 : 4 * rows) + TYS * j; }
+__host__ __device__ inline bool seam2_ok(bool yper, int ny) { return yper && ny % TYS == 0; }
 
 // A tile every node of which, with its two-node halo, is a real node or a
 // plain periodic image in x: full in x, and its halo inside the grid in y
 // and (unless x is periodic) in x -- no quasi-periodic phase, no open-face
 // ghost, no node outside the grid.  Such tiles take the plain-load
 // two-sweep kernel.
-__host__ __device__ inline bool tile_interior2(int x0, int y0, int tyv, int nx, int ny, bool xper) {
+// seam: the y halo may cross the periodic y seam (seam2 instances).
+__host__ __device__ inline bool tile_interior2(int x0, int y0, int tyv, int nx, int ny, bool xper,
+                                               bool seam = false) {
     const bool xin = xper ? (x0 + TX <= nx) : (x0 >= 2 && x0 + TX + 2 <= nx);
-    return xin && y0 >= 2 && y0 + tyv + 2 <= ny;
+    return xin && (seam ? y0 + tyv <= ny : (y0 >= 2 && y0 + tyv + 2 <= ny));
 }
 
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
