@@ -397,17 +397,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 (FP32 complex psi) + f64 reductions",
+        "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "grid": [w.nx, w.ny, w.nz], "h": w.h, "B_eff": Bz, "J": w.J,
                    "inclusions": used, "inclusion_fraction": frac, "tol": w.tol, "dt": w.dt,
                    "mu_tol": 1e-5, "mu_rtol": args.mu_rtol,
                    "tiling": {"rows": tiling["rows"], "chunk": tiling["chunk"], "streaming": tiling["streaming"],
                               "fused": tiling["fused"], "persistent": tiling["persistent"]},
+                   "precision": "psi, links and sweeps in FP32 (complex64 storage); residual, J_av, K, "
+                                "means and the Poisson z solve in FP64",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": ("tdgl::k_sweep2 (two Jacobi sweeps per pass)" if tiling["fused"]
+                     "kernel": ("tdgl::k_sweep2i + tdgl::k_sweep2 (one two-sweep Jacobi pass: super-tiles, "
+                                "and boundary tiles where there are any)" if tiling["fused"]
                                 else "tdgl::k_stencil<1> (Jacobi sweep)"),
                      "sweeps_per_pass": 2 if tiling["fused"] else 1,
                      "bytes_per_launch": SWEEP_BYTES_PER_NODE * N, "mean_launch_ms": sweep_ms,
