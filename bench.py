@@ -80,9 +80,9 @@ def read_traffic(n_nodes, kernel):
         return None
 
 
-def setup(w, tdgl, inputs, torch, tol, mu_rtol):
+def setup(w, tdgl, inputs, torch, tol, mu_rtol, noise_T=0.0):
     p = tdgl.make_params(w.nx, w.ny, w.nz, h=w.h, driven=w.driven, tol=tol, max_iter=100,
-                         mu_tol=1e-5, mu_rtol=mu_rtol, mu_max_cycles=20)
+                         mu_tol=1e-5, mu_rtol=mu_rtol, mu_max_cycles=20, noise_T=noise_T, noise_seed=0x5EED)
     s = tdgl.Solver(p)
     Bx, Bz = s.set_field(0.0, w.B, quantize=True)
     if w.driven:
@@ -95,6 +95,28 @@ def setup(w, tdgl, inputs, torch, tol, mu_rtol):
     s.set_psi(torch.from_numpy(psi0).cuda())
     del psi0
     return s, Bz, used, frac
+
+
+def variant_bench(w, tdgl, inputs, torch, kind, steps, warmup, mu_rtol):
+    """The same workload with one of the paper's options switched on, timed
+    like the main line: "noise" -- the Langevin term (Eq. b) at T = 0.02;
+    "yz" -- the field turned into the yz plane, (By, Bz) = (0.1, B), which
+    the library runs with single sweeps."""
+    s, Bz, used, frac = setup(w, tdgl, inputs, torch, w.tol, mu_rtol, noise_T=0.02 if kind == "noise" else 0.0)
+    if kind == "yz":
+        s.set_field_yz(0.1, w.B, quantize=True)
+    tiling = s.autotune()
+    s.step(warmup, stats=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = s.step(steps, stats=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    s.close()
+    N = w.nx * w.ny * w.nz
+    return {"steps": steps, "ms_per_step": 1e3 * el / steps, "cell_updates_per_s": N * steps / el,
+            "sweeps_per_step": st["sweeps_sum"] / max(st["steps"], 1),
+            "tiling": {k: tiling[k] for k in ("rows", "chunk", "streaming", "fused", "persistent")}}
 
 
 def cpu_baseline(w, seconds_target=20.0):
@@ -277,6 +299,8 @@ def main():
                     help="steps of the c4 forward+adjoint comparison (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=20,
                     help="steps of the 64-instance batched comparison (0 skips it)")
+    ap.add_argument("--variant-steps", type=int, default=10,
+                    help="steps of the same workload with Langevin noise and with a yz-plane field (0 skips)")
     ap.add_argument("--tiling", default=None,
                     help="rows,chunk,streaming,fused[,persistent]: set the stencil tiling instead of tdgl_autotune")
     ap.add_argument("--study", choices=["jacobi"], default=None,
@@ -380,6 +404,14 @@ def main():
         log(f"[bench] batch {batch['batched_rate']:.3e} vs sequential {batch['sequential_rate']:.3e} "
             f"cell-updates/s (x{batch['speedup']:.2f})")
 
+    variants = None
+    if args.variant_steps > 0:
+        variants = {}
+        for kind in ("noise", "yz"):
+            variants[kind] = variant_bench(w, tdgl, inputs, torch, kind, args.variant_steps, 3, args.mu_rtol)
+            log(f"[bench] variant {kind}: {variants[kind]['ms_per_step']:.3f} ms/step, "
+                f"{variants[kind]['sweeps_per_step']:.2f} sweeps/step, tiling {variants[kind]['tiling']}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a bounded sample")
@@ -425,6 +457,7 @@ def main():
             "kernel_breakdown": breakdown,
             "adjoint": adj,
             "batch": batch,
+            "variants": variants,
             "E_mean": obs["E_mean"], "F": obs["F"], "psi2_mean": obs["psi2_mean"],
             "kernel_source_sha": kernel_sha(),
         },
