@@ -68,6 +68,12 @@ def test_hundred_undriven_steps():
     ((32, 32, 8), (False, False, False), 1.0, 0.0),    # fully periodic
     ((48, 20, 1), (False, False, True), 1.0, 0.0),     # one-node z axis (2D film)
     ((16, 16, 40), (False, True, False), 1.0, 0.15),   # open y, periodic z, Bx != 0
+    # degenerate axes
+    ((1, 40, 12), (False, False, True), 1.0, 0.0),     # one node in x, periodic: its own x neighbour
+    ((1, 24, 10), (True, False, True), 1.0, 0.1),      # one node in x, open: no x term at all
+    ((30, 1, 9), (False, False, True), 1.0, 0.0),      # one row in y, quasi-periodic onto itself
+    ((65, 2, 3), (False, True, True), 1.0, 0.0),       # two rows in y, both open faces
+    ((2, 3, 2), (False, False, False), 1.0, 0.0),      # a 12-node torus
 ])
 def test_one_step_boundary_variants(shape, open_, g_, Bx):
     c = Case(*shape, open_=open_, g=g_, Bx=Bx, Bz=0.12, tol=1e-12)
