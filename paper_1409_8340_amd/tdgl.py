@@ -278,6 +278,7 @@ class Solver:
     def set_eps(self, eps, inst=0):
         import torch
         eps = eps.to(device="cuda", dtype=torch.float32).contiguous()
+        torch.cuda.current_stream().synchronize()   # the library reads it on its own stream
         _check(load().tdgl_set_eps(self._ctx, inst, self._dev(eps, torch.float32)))
         self._keep = eps
 
@@ -292,6 +293,7 @@ class Solver:
         import torch
         c = torch.as_tensor(centres, dtype=torch.float64).reshape(-1, 3).contiguous().cuda()
         d = torch.as_tensor(diameters, dtype=torch.float64).reshape(-1).contiguous().cuda()
+        torch.cuda.current_stream().synchronize()
         used, frac = ctypes.c_int(), ctypes.c_double()
         _check(load().tdgl_gen_inclusions(self._ctx, inst, self._dev(c, torch.float64),
                                           self._dev(d, torch.float64), int(d.numel()), float(target),
@@ -303,6 +305,7 @@ class Solver:
         """shapes: (nc, 16) doubles per tdgl_gen_shapes (centre, Q, axis, hlen, ext)."""
         import torch
         sh = torch.as_tensor(shapes, dtype=torch.float64).reshape(-1, 16).contiguous().cuda()
+        torch.cuda.current_stream().synchronize()
         used, frac = ctypes.c_int(), ctypes.c_double()
         _check(load().tdgl_gen_shapes(self._ctx, inst, self._dev(sh, torch.float64), int(sh.shape[0]),
                                       float(target), float(eps_in), float(eps_out), ctypes.byref(used),
@@ -318,6 +321,7 @@ class Solver:
         vals = torch.as_tensor(values, dtype=torch.float32).reshape(-1).contiguous().cuda()
         if vals.numel() != sd.shape[0]:
             raise ValueError("one value per seed")
+        torch.cuda.current_stream().synchronize()
         _check(load().tdgl_gen_voronoi(self._ctx, inst, self._dev(sd, torch.float64), self._dev(vals, torch.float32),
                                        int(sd.shape[0]), int(metric), int(axes)))
 
@@ -334,6 +338,7 @@ class Solver:
     def set_psi(self, psi, inst=0):
         import torch
         psi = psi.to(device="cuda", dtype=torch.complex64).contiguous()
+        torch.cuda.current_stream().synchronize()   # the library reads it on its own stream
         _check(load().tdgl_set_psi(self._ctx, inst, self._dev(psi, torch.complex64)))
         self._stream.synchronize()
 
@@ -347,6 +352,7 @@ class Solver:
     def set_mu(self, mu, inst=0):
         import torch
         mu = mu.to(device="cuda", dtype=torch.float32).contiguous()
+        torch.cuda.current_stream().synchronize()   # the library reads it on its own stream
         _check(load().tdgl_set_mu(self._ctx, inst, self._dev(mu, torch.float32)))
         self._stream.synchronize()
 
