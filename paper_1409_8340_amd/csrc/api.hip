@@ -772,6 +772,15 @@ void launch_stencil_r(tdgl_ctx *c, int l, const float2 *in, float2 *out) {
                            c->d_pref_st, c->n, l, in, out, pub, c->pub_seq);
     }
 }
+template <int R, bool NT, bool YZ>
+void launch_sweep2_v(tdgl_ctx *c, int l, unsigned long long *pub) {
+    if (c->tot_b > 0)
+        hipLaunchKernelGGL((k_sweep2<R, NT, YZ>), dim3(c->tot_b), dim3(WG), 0, c->stream, c->d_inst, c->d_pref_b,
+                           c->n, l, pub, c->pub_seq);
+    if (c->tot_i > 0)
+        hipLaunchKernelGGL((k_sweep2i<R, NT, YZ>), dim3(c->tot_i), dim3(WG * sweep2i_mult(R)), 0, c->stream,
+                           c->d_inst, c->d_pref_i, c->n, l, pub, c->pub_seq);
+}
 // One two-sweep pass (l odd; l = -1: timing pass).
 template <int R>
 void launch_sweep2_r(tdgl_ctx *c, int l) {
@@ -780,25 +789,18 @@ void launch_sweep2_r(tdgl_ctx *c, int l) {
     // write disjoint tiles and read only psi^(l), b/M and (ht/2)/M; run
     // side by side on two streams they were slower than in sequence, the
     // boundary groups taking CU slots from the interior kernel for longer
-    // than the boundary kernel takes alone.
+    // than the boundary kernel takes alone.  Either grid can be empty (no
+    // boundary tiles when super-tiles cover every tile, no super-tile on
+    // grids too small for one); an instance without boundary tiles hands its
+    // rows over from the interior kernel.  YZ: a yz-plane field in the
+    // context (per-plane x-link factor).
     unsigned long long *pub = (c->pub_on && l > 0) ? c->d_pub : nullptr;
-    // (either grid can be empty: no boundary tiles when super-tiles cover
-    // every tile, no super-tile on grids too small to hold one; an instance
-    // without boundary tiles hands its rows over from the interior kernel)
-    if (c->nt) {
-        if (c->tot_b > 0)
-            hipLaunchKernelGGL((k_sweep2<R, true>), dim3(c->tot_b), dim3(WG), 0, c->stream, c->d_inst, c->d_pref_b,
-                               c->n, l, pub, c->pub_seq);
-        if (c->tot_i > 0)
-            hipLaunchKernelGGL((k_sweep2i<R, true>), dim3(c->tot_i), dim3(WG * sweep2i_mult(R)), 0, c->stream,
-                               c->d_inst, c->d_pref_i, c->n, l, pub, c->pub_seq);
+    if (c->any_yz) {
+        if (c->nt) launch_sweep2_v<R, true, true>(c, l, pub);
+        else launch_sweep2_v<R, false, true>(c, l, pub);
     } else {
-        if (c->tot_b > 0)
-            hipLaunchKernelGGL((k_sweep2<R, false>), dim3(c->tot_b), dim3(WG), 0, c->stream, c->d_inst,
-                               c->d_pref_b, c->n, l, pub, c->pub_seq);
-        if (c->tot_i > 0)
-            hipLaunchKernelGGL((k_sweep2i<R, false>), dim3(c->tot_i), dim3(WG * sweep2i_mult(R)), 0, c->stream,
-                               c->d_inst, c->d_pref_i, c->n, l, pub, c->pub_seq);
+        if (c->nt) launch_sweep2_v<R, true, false>(c, l, pub);
+        else launch_sweep2_v<R, false, false>(c, l, pub);
     }
 }
 void launch_sweep2(tdgl_ctx *c, int l) {
@@ -1167,17 +1169,16 @@ void drop_graph(tdgl_ctx *ctx) {
 }
 
 // Recompute whether some instance has a yz-plane field.  The stencil passes
-// then take their per-plane x-link variant and single sweeps (the two-sweep
-// and persistent forms have no such variant), and a captured step graph is
-// dropped because its launches change.
+// then take their per-plane x-link variants (the persistent solve has none
+// and is switched off), and a captured step graph is dropped because its
+// launches change.
 void update_any_yz(tdgl_ctx *ctx) {
     bool any = false;
     for (const auto &h : ctx->inst) any = any || h.yz;
     if (any != ctx->any_yz) drop_graph(ctx);
     ctx->any_yz = any;
-    if (any && (ctx->fused || ctx->persist)) {
+    if (any && ctx->persist) {
         drop_graph(ctx);
-        ctx->fused = false;
         ctx->persist = false;
     }
 }
@@ -1875,7 +1876,7 @@ tdgl_status apply_tiling(tdgl_ctx *ctx, const Tiling &t) {
     drop_graph(ctx);
     ctx->rows = t.rows;
     ctx->nt = t.nt != 0;
-    ctx->fused = t.fused != 0 && !ctx->any_yz;
+    ctx->fused = t.fused != 0;
     ctx->persist = t.persist != 0 && !ctx->fused && !ctx->any_yz;
     for (auto &h : ctx->inst) set_tiling(h, t.rows, t.chunk);
     return upload_tiling(ctx);
@@ -1952,8 +1953,7 @@ tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *ch
         const int chunks[] = {0, 4, 8, 16, 32, 64};
         const int rows[] = {1, 2, 4};
         best_us = 1e300;
-        // (a yz-plane field runs single sweeps only)
-        for (int fu = 0; fu < (ctx->any_yz ? 1 : 2); ++fu)
+        for (int fu = 0; fu < 2; ++fu)
         for (int nt = 0; nt < 2; ++nt)
         for (int r : rows)
             for (int c : chunks) {
@@ -2041,8 +2041,8 @@ tdgl_status tdgl_set_tiling(tdgl_ctx *ctx, const tdgl_tiling *t) {
         (t->persistent != 0 && t->persistent != 1))
         return fail(TDGL_EINVAL, "streaming, fused and persistent must be 0 or 1");
     if (t->fused && t->persistent) return fail(TDGL_EINVAL, "persistent solves use single sweeps (fused = 0)");
-    if (ctx->any_yz && (t->fused || t->persistent))
-        return fail(TDGL_EINVAL, "a context with a yz-plane field runs single sweeps (fused = persistent = 0)");
+    if (ctx->any_yz && t->persistent)
+        return fail(TDGL_EINVAL, "a context with a yz-plane field has no persistent solve (persistent = 0)");
     HIPCHK(hipStreamSynchronize(ctx->stream));
     Tiling s;
     s.rows = t->rows;

@@ -32,9 +32,17 @@ namespace tdgl {
 
 namespace {
 
+// x link of row y on plane p: the row's table entry, times the plane factor
+// wz[p] of a yz-plane field (YZ), computed as the single-sweep kernel does.
+template <bool YZ>
+__device__ __forceinline__ float2 xlink(const Inst &I, float2 u, int p) {
+    return YZ ? xcmul(u, I.wz[p]) : u;
+}
+
 // Jacobi update of the real node (sx, sy) of plane p from global memory,
 // in the domain's coordinates: the neighbours follow cell_src / zplane like
 // the tile path's LDS and register values do.
+template <bool YZ>
 __device__ __forceinline__ float2 node_update(const Inst &I, const gf2 *__restrict__ src,
                                               const gf2 *__restrict__ Pt, const gf2 *__restrict__ bhp,
                                               const gf2 *__restrict__ dhp, int sx, int sy, int p,
@@ -42,37 +50,50 @@ __device__ __forceinline__ float2 node_update(const Inst &I, const gf2 *__restri
     const int nx = I.nx, nz = I.nz;
     const unsigned pb = (unsigned)p * NXY;
     const unsigned so = (unsigned)(sy * nx + sx);
-    const float2 xm = fetch(src, Pt, pb, p, nx, cell_src(I, sx - 1, sy));
-    const float2 xp = fetch(src, Pt, pb, p, nx, cell_src(I, sx + 1, sy));
-    const float2 ym = fetch(src, Pt, pb, p, nx, cell_src(I, sx, sy - 1));
-    const float2 yp = fetch(src, Pt, pb, p, nx, cell_src(I, sx, sy + 1));
+    const float2 xm = fetch<YZ>(src, Pt, pb, p, nx, cell_src(I, sx - 1, sy), I.wz);
+    const float2 xp = fetch<YZ>(src, Pt, pb, p, nx, cell_src(I, sx + 1, sy), I.wz);
+    const float2 ym = fetch<YZ>(src, Pt, pb, p, nx, cell_src(I, sx, sy - 1), I.wz);
+    const float2 yp = fetch<YZ>(src, Pt, pb, p, nx, cell_src(I, sx, sy + 1), I.wz);
     const int pm = zplane(I, p, -1), pp = zplane(I, p, +1);
     const float2 zmv = pm >= 0 ? ld2(src, (unsigned)pm * NXY + so) : make_float2(0.f, 0.f);
     const float2 zpv = pp >= 0 ? ld2(src, (unsigned)pp * NXY + so) : make_float2(0.f, 0.f);
     const bool zm = (p > 0) || zper, zp = (p < nz - 1) || zper;
-    const float2 ns = nsum(I.ux[sy], I.uz[sy], xm, xp, ym, yp, zmv, zpv, zm, zp, I.cx, I.cy, I.cz);
+    const float2 ns = nsum(xlink<YZ>(I, I.ux[sy], p), I.uz[sy], xm, xp, ym, yp, zmv, zpv, zm, zp, I.cx, I.cy, I.cz);
     return jacobi(ld2(bhp, pb + so), ld2(dhp, pb + so), ns);
+}
+
+// The open-x ghost factor of slot s on plane p: s.fac (U^2 or its
+// conjugate), times wz[p]^2 (or its conjugate) for a yz-plane field, as
+// fetch<YZ> applies it.
+template <bool YZ>
+__device__ __forceinline__ float2 fac_at(const Inst &I, const CellSrc &s, int p) {
+    if (!YZ) return s.fac;
+    float2 w2 = xcmul(I.wz[p], I.wz[p]);
+    if (s.px) w2.y = -w2.y;
+    return xcmul(s.fac, w2);
 }
 
 // Value of the slot described by s (its boundary rule relative to the real
 // node s.off) in plane p, given that node's update v: the same operations
 // fetch() applies to a stored value.
-__device__ __forceinline__ float2 apply_src(const gf2 *__restrict__ Pt, int p, int nx, const CellSrc &s,
-                                            float2 v) {
+template <bool YZ>
+__device__ __forceinline__ float2 apply_src(const Inst &I, const gf2 *__restrict__ Pt, int p, int nx,
+                                            const CellSrc &s, float2 v) {
     if (s.mode == SRC_PLAIN) return v;
     if (s.mode == SRC_ZERO) return make_float2(0.f, 0.f);
-    if (s.mode == SRC_FAC) return xcmul(s.fac, v);
+    if (s.mode == SRC_FAC) return xcmul(fac_at<YZ>(I, s, p), v);
     const float2 ph = ld2(Pt, (unsigned)p * nx + s.px);
     return s.mode == SRC_P ? xcmul(ph, v) : xcmulc(ph, v);
 }
 
+template <bool YZ>
 __device__ __forceinline__ float2 slot_update(const Inst &I, const gf2 *__restrict__ src,
                                               const gf2 *__restrict__ Pt, const gf2 *__restrict__ bhp,
                                               const gf2 *__restrict__ dhp, const CellSrc &s, int p,
                                               unsigned NXY, bool zper) {
     if (s.mode == SRC_ZERO) return make_float2(0.f, 0.f);
     const int sy = s.off / I.nx, sx = s.off - sy * I.nx;
-    return apply_src(Pt, p, I.nx, s, node_update(I, src, Pt, bhp, dhp, sx, sy, p, NXY, zper));
+    return apply_src<YZ>(I, Pt, p, I.nx, s, node_update<YZ>(I, src, Pt, bhp, dhp, sx, sy, p, NXY, zper));
 }
 
 }  // namespace
@@ -97,7 +118,7 @@ __device__ __forceinline__ void halo2_cell(int h, int x0, int y0, int &gx, int &
     gy = y0 + ly - 2;
 }
 
-template <int R, bool NT>
+template <int R, bool NT, bool YZ>
 __global__ __launch_bounds__(WG) void k_sweep2(const Inst *__restrict__ insts, const int *__restrict__ prefix,
                                                int ninst, int l, unsigned long long *pub, unsigned seq) {
     constexpr int TYv = 4 * R;
@@ -232,10 +253,12 @@ __global__ __launch_bounds__(WG) void k_sweep2(const Inst *__restrict__ insts, c
     // psi^(l) of plane p: own values and halo values into registers
     auto load_a = [&](int p, float2 *ao, float2 *hv) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) ao[r] = (p < 0) ? make_float2(0.f, 0.f) : fetch(src, Pt, (unsigned)p * NXY, p, nx, own[r]);
+        for (int r = 0; r < R; ++r)
+            ao[r] = (p < 0) ? make_float2(0.f, 0.f) : fetch<YZ>(src, Pt, (unsigned)p * NXY, p, nx, own[r], I.wz);
 #pragma unroll
         for (int q = 0; q < 2; ++q)
-            hv[q] = (p < 0 || !h2on[q]) ? make_float2(0.f, 0.f) : fetch(src, Pt, (unsigned)p * NXY, p, nx, h2s[q]);
+            hv[q] = (p < 0 || !h2on[q]) ? make_float2(0.f, 0.f)
+                                        : fetch<YZ>(src, Pt, (unsigned)p * NXY, p, nx, h2s[q], I.wz);
     };
     auto stage_a = [&](int v, const float2 *ao, const float2 *hv) {
         float2 (*L)[LX] = la[v & 3];
@@ -316,14 +339,14 @@ __global__ __launch_bounds__(WG) void k_sweep2(const Inst *__restrict__ insts, c
                 const int ly = 2 + w * R + r, lx = 2 + lane;
                 if (vy[r]) {
                     const float2 c = L[ly][lx];
-                    const float2 ns = nsum(ux[r], uz[r], L[ly][lx - 1], L[ly][lx + 1], L[ly - 1][lx], L[ly + 1][lx],
-                                           Lm[ly][lx], Lp[ly][lx], zm, zp, cx, cy, cz);
+                    const float2 ns = nsum(xlink<YZ>(I, ux[r], p), uz[r], L[ly][lx - 1], L[ly][lx + 1], L[ly - 1][lx],
+                                           L[ly + 1][lx], Lm[ly][lx], Lp[ly][lx], zm, zp, cx, cy, cz);
                     b0[r] = jacobi(bhc[r], dhc[r], ns);
                     const float r2 = resid2(b0[r], c, dhc[r], ht2);
                     rmax1 = (r2 > rmax1 || r2 != r2) ? r2 : rmax1;
                 } else {
                     // a node outside the grid in a ragged tile: its ghost value
-                    b0[r] = slot_update(I, src, Pt, bhp, dhp, own[r], p, NXY, zper);
+                    b0[r] = slot_update<YZ>(I, src, Pt, bhp, dhp, own[r], p, NXY, zper);
                 }
                 lb[lq][ly - 1][lx - 1] = b0[r];
             }
@@ -331,12 +354,13 @@ __global__ __launch_bounds__(WG) void k_sweep2(const Inst *__restrict__ insts, c
             if (hthr) {
                 float2 val = make_float2(0.f, 0.f);
                 if (rmode == 1) {
-                    const float2 ns = nsum(rux, ruz, L[tly][tlx - 1], L[tly][tlx + 1], L[tly - 1][tlx],
-                                           L[tly + 1][tlx], Lm[tly][tlx], Lp[tly][tlx], zm, zp, cx, cy, cz);
+                    const float2 ns = nsum(xlink<YZ>(I, rux, p), ruz, L[tly][tlx - 1], L[tly][tlx + 1],
+                                           L[tly - 1][tlx], L[tly + 1][tlx], Lm[tly][tlx], Lp[tly][tlx], zm, zp, cx,
+                                           cy, cz);
                     val = jacobi(rbhc, rdhc, ns);
-                    if (rs.mode == SRC_FAC) val = xcmul(rfac, val);
+                    if (rs.mode == SRC_FAC) val = xcmul(YZ ? fac_at<YZ>(I, rs, p) : rfac, val);
                 } else if (rmode == 2) {
-                    val = slot_update(I, src, Pt, bhp, dhp, rs, p, NXY, zper);
+                    val = slot_update<YZ>(I, src, Pt, bhp, dhp, rs, p, NXY, zper);
                 }
                 lb[lq][rly][rlx] = val;
             }
@@ -355,8 +379,9 @@ __global__ __launch_bounds__(WG) void k_sweep2(const Inst *__restrict__ insts, c
             for (int r = 0; r < R; ++r) {
                 const int ly = 1 + w * R + r;
                 if (!vy[r]) continue;
-                const float2 ns = nsum(ux[r], uz[r], lb[lq][ly][lane], lb[lq][ly][lane + 2], lb[lq][ly - 1][lane + 1],
-                                       lb[lq][ly + 1][lane + 1], b2[r], b0[r], zm, zp, cx, cy, cz);
+                const float2 ns = nsum(xlink<YZ>(I, ux[r], pk), uz[r], lb[lq][ly][lane], lb[lq][ly][lane + 2],
+                                       lb[lq][ly - 1][lane + 1], lb[lq][ly + 1][lane + 1], b2[r], b0[r], zm, zp, cx,
+                                       cy, cz);
                 const float2 c2 = jacobi(bhq[r], dhq[r], ns);
                 const float r2 = resid2(c2, b1[r], dhq[r], ht2);
                 rmax2 = (r2 > rmax2 || r2 != r2) ? r2 : rmax2;
@@ -401,7 +426,7 @@ __global__ __launch_bounds__(WG) void k_sweep2(const Inst *__restrict__ insts, c
 // tiles of the other super-tiles.  NT: the new iterate is stored
 // non-temporally; b/M and (ht/2)/M stay cacheable, since the neighbours'
 // rings read them again.
-template <int R, bool NT>
+template <int R, bool NT, bool YZ>
 __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(const Inst *__restrict__ insts,
                                                                const int *__restrict__ prefix, int ninst, int l,
                                                                unsigned long long *pub, unsigned seq) {
@@ -637,8 +662,8 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
             for (int r = 0; r < R; ++r) {
                 const int ly = 2 + w * R + r, lx = 2 + lane;
                 const float2 c = L[ly][lx];
-                const float2 ns = nsum(ux[r], uz[r], L[ly][lx - 1], L[ly][lx + 1], L[ly - 1][lx], L[ly + 1][lx],
-                                       Lm[ly][lx], Lp[ly][lx], zm, zp, cx, cy, cz);
+                const float2 ns = nsum(xlink<YZ>(I, ux[r], p), uz[r], L[ly][lx - 1], L[ly][lx + 1], L[ly - 1][lx],
+                                       L[ly + 1][lx], Lm[ly][lx], Lp[ly][lx], zm, zp, cx, cy, cz);
                 b0[r] = jacobi(bhc[r], dhc[r], ns);
                 const float r2 = resid2(b0[r], c, dhc[r], ht2);
                 rmax1 = (r2 > rmax1 || r2 != r2) ? r2 : rmax1;
@@ -646,10 +671,11 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
             }
             if (hthr) {
                 if (seam && rcross) {
-                    lb[lq][rly][rlx] = slot_update(I, src, Pt, bhp, dhp, rcs, p, NXY, zper);
+                    lb[lq][rly][rlx] = slot_update<YZ>(I, src, Pt, bhp, dhp, rcs, p, NXY, zper);
                 } else {
-                    const float2 ns = nsum(rux, ruz, L[tly][tlx - 1], L[tly][tlx + 1], L[tly - 1][tlx],
-                                           L[tly + 1][tlx], Lm[tly][tlx], Lp[tly][tlx], zm, zp, cx, cy, cz);
+                    const float2 ns = nsum(xlink<YZ>(I, rux, p), ruz, L[tly][tlx - 1], L[tly][tlx + 1],
+                                           L[tly - 1][tlx], L[tly + 1][tlx], Lm[tly][tlx], Lp[tly][tlx], zm, zp, cx,
+                                           cy, cz);
                     lb[lq][rly][rlx] = jacobi(rbhc, rdhc, ns);
                 }
             }
@@ -666,8 +692,9 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int ly = 1 + w * R + r;
-                const float2 ns = nsum(ux[r], uz[r], lb[lq][ly][lane], lb[lq][ly][lane + 2], lb[lq][ly - 1][lane + 1],
-                                       lb[lq][ly + 1][lane + 1], b2[r], b0[r], zm, zp, cx, cy, cz);
+                const float2 ns = nsum(xlink<YZ>(I, ux[r], pk), uz[r], lb[lq][ly][lane], lb[lq][ly][lane + 2],
+                                       lb[lq][ly - 1][lane + 1], lb[lq][ly + 1][lane + 1], b2[r], b0[r], zm, zp, cx,
+                                       cy, cz);
                 const float2 c2 = jacobi(bh2[r], dh2[r], ns);
                 const float r2 = resid2(c2, b1[r], dh2[r], ht2);
                 rmax2 = (r2 > rmax2 || r2 != r2) ? r2 : rmax2;
@@ -696,15 +723,23 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
     }
 }
 
-#define TDGL_INST2(R, NT)                                                                                   \
-    template __global__ void k_sweep2<R, NT>(const Inst *, const int *, int, int, unsigned long long *, unsigned); \
-    template __global__ void k_sweep2i<R, NT>(const Inst *, const int *, int, int, unsigned long long *, unsigned);
-TDGL_INST2(1, false)
-TDGL_INST2(1, true)
-TDGL_INST2(2, false)
-TDGL_INST2(2, true)
-TDGL_INST2(4, false)
-TDGL_INST2(4, true)
+#define TDGL_INST2(R, NT, YZ)                                                                           \
+    template __global__ void k_sweep2<R, NT, YZ>(const Inst *, const int *, int, int, unsigned long long *,  \
+                                                 unsigned);                                                 \
+    template __global__ void k_sweep2i<R, NT, YZ>(const Inst *, const int *, int, int, unsigned long long *, \
+                                                  unsigned);
+TDGL_INST2(1, false, false)
+TDGL_INST2(1, true, false)
+TDGL_INST2(2, false, false)
+TDGL_INST2(2, true, false)
+TDGL_INST2(4, false, false)
+TDGL_INST2(4, true, false)
+TDGL_INST2(1, false, true)
+TDGL_INST2(1, true, true)
+TDGL_INST2(2, false, true)
+TDGL_INST2(2, true, true)
+TDGL_INST2(4, false, true)
+TDGL_INST2(4, true, true)
 #undef TDGL_INST2
 
 }  // namespace tdgl

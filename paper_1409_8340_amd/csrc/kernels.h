@@ -12,10 +12,10 @@ constexpr int JAV_CPT = 16;     // cells per thread of the flat reductions
 constexpr int CO_THREADS = 1024;
 constexpr int FIN_THREADS = 256;  // threads per instance of the solve finalizers
 
-template <int R, bool NT>
+template <int R, bool NT, bool YZ>
 __global__ void k_sweep2(const Inst *insts, const int *prefix, int ninst, int l, unsigned long long *pub,
                          unsigned seq);
-template <int R, bool NT>
+template <int R, bool NT, bool YZ>
 __global__ void k_sweep2i(const Inst *insts, const int *prefix, int ninst, int l, unsigned long long *pub,
                           unsigned seq);
 template <int R, bool NT>

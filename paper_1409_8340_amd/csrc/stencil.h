@@ -154,6 +154,7 @@ __device__ __forceinline__ CellSrc cell_src2(const Inst &I, int gx, int gy) {
         const float2 u2 = xcmul(I.ux[sy], I.ux[sy]);
         s.mode = SRC_FAC;
         s.fac = xmir < 0 ? u2 : make_float2(u2.x, -u2.y);
+        s.px = xmir > 0 ? 1 : 0;
     } else if (ymode != SRC_PLAIN) {
         s.mode = ymode;
         s.px = sx;

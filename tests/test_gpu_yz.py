@@ -134,34 +134,31 @@ def test_xz_instance_in_a_yz_context_is_unchanged():
 
 
 def test_yz_graph_steps_and_tilings():
-    """Graph-replayed steps equal eager steps; every single-sweep tiling
-    gives the same bits; two-sweep and persistent tilings and the adjoint
-    are refused; the autotuner keeps to single sweeps; a return to the xz
-    plane gives the xz results."""
+    """Graph-replayed steps equal eager steps; every tiling, two-sweep
+    passes included, gives the same bits; persistent tilings and the
+    adjoint are refused; a return to the xz plane gives the xz results."""
     c = YZCase(40, 36, 10, By=0.1, Bz=0.1, J=0.02, driven=True, tol=1e-10)
     a = c.solver()
     a.set_tiling(rows=2, chunk=0, streaming=0)
     a.step(3)
     ref = a.get_psi().cpu().numpy()
     a.close()
-    for rows, chunk, nt in ((1, 4, 0), (4, 0, 1), (2, 1, 1)):
+    for rows, chunk, nt, fu in ((1, 4, 0, 0), (4, 0, 1, 0), (2, 1, 1, 0), (1, 4, 0, 1), (2, 8, 1, 1), (4, 2, 0, 1)):
         b = c.solver()
-        b.set_tiling(rows=rows, chunk=chunk, streaming=nt)
+        b.set_tiling(rows=rows, chunk=chunk, streaming=nt, fused=fu)
         b.step(3)
-        assert np.array_equal(b.get_psi().cpu().numpy(), ref), (rows, chunk, nt)
+        assert np.array_equal(b.get_psi().cpu().numpy(), ref), (rows, chunk, nt, fu)
         b.close()
     g = c.solver()
     g.set_tiling(rows=2, chunk=0, streaming=0)
     g.step_graph(3, 60)
     assert np.array_equal(g.get_psi().cpu().numpy(), ref)
     with pytest.raises(tdgl.TdglError):
-        g.set_tiling(rows=2, chunk=0, streaming=0, fused=1)
-    with pytest.raises(tdgl.TdglError):
         g.set_tiling(rows=2, chunk=0, streaming=0, persistent=1)
     with pytest.raises(tdgl.TdglError):
         g.voltage_grad(4, 0, 2)
     t = g.autotune()
-    assert t["fused"] == 0 and t["persistent"] == 0
+    assert t["persistent"] == 0
     g.close()
     # back to the xz plane
     x = Case(40, 36, 10, Bz=0.1, J=0.02, driven=True, tol=1e-10)
@@ -176,6 +173,28 @@ def test_yz_graph_steps_and_tilings():
     assert np.array_equal(s1.get_psi().cpu().numpy(), s2.get_psi().cpu().numpy())
     s1.close()
     s2.close()
+
+
+@pytest.mark.parametrize("shape,open_", [((200, 48, 10), (False, False, True)), ((130, 64, 6), (False, False, True)),
+                                         ((96, 40, 7), (True, False, True))])
+def test_yz_two_sweep_passes_bit_identical(shape, open_):
+    """Two sweeps per pass with the per-plane x links (super-tiles on the
+    seam, boundary tiles, open x faces) give the single sweeps' bits, also
+    through graph replays."""
+    c = YZCase(*shape, open_=open_, By=0.13, Bz=0.11, J=0.02, driven=not open_[0], tol=1e-10)
+    c.eps = inputs.random_real(c.grid.shape, 7, 0.3, 1.0)
+    a, f = c.solver(), c.solver()
+    for rows in (1, 2):
+        a.set_tiling(rows=rows, chunk=4, fused=0)
+        f.set_tiling(rows=rows, chunk=4, fused=1)
+        sa, sf = a.step(2), f.step(2)
+        assert sa["sweeps_sum"] == sf["sweeps_sum"]
+        assert np.array_equal(a.get_psi().cpu().numpy(), f.get_psi().cpu().numpy()), rows
+    f.step_graph(2)
+    a.step(2)
+    assert np.array_equal(a.get_psi().cpu().numpy(), f.get_psi().cpu().numpy())
+    a.close()
+    f.close()
 
 
 def test_yz_needs_open_z_for_By():
