@@ -197,8 +197,7 @@ tdgl_status tdgl_quantize_field_yz(const tdgl_params *p, double By, double Bz,
  * xbar_i) psi, and every gauge-invariant quantity (|psi|^2, currents, mu~,
  * E, F) is the same.  By != 0 requires an open z axis (TDGL_EINVAL
  * otherwise).  A context holding a yz-plane field has no persistent solve
- * (that tiling is switched off and refused) and no adjoint
- * (tdgl_voltage_grad returns TDGL_EINVAL).  tdgl_set_field returns the
+ * (that tiling is switched off and refused).  tdgl_set_field returns the
  * instance to the xz plane.  quantize as for tdgl_set_field. */
 tdgl_status tdgl_set_field_yz(tdgl_ctx *ctx, int inst, double By, double Bz, int quantize,
                               double *By_eff, double *Bz_eff);

@@ -69,7 +69,7 @@ def poisson_T(grid, w, g):
 def forward(grid, p, eps, st0, nsteps, base_links=None):
     """Run nsteps exact steps from st0 (copied) and keep every state."""
     if base_links is None:
-        base_links = O.landau_links(grid, p.Bx, p.Bz, 0.0)
+        base_links = O.base_links_of(grid, p)
     st = O.State(psi=st0.psi.copy(), mu=st0.mu.copy(), K=st0.K)
     states = [(st.psi.copy(), st.mu.copy(), st.K)]
     Es = []
@@ -131,7 +131,7 @@ def step_vjp(grid, p, eps, prev, nxt, psibar, mubar, Kbar, Ebar_loss, base_links
 def voltage_grad(grid, p, eps, st0, nsteps, window_begin=0):
     """dVbar/deps for Vbar = mean of E_n over steps n >= window_begin
     (0-based within the run), exact forward.  Returns (Vbar, grad)."""
-    base = O.landau_links(grid, p.Bx, p.Bz, 0.0)
+    base = O.base_links_of(grid, p)
     states, Es = forward(grid, p, eps, st0, nsteps, base)
     W = nsteps - window_begin
     Vbar = float(np.mean(Es[window_begin:]))

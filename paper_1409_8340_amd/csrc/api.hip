@@ -754,15 +754,13 @@ template <int MODE, int R>
 void launch_stencil_r(tdgl_ctx *c, int l, const float2 *in, float2 *out) {
     constexpr bool can_nt = (MODE == MODE_SWEEP || is_first_mode(MODE));
     unsigned long long *pub = (MODE == MODE_SWEEP && c->pub_on && l > 0) ? c->d_pub : nullptr;
-    // a yz-plane field takes the variant with per-plane x links (the
-    // adjoint's NS mode has none: the adjoint rejects such contexts)
-    constexpr bool can_yz = MODE != MODE_NS;
-    if (can_yz && c->any_yz) {
+    // a yz-plane field takes the variant with per-plane x links
+    if (c->any_yz) {
         if (can_nt && c->nt)
-            hipLaunchKernelGGL((k_stencil<MODE, R, can_nt, can_yz>), dim3(c->tot_st), dim3(WG), 0, c->stream,
+            hipLaunchKernelGGL((k_stencil<MODE, R, can_nt, true>), dim3(c->tot_st), dim3(WG), 0, c->stream,
                                c->d_inst, c->d_pref_st, c->n, l, in, out, pub, c->pub_seq);
         else
-            hipLaunchKernelGGL((k_stencil<MODE, R, false, can_yz>), dim3(c->tot_st), dim3(WG), 0, c->stream,
+            hipLaunchKernelGGL((k_stencil<MODE, R, false, true>), dim3(c->tot_st), dim3(WG), 0, c->stream,
                                c->d_inst, c->d_pref_st, c->n, l, in, out, pub, c->pub_seq);
     } else if (can_nt && c->nt) {
         hipLaunchKernelGGL((k_stencil<MODE, R, can_nt, false>), dim3(c->tot_st), dim3(WG), 0, c->stream, c->d_inst,
@@ -2169,7 +2167,6 @@ tdgl_status tdgl_voltage_grad(tdgl_ctx *ctx, int nsteps, int window_begin, int c
     if (ctx->n != 1) return fail(TDGL_EINVAL, "tdgl_voltage_grad needs a context with one instance");
     const InstHost &h = ctx->inst[0];
     if (!h.p.driven) return fail(TDGL_EINVAL, "the voltage needs a driven instance (driven = 1)");
-    if (h.yz) return fail(TDGL_EINVAL, "the adjoint supports the xz-plane field only");
     if (nsteps < 1 || window_begin < 0 || window_begin >= nsteps || ckpt_every < 1)
         return fail(TDGL_EINVAL, "need nsteps >= 1, 0 <= window_begin < nsteps, ckpt_every >= 1");
     if (!grad || !vbar) return fail(TDGL_EINVAL, "null output");

@@ -22,6 +22,7 @@
 // The kernels act on instance 0 of a one-instance context; flat kernels use
 // a grid-stride loop over the nodes and write per-block partials.
 #include "kernels.h"
+#include "stencil.h"
 
 namespace tdgl {
 
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(256) void k_adj_edge_f(const Inst *__restrict__ ins
         const int mp = (i == I.nx - 1) ? m - (I.nx - 1) : m + 1;
         const float fb0 = node_w(I, i, j, k) * (I.mu[m] - mean);
         const float fb1 = node_w(I, (i == I.nx - 1) ? 0 : i + 1, j, k) * (I.mu[mp] - mean);
-        const float2 up = cmul(I.ux[j], psin[mp]);
+        const float2 up = cmul(xcmul(I.ux[j], I.wz[k]), psin[mp]);
         acc += (double)(fb0 - fb1) * (double)(psin[m].x * up.x + psin[m].y * up.y);
     }
     const double s = wg_sum<256>(acc, red);
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(256) void k_adj_jterm(const Inst *__restrict__ inst
         node_ijk(I, m, i, j, k);
         const int mp = (i == I.nx - 1) ? m - (I.nx - 1) : m + 1;
         const int mm = (i == 0) ? m + (I.nx - 1) : m - 1;
-        const float2 u = I.ux[j];
+        const float2 u = xcmul(I.ux[j], I.wz[k]);
         const float2 up = cmul(u, psin[mp]);
         const float2 t = csub(up, cmulc(u, psin[mm]));
         // c * (i t)
@@ -261,7 +262,7 @@ __global__ __launch_bounds__(256) void k_adj_edge_s(const Inst *__restrict__ ins
         const int mp = (i == I.nx - 1) ? m - (I.nx - 1) : m + 1;
         const float2 l0 = cscale(node_w(I, i, j, k) * sc, nu[m]);
         const float2 l1 = cscale(node_w(I, ip, j, k) * sc, nu[mp]);
-        const float2 u = I.ux[j];
+        const float2 u = xcmul(I.ux[j], I.wz[k]);
         const float2 s0 = cadd(psim[m], psin[m]), s1 = cadd(psim[mp], psin[mp]);
         const float2 a = cmulc(l0, cmul(u, s1));   // conj(lambda_m) U s_{m+x}
         const float2 bb = cmulc(cmul(l1, u), s0);  // conj(lambda_{m+x} U) s_m

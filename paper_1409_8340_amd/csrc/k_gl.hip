@@ -340,7 +340,7 @@ __global__ __launch_bounds__(WG) void k_jacobi_persist(const Inst *__restrict__ 
 #define TDGL_INST(M, R, NT, YZ)                                                                            \
     template __global__ void k_stencil<M, R, NT, YZ>(const Inst *, const int *, int, int, const float2 *, float2 *, \
                                                      unsigned long long *, unsigned);
-// YZ (a yz-plane field in the context): every mode but the adjoint's NS
+// YZ: a yz-plane field in the context (per-plane x-link factor)
 #define TDGL_INST_R(R)                      \
     TDGL_INST(MODE_FIRST, R, false, false)  \
     TDGL_INST(MODE_FIRST, R, true, false)   \
@@ -358,7 +358,8 @@ __global__ __launch_bounds__(WG) void k_jacobi_persist(const Inst *__restrict__ 
     TDGL_INST(MODE_SWEEP, R, false, true)   \
     TDGL_INST(MODE_SWEEP, R, true, true)    \
     TDGL_INST(MODE_RHS, R, false, true)     \
-    TDGL_INST(MODE_ENERGY, R, false, true)
+    TDGL_INST(MODE_ENERGY, R, false, true)  \
+    TDGL_INST(MODE_NS, R, false, true)
 TDGL_INST_R(1)
 TDGL_INST_R(2)
 TDGL_INST_R(4)

@@ -34,6 +34,17 @@ def test_ns_adjoint_dot_product(grid):
     assert abs(lhs - rhs) < 1e-12 * abs(lhs)
 
 
+@pytest.mark.parametrize("grid", GRIDS[:2])
+def test_ns_adjoint_dot_product_yz(grid):
+    # links of the yz-plane field (Eq. A_yz): x seam phases, y and z links varying along x
+    links = O.with_K(O.landau_links_yz(grid, 0.19, 0.27, 0.0), grid.hx, 0.3)
+    w = O.node_weights(grid)
+    v, u = _c(grid.shape, 41), _c(grid.shape, 42)
+    lhs = np.vdot(u, A.ns(grid, links, v))
+    rhs = np.vdot(A.ns_h(grid, links, w, u), v)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
 @pytest.mark.parametrize("grid", GRIDS)
 def test_poisson_transpose_dot_product(grid):
     w = O.node_weights(grid)
@@ -97,6 +108,31 @@ def test_voltage_gradient_against_finite_differences():
     cells = rng.choice(grid.N, 32, replace=False)
     d = 1e-4
     for m in cells:
+        idx = np.unravel_index(m, grid.shape)
+        vals = []
+        for sgn in (+1, -1):
+            e2 = eps.copy()
+            e2[idx] += sgn * d
+            _, Es = A.forward(grid, p, e2, st0, nsteps)
+            vals.append(np.mean(Es[wb:]))
+        fd = (vals[0] - vals[1]) / (2 * d)
+        assert abs(fd - grad[idx]) <= 1e-4 * max(abs(fd), 1e-3 * np.max(np.abs(grad))), (m, fd, grad[idx])
+
+
+def test_voltage_gradient_yz_against_finite_differences():
+    """dVbar/deps with a yz-plane field (Eq. B_yz, gauge of Eq. A_yz; the
+    x links carry K and the x seam carries the phases P_{j,k}), z open:
+    central differences with delta = 1e-4 on 16 random cells."""
+    grid = O.Grid(8, 6, 4, open_=(False, False, True))
+    By, Bz = O.quantize_field_yz(grid, 0.2, 0.4)
+    p = O.Params(By=By, Bz=Bz, plane="yz", J_ext=0.08, dt=0.1, driven=True, mode="exact")
+    eps = _r(grid.shape, 51, 0.3, 1.0)
+    st0 = O.new_state(grid, inputs.psi_init(8, 6, 4, 52).astype(np.complex128))
+    nsteps, wb = 5, 1
+    V, grad = A.voltage_grad(grid, p, eps, st0, nsteps, wb)
+    rng = np.random.default_rng(5)
+    d = 1e-4
+    for m in rng.choice(grid.N, 16, replace=False):
         idx = np.unravel_index(m, grid.shape)
         vals = []
         for sgn in (+1, -1):
