@@ -415,8 +415,9 @@ tdgl_status tdgl_adjoint_plan(const tdgl_ctx *ctx, int nsteps, int ckpt_every, s
  * last segment's states are kept from the forward run, so ckpt_every >=
  * nsteps recomputes nothing: the whole trajectory sits in the workspace,
  * 12 bytes per node and step).  ws/ws_bytes: the
- * workspace of tdgl_adjoint_plan (256-byte aligned).  The context ends in
- * the state after nsteps steps.  Synchronising. */
+ * workspace of tdgl_adjoint_plan (256-byte aligned).  The field may lie in
+ * the xz or the yz plane (the gradient and Vbar are gauge invariant).  The
+ * context ends in the state after nsteps steps.  Synchronising. */
 tdgl_status tdgl_voltage_grad(tdgl_ctx *ctx, int nsteps, int window_begin, int ckpt_every, void *ws,
                               size_t ws_bytes, double *vbar, float *grad_eps);
 
