@@ -167,8 +167,19 @@ __global__ __launch_bounds__(256) void k_jav_partial(const Inst *__restrict__ in
 
 // Deterministic fixed-order sum of `n` partials by one work-group.
 __device__ double wg_reduce_parts(const double *__restrict__ part, int n, double *red) {
+    // each thread sums its partials t, t + 256, ... in that order, with
+    // eight loads in flight before they are added
+    constexpr int B = 8;
     double a = 0.0;
-    for (int t = threadIdx.x; t < n; t += blockDim.x) a += part[t];
+    int t = threadIdx.x;
+    for (; t + (B - 1) * 256 < n; t += B * 256) {
+        double v[B];
+#pragma unroll
+        for (int c = 0; c < B; ++c) v[c] = part[t + c * 256];
+#pragma unroll
+        for (int c = 0; c < B; ++c) a += v[c];
+    }
+    for (; t < n; t += 256) a += part[t];
     return wg_sum<256>(a, red);
 }
 

@@ -211,20 +211,45 @@ __global__ __launch_bounds__(FFT_X_THREADS) void k_fft_x(const Inst *__restrict_
     const int rows = I.ny * I.nz;
     const int pairs = fft_x_pairs(nx);
     float2 *stw = sm + pairs * nx;
-    for (int t = threadIdx.x; t < nx; t += FFT_X_THREADS) stw[t] = I.twx[t];
+    // loads are issued XB per thread at a time (twiddles, then the rows)
+    // before any of them is stored to LDS
+    constexpr int XB = 4;
+    for (int t0 = threadIdx.x; t0 < nx; t0 += XB * FFT_X_THREADS) {
+        float2 v[XB];
+#pragma unroll
+        for (int c = 0; c < XB; ++c) {
+            const int t = t0 + c * FFT_X_THREADS;
+            v[c] = t < nx ? I.twx[t] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int c = 0; c < XB; ++c) {
+            const int t = t0 + c * FFT_X_THREADS;
+            if (t < nx) stw[t] = v[c];
+        }
+    }
     const int row0 = (blockIdx.x - prefix[ii]) * 2 * pairs;
     const float *in = in_ext ? in_ext : I.f;
     float *out = out_ext ? out_ext : I.mu;
     float2 *spec = I.spec;
     const float inv_nx = 1.0f / (float)nx, inv_p = 1.0f / (float)P;
     // sequence s (pair) holds rows row0 + 2 s (real part) and row0 + 2 s + 1
+    const int tot = pairs * nx;
     if (dir < 0) {
-        for (int t = threadIdx.x; t < pairs * nx; t += FFT_X_THREADS) {
-            const int s = fdiv(t, inv_nx), e = t - s * nx;
-            const int ra = row0 + 2 * s, rb = ra + 1;
-            const float a = ra < rows ? in[(size_t)ra * nx + e] : 0.f;
-            const float b = rb < rows ? in[(size_t)rb * nx + e] : 0.f;
-            sm[t] = make_float2(a, b);
+        for (int t0 = threadIdx.x; t0 < tot; t0 += XB * FFT_X_THREADS) {
+            float a[XB], b[XB];
+#pragma unroll
+            for (int c = 0; c < XB; ++c) {
+                const int t = t0 + c * FFT_X_THREADS;
+                const int s = fdiv(t, inv_nx), e = t - s * nx;
+                const int ra = row0 + 2 * s, rb = ra + 1;
+                a[c] = (t < tot && ra < rows) ? in[(size_t)ra * nx + e] : 0.f;
+                b[c] = (t < tot && rb < rows) ? in[(size_t)rb * nx + e] : 0.f;
+            }
+#pragma unroll
+            for (int c = 0; c < XB; ++c) {
+                const int t = t0 + c * FFT_X_THREADS;
+                if (t < tot) sm[t] = make_float2(a[c], b[c]);
+            }
         }
         __syncthreads();
         fft_lds<P2, FFT_X_THREADS, XC>(sm, nx, I.xrad, I.nxrad, pairs, nx, stw, -1.f);
@@ -240,16 +265,27 @@ __global__ __launch_bounds__(FFT_X_THREADS) void k_fft_x(const Inst *__restrict_
             if (rb < rows) spec[(size_t)rb * sp + k] = B;
         }
     } else {
-        for (int t = threadIdx.x; t < pairs * nx; t += FFT_X_THREADS) {
-            const int s = fdiv(t, inv_nx), k = t - s * nx;
-            const int ra = row0 + 2 * s, rb = ra + 1;
-            const bool lo = k < P;
-            const int kk = lo ? k : nx - k;
-            float2 A = ra < rows ? spec[(size_t)ra * sp + kk] : make_float2(0.f, 0.f);
-            float2 B = rb < rows ? spec[(size_t)rb * sp + kk] : make_float2(0.f, 0.f);
-            if (!lo) { A.y = -A.y; B.y = -B.y; }
-            // W = A + i B
-            sm[t] = make_float2(A.x - B.y, A.y + B.x);
+        for (int t0 = threadIdx.x; t0 < tot; t0 += XB * FFT_X_THREADS) {
+            float2 A[XB], B[XB];
+#pragma unroll
+            for (int c = 0; c < XB; ++c) {
+                const int t = t0 + c * FFT_X_THREADS;
+                const int s = fdiv(t, inv_nx), k = t - s * nx;
+                const int ra = row0 + 2 * s, rb = ra + 1;
+                const int kk = k < P ? k : nx - k;
+                A[c] = (t < tot && ra < rows) ? spec[(size_t)ra * sp + kk] : make_float2(0.f, 0.f);
+                B[c] = (t < tot && rb < rows) ? spec[(size_t)rb * sp + kk] : make_float2(0.f, 0.f);
+            }
+#pragma unroll
+            for (int c = 0; c < XB; ++c) {
+                const int t = t0 + c * FFT_X_THREADS;
+                if (t >= tot) continue;
+                const int k = t - fdiv(t, inv_nx) * nx;
+                float2 a = A[c], b = B[c];
+                if (k >= P) { a.y = -a.y; b.y = -b.y; }
+                // W = A + i B
+                sm[t] = make_float2(a.x - b.y, a.y + b.x);
+            }
         }
         __syncthreads();
         fft_lds<P2, FFT_X_THREADS, XC>(sm, nx, I.xrad, I.nxrad, pairs, nx, stw, +1.f);

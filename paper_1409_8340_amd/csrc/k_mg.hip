@@ -399,7 +399,20 @@ __global__ __launch_bounds__(256) void k_mu_mean_partial(const Inst *__restrict_
         const double vxy = (double)L.vol[0][q.x] * L.vol[1][q.y];
         const long nxy = (long)L.nx * L.ny, col = (long)q.y * L.nx + q.x;
         const float *src = which ? L.rhs : L.mu[0];
-        for (int k = q.k0; k < q.k1; ++k) acc += vxy * L.vol[2][k] * (double)src[k * nxy + col];
+        // eight planes' loads in flight before they are summed in plane order
+        constexpr int KB = 8;
+        int k = q.k0;
+        for (; k + KB <= q.k1; k += KB) {
+            float v[KB], wv[KB];
+#pragma unroll
+            for (int c = 0; c < KB; ++c) {
+                v[c] = src[(k + c) * nxy + col];
+                wv[c] = L.vol[2][k + c];
+            }
+#pragma unroll
+            for (int c = 0; c < KB; ++c) acc += vxy * wv[c] * (double)v[c];
+        }
+        for (; k < q.k1; ++k) acc += vxy * L.vol[2][k] * (double)src[k * nxy + col];
     }
     const double s = wg_sum<256>(acc, red);
     if (threadIdx.x == 0) I.part[lb] = s;
