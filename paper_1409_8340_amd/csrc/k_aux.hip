@@ -165,7 +165,7 @@ __global__ __launch_bounds__(256) void k_jav_partial(const Inst *__restrict__ in
     if (threadIdx.x == 0) I.part[lb] = s;
 }
 
-// Deterministic fixed-order sum of `n` partials by one work-group.
+// Deterministic fixed-order sum of `n` partials by one 256-thread work-group.
 __device__ double wg_reduce_parts(const double *__restrict__ part, int n, double *red) {
     // each thread sums its partials t, t + 256, ... in that order, with
     // eight loads in flight before they are added
