@@ -100,8 +100,7 @@ def setup(w, tdgl, inputs, torch, tol, mu_rtol, noise_T=0.0):
 def variant_bench(w, tdgl, inputs, torch, kind, steps, warmup, mu_rtol):
     """The same workload with one of the paper's options switched on, timed
     like the main line: "noise" -- the Langevin term (Eq. b) at T = 0.02;
-    "yz" -- the field turned into the yz plane, (By, Bz) = (0.1, B), which
-    the library runs with single sweeps."""
+    "yz" -- the field turned into the yz plane, (By, Bz) = (0.1, B)."""
     s, Bz, used, frac = setup(w, tdgl, inputs, torch, w.tol, mu_rtol, noise_T=0.02 if kind == "noise" else 0.0)
     if kind == "yz":
         s.set_field_yz(0.1, w.B, quantize=True)
@@ -185,6 +184,39 @@ def adjoint_ratio(tdgl, inputs, torch, nsteps, ckpt, warmup):
     return {"workload": w.name, "steps": nsteps, "ckpt_every": ckpt, "warmup": warmup,
             "plain_ms_per_step": 1e3 * t_fwd / nsteps, "fwd_adj_ms_per_step": 1e3 * t_adj / nsteps,
             "ratio": t_adj / t_fwd, "Vbar": v, "grad_l2": gn}
+
+
+def small_bench(tdgl, inputs, torch, name, steps, warmup):
+    """A small workload, where launches rather than HBM set the pace: steps
+    per second with plain tdgl_step (the host follows convergence) and with
+    graph-replayed steps (each step one captured launch sequence with a fixed
+    sweep budget taken from the timed eager steps), continuing from the same
+    run."""
+    w = inputs.WORKLOADS[name]
+    s, Bz, used, frac = setup(w, tdgl, inputs, torch, w.tol, 0.03)
+    tiling = s.autotune()
+    s.step(warmup, stats=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = s.step(steps, stats=True)
+    torch.cuda.synchronize()
+    t_e = time.perf_counter() - t0
+    budget = min(100, st["sweeps_max"] + max(2, st["sweeps_max"] // 4))
+    s.step_graph(1, budget, stats=False)  # capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sg = s.step_graph(steps, budget, stats=True)
+    torch.cuda.synchronize()
+    t_g = time.perf_counter() - t0
+    s.close()
+    n = w.nx * w.ny * w.nz
+    return {"workload": w.name, "nodes": n, "driven": w.driven, "steps": steps, "warmup": warmup,
+            "tiling": {k: tiling[k] for k in ("rows", "chunk", "streaming", "fused", "persistent")},
+            "eager_us_per_step": 1e6 * t_e / steps, "eager_rate": n * steps / t_e,
+            "eager_sweeps_per_step": st["sweeps_sum"] / steps,
+            "graph_us_per_step": 1e6 * t_g / steps, "graph_rate": n * steps / t_g,
+            "graph_sweeps_per_step": sg["sweeps_sum"] / steps, "graph_sweep_budget": budget,
+            "graph_capped_steps": sg["capped_steps"]}
 
 
 def batch_bench(tdgl, inputs, torch, steps, warmup, n=64):
@@ -299,6 +331,9 @@ def main():
                     help="steps of the c4 forward+adjoint comparison (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=20,
                     help="steps of the 64-instance batched comparison (0 skips it)")
+    ap.add_argument("--small-steps", type=int, default=200,
+                    help="steps of the small-workload lines (32x32x16 undriven, 256x256x64 driven), eager "
+                         "and graph-replayed (0 skips them)")
     ap.add_argument("--variant-steps", type=int, default=10,
                     help="steps of the same workload with Langevin noise and with a yz-plane field (0 skips)")
     ap.add_argument("--tiling", default=None,
@@ -412,6 +447,16 @@ def main():
             log(f"[bench] variant {kind}: {variants[kind]['ms_per_step']:.3f} ms/step, "
                 f"{variants[kind]['sweeps_per_step']:.2f} sweeps/step, tiling {variants[kind]['tiling']}")
 
+    small = None
+    if args.small_steps > 0:
+        small = {}
+        for name in ("c1_small_undriven", "c2_256x256x64_J0.02"):
+            small[name] = small_bench(tdgl, inputs, torch, name, args.small_steps, 20)
+            r = small[name]
+            log(f"[bench] {name}: {r['eager_us_per_step']:.1f} us/step eager, {r['graph_us_per_step']:.1f} "
+                f"us/step graph-replayed ({r['eager_sweeps_per_step']:.2f} / {r['graph_sweeps_per_step']:.2f} "
+                f"sweeps/step)")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a bounded sample")
@@ -458,6 +503,7 @@ def main():
             "adjoint": adj,
             "batch": batch,
             "variants": variants,
+            "small": small,
             "E_mean": obs["E_mean"], "F": obs["F"], "psi2_mean": obs["psi2_mean"],
             "kernel_source_sha": kernel_sha(),
         },
