@@ -498,9 +498,24 @@ __global__ __launch_bounds__(ZS_THREADS) void k_fft_zsolve(const Inst *__restric
     const int tk = min(ZTK, P - kx0);
     const size_t zstride = (size_t)ny * sp;
     float2 *spec = I.spec + (size_t)ky * sp + kx0;
-    for (int t = threadIdx.x; t < nz * ZTK; t += ZS_THREADS) {
-        const int k = t / ZTK, c = t - k * ZTK;
-        tile[k * ZPAD + c] = c < tk ? spec[(size_t)k * zstride + c] : make_float2(0.f, 0.f);
+    // loads are issued ZB per thread at a time before any of them is
+    // stored to LDS
+    constexpr int ZB = 8;
+    const int tot = nz * ZTK;
+    for (int t0 = threadIdx.x; t0 < tot; t0 += ZB * ZS_THREADS) {
+        float2 v[ZB];
+#pragma unroll
+        for (int q = 0; q < ZB; ++q) {
+            const int t = t0 + q * ZS_THREADS;
+            const int k = t / ZTK, c = t - k * ZTK;
+            v[q] = (t < tot && c < tk) ? spec[(size_t)k * zstride + c] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int q = 0; q < ZB; ++q) {
+            const int t = t0 + q * ZS_THREADS;
+            const int k = t / ZTK, c = t - k * ZTK;
+            if (t < tot) tile[k * ZPAD + c] = v[q];
+        }
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -509,11 +524,25 @@ __global__ __launch_bounds__(ZS_THREADS) void k_fft_zsolve(const Inst *__restric
     constexpr int RMAX = FFT_ZMAX / 64;
     const int rpl = (nz + 63) >> 6;
     const int k0 = lane * rpl;
+    // pivots of the wavefront's next column are loaded while the current
+    // one is solved
+    double ipn[RMAX];
+    auto load_piv = [&](int c, double *dst) {
+        const double *ipc = I.zip + ((size_t)ky * P + kx0 + c) * nz;
+#pragma unroll
+        for (int q = 0; q < RMAX; ++q) {
+            const int k = k0 + q;
+            dst[q] = (c < tk && q < rpl && k < nz) ? ipc[k] : 0.0;
+        }
+    };
+    load_piv(w, ipn);
     for (int c = w; c < tk; c += 4) {
         const int kx = kx0 + c;
         const bool singular = (kx == 0 && ky == 0);
-        const double *ipc = I.zip + ((size_t)ky * P + kx) * nz;
         double yr[RMAX], yi[RMAX], ip[RMAX];
+#pragma unroll
+        for (int q = 0; q < RMAX; ++q) ip[q] = ipn[q];
+        load_piv(c + 4, ipn);
 #pragma unroll
         for (int q = 0; q < RMAX; ++q) {
             const int k = k0 + q;
@@ -521,7 +550,6 @@ __global__ __launch_bounds__(ZS_THREADS) void k_fft_zsolve(const Inst *__restric
             const float2 v = ok ? tile[k * ZPAD + c] : make_float2(0.f, 0.f);
             yr[q] = v.x;
             yi[q] = v.y;
-            ip[q] = ok ? ipc[k] : 0.0;
         }
         // the singular column: project the right side onto the range
         // (zero weighted mean) and pin row 0
