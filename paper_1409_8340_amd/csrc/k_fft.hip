@@ -320,9 +320,24 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(const Inst *__restrict__ 
     const float inv_tk = 1.0f / (float)TK;
     float2 *stw = sm + TK * ny;
     for (int t = threadIdx.x; t < ny; t += FFT_THREADS) stw[t] = I.twy[t];
-    for (int t = threadIdx.x; t < ny * TK; t += FFT_THREADS) {
-        const int y = fdiv(t, inv_tk), c = t - y * TK;
-        sm[c * ny + y] = c < tk ? spec[(size_t)y * sp + kx0 + c] : make_float2(0.f, 0.f);
+    // loads are issued YB per thread at a time before any of them is
+    // stored to LDS
+    constexpr int YB = 8;
+    const int tot = ny * TK;
+    for (int t0 = threadIdx.x; t0 < tot; t0 += YB * FFT_THREADS) {
+        float2 v[YB];
+#pragma unroll
+        for (int q = 0; q < YB; ++q) {
+            const int t = t0 + q * FFT_THREADS;
+            const int y = fdiv(t, inv_tk), c = t - y * TK;
+            v[q] = (t < tot && c < tk) ? spec[(size_t)y * sp + kx0 + c] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int q = 0; q < YB; ++q) {
+            const int t = t0 + q * FFT_THREADS;
+            const int y = fdiv(t, inv_tk), c = t - y * TK;
+            if (t < tot) sm[c * ny + y] = v[q];
+        }
     }
     __syncthreads();
     fft_lds<P2, FFT_THREADS, FFT_MAXPTS>(sm, ny, I.yrad, I.nyrad, TK, ny, stw, (float)dir);
