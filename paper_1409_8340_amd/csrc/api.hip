@@ -394,6 +394,7 @@ struct tdgl_ctx {
     int *d_pref_fx = nullptr, *d_pref_fy = nullptr, *d_pref_fz = nullptr;
     int tot_fx = 0, tot_fy = 0, tot_fz = 0;
     size_t fx_lds = 0, fy_lds = 0, fz_lds = 0;
+    int fz_nzmax = 0;  // deepest z over the instances: scan rows per lane of the z solve
     bool fx_p2 = true, fy_p2 = true;  // every spectral instance has power-of-two nx (ny)
     bool fx_long = false;             // some spectral instance has nx > FFT_X_PTS
     bool noisy = false;               // some instance has a Langevin term
@@ -662,6 +663,7 @@ tdgl_status upload_tables(tdgl_ctx *ctx) {
         pfy[i + 1] = pfy[i] + h.fy_blocks;
         pfz[i + 1] = pfz[i] + h.fz_blocks;
         ctx->noisy = ctx->noisy || h.d.zeta_max > 0.f;
+        ctx->fz_nzmax = std::max(ctx->fz_nzmax, h.p.nz);
         if (h.d.fft) {
             ctx->any_fft = true;
             ctx->fx_lds = std::max(ctx->fx_lds, (size_t)(fft_x_pairs(h.p.nx) + 1) * h.p.nx * 8);
@@ -695,8 +697,8 @@ tdgl_status upload_tables(tdgl_ctx *ctx) {
                                    (int)ctx->fy_lds));
         HIPCHK(hipFuncSetAttribute((const void *)k_fft_y<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)ctx->fy_lds));
-        HIPCHK(hipFuncSetAttribute((const void *)k_fft_zsolve, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)ctx->fz_lds));
+        for (const void *fn : {(const void *)k_fft_zsolve<2>, (const void *)k_fft_zsolve<4>})
+            HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ctx->fz_lds));
     }
     HIPCHK(hipMemcpy(ctx->d_pref_st, ps.data(), (n + 1) * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_pref_flat, pf.data(), (n + 1) * 4, hipMemcpyHostToDevice));
@@ -1085,8 +1087,12 @@ tdgl_status enqueue_fft(tdgl_ctx *ctx) {
     };
     xpass(-1);
     ypass(-1);
-    hipLaunchKernelGGL(k_fft_zsolve, dim3(std::max(ctx->tot_fz, 1)), dim3(256), ctx->fz_lds, s, ctx->d_inst,
-                       ctx->d_pref_fz, n);
+    if (ctx->fz_nzmax <= 128)
+        hipLaunchKernelGGL(k_fft_zsolve<2>, dim3(std::max(ctx->tot_fz, 1)), dim3(256), ctx->fz_lds, s, ctx->d_inst,
+                           ctx->d_pref_fz, n);
+    else
+        hipLaunchKernelGGL(k_fft_zsolve<4>, dim3(std::max(ctx->tot_fz, 1)), dim3(256), ctx->fz_lds, s, ctx->d_inst,
+                           ctx->d_pref_fz, n);
     ypass(+1);
     xpass(+1);
     LAUNCHCHK();

@@ -496,6 +496,10 @@ __device__ __forceinline__ void zsolve_lane(const Inst &I, int lb) {
         if (k < nz) spec[(size_t)k * zstride] = make_float2((float)yr[k], (float)yi[k]);
 }
 
+// RMAX: z rows per lane of the scan, at least ceil(nz / 64) for every
+// instance of the launch (2 up to nz = 128, else 4): fewer registers, more
+// work-groups per CU for the common depths.
+template <int RMAX>
 __global__ __launch_bounds__(ZS_THREADS) void k_fft_zsolve(const Inst *__restrict__ insts,
                                                             const int *__restrict__ prefix,
                                                             int ninst) {
@@ -536,7 +540,7 @@ __global__ __launch_bounds__(ZS_THREADS) void k_fft_zsolve(const Inst *__restric
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const double cz = I.cz;
     const double scale = 1.0 / ((double)nx * (double)ny);
-    constexpr int RMAX = FFT_ZMAX / 64;
+    static_assert(RMAX * 64 <= FFT_ZMAX, "scan rows per lane");
     const int rpl = (nz + 63) >> 6;
     const int k0 = lane * rpl;
     // pivots of the wavefront's next column are loaded while the current
@@ -703,5 +707,8 @@ __global__ __launch_bounds__(ZS_THREADS) void k_fft_zsolve(const Inst *__restric
         if (c < tk) spec[(size_t)k * zstride + c] = tile[k * ZPAD + c];
     }
 }
+
+template __global__ void k_fft_zsolve<2>(const Inst *, const int *, int);
+template __global__ void k_fft_zsolve<4>(const Inst *, const int *, int);
 
 }  // namespace tdgl

@@ -56,13 +56,14 @@ __global__ void k_fft_x(const Inst *insts, const int *prefix, int ninst, int dir
                         float *out_ext);
 template <bool P2>
 __global__ void k_fft_y(const Inst *insts, const int *prefix, int ninst, int dir);
+template <int RMAX>
 __global__ void k_fft_zsolve(const Inst *insts, const int *prefix, int ninst);
 __global__ void k_fft_tables(const Inst *insts, int inst);
 __host__ __device__ int fft_x_pairs(int nx);
 __host__ __device__ int fft_y_cols(int ny);
 __host__ __device__ int fft_pitch(int nx);
 __host__ __device__ size_t fft_z_lds(int nz);
-constexpr int FFT_ZTK = 32;     // kx columns per work-group of the z solve
+constexpr int FFT_ZTK = 16;     // kx columns per work-group of the z solve
 constexpr int FFT_ZMAX = 256;   // largest nz of the spectral path
 constexpr int FFT_ZSERIAL = 16; // up to this nz one lane solves a whole z system (no wavefront scan)
 constexpr int FFT_MAXN = 8192;  // points per work-group of the x and y passes
