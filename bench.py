@@ -118,11 +118,24 @@ def variant_bench(w, tdgl, inputs, torch, kind, steps, warmup, mu_rtol):
             "tiling": {k: tiling[k] for k in ("rows", "chunk", "streaming", "fused", "persistent")}}
 
 
-def cpu_baseline(w, seconds_target=20.0):
+def host_cpu_model():
+    """Model name of the host CPU (first processor in /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, seconds_target=20.0, seconds_1t=12.0):
     """FP64 oracle on a bounded sample: the workload's physics (h, B, J,
     inclusion law and fraction, psi init, Jacobi stop rule) on a
     256 x 256 x min(nz, 128) sub-box, as many steps as fit the time target
-    (at least one).  Returns the entry for the JSON line."""
+    (at least one), on all host threads the oracle is given; then the same
+    sample continued on one thread.  Returns the entry for the JSON line."""
     import numpy as np
     from oracle import oracle as O
     from paper_1409_8340_amd import inputs
@@ -138,22 +151,34 @@ def cpu_baseline(w, seconds_target=20.0):
         eps, _, _ = O.gen_inclusions(grid, cen, dia, w.fraction)
     st = O.new_state(grid, inputs.psi_init(nx, ny, nz, w.psi_seed).astype(np.complex128))
     p = O.Params(Bx=Bx, Bz=Bz, J_ext=w.J, dt=w.dt, tol=w.tol, mode="mirror", driven=w.driven)
+
+    def timed(target):
+        t0 = time.perf_counter()
+        steps = 0
+        while True:
+            O.step(grid, p, eps, st)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el >= target or steps >= 50:
+                break
+            if el / steps * (steps + 1) > 1.5 * target:
+                break
+        return steps, time.perf_counter() - t0
+
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    t0 = time.perf_counter()
-    steps = 0
-    while True:
-        O.step(grid, p, eps, st)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= seconds_target or steps >= 50:
-            break
-        if el / steps * (steps + 1) > 1.5 * seconds_target:
-            break
-    el = time.perf_counter() - t0
+    O.set_threads(threads)
+    steps, el = timed(seconds_target)
+    one = None
+    if seconds_1t > 0:
+        O.set_threads(1)
+        s1, e1 = timed(seconds_1t)
+        O.set_threads(threads)
+        one = {"value": grid.N * s1 / e1, "steps": s1, "seconds": round(e1, 2)}
     return {"value": grid.N * steps / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"FP64 oracle, {nx}x{ny}x{nz} sub-box of the workload's physics, {steps} steps from "
                       f"the seeded initial state, Jacobi stop rule max|r|^2<{w.tol:g} (same as GPU), exact "
-                      f"Poisson; {el:.1f} s on {threads} OpenMP threads"}
+                      f"Poisson; {el:.1f} s on {threads} OpenMP threads",
+            "host_cpu": host_cpu_model(), "one_thread": one}
 
 
 def adjoint_ratio(tdgl, inputs, torch, nsteps, ckpt, warmup):
@@ -279,6 +304,36 @@ def batch_bench(tdgl, inputs, torch, steps, warmup, n=64):
             "sequential_sweeps_sum": sweeps_s}
 
 
+def iv_study(tdgl, inputs, torch, w, points, steps, window, mu_rtol):
+    """The workload's current sweep (Sec. 3.1.1, current-voltage
+    characteristics): J = 0 .. 0.06 in `points` equal steps, ascending, the
+    state carried from one point to the next; at each point `steps` steps,
+    the time-averaged field <E_x> over the last `window`.  One JSON line per
+    point (V = Lx <E_x> as well)."""
+    s, Bz, used, frac = setup(w, tdgl, inputs, torch, w.tol, mu_rtol)
+    tiling = s.autotune()
+    Lx = w.nx * w.h
+    for q in range(points):
+        J = 0.06 * q / max(points - 1, 1)
+        s.set_current(J)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        a = s.step(steps - window, stats=True)
+        s.window_reset()
+        b = s.step(window, stats=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        obs = s.observables()
+        print(json.dumps({"study": "iv", "workload": w.name, "J": J, "steps": steps, "window": window,
+                          "E_mean": obs["E_mean"], "V_mean": obs["E_mean"] * Lx, "psi2_mean": obs["psi2_mean"],
+                          "sweeps_per_step": (a["sweeps_sum"] + b["sweeps_sum"]) / steps,
+                          "capped_steps": a["capped_steps"] + b["capped_steps"],
+                          "ms_per_step": 1e3 * el / steps, "B_eff": Bz, "inclusions": used,
+                          "tiling": {k: tiling[k] for k in ("rows", "chunk", "streaming", "fused")}}),
+              flush=True)
+    s.close()
+
+
 def jacobi_study(tdgl, inputs, torch, steps, warmup):
     """The paper's Fig. 5 study on this solver: Jacobi iterations per step
     and time per step of a 2D free-flowing vortex film (one z plane, no
@@ -338,9 +393,14 @@ def main():
                     help="steps of the same workload with Langevin noise and with a yz-plane field (0 skips)")
     ap.add_argument("--tiling", default=None,
                     help="rows,chunk,streaming,fused[,persistent]: set the stencil tiling instead of tdgl_autotune")
-    ap.add_argument("--study", choices=["jacobi"], default=None,
-                    help="instead of the benchmark line, run the Jacobi iteration study (2D film: iterations "
-                         "and time per step against grid size, spacing and tolerance), one JSON line per point")
+    ap.add_argument("--study", choices=["jacobi", "iv"], default=None,
+                    help="instead of the benchmark line: 'jacobi', the Jacobi iteration study (2D film: "
+                         "iterations and time per step against grid size, spacing and tolerance); 'iv', the "
+                         "workload's current sweep J = 0..0.06 in 13 points (--steps per point, <E> over the "
+                         "last half); one JSON line per point")
+    ap.add_argument("--flow-warmup", type=int, default=200,
+                    help="untimed steps after the timed region before the flowing-state figure (0 skips it)")
+    ap.add_argument("--flow-steps", type=int, default=20, help="timed steps of the flowing-state figure")
     ap.add_argument("--copy-calib-gib", type=float, default=0.0,
                     help="run a plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -358,6 +418,9 @@ def main():
         jacobi_study(tdgl, inputs, torch, args.steps, args.warmup)
         return
     w = inputs.WORKLOADS[args.workload]
+    if args.study == "iv":
+        iv_study(tdgl, inputs, torch, w, 13, args.steps, args.steps // 2, args.mu_rtol)
+        return
     N = w.nx * w.ny * w.nz
 
     log(f"[bench] setting up {w.name} ({N} nodes)")
@@ -408,6 +471,24 @@ def main():
                          "share": round(v["ms"] / tot, 4) if tot else 0.0} for k, v in bd.items()}
     obs = s.observables()
 
+    flowing = None
+    if args.flow_warmup > 0 and args.flow_steps > 0:
+        # the same run further on: vortices flowing rather than the start's transient
+        s.step(args.flow_warmup, stats=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fs = s.step(args.flow_steps, stats=True)
+        torch.cuda.synchronize()
+        fe = time.perf_counter() - t0
+        fo = s.observables()
+        done = args.warmup + args.steps + args.breakdown_steps + args.flow_warmup
+        flowing = {"after_steps": done, "steps": args.flow_steps, "ms_per_step": 1e3 * fe / args.flow_steps,
+                   "cell_updates_per_s": N * args.flow_steps / fe,
+                   "sweeps_per_step": fs["sweeps_sum"] / max(fs["steps"], 1),
+                   "E_last": fo["E_last"], "psi2_mean": fo["psi2_mean"]}
+        log(f"[bench] flowing state after {done} steps: {flowing['ms_per_step']:.3f} ms/step, "
+            f"{flowing['sweeps_per_step']:.2f} sweeps/step")
+
     sw = prof["sweep"]
     # Sweep-class launches that did a full pass over the grid (the library
     # counts them: the first iterate of a step comes from the assemble kernel,
@@ -425,9 +506,9 @@ def main():
     adj = None
     if args.adjoint_steps > 0:
         log(f"[bench] c4 forward+adjoint over {args.adjoint_steps} steps")
-        adj = adjoint_ratio(tdgl, inputs, torch, args.adjoint_steps, 50, 100)
+        adj = adjoint_ratio(tdgl, inputs, torch, args.adjoint_steps, 50, 1000)
         # the same with every state of the window kept in HBM (no recompute)
-        whole = adjoint_ratio(tdgl, inputs, torch, args.adjoint_steps, args.adjoint_steps, 100)
+        whole = adjoint_ratio(tdgl, inputs, torch, args.adjoint_steps, args.adjoint_steps, 1000)
         adj["whole_trajectory"] = {k: whole[k] for k in ("ckpt_every", "fwd_adj_ms_per_step", "plain_ms_per_step",
                                                           "ratio")}
         log(f"[bench] adjoint ratio {adj['ratio']:.3f} (checkpoint every 50), {whole['ratio']:.3f} (whole trajectory)")
@@ -500,6 +581,7 @@ def main():
             "assemble_ms": asm_ms,
             "assemble_GBps": ASSEMBLE_BYTES_PER_NODE * N / (asm_ms * 1e-3) / 1e9,
             "kernel_breakdown": breakdown,
+            "flowing": flowing,
             "adjoint": adj,
             "batch": batch,
             "variants": variants,

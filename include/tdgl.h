@@ -240,20 +240,23 @@ tdgl_status tdgl_gen_inclusions(tdgl_ctx *ctx, int inst, const double *centres,
 tdgl_status tdgl_gen_shapes(tdgl_ctx *ctx, int inst, const double *shapes, int nc, double target,
                             float eps_in, float eps_out, int *n_used, double *fraction);
 
-/* Insulating inclusions (Sec. 3.4, item (ii): no current across the edges
- * that bound them).  mask: device memory, unsigned char[N], nonzero =
- * insulating node.  Reading of the paper (which gives no discretisation):
- * every edge between a superconducting and an insulating node is cut out of
- * the covariant Laplacian, psi is 0 on insulating nodes, and the Poisson
- * equation for mu~ is left as it is.  With psi = 0 there, cutting an edge
- * changes only the diagonal of its superconducting end, by c_a = 1/h_a^2
+/* Insulating inclusions (Sec. 3.4, item (ii): no-current boundary
+ * conditions across the internal edges that bound them).  mask: device
+ * memory, unsigned char[N], nonzero = insulating node.  Reading of the paper
+ * (which gives no discretisation): every edge between a superconducting and
+ * an insulating node is cut out of the covariant Laplacian and psi is 0 on
+ * insulating nodes, so no SUPERcurrent crosses an insulator surface; the
+ * Poisson equation for mu~ stays on the full grid, so the normal current
+ * -grad mu~ is not blocked.  With psi = 0 there, cutting an edge changes
+ * only the diagonal of its superconducting end, by c_a = 1/h_a^2
  * (1/(g h_z)^2 along z, 2 c_a for the doubled inner neighbour of an open
  * face node), which is what raising eps by c_a does; so this call rewrites
  * the instance's eps in place (eps += the cut shares, added in float in
  * the order x-, x+, y-, y+, z-, z+; eps = -2^50 on insulating nodes, which
  * keeps psi there below 1e-14 of the neighbours') and zeroes psi on the
- * insulating nodes.  Call it after eps is final (tdgl_set_eps or a
- * generator) and again after any later change of eps.  Synchronising. */
+ * insulating nodes.  Call it once after eps is final (tdgl_set_eps or a
+ * generator); a second call before eps is set or generated again would add
+ * the shares twice and returns TDGL_ESTATE.  Synchronising. */
 tdgl_status tdgl_set_insulators(tdgl_ctx *ctx, int inst, const unsigned char *mask);
 
 /* Tessellation pattern (Sec. 3.4; the Voronoi polycrystal of Fig. 2c):

@@ -76,8 +76,19 @@ def _load():
         lib.orc_free_energy.restype = D
         lib.orc_weighted_sum.argtypes = [G, P]
         lib.orc_weighted_sum.restype = D
+        lib.orc_cut_neighbour_sum.argtypes = [G, P, P, P, P, P, P, P]
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
+        lib.orc_max_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Sets the OpenMP thread count of the C loops; returns the previous one."""
+    lib = _load()
+    prev = lib.orc_max_threads()
+    lib.orc_set_threads(int(n))
+    return prev
 
 
 def _p(a: np.ndarray):
@@ -475,6 +486,7 @@ class Params:
     driven: bool = False
     noise_T: float = 0.0     # Langevin term (Sec. 3.1.2): reduced temperature, 0 = off
     noise_seed: int = 0
+    insulators: np.ndarray = None  # Sec. 3.4 (ii): nonzero = insulating node (cut edges)
 
 
 @dataclass
@@ -497,26 +509,29 @@ def new_state(grid: Grid, psi0) -> State:
                  mu=np.zeros(grid.shape))
 
 
-def gl_solve(grid, links, b, diag, ht, psi_prev, tol, max_iter, mode):
+def gl_solve(grid, links, b, diag, ht, psi_prev, tol, max_iter, mode, sweep=None):
     """Jacobi solution of M psi = b (Sec. 3.1, Eq. final / Eq. convergence).
 
     reading: the initial iterate is psi^-; the residual tested after sweep l
     is that of the sweep's input, r^(l) = b - M psi^(l) = M_mm (psi^(l+1) -
     psi^(l)); the output of the first sweep whose r^(l) passes is returned.
-    Returns (psi, sweeps, last max|r|^2)."""
+    Returns (psi, sweeps, last max|r|^2).  sweep: the iteration to use
+    (default: the uncut Eq. final, jacobi_sweep)."""
+    if sweep is None:
+        sweep = lambda b_, d_, p_: jacobi_sweep(grid, links, b_, d_, ht, p_)  # noqa: E731
     psi = psi_prev
     if mode == "exact":
         bmax = float(np.max(np.abs(b)))
         thr = (1e-13 * max(1.0, bmax)) ** 2
         for l in range(100000):
-            psi_new, r2 = jacobi_sweep(grid, links, b, diag, ht, psi)
+            psi_new, r2 = sweep(b, diag, psi)
             psi = psi_new
             if r2 <= thr:
                 return psi, l + 1, r2
         raise RuntimeError("exact GL solve did not converge")
     r2 = np.inf
     for l in range(max_iter):
-        psi_new, r2 = jacobi_sweep(grid, links, b, diag, ht, psi)
+        psi_new, r2 = sweep(b, diag, psi)
         psi = psi_new
         if r2 < tol:
             return psi, l + 1, r2
@@ -549,16 +564,27 @@ def step(grid: Grid, p: Params, eps: np.ndarray, st: State, in_window: bool = Tr
     base = base_links if base_links is not None else base_links_of(grid, p)
     links = with_K(base, grid.hx, st.K)
     mu = st.mu if p.driven else None
-    b, d = assemble(grid, links, st.psi, eps, mu, p.u, ht)
+    ins = None if p.insulators is None else (np.asarray(p.insulators).reshape(grid.shape) != 0)
+    if ins is None:
+        b, d = assemble(grid, links, st.psi, eps, mu, p.u, ht)
+        sweep = None
+    else:
+        # Sec. 3.4 (ii): psi is 0 on insulating nodes, which are not solved for
+        st.psi = np.where(ins, 0.0, _c128(st.psi))
+        b, d = cut_assemble(grid, links, ins, st.psi, eps, mu, p.u, ht)
+        sweep = lambda b_, d_, p_: cut_jacobi_sweep(grid, links, ins, b_, d_, ht, p_)  # noqa: E731
     if p.noise_T > 0:
         # Eq. b: (ht/2) 2 zeta_m(t), drawn for the step counter before the step
         b = b + ht * langevin_zeta(grid, p.noise_T, p.u, p.dt, p.noise_seed, st.n)
-    psi, sweeps, r2 = gl_solve(grid, links, b, d, ht, st.psi, p.tol, p.max_iter, p.mode)
+        if ins is not None:
+            b[ins] = 0.0
+    psi, sweeps, r2 = gl_solve(grid, links, b, d, ht, st.psi, p.tol, p.max_iter, p.mode,
+                               sweep=sweep)
     st.psi = psi
     st.last_sweeps, st.last_res2 = sweeps, r2
     st.sweeps_hist.append(sweeps)
     if p.driven:
-        Jav = jav(grid, links, psi)
+        Jav = jav(grid, links, psi) if ins is None else cut_jav(grid, links, ins, psi)
         E = p.J_ext - Jav
         st.K = st.K + p.dt * E
         if in_window:
@@ -567,7 +593,7 @@ def step(grid: Grid, p: Params, eps: np.ndarray, st: State, in_window: bool = Tr
         st.K = rewind_K(st.K, grid.hx)
         st.last_E, st.last_Jav = E, Jav
         links = with_K(base, grid.hx, st.K)
-        f = poisson_rhs(grid, links, psi)
+        f = poisson_rhs(grid, links, psi) if ins is None else cut_poisson_rhs(grid, links, ins, psi)
         st.mu = poisson_exact(grid, f)
     st.n += 1
     return st
@@ -651,51 +677,79 @@ def gen_voronoi(grid: Grid, seeds: np.ndarray, values: np.ndarray, metric: int =
     return out, owner
 
 
-def insulate(grid: Grid, mask: np.ndarray, eps: np.ndarray, psi: np.ndarray = None, g: float = None):
-    """Insulating inclusions (Sec. 3.4, item (ii)): no current across the
-    edges between a superconducting node and an insulating one.
+def cut_neighbour_sum(grid: Grid, links, mask, psi):
+    """Insulating inclusions (Sec. 3.4, item (ii): no-current boundary
+    conditions across the internal edges that bound them).
 
-    reading: those edges are cut out of the covariant Laplacian and psi is
-    0 on insulating nodes (the mu~ equation is left unchanged).  For psi
-    with psi = 0 on the insulating nodes, the cut operator equals the
-    uncut one plus, on the diagonal of each superconducting node, the cut
-    shares c_a = 1/h_a^2 (1/(g h_z)^2 on z; 2 c_a for the doubled inner
-    neighbour of an open face node) -- the same as raising eps there by
-    them.  Returns (eps', psi'): eps' = eps + shares (float32 sums in the
-    order x-, x+, y-, y+, z-, z+, as the library stores eps), eps' = -2^50
-    on insulating nodes (a diagonal that keeps psi there at ~0), psi' = psi
-    with the insulating nodes zeroed."""
-    mask = np.asarray(mask).reshape(grid.shape) != 0
-    gg = grid.g if g is None else g
-    nz, ny, nx = grid.shape
-    n = (nx, ny, nz)
-    # per-axis edge coefficient as the stencil holds it (0 on a one-node open axis)
-    inv = (1.0 / (grid.hx * grid.hx), 1.0 / (grid.hy * grid.hy), 1.0 / (gg * gg * grid.hz * grid.hz))
-    c = [np.float32(0.0) if (grid.open_[a] and n[a] == 1) else np.float32(inv[a]) for a in range(3)]
-    out = np.asarray(eps, dtype=np.float32).reshape(grid.shape).copy()
-    axis_of = {0: 2, 1: 1, 2: 0}   # grid axis a -> numpy axis
-    for a in range(3):
-        if c[a] == 0:
-            continue
-        ax = axis_of[a]
-        for d in (-1, 1):
-            nb = np.roll(mask, -d, axis=ax)     # mask of the neighbour at offset d
-            share = np.full(grid.shape, c[a], dtype=np.float32)
-            if grid.open_[a]:
-                idx = np.arange(n[a])
-                exists = (idx + d >= 0) & (idx + d < n[a])
-                face = (idx == 0) | (idx == n[a] - 1)
-                shp = [1, 1, 1]
-                shp[ax] = n[a]
-                nb = nb & exists.reshape(shp)
-                share = np.where(face.reshape(shp), np.float32(2.0) * c[a], share).astype(np.float32)
-            out = np.where(nb & ~mask, (out + share).astype(np.float32), out)
-    out[mask] = np.float32(-1125899906842624.0)
-    p2 = None
-    if psi is not None:
-        p2 = np.array(psi, copy=True).reshape(grid.shape)
-        p2[mask] = 0
-    return out, p2
+    reading: every edge with an insulating end (mask != 0) is removed from
+    the covariant Laplacian, psi is 0 on insulating nodes and their rows are
+    not part of the system (the scalar potential's equation is left on the
+    full grid: only the supercurrent is cut).  Returns (NS, D): the sum over
+    each superconducting node's remaining edges of w_e c_a U_e psi_n and of
+    w_e c_a (w_e = 2 for the inner edge of an open outer face node), so that
+    L_cut psi = NS - D psi; both are 0 on insulating nodes."""
+    m8 = np.ascontiguousarray(np.asarray(mask).reshape(grid.shape) != 0, dtype=np.uint8)
+    out = np.empty(grid.shape, np.complex128)
+    dsum = np.empty(grid.shape, np.float64)
+    G = grid.c()
+    _load().orc_cut_neighbour_sum(ctypes.byref(G), *map(_p, links), _p(m8), _p(_c128(psi)),
+                                  _p(out), _p(dsum))
+    return out, dsum
+
+
+def cut_laplacian(grid: Grid, links, mask, psi):
+    """Covariant Laplacian with the insulator-bounding edges cut out."""
+    ns, d = cut_neighbour_sum(grid, links, mask, psi)
+    return ns - d * _c128(psi)
+
+
+def cut_assemble(grid: Grid, links, mask, psi_prev, eps, mu, u, ht):
+    """b and diag(M) of Eq. GL_linearized / Eq. b for the cut operator: on a
+    superconducting node the 2S of the uncut diagonal becomes the node's own
+    sum D_m of remaining edge coefficients; insulating rows hold the trivial
+    equation psi = 0 (b = 0, M_mm = 1, no neighbours)."""
+    psi_prev = _c128(psi_prev)
+    ns, d = cut_neighbour_sum(grid, links, mask, psi_prev)
+    lap = ns - d * psi_prev
+    eps = _f64(eps)
+    mu_ = np.zeros(grid.shape) if mu is None else _f64(mu)
+    a2 = psi_prev.real ** 2 + psi_prev.imag ** 2
+    b = psi_prev + 0.5 * ht * ((eps - 1j * u * mu_) * psi_prev - a2 * psi_prev + lap)
+    diag = 1.0 + 0.5 * ht * (a2 + d + 1j * u * mu_ - eps)
+    ins = np.asarray(mask).reshape(grid.shape) != 0
+    b[ins] = 0.0
+    diag[ins] = 1.0
+    return b, diag
+
+
+def cut_jacobi_sweep(grid: Grid, links, mask, b, diag, ht, psi_in):
+    """One iteration of Eq. final for the cut system; returns (psi_out, max
+    |r(psi_in)|^2) with r = M_mm (psi_out - psi_in) as for the uncut sweep."""
+    ns, _ = cut_neighbour_sum(grid, links, mask, psi_in)
+    out = (b + 0.5 * ht * ns) / diag
+    r = diag * (out - psi_in)
+    return out, float(np.max(r.real ** 2 + r.imag ** 2))
+
+
+def cut_jav(grid: Grid, links, mask, psi):
+    """J_av of Sec. 3.1.1 over the x edges that remain: (1 / (N hx)) times
+    the sum of Im[psi*_m U_x psi_{m+x}] over edges with two superconducting
+    ends (periodic x, the one-sided form of the same sum)."""
+    if grid.open_[0]:
+        raise ValueError("a current along x needs a periodic x axis")
+    ins = np.asarray(mask).reshape(grid.shape) != 0
+    keep = ~ins & ~np.roll(ins, -1, axis=2)
+    psi = _c128(psi)
+    t = np.imag(np.conj(psi) * links[0] * np.roll(psi, -1, axis=2))
+    return float(np.sum(np.where(keep, t, 0.0))) / (grid.N * grid.hx)
+
+
+def cut_poisson_rhs(grid: Grid, links, mask, psi):
+    """Right side of the Poisson equation of Sec. 3.2 with the cut operator:
+    f_m = Im[psi*_m (L_cut psi)_m] = Im[psi*_m NS_m] (the D_m |psi_m|^2 part
+    is real)."""
+    ns, _ = cut_neighbour_sum(grid, links, mask, psi)
+    return np.imag(np.conj(_c128(psi)) * ns)
 
 
 # A candidate whose box reaches farther than 2^50 node spacings from the

@@ -26,6 +26,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -374,3 +375,63 @@ double orc_weighted_sum(const orc_grid *G, const double *x)
     }
     return s;
 }
+
+/*
+ * Insulating inclusions (Sec. 3.4, item (ii)): no-current (open) boundary
+ * conditions across the internal edges that bound an insulating region.
+ *
+ * reading: every edge with an insulating end (mask != 0) is taken out of the
+ * covariant Laplacian -- row m of a superconducting node keeps
+ *     sum over its remaining edges e of  w_e c_a (U_e psi_n - psi_m),
+ * where c_a is the axis coefficient and w_e = 2 for the single inner edge of
+ * an open outer face node (Sec. 3.3.2), else 1 -- and psi is 0 on insulating
+ * nodes, whose rows are not part of the system.
+ *
+ * This routine returns the two parts of that operator at every node:
+ *     out[m]  = sum_e w_e c_a U_e psi_n      (the remaining neighbours)
+ *     dsum[m] = sum_e w_e c_a                (so L_cut psi = out - dsum psi)
+ * both 0 on insulating nodes.  Links as for orc_neighbour_sum; U on the edge
+ * m -> m-a is conj of the link stored at m-a.
+ */
+void orc_cut_neighbour_sum(const orc_grid *G, const cplx *lx, const cplx *ly,
+                           const cplx *lz, const unsigned char *mask, const cplx *psi,
+                           cplx *out, double *dsum)
+{
+    const cplx *L[3] = {lx, ly, lz};
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < G->nz; ++k)
+        for (int j = 0; j < G->ny; ++j)
+            for (int i = 0; i < G->nx; ++i) {
+                long m = idx(G, i, j, k);
+                cplx acc = 0.0;
+                double dacc = 0.0;
+                if (!mask[m]) {
+                    for (int a = 0; a < 3; ++a) {
+                        int pos, n, open;
+                        long s;
+                        axis_info(G, a, i, j, k, &pos, &n, &open, &s);
+                        if (open && n == 1) continue;
+                        double w = (open && (pos == 0 || pos == n - 1)) ? 2.0 : 1.0;
+                        for (int d = -1; d <= 1; d += 2) {
+                            int t = pos + d;
+                            if (open && (t < 0 || t >= n)) continue;
+                            long nb;
+                            if (t < 0) nb = m + (long)(n - 1) * s;        /* periodic wrap */
+                            else if (t >= n) nb = m - (long)(n - 1) * s;
+                            else nb = m + d * s;
+                            if (mask[nb]) continue;                        /* cut edge */
+                            cplx U = (d == 1) ? L[a][m] : conj(L[a][nb]);
+                            acc += w * coef(G, a) * U * psi[nb];
+                            dacc += w * coef(G, a);
+                        }
+                    }
+                }
+                out[m] = acc;
+                if (dsum) dsum[m] = dacc;
+            }
+}
+
+/* Thread count of the loops above (OpenMP over z), for timing the oracle at
+ * a chosen number of host threads. */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }

@@ -332,6 +332,7 @@ struct InstHost {
     double Bx = 0, Bz = 0, J = 0;
     double By = 0;
     bool yz = false;  // field in the yz plane (tdgl_set_field_yz)
+    bool insulated = false;  // eps holds the cut shares of tdgl_set_insulators
 };
 
 // Stencil tiling of one instance: work-groups of 64 x 4 rows columns
@@ -1466,6 +1467,7 @@ tdgl_status tdgl_set_eps(tdgl_ctx *ctx, int inst, const float *eps) {
     if (!eps) return fail(TDGL_EINVAL, "null eps");
     const Inst &d = ctx->inst[inst].d;
     HIPCHK(hipMemcpyAsync(d.eps, eps, (size_t)d.N * 4, hipMemcpyDeviceToDevice, ctx->stream));
+    ctx->inst[inst].insulated = false;
     return TDGL_OK;
 }
 
@@ -1502,6 +1504,7 @@ tdgl_status tdgl_gen_inclusions(tdgl_ctx *ctx, int inst, const double *centres, 
     hipLaunchKernelGGL(k_incl_write, dim3(fill_grid(d.N)), dim3(256), 0, st, ctx->d_inst, inst, first, eps_in,
                        eps_out);
     LAUNCHCHK();
+    ctx->inst[inst].insulated = false;
     DevState h;
     HIPCHK(hipMemcpyAsync(&h, d.st, sizeof h, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -1514,10 +1517,14 @@ tdgl_status tdgl_set_insulators(tdgl_ctx *ctx, int inst, const unsigned char *ma
     tdgl_status s = check_ctx(ctx, inst);
     if (s) return s;
     if (!mask) return fail(TDGL_EINVAL, "null mask");
+    if (ctx->inst[inst].insulated)
+        return fail(TDGL_ESTATE, "instance %d: eps already holds insulators; set eps (or generate it) again first",
+                    inst);
     const Inst &d = ctx->inst[inst].d;
     hipLaunchKernelGGL(k_insulate, dim3(fill_grid(d.N)), dim3(256), 0, ctx->stream, ctx->d_inst, inst, mask);
     LAUNCHCHK();
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->inst[inst].insulated = true;
     return TDGL_OK;
 }
 
@@ -1535,6 +1542,7 @@ tdgl_status tdgl_gen_voronoi(tdgl_ctx *ctx, int inst, const double *seeds, const
     hipLaunchKernelGGL(k_voronoi, dim3((unsigned)((d.N + 255) / 256)), dim3(256), 0, st, ctx->d_inst, inst, seeds,
                        values, ns, metric, axes);
     LAUNCHCHK();
+    ctx->inst[inst].insulated = false;
     HIPCHK(hipStreamSynchronize(st));
     return TDGL_OK;
 }
@@ -1561,6 +1569,7 @@ tdgl_status tdgl_gen_shapes(tdgl_ctx *ctx, int inst, const double *shapes, int n
     hipLaunchKernelGGL(k_incl_write, dim3(fill_grid(d.N)), dim3(256), 0, st, ctx->d_inst, inst, first, eps_in,
                        eps_out);
     LAUNCHCHK();
+    ctx->inst[inst].insulated = false;
     DevState h;
     HIPCHK(hipMemcpyAsync(&h, d.st, sizeof h, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));

@@ -9,8 +9,9 @@
 // with the inner neighbour doubled on the two face rows and
 //     lam_xy = c_x (2 - 2 cos(2 pi kx / nx)) + c_y (2 - 2 cos(2 pi ky / ny)).
 // Steps: real-to-complex FFT along x (two rows per complex transform), FFT
-// along y, the z systems by parallel cyclic reduction in double precision,
-// inverse FFT along y, complex-to-real inverse along x.  The (0, 0) system
+// along y, the z systems by Thomas' algorithm with precomputed pivots in
+// double precision (its two sweeps evaluated as prefix scans of affine maps
+// across a wavefront), inverse FFT along y, complex-to-real inverse along x.  The (0, 0) system
 // is singular (the constant mode); its right side is projected onto the
 // range (zero weighted mean) and its solution shifted to zero weighted mean,
 // which fixes sum_m w_m mu_m = 0 for the whole grid.

@@ -7,9 +7,11 @@ built; there is no fallback path.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 import re
+import weakref
 from dataclasses import dataclass
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -164,6 +166,31 @@ def load():
     return _lib
 
 
+_live = weakref.WeakSet()
+
+
+def _close_all():
+    """Destroys every context still open and waits for the device at
+    interpreter exit.  Python runs this before it tears its modules down and
+    before the C runtime's exit handlers, so no context is destroyed by a
+    finaliser while the HIP runtime, or a tool attached to it, is already
+    shutting down."""
+    for s in list(_live):
+        try:
+            s.close()
+        except Exception:
+            pass
+    try:
+        import torch
+        if torch.cuda.is_initialized():
+            torch.cuda.synchronize()
+    except Exception:
+        pass
+
+
+atexit.register(_close_all)
+
+
 def _check(status):
     if status != 0:
         msg = load().tdgl_last_error()
@@ -236,11 +263,14 @@ class Solver:
                                ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(ctx)))
         self._ctx = ctx
         self.ws_bytes = ws_bytes
+        _live.add(self)
 
     def close(self):
+        """Destroys the context (synchronising) and releases its workspace."""
         if getattr(self, "_ctx", None) is not None and self._ctx.value:
             load().tdgl_destroy(self._ctx)
             self._ctx = None
+            self._ws = None
 
     def __del__(self):
         try:
