@@ -305,13 +305,19 @@ tdgl_status tdgl_voltage_window_reset(tdgl_ctx *ctx, int inst);
  *      voltage sum, phase rewind K -> K - (2 pi/hx) floor(K hx / 2 pi)
  *      (Sec. 2.2);
  *   4. driven only: Poisson equation of Sec. 3.2 for mu~ with the links at
- *      the new K, solved by multigrid V-cycles whose smoother is the
- *      pseudo-time relaxation of Sec. 3.2 (damped Jacobi) until
- *      max|Delta mu~ - f| < max(mu_tol, mu_rtol * its value before the first
- *      cycle); weighted mean of mu~ fixed to zero.
- * Enqueues work and waits on small device-to-host copies of the
- * convergence words.  stats may be NULL.  With strict = 1, returns
- * TDGL_ENOCONV after the first step whose Jacobi solve hit max_iter.
+ *      the new K, weighted mean of mu~ fixed to zero.  With x and y
+ *      periodic and params.poisson = 0 (the default) it is solved directly:
+ *      real FFT along x, FFT along y, one tridiagonal system along z per
+ *      (kx, ky) by Thomas' algorithm in FP64, inverse FFTs.  Otherwise by
+ *      multigrid V-cycles whose smoother is the pseudo-time relaxation of
+ *      Sec. 3.2 (damped Jacobi) until max|Delta mu~ - f| < max(mu_tol,
+ *      mu_rtol * its value before the first cycle).
+ * Enqueues work; the host learns when a Jacobi solve has converged by
+ * reading convergence words that the sweep kernels store into pinned,
+ * mapped host memory (it spins on them; no device-to-host copies), and
+ * queues one or two speculative sweep launches ahead.  stats may be NULL.
+ * With strict = 1, returns TDGL_ENOCONV after the first step whose Jacobi
+ * solve hit max_iter.
  */
 tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats);
 

@@ -72,7 +72,10 @@ class Obs(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
-KERNEL_CLASSES = ["assemble", "sweep", "current", "rhs", "mg_fine", "mg_coarse", "other"]
+# profile classes, in the order of the TDGL_K_* codes: "poisson" is the solve on the
+# full grid (FFT passes and z systems, or the finest multigrid level),
+# "poisson_coarse" the coarser multigrid levels
+KERNEL_CLASSES = ["assemble", "sweep", "current", "rhs", "poisson", "poisson_coarse", "other"]
 
 
 class Tiling(ctypes.Structure):

@@ -2,6 +2,9 @@
 adjoint, which is itself pinned to finite differences of the exact step.
 The GPU forward is FP32 with iterative solves, so the comparison is
 normwise (relative L2 error and cosine) rather than element by element."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -166,3 +169,57 @@ def test_adjoint_with_persistent_solves():
     s2.close()
     assert v1 == v2
     assert np.array_equal(g1.cpu().numpy(), g2.cpu().numpy())
+
+
+C4_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "c4_adjoint_oracle.json")
+
+
+def test_c4_gradient_vs_oracle():
+    """The adjoint workload at its full size (128 x 128 x 32, B = 0.1, J = 0.03,
+    8 % inclusions of diameter 4): from the seeded state, the warm-up steps,
+    then dVbar/deps over the next steps with a checkpoint every 10 (so the
+    reverse sweep recomputes four of five segments), against the FP64 oracle's
+    adjoint over the same protocol (tests/golden/make_c4_adjoint.py): its L2
+    norm, its projections on four seeded +-1 directions, its 8 x 8 x 4 block
+    sums and its values at 2048 seeded cells (relative L2 and cosine), and at
+    32 seeded cells against FP64 central differences."""
+    import torch
+    gold = json.load(open(C4_GOLDEN))
+    w = inputs.WORKLOADS["c4_adjoint_128x128x32"]
+    p = tdgl.make_params(w.nx, w.ny, w.nz, h=w.h, driven=True, tol=1e-12, max_iter=250, dt=w.dt)
+    s = tdgl.Solver(p)
+    bx, bz = s.set_field(0.0, w.B, quantize=True)
+    assert bz == gold["B_eff"]
+    s.set_current(w.J)
+    cen, dia = inputs.candidates_for(w)
+    used, frac = s.gen_inclusions(cen, dia, w.fraction, w.eps_in, w.eps_out)
+    assert used == gold["inclusions"] and frac == gold["fraction"]
+    s.set_psi(torch.from_numpy(inputs.psi_init(w.nx, w.ny, w.nz, w.psi_seed)).cuda())
+    s.step(gold["warmup"], stats=False)
+    K_warm = s.get_scalars()["K"]
+    v, g = s.voltage_grad(gold["nsteps"], gold["window_begin"], ckpt_every=10)
+    s.close()
+    g = g.double().cpu().numpy()
+    shape = g.shape
+    bz_, by_, bx_ = gold["block"]
+    blocks = g.reshape(shape[0] // bz_, bz_, shape[1] // by_, by_, shape[2] // bx_, bx_).sum(axis=(1, 3, 5))
+    rel_b, cos_b = _compare(blocks.ravel(), gold["block_sums"])
+    rel_s, cos_s = _compare(g.ravel()[gold["sample_cells"]], gold["sample_grad"])
+    l2 = float(np.linalg.norm(g))
+    proj = [float(np.sum(g * np.sign(inputs.random_real(shape, sd, -1.0, 1.0)))) for sd in gold["dir_seeds"]]
+    proj_err = max(abs(a - b) / gold["grad_l2"] for a, b in zip(proj, gold["dir_proj"]))
+    fd = np.array(gold["fd"])
+    gfd = g.ravel()[gold["fd_cells"]]
+    rms = gold["grad_l2"] / np.sqrt(g.size)
+    fd_err = np.abs(gfd - fd) / (np.abs(fd) + rms)
+    print(f"[adjoint c4 vs oracle] K after warm-up gpu {K_warm:.9f} oracle {gold['K_after_warmup']:.9f}; "
+          f"Vbar gpu {v:.9e} oracle {gold['Vbar']:.9e}; |g| gpu {l2:.6e} oracle {gold['grad_l2']:.6e}; "
+          f"blocks rel L2 {rel_b:.3e} cos {cos_b:.6f}; cells rel L2 {rel_s:.3e} cos {cos_s:.6f}; "
+          f"projections {proj_err:.3e} of |g|; 32 cells vs FD max {fd_err.max():.3e} "
+          f"(oracle adjoint vs FD {np.max(np.abs(np.array(gold['fd_adjoint']) - fd) / (np.abs(fd) + rms)):.3e})")
+    assert abs(v - gold["Vbar"]) <= 1e-3 * w.J
+    assert abs(l2 - gold["grad_l2"]) <= 1e-2 * gold["grad_l2"]
+    assert rel_b <= 1e-2 and cos_b >= 0.9999
+    assert rel_s <= 1e-2 and cos_s >= 0.999
+    assert proj_err <= 1e-2
+    assert fd_err.max() <= 2e-2
