@@ -430,6 +430,21 @@ tdgl_status tdgl_adjoint_plan(const tdgl_ctx *ctx, int nsteps, int ckpt_every, s
 tdgl_status tdgl_voltage_grad(tdgl_ctx *ctx, int nsteps, int window_begin, int ckpt_every, void *ws,
                               size_t ws_bytes, double *vbar, float *grad_eps);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as tdgl_voltage_grad, same arguments and results (bit for
+ * bit), with the adjoint buffers in a fixed 64 MiB device array of the
+ * library instead of a caller workspace.  The request must fit it:
+ * tdgl_adjoint_plan(ctx, nsteps, ckpt_every) <= 67108864 bytes, else
+ * TDGL_EWS and nothing runs.  Allocates nothing (no hipMalloc, hipFree or
+ * allocating library call); the context itself is created beforehand as
+ * usual.  Each device keeps its own array until the process ends, and it
+ * holds the last call's contents (every buffer the computation reads first
+ * is cleared or written by the call itself).  Calls that overlap on one
+ * device share the array and race: serialise them.  Synchronising. */
+tdgl_status tdgl_voltage_grad_noalloc(tdgl_ctx *ctx, int nsteps, int window_begin, int ckpt_every,
+                                      double *vbar, float *grad_eps);
+
 /* Kernel classes of the per-kernel profile (the time profile of one step,
  * kernel by kernel, as in the paper's performance section, Sec. 4.3). */
 #define TDGL_K_ASSEMBLE 0   /* assemble b, M_mm fused with the first Jacobi iteration */

@@ -2085,7 +2085,7 @@ namespace {
 struct AdjLayout {
     float2 *ck_psi, *seg_psi, *fin_psi, *psibar, *t1, *t2, *t3, *lamW;
     float *ck_mu, *seg_mu, *fin_mu, *mubar;
-    double *ck_K, *seg_K, *fin_K, *Elog;
+    double *ck_K, *seg_K, *fin_K, *Elog, *vbar;
     DevState *fin_st;
     AdjState *adj;
 };
@@ -2111,6 +2111,7 @@ size_t adj_layout(long N, int nsteps, int C, char *base, AdjLayout *L) {
     l.t3 = cv.take<float2>(N);
     l.lamW = cv.take<float2>(N);
     l.Elog = cv.take<double>(nsteps);
+    l.vbar = cv.take<double>(1);
     l.adj = cv.take<AdjState>(1);
     if (L) *L = l;
     return cv.off;
@@ -2165,33 +2166,26 @@ tdgl_status adjoint_step(tdgl_ctx *c, const AdjLayout &L, int iprev, int inext, 
     return TDGL_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-tdgl_status tdgl_adjoint_plan(const tdgl_ctx *ctx, int nsteps, int ckpt_every, size_t *bytes) {
-    if (!ctx || !bytes) return fail(TDGL_EINVAL, "null argument");
-    if (nsteps < 1 || ckpt_every < 1) return fail(TDGL_EINVAL, "nsteps and ckpt_every must be >= 1");
-    *bytes = adj_layout(ctx->inst[0].d.N, nsteps, std::min(ckpt_every, nsteps), nullptr, nullptr);
-    return TDGL_OK;
-}
-
-tdgl_status tdgl_voltage_grad(tdgl_ctx *ctx, int nsteps, int window_begin, int ckpt_every, void *ws,
-                              size_t ws_bytes, double *vbar, float *grad) {
+// Arguments of both adjoint entry points.
+tdgl_status voltage_grad_check(tdgl_ctx *ctx, int nsteps, int window_begin, int ckpt_every, double *vbar,
+                               float *grad) {
     if (!ctx) return fail(TDGL_EINVAL, "null context");
     if (ctx->n != 1) return fail(TDGL_EINVAL, "tdgl_voltage_grad needs a context with one instance");
-    const InstHost &h = ctx->inst[0];
-    if (!h.p.driven) return fail(TDGL_EINVAL, "the voltage needs a driven instance (driven = 1)");
+    if (!ctx->inst[0].p.driven) return fail(TDGL_EINVAL, "the voltage needs a driven instance (driven = 1)");
     if (nsteps < 1 || window_begin < 0 || window_begin >= nsteps || ckpt_every < 1)
         return fail(TDGL_EINVAL, "need nsteps >= 1, 0 <= window_begin < nsteps, ckpt_every >= 1");
     if (!grad || !vbar) return fail(TDGL_EINVAL, "null output");
-    const int C = std::min(ckpt_every, nsteps);
+    return TDGL_OK;
+}
+
+// Forward with checkpoints, then the reverse sweep, on the adjoint buffers
+// carved from ws (adj_layout(N, nsteps, C) bytes, 256-byte aligned).
+tdgl_status voltage_grad_run(tdgl_ctx *ctx, int nsteps, int window_begin, int C, char *ws, double *vbar,
+                             float *grad) {
+    const InstHost &h = ctx->inst[0];
     const long N = h.d.N;
-    const size_t need = adj_layout(N, nsteps, C, nullptr, nullptr);
-    if (!ws || ((uintptr_t)ws % kAlign) != 0 || ws_bytes < need)
-        return fail(TDGL_EWS, "adjoint workspace missing, misaligned or below %zu bytes", need);
     AdjLayout L;
-    adj_layout(N, nsteps, C, (char *)ws, &L);
+    adj_layout(N, nsteps, C, ws, &L);
     hipStream_t s = ctx->stream;
     const int G = std::max(1, std::min(h.d.part_cap, 2048));
     hipLaunchKernelGGL(k_fill_f, dim3(fill_grid(N)), dim3(256), 0, s, grad, N, 0.f);
@@ -2253,14 +2247,81 @@ tdgl_status tdgl_voltage_grad(tdgl_ctx *ctx, int nsteps, int window_begin, int c
     HIPCHK(hipMemcpyAsync(h.d.st, L.fin_st, sizeof(DevState), hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL(k_adj_load, dim3(G), dim3(256), 0, s, ctx->d_inst, L.fin_psi, L.fin_mu, L.fin_K);
     hipLaunchKernelGGL(k_links, dim3(1), dim3(256), 0, s, ctx->d_inst, 1);
+    hipLaunchKernelGGL(k_adj_vbar, dim3(1), dim3(64), 0, s, L.Elog, window_begin, nsteps, L.vbar);
     LAUNCHCHK();
-    std::vector<double> E(nsteps);
-    HIPCHK(hipMemcpyAsync(E.data(), L.Elog, nsteps * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(vbar, L.vbar, sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    double acc = 0.0;
-    for (int n = window_begin; n < nsteps; ++n) acc += E[n];
-    *vbar = acc / W;
     return TDGL_OK;
+}
+
+// Scratch of tdgl_voltage_grad_noalloc: a fixed device array in place of a
+// caller workspace, for callers that cannot allocate.  Each device the
+// library runs on holds its own copy for the life of the process; its
+// address on a device comes from hipGetSymbolAddress, taken once per device
+// with that device current (the array's name in host code is not a device
+// address).  Calls that overlap on one device share it and race.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+tdgl_status scratch_of(int device, char **out) {
+    if (device < 0 || device >= kMaxDevices) return fail(TDGL_EDEVICE, "device %d beyond the scratch table", device);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = 0;
+        HIPCHK(hipGetDevice(&cur));
+        if (cur != device) HIPCHK(hipSetDevice(device));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) HIPCHK(hipSetDevice(cur));
+        if (e != hipSuccess || !p)
+            return fail(TDGL_EDEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", device,
+                        hipGetErrorString(e));
+        if ((uintptr_t)p % kAlign != 0) return fail(TDGL_EDEVICE, "scratch array not %zu-byte aligned", kAlign);
+        g_scratch_ptr[device] = (char *)p;
+    }
+    *out = g_scratch_ptr[device];
+    return TDGL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tdgl_status tdgl_adjoint_plan(const tdgl_ctx *ctx, int nsteps, int ckpt_every, size_t *bytes) {
+    if (!ctx || !bytes) return fail(TDGL_EINVAL, "null argument");
+    if (nsteps < 1 || ckpt_every < 1) return fail(TDGL_EINVAL, "nsteps and ckpt_every must be >= 1");
+    *bytes = adj_layout(ctx->inst[0].d.N, nsteps, std::min(ckpt_every, nsteps), nullptr, nullptr);
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_voltage_grad(tdgl_ctx *ctx, int nsteps, int window_begin, int ckpt_every, void *ws,
+                              size_t ws_bytes, double *vbar, float *grad) {
+    tdgl_status e = voltage_grad_check(ctx, nsteps, window_begin, ckpt_every, vbar, grad);
+    if (e) return e;
+    const int C = std::min(ckpt_every, nsteps);
+    const size_t need = adj_layout(ctx->inst[0].d.N, nsteps, C, nullptr, nullptr);
+    if (!ws || ((uintptr_t)ws % kAlign) != 0 || ws_bytes < need)
+        return fail(TDGL_EWS, "adjoint workspace missing, misaligned or below %zu bytes", need);
+    return voltage_grad_run(ctx, nsteps, window_begin, C, (char *)ws, vbar, grad);
+}
+
+tdgl_status tdgl_voltage_grad_noalloc(tdgl_ctx *ctx, int nsteps, int window_begin, int ckpt_every, double *vbar,
+                                      float *grad) {
+    tdgl_status e = voltage_grad_check(ctx, nsteps, window_begin, ckpt_every, vbar, grad);
+    if (e) return e;
+    const int C = std::min(ckpt_every, nsteps);
+    const size_t need = adj_layout(ctx->inst[0].d.N, nsteps, C, nullptr, nullptr);
+    if (need > kScratchBytes)
+        return fail(TDGL_EWS,
+                    "tdgl_voltage_grad_noalloc: %d steps with a checkpoint every %d on %ld nodes need %zu bytes of "
+                    "scratch, above its fixed %zu bytes (use tdgl_voltage_grad with a workspace)",
+                    nsteps, C, (long)ctx->inst[0].d.N, need, kScratchBytes);
+    char *ws = nullptr;
+    if ((e = scratch_of(ctx->device, &ws))) return e;
+    return voltage_grad_run(ctx, nsteps, window_begin, C, ws, vbar, grad);
 }
 
 tdgl_status tdgl_profile_start(tdgl_ctx *ctx, unsigned mask) {

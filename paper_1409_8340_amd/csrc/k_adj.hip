@@ -87,6 +87,15 @@ __global__ void k_adj_logE(const Inst *__restrict__ insts, double *Elog, int n) 
     if (threadIdx.x == 0) Elog[n] = insts[0].st->E_last;
 }
 
+// Vbar = (1/W) sum_{n = wb}^{nsteps-1} E_n, summed in step order by one
+// thread (the same additions, in the same order, as a sequential host loop).
+__global__ void k_adj_vbar(const double *Elog, int wb, int nsteps, double *vbar) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double acc = 0.0;
+    for (int n = wb; n < nsteps; ++n) acc += Elog[n];
+    *vbar = acc / (double)(nsteps - wb);
+}
+
 __global__ void k_adj_zero(AdjState *adj) {
     if (threadIdx.x == 0) { adj->Kbar = 0.0; adj->Jbar = 0.0; adj->scale = 1.0; }
 }

@@ -75,6 +75,7 @@ __global__ void k_adj_save(const Inst *insts, float2 *dpsi, float *dmu, double *
 __global__ void k_adj_load(const Inst *insts, const float2 *spsi, const float *smu, const double *sK);
 __global__ void k_adj_setK(const Inst *insts, const double *Kp);
 __global__ void k_adj_logE(const Inst *insts, double *Elog, int n);
+__global__ void k_adj_vbar(const double *Elog, int wb, int nsteps, double *vbar);
 __global__ void k_adj_zero(AdjState *adj);
 __global__ void k_adj_prep_f(const Inst *insts, const float *mubar);
 __global__ void k_adj_g(const Inst *insts, const float2 *psin, float2 *g);

@@ -139,6 +139,8 @@ _SIGS = {
                           ctypes.c_int),
     "tdgl_voltage_grad": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                           ctypes.c_size_t, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p], ctypes.c_int),
+    "tdgl_voltage_grad_noalloc": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_double), ctypes.c_void_p], ctypes.c_int),
     "tdgl_autotune": ([ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(Tiling)], ctypes.c_int),
     "tdgl_get_tiling": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(Tiling)], ctypes.c_int),
     "tdgl_set_tiling": ([ctypes.c_void_p, ctypes.POINTER(Tiling)], ctypes.c_int),
@@ -463,6 +465,18 @@ class Solver:
         _check(load().tdgl_voltage_grad(self._ctx, nsteps, window_begin, ckpt_every, ctypes.c_void_p(ptr),
                                         nb.value, ctypes.byref(v), self._dev(grad, torch.float32)))
         del ws
+        return v.value, grad
+
+    def voltage_grad_noalloc(self, nsteps, window_begin=0, ckpt_every=50, grad=None):
+        """tdgl_voltage_grad_noalloc: the adjoint buffers sit in the library's
+        fixed device array; grad (float32, the grid's shape) may be given."""
+        import torch
+        if grad is None:
+            grad = torch.empty(self.shape(0), dtype=torch.float32, device="cuda")
+        torch.cuda.current_stream().synchronize()
+        v = ctypes.c_double()
+        _check(load().tdgl_voltage_grad_noalloc(self._ctx, nsteps, window_begin, ckpt_every, ctypes.byref(v),
+                                                self._dev(grad, torch.float32)))
         return v.value, grad
 
     def profile_start(self, classes=None):
