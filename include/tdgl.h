@@ -111,9 +111,16 @@ typedef struct tdgl_step_stats {
     float mu_last_res;      /* last Poisson residual max-norm                  */
     long long sweep_passes; /* Jacobi-kernel passes that did a full pass over
                                the grid: sweeps - 1 per step (the first
-                               iterate comes from the assemble pass), or
-                               sweeps / 2 with two-sweep passes; launches that
-                               exit at once and corrective sweeps excluded */
+                               iterate comes from the assemble pass), or,
+                               with two-sweep passes, sweeps / 2 when the
+                               pairs start at the second iterate and
+                               (sweeps + 1) / 2 when one single sweep comes
+                               first; launches that exit at once and
+                               corrective sweeps excluded */
+    int single_first_steps; /* steps whose two-sweep solve began with one
+                               single sweep, so that the pairs end on even
+                               iterates (chosen when the recent sweep
+                               counts are mostly even)               */
 } tdgl_step_stats;
 
 /* Scalars that, with psi~ and mu~, make up the full state (exact resume). */

@@ -406,6 +406,11 @@ struct tdgl_ctx {
     int rows = 2;     // stencil rows per thread
     bool nt = false;  // streaming (non-temporal) hints in the sweep and assemble passes
     bool fused = false;  // Jacobi sweeps after the first run as two-sweep passes
+    // the last kHist sweep counts of every instance's host-driven solves
+    // (0: time steps, 1: the adjoint's systems; -1 = none yet), from which
+    // each solve picks the pass schedule with the fewer expected passes
+    std::vector<int> sweep_hist[2];
+    int hist_pos[2] = {0, 0};
     bool persist = false;  // the Jacobi solve as one cooperative launch
     int num_cu = 0;        // compute units of the device
     // captured step of tdgl_step_graph (rebuilt when the budget or the
@@ -668,7 +673,7 @@ tdgl_status upload_tables(tdgl_ctx *ctx) {
         if (h.d.fft) {
             ctx->any_fft = true;
             ctx->fx_lds = std::max(ctx->fx_lds, (size_t)(fft_x_pairs(h.p.nx) + 1) * h.p.nx * 8);
-            ctx->fy_lds = std::max(ctx->fy_lds, (size_t)(fft_y_cols(h.p.ny) + 1) * h.p.ny * 8);
+            ctx->fy_lds = std::max(ctx->fy_lds, ((size_t)fft_y_cols(h.p.ny) * fft_y_stride(h.p.ny) + h.p.ny) * 8);
             ctx->fx_p2 = ctx->fx_p2 && (h.p.nx & (h.p.nx - 1)) == 0;
             ctx->fx_long = ctx->fx_long || h.p.nx > FFT_X_PTS;
             ctx->fy_p2 = ctx->fy_p2 && (h.p.ny & (h.p.ny - 1)) == 0;
@@ -930,6 +935,35 @@ tdgl_status wait_pub(tdgl_ctx *ctx, const unsigned long long *w, unsigned *bits)
     }
 }
 
+constexpr int kHist = 4;
+
+// Passes (corrective sweep included) a solve of s sweeps costs under
+// schedule 1 (two-sweep passes from l = 1) or 2 (one single sweep, then
+// two-sweep passes from l = 2): a solve that ends on the first sweep of a
+// pair pays a corrective single sweep.
+int sched_cost(int sched, int s) {
+    if (sched == 1) return pass_count(1, s) + ((s > 1 && !(s & 1)) ? 1 : 0);
+    return pass_count(2, s) + ((s > 1 && (s & 1)) ? 1 : 0);
+}
+
+// Pass schedule of the next two-sweep solve of kind `kind`: the one with
+// the smaller cost over the recent sweep counts, weighted by the instances'
+// node counts (schedule 1 without history).
+int pick_schedule(tdgl_ctx *ctx, int kind) {
+    const std::vector<int> &h = ctx->sweep_hist[kind];
+    if ((int)h.size() != ctx->n * kHist) return 1;
+    double c1 = 0.0, c2 = 0.0;
+    for (int i = 0; i < ctx->n; ++i)
+        for (int q = 0; q < kHist; ++q) {
+            const int sw = h[(size_t)i * kHist + q];
+            if (sw <= 0) continue;
+            const double w = (double)ctx->inst[i].d.N;
+            c1 += w * sched_cost(1, sw);
+            c2 += w * sched_cost(2, sw);
+        }
+    return c2 < c1 ? 2 : 1;
+}
+
 // The Jacobi iterations after the first sweep (already enqueued, its input
 // residual in row 0): sweep l reads row l-1 on the device and is a no-op
 // for instances whose solve has ended.  The work-group of each instance's
@@ -976,6 +1010,10 @@ tdgl_status jacobi_loop(tdgl_ctx *ctx, tdgl_step_stats *acc, bool *strict_fail, 
     std::vector<int> starts{0};
     starts.reserve(MI + 1);
     int remaining = n, launched = 1, polled = 0;
+    // two-sweep passes from l = 1 (schedule 1) or after one single sweep
+    // from l = 2 (schedule 2), whichever the recent sweep counts favour
+    const int kind = count_step ? 0 : 1;
+    const int sched = ctx->fused ? pick_schedule(ctx, kind) : 0;
     for (;;) {
         // rows handed over by launches at least poll_lag behind the newest
         // (all of them once no launch can follow)
@@ -1006,10 +1044,11 @@ tdgl_status jacobi_loop(tdgl_ctx *ctx, tdgl_step_stats *acc, bool *strict_fail, 
         }
         if (remaining == 0 || launched >= MI) break;
         const int l = launched;
-        const int nr = ctx->fused ? std::min(2, MI - l) : 1;
+        const bool pair = ctx->fused && !(sched == 2 && l == 1);
+        const int nr = pair ? std::min(2, MI - l) : 1;
         {
             ProfScope ps(ctx, TDGL_K_SWEEP);
-            if (ctx->fused) launch_sweep2(ctx, l);
+            if (pair) launch_sweep2(ctx, l);
             else launch_stencil<MODE_SWEEP>(ctx, l);
         }
         LAUNCHCHK();
@@ -1022,10 +1061,19 @@ tdgl_status jacobi_loop(tdgl_ctx *ctx, tdgl_step_stats *acc, bool *strict_fail, 
     {
         ProfScope ps(ctx, TDGL_K_OTHER);
         hipLaunchKernelGGL(k_solve_finalize, dim3(n), dim3(FIN_THREADS), 0, s, ctx->d_inst, n, count_step,
-                           launched, ctx->fused ? 1 : 0, fin, ctx->pub_seq);
+                           launched, sched, fin, ctx->pub_seq);
         if (ctx->fused) launch_stencil<MODE_SWEEP>(ctx, -2);  // corrective sweep where needed
     }
     LAUNCHCHK();
+    if (acc && sched == 2) acc->single_first_steps++;
+    if (ctx->fused) {
+        // sweep counts the host has seen (capped or deferred solves left out)
+        std::vector<int> &h = ctx->sweep_hist[kind];
+        if ((int)h.size() != n * kHist) h.assign((size_t)n * kHist, -1);
+        const int q = ctx->hist_pos[kind];
+        for (int i = 0; i < n; ++i) h[(size_t)i * kHist + q] = deferred[i] ? -1 : conv_at[i] + 1;
+        ctx->hist_pos[kind] = (q + 1) % kHist;
+    }
     bool need_strict = false;
     for (int i = 0; i < n; ++i) need_strict = need_strict || (deferred[i] && ctx->inst[i].p.strict);
     if (!acc && !(need_strict && strict_fail)) return TDGL_OK;
@@ -1047,7 +1095,7 @@ tdgl_status jacobi_loop(tdgl_ctx *ctx, tdgl_step_stats *acc, bool *strict_fail, 
         const bool capped = !(r < (float)h.p.tol);
         if (capped && h.p.strict && strict_fail) *strict_fail = true;
         if (!acc) continue;
-        acc->sweep_passes += ctx->fused ? sw / 2 : sw - 1;
+        acc->sweep_passes += pass_count(sched, sw);
         acc->sweeps_min = std::min(acc->sweeps_min, sw);
         acc->sweeps_max = std::max(acc->sweeps_max, sw);
         acc->sweeps_sum += sw;
@@ -1963,13 +2011,18 @@ tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *ch
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
-        const int chunks[] = {0, 4, 8, 16, 32, 64};
+        // z runs up to the deepest instance's whole z (a run re-reads the
+        // planes around its ends); longer requests would repeat a candidate
+        const int chunks[] = {0, 4, 8, 16, 32, 64, 128, 256};
+        int nzmax = 1;
+        for (const auto &h : ctx->inst) nzmax = std::max(nzmax, h.p.nz);
         const int rows[] = {1, 2, 4};
         best_us = 1e300;
         for (int fu = 0; fu < 2; ++fu)
         for (int nt = 0; nt < 2; ++nt)
         for (int r : rows)
             for (int c : chunks) {
+                if (c > 4 && c / 2 >= nzmax) continue;
                 Tiling t;
                 t.rows = r;
                 t.chunk = c;

@@ -64,7 +64,9 @@ __global__ void k_links(const Inst *__restrict__ insts, int which) {
 // End of a Jacobi solve: the first sweep l whose input residual met tol ends
 // the solve with that sweep's output (Eq. convergence); otherwise the cap,
 // which is the instance's max_iter or the nl sweeps launched, whichever is
-// smaller.  fused: the sweeps after the first ran as two-sweep passes.
+// smaller.  fused: 0 -- single sweeps; 1 -- the sweeps after the first ran
+// as two-sweep passes from l = 1; 2 -- one single sweep (l = 1), then
+// two-sweep passes from l = 2.
 // Updates the psi buffer index and step counters and clears the residual
 // words for the next step.
 __global__ __launch_bounds__(FIN_THREADS) void k_solve_finalize(const Inst *__restrict__ insts, int ninst,
@@ -93,19 +95,24 @@ __global__ __launch_bounds__(FIN_THREADS) void k_solve_finalize(const Inst *__re
                 st->cur ^= (sweeps & 1);
                 st->fix = 0;
             } else {
-                // two-sweep passes store the odd iterates: psi^(s), s odd,
-                // sits in cur ^ ((s + 1) / 2 & 1); an even s is recomputed
-                // from psi^(s-1) into the other buffer by the corrective sweep
-                const int so = (sweeps & 1) ? sweeps : sweeps - 1;
-                const int bo = st->cur ^ (((so + 1) >> 1) & 1);
-                st->fix = (sweeps & 1) ? 0 : 1;
-                st->cur = (sweeps & 1) ? bo : (bo ^ 1);
+                // the iterates the passes store: psi^(1) and, from the
+                // pairs, those of the parity of the pairs' end (odd from
+                // l = 1, even from l = 2), psi^(s) in cur ^ pair_src(s) --
+                // a pair's output is the next pair's input; any other s is
+                // recomputed from psi^(s-1) into the other buffer by the
+                // corrective sweep
+                const int ps = (fused == 1) ? 1 : 0;  // parity of the stored iterates
+                const bool stored = (sweeps == 1) || ((sweeps & 1) == ps);
+                const int so = stored ? sweeps : sweeps - 1;
+                const int bo = st->cur ^ (so == 1 ? 1 : pair_src(so));
+                st->fix = stored ? 0 : 1;
+                st->cur = stored ? bo : (bo ^ 1);
             }
             if (count_step) {
                 st->t += I.dt;
                 st->n += 1.0;
                 st->acc_sweeps += sweeps;
-                st->acc_passes += fused ? sweeps / 2 : sweeps - 1;
+                st->acc_passes += pass_count(fused, sweeps);
                 st->acc_capped += capped;
                 st->acc_sw_min = min(st->acc_sw_min, sweeps);
                 st->acc_sw_max = max(st->acc_sw_max, sweeps);
@@ -138,26 +145,46 @@ __global__ __launch_bounds__(256) void k_jav_partial(const Inst *__restrict__ in
     double acc = 0.0;
     const int nx = I.nx, ny = I.ny;
     const bool yz = I.st->yz != 0;
-    // cell m = base + c 256 + tid: its x, y and z indices follow from one
-    // division for c = 0 and then by stepping 256 cells at a time
+    // cells m = base + c 256 + tid, c = 0 .. JAV_CPT-1, summed in that
+    // order; their x, y and z indices follow from one division for c = 0
+    // and then by stepping 256 cells at a time.  A wavefront's 64 lanes hold
+    // 64 consecutive cells, so psi_{m+x} is the next lane's psi_m (a
+    // shuffle); the last lane and the end of an x row load it.  The loads of
+    // JB cells are issued before any of them is used (a cell past the end
+    // loads cell 0 and adds nothing).
+    constexpr int JB = 8;
+    static_assert(JAV_CPT % JB == 0, "whole batches");
+    const int lane = threadIdx.x & 63;
     int m = (int)((long)lb * 256 * JAV_CPT) + (int)threadIdx.x;
     int i = m % nx, j = (m / nx) % ny, k = m / (nx * ny);
-    for (int c = 0; c < JAV_CPT; ++c) {
-        if (m < I.N) {
-            const int mp = (i == nx - 1) ? m - (nx - 1) : m + 1;
-            const float2 a = psi[m], p = psi[mp];
-            float2 u = I.ux[j];
-            if (yz) u = xcmul(u, I.wz[k]);
-            const float2 up = cmul(u, p);
-            acc += (double)(a.x * up.y - a.y * up.x);
+    const int N = (int)I.N;
+    for (int c0 = 0; c0 < JAV_CPT; c0 += JB) {
+        float2 a[JB];
+#pragma unroll
+        for (int q = 0; q < JB; ++q) {
+            const int mq = m + q * 256;
+            a[q] = psi[mq < N ? mq : 0];
         }
-        m += 256;
-        i += 256;
-        while (i >= nx) {
-            i -= nx;
-            if (++j == ny) {
-                j = 0;
-                ++k;
+#pragma unroll
+        for (int q = 0; q < JB; ++q) {
+            float2 p;
+            p.x = __shfl_down(a[q].x, 1, 64);
+            p.y = __shfl_down(a[q].y, 1, 64);
+            if (m < N) {
+                if (lane == 63 || i == nx - 1) p = psi[(i == nx - 1) ? m - (nx - 1) : m + 1];
+                float2 u = I.ux[j];
+                if (yz) u = xcmul(u, I.wz[k]);
+                const float2 up = cmul(u, p);
+                acc += (double)(a[q].x * up.y - a[q].y * up.x);
+            }
+            m += 256;
+            i += 256;
+            while (i >= nx) {
+                i -= nx;
+                if (++j == ny) {
+                    j = 0;
+                    ++k;
+                }
             }
         }
     }

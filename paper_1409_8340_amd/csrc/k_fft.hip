@@ -187,6 +187,8 @@ __host__ __device__ int fft_y_cols(int ny) {
     int t = FFT_MAXPTS / ny;
     return t < 1 ? 1 : (t > 16 ? 16 : t);
 }
+// LDS stride of the y passes' columns (complex elements).
+__host__ __device__ int fft_y_stride(int ny) { return ny + 1; }
 // Row pitch (complex elements) of the half spectrum: nx/2 + 1 rounded up to
 // 16 elements, so that every row starts on a 128-byte line.
 __host__ __device__ int fft_pitch(int nx) { return (nx / 2 + 1 + 15) & ~15; }
@@ -319,7 +321,11 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(const Inst *__restrict__ 
     const int tk = min(TK, P - kx0);
     float2 *spec = I.spec + (size_t)z * ny * sp;
     const float inv_tk = 1.0f / (float)TK;
-    float2 *stw = sm + TK * ny;
+    // columns sit ss = ny + 1 apart in LDS: the staging loop writes (and the
+    // final loop reads) TK columns per y with consecutive lanes, which a
+    // power-of-two stride would put on one bank
+    const int ss = fft_y_stride(ny);
+    float2 *stw = sm + TK * ss;
     for (int t = threadIdx.x; t < ny; t += FFT_THREADS) stw[t] = I.twy[t];
     // loads are issued YB per thread at a time before any of them is
     // stored to LDS
@@ -337,14 +343,14 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(const Inst *__restrict__ 
         for (int q = 0; q < YB; ++q) {
             const int t = t0 + q * FFT_THREADS;
             const int y = fdiv(t, inv_tk), c = t - y * TK;
-            if (t < tot) sm[c * ny + y] = v[q];
+            if (t < tot) sm[c * ss + y] = v[q];
         }
     }
     __syncthreads();
-    fft_lds<P2, FFT_THREADS, FFT_MAXPTS>(sm, ny, I.yrad, I.nyrad, TK, ny, stw, (float)dir);
+    fft_lds<P2, FFT_THREADS, FFT_MAXPTS>(sm, ny, I.yrad, I.nyrad, TK, ss, stw, (float)dir);
     for (int t = threadIdx.x; t < ny * TK; t += FFT_THREADS) {
         const int y = fdiv(t, inv_tk), c = t - y * TK;
-        if (c < tk) spec[(size_t)y * sp + kx0 + c] = sm[c * ny + y];
+        if (c < tk) spec[(size_t)y * sp + kx0 + c] = sm[c * ss + y];
     }
 }
 

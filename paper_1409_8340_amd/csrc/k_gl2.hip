@@ -20,11 +20,13 @@
 // every iterate is bit-identical to two single sweeps.
 //
 // Residuals: the group reduces max |r|^2 of psi^(l) (row l) and of psi^(l+1)
-// (row l+1), exactly as two single sweeps would.  Buffers: pass l (odd, the
-// first from psi^(1)) reads psi[cur ^ ((l + 1) / 2 & 1)] and writes the
-// other one.  When the solve ends on psi^(l+1) -- the first sweep of a pair
-// converged, or an even cap -- a corrective single sweep recomputes it from
-// psi^(l) (see k_solve_finalize and the single-sweep kernel's fix pass).
+// (row l+1), exactly as two single sweeps would.  Buffers: the pairs start
+// either at l = 1 (from the assemble kernel's psi^(1)) or at l = 2 (after one
+// single sweep); pass l reads psi[cur ^ pair_src(l)] and writes the other
+// one, so the iterates the pairs store alternate between the two buffers.
+// When the solve ends on the first sweep of a pair (or on a cap inside one),
+// a corrective single sweep recomputes that iterate from the stored one
+// before it (see k_solve_finalize and the single-sweep kernel's fix pass).
 #include "kernels.h"
 #include "stencil.h"
 
@@ -173,7 +175,7 @@ __global__ __launch_bounds__(WG) void k_sweep2(const Inst *__restrict__ insts, c
     const bool zper = I.per[2] != 0;
 
     const int cur = st->cur;
-    const int xs = timing ? 0 : (((l + 1) >> 1) & 1);
+    const int xs = timing ? 0 : pair_src(l);
     const gf2 *__restrict__ src = (const gf2 *)I.psi[cur ^ xs];
     gf2 *__restrict__ dst = (gf2 *)I.psi[cur ^ xs ^ 1];
     const gf2 *__restrict__ Pt = (const gf2 *)I.P;
@@ -491,7 +493,7 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
     const bool zper = I.per[2] != 0;
 
     const int cur = I.st->cur;
-    const int xs = timing ? 0 : (((l + 1) >> 1) & 1);
+    const int xs = timing ? 0 : pair_src(l);
     const gf2 *__restrict__ src = (const gf2 *)I.psi[cur ^ xs];
     gf2 *__restrict__ dst = (gf2 *)I.psi[cur ^ xs ^ 1];
     const gf2 *__restrict__ bhp = (const gf2 *)I.bh;

@@ -60,6 +60,7 @@ template <int RMAX>
 __global__ void k_fft_zsolve(const Inst *insts, const int *prefix, int ninst);
 __global__ void k_fft_tables(const Inst *insts, int inst);
 __host__ __device__ int fft_x_pairs(int nx);
+__host__ __device__ int fft_y_stride(int ny);
 __host__ __device__ int fft_y_cols(int ny);
 __host__ __device__ int fft_pitch(int nx);
 __host__ __device__ size_t fft_z_lds(int nz);

@@ -199,6 +199,19 @@ __host__ __device__ inline bool tile_interior2(int x0, int y0, int tyv, int nx, 
     return xin && (seam ? y0 + tyv <= ny : (y0 >= 2 && y0 + tyv + 2 <= ny));
 }
 
+// Buffer of the input psi^(l) of the two-sweep pass l, relative to cur:
+// pairs from odd l follow psi^(1) (in cur ^ 1), pairs from even l follow one
+// single sweep's psi^(2) (in cur); either way consecutive pairs alternate.
+__host__ __device__ inline int pair_src(int l) { return ((l + 2 - (l & 1)) >> 1) & 1; }
+
+// Full passes over the grid after the assemble kernel for a solve of s
+// sweeps (k_solve_finalize's schedules; the corrective sweep not counted).
+__host__ __device__ inline int pass_count(int fused, int s) {
+    if (fused == 0) return s - 1;
+    if (fused == 1) return s / 2;
+    return s == 1 ? 0 : (s + 1) / 2;
+}
+
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
     const int q = nb >> 3, r = nb & 7;
     const int x = b & 7, l = b >> 3;

@@ -46,7 +46,8 @@ class StepStats(ctypes.Structure):
                 ("sweeps_max", ctypes.c_int), ("sweeps_sum", ctypes.c_longlong),
                 ("capped_steps", ctypes.c_int), ("last_res2", ctypes.c_float),
                 ("mu_cycles_sum", ctypes.c_int), ("mu_capped_steps", ctypes.c_int),
-                ("mu_last_res", ctypes.c_float), ("sweep_passes", ctypes.c_longlong)]
+                ("mu_last_res", ctypes.c_float), ("sweep_passes", ctypes.c_longlong),
+                ("single_first_steps", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -333,6 +333,41 @@ def test_two_sweep_passes_bit_identical(shape, open_, Bx, Bz, driven, rows):
     f.close()
 
 
+@pytest.mark.parametrize("shape,open_,Bx,Bz,driven", [FUSED_CASES[0], FUSED_CASES[1], FUSED_CASES[8]])
+def test_two_sweep_schedules_bit_identical(shape, open_, Bx, Bz, driven):
+    """Two-sweep solves pick their schedule from the recent sweep counts:
+    pairs from the second iterate (ending on odd iterates) or one single
+    sweep first (pairs ending on even ones).  Over several stop tolerances
+    both schedules run, and every step equals single sweeps bit for bit,
+    with the same sweep statistics."""
+    nx, ny, nz = shape
+    eps = inputs.random_real((nz, ny, nx), 5, 0.4, 1.0)
+    used = 0
+    for tol in (1e-6, 1e-7, 1e-8, 1e-9, 1e-10):
+        c = Case(nx, ny, nz, open_=open_, Bx=Bx, Bz=Bz, eps=eps, tol=tol, psi_seed=9, driven=driven,
+                 J=0.02 if driven else 0.0)
+        a = c.solver()
+        f = c.solver()
+        a.set_tiling(rows=2, chunk=4, fused=0)
+        f.set_tiling(rows=2, chunk=4, fused=1)
+        for rep in range(6):
+            sa = a.step(1)
+            sf = f.step(1)
+            for k in ("sweeps_sum", "sweeps_min", "sweeps_max", "capped_steps"):
+                assert sa[k] == sf[k], (tol, rep, k, sa, sf)
+            assert np.array_equal(a.get_psi().cpu().numpy(), f.get_psi().cpu().numpy()), (tol, rep)
+            if driven:
+                assert np.array_equal(a.get_mu().cpu().numpy(), f.get_mu().cpu().numpy()), (tol, rep)
+            used += sf["single_first_steps"]
+            sw = sf["sweeps_sum"]
+            want = sw // 2 if not sf["single_first_steps"] else (0 if sw == 1 else (sw + 1) // 2)
+            assert sf["sweep_passes"] == want, (tol, rep, sf)
+        a.close()
+        f.close()
+    print(f"[schedules] {shape} {open_}: {used} steps began with one single sweep")
+    assert used > 0
+
+
 @pytest.mark.parametrize("shape,open_,Bx,Bz,driven", FUSED_CASES[:2])
 def test_tilings_bit_identical(shape, open_, Bx, Bz, driven):
     """The node arithmetic of the assemble, the sweeps and the Poisson right
