@@ -115,7 +115,7 @@ def variant_bench(w, tdgl, inputs, torch, kind, steps, warmup, mu_rtol):
     N = w.nx * w.ny * w.nz
     return {"steps": steps, "ms_per_step": 1e3 * el / steps, "cell_updates_per_s": N * steps / el,
             "sweeps_per_step": st["sweeps_sum"] / max(st["steps"], 1),
-            "tiling": {k: tiling[k] for k in ("rows", "chunk", "streaming", "fused", "persistent")}}
+            "tiling": {k: tiling[k] for k in ("rows", "chunk", "chunk2", "streaming", "fused", "persistent")}}
 
 
 def host_cpu_model():
@@ -236,7 +236,7 @@ def small_bench(tdgl, inputs, torch, name, steps, warmup):
     s.close()
     n = w.nx * w.ny * w.nz
     return {"workload": w.name, "nodes": n, "driven": w.driven, "steps": steps, "warmup": warmup,
-            "tiling": {k: tiling[k] for k in ("rows", "chunk", "streaming", "fused", "persistent")},
+            "tiling": {k: tiling[k] for k in ("rows", "chunk", "chunk2", "streaming", "fused", "persistent")},
             "eager_us_per_step": 1e6 * t_e / steps, "eager_rate": n * steps / t_e,
             "eager_sweeps_per_step": st["sweeps_sum"] / steps,
             "graph_us_per_step": 1e6 * t_g / steps, "graph_rate": n * steps / t_g,
@@ -329,7 +329,7 @@ def iv_study(tdgl, inputs, torch, w, points, steps, window, mu_rtol):
                           "sweeps_per_step": (a["sweeps_sum"] + b["sweeps_sum"]) / steps,
                           "capped_steps": a["capped_steps"] + b["capped_steps"],
                           "ms_per_step": 1e3 * el / steps, "B_eff": Bz, "inclusions": used,
-                          "tiling": {k: tiling[k] for k in ("rows", "chunk", "streaming", "fused")}}),
+                          "tiling": {k: tiling[k] for k in ("rows", "chunk", "chunk2", "streaming", "fused")}}),
               flush=True)
     s.close()
 
@@ -364,7 +364,7 @@ def jacobi_study(tdgl, inputs, torch, steps, warmup):
                "sweeps_per_step": st["sweeps_sum"] / steps, "sweeps_min": st["sweeps_min"],
                "sweeps_max": st["sweeps_max"], "capped_steps": st["capped_steps"],
                "ms_per_step": 1e3 * el / steps, "cell_updates_per_s": n * n * steps / el,
-               "tiling": {k: tiling[k] for k in ("rows", "chunk", "streaming", "fused")}}
+               "tiling": {k: tiling[k] for k in ("rows", "chunk", "chunk2", "streaming", "fused")}}
         log(f"[study] {axis}: n={n} h={h} tol={tol:g}: {rec['sweeps_per_step']:.2f} sweeps/step, "
             f"{rec['ms_per_step']:.4f} ms/step")
         print(json.dumps(rec), flush=True)
@@ -392,7 +392,7 @@ def main():
     ap.add_argument("--variant-steps", type=int, default=10,
                     help="steps of the same workload with Langevin noise and with a yz-plane field (0 skips)")
     ap.add_argument("--tiling", default=None,
-                    help="rows,chunk,streaming,fused[,persistent]: set the stencil tiling instead of tdgl_autotune")
+                    help="rows,chunk,streaming,fused[,persistent[,chunk2]]: set the stencil tiling instead of tdgl_autotune")
     ap.add_argument("--study", choices=["jacobi", "iv"], default=None,
                     help="instead of the benchmark line: 'jacobi', the Jacobi iteration study (2D film: "
                          "iterations and time per step against grid size, spacing and tolerance); 'iv', the "
@@ -427,8 +427,8 @@ def main():
     s, Bz, used, frac = setup(w, tdgl, inputs, torch, w.tol, args.mu_rtol)
     log(f"[bench] B_eff={Bz:.6f} inclusions={used} fraction={frac}")
     if args.tiling:
-        v_ = [int(v) for v in args.tiling.split(",")] + [0]
-        s.set_tiling(rows=v_[0], chunk=v_[1], streaming=v_[2], fused=v_[3], persistent=v_[4])
+        v_ = [int(v) for v in args.tiling.split(",")] + [0, 0]
+        s.set_tiling(rows=v_[0], chunk=v_[1], streaming=v_[2], fused=v_[3], persistent=v_[4], chunk2=v_[5])
         tiling = s.tiling()
     else:
         tiling = s.autotune()
@@ -560,8 +560,9 @@ def main():
         "config": {"workload": w.name, "grid": [w.nx, w.ny, w.nz], "h": w.h, "B_eff": Bz, "J": w.J,
                    "inclusions": used, "inclusion_fraction": frac, "tol": w.tol, "dt": w.dt,
                    "mu_tol": 1e-5, "mu_rtol": args.mu_rtol,
-                   "tiling": {"rows": tiling["rows"], "chunk": tiling["chunk"], "streaming": tiling["streaming"],
-                              "fused": tiling["fused"], "persistent": tiling["persistent"]},
+                   "tiling": {"rows": tiling["rows"], "chunk": tiling["chunk"], "chunk2": tiling["chunk2"],
+                              "streaming": tiling["streaming"], "fused": tiling["fused"],
+                              "persistent": tiling["persistent"]},
                    "precision": "psi, links and sweeps in FP32 (complex64 storage); residual, J_av, K, "
                                 "means and the Poisson z solve in FP64",
                    "parallelism": "single GPU"},

@@ -381,12 +381,19 @@ typedef struct tdgl_tiling {
                         barriers included, beat separate launches by 10 %. */
     double sweep_us; /* measured time of one Jacobi sweep of the whole context
                         (tdgl_autotune; 0 from tdgl_get_tiling)             */
+    int chunk2;      /* z planes per work-group of the two-sweep passes'
+                        super-tile kernel (fused = 1); 0: chunk.  The stencil
+                        passes (assemble, Poisson right side, single sweeps)
+                        keep chunk                                          */
 } tdgl_tiling;
 
 /* Picks the stencil tiling of the context by timing one Jacobi sweep for
  * each candidate (rows in {1, 2, 4} x chunk in {heuristic, 4, 8, 16, 32,
- * 64} x streaming hints off/on x one or two sweeps per pass) on the
- * context's stream and keeping the fastest per iteration; then 16 sweeps of
+ * 64, 128, 256} up to the deepest instance's z x streaming hints off/on x
+ * one or two sweeps per pass; the two-sweep candidates vary chunk2 and keep
+ * the stencil chunk of the fastest single sweep with the same rows and
+ * hints) on the context's stream and keeping the fastest per iteration;
+ * then 16 sweeps of
  * that tiling in one persistent launch are timed, and persistent solves are
  * chosen when they are at least 10 % faster per sweep.  The timing sweeps
  * read the current psi~ and b/M, (ht/2)/M arrays and write only the spare

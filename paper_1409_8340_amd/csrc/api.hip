@@ -336,8 +336,10 @@ struct InstHost {
 };
 
 // Stencil tiling of one instance: work-groups of 64 x 4 rows columns
-// marching through z runs of `chunk` planes (chunk_req = 0: heuristic).
-void set_tiling(InstHost &h, int rows, int chunk_req) {
+// marching through z runs of `chunk` planes (chunk_req = 0: heuristic); the
+// two-sweep super-tile kernel marches through z runs of its own
+// (chunk2_req = 0: the stencil's).
+void set_tiling(InstHost &h, int rows, int chunk_req, int chunk2_req) {
     Inst &d = h.d;
     const tdgl_params &p = h.p;
     d.rows = rows;
@@ -346,6 +348,8 @@ void set_tiling(InstHost &h, int rows, int chunk_req) {
     const long txy = (long)d.tiles_x * d.tiles_y;
     d.chunk = auto_chunk(txy, p.nz, chunk_req);
     d.tiles_z = cdiv(p.nz, d.chunk);
+    d.chunk2 = chunk2_req > 0 ? std::min(chunk2_req, p.nz) : d.chunk;
+    d.tiles_z2 = cdiv(p.nz, d.chunk2);
     h.st_blocks = (int)(txy * d.tiles_z);
 }
 
@@ -365,7 +369,8 @@ struct tdgl_ctx {
     int *d_pref_st = nullptr, *d_pref_flat = nullptr, *d_pref_mg = nullptr, *d_pref_mid = nullptr;
     int *d_pref_b = nullptr;  // blocks of the two-sweep boundary kernel per instance
     int *d_pref_i = nullptr;  // ... and of the interior (super-tile) kernel
-    int tot_b = 0, tot_i = 0;
+    int *d_pref_sr = nullptr;  // ... and of the seam-ring pre-pass (seam2 instances)
+    int tot_b = 0, tot_i = 0, tot_sr = 0;
     int *d_np_st = nullptr, *d_np_flat = nullptr, *d_np_mg0 = nullptr;
     unsigned *d_res = nullptr, *d_mures = nullptr;
     unsigned *h_mures = nullptr;  // pinned copy of the Poisson rows
@@ -451,6 +456,7 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
     int *pref_fz = cv.take<int>(n + 1);
     int *pref_b = cv.take<int>(n + 1);
     int *pref_i = cv.take<int>(n + 1);
+    int *pref_sr = cv.take<int>(n + 1);
     int *np_st = cv.take<int>(n);
     int *np_flat = cv.take<int>(n);
     int *np_mg0 = cv.take<int>(n);
@@ -501,6 +507,7 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
         d.P = cv.take<float2>((size_t)p.nx * p.nz);
         d.wz = cv.take<float2>(p.nz);
         d.btile = cv.take<int>((size_t)cdiv(p.nx, TX) * cdiv(p.ny, 4));  // room for any rows per thread
+        if (seam2_ok(p.bc[1] == TDGL_PERIODIC, p.ny)) d.sring = cv.take<float2>((size_t)2 * p.nz * p.nx);
         d.st = cv.take<DevState>(1);
         d.res = res ? res + i : nullptr;
         d.mures = mures ? mures + i : nullptr;
@@ -509,7 +516,7 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
         d.max_iter = p.max_iter;
         d.mu_max_cycles = p.driven ? p.mu_max_cycles : 1;
         // stencil tiling
-        set_tiling(h, ctx_rows(n, params), p.tile_cz);
+        set_tiling(h, ctx_rows(n, params), p.tile_cz, 0);
         h.flat_blocks = cdiv(N, 256L * JAV_CPT);
         int part_cap = (int)std::max<long>(max_st_blocks(p), h.flat_blocks);
         // multigrid
@@ -594,6 +601,7 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
         ctx->d_pref_fz = pref_fz;
         ctx->d_pref_b = pref_b;
         ctx->d_pref_i = pref_i;
+        ctx->d_pref_sr = pref_sr;
         ctx->d_np_st = np_st;
         ctx->d_np_flat = np_flat;
         ctx->d_np_mg0 = np_mg0;
@@ -783,9 +791,15 @@ void launch_sweep2_v(tdgl_ctx *c, int l, unsigned long long *pub) {
     if (c->tot_b > 0)
         hipLaunchKernelGGL((k_sweep2<R, NT, YZ>), dim3(c->tot_b), dim3(WG), 0, c->stream, c->d_inst, c->d_pref_b,
                            c->n, l, pub, c->pub_seq);
-    if (c->tot_i > 0)
+    if (c->tot_i > 0) {
+        // the super-tiles on the quasi-periodic seam read their ring slots
+        // beyond it from this pre-pass
+        if (c->tot_sr > 0)
+            hipLaunchKernelGGL((k_seam_ring<YZ>), dim3(c->tot_sr), dim3(256), 0, c->stream, c->d_inst, c->d_pref_sr,
+                               c->n, l);
         hipLaunchKernelGGL((k_sweep2i<R, NT, YZ>), dim3(c->tot_i), dim3(WG * sweep2i_mult(R)), 0, c->stream,
                            c->d_inst, c->d_pref_i, c->n, l, pub, c->pub_seq);
+    }
 }
 // One two-sweep pass (l odd; l = -1: timing pass).
 template <int R>
@@ -850,11 +864,11 @@ void launch_stencil(tdgl_ctx *c, int l, const float2 *in = nullptr, float2 *out 
     else launch_stencil_r<MODE, 4>(c, l, in, out);
 }
 // The assemble pass, with the Langevin draws where some instance has them.
-void launch_assemble(tdgl_ctx *c) {
+void launch_assemble(tdgl_ctx *c, int l = 0) {
     if (c->noisy)
-        launch_stencil<MODE_FIRSTN>(c, 0);
+        launch_stencil<MODE_FIRSTN>(c, l);
     else
-        launch_stencil<MODE_FIRST>(c, 0);
+        launch_stencil<MODE_FIRST>(c, l);
 }
 
 // One multigrid V-cycle for every driven instance (cycle index cyc).
@@ -1882,7 +1896,7 @@ constexpr int kBoundaryChunk = 8;
 
 tdgl_status upload_tiling(tdgl_ctx *ctx) {
     const int n = ctx->n;
-    std::vector<int> ps(n + 1, 0), nps(n), pb(n + 1, 0), pi(n + 1, 0);
+    std::vector<int> ps(n + 1, 0), nps(n), pb(n + 1, 0), pi(n + 1, 0), psr(n + 1, 0);
     std::vector<Inst> di(n);
     for (int i = 0; i < n; ++i) {
         InstHost &h = ctx->inst[i];
@@ -1905,7 +1919,9 @@ tdgl_status upload_tiling(tdgl_ctx *ctx) {
                                                   d.per[0] != 0, seam);
                 if (!inner) bt.push_back(tx + d.tiles_x * ty);
             }
-        pi[i + 1] = pi[i] + d.tiles_x * nsy * d.tiles_z;
+        pi[i + 1] = pi[i] + d.tiles_x * nsy * d.tiles_z2;
+        // rows ny-1 and 0 of every plane, for the super-tiles on the seam
+        psr[i + 1] = psr[i] + ((seam && nsy > 0) ? cdiv(2L * d.nz * d.nx, 256L) : 0);
         if (!bt.empty()) HIPCHK(hipMemcpy(d.btile, bt.data(), bt.size() * 4, hipMemcpyHostToDevice));
         d.nbt = (int)bt.size();
         d.bchunk = std::min(d.chunk, kBoundaryChunk);
@@ -1918,16 +1934,19 @@ tdgl_status upload_tiling(tdgl_ctx *ctx) {
     HIPCHK(hipMemcpy(ctx->d_np_st, nps.data(), n * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_pref_b, pb.data(), (n + 1) * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_pref_i, pi.data(), (n + 1) * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_pref_sr, psr.data(), (n + 1) * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_inst, di.data(), n * sizeof(Inst), hipMemcpyHostToDevice));
     ctx->tot_st = ps[n];
     ctx->tot_b = pb[n];
     ctx->tot_i = pi[n];
+    ctx->tot_sr = psr[n];
     return TDGL_OK;
 }
 
 struct Tiling {
     int rows = 2;
     int chunk = 0;  // 0: heuristic
+    int chunk2 = 0;  // z run of the two-sweep super-tile kernel; 0: chunk
     int nt = 0;       // streaming hints
     int fused = 0;    // two-sweep passes
     int persist = 0;  // one cooperative launch per Jacobi solve
@@ -1939,7 +1958,7 @@ tdgl_status apply_tiling(tdgl_ctx *ctx, const Tiling &t) {
     ctx->nt = t.nt != 0;
     ctx->fused = t.fused != 0;
     ctx->persist = t.persist != 0 && !ctx->fused && !ctx->any_yz;
-    for (auto &h : ctx->inst) set_tiling(h, t.rows, t.chunk);
+    for (auto &h : ctx->inst) set_tiling(h, t.rows, t.chunk, t.chunk2);
     return upload_tiling(ctx);
 }
 
@@ -1967,13 +1986,15 @@ bool tune_file_lookup(const char *path, const std::string &key, Tiling *t, doubl
     bool found = false;
     while (fgets(line, sizeof line, f)) {
         char k[4000];
-        int r, c, nt, fu, pe;
+        int r, c, nt, fu, pe, c2 = 0;
         double u;
-        if (sscanf(line, "%3999s %d %d %d %d %d %lf", k, &r, &c, &nt, &fu, &pe, &u) == 7 && key == k &&
-            (r == 1 || r == 2 || r == 4) && c >= 0 && (nt == 0 || nt == 1) && (fu == 0 || fu == 1) &&
-            (pe == 0 || pe == 1)) {
+        // key rows chunk streaming fused persistent us [chunk2]
+        const int got = sscanf(line, "%3999s %d %d %d %d %d %lf %d", k, &r, &c, &nt, &fu, &pe, &u, &c2);
+        if ((got == 7 || got == 8) && key == k && (r == 1 || r == 2 || r == 4) && c >= 0 && c2 >= 0 &&
+            (nt == 0 || nt == 1) && (fu == 0 || fu == 1) && (pe == 0 || pe == 1)) {
             t->rows = r;
             t->chunk = c;
+            t->chunk2 = got == 8 ? c2 : 0;
             t->nt = nt;
             t->fused = fu;
             t->persist = pe;
@@ -2018,6 +2039,13 @@ tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *ch
         for (const auto &h : ctx->inst) nzmax = std::max(nzmax, h.p.nz);
         const int rows[] = {1, 2, 4};
         best_us = 1e300;
+        // single sweeps first: their best z run per (streaming, rows) is
+        // also the z run of the stencil passes (assemble, Poisson right
+        // side, single sweeps) under the two-sweep candidates, which vary
+        // only the super-tile kernel's own z run
+        int stencil_chunk[2][5] = {};
+        double stencil_us[2][5];
+        for (auto &a : stencil_us) for (double &v : a) v = 1e300;
         for (int fu = 0; fu < 2; ++fu)
         for (int nt = 0; nt < 2; ++nt)
         for (int r : rows)
@@ -2025,7 +2053,9 @@ tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *ch
                 if (c > 4 && c / 2 >= nzmax) continue;
                 Tiling t;
                 t.rows = r;
-                t.chunk = c;
+                t.chunk = fu ? stencil_chunk[nt][r] : c;
+                t.chunk2 = fu ? std::max(c, 1) : 0;
+                if (fu && c == 0) continue;  // the heuristic z run is a single-sweep notion
                 t.nt = nt;
                 t.fused = fu;
                 tdgl_status e = apply_tiling(ctx, t);
@@ -2045,11 +2075,43 @@ tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *ch
                 HIPCHK(hipEventElapsedTime(&ms, e0, e1));
                 // time per Jacobi iteration (a two-sweep pass makes two)
                 const double us = 1e3 * ms / reps / (fu ? 2 : 1);
+                if (!fu && us < stencil_us[nt][r]) {
+                    stencil_us[nt][r] = us;
+                    stencil_chunk[nt][r] = c;
+                }
                 if (us < best_us) {
                     best_us = us;
                     best = t;
                 }
             }
+        // two-sweep passes: the stencil passes that remain (the assemble
+        // every step, the Poisson right side, an occasional single sweep)
+        // take the z run under which the assemble is fastest
+        if (best.fused) {
+            double best_a = 1e300;
+            int best_c = best.chunk;
+            for (int c : chunks) {
+                if (c > 4 && c / 2 >= nzmax) continue;
+                Tiling t = best;
+                t.chunk = c;
+                tdgl_status e = apply_tiling(ctx, t);
+                if (e) return e;
+                launch_assemble(ctx, -1);  // warm-up
+                HIPCHK(hipEventRecord(e0, s));
+                const int reps = 4;
+                for (int q = 0; q < reps; ++q) launch_assemble(ctx, -1);
+                HIPCHK(hipEventRecord(e1, s));
+                LAUNCHCHK();
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best_a) {
+                    best_a = ms;
+                    best_c = c;
+                }
+            }
+            best.chunk = best_c;
+        }
         // the best single-sweep tiling as one persistent launch: chosen when
         // its sweeps, barrier included, beat separate launches by 10 %
         if (!best.fused && !ctx->any_yz) {
@@ -2076,8 +2138,8 @@ tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *ch
         if (cache_path) {
             FILE *f = fopen(cache_path, "a");
             if (f) {
-                fprintf(f, "%s %d %d %d %d %d %.3f\n", key.c_str(), best.rows, best.chunk, best.nt, best.fused,
-                        best.persist, best_us);
+                fprintf(f, "%s %d %d %d %d %d %.3f %d\n", key.c_str(), best.rows, best.chunk, best.nt, best.fused,
+                        best.persist, best_us, best.chunk2);
                 fclose(f);
             }
         }
@@ -2091,6 +2153,7 @@ tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *ch
     if (chosen) {
         chosen->rows = best.rows;
         chosen->chunk = ctx->inst[0].d.chunk;
+        chosen->chunk2 = ctx->inst[0].d.chunk2;
         chosen->streaming = best.nt;
         chosen->fused = best.fused;
         chosen->persistent = ctx->persist ? 1 : 0;
@@ -2103,6 +2166,7 @@ tdgl_status tdgl_set_tiling(tdgl_ctx *ctx, const tdgl_tiling *t) {
     if (!ctx || !t) return fail(TDGL_EINVAL, "null argument");
     if (t->rows != 1 && t->rows != 2 && t->rows != 4) return fail(TDGL_EINVAL, "rows must be 1, 2 or 4");
     if (t->chunk < 0 || t->chunk > 1024) return fail(TDGL_EINVAL, "chunk must be in [0, 1024]");
+    if (t->chunk2 < 0 || t->chunk2 > 1024) return fail(TDGL_EINVAL, "chunk2 must be in [0, 1024]");
     if ((t->streaming != 0 && t->streaming != 1) || (t->fused != 0 && t->fused != 1) ||
         (t->persistent != 0 && t->persistent != 1))
         return fail(TDGL_EINVAL, "streaming, fused and persistent must be 0 or 1");
@@ -2113,6 +2177,7 @@ tdgl_status tdgl_set_tiling(tdgl_ctx *ctx, const tdgl_tiling *t) {
     Tiling s;
     s.rows = t->rows;
     s.chunk = t->chunk;
+    s.chunk2 = t->chunk2;
     s.nt = t->streaming;
     s.fused = t->fused;
     s.persist = t->persistent;
@@ -2124,6 +2189,7 @@ tdgl_status tdgl_get_tiling(const tdgl_ctx *ctx, int inst, tdgl_tiling *out) {
     if (inst < 0 || inst >= ctx->n) return fail(TDGL_EINVAL, "instance %d out of range", inst);
     out->rows = ctx->rows;
     out->chunk = ctx->inst[inst].d.chunk;
+    out->chunk2 = ctx->inst[inst].d.chunk2;
     out->streaming = ctx->nt ? 1 : 0;
     out->fused = ctx->fused ? 1 : 0;
     out->persistent = ctx->persist ? 1 : 0;

@@ -52,8 +52,10 @@ __device__ __forceinline__ void stencil_tile(const Inst *__restrict__ insts, con
     // records no residual, so the solver state is left as it was.
     // l = -2: the corrective sweep of two-sweep mode -- when the solve ended
     // on an even iterate, recompute it from the odd one in psi[cur ^ 1] into
-    // psi[cur] (no residual row).
-    const bool timing = (MODE == MODE_SWEEP) && l == -1;
+    // psi[cur] (no residual row).  The assemble pass takes l = -1 as a
+    // timing pass too: b/M and (ht/2)/M (dead between steps) and the spare
+    // psi buffer are written, no residual row.
+    const bool timing = (MODE == MODE_SWEEP || is_first_mode(MODE)) && l == -1;
     const bool fixp = (MODE == MODE_SWEEP) && l == -2;
     if (fixp && !st->fix) return;
     if (timing) l = 0;

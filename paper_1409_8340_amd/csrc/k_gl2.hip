@@ -416,6 +416,36 @@ __global__ __launch_bounds__(WG) void k_sweep2(const Inst *__restrict__ insts, c
     }
 }
 
+// Pre-pass of a two-sweep pass on a seam2 instance: psi^(l+1) of rows ny-1
+// and 0 of every plane, i.e. the Jacobi updates of the real nodes behind the
+// ring slots that the super-tiles on the quasi-periodic y seam hold beyond
+// it (row -1 is row ny-1 times P, row ny is row 0 times conj P).  Same
+// function and operands as k_sweep2's slot update, so the same bits; the
+// super-tile kernel then applies the phase.  out[(p 2 + r) nx + x], r = 0
+// for row ny-1, 1 for row 0.  Exits like the pass when the solve has ended.
+template <bool YZ>
+__global__ __launch_bounds__(256) void k_seam_ring(const Inst *__restrict__ insts, const int *__restrict__ prefix,
+                                                   int ninst, int l) {
+    const int b = blockIdx.x;
+    const int ii = find_inst(prefix, ninst, b);
+    const Inst &I = insts[ii];
+    const bool timing = l < 0;
+    if (!timing) {
+        if (l >= I.max_iter) return;
+        if (row_max_wave(I.res, I.rstride, l - 1) < I.tol) return;
+        if (l >= 2 && row_max_wave(I.res, I.rstride, l - 2) < I.tol) return;
+    }
+    const int nx = I.nx, ny = I.ny, nz = I.nz;
+    const int t = (b - prefix[ii]) * 256 + (int)threadIdx.x;
+    if (t >= 2 * nz * nx) return;
+    const int x = t % nx, pr = t / nx, r = pr & 1, p = pr >> 1;
+    const int cur = I.st->cur;
+    const int xs = timing ? 0 : pair_src(l);
+    const gf2 *__restrict__ src = (const gf2 *)I.psi[cur ^ xs];
+    I.sring[t] = node_update<YZ>(I, src, (const gf2 *)I.P, (const gf2 *)I.bh, (const gf2 *)I.dh, x,
+                                 r == 0 ? ny - 1 : 0, p, (unsigned)nx * (unsigned)ny, I.per[2] != 0);
+}
+
 // The two-sweep pass on interior super-tiles (tile_interior2 with height
 // TYS): the tile, its two-node halo of psi^(l) and its ring of psi^(l+1)
 // are real nodes with real neighbours (or their plain images across a
@@ -448,7 +478,7 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
     const int ii = find_inst(prefix, ninst, b);
     const Inst &I = insts[ii];
     const int nx = I.nx, ny = I.ny, nz = I.nz;
-    // blocks: tiles_x x sweep2i_rows x tiles_z super-tiles
+    // blocks: tiles_x x sweep2i_rows x tiles_z2 super-tiles
     const bool seam2 = I.seam2 != 0;
     const int nsy = sweep2i_rows(ny, R, seam2);
     int t = b - prefix[ii];
@@ -457,9 +487,9 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
     t /= I.tiles_x;
     const int tyr = t % nsy;
     const int tzi = t / nsy;
-    // seam2: the two seam rows (slower: their ring slots beyond the seam
-    // are computed from global memory) are taken first, so that they do not
-    // finish last: row order 0, nsy - 1, 1, 2, ..., nsy - 2
+    // seam2: the two seam rows (a little slower: their halo rows beyond the
+    // seam carry the phase) are taken first, so that they do not finish
+    // last: row order 0, nsy - 1, 1, 2, ..., nsy - 2
     const int tyi = (!seam2 || tyr == 0) ? tyr : (tyr == 1 ? nsy - 1 : tyr - 1);
     const int x0 = txi * TX, y0 = sweep2i_y0(tyi, R, seam2);
     const bool xper = I.per[0] != 0;
@@ -480,13 +510,14 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
     if (!tile_interior2(x0, y0, TYv, nx, ny, xper, seam2)) return;
     // a super-tile on the quasi-periodic y seam (seam2): its y halo rows
     // beyond the grid are the wrapped rows times the phase P (or conj P),
-    // and its ring slots there are the wrapped nodes' updates with that
-    // phase, as cell_src2 / slot_update give them to the general kernel
+    // and its ring slots there are the wrapped nodes' updates (made by
+    // k_seam_ring before the pass) with that phase, as cell_src2 /
+    // slot_update give them to the general kernel
     const bool seam = seam2 && (y0 == 0 || y0 + TYv == ny);
     const gf2 *__restrict__ Pt = (const gf2 *)I.P;
     const bool rec2 = !timing && (l + 1 < I.max_iter);
-    const int k0 = tzi * I.chunk;
-    const int k1 = min(k0 + I.chunk, nz);
+    const int k0 = tzi * I.chunk2;
+    const int k1 = min(k0 + I.chunk2, nz);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int x = x0 + lane;
     const unsigned NXY = (unsigned)nx * (unsigned)ny;
@@ -544,15 +575,20 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
     int rlx = 0, rly = 0, tlx = 2, tly = 2;
     unsigned rso = oo[0];
     float2 rux = make_float2(1.f, 0.f), ruz = make_float2(1.f, 0.f);
-    bool rcross = false;  // ring slot beyond the seam: computed from global memory
-    CellSrc rcs{0, SRC_ZERO, 0, make_float2(1.f, 0.f)};
+    // ring slot beyond the seam (a row slot at y = -1 or ny): its real
+    // node's update comes from k_seam_ring, at sring[(p 2) nx + rsr], times
+    // P (row -1) or conj P (row ny) at its x, cell_src2's rule for the slot
+    bool rcross = false, rtop = false;
+    unsigned rsr = 0, rsx = 0;
     if (hthr) {
         int gx, gy;
         halo_cell<TYv>(hidx, x0, y0, gx, gy, rlx, rly);
         const int sx = xper ? ((gx % nx) + nx) % nx : gx;
         rcross = gy < 0 || gy >= ny;
+        rtop = gy < 0;
         const int sy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
-        if (rcross) rcs = cell_src2(I, gx, gy);
+        rsx = (unsigned)sx;
+        rsr = (unsigned)((gy < 0 ? 0 : nx) + sx);
         rso = (unsigned)(sy * nx + sx);
         tlx = gx - x0 + 2;
         tly = gy - y0 + 2;
@@ -673,7 +709,9 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
             }
             if (hthr) {
                 if (seam && rcross) {
-                    lb[lq][rly][rlx] = slot_update<YZ>(I, src, Pt, bhp, dhp, rcs, p, NXY, zper);
+                    const float2 v = ld2((const gf2 *)I.sring, (unsigned)p * 2u * (unsigned)nx + rsr);
+                    const float2 ph = ld2(Pt, (unsigned)p * nx + rsx);
+                    lb[lq][rly][rlx] = rtop ? xcmul(ph, v) : xcmulc(ph, v);
                 } else {
                     const float2 ns = nsum(xlink<YZ>(I, rux, p), ruz, L[tly][tlx - 1], L[tly][tlx + 1],
                                            L[tly - 1][tlx], L[tly + 1][tlx], Lm[tly][tlx], Lp[tly][tlx], zm, zp, cx,
@@ -724,6 +762,9 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
         wg_max_to<WGI>(row_slot(I.res, I.rstride, l + 1, b), rmax2, red);
     }
 }
+
+template __global__ void k_seam_ring<false>(const Inst *, const int *, int, int);
+template __global__ void k_seam_ring<true>(const Inst *, const int *, int, int);
 
 #define TDGL_INST2(R, NT, YZ)                                                                           \
     template __global__ void k_sweep2<R, NT, YZ>(const Inst *, const int *, int, int, unsigned long long *,  \

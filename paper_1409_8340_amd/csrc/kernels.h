@@ -15,6 +15,8 @@ constexpr int FIN_THREADS = 256;  // threads per instance of the solve finalizer
 template <int R, bool NT, bool YZ>
 __global__ void k_sweep2(const Inst *insts, const int *prefix, int ninst, int l, unsigned long long *pub,
                          unsigned seq);
+template <bool YZ>
+__global__ void k_seam_ring(const Inst *insts, const int *prefix, int ninst, int l);
 template <int R, bool NT, bool YZ>
 __global__ void k_sweep2i(const Inst *insts, const int *prefix, int ninst, int l, unsigned long long *pub,
                           unsigned seq);

@@ -128,6 +128,7 @@ struct Inst {
     double *part;        // per-work-group partial sums
     int part_cap;
     int tiles_x, tiles_y, tiles_z, chunk;   // stencil tiling (chunk: z planes per tile)
+    int chunk2, tiles_z2;                   // z planes per work-group of the two-sweep super-tile kernel
     int rows;                               // rows per thread R (tile 64 x 4R)
     // two-sweep passes: (x, y) tiles that are not interior (tile_interior2),
     // as txi + tiles_x tyi in increasing order, and the z planes per
@@ -135,6 +136,7 @@ struct Inst {
     int *btile;
     int nbt, bchunk;
     int seam2;           // super-tiles start at y = 0 and cover the quasi-periodic y seam
+    float2 *sring;       // seam2: Jacobi updates of rows ny-1 and 0, [plane][2][x], made per two-sweep pass
                          // (periodic y, ny a multiple of TYS); else they start one tile row in
     int nlev;
     MGLevel lev[kMaxLevels];

@@ -303,14 +303,20 @@ def test_two_sweep_passes_bit_identical(shape, open_, Bx, Bz, driven, rows):
     c = Case(nx, ny, nz, **kw)
     a = c.solver()
     f = c.solver()
+    g = c.solver()
     a.set_tiling(rows=rows, chunk=4, fused=0)
     f.set_tiling(rows=rows, chunk=4, fused=1)
+    # the super-tile kernel with z runs of its own (chunk2)
+    g.set_tiling(rows=rows, chunk=4, fused=1, chunk2=3)
+    assert g.tiling()["chunk2"] == min(3, nz) and g.tiling()["chunk"] == min(4, nz)
     for rep in range(3):
         sa = a.step(2)
         sf = f.step(2)
+        sg = g.step(2)
         for k in ("sweeps_sum", "sweeps_min", "sweeps_max", "capped_steps"):
-            assert sa[k] == sf[k], (rep, k, sa, sf)
+            assert sa[k] == sf[k] == sg[k], (rep, k, sa, sf, sg)
         assert np.array_equal(a.get_psi().cpu().numpy(), f.get_psi().cpu().numpy()), rep
+        assert np.array_equal(a.get_psi().cpu().numpy(), g.get_psi().cpu().numpy()), rep
     sg = f.step_graph(2)
     sa = a.step(2)
     assert sa["sweeps_sum"] == sg["sweeps_sum"]
@@ -331,6 +337,7 @@ def test_two_sweep_passes_bit_identical(shape, open_, Bx, Bz, driven, rows):
     print(f"[fused] {shape} {open_} rows={rows} sweeps {sa['sweeps_sum']} passes {sf['sweep_passes']}")
     a.close()
     f.close()
+    g.close()
 
 
 @pytest.mark.parametrize("shape,open_,Bx,Bz,driven", [FUSED_CASES[0], FUSED_CASES[1], FUSED_CASES[8]])
