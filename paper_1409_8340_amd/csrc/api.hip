@@ -2202,7 +2202,7 @@ tdgl_status tdgl_get_tiling(const tdgl_ctx *ctx, int inst, tdgl_tiling *out) {
 namespace {
 
 struct AdjLayout {
-    float2 *ck_psi, *seg_psi, *fin_psi, *psibar, *t1, *t2, *t3, *lamW;
+    float2 *ck_psi, *seg_psi, *fin_psi, *psibar, *t1, *t2, *t3, *lamW, *lamW2;
     float *ck_mu, *seg_mu, *fin_mu, *mubar;
     double *ck_K, *seg_K, *fin_K, *Elog, *vbar;
     DevState *fin_st;
@@ -2229,6 +2229,7 @@ size_t adj_layout(long N, int nsteps, int C, char *base, AdjLayout *L) {
     l.t2 = cv.take<float2>(N);
     l.t3 = cv.take<float2>(N);
     l.lamW = cv.take<float2>(N);
+    l.lamW2 = cv.take<float2>(N);
     l.Elog = cv.take<double>(nsteps);
     l.vbar = cv.take<double>(1);
     l.adj = cv.take<AdjState>(1);
@@ -2237,7 +2238,12 @@ size_t adj_layout(long N, int nsteps, int C, char *base, AdjLayout *L) {
 }
 
 // Reverse of one step: prev = state n-1, nxt = state n (segment slots).
-tdgl_status adjoint_step(tdgl_ctx *c, const AdjLayout &L, int iprev, int inext, double ew, float *grad) {
+// k: reverse steps done before this one.  The last two reverse steps'
+// solutions (lambda / W) alternate between lamW and lamW2: the newest warm
+// starts this step's M^H solve (extrapolated with the older from the third
+// reverse step on), and this step's solution replaces the older.
+tdgl_status adjoint_step(tdgl_ctx *c, const AdjLayout &L, int iprev, int inext, double ew, float *grad, int k) {
+    float2 *newest = (k & 1) ? L.lamW2 : L.lamW, *older = (k & 1) ? L.lamW : L.lamW2;
     const Inst &d = c->inst[0].d;
     const long N = d.N;
     hipStream_t s = c->stream;
@@ -2270,13 +2276,13 @@ tdgl_status adjoint_step(tdgl_ctx *c, const AdjLayout &L, int iprev, int inext, 
     // the Crank-Nicolson system transposed
     hipLaunchKernelGGL(k_adj_maxabs, dim3(G), dim3(256), 0, s, c->d_inst, L.psibar);
     hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(256), 0, s, c->d_inst, G, 3, 0.0, L.adj);
-    hipLaunchKernelGGL(k_adj_assemble, dim3(G), dim3(256), 0, s, c->d_inst, L.psibar, psim, mum, L.lamW, L.adj);
+    hipLaunchKernelGGL(k_adj_assemble, dim3(G), dim3(256), 0, s, c->d_inst, L.psibar, psim, mum, newest, older, k >= 2 ? 1 : 0, L.adj);
     LAUNCHCHK();
     e = jacobi_loop(c, nullptr, nullptr, 0);
     if (e) return e;
     // sources: eps gradient, mubar^-, K terms and psibar^-
-    hipLaunchKernelGGL(k_adj_scale_nu, dim3(G), dim3(256), 0, s, c->d_inst, L.adj, L.lamW);
-    launch_stencil<MODE_NS>(c, 0, L.lamW, L.t2);
+    hipLaunchKernelGGL(k_adj_scale_nu, dim3(G), dim3(256), 0, s, c->d_inst, L.adj, older);
+    launch_stencil<MODE_NS>(c, 0, older, L.t2);
     hipLaunchKernelGGL(k_adj_edge_s, dim3(G), dim3(256), 0, s, c->d_inst, psim, psin, L.adj);
     hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(256), 0, s, c->d_inst, G, 2, 0.0, L.adj);
     hipLaunchKernelGGL(k_adj_sources, dim3(G), dim3(256), 0, s, c->d_inst, L.psibar, L.mubar, grad, psim, psin,
@@ -2310,6 +2316,7 @@ tdgl_status voltage_grad_run(tdgl_ctx *ctx, int nsteps, int window_begin, int C,
     hipLaunchKernelGGL(k_fill_f, dim3(fill_grid(N)), dim3(256), 0, s, grad, N, 0.f);
     hipLaunchKernelGGL(k_fill_c, dim3(fill_grid(N)), dim3(256), 0, s, L.psibar, N, 0.f, 0.f);
     hipLaunchKernelGGL(k_fill_c, dim3(fill_grid(N)), dim3(256), 0, s, L.lamW, N, 0.f, 0.f);
+    hipLaunchKernelGGL(k_fill_c, dim3(fill_grid(N)), dim3(256), 0, s, L.lamW2, N, 0.f, 0.f);
     hipLaunchKernelGGL(k_fill_f, dim3(fill_grid(N)), dim3(256), 0, s, L.mubar, N, 0.f);
     hipLaunchKernelGGL(k_adj_zero, dim3(1), dim3(64), 0, s, L.adj);
     LAUNCHCHK();
@@ -2358,7 +2365,7 @@ tdgl_status voltage_grad_run(tdgl_ctx *ctx, int nsteps, int window_begin, int C,
         }
         for (int n = s1; n > s0; --n) {
             const double ew = (n - 1 >= window_begin) ? 1.0 / W : 0.0;
-            tdgl_status e = adjoint_step(ctx, L, n - 1 - s0, n - s0, ew, grad);
+            tdgl_status e = adjoint_step(ctx, L, n - 1 - s0, n - s0, ew, grad, nsteps - n);
             if (e) return e;
         }
     }

@@ -187,14 +187,18 @@ __global__ __launch_bounds__(256) void k_adj_maxabs(const Inst *__restrict__ ins
 
 // Adjoint system of step n: M~ nu = W^-1 psibar / scale with M from
 // (psi^-, mu^-, eps).  Writes b/M~ and (ht/2)/M~.  The solve starts warm
-// from the previous reverse step's solution: lamW holds scale' nu' of that
-// step (zero before the first), so nu^(0) = lamW / scale.  No sweep has
+// from the previous reverse steps' solutions: lamW holds scale' nu' of the
+// last one (zero before the first) and lamW_old that of the one before, so
+// nu^(0) = lamW / scale, or, with extrap, the linear extrapolation
+// (2 lamW - lamW_old) / scale in reverse time (about a third fewer sweeps
+// at 128 x 128 x 32; the stop rule is unchanged).  No sweep has
 // produced that iterate, so it is stored as iterate 1 and convergence row 0
 // is marked open (+inf): sweep 1 then measures the residual of nu^(0) and
 // the solve proceeds as usual, one iteration index later.
 __global__ __launch_bounds__(256) void k_adj_assemble(const Inst *__restrict__ insts, const float2 *psibar,
                                                       const float2 *psim, const float *mum,
-                                                      const float2 *lamW, const AdjState *adj) {
+                                                      const float2 *lamW, const float2 *lamW_old, int extrap,
+                                                      const AdjState *adj) {
     __shared__ float red[4];
     const Inst &I = insts[0];
     const float inv_s = (float)(1.0 / adj->scale);
@@ -211,7 +215,13 @@ __global__ __launch_bounds__(256) void k_adj_assemble(const Inst *__restrict__ i
         const float2 rhs = cscale(inv_s / node_wm(I, m), psibar[m]);
         I.bh[m] = cmul(rhs, Mi);
         I.dh[m] = cscale(ht2, Mi);
-        nu1[m] = cscale(inv_s, lamW[m]);
+        const float2 w0 = lamW[m];
+        float2 g = w0;
+        if (extrap) {
+            const float2 w1 = lamW_old[m];
+            g = make_float2(2.f * w0.x - w1.x, 2.f * w0.y - w1.y);
+        }
+        nu1[m] = cscale(inv_s, g);
     }
     wg_max_to<256>(row_slot(I.res, I.rstride, 0, blockIdx.x), __int_as_float(0x7f800000), red);
 }

@@ -87,7 +87,7 @@ __global__ void k_adj_edge_f(const Inst *insts, const float2 *psin);
 __global__ void k_adj_jterm(const Inst *insts, float2 *psibar, const float2 *psin, const AdjState *adj);
 __global__ void k_adj_maxabs(const Inst *insts, const float2 *psibar);
 __global__ void k_adj_assemble(const Inst *insts, const float2 *psibar, const float2 *psim, const float *mum,
-                               const float2 *lamW, const AdjState *adj);
+                               const float2 *lamW, const float2 *lamW_old, int extrap, const AdjState *adj);
 __global__ void k_adj_scale_nu(const Inst *insts, const AdjState *adj, float2 *tmp);
 __global__ void k_adj_sources(const Inst *insts, float2 *psibar, float *mubar, float *epsbar, const float2 *psim,
                               const float2 *psin, const float *mum, const float2 *ns_l, const AdjState *adj);
