@@ -81,8 +81,8 @@ def test_checkpoint_spacing_and_final_state(name):
     psi3, mu3, sc3 = s3.get_psi().cpu().numpy(), s3.get_mu().cpu().numpy(), s3.get_scalars()
     s3.close()
     assert v1 == v2
-    # checkpoints replay the steps bit for bit and every reverse solve starts
-    # from zero, so the spacing changes nothing
+    # checkpoints replay the steps bit for bit and the reverse solves run in
+    # the same order from the same warm starts, so the spacing changes nothing
     assert np.array_equal(g1.cpu().numpy(), g2.cpu().numpy())
     assert np.array_equal(psi1, psi3)
     assert np.array_equal(mu1, mu3)
@@ -156,19 +156,32 @@ def test_directional_derivative_at_c4_size():
     assert abs(fd - ad) <= 2e-2 * abs(fd)
 
 
-def test_adjoint_with_persistent_solves():
-    """tdgl_voltage_grad gives the same gradient when every Jacobi solve
-    (forward replays and adjoint systems) runs as one persistent launch."""
-    case = _make("spectral")
-    s1 = case.solver()
-    v1, g1 = s1.voltage_grad(5, 1, ckpt_every=2)
-    s1.close()
-    s2 = case.solver()
-    s2.set_tiling(rows=2, persistent=1)
-    v2, g2 = s2.voltage_grad(5, 1, ckpt_every=2)
-    s2.close()
-    assert v1 == v2
-    assert np.array_equal(g1.cpu().numpy(), g2.cpu().numpy())
+@pytest.mark.parametrize("name", list(CASES))
+def test_adjoint_tiling_independent(name):
+    """Iterates do not depend on the tiling, so neither does the adjoint:
+    the same V and gradient under the default tiling, a persistent solve and
+    two-sweep passes (whose forward, recomputed and adjoint solves take
+    either pass schedule), and the state left is the one plain steps reach."""
+    case = _make(name)
+    out = []
+    for t in (None, dict(rows=2, persistent=1), dict(rows=2, chunk=4, fused=1, chunk2=8)):
+        s = case.solver()
+        if t is not None:
+            s.set_tiling(**t)
+        v, g = s.voltage_grad(5, 1, ckpt_every=2)
+        psi, mu = s.get_psi().cpu().numpy(), s.get_mu().cpu().numpy()
+        s.close()
+        s = case.solver()
+        if t is not None:
+            s.set_tiling(**t)
+        s.step(5)
+        assert np.array_equal(psi, s.get_psi().cpu().numpy())
+        assert np.array_equal(mu, s.get_mu().cpu().numpy())
+        s.close()
+        out.append((v, g.cpu().numpy()))
+    for v, g in out[1:]:
+        assert v == out[0][0]
+        assert np.array_equal(g, out[0][1])
 
 
 C4_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "c4_adjoint_oracle.json")
