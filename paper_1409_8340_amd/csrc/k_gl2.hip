@@ -604,15 +604,21 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
     // (the phase entries are loaded by every tile, with the other loads and
     // unconditionally, so that no load sits under a branch; only seam tiles
     // use them)
+    // A load whose values are not used (p < 0: a plane beyond an open face,
+    // or a padding step after the run) reads the tile's first node from
+    // every lane, one line per wavefront, rather than a whole plane whose
+    // lines have long left L2.
+    const unsigned o0 = (unsigned)(y0 * nx + x0);
     auto load_a = [&](int p, float2 *ao, float2 *hv, float2 *ph) {
         const int pp = p < 0 ? 0 : p;
-        const unsigned pb = (unsigned)pp * NXY;
+        const unsigned msk = p < 0 ? 0u : ~0u;
+        const unsigned pb = p < 0 ? o0 : (unsigned)pp * NXY;
 #pragma unroll
-        for (int r = 0; r < R; ++r) ao[r] = ld2(src, pb + oo[r]);
+        for (int r = 0; r < R; ++r) ao[r] = ld2(src, pb + (oo[r] & msk));
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) hv[q] = ld2(src, pb + h2o[q]);
+        for (int q = 0; q < NQ; ++q) hv[q] = ld2(src, pb + (h2o[q] & msk));
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) ph[q] = ld2(Pt, (unsigned)pp * nx + h2x[q]);
+        for (int q = 0; q < NQ; ++q) ph[q] = ld2(Pt, (unsigned)pp * nx + (h2x[q] & msk));
     };
     auto stage_a = [&](int v, const float2 *ao, const float2 *hv, const float2 *ph) {
         float2 (*L)[LX] = la[v & 3];
@@ -632,14 +638,15 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
         }
     };
     auto load_bd = [&](int p, float2 *bh_, float2 *dh_, float2 &rbh, float2 &rdh) {
-        const unsigned pb = (unsigned)(p < 0 ? 0 : p) * NXY;
+        const unsigned msk = p < 0 ? 0u : ~0u;
+        const unsigned pb = p < 0 ? o0 : (unsigned)p * NXY;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            bh_[r] = ld2(bhp, pb + oo[r]);
-            dh_[r] = ld2(dhp, pb + oo[r]);
+            bh_[r] = ld2(bhp, pb + (oo[r] & msk));
+            dh_[r] = ld2(dhp, pb + (oo[r] & msk));
         }
-        rbh = ld2(bhp, pb + rso);
-        rdh = ld2(dhp, pb + rso);
+        rbh = ld2(bhp, pb + (rso & msk));
+        rdh = ld2(dhp, pb + (rso & msk));
     };
 
     const int vb0 = (pz(k0 - 1) >= 0) ? k0 - 1 : k0;
