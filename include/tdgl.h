@@ -385,6 +385,9 @@ typedef struct tdgl_tiling {
                         super-tile kernel (fused = 1); 0: chunk.  The stencil
                         passes (assemble, Poisson right side, single sweeps)
                         keep chunk                                          */
+    int rhs_rows;    /* rows per thread of the Poisson right-side pass: 0 =
+                        rows, or 4 (64 x 16 tiles, z runs chosen as for
+                        chunk); the result does not depend on it           */
 } tdgl_tiling;
 
 /* Picks the stencil tiling of the context by timing one Jacobi sweep for

@@ -327,6 +327,8 @@ struct InstHost {
     Inst d;
     Hierarchy H;
     int st_blocks = 0, flat_blocks = 0;
+    int r4_blocks = 0;  // blocks of the four-row Poisson right-side pass
+    float2 *edge_buf = nullptr;  // side copies of b/M for two-sweep super-tiles (Inst::edge when in use)
     int mg_blocks[kMaxLevels] = {0};
     int fx_blocks = 0, fy_blocks = 0, fz_blocks = 0;  // spectral Poisson passes
     double Bx = 0, Bz = 0, J = 0;
@@ -351,6 +353,12 @@ void set_tiling(InstHost &h, int rows, int chunk_req, int chunk2_req) {
     d.chunk2 = chunk2_req > 0 ? std::min(chunk2_req, p.nz) : d.chunk;
     d.tiles_z2 = cdiv(p.nz, d.chunk2);
     h.st_blocks = (int)(txy * d.tiles_z);
+    // the four-row right-side tiling (the stencil's own when rows = 4)
+    d.tiles_y4 = cdiv(p.ny, 16);
+    const long txy4 = (long)d.tiles_x * d.tiles_y4;
+    d.chunk4 = auto_chunk(txy4, p.nz, chunk_req);
+    d.tiles_z4 = cdiv(p.nz, d.chunk4);
+    h.r4_blocks = (int)(txy4 * d.tiles_z4);
 }
 
 }  // namespace
@@ -370,8 +378,11 @@ struct tdgl_ctx {
     int *d_pref_b = nullptr;  // blocks of the two-sweep boundary kernel per instance
     int *d_pref_i = nullptr;  // ... and of the interior (super-tile) kernel
     int *d_pref_sr = nullptr;  // ... and of the seam-ring pre-pass (seam2 instances)
-    int tot_b = 0, tot_i = 0, tot_sr = 0;
+    int *d_pref_r4 = nullptr;  // blocks of the four-row Poisson right-side pass
+    int tot_b = 0, tot_i = 0, tot_sr = 0, tot_r4 = 0;
+    int rhs_rows = 0;  // rows per thread of the Poisson right side (0: rows)
     int *d_np_st = nullptr, *d_np_flat = nullptr, *d_np_mg0 = nullptr;
+    int *d_np_r4 = nullptr;  // per instance: blocks of the four-row right-side pass
     unsigned *d_res = nullptr, *d_mures = nullptr;
     unsigned *h_mures = nullptr;  // pinned copy of the Poisson rows
     // Jacobi convergence words handed over by the sweeps themselves (pinned,
@@ -457,7 +468,9 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
     int *pref_b = cv.take<int>(n + 1);
     int *pref_i = cv.take<int>(n + 1);
     int *pref_sr = cv.take<int>(n + 1);
+    int *pref_r4 = cv.take<int>(n + 1);
     int *np_st = cv.take<int>(n);
+    int *np_r4 = cv.take<int>(n);
     int *np_flat = cv.take<int>(n);
     int *np_mg0 = cv.take<int>(n);
     const int npad = (n + 63) / 64 * 64;
@@ -501,6 +514,7 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
         d.psi[1] = cv.take<float2>(N);
         d.bh = cv.take<float2>(N);
         d.dh = cv.take<float2>(N);
+        h.edge_buf = cv.take<float2>((size_t)4 * cdiv(p.nx, TX) * p.ny * p.nz);
         d.eps = cv.take<float>(N);
         d.ux = cv.take<float2>(p.ny);
         d.uz = cv.take<float2>(p.ny);
@@ -517,7 +531,11 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
         d.mu_max_cycles = p.driven ? p.mu_max_cycles : 1;
         // stencil tiling
         set_tiling(h, ctx_rows(n, params), p.tile_cz, 0);
-        h.flat_blocks = cdiv(N, 256L * JAV_CPT);
+        // longer runs per thread where the grid is large: a work-group's
+        // fixed costs (descriptor loads, the FP64 reduction) are paid once
+        // for more cells
+        d.fcpt = (int)std::max<long>(JAV_CPT, std::min<long>(JAV_CPT_MAX, N / (256L * 2048) / 8 * 8));
+        h.flat_blocks = cdiv(N, 256L * d.fcpt);
         int part_cap = (int)std::max<long>(max_st_blocks(p), h.flat_blocks);
         // multigrid
         if (p.driven) {
@@ -580,7 +598,13 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
                 d.twx = cv.take<float2>(p.nx);
                 d.twy = cv.take<float2>(p.ny);
                 d.zip = cv.take<double>((size_t)p.ny * P * p.nz);
-                h.fx_blocks = cdiv((long)p.ny * p.nz, 2L * fft_x_pairs(p.nx));
+                {
+                    // groups of fft_x_pairs row pairs; up to eight per
+                    // work-group while at least 2048 groups' work remain
+                    const long groups = cdiv((long)p.ny * p.nz, 2L * fft_x_pairs(p.nx));
+                    d.fxg = (int)std::max(1L, std::min(8L, groups / 2048));
+                    h.fx_blocks = (int)cdiv(groups, (long)d.fxg);
+                }
                 h.fy_blocks = p.nz * cdiv(P, fft_y_cols(p.ny));
                 h.fz_blocks = p.nz <= FFT_ZSERIAL ? cdiv(p.ny * P, 256) : p.ny * cdiv(P, FFT_ZTK);
             }
@@ -602,7 +626,9 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
         ctx->d_pref_b = pref_b;
         ctx->d_pref_i = pref_i;
         ctx->d_pref_sr = pref_sr;
+        ctx->d_pref_r4 = pref_r4;
         ctx->d_np_st = np_st;
+        ctx->d_np_r4 = np_r4;
         ctx->d_np_flat = np_flat;
         ctx->d_np_mg0 = np_mg0;
         ctx->d_res = res;
@@ -863,6 +889,25 @@ void launch_stencil(tdgl_ctx *c, int l, const float2 *in = nullptr, float2 *out 
     else if (c->rows == 2) launch_stencil_r<MODE, 2>(c, l, in, out);
     else launch_stencil_r<MODE, 4>(c, l, in, out);
 }
+// The Poisson right-side pass: with the context's tile, or on 64 x 16
+// tiles with four rows per thread (its own block table) when the tiling
+// asks for them.
+void launch_rhs(tdgl_ctx *c) {
+    if (c->rhs_rows != 4) {
+        launch_stencil<MODE_RHS>(c, 0);
+        return;
+    }
+    if (c->any_yz)
+        hipLaunchKernelGGL((k_stencil<MODE_RHS, 4, false, true>), dim3(c->tot_r4), dim3(WG), 0, c->stream,
+                           c->d_inst, c->d_pref_r4, c->n, 0, nullptr, nullptr, nullptr, 0u);
+    else
+        hipLaunchKernelGGL((k_stencil<MODE_RHS, 4, false, false>), dim3(c->tot_r4), dim3(WG), 0, c->stream,
+                           c->d_inst, c->d_pref_r4, c->n, 0, nullptr, nullptr, nullptr, 0u);
+}
+
+// Per-instance counts of the partial sums the right-side pass writes.
+const int *rhs_parts(const tdgl_ctx *c) { return c->rhs_rows == 4 ? c->d_np_r4 : c->d_np_st; }
+
 // The assemble pass, with the Langevin draws where some instance has them.
 void launch_assemble(tdgl_ctx *c, int l = 0) {
     if (c->noisy)
@@ -1271,8 +1316,8 @@ tdgl_status enqueue_step_fixed(tdgl_ctx *ctx, int budget) {
     if (!ctx->any_driven) return TDGL_OK;
     hipLaunchKernelGGL(k_jav_partial, dim3(ctx->tot_flat), dim3(256), 0, s, ctx->d_inst, ctx->d_pref_flat, n);
     hipLaunchKernelGGL(k_kupdate, dim3(n), dim3(256), 0, s, ctx->d_inst, ctx->d_np_flat);
-    launch_stencil<MODE_RHS>(ctx, 0);
-    hipLaunchKernelGGL(k_reduce_to_state, dim3(n), dim3(256), 0, s, ctx->d_inst, ctx->d_np_st, 0, 1);
+    launch_rhs(ctx);
+    hipLaunchKernelGGL(k_reduce_to_state, dim3(n), dim3(256), 0, s, ctx->d_inst, rhs_parts(ctx), 0, 1);
     LAUNCHCHK();
     tdgl_status e = enqueue_fft(ctx);
     if (e) return e;
@@ -1760,8 +1805,8 @@ tdgl_status tdgl_step(tdgl_ctx *ctx, int nsteps, tdgl_step_stats *stats) {
             }
             {
                 ProfScope ps(ctx, TDGL_K_RHS);
-                launch_stencil<MODE_RHS>(ctx, 0);
-                hipLaunchKernelGGL(k_reduce_to_state, dim3(n), dim3(256), 0, s, ctx->d_inst, ctx->d_np_st, 0, 1);
+                launch_rhs(ctx);
+                hipLaunchKernelGGL(k_reduce_to_state, dim3(n), dim3(256), 0, s, ctx->d_inst, rhs_parts(ctx), 0, 1);
             }
             LAUNCHCHK();
             tdgl_status e = enqueue_poisson(ctx, &acc);
@@ -1896,7 +1941,7 @@ constexpr int kBoundaryChunk = 8;
 
 tdgl_status upload_tiling(tdgl_ctx *ctx) {
     const int n = ctx->n;
-    std::vector<int> ps(n + 1, 0), nps(n), pb(n + 1, 0), pi(n + 1, 0), psr(n + 1, 0);
+    std::vector<int> ps(n + 1, 0), nps(n), pb(n + 1, 0), pi(n + 1, 0), psr(n + 1, 0), pr4(n + 1, 0), npr4(n);
     std::vector<Inst> di(n);
     for (int i = 0; i < n; ++i) {
         InstHost &h = ctx->inst[i];
@@ -1925,8 +1970,21 @@ tdgl_status upload_tiling(tdgl_ctx *ctx) {
         if (!bt.empty()) HIPCHK(hipMemcpy(d.btile, bt.data(), bt.size() * 4, hipMemcpyHostToDevice));
         d.nbt = (int)bt.size();
         d.bchunk = std::min(d.chunk, kBoundaryChunk);
+        // side copies of b/M for the super-tiles' ring, addressed from bh and
+        // dh with 32-bit offsets
+        {
+            const size_t esz = (size_t)4 * d.tiles_x * d.ny * d.nz;
+            const bool fit = h.edge_buf > d.dh && d.dh > d.bh &&
+                             (size_t)(h.edge_buf - d.bh) + esz < (size_t(1) << 32);
+            d.edge = (ctx->fused && fit && nsy > 0) ? h.edge_buf : nullptr;
+            d.edge_r = (unsigned)(esz / 2);
+            d.edge_ob = fit ? (unsigned)(h.edge_buf - d.bh) : 0u;
+            d.edge_od = fit ? (unsigned)(h.edge_buf - d.dh) : 0u;
+        }
         ps[i + 1] = ps[i] + h.st_blocks;
         nps[i] = h.st_blocks;
+        pr4[i + 1] = pr4[i] + h.r4_blocks;
+        npr4[i] = h.r4_blocks;
         pb[i + 1] = pb[i] + d.nbt * cdiv(d.nz, d.bchunk);
         di[i] = d;
     }
@@ -1935,11 +1993,14 @@ tdgl_status upload_tiling(tdgl_ctx *ctx) {
     HIPCHK(hipMemcpy(ctx->d_pref_b, pb.data(), (n + 1) * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_pref_i, pi.data(), (n + 1) * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_pref_sr, psr.data(), (n + 1) * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_pref_r4, pr4.data(), (n + 1) * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_np_r4, npr4.data(), n * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_inst, di.data(), n * sizeof(Inst), hipMemcpyHostToDevice));
     ctx->tot_st = ps[n];
     ctx->tot_b = pb[n];
     ctx->tot_i = pi[n];
     ctx->tot_sr = psr[n];
+    ctx->tot_r4 = pr4[n];
     return TDGL_OK;
 }
 
@@ -1950,11 +2011,13 @@ struct Tiling {
     int nt = 0;       // streaming hints
     int fused = 0;    // two-sweep passes
     int persist = 0;  // one cooperative launch per Jacobi solve
+    int rhs4 = 0;     // Poisson right side on 64 x 16 tiles (four rows per thread)
 };
 
 tdgl_status apply_tiling(tdgl_ctx *ctx, const Tiling &t) {
     drop_graph(ctx);
     ctx->rows = t.rows;
+    ctx->rhs_rows = (t.rhs4 && t.rows != 4) ? 4 : 0;
     ctx->nt = t.nt != 0;
     ctx->fused = t.fused != 0;
     ctx->persist = t.persist != 0 && !ctx->fused && !ctx->any_yz;
@@ -1986,15 +2049,16 @@ bool tune_file_lookup(const char *path, const std::string &key, Tiling *t, doubl
     bool found = false;
     while (fgets(line, sizeof line, f)) {
         char k[4000];
-        int r, c, nt, fu, pe, c2 = 0;
+        int r, c, nt, fu, pe, c2 = 0, r4 = 0;
         double u;
-        // key rows chunk streaming fused persistent us [chunk2]
-        const int got = sscanf(line, "%3999s %d %d %d %d %d %lf %d", k, &r, &c, &nt, &fu, &pe, &u, &c2);
-        if ((got == 7 || got == 8) && key == k && (r == 1 || r == 2 || r == 4) && c >= 0 && c2 >= 0 &&
-            (nt == 0 || nt == 1) && (fu == 0 || fu == 1) && (pe == 0 || pe == 1)) {
+        // key rows chunk streaming fused persistent us [chunk2 [rhs4]]
+        const int got = sscanf(line, "%3999s %d %d %d %d %d %lf %d %d", k, &r, &c, &nt, &fu, &pe, &u, &c2, &r4);
+        if (got >= 7 && key == k && (r == 1 || r == 2 || r == 4) && c >= 0 && c2 >= 0 &&
+            (nt == 0 || nt == 1) && (fu == 0 || fu == 1) && (pe == 0 || pe == 1) && (r4 == 0 || r4 == 1)) {
             t->rows = r;
             t->chunk = c;
-            t->chunk2 = got == 8 ? c2 : 0;
+            t->chunk2 = got >= 8 ? c2 : 0;
+            t->rhs4 = got >= 9 ? r4 : 0;
             t->nt = nt;
             t->fused = fu;
             t->persist = pe;
@@ -2133,13 +2197,34 @@ tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *ch
                 best_us = pus;
             }
         }
+        // the Poisson right side on the chosen tile or on 64 x 16 tiles with
+        // four rows per thread, whichever runs faster
+        bool any_driven = false;
+        for (const auto &h : ctx->inst) any_driven = any_driven || h.p.driven;
+        if (any_driven && best.rows != 4) {
+            float rms[2];
+            for (int q4 = 0; q4 < 2; ++q4) {
+                Tiling t = best;
+                t.rhs4 = q4;
+                tdgl_status e = apply_tiling(ctx, t);
+                if (e) return e;
+                launch_rhs(ctx);  // warm-up
+                HIPCHK(hipEventRecord(e0, s));
+                for (int q = 0; q < 4; ++q) launch_rhs(ctx);
+                HIPCHK(hipEventRecord(e1, s));
+                LAUNCHCHK();
+                HIPCHK(hipEventSynchronize(e1));
+                HIPCHK(hipEventElapsedTime(&rms[q4], e0, e1));
+            }
+            best.rhs4 = rms[1] < rms[0] ? 1 : 0;
+        }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (cache_path) {
             FILE *f = fopen(cache_path, "a");
             if (f) {
-                fprintf(f, "%s %d %d %d %d %d %.3f %d\n", key.c_str(), best.rows, best.chunk, best.nt, best.fused,
-                        best.persist, best_us, best.chunk2);
+                fprintf(f, "%s %d %d %d %d %d %.3f %d %d\n", key.c_str(), best.rows, best.chunk, best.nt, best.fused,
+                        best.persist, best_us, best.chunk2, best.rhs4);
                 fclose(f);
             }
         }
@@ -2158,6 +2243,7 @@ tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *ch
         chosen->fused = best.fused;
         chosen->persistent = ctx->persist ? 1 : 0;
         chosen->sweep_us = best_us;
+        chosen->rhs_rows = ctx->rhs_rows;
     }
     return TDGL_OK;
 }
@@ -2167,6 +2253,8 @@ tdgl_status tdgl_set_tiling(tdgl_ctx *ctx, const tdgl_tiling *t) {
     if (t->rows != 1 && t->rows != 2 && t->rows != 4) return fail(TDGL_EINVAL, "rows must be 1, 2 or 4");
     if (t->chunk < 0 || t->chunk > 1024) return fail(TDGL_EINVAL, "chunk must be in [0, 1024]");
     if (t->chunk2 < 0 || t->chunk2 > 1024) return fail(TDGL_EINVAL, "chunk2 must be in [0, 1024]");
+    if (t->rhs_rows != 0 && t->rhs_rows != 4 && t->rhs_rows != t->rows)
+        return fail(TDGL_EINVAL, "rhs_rows must be 0, 4 or rows");
     if ((t->streaming != 0 && t->streaming != 1) || (t->fused != 0 && t->fused != 1) ||
         (t->persistent != 0 && t->persistent != 1))
         return fail(TDGL_EINVAL, "streaming, fused and persistent must be 0 or 1");
@@ -2181,6 +2269,7 @@ tdgl_status tdgl_set_tiling(tdgl_ctx *ctx, const tdgl_tiling *t) {
     s.nt = t->streaming;
     s.fused = t->fused;
     s.persist = t->persistent;
+    s.rhs4 = t->rhs_rows == 4 ? 1 : 0;
     return apply_tiling(ctx, s);
 }
 
@@ -2194,6 +2283,7 @@ tdgl_status tdgl_get_tiling(const tdgl_ctx *ctx, int inst, tdgl_tiling *out) {
     out->fused = ctx->fused ? 1 : 0;
     out->persistent = ctx->persist ? 1 : 0;
     out->sweep_us = 0.0;
+    out->rhs_rows = ctx->rhs_rows;
     return TDGL_OK;
 }
 

@@ -213,8 +213,23 @@ __global__ __launch_bounds__(256) void k_adj_assemble(const Inst *__restrict__ i
         const float inv = 1.f / cabs2(Mc);
         const float2 Mi = make_float2(Mc.x * inv, -Mc.y * inv);
         const float2 rhs = cscale(inv_s / node_wm(I, m), psibar[m]);
-        I.bh[m] = cmul(rhs, Mi);
-        I.dh[m] = cscale(ht2, Mi);
+        const float2 bhv = cmul(rhs, Mi), dhv = cscale(ht2, Mi);
+        I.bh[m] = bhv;
+        I.dh[m] = dhv;
+        if (I.edge) {
+            // side copies for the two-sweep super-tiles
+            const int x = (int)(m % I.nx), t = (int)(m / I.nx);
+            int el, er;
+            edge_slots(I, x, t % I.ny, t / I.ny, el, er);
+            if (el >= 0) {
+                I.edge[el] = bhv;
+                I.edge[el + 1] = dhv;
+            }
+            if (er >= 0) {
+                I.edge[er] = bhv;
+                I.edge[er + 1] = dhv;
+            }
+        }
         const float2 w0 = lamW[m];
         float2 g = w0;
         if (extrap) {

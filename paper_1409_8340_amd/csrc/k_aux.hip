@@ -145,38 +145,29 @@ __global__ __launch_bounds__(256) void k_jav_partial(const Inst *__restrict__ in
     double acc = 0.0;
     const int nx = I.nx, ny = I.ny;
     const bool yz = I.st->yz != 0;
-    // cells m = base + c 256 + tid, c = 0 .. JAV_CPT-1, summed in that
+    // cells m = base + c 256 + tid, c = 0 .. fcpt-1, summed in that
     // order; their x, y and z indices follow from one division for c = 0
     // and then by stepping 256 cells at a time.  A wavefront's 64 lanes hold
     // 64 consecutive cells, so psi_{m+x} is the next lane's psi_m (a
-    // shuffle); the last lane and the end of an x row load it.  The loads of
-    // JB cells are issued before any of them is used (a cell past the end
-    // loads cell 0 and adds nothing).
+    // shuffle); the last lane and the end of an x row load it.  Every load
+    // of JB cells -- psi, those neighbours, the x links of their rows -- is
+    // issued before any of them is used, so a batch waits for memory once
+    // (a cell past the end loads cell 0 and adds nothing).
     constexpr int JB = 8;
-    static_assert(JAV_CPT % JB == 0, "whole batches");
+    static_assert(JAV_CPT % JB == 0 && JAV_CPT_MAX % JB == 0, "whole batches");
     const int lane = threadIdx.x & 63;
-    int m = (int)((long)lb * 256 * JAV_CPT) + (int)threadIdx.x;
+    const int cpt = I.fcpt;
+    int m = (int)((long)lb * 256 * cpt) + (int)threadIdx.x;
     int i = m % nx, j = (m / nx) % ny, k = m / (nx * ny);
     const int N = (int)I.N;
-    for (int c0 = 0; c0 < JAV_CPT; c0 += JB) {
-        float2 a[JB];
+    for (int c0 = 0; c0 < cpt; c0 += JB) {
+        int mq[JB], iq[JB], jq[JB], kq[JB];
 #pragma unroll
         for (int q = 0; q < JB; ++q) {
-            const int mq = m + q * 256;
-            a[q] = psi[mq < N ? mq : 0];
-        }
-#pragma unroll
-        for (int q = 0; q < JB; ++q) {
-            float2 p;
-            p.x = __shfl_down(a[q].x, 1, 64);
-            p.y = __shfl_down(a[q].y, 1, 64);
-            if (m < N) {
-                if (lane == 63 || i == nx - 1) p = psi[(i == nx - 1) ? m - (nx - 1) : m + 1];
-                float2 u = I.ux[j];
-                if (yz) u = xcmul(u, I.wz[k]);
-                const float2 up = cmul(u, p);
-                acc += (double)(a[q].x * up.y - a[q].y * up.x);
-            }
+            mq[q] = m;
+            iq[q] = i;
+            jq[q] = j < ny ? j : 0;
+            kq[q] = m < N ? k : 0;
             m += 256;
             i += 256;
             while (i >= nx) {
@@ -185,6 +176,31 @@ __global__ __launch_bounds__(256) void k_jav_partial(const Inst *__restrict__ in
                     j = 0;
                     ++k;
                 }
+            }
+        }
+        float2 a[JB], nb[JB], u[JB];
+#pragma unroll
+        for (int q = 0; q < JB; ++q) a[q] = psi[mq[q] < N ? mq[q] : 0];
+#pragma unroll
+        for (int q = 0; q < JB; ++q) {
+            const bool own = (lane == 63 || iq[q] == nx - 1) && mq[q] < N;
+            nb[q] = own ? psi[(iq[q] == nx - 1) ? mq[q] - (nx - 1) : mq[q] + 1] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int q = 0; q < JB; ++q) u[q] = I.ux[jq[q]];
+        if (yz) {
+#pragma unroll
+            for (int q = 0; q < JB; ++q) u[q] = xcmul(u[q], I.wz[kq[q]]);
+        }
+#pragma unroll
+        for (int q = 0; q < JB; ++q) {
+            float2 p;
+            p.x = __shfl_down(a[q].x, 1, 64);
+            p.y = __shfl_down(a[q].y, 1, 64);
+            if (mq[q] < N) {
+                if (lane == 63 || iq[q] == nx - 1) p = nb[q];
+                const float2 up = cmul(u[q], p);
+                acc += (double)(a[q].x * up.y - a[q].y * up.x);
             }
         }
     }
@@ -273,8 +289,8 @@ __global__ __launch_bounds__(256) void k_psi2_partial(const Inst *__restrict__ i
     const int lb = b - prefix[ii];
     const float2 *__restrict__ psi = I.psi[I.st->cur];
     double acc = 0.0;
-    const long base = (long)lb * 256 * JAV_CPT;
-    for (int c = 0; c < JAV_CPT; ++c) {
+    const long base = (long)lb * 256 * I.fcpt;
+    for (int c = 0; c < I.fcpt; ++c) {
         const long m = base + (long)c * 256 + threadIdx.x;
         if (m < I.N) acc += (double)cabs2(psi[m]);
     }

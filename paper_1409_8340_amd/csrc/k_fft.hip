@@ -230,48 +230,73 @@ __global__ __launch_bounds__(FFT_X_THREADS) void k_fft_x(const Inst *__restrict_
             if (t < nx) stw[t] = v[c];
         }
     }
-    const int row0 = (blockIdx.x - prefix[ii]) * 2 * pairs;
     const float *in = in_ext ? in_ext : I.f;
     float *out = out_ext ? out_ext : I.mu;
     float2 *spec = I.spec;
     const float inv_nx = 1.0f / (float)nx, inv_p = 1.0f / (float)P;
-    // sequence s (pair) holds rows row0 + 2 s (real part) and row0 + 2 s + 1
+    // a work-group takes I.fxg consecutive groups of `pairs` row pairs; the
+    // loads of the next group are issued before the current one is
+    // transformed, so they are in flight while the group works in LDS (PF;
+    // for rows longer than FFT_X_PTS the held points would cost too many
+    // registers, and each group loads its own).  Sequence s (pair) of a
+    // group holds rows row0 + 2 s (real part) and row0 + 2 s + 1; every
+    // thread holds ML of a group's points.
+    constexpr bool PF = XC <= FFT_X_PTS;
+    constexpr int ML = PF ? XC / FFT_X_THREADS : 4;  // points held (PF), or loaded per batch
     const int tot = pairs * nx;
+    const int g0 = (blockIdx.x - prefix[ii]) * I.fxg;
     if (dir < 0) {
-        for (int t0 = threadIdx.x; t0 < tot; t0 += XB * FFT_X_THREADS) {
-            float a[XB], b[XB];
+        float a[ML], b[ML];
+        auto load = [&](int row0, int t0) {
 #pragma unroll
-            for (int c = 0; c < XB; ++c) {
+            for (int c = 0; c < ML; ++c) {
                 const int t = t0 + c * FFT_X_THREADS;
                 const int s = fdiv(t, inv_nx), e = t - s * nx;
                 const int ra = row0 + 2 * s, rb = ra + 1;
                 a[c] = (t < tot && ra < rows) ? in[(size_t)ra * nx + e] : 0.f;
                 b[c] = (t < tot && rb < rows) ? in[(size_t)rb * nx + e] : 0.f;
             }
+        };
+        auto stage = [&](int t0) {
 #pragma unroll
-            for (int c = 0; c < XB; ++c) {
+            for (int c = 0; c < ML; ++c) {
                 const int t = t0 + c * FFT_X_THREADS;
                 if (t < tot) sm[t] = make_float2(a[c], b[c]);
             }
-        }
-        __syncthreads();
-        fft_lds<P2, FFT_X_THREADS, XC>(sm, nx, I.xrad, I.nxrad, pairs, nx, stw, -1.f);
-        for (int t = threadIdx.x; t < pairs * P; t += FFT_X_THREADS) {
-            const int s = fdiv(t, inv_p), k = t - s * P;
-            const float2 z = sm[s * nx + k];
-            const float2 zc = sm[s * nx + (k == 0 ? 0 : nx - k)];
-            // A = (z + conj zc)/2, B = (z - conj zc)/(2i)
-            const float2 A = make_float2(0.5f * (z.x + zc.x), 0.5f * (z.y - zc.y));
-            const float2 B = make_float2(0.5f * (z.y + zc.y), -0.5f * (z.x - zc.x));
-            const int ra = row0 + 2 * s, rb = ra + 1;
-            if (ra < rows) spec[(size_t)ra * sp + k] = A;
-            if (rb < rows) spec[(size_t)rb * sp + k] = B;
+        };
+        if (PF) load(g0 * 2 * pairs, threadIdx.x);
+        for (int g = 0; g < I.fxg; ++g) {
+            const int row0 = (g0 + g) * 2 * pairs;
+            if (row0 >= rows) break;
+            if (PF) {
+                stage(threadIdx.x);
+            } else {
+                for (int t0 = threadIdx.x; t0 < tot; t0 += ML * FFT_X_THREADS) {
+                    load(row0, t0);
+                    stage(t0);
+                }
+            }
+            __syncthreads();
+            if (PF && g + 1 < I.fxg) load(row0 + 2 * pairs, threadIdx.x);
+            fft_lds<P2, FFT_X_THREADS, XC>(sm, nx, I.xrad, I.nxrad, pairs, nx, stw, -1.f);
+            for (int t = threadIdx.x; t < pairs * P; t += FFT_X_THREADS) {
+                const int s = fdiv(t, inv_p), k = t - s * P;
+                const float2 z = sm[s * nx + k];
+                const float2 zc = sm[s * nx + (k == 0 ? 0 : nx - k)];
+                // A = (z + conj zc)/2, B = (z - conj zc)/(2i)
+                const float2 A = make_float2(0.5f * (z.x + zc.x), 0.5f * (z.y - zc.y));
+                const float2 B = make_float2(0.5f * (z.y + zc.y), -0.5f * (z.x - zc.x));
+                const int ra = row0 + 2 * s, rb = ra + 1;
+                if (ra < rows) spec[(size_t)ra * sp + k] = A;
+                if (rb < rows) spec[(size_t)rb * sp + k] = B;
+            }
+            __syncthreads();
         }
     } else {
-        for (int t0 = threadIdx.x; t0 < tot; t0 += XB * FFT_X_THREADS) {
-            float2 A[XB], B[XB];
+        float2 A[ML], B[ML];
+        auto load = [&](int row0, int t0) {
 #pragma unroll
-            for (int c = 0; c < XB; ++c) {
+            for (int c = 0; c < ML; ++c) {
                 const int t = t0 + c * FFT_X_THREADS;
                 const int s = fdiv(t, inv_nx), k = t - s * nx;
                 const int ra = row0 + 2 * s, rb = ra + 1;
@@ -279,8 +304,10 @@ __global__ __launch_bounds__(FFT_X_THREADS) void k_fft_x(const Inst *__restrict_
                 A[c] = (t < tot && ra < rows) ? spec[(size_t)ra * sp + kk] : make_float2(0.f, 0.f);
                 B[c] = (t < tot && rb < rows) ? spec[(size_t)rb * sp + kk] : make_float2(0.f, 0.f);
             }
+        };
+        auto stage = [&](int t0) {
 #pragma unroll
-            for (int c = 0; c < XB; ++c) {
+            for (int c = 0; c < ML; ++c) {
                 const int t = t0 + c * FFT_X_THREADS;
                 if (t >= tot) continue;
                 const int k = t - fdiv(t, inv_nx) * nx;
@@ -289,15 +316,30 @@ __global__ __launch_bounds__(FFT_X_THREADS) void k_fft_x(const Inst *__restrict_
                 // W = A + i B
                 sm[t] = make_float2(a.x - b.y, a.y + b.x);
             }
-        }
-        __syncthreads();
-        fft_lds<P2, FFT_X_THREADS, XC>(sm, nx, I.xrad, I.nxrad, pairs, nx, stw, +1.f);
-        for (int t = threadIdx.x; t < pairs * nx; t += FFT_X_THREADS) {
-            const int s = fdiv(t, inv_nx), e = t - s * nx;
-            const int ra = row0 + 2 * s, rb = ra + 1;
-            const float2 w = sm[t];
-            if (ra < rows) out[(size_t)ra * nx + e] = w.x;
-            if (rb < rows) out[(size_t)rb * nx + e] = w.y;
+        };
+        if (PF) load(g0 * 2 * pairs, threadIdx.x);
+        for (int g = 0; g < I.fxg; ++g) {
+            const int row0 = (g0 + g) * 2 * pairs;
+            if (row0 >= rows) break;
+            if (PF) {
+                stage(threadIdx.x);
+            } else {
+                for (int t0 = threadIdx.x; t0 < tot; t0 += ML * FFT_X_THREADS) {
+                    load(row0, t0);
+                    stage(t0);
+                }
+            }
+            __syncthreads();
+            if (PF && g + 1 < I.fxg) load(row0 + 2 * pairs, threadIdx.x);
+            fft_lds<P2, FFT_X_THREADS, XC>(sm, nx, I.xrad, I.nxrad, pairs, nx, stw, +1.f);
+            for (int t = threadIdx.x; t < pairs * nx; t += FFT_X_THREADS) {
+                const int s = fdiv(t, inv_nx), e = t - s * nx;
+                const int ra = row0 + 2 * s, rb = ra + 1;
+                const float2 w = sm[t];
+                if (ra < rows) out[(size_t)ra * nx + e] = w.x;
+                if (rb < rows) out[(size_t)rb * nx + e] = w.y;
+            }
+            __syncthreads();
         }
     }
 }

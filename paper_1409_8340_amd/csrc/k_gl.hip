@@ -71,14 +71,19 @@ __device__ __forceinline__ void stencil_tile(const Inst *__restrict__ insts, con
     }
     if ((MODE == MODE_RHS) && !I.driven) return;
 
+    // the Poisson right side with four rows per thread has a 64 x 16 tiling
+    // of its own (the same as the stencil's when the context's rows are 4)
+    constexpr bool own4 = (MODE == MODE_RHS) && (ROWS == 4);
+    const int tiles_y = own4 ? I.tiles_y4 : I.tiles_y;
+    const int chunk = own4 ? I.chunk4 : I.chunk;
     int t = b - prefix[ii];
     const int txi = t % I.tiles_x;
     t /= I.tiles_x;
-    const int tyi = t % I.tiles_y;
-    const int tzi = t / I.tiles_y;
+    const int tyi = t % tiles_y;
+    const int tzi = t / tiles_y;
     const int x0 = txi * TX, y0 = tyi * TYv;
-    const int k0 = tzi * I.chunk;
-    const int k1 = min(k0 + I.chunk, I.nz);
+    const int k0 = tzi * chunk;
+    const int k1 = min(k0 + chunk, I.nz);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int x = x0 + lane;
     const int nx = I.nx, ny = I.ny, nz = I.nz;
@@ -175,6 +180,12 @@ __device__ __forceinline__ void stencil_tile(const Inst *__restrict__ insts, con
     const unsigned long long nstep = noise ? (unsigned long long)st->n : 0ull;
     float rmax = 0.f;
     double acc = 0.0;
+    // assemble under a two-sweep tiling: slots in the side copies of b/M and
+    // (ht/2)/M of this thread's first row at z = 0 (-1: its column x is not
+    // beside a tile column); row r adds 2 r, plane k adds 2 ny k
+    int eL = -1, eR = -1;
+    if (is_first_mode(MODE) && I.edge) edge_slots(I, x, y0 + w * ROWS, 0, eL, eR);
+    const unsigned eplane = 2u * (unsigned)ny;
 
     for (int k = k0; k < k1; ++k) {
         const int buf = (k - k0) & 1;
@@ -255,6 +266,10 @@ __device__ __forceinline__ void stencil_tile(const Inst *__restrict__ insts, con
                     st2(bhw, m, bhv);
                     st2(dhw, m, dhv);
                 }
+                // side copies for the two-sweep super-tiles (one 16-byte
+                // global store each)
+                if (eL >= 0) st4(I.edge, (unsigned)eL + 2u * r + eplane * k, bhv, dhv);
+                if (eR >= 0) st4(I.edge, (unsigned)eR + 2u * r + eplane * k, bhv, dhv);
                 rmax = (r2 > rmax || r2 != r2) ? r2 : rmax;
             } else {
                 nw = jacobi(bh[r], dh[r], ns);

@@ -573,7 +573,10 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
     const int hidx = w * (HALOv / 4) + lane;
     const bool hthr = w < 4 && lane < HALOv / 4;
     int rlx = 0, rly = 0, tlx = 2, tly = 2;
-    unsigned rso = oo[0];
+    // the slot's b/M and (ht/2)/M: offsets from bh and from dh and the
+    // plane stride (a slot beside the tile reads the side copies, where the
+    // 16 rows of a side lie in one run)
+    unsigned rob = oo[0], rod = oo[0], rst = NXY;
     float2 rux = make_float2(1.f, 0.f), ruz = make_float2(1.f, 0.f);
     // ring slot beyond the seam (a row slot at y = -1 or ny): its real
     // node's update comes from k_seam_ring, at sring[(p 2) nx + rsr], times
@@ -589,7 +592,14 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
         const int sy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
         rsx = (unsigned)sx;
         rsr = (unsigned)((gy < 0 ? 0 : nx) + sx);
-        rso = (unsigned)(sy * nx + sx);
+        rob = rod = (unsigned)(sy * nx + sx);
+        if (I.edge && gy >= y0 && gy < y0 + TYv) {
+            const unsigned e = (gx < x0 ? 0u : I.edge_r) +
+                               2u * ((unsigned)txi * (unsigned)nz * (unsigned)ny + (unsigned)gy);
+            rob = I.edge_ob + e;
+            rod = I.edge_od + e + 1u;
+            rst = 2u * (unsigned)ny;
+        }
         tlx = gx - x0 + 2;
         tly = gy - y0 + 2;
         rux = I.ux[sy];
@@ -645,8 +655,9 @@ __global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(
             bh_[r] = ld2(bhp, pb + (oo[r] & msk));
             dh_[r] = ld2(dhp, pb + (oo[r] & msk));
         }
-        rbh = ld2(bhp, pb + (rso & msk));
-        rdh = ld2(dhp, pb + (rso & msk));
+        const unsigned rp = p < 0 ? o0 : (unsigned)p * rst;
+        rbh = ld2(bhp, rp + (rob & msk));
+        rdh = ld2(dhp, rp + (rod & msk));
     };
 
     const int vb0 = (pz(k0 - 1) >= 0) ? k0 - 1 : k0;

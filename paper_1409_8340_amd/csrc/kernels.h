@@ -8,7 +8,8 @@ enum { MODE_FIRST = 0, MODE_SWEEP = 1, MODE_RHS = 2, MODE_ENERGY = 3, MODE_NS = 
 // MODE_FIRSTN: MODE_FIRST with the Langevin term (a separate instantiation,
 // so that the noiseless assemble carries none of the generator's registers).
 constexpr bool is_first_mode(int m) { return m == MODE_FIRST || m == MODE_FIRSTN; }
-constexpr int JAV_CPT = 16;     // cells per thread of the flat reductions
+constexpr int JAV_CPT = 16;     // least cells per thread of the flat reductions (a multiple of 8)
+constexpr int JAV_CPT_MAX = 64; // most cells per thread, taken while 2048 or more work-groups remain
 constexpr int CO_THREADS = 1024;
 constexpr int FIN_THREADS = 256;  // threads per instance of the solve finalizers
 

@@ -38,6 +38,18 @@ __device__ __forceinline__ void st2(gf2 *p, unsigned i, float2 a) {
     v.y = a.y;
     p[i] = v;
 }
+// Two complex values at p[i], p[i + 1] (i even, p 16-byte aligned) as one
+// 16-byte global store.
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) v4f gf4;
+__device__ __forceinline__ void st4(float2 *p, unsigned i, float2 a, float2 b) {
+    v4f v;
+    v.x = a.x;
+    v.y = a.y;
+    v.z = b.x;
+    v.w = b.y;
+    ((gf4 *)p)[i >> 1] = v;
+}
 
 // The Jacobi update below is written with explicit fused multiply-adds and
 // with contraction of the remaining products and sums switched off, so that

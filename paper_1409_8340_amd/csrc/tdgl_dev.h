@@ -129,6 +129,7 @@ struct Inst {
     int part_cap;
     int tiles_x, tiles_y, tiles_z, chunk;   // stencil tiling (chunk: z planes per tile)
     int chunk2, tiles_z2;                   // z planes per work-group of the two-sweep super-tile kernel
+    int tiles_y4, chunk4, tiles_z4;         // 64 x 16 tiling of the Poisson right side with four rows per thread
     int rows;                               // rows per thread R (tile 64 x 4R)
     // two-sweep passes: (x, y) tiles that are not interior (tile_interior2),
     // as txi + tiles_x tyi in increasing order, and the z planes per
@@ -137,6 +138,14 @@ struct Inst {
     int nbt, bchunk;
     int seam2;           // super-tiles start at y = 0 and cover the quasi-periodic y seam
     float2 *sring;       // seam2: Jacobi updates of rows ny-1 and 0, [plane][2][x], made per two-sweep pass
+    // two-sweep super-tiles: copies of b/M and (ht/2)/M of the nodes beside
+    // each 64-column tile column c (x = 64c - 1 below edge_r, x = 64c + 64
+    // from edge_r), laid out [c][z][y][2], so that a super-tile reads the 16
+    // rows of one side as one run instead of a line per row (null when the
+    // tiling has no two-sweep passes or the offsets do not fit 32 bits);
+    // edge_ob, edge_od: edge relative to bh and to dh, in complex values
+    float2 *edge;
+    unsigned edge_r, edge_ob, edge_od;
                          // (periodic y, ny a multiple of TYS); else they start one tile row in
     int nlev;
     MGLevel lev[kMaxLevels];
@@ -146,6 +155,8 @@ struct Inst {
     int xrad[16], yrad[16];
     float2 *spec;        // half spectrum, nz * ny rows of pitch sp >= nx/2 + 1
     int sp;              // row pitch of spec (complex elements)
+    int fxg;             // row-pair groups per work-group of the x passes (their loads overlap the transforms)
+    int fcpt;            // cells per thread of the flat reductions (J_av, |psi|^2)
     float2 *twx, *twy;   // twiddles exp(-2 pi i k / n) along x and y
     double *zip;         // Thomas pivots of the z systems, ny * (nx/2 + 1) columns of nz
 };
@@ -212,6 +223,23 @@ __host__ __device__ inline int pass_count(int fused, int s) {
     if (fused == 0) return s - 1;
     if (fused == 1) return s / 2;
     return s == 1 ? 0 : (s + 1) / 2;
+}
+
+// Slots (complex-value index of the b/M copy; (ht/2)/M follows it) of the
+// side copies of node (x, y, z), -1 where it is not beside a tile column:
+// x = 64c - 1 is the left side of column c, x = 64c + 64 its right side
+// (across the periodic x wrap where there is one).
+__device__ __forceinline__ void edge_slots(const Inst &I, int x, int y, int z, int &el, int &er) {
+    const int nx = I.nx;
+    const bool xper = I.per[0] != 0;
+    int cl = -1, cr = -1;
+    if (((x + 1) & 63) == 0 && x + 1 < nx) cl = (x + 1) >> 6;
+    else if (xper && x == nx - 1) cl = 0;
+    if ((x & 63) == 0 && x >= 64) cr = (x >> 6) - 1;
+    else if (xper && x == 0 && (nx & 63) == 0) cr = I.tiles_x - 1;
+    const unsigned zy = (unsigned)z * (unsigned)I.ny + (unsigned)y, cz = (unsigned)I.nz * (unsigned)I.ny;
+    el = cl >= 0 ? (int)(2u * ((unsigned)cl * cz + zy)) : -1;
+    er = cr >= 0 ? (int)(I.edge_r + 2u * ((unsigned)cr * cz + zy)) : -1;
 }
 
 __device__ __forceinline__ int xcd_remap(int b, int nb) {

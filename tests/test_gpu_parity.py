@@ -375,11 +375,13 @@ def test_two_sweep_schedules_bit_identical(shape, open_, Bx, Bz, driven):
     assert used > 0
 
 
-@pytest.mark.parametrize("shape,open_,Bx,Bz,driven", FUSED_CASES[:2])
+@pytest.mark.parametrize("shape,open_,Bx,Bz,driven",
+                         FUSED_CASES[:2] + [((40, 24, 12), (False, True, True), 0.0, 0.2, True)])  # + multigrid
 def test_tilings_bit_identical(shape, open_, Bx, Bz, driven):
     """The node arithmetic of the assemble, the sweeps and the Poisson right
-    side is contraction-proof, so rows per tile, z chunk and streaming hints
-    change the order of work, never the bits of psi, mu or the statistics."""
+    side is contraction-proof, so rows per tile (the right side's own
+    included), z chunk and streaming hints change the order of work, never
+    the bits of psi, mu or the statistics."""
     nx, ny, nz = shape
     eps = inputs.random_real((nz, ny, nx), 5, 0.4, 1.0)
     c = Case(nx, ny, nz, open_=open_, Bx=Bx, Bz=Bz, eps=eps, tol=1e-10, psi_seed=9, driven=driven,
@@ -389,13 +391,15 @@ def test_tilings_bit_identical(shape, open_, Bx, Bz, driven):
     sr = ref.step(3)
     want_psi, want_mu = ref.get_psi().cpu().numpy(), ref.get_mu().cpu().numpy()
     ref.close()
-    for rows, chunk, nt in ((1, 4, 0), (1, 0, 1), (4, 2, 0), (4, 0, 1), (2, 1, 1)):
+    for rows, chunk, nt, r4 in ((1, 4, 0, 0), (1, 0, 1, 4), (4, 2, 0, 0), (4, 0, 1, 0), (2, 1, 1, 0),
+                                (2, 1, 1, 4), (2, 0, 0, 4)):
         s = c.solver()
-        s.set_tiling(rows=rows, chunk=chunk, streaming=nt)
+        s.set_tiling(rows=rows, chunk=chunk, streaming=nt, rhs_rows=r4)
+        assert s.tiling()["rhs_rows"] == (4 if r4 and rows != 4 else 0)
         st = s.step(3)
-        assert st["sweeps_sum"] == sr["sweeps_sum"], (rows, chunk, nt)
-        assert np.array_equal(s.get_psi().cpu().numpy(), want_psi), (rows, chunk, nt)
-        assert np.array_equal(s.get_mu().cpu().numpy(), want_mu), (rows, chunk, nt)
+        assert st["sweeps_sum"] == sr["sweeps_sum"], (rows, chunk, nt, r4)
+        assert np.array_equal(s.get_psi().cpu().numpy(), want_psi), (rows, chunk, nt, r4)
+        assert np.array_equal(s.get_mu().cpu().numpy(), want_mu), (rows, chunk, nt, r4)
         s.close()
 
 
