@@ -141,7 +141,9 @@ __global__ __launch_bounds__(256) void k_jav_partial(const Inst *__restrict__ in
     const int ii = find_inst(prefix, ninst, b);
     const Inst &I = insts[ii];
     const int lb = b - prefix[ii];
-    const float2 *__restrict__ psi = I.psi[I.st->cur];
+    const gf2 *__restrict__ psi = (const gf2 *)I.psi[I.st->cur];
+    const gf2 *__restrict__ uxg = (const gf2 *)I.ux;
+    const gf2 *__restrict__ wzg = (const gf2 *)I.wz;
     double acc = 0.0;
     const int nx = I.nx, ny = I.ny;
     const bool yz = I.st->yz != 0;
@@ -180,17 +182,17 @@ __global__ __launch_bounds__(256) void k_jav_partial(const Inst *__restrict__ in
         }
         float2 a[JB], nb[JB], u[JB];
 #pragma unroll
-        for (int q = 0; q < JB; ++q) a[q] = psi[mq[q] < N ? mq[q] : 0];
+        for (int q = 0; q < JB; ++q) a[q] = ld2(psi, mq[q] < N ? mq[q] : 0);
 #pragma unroll
         for (int q = 0; q < JB; ++q) {
             const bool own = (lane == 63 || iq[q] == nx - 1) && mq[q] < N;
-            nb[q] = own ? psi[(iq[q] == nx - 1) ? mq[q] - (nx - 1) : mq[q] + 1] : make_float2(0.f, 0.f);
+            nb[q] = own ? ld2(psi, (iq[q] == nx - 1) ? mq[q] - (nx - 1) : mq[q] + 1) : make_float2(0.f, 0.f);
         }
 #pragma unroll
-        for (int q = 0; q < JB; ++q) u[q] = I.ux[jq[q]];
+        for (int q = 0; q < JB; ++q) u[q] = ld2(uxg, jq[q]);
         if (yz) {
 #pragma unroll
-            for (int q = 0; q < JB; ++q) u[q] = xcmul(u[q], I.wz[kq[q]]);
+            for (int q = 0; q < JB; ++q) u[q] = xcmul(u[q], ld2(wzg, kq[q]));
         }
 #pragma unroll
         for (int q = 0; q < JB; ++q) {

@@ -20,6 +20,7 @@
 // a thread's butterfly inputs into registers, synchronises, and writes the
 // outputs to their sorted positions, so a single LDS buffer suffices.
 #include "kernels.h"
+#include "stencil.h"
 
 namespace tdgl {
 
@@ -222,7 +223,7 @@ __global__ __launch_bounds__(FFT_X_THREADS) void k_fft_x(const Inst *__restrict_
 #pragma unroll
         for (int c = 0; c < XB; ++c) {
             const int t = t0 + c * FFT_X_THREADS;
-            v[c] = t < nx ? I.twx[t] : make_float2(0.f, 0.f);
+            v[c] = t < nx ? ld2((const gf2 *)I.twx, t) : make_float2(0.f, 0.f);
         }
 #pragma unroll
         for (int c = 0; c < XB; ++c) {
@@ -230,9 +231,9 @@ __global__ __launch_bounds__(FFT_X_THREADS) void k_fft_x(const Inst *__restrict_
             if (t < nx) stw[t] = v[c];
         }
     }
-    const float *in = in_ext ? in_ext : I.f;
-    float *out = out_ext ? out_ext : I.mu;
-    float2 *spec = I.spec;
+    const gf1 *in = (const gf1 *)(in_ext ? in_ext : I.f);
+    gf1 *out = (gf1 *)(out_ext ? out_ext : I.mu);
+    gf2 *spec = (gf2 *)I.spec;
     const float inv_nx = 1.0f / (float)nx, inv_p = 1.0f / (float)P;
     // a work-group takes I.fxg consecutive groups of `pairs` row pairs; the
     // loads of the next group are issued before the current one is
@@ -287,8 +288,8 @@ __global__ __launch_bounds__(FFT_X_THREADS) void k_fft_x(const Inst *__restrict_
                 const float2 A = make_float2(0.5f * (z.x + zc.x), 0.5f * (z.y - zc.y));
                 const float2 B = make_float2(0.5f * (z.y + zc.y), -0.5f * (z.x - zc.x));
                 const int ra = row0 + 2 * s, rb = ra + 1;
-                if (ra < rows) spec[(size_t)ra * sp + k] = A;
-                if (rb < rows) spec[(size_t)rb * sp + k] = B;
+                if (ra < rows) st2(spec, (unsigned)ra * sp + k, A);
+                if (rb < rows) st2(spec, (unsigned)rb * sp + k, B);
             }
             __syncthreads();
         }
@@ -301,8 +302,8 @@ __global__ __launch_bounds__(FFT_X_THREADS) void k_fft_x(const Inst *__restrict_
                 const int s = fdiv(t, inv_nx), k = t - s * nx;
                 const int ra = row0 + 2 * s, rb = ra + 1;
                 const int kk = k < P ? k : nx - k;
-                A[c] = (t < tot && ra < rows) ? spec[(size_t)ra * sp + kk] : make_float2(0.f, 0.f);
-                B[c] = (t < tot && rb < rows) ? spec[(size_t)rb * sp + kk] : make_float2(0.f, 0.f);
+                A[c] = (t < tot && ra < rows) ? ld2(spec, (unsigned)ra * sp + kk) : make_float2(0.f, 0.f);
+                B[c] = (t < tot && rb < rows) ? ld2(spec, (unsigned)rb * sp + kk) : make_float2(0.f, 0.f);
             }
         };
         auto stage = [&](int t0) {
@@ -361,14 +362,14 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(const Inst *__restrict__ 
     const int lb = xcd_remap(blockIdx.x - prefix[ii], nblk);
     const int z = lb / ntk, kx0 = (lb - z * ntk) * TK;
     const int tk = min(TK, P - kx0);
-    float2 *spec = I.spec + (size_t)z * ny * sp;
+    gf2 *spec = (gf2 *)(I.spec + (size_t)z * ny * sp);
     const float inv_tk = 1.0f / (float)TK;
     // columns sit ss = ny + 1 apart in LDS: the staging loop writes (and the
     // final loop reads) TK columns per y with consecutive lanes, which a
     // power-of-two stride would put on one bank
     const int ss = fft_y_stride(ny);
     float2 *stw = sm + TK * ss;
-    for (int t = threadIdx.x; t < ny; t += FFT_THREADS) stw[t] = I.twy[t];
+    for (int t = threadIdx.x; t < ny; t += FFT_THREADS) stw[t] = ld2((const gf2 *)I.twy, t);
     // loads are issued YB per thread at a time before any of them is
     // stored to LDS
     constexpr int YB = 8;
@@ -379,7 +380,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(const Inst *__restrict__ 
         for (int q = 0; q < YB; ++q) {
             const int t = t0 + q * FFT_THREADS;
             const int y = fdiv(t, inv_tk), c = t - y * TK;
-            v[q] = (t < tot && c < tk) ? spec[(size_t)y * sp + kx0 + c] : make_float2(0.f, 0.f);
+            v[q] = (t < tot && c < tk) ? ld2(spec, (unsigned)(y * sp + kx0 + c)) : make_float2(0.f, 0.f);
         }
 #pragma unroll
         for (int q = 0; q < YB; ++q) {
@@ -392,7 +393,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(const Inst *__restrict__ 
     fft_lds<P2, FFT_THREADS, FFT_MAXPTS>(sm, ny, I.yrad, I.nyrad, TK, ss, stw, (float)dir);
     for (int t = threadIdx.x; t < ny * TK; t += FFT_THREADS) {
         const int y = fdiv(t, inv_tk), c = t - y * TK;
-        if (c < tk) spec[(size_t)y * sp + kx0 + c] = sm[c * ss + y];
+        if (c < tk) st2(spec, (unsigned)(y * sp + kx0 + c), sm[c * ss + y]);
     }
 }
 
@@ -564,8 +565,8 @@ __global__ __launch_bounds__(ZS_THREADS) void k_fft_zsolve(const Inst *__restric
     const int lb = blockIdx.x - prefix[ii];
     const int ky = lb / ntk, kx0 = (lb - ky * ntk) * ZTK;
     const int tk = min(ZTK, P - kx0);
-    const size_t zstride = (size_t)ny * sp;
-    float2 *spec = I.spec + (size_t)ky * sp + kx0;
+    const unsigned zstride = (unsigned)ny * (unsigned)sp;
+    gf2 *spec = (gf2 *)(I.spec + (size_t)ky * sp + kx0);
     // loads are issued ZB per thread at a time before any of them is
     // stored to LDS
     constexpr int ZB = 8;
@@ -576,7 +577,7 @@ __global__ __launch_bounds__(ZS_THREADS) void k_fft_zsolve(const Inst *__restric
         for (int q = 0; q < ZB; ++q) {
             const int t = t0 + q * ZS_THREADS;
             const int k = t / ZTK, c = t - k * ZTK;
-            v[q] = (t < tot && c < tk) ? spec[(size_t)k * zstride + c] : make_float2(0.f, 0.f);
+            v[q] = (t < tot && c < tk) ? ld2(spec, (unsigned)k * zstride + c) : make_float2(0.f, 0.f);
         }
 #pragma unroll
         for (int q = 0; q < ZB; ++q) {
@@ -596,7 +597,7 @@ __global__ __launch_bounds__(ZS_THREADS) void k_fft_zsolve(const Inst *__restric
     // one is solved
     double ipn[RMAX];
     auto load_piv = [&](int c, double *dst) {
-        const double *ipc = I.zip + ((size_t)ky * P + kx0 + c) * nz;
+        const gd1 *ipc = (const gd1 *)(I.zip + ((size_t)ky * P + kx0 + c) * nz);
 #pragma unroll
         for (int q = 0; q < RMAX; ++q) {
             const int k = k0 + q;
@@ -753,7 +754,7 @@ __global__ __launch_bounds__(ZS_THREADS) void k_fft_zsolve(const Inst *__restric
     __syncthreads();
     for (int t = threadIdx.x; t < nz * ZTK; t += ZS_THREADS) {
         const int k = t / ZTK, c = t - k * ZTK;
-        if (c < tk) spec[(size_t)k * zstride + c] = tile[k * ZPAD + c];
+        if (c < tk) st2(spec, (unsigned)k * zstride + c, tile[k * ZPAD + c]);
     }
 }
 

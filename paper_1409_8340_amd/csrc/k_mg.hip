@@ -19,6 +19,7 @@
 // Kernels map one thread to one (x, y) column of a 64 x 4 tile and march
 // through a chunk of z planes, keeping the z neighbours in registers.
 #include "kernels.h"
+#include "stencil.h"
 
 namespace tdgl {
 
@@ -398,7 +399,8 @@ __global__ __launch_bounds__(256) void k_mu_mean_partial(const Inst *__restrict_
     if (q.valid) {
         const double vxy = (double)L.vol[0][q.x] * L.vol[1][q.y];
         const long nxy = (long)L.nx * L.ny, col = (long)q.y * L.nx + q.x;
-        const float *src = which ? L.rhs : L.mu[0];
+        const gf1 *src = (const gf1 *)(which ? L.rhs : L.mu[0]);
+        const gf1 *volz = (const gf1 *)L.vol[2];
         // eight planes' loads in flight before they are summed in plane order
         constexpr int KB = 8;
         int k = q.k0;
@@ -407,12 +409,12 @@ __global__ __launch_bounds__(256) void k_mu_mean_partial(const Inst *__restrict_
 #pragma unroll
             for (int c = 0; c < KB; ++c) {
                 v[c] = src[(k + c) * nxy + col];
-                wv[c] = L.vol[2][k + c];
+                wv[c] = volz[k + c];
             }
 #pragma unroll
             for (int c = 0; c < KB; ++c) acc += vxy * wv[c] * (double)v[c];
         }
-        for (; k < q.k1; ++k) acc += vxy * L.vol[2][k] * (double)src[k * nxy + col];
+        for (; k < q.k1; ++k) acc += vxy * volz[k] * (double)src[k * nxy + col];
     }
     const double s = wg_sum<256>(acc, red);
     if (threadIdx.x == 0) I.part[lb] = s;

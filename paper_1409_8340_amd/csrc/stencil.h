@@ -7,11 +7,15 @@
 namespace tdgl {
 
 // Global-address-space views: pointers read out of the descriptor are
-// generic, which would make every access a FLAT instruction.  Complex values
-// move as native two-float vectors.
+// generic, which would make every access a FLAT instruction.  A FLAT load
+// also counts against the LDS wait counter, so a kernel that mixes LDS or
+// cross-lane operations with FLAT loads in flight waits for the loads at
+// every LDS wait; through these views the loads are global instructions.
+// Complex values move as native two-float vectors.
 typedef float v2f __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(1))) v2f gf2;
 typedef __attribute__((address_space(1))) float gf1;
+typedef __attribute__((address_space(1))) double gd1;
 __device__ __forceinline__ float2 ld2(const gf2 *p, unsigned i) {
     const v2f v = p[i];
     return make_float2(v.x, v.y);
