@@ -136,7 +136,9 @@ __global__ __launch_bounds__(FIN_THREADS) void k_solve_finalize(const Inst *__re
 // sum when x is periodic).  Flat mapping: CPT consecutive cells per thread.
 __global__ __launch_bounds__(256) void k_jav_partial(const Inst *__restrict__ insts,
                                                      const int *__restrict__ prefix, int ninst) {
+    constexpr int JB = 8;
     __shared__ double red[4];
+    __shared__ float2 first[JB][4];  // lane 0 of every wavefront, per cell of a batch
     const int b = blockIdx.x;
     const int ii = find_inst(prefix, ninst, b);
     const Inst &I = insts[ii];
@@ -147,17 +149,19 @@ __global__ __launch_bounds__(256) void k_jav_partial(const Inst *__restrict__ in
     double acc = 0.0;
     const int nx = I.nx, ny = I.ny;
     const bool yz = I.st->yz != 0;
-    // cells m = base + c 256 + tid, c = 0 .. fcpt-1, summed in that
-    // order; their x, y and z indices follow from one division for c = 0
-    // and then by stepping 256 cells at a time.  A wavefront's 64 lanes hold
-    // 64 consecutive cells, so psi_{m+x} is the next lane's psi_m (a
-    // shuffle); the last lane and the end of an x row load it.  Every load
-    // of JB cells -- psi, those neighbours, the x links of their rows -- is
-    // issued before any of them is used, so a batch waits for memory once
-    // (a cell past the end loads cell 0 and adds nothing).
-    constexpr int JB = 8;
+    // cells m = base + c 256 + tid, c = 0 .. fcpt-1, summed in that order;
+    // their x, y and z indices follow from one division for c = 0 and then
+    // by stepping 256 cells at a time.  The 256 threads hold 256
+    // consecutive cells, so psi_{m+x} is the next lane's psi_m (a shuffle),
+    // the next wavefront's first cell for lane 63 (through LDS), and is
+    // loaded only at the end of an x row (the periodic wrap) and for the
+    // block's last cell of a batch.  With nx a multiple of 64 a wavefront's
+    // cells lie in one row, whose x link it reads once.  Every load of a
+    // batch of JB cells is issued before any is used (a cell past the end
+    // loads cell 0 and adds nothing).
     static_assert(JAV_CPT % JB == 0 && JAV_CPT_MAX % JB == 0, "whole batches");
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const bool rows64 = (nx & 63) == 0;
     const int cpt = I.fcpt;
     int m = (int)((long)lb * 256 * cpt) + (int)threadIdx.x;
     int i = m % nx, j = (m / nx) % ny, k = m / (nx * ny);
@@ -183,28 +187,44 @@ __global__ __launch_bounds__(256) void k_jav_partial(const Inst *__restrict__ in
         float2 a[JB], nb[JB], u[JB];
 #pragma unroll
         for (int q = 0; q < JB; ++q) a[q] = ld2(psi, mq[q] < N ? mq[q] : 0);
+        // loaded neighbours: the x wrap, and the cell after the block's last
+        // one in the batch's last step
 #pragma unroll
         for (int q = 0; q < JB; ++q) {
-            const bool own = (lane == 63 || iq[q] == nx - 1) && mq[q] < N;
-            nb[q] = own ? ld2(psi, (iq[q] == nx - 1) ? mq[q] - (nx - 1) : mq[q] + 1) : make_float2(0.f, 0.f);
+            const bool wrap = iq[q] == nx - 1;
+            const bool own = (wrap || (threadIdx.x == 255 && q == JB - 1)) && mq[q] < N;
+            nb[q] = own ? ld2(psi, wrap ? mq[q] - (nx - 1) : mq[q] + 1) : make_float2(0.f, 0.f);
         }
 #pragma unroll
-        for (int q = 0; q < JB; ++q) u[q] = ld2(uxg, jq[q]);
+        for (int q = 0; q < JB; ++q) u[q] = ld2(uxg, rows64 ? __builtin_amdgcn_readfirstlane(jq[q]) : jq[q]);
         if (yz) {
 #pragma unroll
             for (int q = 0; q < JB; ++q) u[q] = xcmul(u[q], ld2(wzg, kq[q]));
         }
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < JB; ++q) first[q][w] = a[q];
+        }
+        __syncthreads();
 #pragma unroll
         for (int q = 0; q < JB; ++q) {
             float2 p;
             p.x = __shfl_down(a[q].x, 1, 64);
             p.y = __shfl_down(a[q].y, 1, 64);
+            if (lane == 63) {
+                // the next wavefront's first cell; after wavefront 3, the
+                // first cell of the next step (loaded for the last step)
+                if (w < 3) p = first[q][w + 1];
+                else if (q < JB - 1) p = first[q + 1][0];
+                else p = nb[q];
+            }
+            if (iq[q] == nx - 1) p = nb[q];
             if (mq[q] < N) {
-                if (lane == 63 || iq[q] == nx - 1) p = nb[q];
                 const float2 up = cmul(u[q], p);
                 acc += (double)(a[q].x * up.y - a[q].y * up.x);
             }
         }
+        __syncthreads();
     }
     const double s = wg_sum<256>(acc, red);
     if (threadIdx.x == 0) I.part[lb] = s;
