@@ -1429,7 +1429,7 @@ tdgl_status tdgl_create(int n, const tdgl_params *params, void *ws, size_t ws_by
     hipLaunchKernelGGL(k_fill_u, dim3(64), dim3(256), 0, st, c->d_res, (long)(c->max_iter * c->row_words()), 0u);
     hipLaunchKernelGGL(k_fill_u, dim3(64), dim3(256), 0, st, c->d_mures, (long)(c->max_cycles * c->row_words()),
                        0u);
-    hipLaunchKernelGGL(k_links, dim3(n), dim3(256), 0, st, c->d_inst, 0);
+    hipLaunchKernelGGL(k_links, dim3(n), dim3(256), 0, st, c->d_inst, 0, (const double *)nullptr);
     for (int i = 0; i < n; ++i) {
         const tdgl_params &p = c->inst[i].p;
         if (!c->inst[i].d.fft) continue;
@@ -1515,7 +1515,7 @@ tdgl_status tdgl_set_field_yz(tdgl_ctx *ctx, int inst, double By, double Bz, int
     hipLaunchKernelGGL(k_state_set, dim3(1), dim3(1), 0, ctx->stream, ctx->d_inst, inst, 9, qz);
     hipLaunchKernelGGL(k_state_set, dim3(1), dim3(1), 0, ctx->stream, ctx->d_inst, inst, 13, qy);
     hipLaunchKernelGGL(k_state_set, dim3(1), dim3(1), 0, ctx->stream, ctx->d_inst, inst, 14, 1.0);
-    hipLaunchKernelGGL(k_links, dim3(1), dim3(256), 0, ctx->stream, ctx->d_inst + inst, 0);
+    hipLaunchKernelGGL(k_links, dim3(1), dim3(256), 0, ctx->stream, ctx->d_inst + inst, 0, (const double *)nullptr);
     LAUNCHCHK();
     if (By_eff) *By_eff = qy;
     if (Bz_eff) *Bz_eff = qz;
@@ -1549,7 +1549,7 @@ tdgl_status tdgl_set_field(tdgl_ctx *ctx, int inst, double Bx, double Bz, int qu
     hipLaunchKernelGGL(k_state_set, dim3(1), dim3(1), 0, ctx->stream, ctx->d_inst, inst, 14, 0.0);
     // rebuild the tables of this instance only: launch over all with a
     // single-instance view (the kernel reads the descriptor by block index)
-    hipLaunchKernelGGL(k_links, dim3(1), dim3(256), 0, ctx->stream, ctx->d_inst + inst, 0);
+    hipLaunchKernelGGL(k_links, dim3(1), dim3(256), 0, ctx->stream, ctx->d_inst + inst, 0, (const double *)nullptr);
     LAUNCHCHK();
     if (Bx_eff) *Bx_eff = qx;
     if (Bz_eff) *Bz_eff = qz;
@@ -1756,7 +1756,7 @@ tdgl_status tdgl_set_scalars(tdgl_ctx *ctx, int inst, const tdgl_scalars *sc) {
     const double v[7] = {sc->K, sc->t, sc->V_sum, (double)sc->n, (double)sc->n_avg, sc->E_last, sc->J_av_last};
     for (int f = 0; f < 7; ++f)
         hipLaunchKernelGGL(k_state_set, dim3(1), dim3(1), 0, ctx->stream, ctx->d_inst, inst, f, v[f]);
-    hipLaunchKernelGGL(k_links, dim3(1), dim3(256), 0, ctx->stream, ctx->d_inst + inst, 1);
+    hipLaunchKernelGGL(k_links, dim3(1), dim3(256), 0, ctx->stream, ctx->d_inst + inst, 1, (const double *)nullptr);
     LAUNCHCHK();
     return TDGL_OK;
 }
@@ -2350,8 +2350,7 @@ tdgl_status adjoint_step(tdgl_ctx *c, const AdjLayout &L, int iprev, int inext, 
     tdgl_status e = enqueue_poisson(c, nullptr);
     if (e) return e;
     // adjoint of the Poisson right side, links at K_n
-    hipLaunchKernelGGL(k_adj_setK, dim3(1), dim3(64), 0, s, c->d_inst, Kn);
-    hipLaunchKernelGGL(k_links, dim3(1), dim3(256), 0, s, c->d_inst, 1);
+    hipLaunchKernelGGL(k_links, dim3(1), dim3(256), 0, s, c->d_inst, 1, Kn);
     hipLaunchKernelGGL(k_adj_g, dim3(G), dim3(256), 0, s, c->d_inst, psin, L.t1);
     launch_stencil<MODE_NS>(c, 0, psin, L.t2);
     launch_stencil<MODE_NS>(c, 0, L.t1, L.t3);
@@ -2359,8 +2358,7 @@ tdgl_status adjoint_step(tdgl_ctx *c, const AdjLayout &L, int iprev, int inext, 
     hipLaunchKernelGGL(k_adj_edge_f, dim3(G), dim3(256), 0, s, c->d_inst, psin);
     hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(256), 0, s, c->d_inst, G, 0, ew, L.adj);
     // J_av(psi_n, K_{n-1}) and the K update
-    hipLaunchKernelGGL(k_adj_setK, dim3(1), dim3(64), 0, s, c->d_inst, Km);
-    hipLaunchKernelGGL(k_links, dim3(1), dim3(256), 0, s, c->d_inst, 1);
+    hipLaunchKernelGGL(k_links, dim3(1), dim3(256), 0, s, c->d_inst, 1, Km);
     hipLaunchKernelGGL(k_adj_jterm, dim3(G), dim3(256), 0, s, c->d_inst, L.psibar, psin, L.adj);
     hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(256), 0, s, c->d_inst, G, 1, 0.0, L.adj);
     // the Crank-Nicolson system transposed
@@ -2442,7 +2440,7 @@ tdgl_status voltage_grad_run(tdgl_ctx *ctx, int nsteps, int window_begin, int C,
         if (q != ncp - 1) {
             hipLaunchKernelGGL(k_adj_load, dim3(G), dim3(256), 0, s, ctx->d_inst, L.ck_psi + (size_t)q * N,
                                L.ck_mu + (size_t)q * N, L.ck_K + 3 * q);
-            hipLaunchKernelGGL(k_links, dim3(1), dim3(256), 0, s, ctx->d_inst, 1);
+            hipLaunchKernelGGL(k_links, dim3(1), dim3(256), 0, s, ctx->d_inst, 1, (const double *)nullptr);
             hipLaunchKernelGGL(k_adj_save, dim3(G), dim3(256), 0, s, ctx->d_inst, L.seg_psi, L.seg_mu, L.seg_K,
                                0);
             LAUNCHCHK();
@@ -2462,7 +2460,7 @@ tdgl_status voltage_grad_run(tdgl_ctx *ctx, int nsteps, int window_begin, int C,
     // back to the state after the forward run
     HIPCHK(hipMemcpyAsync(h.d.st, L.fin_st, sizeof(DevState), hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL(k_adj_load, dim3(G), dim3(256), 0, s, ctx->d_inst, L.fin_psi, L.fin_mu, L.fin_K);
-    hipLaunchKernelGGL(k_links, dim3(1), dim3(256), 0, s, ctx->d_inst, 1);
+    hipLaunchKernelGGL(k_links, dim3(1), dim3(256), 0, s, ctx->d_inst, 1, (const double *)nullptr);
     hipLaunchKernelGGL(k_adj_vbar, dim3(1), dim3(64), 0, s, L.Elog, window_begin, nsteps, L.vbar);
     LAUNCHCHK();
     HIPCHK(hipMemcpyAsync(vbar, L.vbar, sizeof(double), hipMemcpyDeviceToHost, s));

@@ -79,10 +79,6 @@ __global__ void k_adj_load(const Inst *__restrict__ insts, const float2 *spsi, c
     }
 }
 
-__global__ void k_adj_setK(const Inst *__restrict__ insts, const double *Kp) {
-    if (threadIdx.x == 0) insts[0].st->K = *Kp;
-}
-
 __global__ void k_adj_logE(const Inst *__restrict__ insts, double *Elog, int n) {
     if (threadIdx.x == 0) Elog[n] = insts[0].st->E_last;
 }

@@ -37,12 +37,16 @@ __device__ __forceinline__ double link_yref(const Inst &I, const DevState *st) {
 // (same flux through every plaquette and the same phase around every
 // periodic loop; z must be open when By != 0).
 // One work-group per instance (grid = ninst); `which` = 1 refreshes ux only.
-__global__ void k_links(const Inst *__restrict__ insts, int which) {
+// Kp (the adjoint's replay): K = *Kp is stored in the state first and the
+// links are those at it.
+__global__ void k_links(const Inst *__restrict__ insts, int which, const double *Kp) {
     const Inst &I = insts[blockIdx.x];
-    const DevState *st = I.st;
+    DevState *st = I.st;
     const double Ly = I.per[1] ? I.ny * I.hy : (I.ny - 1) * I.hy;
     const double Lx = I.per[0] ? I.nx * I.hx : (I.nx - 1) * I.hx;
-    const double K = I.driven ? st->K : 0.0, Bx = st->Bx, Bz = st->Bz, By = st->By;
+    const double Kn = Kp ? *Kp : st->K;
+    if (Kp && threadIdx.x == 0) st->K = Kn;
+    const double K = I.driven ? Kn : 0.0, Bx = st->Bx, Bz = st->Bz, By = st->By;
     const bool yz = st->yz != 0;
     const double yref = link_yref(I, st);
     for (int j = threadIdx.x; j < I.ny; j += blockDim.x) {

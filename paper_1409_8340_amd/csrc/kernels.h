@@ -27,7 +27,7 @@ template <int MODE, int R, bool NT, bool YZ>
 __global__ void k_stencil(const Inst *insts, const int *prefix, int ninst, int l, const float2 *ext_in,
                           float2 *ext_out, unsigned long long *pub, unsigned seq);
 
-__global__ void k_links(const Inst *insts, int which);
+__global__ void k_links(const Inst *insts, int which, const double *Kp);
 __global__ void k_solve_finalize(const Inst *insts, int ninst, int count_step, int nl, int fused,
                                  unsigned long long *pub, unsigned seq);
 __global__ void k_acc_reset(const Inst *insts, int ninst);
@@ -77,7 +77,6 @@ constexpr int FFT_X_PTS = 1024;       // complex points per work-group of the x 
 
 __global__ void k_adj_save(const Inst *insts, float2 *dpsi, float *dmu, double *dK, int raw);
 __global__ void k_adj_load(const Inst *insts, const float2 *spsi, const float *smu, const double *sK);
-__global__ void k_adj_setK(const Inst *insts, const double *Kp);
 __global__ void k_adj_logE(const Inst *insts, double *Elog, int n);
 __global__ void k_adj_vbar(const double *Elog, int wb, int nsteps, double *vbar);
 __global__ void k_adj_zero(AdjState *adj);
