@@ -427,6 +427,9 @@ struct tdgl_ctx {
     // each solve picks the pass schedule with the fewer expected passes
     std::vector<int> sweep_hist[2];
     int hist_pos[2] = {0, 0};
+    // sweep count of instance 0's last host-driven solve (-1: the host did
+    // not see it: a persistent solve, or one decided on the device)
+    int last_sweeps = -1;
     bool persist = false;  // the Jacobi solve as one cooperative launch
     int num_cu = 0;        // compute units of the device
     // captured step of tdgl_step_graph (rebuilt when the budget or the
@@ -1050,6 +1053,7 @@ tdgl_status jacobi_loop(tdgl_ctx *ctx, tdgl_step_stats *acc, bool *strict_fail, 
         hipLaunchKernelGGL(k_solve_finalize, dim3(n), dim3(FIN_THREADS), 0, s, ctx->d_inst, n, count_step,
                            ctx->max_iter, 0, nullptr, 0u);
         LAUNCHCHK();
+        ctx->last_sweeps = -1;
         return TDGL_OK;
     }
     ++ctx->pub_seq;
@@ -1125,6 +1129,7 @@ tdgl_status jacobi_loop(tdgl_ctx *ctx, tdgl_step_stats *acc, bool *strict_fail, 
     }
     LAUNCHCHK();
     if (acc && sched == 2) acc->single_first_steps++;
+    ctx->last_sweeps = deferred[0] ? -1 : conv_at[0] + 1;
     if (ctx->fused) {
         // sweep counts the host has seen (capped or deferred solves left out)
         std::vector<int> &h = ctx->sweep_hist[kind];
@@ -2413,6 +2418,9 @@ tdgl_status voltage_grad_run(tdgl_ctx *ctx, int nsteps, int window_begin, int C,
     // ckpt_every >= nsteps nothing is)
     const int ncp = (nsteps + C - 1) / C;
     const int s0_last = (ncp - 1) * C;
+    // each forward solve's sweep count, for the replays (-1: not seen by
+    // the host)
+    std::vector<int> fw_sweeps(nsteps, -1);
     for (int n = 0; n < nsteps; ++n) {
         if (n % C == 0) {
             const int q = n / C;
@@ -2423,6 +2431,7 @@ tdgl_status voltage_grad_run(tdgl_ctx *ctx, int nsteps, int window_begin, int C,
             hipLaunchKernelGGL(k_adj_save, dim3(G), dim3(256), 0, s, ctx->d_inst, L.seg_psi, L.seg_mu, L.seg_K, 0);
         tdgl_status e = tdgl_step(ctx, 1, nullptr);
         if (e) return e;
+        fw_sweeps[n] = ctx->last_sweeps;
         hipLaunchKernelGGL(k_adj_logE, dim3(1), dim3(64), 0, s, ctx->d_inst, L.Elog, n);
         if (n >= s0_last) {
             const int j = n + 1 - s0_last;
@@ -2445,7 +2454,13 @@ tdgl_status voltage_grad_run(tdgl_ctx *ctx, int nsteps, int window_begin, int C,
                                0);
             LAUNCHCHK();
             for (int j = 1; j <= s1 - s0; ++j) {
-                tdgl_status e = tdgl_step(ctx, 1, nullptr);
+                // a replayed step whose forward solve took sw sweeps runs
+                // the fixed launch sequence of sw sweeps (the same iterates,
+                // with no host round trip); spectral Poisson only, where the
+                // rest of the step is a fixed sequence too
+                const int sw = fw_sweeps[s0 + j - 1];
+                tdgl_status e = (sw > 0 && !ctx->any_mg && !ctx->persist) ? enqueue_step_fixed(ctx, sw)
+                                                                           : tdgl_step(ctx, 1, nullptr);
                 if (e) return e;
                 hipLaunchKernelGGL(k_adj_save, dim3(G), dim3(256), 0, s, ctx->d_inst, L.seg_psi + (size_t)j * N,
                                    L.seg_mu + (size_t)j * N, L.seg_K + j, 0);
