@@ -26,13 +26,6 @@ namespace tdgl {
 
 namespace {
 
-// exp(i pi x) for x in [-2, 2]
-__device__ __forceinline__ float2 expi_pi(float x) {
-    float s, c;
-    sincospif(x, &s, &c);
-    return make_float2(c, s);
-}
-
 // In-register DFT of size R (sign -1 forward, +1 inverse).
 template <int R>
 __device__ __forceinline__ void dft(float2 *v, float sign);
