@@ -524,7 +524,7 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
         d.P = cv.take<float2>((size_t)p.nx * p.nz);
         d.wz = cv.take<float2>(p.nz);
         d.btile = cv.take<int>((size_t)cdiv(p.nx, TX) * cdiv(p.ny, 4));  // room for any rows per thread
-        if (seam2_ok(p.bc[1] == TDGL_PERIODIC, p.ny)) d.sring = cv.take<float2>((size_t)2 * p.nz * p.nx);
+        if (p.bc[1] == TDGL_PERIODIC && p.ny % TYS_MIN == 0) d.sring = cv.take<float2>((size_t)2 * p.nz * p.nx);
         d.st = cv.take<DevState>(1);
         d.res = res ? res + i : nullptr;
         d.mures = mures ? mures + i : nullptr;
@@ -1955,7 +1955,7 @@ tdgl_status upload_tiling(tdgl_ctx *ctx) {
         // the plain-load two-sweep kernel does not take
         std::vector<int> bt;
         const int M = sweep2i_mult(d.rows);
-        d.seam2 = seam2_ok(d.per[1] != 0, d.ny) ? 1 : 0;
+        d.seam2 = seam2_ok(d.per[1] != 0, d.ny, d.rows) ? 1 : 0;
         const bool seam = d.seam2 != 0;
         const int nsy = sweep2i_rows(d.ny, d.rows, seam);
         for (int ty = 0; ty < d.tiles_y; ++ty)
@@ -1965,7 +1965,7 @@ tdgl_status upload_tiling(tdgl_ctx *ctx) {
                 const int tr = seam ? ty : ty - 1;
                 const int j = tr / M;
                 const bool inner = tr >= 0 && j < nsy &&
-                                   tile_interior2(tx * TX, sweep2i_y0(j, d.rows, seam), TYS, d.nx, d.ny,
+                                   tile_interior2(tx * TX, sweep2i_y0(j, d.rows, seam), tys_of(d.rows), d.nx, d.ny,
                                                   d.per[0] != 0, seam);
                 if (!inner) bt.push_back(tx + d.tiles_x * ty);
             }

@@ -446,8 +446,8 @@ __global__ __launch_bounds__(256) void k_seam_ring(const Inst *__restrict__ inst
                                  r == 0 ? ny - 1 : 0, p, (unsigned)nx * (unsigned)ny, I.per[2] != 0);
 }
 
-// The two-sweep pass on interior super-tiles (tile_interior2 with height
-// TYS): the tile, its two-node halo of psi^(l) and its ring of psi^(l+1)
+// The two-sweep pass on interior super-tiles (tile_interior2 with the
+// height tys_of(R)): the tile, its two-node halo of psi^(l) and its ring of psi^(l+1)
 // are real nodes with real neighbours (or their plain images across a
 // periodic x wrap), so every load is a plain load at a fixed in-plane
 // offset, issued unconditionally (a plane outside the grid reads a real
@@ -459,12 +459,12 @@ __global__ __launch_bounds__(256) void k_seam_ring(const Inst *__restrict__ inst
 // non-temporally; b/M and (ht/2)/M stay cacheable, since the neighbours'
 // rings read them again.
 template <int R, bool NT, bool YZ>
-__global__ __launch_bounds__(WG * TYS / (4 * R), R == 4 ? 2 : 4) void k_sweep2i(const Inst *__restrict__ insts,
+__global__ __launch_bounds__(WG * sweep2i_mult(R), 4) void k_sweep2i(const Inst *__restrict__ insts,
                                                                const int *__restrict__ prefix, int ninst, int l,
                                                                unsigned long long *pub, unsigned seq) {
     constexpr int M = sweep2i_mult(R);
     constexpr int WGI = WG * M;
-    constexpr int TYv = TYS;
+    constexpr int TYv = tys_of(R);
     constexpr int LX = TX + 4, LY = TYv + 4;
     constexpr int NH2 = LX * LY - TX * TYv;
     constexpr int NQ = (NH2 + WGI - 1) / WGI;  // two-node halo slots per thread

@@ -146,7 +146,7 @@ struct Inst {
     // edge_ob, edge_od: edge relative to bh and to dh, in complex values
     float2 *edge;
     unsigned edge_r, edge_ob, edge_od;
-                         // (periodic y, ny a multiple of TYS); else they start one tile row in
+                         // (periodic y, ny a multiple of the super-tile height); else they start one tile row in
     int nlev;
     MGLevel lev[kMaxLevels];
     // direct spectral Poisson solve (periodic x and y, open z)
@@ -181,24 +181,30 @@ __device__ __forceinline__ float2 cdiv(float2 a, float2 b) {
 // Work-groups are dispatched round-robin over the 8 XCDs (blockIdx % 8).
 // Remap so that each XCD receives a contiguous range of logical tiles: tiles
 // that share halos then share that XCD's L2.
-// The plain-load two-sweep kernel works on 64 x 16 super-tiles: M = 4 / R
-// wavefront groups of the 64 x 4R tile, so WG * M threads (R = 1: 1024,
-// R = 2: 512, R = 4: 256); the taller tile halves the share of halo and
-// ring nodes against 64 x 8.
-constexpr int TYS = 16;
-__host__ __device__ constexpr int sweep2i_mult(int rows) { return TYS / (4 * rows); }
+// The plain-load two-sweep kernel works on 64 x TYS super-tiles: M =
+// TYS / 4R wavefront groups of the 64 x 4R tile, so WG * M threads.  TYS is
+// 32 rows (R = 2: 1024 threads, R = 4: 512), or 16 with one row per thread
+// (1024 threads): the taller the tile, the smaller the share of its
+// two-node y halo and of its ring rows, which are read again by the
+// neighbouring super-tiles.
+__host__ __device__ constexpr int tys_of(int rows) { return rows == 1 ? 16 : 32; }
+constexpr int TYS_MIN = 16;  // the smallest super-tile height (every other one is a multiple of it)
+__host__ __device__ constexpr int sweep2i_mult(int rows) { return tys_of(rows) / (4 * rows); }
 // Super-tile rows start one 64 x 4R tile row into the grid (y0 = 4R + TYS j,
 // j < sweep2i_rows), so that a quasi-periodic y seam leaves only the first
 // and the last tile row to the general kernel -- unless the instance is
 // periodic in y with ny a multiple of TYS (seam2): then they start at
 // y0 = TYS j and the super-tiles on the seam apply its phase themselves.
 __host__ __device__ inline int sweep2i_rows(int ny, int rows, bool seam) {
-    if (seam) return ny / TYS;
+    const int tys = tys_of(rows);
+    if (seam) return ny / tys;
     const int r = ny - 4 * rows;
-    return r > 0 ? (r + TYS - 1) / TYS : 0;
+    return r > 0 ? (r + tys - 1) / tys : 0;
 }
-__host__ __device__ inline int sweep2i_y0(int j, int rows, bool seam) { return (seam ? 0 : 4 * rows) + TYS * j; }
-__host__ __device__ inline bool seam2_ok(bool yper, int ny) { return yper && ny % TYS == 0; }
+__host__ __device__ inline int sweep2i_y0(int j, int rows, bool seam) {
+    return (seam ? 0 : 4 * rows) + tys_of(rows) * j;
+}
+__host__ __device__ inline bool seam2_ok(bool yper, int ny, int rows) { return yper && ny % tys_of(rows) == 0; }
 
 // A tile every node of which, with its two-node halo, is a real node or a
 // plain periodic image in x: full in x, and its halo inside the grid in y

@@ -281,11 +281,13 @@ FUSED_CASES = [
     # grids with interior tiles (the plain-load kernel) beside boundary ones
     ((200, 40, 12), (False, False, True), 0.0, 0.15, True),   # quasi-periodic y, ragged x, open z
     ((160, 42, 7), (True, True, False), 0.1, 0.05, False),    # open x and y faces, periodic z
-    # super-tiles over the quasi-periodic y seam (periodic y, ny a multiple of 16)
+    # super-tiles over the quasi-periodic y seam (periodic y, ny a multiple of
+    # the super-tile height: 16 rows with one row per thread, 32 with two)
     ((128, 48, 10), (False, False, True), 0.0, 0.15, True),   # every tile interior: no boundary kernel
     ((192, 32, 6), (False, False, False), 0.2, 0.1, False),   # periodic z, tilted field: P varies with z
     ((130, 64, 5), (False, False, True), 0.0, 0.2, True),     # ragged x beside seam super-tiles
     ((70, 16, 9), (True, False, True), 0.0, 0.1, False),      # one super-tile row touching both seams
+    ((128, 96, 6), (False, False, True), 0.0, 0.15, True),    # three (six) super-tile rows over the seam
 ]
 
 
