@@ -586,6 +586,11 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
                 L.tiles_x = cdiv(L.nx, MTX);
                 L.tiles_y = cdiv(L.ny, MTY);
                 L.chunk = auto_chunk(mtxy, L.nz, 0);
+                // a spectral instance uses its level-0 tiles only for the
+                // mean of mu: z runs of at least one batch of loads (eight
+                // planes), so that a batch of small instances does not
+                // become a swarm of work-groups that each sum two planes
+                if (l == 0 && fft_eligible(p)) L.chunk = std::min(L.nz, std::max(L.chunk, 8));
                 L.tiles_z = cdiv(L.nz, L.chunk);
                 h.mg_blocks[l] = (int)(mtxy * L.tiles_z);
             }
@@ -608,7 +613,7 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
                     d.fxg = (int)std::max(1L, std::min(8L, groups / 2048));
                     h.fx_blocks = (int)cdiv(groups, (long)d.fxg);
                 }
-                h.fy_blocks = p.nz * cdiv(P, fft_y_cols(p.ny));
+                h.fy_blocks = fft_y_plan(p.nx, p.ny, p.nz).blocks;
                 h.fz_blocks = p.nz <= FFT_ZSERIAL ? cdiv(p.ny * P, 256) : p.ny * cdiv(P, FFT_ZTK);
             }
             part_cap = std::max(part_cap, h.mg_blocks[0]);
@@ -710,7 +715,8 @@ tdgl_status upload_tables(tdgl_ctx *ctx) {
         if (h.d.fft) {
             ctx->any_fft = true;
             ctx->fx_lds = std::max(ctx->fx_lds, (size_t)(fft_x_pairs(h.p.nx) + 1) * h.p.nx * 8);
-            ctx->fy_lds = std::max(ctx->fy_lds, ((size_t)fft_y_cols(h.p.ny) * fft_y_stride(h.p.ny) + h.p.ny) * 8);
+            ctx->fy_lds = std::max(ctx->fy_lds, ((size_t)fft_y_plan(h.p.nx, h.p.ny, h.p.nz).TK *
+                                                      fft_y_stride(h.p.ny) + h.p.ny) * 8);
             ctx->fx_p2 = ctx->fx_p2 && (h.p.nx & (h.p.nx - 1)) == 0;
             ctx->fx_long = ctx->fx_long || h.p.nx > FFT_X_PTS;
             ctx->fy_p2 = ctx->fy_p2 && (h.p.ny & (h.p.ny - 1)) == 0;
@@ -1200,7 +1206,9 @@ tdgl_status enqueue_fft(tdgl_ctx *ctx) {
     };
     xpass(-1);
     ypass(-1);
-    if (ctx->fz_nzmax <= 128)
+    // up to 64 planes two rows per lane, else four (32-lane segments up to
+    // 128 planes, 64-lane ones beyond)
+    if (ctx->fz_nzmax <= 64)
         hipLaunchKernelGGL(k_fft_zsolve<2>, dim3(std::max(ctx->tot_fz, 1)), dim3(256), ctx->fz_lds, s, ctx->d_inst,
                            ctx->d_pref_fz, n);
     else

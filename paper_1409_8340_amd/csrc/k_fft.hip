@@ -176,10 +176,28 @@ __host__ __device__ int fft_x_pairs(int nx) {
     int p = FFT_X_PTS / nx;
     return p < 1 ? 1 : (p > 32 ? 32 : p);
 }
-// kx columns per work-group of the y passes: TK * ny <= FFT_MAXPTS.
-__host__ __device__ int fft_y_cols(int ny) {
+// Tiles of the y passes over an instance's columns (z, kx), P = nx/2 + 1
+// per plane: a work-group holds at most FFT_MAXPTS points (and 1024
+// columns).  Where a whole plane's P columns fit, a tile is G whole planes
+// (as many as fit); otherwise each plane is cut into ntk tiles of about
+// equal width.  Tiles start on a plane or at kx = j TK within one, so their
+// rows start on the same 128-byte lines for every plane.
+__host__ __device__ FftYPlan fft_y_plan(int nx, int ny, int nz) {
+    const int P = nx / 2 + 1;
     int t = FFT_MAXPTS / ny;
-    return t < 1 ? 1 : (t > 16 ? 16 : t);
+    t = t < 1 ? 1 : (t > 1024 ? 1024 : t);
+    FftYPlan q;
+    if (t >= P) {
+        q.G = t / P < nz ? t / P : nz;
+        q.ntk = 1;
+        q.TK = q.G * P;
+    } else {
+        q.G = 1;
+        q.ntk = (P + t - 1) / t;
+        q.TK = (P + q.ntk - 1) / q.ntk;
+    }
+    q.blocks = ((nz + q.G - 1) / q.G) * q.ntk;
+    return q;
 }
 // LDS stride of the y passes' columns (complex elements).
 __host__ __device__ int fft_y_stride(int ny) { return ny + 1; }
@@ -339,8 +357,9 @@ __global__ __launch_bounds__(FFT_X_THREADS) void k_fft_x(const Inst *__restrict_
 }
 
 // FFT along y of the half spectrum, forward (dir = -1) or inverse (+1):
-// a work-group takes TK consecutive kx at one z, all y.  Consecutive tiles
-// share 128-byte lines, so neighbouring logical tiles run on one XCD.
+// a work-group takes one tile of fft_y_plan -- TK consecutive kx of one
+// plane on tall grids, G whole planes on short ones -- all y.  Consecutive
+// tiles share 128-byte lines, so neighbouring logical tiles run on one XCD.
 template <bool P2>
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(const Inst *__restrict__ insts,
                                                        const int *__restrict__ prefix, int ninst,
@@ -348,15 +367,24 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(const Inst *__restrict__ 
     extern __shared__ float2 sm[];
     const int ii = find_inst(prefix, ninst, blockIdx.x);
     const Inst &I = insts[ii];
-    const int nx = I.nx, ny = I.ny, P = nx / 2 + 1, sp = I.sp;
-    const int TK = fft_y_cols(ny);
-    const int ntk = (P + TK - 1) / TK;
+    const int nx = I.nx, ny = I.ny, nz = I.nz, P = nx / 2 + 1, sp = I.sp;
+    const FftYPlan pl = fft_y_plan(nx, ny, nz);
+    const int TK = pl.TK;
     const int nblk = prefix[ii + 1] - prefix[ii];
     const int lb = xcd_remap(blockIdx.x - prefix[ii], nblk);
-    const int z = lb / ntk, kx0 = (lb - z * ntk) * TK;
-    const int tk = min(TK, P - kx0);
-    gf2 *spec = (gf2 *)(I.spec + (size_t)z * ny * sp);
-    const float inv_tk = 1.0f / (float)TK;
+    const int zt = lb / pl.ntk, j = lb - zt * pl.ntk;
+    // the tile's first column is kx = r0 of plane z0; column c of the tile
+    // is kx = u - q P of plane z0 + q, u = r0 + c, q = floor(u / P)
+    const int z0 = zt * pl.G, r0 = j * TK;
+    const int tk = pl.ntk == 1 ? min(pl.G, nz - z0) * P : min(TK, P - r0);
+    const size_t zs = (size_t)ny * (size_t)sp;
+    const gf2 *__restrict__ specr = (const gf2 *)(I.spec + (size_t)z0 * zs);
+    gf2 *__restrict__ specw = (gf2 *)(I.spec + (size_t)z0 * zs);
+    const float inv_tk = 1.0f / (float)TK, inv_p = 1.0f / (float)P;
+    auto col = [&](int c) -> size_t {
+        const int u = r0 + c, q = fdiv(u, inv_p);
+        return (size_t)q * zs + (size_t)(u - q * P);
+    };
     // columns sit ss = ny + 1 apart in LDS: the staging loop writes (and the
     // final loop reads) TK columns per y with consecutive lanes, which a
     // power-of-two stride would put on one bank
@@ -373,7 +401,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(const Inst *__restrict__ 
         for (int q = 0; q < YB; ++q) {
             const int t = t0 + q * FFT_THREADS;
             const int y = fdiv(t, inv_tk), c = t - y * TK;
-            v[q] = (t < tot && c < tk) ? ld2(spec, (unsigned)(y * sp + kx0 + c)) : make_float2(0.f, 0.f);
+            v[q] = (t < tot && c < tk) ? ld2(specr + col(c), (unsigned)(y * sp)) : make_float2(0.f, 0.f);
         }
 #pragma unroll
         for (int q = 0; q < YB; ++q) {
@@ -386,7 +414,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(const Inst *__restrict__ 
     fft_lds<P2, FFT_THREADS, FFT_MAXPTS>(sm, ny, I.yrad, I.nyrad, TK, ss, stw, (float)dir);
     for (int t = threadIdx.x; t < ny * TK; t += FFT_THREADS) {
         const int y = fdiv(t, inv_tk), c = t - y * TK;
-        if (c < tk) st2(spec, (unsigned)(y * sp + kx0 + c), sm[c * ss + y]);
+        if (c < tk) st2(specw + col(c), (unsigned)(y * sp), sm[c * ss + y]);
     }
 }
 
@@ -438,13 +466,13 @@ template __global__ void k_fft_y<true>(const Inst *, const int *, int, int);
 
 // The z systems, one per (kx, ky), in double precision.  A work-group loads
 // a tile of ZTK consecutive kx at one ky and all z (coalesced rows); each
-// wavefront then solves the columns of the tile one at a time.  With the
-// pivots of the set-up, Thomas' two sweeps are first-order linear
+// wavefront then solves the columns of the tile, one or two at a time.
+// With the pivots of the set-up, Thomas' two sweeps are first-order linear
 // recurrences,
 //   y_k = -a_k ip_k y_{k-1} + ip_k d_k,   mu_k = -c_k ip_k mu_{k+1} + y_k,
-// i.e. compositions of affine maps, which the 64 lanes evaluate as a
-// prefix scan (lane l owns rows l RPL .. l RPL + RPL - 1): compose the
-// lane's maps, scan the lane maps across the wavefront with shuffles, then
+// i.e. compositions of affine maps, which a segment of L lanes evaluates as
+// a prefix scan (lane l owns rows l RPL .. l RPL + RPL - 1): compose the
+// lane's maps, scan the lane maps across the segment with shuffles, then
 // replay the rows from the lane's incoming value.  The result is scaled by
 // 1/(nx ny) (the two inverse FFTs are unnormalised).
 constexpr int ZTK = FFT_ZTK;
@@ -539,9 +567,11 @@ __device__ __forceinline__ void zsolve_lane(const Inst &I, int lb) {
         if (k < nz) spec[(size_t)k * zstride] = make_float2((float)yr[k], (float)yi[k]);
 }
 
-// RMAX: z rows per lane of the scan, at least ceil(nz / 64) for every
-// instance of the launch (2 up to nz = 128, else 4): fewer registers, more
-// work-groups per CU for the common depths.
+// RMAX: z rows per lane of the scan for every instance of the launch (2 up
+// to nz = 64, else 4): fewer registers, more work-groups per CU for the
+// shallow boxes.  Columns of up to 32 RMAX rows are scanned on 32-lane
+// segments (two columns per wavefront), deeper ones on the whole
+// wavefront.
 template <int RMAX>
 __global__ __launch_bounds__(ZS_THREADS) void k_fft_zsolve(const Inst *__restrict__ insts,
                                                             const int *__restrict__ prefix,
@@ -584,8 +614,16 @@ __global__ __launch_bounds__(ZS_THREADS) void k_fft_zsolve(const Inst *__restric
     const double cz = I.cz;
     const double scale = 1.0 / ((double)nx * (double)ny);
     static_assert(RMAX * 64 <= FFT_ZMAX, "scan rows per lane");
-    const int rpl = (nz + 63) >> 6;
-    const int k0 = lane * rpl;
+    // the scan runs on segments of L lanes, 64 / L columns per wavefront at
+    // a time: the scan's cost is per column, so columns of up to 32 RMAX
+    // rows take 32-lane segments (with nz <= 32 the same maps are composed
+    // in the same order as on 64 lanes, whose upper half would only hold
+    // identity maps)
+    const int L = nz <= 32 * RMAX ? 32 : 64;
+    const int S = 64 / L;
+    const int sl = lane & (L - 1), sg = lane / L;
+    const int rpl = (nz + L - 1) / L;
+    const int k0 = sl * rpl;
     // pivots of the wavefront's next column are loaded while the current
     // one is solved
     double ipn[RMAX];
@@ -597,14 +635,14 @@ __global__ __launch_bounds__(ZS_THREADS) void k_fft_zsolve(const Inst *__restric
             dst[q] = (c < tk && q < rpl && k < nz) ? ipc[k] : 0.0;
         }
     };
-    load_piv(w, ipn);
-    for (int c = w; c < tk; c += 4) {
+    load_piv(w * S + sg, ipn);
+    for (int c = w * S + sg; c < tk; c += 4 * S) {
         const int kx = kx0 + c;
         const bool singular = (kx == 0 && ky == 0);
         double yr[RMAX], yi[RMAX], ip[RMAX];
 #pragma unroll
         for (int q = 0; q < RMAX; ++q) ip[q] = ipn[q];
-        load_piv(c + 4, ipn);
+        load_piv(c + 4 * S, ipn);
 #pragma unroll
         for (int q = 0; q < RMAX; ++q) {
             const int k = k0 + q;
@@ -627,10 +665,10 @@ __global__ __launch_bounds__(ZS_THREADS) void k_fft_zsolve(const Inst *__restric
                     sw += wk;
                 }
             }
-            for (int o = 32; o > 0; o >>= 1) {
-                sr += __shfl_xor(sr, o, 64);
-                si += __shfl_xor(si, o, 64);
-                sw += __shfl_xor(sw, o, 64);
+            for (int o = L / 2; o > 0; o >>= 1) {
+                sr += __shfl_xor(sr, o, L);
+                si += __shfl_xor(si, o, L);
+                sw += __shfl_xor(sw, o, L);
             }
 #pragma unroll
             for (int q = 0; q < RMAX; ++q) {
@@ -653,16 +691,16 @@ __global__ __launch_bounds__(ZS_THREADS) void k_fft_zsolve(const Inst *__restric
                 A = Ak * A;
             }
         }
-        for (int o = 1; o < 64; o <<= 1) {
-            const double pA = __shfl_up(A, o, 64), pr = __shfl_up(Br, o, 64), pi = __shfl_up(Bi, o, 64);
-            if (lane >= o) {
+        for (int o = 1; o < L; o <<= 1) {
+            const double pA = __shfl_up(A, o, L), pr = __shfl_up(Br, o, L), pi = __shfl_up(Bi, o, L);
+            if (sl >= o) {
                 Br = A * pr + Br;
                 Bi = A * pi + Bi;
                 A = A * pA;
             }
         }
-        double ur = __shfl_up(Br, 1, 64), ui = __shfl_up(Bi, 1, 64);
-        if (lane == 0) { ur = 0.0; ui = 0.0; }
+        double ur = __shfl_up(Br, 1, L), ui = __shfl_up(Bi, 1, L);
+        if (sl == 0) { ur = 0.0; ui = 0.0; }
 #pragma unroll
         for (int q = 0; q < RMAX; ++q) {
             const int k = k0 + q;
@@ -691,16 +729,16 @@ __global__ __launch_bounds__(ZS_THREADS) void k_fft_zsolve(const Inst *__restric
                 C = Ck * C;
             }
         }
-        for (int o = 1; o < 64; o <<= 1) {
-            const double nC = __shfl_down(C, o, 64), nr = __shfl_down(Dr, o, 64), ni = __shfl_down(Di, o, 64);
-            if (lane + o < 64) {
+        for (int o = 1; o < L; o <<= 1) {
+            const double nC = __shfl_down(C, o, L), nr = __shfl_down(Dr, o, L), ni = __shfl_down(Di, o, L);
+            if (sl + o < L) {
                 Dr = C * nr + Dr;
                 Di = C * ni + Di;
                 C = C * nC;
             }
         }
-        double xr = __shfl_down(Dr, 1, 64), xi = __shfl_down(Di, 1, 64);
-        if (lane == 63) { xr = 0.0; xi = 0.0; }
+        double xr = __shfl_down(Dr, 1, L), xi = __shfl_down(Di, 1, L);
+        if (sl == L - 1) { xr = 0.0; xi = 0.0; }
 #pragma unroll
         for (int q = RMAX - 1; q >= 0; --q) {
             const int k = k0 + q;
@@ -727,10 +765,10 @@ __global__ __launch_bounds__(ZS_THREADS) void k_fft_zsolve(const Inst *__restric
                     sw += wk;
                 }
             }
-            for (int o = 32; o > 0; o >>= 1) {
-                sr += __shfl_xor(sr, o, 64);
-                si += __shfl_xor(si, o, 64);
-                sw += __shfl_xor(sw, o, 64);
+            for (int o = L / 2; o > 0; o >>= 1) {
+                sr += __shfl_xor(sr, o, L);
+                si += __shfl_xor(si, o, L);
+                sw += __shfl_xor(sw, o, L);
             }
 #pragma unroll
             for (int q = 0; q < RMAX; ++q) {

@@ -64,7 +64,13 @@ __global__ void k_fft_zsolve(const Inst *insts, const int *prefix, int ninst);
 __global__ void k_fft_tables(const Inst *insts, int inst);
 __host__ __device__ int fft_x_pairs(int nx);
 __host__ __device__ int fft_y_stride(int ny);
-__host__ __device__ int fft_y_cols(int ny);
+struct FftYPlan {
+    int G;       // whole planes per tile (ntk = 1)
+    int ntk;     // tiles per plane (G = 1)
+    int TK;      // columns per tile: G P, or about P / ntk
+    int blocks;  // tiles of the instance
+};
+__host__ __device__ FftYPlan fft_y_plan(int nx, int ny, int nz);
 __host__ __device__ int fft_pitch(int nx);
 __host__ __device__ size_t fft_z_lds(int nz);
 constexpr int FFT_ZTK = 16;     // kx columns per work-group of the z solve
