@@ -116,7 +116,7 @@ def variant_bench(w, tdgl, inputs, torch, kind, steps, warmup, mu_rtol):
     return {"steps": steps, "ms_per_step": 1e3 * el / steps, "cell_updates_per_s": N * steps / el,
             "sweeps_per_step": st["sweeps_sum"] / max(st["steps"], 1),
             "tiling": {k: tiling[k] for k in ("rows", "chunk", "chunk2", "streaming", "fused", "persistent",
-                                               "rhs_rows")}}
+                                               "rhs_rows", "super_rows")}}
 
 
 def host_cpu_model():
@@ -238,7 +238,7 @@ def small_bench(tdgl, inputs, torch, name, steps, warmup):
     n = w.nx * w.ny * w.nz
     return {"workload": w.name, "nodes": n, "driven": w.driven, "steps": steps, "warmup": warmup,
             "tiling": {k: tiling[k] for k in ("rows", "chunk", "chunk2", "streaming", "fused", "persistent",
-                                               "rhs_rows")},
+                                               "rhs_rows", "super_rows")},
             "eager_us_per_step": 1e6 * t_e / steps, "eager_rate": n * steps / t_e,
             "eager_sweeps_per_step": st["sweeps_sum"] / steps,
             "graph_us_per_step": 1e6 * t_g / steps, "graph_rate": n * steps / t_g,
@@ -394,7 +394,7 @@ def main():
     ap.add_argument("--variant-steps", type=int, default=10,
                     help="steps of the same workload with Langevin noise and with a yz-plane field (0 skips)")
     ap.add_argument("--tiling", default=None,
-                    help="rows,chunk,streaming,fused[,persistent[,chunk2[,rhs_rows]]]: set the stencil tiling instead of "
+                    help="rows,chunk,streaming,fused[,persistent[,chunk2[,rhs_rows[,super_rows]]]]: set the stencil tiling instead of "
                          "tdgl_autotune")
     ap.add_argument("--study", choices=["jacobi", "iv"], default=None,
                     help="instead of the benchmark line: 'jacobi', the Jacobi iteration study (2D film: "
@@ -430,9 +430,9 @@ def main():
     s, Bz, used, frac = setup(w, tdgl, inputs, torch, w.tol, args.mu_rtol)
     log(f"[bench] B_eff={Bz:.6f} inclusions={used} fraction={frac}")
     if args.tiling:
-        v_ = [int(v) for v in args.tiling.split(",")] + [0, 0, 0]
+        v_ = [int(v) for v in args.tiling.split(",")] + [0, 0, 0, 0]
         s.set_tiling(rows=v_[0], chunk=v_[1], streaming=v_[2], fused=v_[3], persistent=v_[4], chunk2=v_[5],
-                     rhs_rows=v_[6])
+                     rhs_rows=v_[6], super_rows=v_[7])
         tiling = s.tiling()
     else:
         tiling = s.autotune()
@@ -566,7 +566,7 @@ def main():
                    "mu_tol": 1e-5, "mu_rtol": args.mu_rtol,
                    "tiling": {"rows": tiling["rows"], "chunk": tiling["chunk"], "chunk2": tiling["chunk2"],
                               "streaming": tiling["streaming"], "fused": tiling["fused"],
-                              "persistent": tiling["persistent"], "rhs_rows": tiling["rhs_rows"]},
+                              "persistent": tiling["persistent"], "rhs_rows": tiling["rhs_rows"], "super_rows": tiling["super_rows"]},
                    "precision": "psi, links and sweeps in FP32 (complex64 storage); residual, J_av, K, "
                                 "means and the Poisson z solve in FP64",
                    "parallelism": "single GPU"},

@@ -188,8 +188,9 @@ tdgl_status tdgl_set_field(tdgl_ctx *ctx, int inst, double Bx, double Bz, int qu
                            double *Bx_eff, double *Bz_eff);
 
 /* Rounding for a field in the yz plane (Eq. B_yz): Bz = 2 pi n_z / (Lx Ly)
- * if x and y are periodic; By unchanged (it is only allowed with an open z
- * axis, which imposes no quantisation). */
+ * if x and y are periodic, By = 2 pi n_y / (Lx Lz) if x and z are (Sec.
+ * 3.3.1, the flux through each periodic cross section is a whole number of
+ * quanta); a field component across an open axis is unchanged. */
 tdgl_status tdgl_quantize_field_yz(const tdgl_params *p, double By, double Bz,
                                    double *By_eff, double *Bz_eff);
 
@@ -202,9 +203,13 @@ tdgl_status tdgl_quantize_field_yz(const tdgl_params *p, double By, double Bz,
  * another gauge: psi~ here relates to psi~ in the gauge of Eq. A_yz (x
  * quasi-periodic, Sec. 3.3.1) by psi_paper = exp(i (j hy Bz - k hz By)
  * xbar_i) psi, and every gauge-invariant quantity (|psi|^2, currents, mu~,
- * E, F) is the same.  By != 0 requires an open z axis (TDGL_EINVAL
- * otherwise).  A context holding a yz-plane field has no persistent solve
- * (that tiling is switched off and refused).  tdgl_set_field returns the
+ * E, F) is the same.  With By != 0 on a periodic z axis the z wrap carries
+ * a phase too: psi_{i,j,-1} = exp(-i xbar_i Lz By) psi_{i,j,nz-1}; such a
+ * context runs single sweeps only (TDGL_EINVAL if its tiling is fused:
+ * set fused = 0 first; the autotuner then skips two-sweep candidates and
+ * tdgl_set_tiling refuses them) and has no adjoint (tdgl_voltage_grad
+ * returns TDGL_EINVAL).  A context holding a yz-plane field has no
+ * persistent solve (that tiling is switched off and refused).  tdgl_set_field returns the
  * instance to the xz plane.  quantize as for tdgl_set_field. */
 tdgl_status tdgl_set_field_yz(tdgl_ctx *ctx, int inst, double By, double Bz, int quantize,
                               double *By_eff, double *Bz_eff);
@@ -388,12 +393,18 @@ typedef struct tdgl_tiling {
     int rhs_rows;    /* rows per thread of the Poisson right-side pass: 0 =
                         rows, or 4 (64 x 16 tiles, z runs chosen as for
                         chunk); the result does not depend on it           */
+    int super_rows;  /* rows of the two-sweep passes' super-tiles (64 wide):
+                        16 or 32 (32 needs rows 2 or 4); 0: 32 for rows 2
+                        and 4, 16 for rows 1.  Taller tiles re-read fewer
+                        halo rows, shorter ones fit more work-groups per CU;
+                        the result does not depend on it                  */
 } tdgl_tiling;
 
 /* Picks the stencil tiling of the context by timing one Jacobi sweep for
  * each candidate (rows in {1, 2, 4} x chunk in {heuristic, 4, 8, 16, 32,
  * 64, 128, 256} up to the deepest instance's z x streaming hints off/on x
- * one or two sweeps per pass; the two-sweep candidates vary chunk2 and keep
+ * one or two sweeps per pass; the two-sweep candidates vary chunk2 and the
+ * super-tile height (super_rows 16 or 32) and keep
  * the stencil chunk of the fastest single sweep with the same rows and
  * hints) on the context's stream and keeping the fastest per iteration;
  * then 16 sweeps of

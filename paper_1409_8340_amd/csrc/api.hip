@@ -341,10 +341,11 @@ struct InstHost {
 // marching through z runs of `chunk` planes (chunk_req = 0: heuristic); the
 // two-sweep super-tile kernel marches through z runs of its own
 // (chunk2_req = 0: the stencil's).
-void set_tiling(InstHost &h, int rows, int chunk_req, int chunk2_req) {
+void set_tiling(InstHost &h, int rows, int chunk_req, int chunk2_req, int tys) {
     Inst &d = h.d;
     const tdgl_params &p = h.p;
     d.rows = rows;
+    d.tys = tys > 0 ? tys : tys_default(rows);
     d.tiles_x = cdiv(p.nx, TX);
     d.tiles_y = cdiv(p.ny, 4 * rows);
     const long txy = (long)d.tiles_x * d.tiles_y;
@@ -416,6 +417,7 @@ struct tdgl_ctx {
     bool fx_long = false;             // some spectral instance has nx > FFT_X_PTS
     bool noisy = false;               // some instance has a Langevin term
     bool any_yz = false;              // some instance has a yz-plane field
+    bool any_zseam = false;           // ... with By != 0 on a periodic z axis (single sweeps, no adjoint)
     bool any_fft = false, any_mg = false;
     bool any_driven = false;
     int max_iter = 1, max_cycles = 1;
@@ -523,6 +525,7 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
         d.uz = cv.take<float2>(p.ny);
         d.P = cv.take<float2>((size_t)p.nx * p.nz);
         d.wz = cv.take<float2>(p.nz);
+        d.zs = cv.take<float2>(p.nx);
         d.btile = cv.take<int>((size_t)cdiv(p.nx, TX) * cdiv(p.ny, 4));  // room for any rows per thread
         if (p.bc[1] == TDGL_PERIODIC && p.ny % TYS_MIN == 0) d.sring = cv.take<float2>((size_t)2 * p.nz * p.nx);
         d.st = cv.take<DevState>(1);
@@ -533,7 +536,7 @@ size_t layout(int n, const tdgl_params *params, char *base, tdgl_ctx *ctx) {
         d.max_iter = p.max_iter;
         d.mu_max_cycles = p.driven ? p.mu_max_cycles : 1;
         // stencil tiling
-        set_tiling(h, ctx_rows(n, params), p.tile_cz, 0);
+        set_tiling(h, ctx_rows(n, params), p.tile_cz, 0, 0);
         // longer runs per thread where the grid is large: a work-group's
         // fixed costs (descriptor loads, the FP64 reduction) are paid once
         // for more cells
@@ -832,8 +835,16 @@ void launch_sweep2_v(tdgl_ctx *c, int l, unsigned long long *pub) {
         if (c->tot_sr > 0)
             hipLaunchKernelGGL((k_seam_ring<YZ>), dim3(c->tot_sr), dim3(256), 0, c->stream, c->d_inst, c->d_pref_sr,
                                c->n, l);
-        hipLaunchKernelGGL((k_sweep2i<R, NT, YZ>), dim3(c->tot_i), dim3(WG * sweep2i_mult(R)), 0, c->stream,
-                           c->d_inst, c->d_pref_i, c->n, l, pub, c->pub_seq);
+        const int tys = c->inst[0].d.tys;
+        if constexpr (R > 1) {
+            if (tys == 32) {
+                hipLaunchKernelGGL((k_sweep2i<R, NT, YZ, 32>), dim3(c->tot_i), dim3(WG * sweep2i_mult(R, 32)), 0,
+                                   c->stream, c->d_inst, c->d_pref_i, c->n, l, pub, c->pub_seq);
+                return;
+            }
+        }
+        hipLaunchKernelGGL((k_sweep2i<R, NT, YZ, 16>), dim3(c->tot_i), dim3(WG * sweep2i_mult(R, 16)), 0,
+                           c->stream, c->d_inst, c->d_pref_i, c->n, l, pub, c->pub_seq);
     }
 }
 // One two-sweep pass (l odd; l = -1: timing pass).
@@ -1299,9 +1310,14 @@ void drop_graph(tdgl_ctx *ctx) {
 // launches change.
 void update_any_yz(tdgl_ctx *ctx) {
     bool any = false;
-    for (const auto &h : ctx->inst) any = any || h.yz;
+    bool zs = false;
+    for (const auto &h : ctx->inst) {
+        any = any || h.yz;
+        zs = zs || (h.yz && h.By != 0.0 && h.p.bc[2] != TDGL_OPEN);
+    }
     if (any != ctx->any_yz) drop_graph(ctx);
     ctx->any_yz = any;
+    ctx->any_zseam = zs;
     if (any && ctx->persist) {
         drop_graph(ctx);
         ctx->persist = false;
@@ -1497,6 +1513,10 @@ tdgl_status tdgl_quantize_field_yz(const tdgl_params *p, double By, double Bz, d
     const double Lx = len(p->nx, p->hx, p->bc[0]), Ly = len(p->ny, p->hy, p->bc[1]);
     if (p->bc[0] == TDGL_PERIODIC && p->bc[1] == TDGL_PERIODIC)
         Bz = twopi * std::nearbyint(Bz * Lx * Ly / twopi) / (Lx * Ly);
+    if (p->bc[0] == TDGL_PERIODIC && p->bc[2] == TDGL_PERIODIC) {
+        const double Lz = len(p->nz, p->hz, p->bc[2]);
+        By = twopi * std::nearbyint(By * Lx * Lz / twopi) / (Lx * Lz);
+    }
     *By_eff = By;
     *Bz_eff = Bz;
     return TDGL_OK;
@@ -1508,17 +1528,20 @@ tdgl_status tdgl_set_field_yz(tdgl_ctx *ctx, int inst, double By, double Bz, int
     if (s) return s;
     if (!std::isfinite(By) || !std::isfinite(Bz)) return fail(TDGL_EINVAL, "field must be finite");
     InstHost &h = ctx->inst[inst];
-    if (By != 0.0 && h.p.bc[2] != TDGL_OPEN)
-        return fail(TDGL_EINVAL, "a yz-plane field with By != 0 needs an open z axis");
     double qy, qz;
     tdgl_quantize_field_yz(&h.p, By, Bz, &qy, &qz);
     if (!quantize) {
-        if (std::fabs(Bz - qz) > 1e-9 * std::max(1.0, std::fabs(qz)))
+        auto off = [](double a, double b) { return std::fabs(a - b) > 1e-9 * std::max(1.0, std::fabs(b)); };
+        if (off(By, qy) || off(Bz, qz))
             return fail(TDGL_EINVAL,
-                        "Bz = %.9g is not a whole number of flux quanta through the periodic xy cross section "
-                        "(nearest: %.9g); pass quantize=1", Bz, qz);
+                        "field (%.9g, %.9g) is not a whole number of flux quanta through the periodic "
+                        "cross sections (nearest: %.9g, %.9g); pass quantize=1", By, Bz, qy, qz);
+        qy = By;
         qz = Bz;
     }
+    if (qy != 0.0 && h.p.bc[2] != TDGL_OPEN && ctx->fused)
+        return fail(TDGL_EINVAL, "a yz-plane field with By != 0 on a periodic z axis needs single-sweep "
+                                 "tiling (set fused = 0 first)");
     h.Bx = 0.0;
     h.By = qy;
     h.Bz = qz;
@@ -1962,10 +1985,10 @@ tdgl_status upload_tiling(tdgl_ctx *ctx) {
         // the 64 x 4R tiles of the super-tiles (M of them stacked in y) that
         // the plain-load two-sweep kernel does not take
         std::vector<int> bt;
-        const int M = sweep2i_mult(d.rows);
-        d.seam2 = seam2_ok(d.per[1] != 0, d.ny, d.rows) ? 1 : 0;
+        const int M = sweep2i_mult(d.rows, d.tys);
+        d.seam2 = seam2_ok(d.per[1] != 0, d.ny, d.tys) ? 1 : 0;
         const bool seam = d.seam2 != 0;
-        const int nsy = sweep2i_rows(d.ny, d.rows, seam);
+        const int nsy = sweep2i_rows(d.ny, d.rows, d.tys, seam);
         for (int ty = 0; ty < d.tiles_y; ++ty)
             for (int tx = 0; tx < d.tiles_x; ++tx) {
                 // tile row ty lies in super-tile row ty / M (seam2) or, one
@@ -1973,7 +1996,7 @@ tdgl_status upload_tiling(tdgl_ctx *ctx) {
                 const int tr = seam ? ty : ty - 1;
                 const int j = tr / M;
                 const bool inner = tr >= 0 && j < nsy &&
-                                   tile_interior2(tx * TX, sweep2i_y0(j, d.rows, seam), tys_of(d.rows), d.nx, d.ny,
+                                   tile_interior2(tx * TX, sweep2i_y0(j, d.rows, d.tys, seam), d.tys, d.nx, d.ny,
                                                   d.per[0] != 0, seam);
                 if (!inner) bt.push_back(tx + d.tiles_x * ty);
             }
@@ -2025,6 +2048,7 @@ struct Tiling {
     int fused = 0;    // two-sweep passes
     int persist = 0;  // one cooperative launch per Jacobi solve
     int rhs4 = 0;     // Poisson right side on 64 x 16 tiles (four rows per thread)
+    int tys = 0;      // rows of the two-sweep super-tiles (0: tys_default(rows))
 };
 
 tdgl_status apply_tiling(tdgl_ctx *ctx, const Tiling &t) {
@@ -2032,9 +2056,9 @@ tdgl_status apply_tiling(tdgl_ctx *ctx, const Tiling &t) {
     ctx->rows = t.rows;
     ctx->rhs_rows = (t.rhs4 && t.rows != 4) ? 4 : 0;
     ctx->nt = t.nt != 0;
-    ctx->fused = t.fused != 0;
+    ctx->fused = t.fused != 0 && !ctx->any_zseam;  // the two-sweep kernels have no z-seam phase
     ctx->persist = t.persist != 0 && !ctx->fused && !ctx->any_yz;
-    for (auto &h : ctx->inst) set_tiling(h, t.rows, t.chunk, t.chunk2);
+    for (auto &h : ctx->inst) set_tiling(h, t.rows, t.chunk, t.chunk2, t.tys);
     return upload_tiling(ctx);
 }
 
@@ -2062,16 +2086,19 @@ bool tune_file_lookup(const char *path, const std::string &key, Tiling *t, doubl
     bool found = false;
     while (fgets(line, sizeof line, f)) {
         char k[4000];
-        int r, c, nt, fu, pe, c2 = 0, r4 = 0;
+        int r, c, nt, fu, pe, c2 = 0, r4 = 0, ty = 0;
         double u;
-        // key rows chunk streaming fused persistent us [chunk2 [rhs4]]
-        const int got = sscanf(line, "%3999s %d %d %d %d %d %lf %d %d", k, &r, &c, &nt, &fu, &pe, &u, &c2, &r4);
+        // key rows chunk streaming fused persistent us [chunk2 [rhs4 [super-tile rows]]]
+        const int got =
+            sscanf(line, "%3999s %d %d %d %d %d %lf %d %d %d", k, &r, &c, &nt, &fu, &pe, &u, &c2, &r4, &ty);
         if (got >= 7 && key == k && (r == 1 || r == 2 || r == 4) && c >= 0 && c2 >= 0 &&
-            (nt == 0 || nt == 1) && (fu == 0 || fu == 1) && (pe == 0 || pe == 1) && (r4 == 0 || r4 == 1)) {
+            (nt == 0 || nt == 1) && (fu == 0 || fu == 1) && (pe == 0 || pe == 1) && (r4 == 0 || r4 == 1) &&
+            (ty == 0 || ty == 16 || (ty == 32 && r >= 2))) {
             t->rows = r;
             t->chunk = c;
             t->chunk2 = got >= 8 ? c2 : 0;
             t->rhs4 = got >= 9 ? r4 : 0;
+            t->tys = got >= 10 ? ty : 0;
             t->nt = nt;
             t->fused = fu;
             t->persist = pe;
@@ -2126,8 +2153,13 @@ tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *ch
         for (int fu = 0; fu < 2; ++fu)
         for (int nt = 0; nt < 2; ++nt)
         for (int r : rows)
-            for (int c : chunks) {
+        for (int c : chunks)
+            for (int ty : {0, 16, 32}) {
                 if (c > 4 && c / 2 >= nzmax) continue;
+                // super-tile heights are a two-sweep notion; 32 rows need R >= 2
+                if ((fu == 0) != (ty == 0) || (ty == 32 && r == 1)) continue;
+                // the two-sweep kernels have no z-seam phase
+                if (fu && ctx->any_zseam) continue;
                 Tiling t;
                 t.rows = r;
                 t.chunk = fu ? stencil_chunk[nt][r] : c;
@@ -2135,6 +2167,7 @@ tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *ch
                 if (fu && c == 0) continue;  // the heuristic z run is a single-sweep notion
                 t.nt = nt;
                 t.fused = fu;
+                t.tys = ty;
                 tdgl_status e = apply_tiling(ctx, t);
                 if (e) return e;
                 auto pass = [&]() {
@@ -2236,8 +2269,8 @@ tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *ch
         if (cache_path) {
             FILE *f = fopen(cache_path, "a");
             if (f) {
-                fprintf(f, "%s %d %d %d %d %d %.3f %d %d\n", key.c_str(), best.rows, best.chunk, best.nt, best.fused,
-                        best.persist, best_us, best.chunk2, best.rhs4);
+                fprintf(f, "%s %d %d %d %d %d %.3f %d %d %d\n", key.c_str(), best.rows, best.chunk, best.nt,
+                        best.fused, best.persist, best_us, best.chunk2, best.rhs4, best.tys);
                 fclose(f);
             }
         }
@@ -2257,6 +2290,7 @@ tdgl_status tdgl_autotune(tdgl_ctx *ctx, const char *cache_path, tdgl_tiling *ch
         chosen->persistent = ctx->persist ? 1 : 0;
         chosen->sweep_us = best_us;
         chosen->rhs_rows = ctx->rhs_rows;
+        chosen->super_rows = ctx->inst[0].d.tys;
     }
     return TDGL_OK;
 }
@@ -2268,12 +2302,19 @@ tdgl_status tdgl_set_tiling(tdgl_ctx *ctx, const tdgl_tiling *t) {
     if (t->chunk2 < 0 || t->chunk2 > 1024) return fail(TDGL_EINVAL, "chunk2 must be in [0, 1024]");
     if (t->rhs_rows != 0 && t->rhs_rows != 4 && t->rhs_rows != t->rows)
         return fail(TDGL_EINVAL, "rhs_rows must be 0, 4 or rows");
+    if (t->super_rows != 0 && t->super_rows != 16 && t->super_rows != 32)
+        return fail(TDGL_EINVAL, "super_rows must be 0, 16 or 32");
+    if (t->super_rows == 32 && t->rows == 1)
+        return fail(TDGL_EINVAL, "32-row super-tiles need rows 2 or 4");
     if ((t->streaming != 0 && t->streaming != 1) || (t->fused != 0 && t->fused != 1) ||
         (t->persistent != 0 && t->persistent != 1))
         return fail(TDGL_EINVAL, "streaming, fused and persistent must be 0 or 1");
     if (t->fused && t->persistent) return fail(TDGL_EINVAL, "persistent solves use single sweeps (fused = 0)");
     if (ctx->any_yz && t->persistent)
         return fail(TDGL_EINVAL, "a context with a yz-plane field has no persistent solve (persistent = 0)");
+    if (ctx->any_zseam && t->fused)
+        return fail(TDGL_EINVAL, "a yz-plane field with By != 0 on a periodic z axis has no two-sweep passes "
+                                 "(fused = 0)");
     HIPCHK(hipStreamSynchronize(ctx->stream));
     Tiling s;
     s.rows = t->rows;
@@ -2283,6 +2324,7 @@ tdgl_status tdgl_set_tiling(tdgl_ctx *ctx, const tdgl_tiling *t) {
     s.fused = t->fused;
     s.persist = t->persistent;
     s.rhs4 = t->rhs_rows == 4 ? 1 : 0;
+    s.tys = t->super_rows;
     return apply_tiling(ctx, s);
 }
 
@@ -2297,6 +2339,7 @@ tdgl_status tdgl_get_tiling(const tdgl_ctx *ctx, int inst, tdgl_tiling *out) {
     out->persistent = ctx->persist ? 1 : 0;
     out->sweep_us = 0.0;
     out->rhs_rows = ctx->rhs_rows;
+    out->super_rows = ctx->inst[inst].d.tys;
     return TDGL_OK;
 }
 
@@ -2398,6 +2441,8 @@ tdgl_status voltage_grad_check(tdgl_ctx *ctx, int nsteps, int window_begin, int 
     if (!ctx) return fail(TDGL_EINVAL, "null context");
     if (ctx->n != 1) return fail(TDGL_EINVAL, "tdgl_voltage_grad needs a context with one instance");
     if (!ctx->inst[0].p.driven) return fail(TDGL_EINVAL, "the voltage needs a driven instance (driven = 1)");
+    if (ctx->any_zseam)
+        return fail(TDGL_EINVAL, "no adjoint for a yz-plane field with By != 0 on a periodic z axis");
     if (nsteps < 1 || window_begin < 0 || window_begin >= nsteps || ckpt_every < 1)
         return fail(TDGL_EINVAL, "need nsteps >= 1, 0 <= window_begin < nsteps, ckpt_every >= 1");
     if (!grad || !vbar) return fail(TDGL_EINVAL, "null output");

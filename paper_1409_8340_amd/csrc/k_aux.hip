@@ -57,6 +57,12 @@ __global__ void k_links(const Inst *__restrict__ insts, int which, const double 
     if (which == 0) {
         for (int k = threadIdx.x; k < I.nz; k += blockDim.x)
             I.wz[k] = yz ? expi(-I.hx * By * (k * I.hz)) : make_float2(1.f, 0.f);
+        // the z wrap of a yz field on a periodic z axis: A_x grows by Lz By
+        // across it, a gauge shift by xbar Lz By (xbar = i hx - Lx/2)
+        const double Lz = I.nz * I.hz;
+        const bool zseam = yz && I.per[2] && By != 0.0;
+        for (int i = threadIdx.x; i < I.nx; i += blockDim.x)
+            I.zs[i] = zseam ? expi(-(i * I.hx - 0.5 * Lx) * Lz * By) : make_float2(1.f, 0.f);
         const long n = (long)I.nx * I.nz;
         for (long t = threadIdx.x; t < n; t += blockDim.x) {
             const int i = (int)(t % I.nx), k = (int)(t / I.nx);

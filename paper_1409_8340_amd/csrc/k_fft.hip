@@ -373,17 +373,20 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(const Inst *__restrict__ 
     const int nblk = prefix[ii + 1] - prefix[ii];
     const int lb = xcd_remap(blockIdx.x - prefix[ii], nblk);
     const int zt = lb / pl.ntk, j = lb - zt * pl.ntk;
-    // the tile's first column is kx = r0 of plane z0; column c of the tile
-    // is kx = u - q P of plane z0 + q, u = r0 + c, q = floor(u / P)
+    // the tile starts at kx = r0 of plane z0; column c is kx = r0 + c of
+    // that plane (per-plane tiles) or kx = c - q P of plane z0 + q, q =
+    // floor(c / P) (whole planes, r0 = 0); offsets within a tile fit 32 bits
     const int z0 = zt * pl.G, r0 = j * TK;
-    const int tk = pl.ntk == 1 ? min(pl.G, nz - z0) * P : min(TK, P - r0);
-    const size_t zs = (size_t)ny * (size_t)sp;
+    const bool whole = pl.ntk == 1;
+    const int tk = whole ? min(pl.G, nz - z0) * P : min(TK, P - r0);
+    const unsigned zs = (unsigned)ny * (unsigned)sp;
     const gf2 *__restrict__ specr = (const gf2 *)(I.spec + (size_t)z0 * zs);
     gf2 *__restrict__ specw = (gf2 *)(I.spec + (size_t)z0 * zs);
     const float inv_tk = 1.0f / (float)TK, inv_p = 1.0f / (float)P;
-    auto col = [&](int c) -> size_t {
-        const int u = r0 + c, q = fdiv(u, inv_p);
-        return (size_t)q * zs + (size_t)(u - q * P);
+    auto col = [&](int c) -> unsigned {
+        if (!whole) return (unsigned)(r0 + c);
+        const int q = fdiv(c, inv_p);
+        return (unsigned)q * zs + (unsigned)(c - q * P);
     };
     // columns sit ss = ny + 1 apart in LDS: the staging loop writes (and the
     // final loop reads) TK columns per y with consecutive lanes, which a
@@ -401,7 +404,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(const Inst *__restrict__ 
         for (int q = 0; q < YB; ++q) {
             const int t = t0 + q * FFT_THREADS;
             const int y = fdiv(t, inv_tk), c = t - y * TK;
-            v[q] = (t < tot && c < tk) ? ld2(specr + col(c), (unsigned)(y * sp)) : make_float2(0.f, 0.f);
+            v[q] = (t < tot && c < tk) ? ld2(specr, col(c) + (unsigned)(y * sp)) : make_float2(0.f, 0.f);
         }
 #pragma unroll
         for (int q = 0; q < YB; ++q) {
@@ -414,7 +417,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(const Inst *__restrict__ 
     fft_lds<P2, FFT_THREADS, FFT_MAXPTS>(sm, ny, I.yrad, I.nyrad, TK, ss, stw, (float)dir);
     for (int t = threadIdx.x; t < ny * TK; t += FFT_THREADS) {
         const int y = fdiv(t, inv_tk), c = t - y * TK;
-        if (c < tk) st2(specw + col(c), (unsigned)(y * sp), sm[c * ss + y]);
+        if (c < tk) st2(specw, col(c) + (unsigned)(y * sp), sm[c * ss + y]);
     }
 }
 

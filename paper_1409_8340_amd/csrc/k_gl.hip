@@ -175,6 +175,10 @@ __device__ __forceinline__ void stencil_tile(const Inst *__restrict__ insts, con
 
     const float ht2 = I.ht2, S2 = I.S2, u = I.u;
     const bool zper = I.per[2] != 0;
+    // a yz field on a periodic z axis: the z neighbours across the wrap
+    // carry the seam phase, psi_{-1} = zs psi_{nz-1} and psi_{nz} =
+    // conj(zs) psi_0 (zs = 1 for any other field)
+    const float2 zsx = (YZ && zper) ? I.zs[min(x, nx - 1)] : make_float2(1.f, 0.f);
     // Langevin draws of this step (assemble only): step counter before the step
     const bool noise = (MODE == MODE_FIRSTN) && I.zeta_max > 0.f;
     const unsigned long long nstep = noise ? (unsigned long long)st->n : 0ull;
@@ -206,6 +210,22 @@ __device__ __forceinline__ void stencil_tile(const Inst *__restrict__ insts, con
             if (hthr) lds[buf ^ 1][hly][hlx] = hv;
         }
         const bool zm = (k > 0) || zper, zp = (k < nz - 1) || zper;
+        float2 pmk[ROWS], pnk[ROWS];
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            pmk[r] = pm[r];
+            pnk[r] = pn[r];
+        }
+        if (YZ && zper) {
+            if (k == 0) {
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r) pmk[r] = xcmul(zsx, pm[r]);
+            }
+            if (k == nz - 1) {
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r) pnk[r] = xcmulc(zsx, pn[r]);
+            }
+        }
         // x links of this plane (a yz-plane field adds the factor wz[k])
         float2 uxk[ROWS];
         if (YZ) {
@@ -235,13 +255,13 @@ __device__ __forceinline__ void stencil_tile(const Inst *__restrict__ insts, con
                 double e = (double)(wxn * wyn * wzn) * (double)(-ep[r] * a2 + 0.5f * a2 * a2);
                 if (fx) e += (double)(wyn * wzn * cx) * (double)cabs2(csub(cmul(uxk[r], xp), c));
                 if (fy) e += (double)(wxn * wzn * cy) * (double)cabs2(csub(yp, c));
-                if (zp) e += (double)(wxn * wyn * cz) * (double)cabs2(csub(cmul(uz[r], pn[r]), c));
+                if (zp) e += (double)(wxn * wyn * cz) * (double)cabs2(csub(cmul(uz[r], pnk[r]), c));
                 acc += e;
                 continue;
             }
             // off-diagonal neighbour sum NS of the covariant Laplacian
             // (Eq. LaplUV_xz), open faces doubling the inner neighbour.
-            const float2 ns = nsum(uxk[r], uz[r], xm, xp, ym, yp, pm[r], pn[r], zm, zp, cx, cy, cz);
+            const float2 ns = nsum(uxk[r], uz[r], xm, xp, ym, yp, pmk[r], pnk[r], zm, zp, cx, cy, cz);
             if (MODE == MODE_NS) {
                 st2(nsout, m, ns);
                 continue;

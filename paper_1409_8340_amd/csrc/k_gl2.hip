@@ -447,7 +447,7 @@ __global__ __launch_bounds__(256) void k_seam_ring(const Inst *__restrict__ inst
 }
 
 // The two-sweep pass on interior super-tiles (tile_interior2 with the
-// height tys_of(R)): the tile, its two-node halo of psi^(l) and its ring of psi^(l+1)
+// height TY): the tile, its two-node halo of psi^(l) and its ring of psi^(l+1)
 // are real nodes with real neighbours (or their plain images across a
 // periodic x wrap), so every load is a plain load at a fixed in-plane
 // offset, issued unconditionally (a plane outside the grid reads a real
@@ -458,13 +458,13 @@ __global__ __launch_bounds__(256) void k_seam_ring(const Inst *__restrict__ inst
 // tiles of the other super-tiles.  NT: the new iterate is stored
 // non-temporally; b/M and (ht/2)/M stay cacheable, since the neighbours'
 // rings read them again.
-template <int R, bool NT, bool YZ>
-__global__ __launch_bounds__(WG * sweep2i_mult(R), 4) void k_sweep2i(const Inst *__restrict__ insts,
+template <int R, bool NT, bool YZ, int TY>
+__global__ __launch_bounds__(WG * sweep2i_mult(R, TY), 4) void k_sweep2i(const Inst *__restrict__ insts,
                                                                const int *__restrict__ prefix, int ninst, int l,
                                                                unsigned long long *pub, unsigned seq) {
-    constexpr int M = sweep2i_mult(R);
+    constexpr int M = sweep2i_mult(R, TY);
     constexpr int WGI = WG * M;
-    constexpr int TYv = tys_of(R);
+    constexpr int TYv = TY;
     constexpr int LX = TX + 4, LY = TYv + 4;
     constexpr int NH2 = LX * LY - TX * TYv;
     constexpr int NQ = (NH2 + WGI - 1) / WGI;  // two-node halo slots per thread
@@ -480,7 +480,7 @@ __global__ __launch_bounds__(WG * sweep2i_mult(R), 4) void k_sweep2i(const Inst 
     const int nx = I.nx, ny = I.ny, nz = I.nz;
     // blocks: tiles_x x sweep2i_rows x tiles_z2 super-tiles
     const bool seam2 = I.seam2 != 0;
-    const int nsy = sweep2i_rows(ny, R, seam2);
+    const int nsy = sweep2i_rows(ny, R, TY, seam2);
     int t = b - prefix[ii];
     const bool first = t == 0;
     const int txi = t % I.tiles_x;
@@ -491,7 +491,7 @@ __global__ __launch_bounds__(WG * sweep2i_mult(R), 4) void k_sweep2i(const Inst 
     // seam carry the phase) are taken first, so that they do not finish
     // last: row order 0, nsy - 1, 1, 2, ..., nsy - 2
     const int tyi = (!seam2 || tyr == 0) ? tyr : (tyr == 1 ? nsy - 1 : tyr - 1);
-    const int x0 = txi * TX, y0 = sweep2i_y0(tyi, R, seam2);
+    const int x0 = txi * TX, y0 = sweep2i_y0(tyi, R, TY, seam2);
     const bool xper = I.per[0] != 0;
     const bool timing = l < 0;
     if (!timing) {
@@ -784,11 +784,13 @@ __global__ __launch_bounds__(WG * sweep2i_mult(R), 4) void k_sweep2i(const Inst 
 template __global__ void k_seam_ring<false>(const Inst *, const int *, int, int);
 template __global__ void k_seam_ring<true>(const Inst *, const int *, int, int);
 
+#define TDGL_INST2I(R, NT, YZ, TY)                                                                        \
+    template __global__ void k_sweep2i<R, NT, YZ, TY>(const Inst *, const int *, int, int, unsigned long long *, \
+                                                      unsigned);
 #define TDGL_INST2(R, NT, YZ)                                                                           \
     template __global__ void k_sweep2<R, NT, YZ>(const Inst *, const int *, int, int, unsigned long long *,  \
                                                  unsigned);                                                 \
-    template __global__ void k_sweep2i<R, NT, YZ>(const Inst *, const int *, int, int, unsigned long long *, \
-                                                  unsigned);
+    TDGL_INST2I(R, NT, YZ, 16)
 TDGL_INST2(1, false, false)
 TDGL_INST2(1, true, false)
 TDGL_INST2(2, false, false)
@@ -801,6 +803,16 @@ TDGL_INST2(2, false, true)
 TDGL_INST2(2, true, true)
 TDGL_INST2(4, false, true)
 TDGL_INST2(4, true, true)
+// 32-row super-tiles: R = 2 and 4 (R = 1 would need 2048 threads)
+TDGL_INST2I(2, false, false, 32)
+TDGL_INST2I(2, true, false, 32)
+TDGL_INST2I(4, false, false, 32)
+TDGL_INST2I(4, true, false, 32)
+TDGL_INST2I(2, false, true, 32)
+TDGL_INST2I(2, true, true, 32)
+TDGL_INST2I(4, false, true, 32)
+TDGL_INST2I(4, true, true, 32)
 #undef TDGL_INST2
+#undef TDGL_INST2I
 
 }  // namespace tdgl

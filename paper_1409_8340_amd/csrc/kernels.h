@@ -18,7 +18,7 @@ __global__ void k_sweep2(const Inst *insts, const int *prefix, int ninst, int l,
                          unsigned seq);
 template <bool YZ>
 __global__ void k_seam_ring(const Inst *insts, const int *prefix, int ninst, int l);
-template <int R, bool NT, bool YZ>
+template <int R, bool NT, bool YZ, int TY>
 __global__ void k_sweep2i(const Inst *insts, const int *prefix, int ninst, int l, unsigned long long *pub,
                           unsigned seq);
 template <int R, bool NT>

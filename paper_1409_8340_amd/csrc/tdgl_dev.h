@@ -113,6 +113,8 @@ struct Inst {
     float2 *uz;          // z links per y index: exp(-i hz Bx ybar_j)
     float2 *P;           // y wrap phase per (i,k): exp(i (i hx Ly Bz - k hz Ly Bx))
     float2 *wz;          // x-link factor per z plane: exp(-i hx By k hz) (yz field), else 1
+    float2 *zs;          // z-seam phase per x of a yz field on a periodic z axis: psi_{i,j,-1} =
+                         // zs[i] psi_{i,j,nz-1}, zs[i] = exp(-i xbar_i Lz By); else 1
     DevState *st;
     // Convergence words.  Work-groups reduce their maxima with atomics into
     // one of NSLOT slots (chosen by block index) placed in separate cache
@@ -129,6 +131,7 @@ struct Inst {
     int part_cap;
     int tiles_x, tiles_y, tiles_z, chunk;   // stencil tiling (chunk: z planes per tile)
     int chunk2, tiles_z2;                   // z planes per work-group of the two-sweep super-tile kernel
+    int tys;                                // rows of its super-tiles (16 or 32)
     int tiles_y4, chunk4, tiles_z4;         // 64 x 16 tiling of the Poisson right side with four rows per thread
     int rows;                               // rows per thread R (tile 64 x 4R)
     // two-sweep passes: (x, y) tiles that are not interior (tile_interior2),
@@ -183,28 +186,28 @@ __device__ __forceinline__ float2 cdiv(float2 a, float2 b) {
 // that share halos then share that XCD's L2.
 // The plain-load two-sweep kernel works on 64 x TYS super-tiles: M =
 // TYS / 4R wavefront groups of the 64 x 4R tile, so WG * M threads.  TYS is
-// 32 rows (R = 2: 1024 threads, R = 4: 512), or 16 with one row per thread
-// (1024 threads): the taller the tile, the smaller the share of its
-// two-node y halo and of its ring rows, which are read again by the
-// neighbouring super-tiles.
-__host__ __device__ constexpr int tys_of(int rows) { return rows == 1 ? 16 : 32; }
+// a tiling choice, 16 or 32 rows (32 needs R >= 2: R = 2 then takes 1024
+// threads, R = 4 512); by default 32 for R = 2 and 4, 16 for R = 1 (1024
+// threads).  The taller the tile, the smaller the share of its two-node y
+// halo and of its ring rows, which the neighbouring super-tiles read again;
+// the shorter, the more groups per CU.
+__host__ __device__ constexpr int tys_default(int rows) { return rows == 1 ? 16 : 32; }
 constexpr int TYS_MIN = 16;  // the smallest super-tile height (every other one is a multiple of it)
-__host__ __device__ constexpr int sweep2i_mult(int rows) { return tys_of(rows) / (4 * rows); }
+__host__ __device__ constexpr int sweep2i_mult(int rows, int tys) { return tys / (4 * rows); }
 // Super-tile rows start one 64 x 4R tile row into the grid (y0 = 4R + TYS j,
 // j < sweep2i_rows), so that a quasi-periodic y seam leaves only the first
 // and the last tile row to the general kernel -- unless the instance is
 // periodic in y with ny a multiple of TYS (seam2): then they start at
 // y0 = TYS j and the super-tiles on the seam apply its phase themselves.
-__host__ __device__ inline int sweep2i_rows(int ny, int rows, bool seam) {
-    const int tys = tys_of(rows);
+__host__ __device__ inline int sweep2i_rows(int ny, int rows, int tys, bool seam) {
     if (seam) return ny / tys;
     const int r = ny - 4 * rows;
     return r > 0 ? (r + tys - 1) / tys : 0;
 }
-__host__ __device__ inline int sweep2i_y0(int j, int rows, bool seam) {
-    return (seam ? 0 : 4 * rows) + tys_of(rows) * j;
+__host__ __device__ inline int sweep2i_y0(int j, int rows, int tys, bool seam) {
+    return (seam ? 0 : 4 * rows) + tys * j;
 }
-__host__ __device__ inline bool seam2_ok(bool yper, int ny, int rows) { return yper && ny % tys_of(rows) == 0; }
+__host__ __device__ inline bool seam2_ok(bool yper, int ny, int tys) { return yper && ny % tys == 0; }
 
 // A tile every node of which, with its two-node halo, is a real node or a
 // plain periodic image in x: full in x, and its halo inside the grid in y

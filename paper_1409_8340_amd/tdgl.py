@@ -82,7 +82,7 @@ KERNEL_CLASSES = ["assemble", "sweep", "current", "rhs", "poisson", "poisson_coa
 class Tiling(ctypes.Structure):
     _fields_ = [("rows", ctypes.c_int), ("chunk", ctypes.c_int), ("streaming", ctypes.c_int),
                 ("fused", ctypes.c_int), ("persistent", ctypes.c_int), ("sweep_us", ctypes.c_double),
-                ("chunk2", ctypes.c_int), ("rhs_rows", ctypes.c_int)]
+                ("chunk2", ctypes.c_int), ("rhs_rows", ctypes.c_int), ("super_rows", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -444,9 +444,9 @@ class Solver:
         _check(load().tdgl_autotune(self._ctx, path, ctypes.byref(t)))
         return t.as_dict()
 
-    def set_tiling(self, rows=2, chunk=0, streaming=0, fused=0, persistent=0, chunk2=0, rhs_rows=0):
+    def set_tiling(self, rows=2, chunk=0, streaming=0, fused=0, persistent=0, chunk2=0, rhs_rows=0, super_rows=0):
         t = Tiling(rows=rows, chunk=chunk, streaming=streaming, fused=fused, persistent=persistent,
-                   sweep_us=0.0, chunk2=chunk2, rhs_rows=rhs_rows)
+                   sweep_us=0.0, chunk2=chunk2, rhs_rows=rhs_rows, super_rows=super_rows)
         _check(load().tdgl_set_tiling(self._ctx, ctypes.byref(t)))
 
     def tiling(self, inst=0):

@@ -70,6 +70,9 @@ def _run(c, nsteps, mode="exact"):
     ((40, 33, 9), (True, False, True), 0.2, 0.12),    # open x: the ghost carries the plane's factor squared
     ((36, 30, 8), (False, True, True), 0.1, 0.1),     # open y
     ((70, 37, 1), (False, False, True), 0.0, 0.2),    # a film, Bz only
+    ((48, 40, 12), (False, False, False), 0.15, 0.1),  # periodic z: the z wrap carries a phase too
+    ((40, 33, 9), (True, False, False), 0.2, 0.12),    # open x, periodic z
+    ((64, 16, 1), (False, False, False), 0.3, 0.1),    # one periodic plane: both z neighbours are the node
 ])
 def test_yz_steps_vs_oracle(shape, open_, By, Bz):
     c = YZCase(*shape, open_=open_, By=By, Bz=Bz, tol=1e-12)
@@ -83,10 +86,11 @@ def test_yz_steps_vs_oracle(shape, open_, By, Bz):
     assert err5 <= 1e-4
 
 
-def test_yz_driven_steps_vs_oracle():
+@pytest.mark.parametrize("open_", [(False, False, True), (False, False, False)])
+def test_yz_driven_steps_vs_oracle(open_):
     """Current along x with the field in the yz plane (full Lorentz force):
-    psi, K, E and mu~ after three steps."""
-    c = YZCase(48, 40, 12, By=0.12, Bz=0.1, J=0.03, driven=True, tol=1e-12, mu_tol=1e-6, K0=0.2)
+    psi, K, E and mu~ after three steps; open or periodic z."""
+    c = YZCase(48, 40, 12, open_=open_, By=0.12, Bz=0.1, J=0.03, driven=True, tol=1e-12, mu_tol=1e-6, K0=0.2)
     c.eps = inputs.random_real(c.grid.shape, 9, 0.2, 1.0)
     g, o = _run(c, 3)
     err = rel_maxerr(g["psi"], np.exp(-1j * c.chi) * o.psi)
@@ -223,10 +227,29 @@ def test_yz_two_sweep_passes_bit_identical(shape, open_):
     f.close()
 
 
-def test_yz_needs_open_z_for_By():
-    s = tdgl.Solver(tdgl.make_params(16, 16, 8, bc=(tdgl.TDGL_PERIODIC,) * 3))
+def test_yz_periodic_z_rules():
+    """By on a periodic z axis: quantised through the xz cross section,
+    single sweeps only (two-sweep tilings refused, the autotuner keeps
+    them out) and no adjoint."""
+    s = tdgl.Solver(tdgl.make_params(16, 16, 8, bc=(tdgl.TDGL_PERIODIC,) * 3, driven=True))
     with pytest.raises(tdgl.TdglError):
-        s.set_field_yz(0.1, 0.0)
-    by, bz = s.set_field_yz(0.0, 0.3)
-    assert by == 0.0 and abs(bz * 8 * 8 / (2 * np.pi) - round(bz * 8 * 8 / (2 * np.pi))) < 1e-9
+        s.set_field_yz(0.1, 0.0, quantize=False)
+    by, bz = s.set_field_yz(0.1, 0.3)
+    for b, L2 in ((by, 16 * 8), (bz, 16 * 16)):
+        n = b * L2 / (2 * np.pi)
+        assert abs(n - round(n)) < 1e-9 and round(n) != 0
+    with pytest.raises(tdgl.TdglError):
+        s.set_tiling(rows=2, fused=1)
+    t = s.autotune()
+    assert t["fused"] == 0
+    with pytest.raises(tdgl.TdglError):
+        s.voltage_grad(2, window_begin=0, ckpt_every=1)
+    s.close()
+    # a fused context takes no z-seam field until its tiling is single-sweep
+    s = tdgl.Solver(tdgl.make_params(16, 16, 8, bc=(tdgl.TDGL_PERIODIC,) * 3))
+    s.set_tiling(rows=2, fused=1)
+    with pytest.raises(tdgl.TdglError):
+        s.set_field_yz(0.1, 0.3)
+    s.set_tiling(rows=2, fused=0)
+    s.set_field_yz(0.1, 0.3)
     s.close()

@@ -70,7 +70,8 @@ def gpu_layout_links(grid, By, Bz):
     """The links the GPU library stores for a yz-plane field, built here
     from its documented formulas: x link exp(i hx (Bz j hy - By k hz)),
     y and z links 1, the periodic y wrap edge conj(P_i) with
-    P_i = exp(i xbar_i Ly Bz)."""
+    P_i = exp(i xbar_i Ly Bz), the periodic z wrap edge conj(Q_i) with
+    Q_i = exp(-i xbar_i Lz By)."""
     nz, ny, nx = grid.shape
     j = np.arange(ny)[None, :, None]
     k = np.arange(nz)[:, None, None]
@@ -80,6 +81,9 @@ def gpu_layout_links(grid, By, Bz):
         xbar = np.arange(nx) * grid.hx - grid.length(0) / 2.0
         ly[:, ny - 1, :] = np.conj(np.exp(1j * xbar * grid.length(1) * Bz))[None, :]
     lz = np.ones(grid.shape, np.complex128)
+    if not grid.open_[2]:
+        xbar = np.arange(nx) * grid.hx - grid.length(0) / 2.0
+        lz[nz - 1, :, :] = np.conj(np.exp(-1j * xbar * grid.length(2) * By))[None, :]
     return tuple(np.ascontiguousarray(a, dtype=np.complex128) for a in (lx, ly, lz))
 
 
@@ -93,7 +97,8 @@ def gauge_phase(grid, By, Bz):
 
 
 @pytest.mark.parametrize("open_,driven", [((False, False, True), True), ((True, False, True), False),
-                                          ((False, True, True), True)])
+                                          ((False, True, True), True), ((False, False, False), True),
+                                          ((True, False, False), False)])
 def test_gpu_layout_is_a_gauge_transform_of_the_paper(open_, driven):
     """Steps taken with the GPU library's links equal the paper's steps up to
     psi_paper = exp(i chi) psi: the same psi up to that phase, the same K, E
@@ -123,3 +128,10 @@ def test_gpu_layout_is_a_gauge_transform_of_the_paper(open_, driven):
             s3 = O.new_state(grid, np.exp(-1j * chi) * psi0)
             O.run(grid, p, eps, s3, 3, base_links=tuple(bad))
             assert np.max(np.abs(np.exp(1j * chi) * s3.psi - s1.psi)) > 1e-6
+    # likewise a z seam without its phase
+    if not open_[2] and By != 0.0:
+        bad = list(gpu_layout_links(grid, By, Bz))
+        bad[2] = np.ones(grid.shape, np.complex128)
+        s4 = O.new_state(grid, np.exp(-1j * chi) * psi0)
+        O.run(grid, p, eps, s4, 3, base_links=tuple(bad))
+        assert np.max(np.abs(np.exp(1j * chi) * s4.psi - s1.psi)) > 1e-6
