@@ -207,8 +207,7 @@ tdgl_status tdgl_quantize_field_yz(const tdgl_params *p, double By, double Bz,
  * a phase too: psi_{i,j,-1} = exp(-i xbar_i Lz By) psi_{i,j,nz-1}; such a
  * context runs single sweeps only (TDGL_EINVAL if its tiling is fused:
  * set fused = 0 first; the autotuner then skips two-sweep candidates and
- * tdgl_set_tiling refuses them) and has no adjoint (tdgl_voltage_grad
- * returns TDGL_EINVAL).  A context holding a yz-plane field has no
+ * tdgl_set_tiling refuses them).  A context holding a yz-plane field has no
  * persistent solve (that tiling is switched off and refused).  tdgl_set_field returns the
  * instance to the xz plane.  quantize as for tdgl_set_field. */
 tdgl_status tdgl_set_field_yz(tdgl_ctx *ctx, int inst, double By, double Bz, int quantize,

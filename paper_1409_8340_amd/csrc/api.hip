@@ -2441,8 +2441,6 @@ tdgl_status voltage_grad_check(tdgl_ctx *ctx, int nsteps, int window_begin, int 
     if (!ctx) return fail(TDGL_EINVAL, "null context");
     if (ctx->n != 1) return fail(TDGL_EINVAL, "tdgl_voltage_grad needs a context with one instance");
     if (!ctx->inst[0].p.driven) return fail(TDGL_EINVAL, "the voltage needs a driven instance (driven = 1)");
-    if (ctx->any_zseam)
-        return fail(TDGL_EINVAL, "no adjoint for a yz-plane field with By != 0 on a periodic z axis");
     if (nsteps < 1 || window_begin < 0 || window_begin >= nsteps || ckpt_every < 1)
         return fail(TDGL_EINVAL, "need nsteps >= 1, 0 <= window_begin < nsteps, ckpt_every >= 1");
     if (!grad || !vbar) return fail(TDGL_EINVAL, "null output");

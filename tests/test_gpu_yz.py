@@ -180,6 +180,7 @@ def test_yz_graph_steps_and_tilings():
 @pytest.mark.parametrize("shape,open_,By,Bz", [
     ((16, 12, 8), (False, False, True), 0.15, 0.3),   # spectral Poisson path, y seam
     ((16, 10, 6), (False, True, True), 0.2, 0.25),    # multigrid Poisson path
+    ((16, 12, 8), (False, False, False), 0.2, 0.3),   # periodic z: the z seam's phase in the M^H solves
 ])
 def test_yz_voltage_grad_vs_oracle(shape, open_, By, Bz):
     """dVbar/deps (tdgl_voltage_grad) with a yz-plane field against the
@@ -230,7 +231,7 @@ def test_yz_two_sweep_passes_bit_identical(shape, open_):
 def test_yz_periodic_z_rules():
     """By on a periodic z axis: quantised through the xz cross section,
     single sweeps only (two-sweep tilings refused, the autotuner keeps
-    them out) and no adjoint."""
+    them out)."""
     s = tdgl.Solver(tdgl.make_params(16, 16, 8, bc=(tdgl.TDGL_PERIODIC,) * 3, driven=True))
     with pytest.raises(tdgl.TdglError):
         s.set_field_yz(0.1, 0.0, quantize=False)
@@ -242,8 +243,6 @@ def test_yz_periodic_z_rules():
         s.set_tiling(rows=2, fused=1)
     t = s.autotune()
     assert t["fused"] == 0
-    with pytest.raises(tdgl.TdglError):
-        s.voltage_grad(2, window_begin=0, ckpt_every=1)
     s.close()
     # a fused context takes no z-seam field until its tiling is single-sweep
     s = tdgl.Solver(tdgl.make_params(16, 16, 8, bc=(tdgl.TDGL_PERIODIC,) * 3))
