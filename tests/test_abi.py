@@ -114,6 +114,23 @@ def test_flux_quantisation_matches_oracle(lib, open_):
         assert qz == pytest.approx(oz, rel=1e-15, abs=0)
 
 
+@pytest.mark.parametrize("open_", [(False, False, True), (False, False, False), (True, False, False),
+                                   (False, True, False), (True, True, True)])
+def test_yz_flux_quantisation_matches_oracle(lib, open_):
+    """The yz-plane field's rounding (Bz through the xy cross section, By
+    through the xz one, each only where both of its axes are periodic)
+    against the oracle's."""
+    for (nx, ny, nz, By, Bz) in [(48, 40, 12, 0.15, 0.1), (40, 33, 9, 0.2, 0.12), (64, 16, 1, 0.3, 0.1),
+                                 (1024, 1024, 128, 0.1, 0.2)]:
+        bc = tuple(tdgl.TDGL_OPEN if o else tdgl.TDGL_PERIODIC for o in open_)
+        p = tdgl.make_params(nx, ny, nz, bc=bc)
+        g = O.Grid(nx, ny, nz, open_=open_)
+        qy, qz = tdgl.quantize_field_yz(p, By, Bz)
+        oy, oz = O.quantize_field_yz(g, By, Bz)
+        assert qy == pytest.approx(oy, rel=1e-15, abs=0)
+        assert qz == pytest.approx(oz, rel=1e-15, abs=0)
+
+
 def test_quantised_field_values_of_the_workloads(lib):
     """B_eff of the measured workloads (n = round(B Lx Ly / 2 pi))."""
     cases = [((32, 32, 16), 0.1, 4), ((256, 256, 64), 0.1, 261), ((128, 128, 32), 0.1, 65),
